@@ -1,0 +1,614 @@
+/*
+ * oracle.c -- plain, slow, double-precision CPU reference for one
+ * finite-volume hydro step of the moving Voronoi-mesh Godunov scheme
+ * (Springel, "E pur si muove", arXiv:0901.4107, Section 3).
+ *
+ * TEST INFRASTRUCTURE. This file is the checker, not the product: only the
+ * test suite, the smoke check and the CPU-baseline leg of the benchmark may
+ * load it. It shares no source with the GPU library and includes none of its
+ * headers. Every function names the passage of the paper it follows; where
+ * the paper is silent the reading taken is stated in the comment and listed
+ * in the design notes.
+ *
+ * Layouts (identical to the public ABI so that tests can pass the same
+ * arrays to both sides, but re-declared here on purpose):
+ *   conserved  Q [D+2][N]  rows m, p_x, p_y(, p_z), E      (cell totals)
+ *   primitive  W [D+2][N]  rows rho, v_x, v_y(, v_z), P
+ *   gradient   G [D+2][D][N]  G[(c*D + k)*N + i] = d W_c / d x_k in cell i
+ *   per-face vectors [D][F]; per-cell vectors [D][N]
+ *   face_ctr   g = f - r_L  (face centroid relative to the left generator)
+ *   face_sep   d = r_R - r_L (periodic image of R as seen from L)
+ *   centroid_off  delta_i = s_i - r_i
+ * The face normal points from L to R.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <float.h>
+
+#define PI_D 3.14159265358979323846
+
+typedef struct {
+    int32_t dim;
+    int64_t n_cells, n_faces;
+    const double *volume;       /* [N] */
+    const double *centroid_off; /* [D][N] s_i - r_i */
+    const double *mesh_vel;     /* [D][N] w_i */
+    const int32_t *face_L, *face_R; /* [F] */
+    const double *face_area;    /* [F] */
+    const double *face_ctr;     /* [D][F] f - r_L */
+    const double *face_sep;     /* [D][F] r_R - r_L */
+} om_mesh;
+
+typedef struct {
+    double gamma;
+    double cfl;
+} om_params;
+
+/* ------------------------------------------------------------------ */
+/* Exact Riemann solver for the 1D Euler equations of an ideal gas.      */
+/* Section 3.3 (flux computation) names an exact solver with a vacuum    */
+/* extension; the wave structure below is the textbook exact solution:   */
+/* two nonlinear waves (shock or rarefaction) around a contact, the star */
+/* pressure being the root of the pressure function                      */
+/*   f(p) = f_L(p) + f_R(p) + (u_R - u_L).                               */
+/* ------------------------------------------------------------------ */
+
+enum { OR_NORMAL = 0, OR_LEFT_VACUUM = 1, OR_RIGHT_VACUUM = 2,
+       OR_VACUUM_GENERATED = 3, OR_BOTH_VACUUM = 4 };
+
+/* One side's contribution f_K(p) to the pressure function and its
+ * derivative. Shock branch (p > p_K): Rankine-Hugoniot relation; rarefaction
+ * branch (p <= p_K): isentropic relation with the generalised Riemann
+ * invariant. */
+static void pressure_side(double p, double rho, double P, double c, double g,
+                          double *f, double *df)
+{
+    if (p > P) {
+        double Ak = 2.0 / ((g + 1.0) * rho);
+        double Bk = (g - 1.0) / (g + 1.0) * P;
+        double q = sqrt(Ak / (p + Bk));
+        *f = (p - P) * q;
+        *df = q * (1.0 - 0.5 * (p - P) / (p + Bk));
+    } else {
+        double z = (g - 1.0) / (2.0 * g);
+        double ratio = p / P;
+        *f = 2.0 * c / (g - 1.0) * (pow(ratio, z) - 1.0);
+        /* d/dp of the above = (1/(rho c)) (p/P)^(-(g+1)/(2g)) */
+        *df = (p > 0.0) ? pow(ratio, -(g + 1.0) / (2.0 * g)) / (rho * c) : INFINITY;
+    }
+}
+
+static double pressure_function(double p, const double *L, const double *R,
+                                double cL, double cR, double g, double *dfdp)
+{
+    double fl, dfl, fr, dfr;
+    pressure_side(p, L[0], L[2], cL, g, &fl, &dfl);
+    pressure_side(p, R[0], R[2], cR, g, &fr, &dfr);
+    if (dfdp) *dfdp = dfl + dfr;
+    return fl + fr + (R[1] - L[1]);
+}
+
+/* Root of the (monotone increasing, concave) pressure function, found by
+ * Newton's method kept inside a bisection bracket [lo, hi] with
+ * f(lo) < 0 < f(hi). Runs until the step is within 4 ulp of p. Returns the
+ * number of iterations. */
+static int star_pressure(const double *L, const double *R, double cL, double cR,
+                         double g, double *pstar)
+{
+    double lo = 0.0;
+    double hi = fmax(L[2], R[2]);
+    int guard = 0;
+    while (pressure_function(hi, L, R, cL, cR, g, NULL) <= 0.0 && guard < 2000) {
+        hi *= 2.0;
+        guard++;
+    }
+    double p = 0.5 * (L[2] + R[2]);
+    if (!(p > lo && p < hi)) p = 0.5 * (lo + hi);
+    int it;
+    for (it = 1; it <= 400; it++) {
+        double df;
+        double f = pressure_function(p, L, R, cL, cR, g, &df);
+        if (f == 0.0) break;
+        if (f < 0.0) lo = p; else hi = p;
+        double pn = p - f / df;
+        /* a Newton step below 4 ulp that stays in the closed bracket ends
+         * the search (the step may round to p itself) */
+        if (fabs(pn - p) <= 4.0 * DBL_EPSILON * p && pn >= lo && pn <= hi) { p = pn; break; }
+        if (!(pn > lo && pn < hi)) pn = 0.5 * (lo + hi);
+        p = pn;
+        if (hi - lo <= 4.0 * DBL_EPSILON * hi) break;
+    }
+    *pstar = p;
+    return it;
+}
+
+/* Sample the rarefaction fan of the left (sign=+1) or right (sign=-1)
+ * state at x/t = S: the characteristic u -/+ c = S meets the Riemann
+ * invariant u +/- 2c/(g-1) carried from the undisturbed side. */
+static void sample_fan(const double *K, double cK, double g, double S, int left,
+                       double *out)
+{
+    double c;
+    if (left)
+        c = 2.0 / (g + 1.0) * (cK + 0.5 * (g - 1.0) * (K[1] - S));
+    else
+        c = 2.0 / (g + 1.0) * (cK - 0.5 * (g - 1.0) * (K[1] - S));
+    double ratio = c / cK;
+    out[0] = K[0] * pow(ratio, 2.0 / (g - 1.0));
+    out[1] = left ? S + c : S - c;
+    out[2] = K[2] * pow(ratio, 2.0 * g / (g - 1.0));
+}
+
+/*
+ * Solve the Riemann problem with left state L=(rho,u,P), right state R and
+ * sample it at x/t = 0 (Section 3.3). out[0..2] = (rho_F, u_F, P_F) and
+ * out[3] = 0 if the sample lies on the left-state side of the contact
+ * (whose transverse velocity is then upwind), 1 if on the right side.
+ * star[0..1] = (p*, u*) where defined (NaN otherwise); *iters = iterations of
+ * the root finder (0 if not run). A side with rho <= 0 or P <= 0 is taken as
+ * vacuum. Returns the case code.
+ */
+int oracle_riemann(double g, const double *Lin, const double *Rin,
+                   double *out, double *star, int *iters)
+{
+    double L[3] = {Lin[0], Lin[1], Lin[2]};
+    double R[3] = {Rin[0], Rin[1], Rin[2]};
+    const double S = 0.0;
+    int lvac = !(L[0] > 0.0 && L[2] > 0.0);
+    int rvac = !(R[0] > 0.0 && R[2] > 0.0);
+    star[0] = NAN; star[1] = NAN;
+    if (iters) *iters = 0;
+
+    if (lvac && rvac) {
+        out[0] = 0.0; out[1] = 0.0; out[2] = 0.0; out[3] = 0.0;
+        return OR_BOTH_VACUUM;
+    }
+    if (lvac) {
+        /* right state next to vacuum: a left-facing fan ending at the
+         * vacuum front u_R - 2 c_R/(g-1) */
+        double cR = sqrt(g * R[2] / R[0]);
+        double head = R[1] + cR;
+        double front = R[1] - 2.0 * cR / (g - 1.0);
+        out[3] = 1.0;
+        if (S >= head) { out[0] = R[0]; out[1] = R[1]; out[2] = R[2]; }
+        else if (S <= front) { out[0] = 0.0; out[1] = 0.0; out[2] = 0.0; }
+        else sample_fan(R, cR, g, S, 0, out);
+        return OR_LEFT_VACUUM;
+    }
+    if (rvac) {
+        double cL = sqrt(g * L[2] / L[0]);
+        double head = L[1] - cL;
+        double front = L[1] + 2.0 * cL / (g - 1.0);
+        out[3] = 0.0;
+        if (S <= head) { out[0] = L[0]; out[1] = L[1]; out[2] = L[2]; }
+        else if (S >= front) { out[0] = 0.0; out[1] = 0.0; out[2] = 0.0; }
+        else sample_fan(L, cL, g, S, 1, out);
+        return OR_RIGHT_VACUUM;
+    }
+
+    double cL = sqrt(g * L[2] / L[0]);
+    double cR = sqrt(g * R[2] / R[0]);
+    if (R[1] - L[1] >= 2.0 * (cL + cR) / (g - 1.0)) {
+        /* the two rarefactions do not meet: vacuum opens between them */
+        double frontL = L[1] + 2.0 * cL / (g - 1.0);
+        double frontR = R[1] - 2.0 * cR / (g - 1.0);
+        if (S <= frontL) {
+            out[3] = 0.0;
+            if (S <= L[1] - cL) { out[0] = L[0]; out[1] = L[1]; out[2] = L[2]; }
+            else sample_fan(L, cL, g, S, 1, out);
+        } else if (S >= frontR) {
+            out[3] = 1.0;
+            if (S >= R[1] + cR) { out[0] = R[0]; out[1] = R[1]; out[2] = R[2]; }
+            else sample_fan(R, cR, g, S, 0, out);
+        } else {
+            out[0] = 0.0; out[1] = 0.0; out[2] = 0.0; out[3] = 0.0;
+        }
+        return OR_VACUUM_GENERATED;
+    }
+
+    double ps;
+    int it = star_pressure(L, R, cL, cR, g, &ps);
+    if (iters) *iters = it;
+    double fl, dfl, fr, dfr;
+    pressure_side(ps, L[0], L[2], cL, g, &fl, &dfl);
+    pressure_side(ps, R[0], R[2], cR, g, &fr, &dfr);
+    double us = 0.5 * (L[1] + R[1]) + 0.5 * (fr - fl);
+    star[0] = ps; star[1] = us;
+
+    double gm = (g - 1.0) / (g + 1.0);
+    if (S <= us) {
+        out[3] = 0.0;
+        if (ps > L[2]) {
+            double SL = L[1] - cL * sqrt((g + 1.0) / (2.0 * g) * ps / L[2] + (g - 1.0) / (2.0 * g));
+            if (S <= SL) { out[0] = L[0]; out[1] = L[1]; out[2] = L[2]; }
+            else {
+                double r = ps / L[2];
+                out[0] = L[0] * (r + gm) / (gm * r + 1.0);
+                out[1] = us; out[2] = ps;
+            }
+        } else {
+            double head = L[1] - cL;
+            double cs = cL * pow(ps / L[2], (g - 1.0) / (2.0 * g));
+            double tail = us - cs;
+            if (S <= head) { out[0] = L[0]; out[1] = L[1]; out[2] = L[2]; }
+            else if (S >= tail) {
+                out[0] = L[0] * pow(ps / L[2], 1.0 / g);
+                out[1] = us; out[2] = ps;
+            } else sample_fan(L, cL, g, S, 1, out);
+        }
+    } else {
+        out[3] = 1.0;
+        if (ps > R[2]) {
+            double SR = R[1] + cR * sqrt((g + 1.0) / (2.0 * g) * ps / R[2] + (g - 1.0) / (2.0 * g));
+            if (S >= SR) { out[0] = R[0]; out[1] = R[1]; out[2] = R[2]; }
+            else {
+                double r = ps / R[2];
+                out[0] = R[0] * (r + gm) / (gm * r + 1.0);
+                out[1] = us; out[2] = ps;
+            }
+        } else {
+            double head = R[1] + cR;
+            double cs = cR * pow(ps / R[2], (g - 1.0) / (2.0 * g));
+            double tail = us + cs;
+            if (S >= head) { out[0] = R[0]; out[1] = R[1]; out[2] = R[2]; }
+            else if (S <= tail) {
+                out[0] = R[0] * pow(ps / R[2], 1.0 / g);
+                out[1] = us; out[2] = ps;
+            } else sample_fan(R, cR, g, S, 0, out);
+        }
+    }
+    return OR_NORMAL;
+}
+
+/* Batched form for the tests: arrays of n problems. */
+void oracle_riemann_batch(int64_t n, double g,
+                          const double *rhoL, const double *uL, const double *PL,
+                          const double *rhoR, const double *uR, const double *PR,
+                          double *rhoF, double *uF, double *PF, double *side,
+                          double *pstar, double *ustar, int32_t *kase, int32_t *iters)
+{
+    for (int64_t i = 0; i < n; i++) {
+        double L[3] = {rhoL[i], uL[i], PL[i]};
+        double R[3] = {rhoR[i], uR[i], PR[i]};
+        double out[4], st[2];
+        int it;
+        int k = oracle_riemann(g, L, R, out, st, &it);
+        rhoF[i] = out[0]; uF[i] = out[1]; PF[i] = out[2]; side[i] = out[3];
+        pstar[i] = st[0]; ustar[i] = st[1];
+        if (kase) kase[i] = k;
+        if (iters) iters[i] = it;
+    }
+}
+
+/* The pressure function itself, exposed so that tests can check that a
+ * returned p* is a root (f(p*) = 0) independently of the solver loop. */
+double oracle_pressure_function(double g, const double *L, const double *R, double p)
+{
+    double cL = sqrt(g * L[2] / L[0]);
+    double cR = sqrt(g * R[2] / R[0]);
+    return pressure_function(p, L, R, cL, cR, g, NULL);
+}
+
+/* ------------------------------------------------------------------ */
+/* Step (ii): conserved -> primitive (Section 3, state vector and EOS).  */
+/* rho = m/V, v = p/m, P = (g-1)(E - m v^2/2)/V. A cell with m <= 0 is   */
+/* vacuum: all primitives zero.                                          */
+/* ------------------------------------------------------------------ */
+void oracle_prim(int32_t dim, int64_t n, double g, const double *V,
+                 const double *Q, double *W)
+{
+    const int nv = dim + 2;
+    for (int64_t i = 0; i < n; i++) {
+        double m = Q[0 * n + i];
+        double E = Q[(nv - 1) * n + i];
+        if (!(m > 0.0)) {
+            for (int c = 0; c < nv; c++) W[c * n + i] = 0.0;
+            continue;
+        }
+        double ke = 0.0;
+        W[0 * n + i] = m / V[i];
+        for (int k = 0; k < dim; k++) {
+            double v = Q[(1 + k) * n + i] / m;
+            W[(1 + k) * n + i] = v;
+            ke += v * v;
+        }
+        W[(nv - 1) * n + i] = (g - 1.0) * (E - 0.5 * m * ke) / V[i];
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Step (iii): gradients and slope limiting (Section 3.1).               */
+/* Gradient: the Voronoi estimate exact to linear order,                 */
+/*   V_i grad phi_i = sum_j A_ij ( [phi_j - phi_i] c_ij / r_ij           */
+/*                                 - (phi_i + phi_j)/2 * r_ij / r_ij ),  */
+/* with r_ij = r_i - r_j and c_ij = f_ij - (r_i + r_j)/2. Written per     */
+/* face from the left cell's view (r_LR = -d, c = g - d/2); the right     */
+/* cell's term is the negative because A, c and |r| are symmetric while   */
+/* r_ij flips sign. Accumulated per cell in face-list order.             */
+/* Limiter: alpha_i = min(1, min_j psi_ij) per primitive, with the        */
+/* neighbour extrema taken over the face neighbours and i itself, and    */
+/* Delta phi_ij = grad phi_i . (f_ij - s_i). A |Delta phi| at round-off   */
+/* level (<= 1e-13 max(|phi_i|, phi_max - phi_min)) is read as zero.      */
+/* ------------------------------------------------------------------ */
+void oracle_gradients(const om_mesh *M, const double *W, double *grad_raw,
+                      double *grad_lim, double *alpha)
+{
+    const int D = M->dim, nv = D + 2;
+    const int64_t n = M->n_cells, nf = M->n_faces;
+    const double *A = M->face_area, *gc = M->face_ctr, *ds = M->face_sep;
+    double *phimin = (double *)malloc(sizeof(double) * nv * n);
+    double *phimax = (double *)malloc(sizeof(double) * nv * n);
+    double *acc = (double *)calloc((size_t)nv * D * n, sizeof(double));
+
+    for (int c = 0; c < nv; c++)
+        for (int64_t i = 0; i < n; i++) {
+            phimin[c * n + i] = W[c * n + i];
+            phimax[c * n + i] = W[c * n + i];
+        }
+
+    for (int64_t f = 0; f < nf; f++) {
+        int64_t l = M->face_L[f], r = M->face_R[f];
+        double d[3] = {0, 0, 0}, cc[3] = {0, 0, 0}, ell = 0.0;
+        for (int k = 0; k < D; k++) { d[k] = ds[k * nf + f]; ell += d[k] * d[k]; }
+        ell = sqrt(ell);
+        for (int k = 0; k < D; k++) cc[k] = gc[k * nf + f] - 0.5 * d[k];
+        for (int c = 0; c < nv; c++) {
+            double pl = W[c * n + l], pr = W[c * n + r];
+            for (int k = 0; k < D; k++) {
+                double G = A[f] / ell * ((pr - pl) * cc[k] + 0.5 * (pl + pr) * d[k]);
+                acc[(c * D + k) * n + l] += G;
+                acc[(c * D + k) * n + r] -= G;
+            }
+            if (pr < phimin[c * n + l]) phimin[c * n + l] = pr;
+            if (pr > phimax[c * n + l]) phimax[c * n + l] = pr;
+            if (pl < phimin[c * n + r]) phimin[c * n + r] = pl;
+            if (pl > phimax[c * n + r]) phimax[c * n + r] = pl;
+        }
+    }
+    for (int c = 0; c < nv; c++)
+        for (int k = 0; k < D; k++)
+            for (int64_t i = 0; i < n; i++)
+                grad_raw[(c * D + k) * n + i] = acc[(c * D + k) * n + i] / M->volume[i];
+
+    /* limiter */
+    double *al = (double *)malloc(sizeof(double) * nv * n);
+    for (int64_t q = 0; q < (int64_t)nv * n; q++) al[q] = 1.0;
+    for (int64_t f = 0; f < nf; f++) {
+        int64_t side_cell[2] = {M->face_L[f], M->face_R[f]};
+        for (int s = 0; s < 2; s++) {
+            int64_t i = side_cell[s];
+            double dx[3] = {0, 0, 0};
+            for (int k = 0; k < D; k++) {
+                /* f - s_i: for L, g - delta_L; for R, g - d - delta_R */
+                double fr = gc[k * nf + f] - (s ? ds[k * nf + f] : 0.0);
+                dx[k] = fr - M->centroid_off[k * n + i];
+            }
+            for (int c = 0; c < nv; c++) {
+                double phi = W[c * n + i];
+                double dphi = 0.0;
+                for (int k = 0; k < D; k++) dphi += grad_raw[(c * D + k) * n + i] * dx[k];
+                double range = phimax[c * n + i] - phimin[c * n + i];
+                double tol = 1e-13 * fmax(fabs(phi), range);
+                double psi;
+                if (dphi > tol) psi = (phimax[c * n + i] - phi) / dphi;
+                else if (dphi < -tol) psi = (phimin[c * n + i] - phi) / dphi;
+                else psi = 1.0;
+                if (psi < al[c * n + i]) al[c * n + i] = psi;
+            }
+        }
+    }
+    for (int c = 0; c < nv; c++)
+        for (int k = 0; k < D; k++)
+            for (int64_t i = 0; i < n; i++)
+                grad_lim[(c * D + k) * n + i] = al[c * n + i] * grad_raw[(c * D + k) * n + i];
+    if (alpha) memcpy(alpha, al, sizeof(double) * nv * n);
+    free(al); free(acc); free(phimin); free(phimax);
+}
+
+/* ------------------------------------------------------------------ */
+/* Face velocity (Section 3.3, motion of the face centroid): the mean of */
+/* the two generator velocities plus the normal motion of the centroid   */
+/* induced by their residual motion,                                     */
+/*   w = (w_L + w_R)/2 + [(w_L - w_R) . (f - (r_L+r_R)/2) / |d|] d/|d|.  */
+/* ------------------------------------------------------------------ */
+void oracle_face_velocity(const om_mesh *M, double *wf)
+{
+    const int D = M->dim;
+    const int64_t n = M->n_cells, nf = M->n_faces;
+    for (int64_t f = 0; f < nf; f++) {
+        int64_t l = M->face_L[f], r = M->face_R[f];
+        double d[3] = {0, 0, 0}, cc[3] = {0, 0, 0}, ell2 = 0.0, proj = 0.0;
+        for (int k = 0; k < D; k++) {
+            d[k] = M->face_sep[k * nf + f];
+            cc[k] = M->face_ctr[k * nf + f] - 0.5 * d[k];
+            ell2 += d[k] * d[k];
+        }
+        for (int k = 0; k < D; k++)
+            proj += (M->mesh_vel[k * n + l] - M->mesh_vel[k * n + r]) * cc[k];
+        for (int k = 0; k < D; k++)
+            wf[k * nf + f] = 0.5 * (M->mesh_vel[k * n + l] + M->mesh_vel[k * n + r])
+                             + proj * d[k] / ell2;
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Step (vi): the flux across every face (Section 3.3).                  */
+/* For each side K: go to the face rest frame (v' = v - w), extrapolate  */
+/* to the face centroid with the limited gradient about the cell's       */
+/* centre of mass and half a step forward in time with the primitive     */
+/* Euler equations dW/dt = -A(W) grad W (evaluated at the cell's face-   */
+/* frame state); split the velocity into the component along the unit   */
+/* normal n = d/|d| and the transverse rest (the rotation Lambda only    */
+/* needs that split); solve the Riemann problem and sample x/t = 0; use   */
+/* the transverse velocity of the side the sample came from; form the    */
+/* moving-face flux and return to the lab frame:                         */
+/*   m_f = rho_F u_F,  Pi = m_f v_F + P_F n,                             */
+/*   eps = m_f |v_F|^2/2 + u_F P_F g/(g-1),                              */
+/*   lab flux = (m_f, Pi + m_f w, eps + Pi.w + m_f |w|^2/2).             */
+/* If an extrapolated density or pressure is not positive on either     */
+/* side, both sides use their unextrapolated face-frame cell states      */
+/* (a reading: the paper does not treat this case).                      */
+/* face_flux[c][f] = dt * A_f * Fhat_c. fallback[f] = 1 if that happened. */
+/* ------------------------------------------------------------------ */
+static void half_step(int D, double g, double dt, const double *Wc, const double grad[5][3],
+                      const double *dx, double *out)
+{
+    /* Wc: rho, v'[D], P in the face frame; grad[c][k] = d W_c/d x_k */
+    const int nv = D + 2;
+    double rho = Wc[0], P = Wc[nv - 1];
+    double div = 0.0;
+    for (int k = 0; k < D; k++) div += grad[1 + k][k];
+    double s, t;
+    /* density */
+    s = 0.0; t = 0.0;
+    for (int k = 0; k < D; k++) { s += grad[0][k] * dx[k]; t += Wc[1 + k] * grad[0][k]; }
+    out[0] = rho + s - 0.5 * dt * (t + rho * div);
+    /* velocity */
+    for (int i = 0; i < D; i++) {
+        s = 0.0; t = 0.0;
+        for (int k = 0; k < D; k++) { s += grad[1 + i][k] * dx[k]; t += Wc[1 + k] * grad[1 + i][k]; }
+        out[1 + i] = Wc[1 + i] + s - 0.5 * dt * (t + grad[nv - 1][i] / rho);
+    }
+    /* pressure */
+    s = 0.0; t = 0.0;
+    for (int k = 0; k < D; k++) { s += grad[nv - 1][k] * dx[k]; t += Wc[1 + k] * grad[nv - 1][k]; }
+    out[nv - 1] = P + s - 0.5 * dt * (t + g * P * div);
+}
+
+void oracle_face_fluxes(const om_mesh *M, const om_params *prm, double dt,
+                        const double *W, const double *grad, double *face_flux,
+                        int32_t *fallback, int32_t *kase)
+{
+    const int D = M->dim, nv = D + 2;
+    const int64_t n = M->n_cells, nf = M->n_faces;
+    const double g = prm->gamma;
+    double *wf = (double *)malloc(sizeof(double) * D * nf);
+    oracle_face_velocity(M, wf);
+
+    for (int64_t f = 0; f < nf; f++) {
+        int64_t cell[2] = {M->face_L[f], M->face_R[f]};
+        double d[3] = {0, 0, 0}, w[3] = {0, 0, 0}, nrm[3] = {0, 0, 0}, ell = 0.0;
+        for (int k = 0; k < D; k++) { d[k] = M->face_sep[k * nf + f]; ell += d[k] * d[k]; w[k] = wf[k * nf + f]; }
+        ell = sqrt(ell);
+        for (int k = 0; k < D; k++) nrm[k] = d[k] / ell;
+
+        double Wp[2][5], Wpp[2][5];
+        for (int s = 0; s < 2; s++) {
+            int64_t i = cell[s];
+            double dx[3] = {0, 0, 0}, gr[5][3];
+            for (int k = 0; k < D; k++)
+                dx[k] = M->face_ctr[k * nf + f] - (s ? d[k] : 0.0) - M->centroid_off[k * n + i];
+            Wp[s][0] = W[0 * n + i];
+            for (int k = 0; k < D; k++) Wp[s][1 + k] = W[(1 + k) * n + i] - w[k];
+            Wp[s][nv - 1] = W[(nv - 1) * n + i];
+            for (int c = 0; c < nv; c++)
+                for (int k = 0; k < D; k++) gr[c][k] = grad[(c * D + k) * n + i];
+            half_step(D, g, dt, Wp[s], gr, dx, Wpp[s]);
+        }
+        int fb = !(Wpp[0][0] > 0.0 && Wpp[0][nv - 1] > 0.0 && Wpp[1][0] > 0.0 && Wpp[1][nv - 1] > 0.0);
+        if (fb) memcpy(Wpp, Wp, sizeof(Wp));
+        if (fallback) fallback[f] = fb;
+
+        /* normal / transverse split */
+        double un[2], tr[2][3] = {{0, 0, 0}, {0, 0, 0}};
+        for (int s = 0; s < 2; s++) {
+            double u = 0.0;
+            for (int k = 0; k < D; k++) u += Wpp[s][1 + k] * nrm[k];
+            un[s] = u;
+            for (int k = 0; k < D; k++) tr[s][k] = Wpp[s][1 + k] - u * nrm[k];
+        }
+        double Ls[3] = {Wpp[0][0], un[0], Wpp[0][nv - 1]};
+        double Rs[3] = {Wpp[1][0], un[1], Wpp[1][nv - 1]};
+        double out[4], st[2];
+        int k0 = oracle_riemann(g, Ls, Rs, out, st, NULL);
+        if (kase) kase[f] = k0;
+        double rhoF = out[0], uF = out[1], PF = out[2];
+        int side = out[3] > 0.5;
+
+        double vF[3] = {0, 0, 0};
+        for (int k = 0; k < D; k++) vF[k] = uF * nrm[k] + tr[side][k];
+        double mf = rhoF * uF;
+        double v2 = 0.0, w2 = 0.0, Piw = 0.0, Pi[3] = {0, 0, 0};
+        for (int k = 0; k < D; k++) {
+            v2 += vF[k] * vF[k];
+            w2 += w[k] * w[k];
+            Pi[k] = mf * vF[k] + PF * nrm[k];
+            Piw += Pi[k] * w[k];
+        }
+        double eps = mf * 0.5 * v2 + uF * PF * g / (g - 1.0);
+        double scale = dt * M->face_area[f];
+        face_flux[0 * nf + f] = scale * mf;
+        for (int k = 0; k < D; k++) face_flux[(1 + k) * nf + f] = scale * (Pi[k] + mf * w[k]);
+        face_flux[(nv - 1) * nf + f] = scale * (eps + Piw + 0.5 * mf * w2);
+    }
+    free(wf);
+}
+
+/* ------------------------------------------------------------------ */
+/* Step (vii): conservative update, Q_i <- Q_i - dt sum_j A_ij F_ij,     */
+/* with F_ji = -F_ij (Section 3, discrete update): the left cell loses   */
+/* the face flux and the right cell gains it, in face-list order.        */
+/* ------------------------------------------------------------------ */
+void oracle_apply_update(const om_mesh *M, const double *face_flux, double *Q)
+{
+    const int nv = M->dim + 2;
+    const int64_t n = M->n_cells, nf = M->n_faces;
+    for (int64_t f = 0; f < nf; f++) {
+        int64_t l = M->face_L[f], r = M->face_R[f];
+        for (int c = 0; c < nv; c++) {
+            Q[c * n + l] -= face_flux[c * nf + f];
+            Q[c * n + r] += face_flux[c * nf + f];
+        }
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Step (v): global Courant timestep (Section 7.1):                      */
+/*   dt = C min_i R_i / (c_i + |v_i - w_i|),                             */
+/* R_i = (3V/4pi)^(1/3) in 3D, (V/pi)^(1/2) in 2D. Vacuum cells (rho<=0  */
+/* or P<=0) impose no limit.                                             */
+/* ------------------------------------------------------------------ */
+double oracle_cfl_dt(const om_mesh *M, const om_params *prm, const double *W)
+{
+    const int D = M->dim, nv = D + 2;
+    const int64_t n = M->n_cells;
+    double best = INFINITY;
+    for (int64_t i = 0; i < n; i++) {
+        double rho = W[0 * n + i], P = W[(nv - 1) * n + i];
+        if (!(rho > 0.0 && P > 0.0)) continue;
+        double R = (D == 3) ? cbrt(3.0 * M->volume[i] / (4.0 * PI_D)) : sqrt(M->volume[i] / PI_D);
+        double c = sqrt(prm->gamma * P / rho);
+        double rel = 0.0;
+        for (int k = 0; k < D; k++) {
+            double dv = W[(1 + k) * n + i] - M->mesh_vel[k * n + i];
+            rel += dv * dv;
+        }
+        double dti = prm->cfl * R / (c + sqrt(rel));
+        if (dti < best) best = dti;
+    }
+    return best;
+}
+
+/* ------------------------------------------------------------------ */
+/* Steps (ii), (iii), (v), (vi), (vii) in the order of Section 3's step  */
+/* list. dt <= 0 requests the Courant timestep. Q is updated in place.   */
+/* Returns the timestep used.                                            */
+/* ------------------------------------------------------------------ */
+double oracle_hydro_step(const om_mesh *M, const om_params *prm, double dt, double *Q)
+{
+    const int D = M->dim, nv = D + 2;
+    const int64_t n = M->n_cells, nf = M->n_faces;
+    double *W = (double *)malloc(sizeof(double) * nv * n);
+    double *gr = (double *)malloc(sizeof(double) * nv * D * n);
+    double *gl = (double *)malloc(sizeof(double) * nv * D * n);
+    double *fl = (double *)malloc(sizeof(double) * nv * nf);
+    oracle_prim(D, n, prm->gamma, M->volume, Q, W);
+    oracle_gradients(M, W, gr, gl, NULL);
+    if (!(dt > 0.0)) dt = oracle_cfl_dt(M, prm, W);
+    oracle_face_fluxes(M, prm, dt, W, gl, fl, NULL, NULL);
+    oracle_apply_update(M, fl, Q);
+    free(W); free(gr); free(gl); free(fl);
+    return dt;
+}

@@ -1,0 +1,172 @@
+"""ctypes binding of ``oracle.c`` (test infrastructure only; see the header of
+``oracle.c``). Mesh arguments are any object with the attributes ``dim,
+volume, centroid_off, mesh_vel, face_L, face_R, face_area, face_ctr,
+face_sep`` as numpy arrays in the layouts documented there."""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.environ.get("ORACLE_SO") or os.path.join(_HERE, "liboracle.so")
+_LIB = None
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int32)
+
+
+def build() -> str:
+    """Compile the oracle with gcc (plain -O2, no fast-math, no FMA)."""
+    src = os.path.join(_HERE, "oracle.c")
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall",
+                           "-ffp-contract=off", "-o", _SO, src, "-lm"])
+    return _SO
+
+
+class _OMesh(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("n_cells", ctypes.c_int64), ("n_faces", ctypes.c_int64),
+                ("volume", _dp), ("centroid_off", _dp), ("mesh_vel", _dp),
+                ("face_L", _ip), ("face_R", _ip), ("face_area", _dp),
+                ("face_ctr", _dp), ("face_sep", _dp)]
+
+
+class _OParams(ctypes.Structure):
+    _fields_ = [("gamma", ctypes.c_double), ("cfl", ctypes.c_double)]
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(_SO):
+            build()
+        lib = ctypes.CDLL(_SO)
+        lib.oracle_riemann_batch.argtypes = [ctypes.c_int64, ctypes.c_double] + [_dp] * 12 + [_ip, _ip]
+        lib.oracle_pressure_function.restype = ctypes.c_double
+        lib.oracle_pressure_function.argtypes = [ctypes.c_double, _dp, _dp, ctypes.c_double]
+        lib.oracle_prim.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_double, _dp, _dp, _dp]
+        lib.oracle_gradients.argtypes = [ctypes.POINTER(_OMesh), _dp, _dp, _dp, _dp]
+        lib.oracle_face_velocity.argtypes = [ctypes.POINTER(_OMesh), _dp]
+        lib.oracle_face_fluxes.argtypes = [ctypes.POINTER(_OMesh), ctypes.POINTER(_OParams), ctypes.c_double,
+                                           _dp, _dp, _dp, _ip, _ip]
+        lib.oracle_apply_update.argtypes = [ctypes.POINTER(_OMesh), _dp, _dp]
+        lib.oracle_cfl_dt.restype = ctypes.c_double
+        lib.oracle_cfl_dt.argtypes = [ctypes.POINTER(_OMesh), ctypes.POINTER(_OParams), _dp]
+        lib.oracle_hydro_step.restype = ctypes.c_double
+        lib.oracle_hydro_step.argtypes = [ctypes.POINTER(_OMesh), ctypes.POINTER(_OParams), ctypes.c_double, _dp]
+        _LIB = lib
+    return _LIB
+
+
+def _d(a):
+    return a.ctypes.data_as(_dp)
+
+
+def _i(a):
+    return a.ctypes.data_as(_ip)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class _Held:
+    """Keeps the numpy arrays behind an _OMesh alive."""
+
+    def __init__(self, mesh):
+        self.arrs = dict(
+            volume=_f64(mesh.volume), centroid_off=_f64(mesh.centroid_off),
+            mesh_vel=_f64(mesh.mesh_vel if mesh.mesh_vel is not None else np.zeros_like(mesh.centroid_off)),
+            face_L=np.ascontiguousarray(mesh.face_L, dtype=np.int32),
+            face_R=np.ascontiguousarray(mesh.face_R, dtype=np.int32),
+            face_area=_f64(mesh.face_area), face_ctr=_f64(mesh.face_ctr), face_sep=_f64(mesh.face_sep))
+        a = self.arrs
+        self.s = _OMesh(int(mesh.dim), a["volume"].shape[0], a["face_area"].shape[0],
+                        _d(a["volume"]), _d(a["centroid_off"]), _d(a["mesh_vel"]),
+                        _i(a["face_L"]), _i(a["face_R"]), _d(a["face_area"]),
+                        _d(a["face_ctr"]), _d(a["face_sep"]))
+        self.dim = int(mesh.dim)
+        self.n = a["volume"].shape[0]
+        self.nf = a["face_area"].shape[0]
+
+
+def riemann(gamma, rhoL, uL, PL, rhoR, uR, PR):
+    """Exact Riemann problems sampled at x/t=0. Returns a dict of arrays:
+    rho, u, P (sampled state), side (0 left / 1 right of the contact),
+    pstar, ustar (NaN where undefined), case, iters."""
+    arrs = [_f64(np.atleast_1d(x)) for x in (rhoL, uL, PL, rhoR, uR, PR)]
+    n = max(a.shape[0] for a in arrs)
+    arrs = [np.ascontiguousarray(np.broadcast_to(a, (n,))) for a in arrs]
+    out = {k: np.empty(n) for k in ("rho", "u", "P", "side", "pstar", "ustar")}
+    kase = np.empty(n, dtype=np.int32)
+    iters = np.empty(n, dtype=np.int32)
+    _lib().oracle_riemann_batch(n, float(gamma), *[_d(a) for a in arrs],
+                                _d(out["rho"]), _d(out["u"]), _d(out["P"]), _d(out["side"]),
+                                _d(out["pstar"]), _d(out["ustar"]), _i(kase), _i(iters))
+    out["case"] = kase
+    out["iters"] = iters
+    return out
+
+
+def pressure_function(gamma, L, R, p):
+    L = _f64(L); R = _f64(R)
+    return _lib().oracle_pressure_function(float(gamma), _d(L), _d(R), float(p))
+
+
+def prim(dim, gamma, volume, Q):
+    Q = _f64(Q); V = _f64(volume)
+    W = np.empty_like(Q)
+    _lib().oracle_prim(int(dim), V.shape[0], float(gamma), _d(V), _d(Q), _d(W))
+    return W
+
+
+def gradients(mesh, W):
+    h = _Held(mesh)
+    W = _f64(W)
+    nv = h.dim + 2
+    raw = np.empty((nv * h.dim, h.n)); lim = np.empty_like(raw); alpha = np.empty((nv, h.n))
+    _lib().oracle_gradients(ctypes.byref(h.s), _d(W), _d(raw), _d(lim), _d(alpha))
+    return raw, lim, alpha
+
+
+def face_velocity(mesh):
+    h = _Held(mesh)
+    wf = np.empty((h.dim, h.nf))
+    _lib().oracle_face_velocity(ctypes.byref(h.s), _d(wf))
+    return wf
+
+
+def face_fluxes(mesh, gamma, dt, W, grad):
+    h = _Held(mesh)
+    W = _f64(W); grad = _f64(grad)
+    fl = np.empty((h.dim + 2, h.nf))
+    fb = np.empty(h.nf, dtype=np.int32)
+    kase = np.empty(h.nf, dtype=np.int32)
+    p = _OParams(float(gamma), 0.0)
+    _lib().oracle_face_fluxes(ctypes.byref(h.s), ctypes.byref(p), float(dt), _d(W), _d(grad),
+                              _d(fl), _i(fb), _i(kase))
+    return fl, fb, kase
+
+
+def apply_update(mesh, face_flux, Q):
+    h = _Held(mesh)
+    Q = _f64(Q).copy()
+    _lib().oracle_apply_update(ctypes.byref(h.s), _d(_f64(face_flux)), _d(Q))
+    return Q
+
+
+def cfl_dt(mesh, gamma, cfl, W):
+    h = _Held(mesh)
+    p = _OParams(float(gamma), float(cfl))
+    return _lib().oracle_cfl_dt(ctypes.byref(h.s), ctypes.byref(p), _d(_f64(W)))
+
+
+def hydro_step(mesh, gamma, cfl, Q, dt=0.0):
+    """One full step; returns (Q_new, dt_used). dt <= 0 uses the CFL step."""
+    h = _Held(mesh)
+    Q = _f64(Q).copy()
+    p = _OParams(float(gamma), float(cfl))
+    used = _lib().oracle_hydro_step(ctypes.byref(h.s), ctypes.byref(p), float(dt), _d(Q))
+    return Q, used

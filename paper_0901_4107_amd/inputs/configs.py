@@ -1,0 +1,151 @@
+"""Seeded synthetic workloads with the shapes of the paper's test problems.
+
+Every workload is a periodic unit box tessellated by :func:`build_mesh`, with
+cells in Morton order and faces sorted by their left cell. Fluid states are
+set from primitive fields evaluated at each cell's centre of mass and turned
+into cell totals ``Q = (m, p, E)`` with ``m = rho V``, ``p = m v`` and
+``E = P V/(gamma-1) + m |v|^2/2`` (the definition of the state vector and the
+ideal-gas law, Section 3). Nothing here evaluates any step of the scheme.
+
+Workloads
+  kh2d       2D Kelvin-Helmholtz (Section 8.6), 64x64 jittered lattice.
+  random3d   3D random states on a 64^3 jittered lattice (log-uniform density
+             and pressure, Gaussian velocities of three sound speeds), fixed
+             mesh; stresses the Riemann solver.
+  kh3d       3D Kelvin-Helmholtz shear layer on Poisson points with a uniform
+             bulk boost and a comoving mesh (Galilean-invariance workload).
+  sedov3d    3D Sedov-Taylor blast on a jittered lattice (Section 8.5).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+from .mesh import Mesh, build_mesh, morton_order
+
+
+@dataclass
+class Workload:
+    name: str
+    mesh: Mesh
+    Q: np.ndarray          # [D+2][N] conserved cell totals
+    gamma: float
+    cfl: float
+    boost: np.ndarray      # [D] uniform bulk velocity added to the flow (zeros if none)
+    seed: int
+
+    @property
+    def dim(self) -> int:
+        return self.mesh.dim
+
+
+def conserved_from_primitive(volume, rho, vel, P, gamma):
+    """Cell totals from primitive values: m = rho V, p = m v, E = P V/(g-1) + m v^2/2."""
+    m = rho * volume
+    p = m[None, :] * vel
+    E = P * volume / (gamma - 1.0) + 0.5 * m * np.sum(vel * vel, axis=0)
+    return np.ascontiguousarray(np.concatenate([m[None], p, E[None]], axis=0))
+
+
+def jittered_lattice(n_side: int, dim: int, jitter: float, rng) -> np.ndarray:
+    """Lattice points (i+1/2)/n with each coordinate displaced by
+    U(-jitter, +jitter) lattice spacings, in Morton order."""
+    h = 1.0 / n_side
+    axes = [(np.arange(n_side) + 0.5) * h] * dim
+    grid = np.stack(np.meshgrid(*axes, indexing="ij"), axis=-1).reshape(-1, dim)
+    grid = grid + rng.uniform(-jitter, jitter, size=grid.shape) * h
+    grid = np.mod(grid, 1.0)
+    return grid[morton_order(grid)]
+
+
+def poisson_points(n: int, dim: int, rng) -> np.ndarray:
+    pts = rng.random((n, dim))
+    return pts[morton_order(pts)]
+
+
+def _centres(mesh: Mesh) -> np.ndarray:
+    return np.mod(mesh.positions.T + mesh.centroid_off, 1.0)   # [D][N]
+
+
+def kh2d(n_side: int = 64, jitter: float = 0.05, seed: int = 1000, nthreads: int = 0) -> Workload:
+    """2D KH: rho = 2 for |y-1/2| < 1/4 else 1, P = 2.5, v_x = +-0.5 (inside /
+    outside), v_y = w0 sin(4 pi x)[exp(-(y-1/4)^2/(2 s^2)) + exp(-(y-3/4)^2/(2 s^2))]
+    with w0 = 0.1, 2 s^2 = 0.005; gamma = 5/3. Mesh moves with the flow."""
+    rng = np.random.default_rng(seed)
+    gamma = 5.0 / 3.0
+    mesh = build_mesh(jittered_lattice(n_side, 2, jitter, rng), nthreads)
+    x, y = _centres(mesh)
+    inside = np.abs(y - 0.5) < 0.25
+    rho = np.where(inside, 2.0, 1.0)
+    P = np.full_like(rho, 2.5)
+    vx = np.where(inside, 0.5, -0.5)
+    vy = 0.1 * np.sin(4 * np.pi * x) * (np.exp(-(y - 0.25) ** 2 / 0.005) + np.exp(-(y - 0.75) ** 2 / 0.005))
+    vel = np.stack([vx, vy])
+    Q = conserved_from_primitive(mesh.volume, rho, vel, P, gamma)
+    mesh.with_velocity(vel.copy())
+    return Workload("kh2d_64x64", mesh, Q, gamma, 0.4, np.zeros(2), seed)
+
+
+def random_states(n: int, dim: int, gamma: float, rng):
+    """log10 rho, log10 P ~ U(-2, 2); each velocity component ~ N(0, (3 c)^2)
+    with c the cell's own sound speed sqrt(gamma P / rho)."""
+    rho = 10.0 ** rng.uniform(-2.0, 2.0, n)
+    P = 10.0 ** rng.uniform(-2.0, 2.0, n)
+    c = np.sqrt(gamma * P / rho)
+    vel = rng.normal(0.0, 1.0, (dim, n)) * (3.0 * c)[None, :]
+    return rho, vel, P
+
+
+def random3d(n_side: int = 64, jitter: float = 0.1, seed: int = 1001, nthreads: int = 0) -> Workload:
+    rng = np.random.default_rng(seed)
+    gamma = 5.0 / 3.0
+    mesh = build_mesh(jittered_lattice(n_side, 3, jitter, rng), nthreads)
+    rho, vel, P = random_states(mesh.n_cells, 3, gamma, rng)
+    Q = conserved_from_primitive(mesh.volume, rho, vel, P, gamma)
+    return Workload(f"random3d_{n_side}^3", mesh, Q, gamma, 0.4, np.zeros(3), seed)
+
+
+def kh3d(n_points: int = 128 ** 3, seed: int = 1002, boost_mach: float = 10.0,
+         nthreads: int = 0, points: np.ndarray | None = None) -> Workload:
+    """3D KH: the 2D profile of the paper's KH test extended uniformly in z,
+    on Poisson points, plus a bulk boost v0 = (boost_mach * c, 0, 0) with c
+    the sound speed of the lighter phase (sqrt(gamma 2.5 / 1)); the mesh moves
+    with the (boosted) flow."""
+    rng = np.random.default_rng(seed)
+    gamma = 5.0 / 3.0
+    pts = poisson_points(n_points, 3, rng) if points is None else points
+    mesh = build_mesh(pts, nthreads)
+    x, y, _ = _centres(mesh)
+    inside = np.abs(y - 0.5) < 0.25
+    rho = np.where(inside, 2.0, 1.0)
+    P = np.full_like(rho, 2.5)
+    vx = np.where(inside, 0.5, -0.5)
+    vy = 0.1 * np.sin(4 * np.pi * x) * (np.exp(-(y - 0.25) ** 2 / 0.005) + np.exp(-(y - 0.75) ** 2 / 0.005))
+    c_light = np.sqrt(gamma * 2.5 / 1.0)
+    boost = np.array([boost_mach * c_light, 0.0, 0.0])
+    vel = np.stack([vx, vy, np.zeros_like(vx)]) + boost[:, None]
+    Q = conserved_from_primitive(mesh.volume, rho, vel, P, gamma)
+    mesh.with_velocity(vel.copy())
+    return Workload(f"kh3d_poisson_{n_points}", mesh, Q, gamma, 0.4, boost, seed)
+
+
+def sedov3d(n_side: int = 256, jitter: float = 0.1, seed: int = 1004, n_hot: int = 32,
+            energy: float = 1.0, nthreads: int = 0) -> Workload:
+    """Sedov blast: rho = 1, P = 1e-5, v = 0, with total energy `energy` added
+    as thermal energy in equal parts to the n_hot cells whose generators lie
+    nearest the box centre (ties to the lower index). Mesh moves with the
+    flow (zero at the start)."""
+    rng = np.random.default_rng(seed)
+    gamma = 5.0 / 3.0
+    mesh = build_mesh(jittered_lattice(n_side, 3, jitter, rng), nthreads)
+    n = mesh.n_cells
+    rho = np.ones(n)
+    P = np.full(n, 1e-5)
+    vel = np.zeros((3, n))
+    Q = conserved_from_primitive(mesh.volume, rho, vel, P, gamma)
+    r2 = np.sum((mesh.positions - 0.5) ** 2, axis=1)
+    hot = np.lexsort((np.arange(n), r2))[:n_hot]
+    Q[4, hot] += energy / n_hot
+    mesh.with_velocity(vel.copy())
+    return Workload(f"sedov3d_{n_side}^3", mesh, Q, gamma, 0.4, np.zeros(3), seed)

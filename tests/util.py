@@ -1,0 +1,29 @@
+"""Helpers shared by the tests (no step of the scheme lives here)."""
+import numpy as np
+
+
+def boost(Q, v0):
+    """Galilean boost of cell totals by v0, Section 3.4's G(Q, v):
+    (m, p, E) -> (m, p + m v0, E + p.v0 + m |v0|^2 / 2)."""
+    D = Q.shape[0] - 2
+    v0 = np.asarray(v0, dtype=np.float64)
+    out = Q.copy()
+    out[1:1 + D] = Q[1:1 + D] + Q[0][None, :] * v0[:, None]
+    out[D + 1] = Q[D + 1] + np.sum(Q[1:1 + D] * v0[:, None], axis=0) + 0.5 * Q[0] * float(v0 @ v0)
+    return out
+
+
+def normwise_rel(a, b):
+    """Per component k: max_i |a_ki - b_ki| / max_i |b_ki|."""
+    a = np.asarray(a); b = np.asarray(b)
+    den = np.max(np.abs(b), axis=1)
+    den = np.where(den > 0, den, 1.0)
+    return np.max(np.abs(a - b), axis=1) / den
+
+
+def l1_rel(a, b):
+    """Per component k: sum_i |a_ki - b_ki| / sum_i |b_ki|."""
+    a = np.asarray(a); b = np.asarray(b)
+    den = np.sum(np.abs(b), axis=1)
+    den = np.where(den > 0, den, 1.0)
+    return np.sum(np.abs(a - b), axis=1) / den
