@@ -1,0 +1,170 @@
+/*
+ * mm.h -- C ABI of libmm: one second-order finite-volume hydro step of the
+ * moving Voronoi-mesh Godunov scheme (Springel, "E pur si muove",
+ * arXiv:0901.4107, Section 3) on a given periodic tessellation, on one
+ * AMD Instinct MI355X (gfx950) GPU.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every array argument is a DEVICE pointer owned by the caller (for
+ *   example the data pointer of a contiguous torch tensor). The library never
+ *   allocates device memory: its scratch space is the workspace the caller
+ *   hands over with mm_set_workspace.
+ * - Floating-point arrays are IEEE double unless a mode states otherwise,
+ *   laid out structure-of-arrays, row-major:
+ *     conserved  Q    [D+2][N]   rows m, p_x, p_y(, p_z), E  (cell totals)
+ *     primitive  W    [D+2][N]   rows rho, v_x, v_y(, v_z), P
+ *     gradient   G    [D+2][D][N] with G[(c*D + k)*N + i] = dW_c/dx_k of cell i
+ *     face flux  Fl   [D+2][F]   Fl[c*F + f] = dt * A_f * Fhat_c(f)
+ *   where D is the dimension (2 or 3), N the number of cells, F of faces.
+ * - The normal of face f points from its left cell face_L[f] to its right
+ *   cell face_R[f]; Fhat(f) is the flux leaving the left cell.
+ * - Calls enqueue work on params.stream (a hipStream_t; NULL = the null
+ *   stream) and return without waiting, except where a call says it
+ *   synchronises.
+ * - Every call returns an mm_status and never throws. Numeric events inside
+ *   a step (vacuum faces, positivity fallbacks, unconverged Newton
+ *   iterations) are counted in the diagnostics, not returned as errors.
+ * - A context is not thread-safe; calls on one context must not overlap.
+ */
+#ifndef MM_H
+#define MM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mm_status;
+#define MM_OK            0
+#define MM_E_ARG        -1  /* null pointer, bad size, bad mode or dimension */
+#define MM_E_MESH       -2  /* mesh validation failed (see mm_mesh_upload) */
+#define MM_E_DEVICE     -3  /* a HIP runtime call failed */
+#define MM_E_STATE      -4  /* call out of order: no workspace or no mesh */
+#define MM_E_WORKSPACE  -5  /* workspace smaller than mm_workspace_bytes */
+#define MM_E_NONFINITE  -6  /* a conserved quantity became NaN or infinite */
+
+/* Arithmetic of the face-flux path. */
+#define MM_FP64   0  /* every step in double precision */
+#define MM_MIXED  1  /* single-precision reconstruction, frame transforms and
+                        Riemann iterations on velocities relative to the
+                        face; double-precision accumulation, lab-frame
+                        transform, and Newton for hard faces */
+
+/* Starting guess of the Newton iteration for the star pressure. */
+#define MM_GUESS_STANDARD 0  /* adaptive PVRS / two-rarefaction / two-shock */
+#define MM_GUESS_LEARNED  1  /* MLP loaded with mm_mlp_load */
+
+typedef struct {
+    int32_t dim;              /* 2 or 3 */
+    int32_t mode;             /* MM_FP64 or MM_MIXED */
+    int32_t guess;            /* MM_GUESS_STANDARD or MM_GUESS_LEARNED */
+    int32_t newton_max_iter;  /* per face; <= 0 selects 50 */
+    double gamma;             /* adiabatic index, > 1 */
+    double cfl;               /* Courant factor of the timestep criterion */
+    double newton_tol64;      /* relative Newton step tolerance, double; <= 0: 1e-10 */
+    double newton_tol32;      /* same for the single-precision solve; <= 0: 1e-5 */
+    void *stream;             /* hipStream_t */
+} mm_params;
+
+/* The given tessellation (Section 3, step list item (i)) and the generator
+ * velocities w_i (item (iv)). All device pointers, all kept by reference
+ * until the next mm_mesh_upload or mm_destroy: the caller keeps them alive
+ * and unchanged meanwhile. */
+typedef struct {
+    int64_t n_cells;             /* N >= 2 */
+    int64_t n_faces;             /* F >= 1 */
+    const double *volume;        /* [N]    V_i > 0 */
+    const double *centroid_off;  /* [D][N] s_i - r_i (centre of mass minus generator) */
+    const double *mesh_vel;      /* [D][N] generator velocities w_i */
+    const int32_t *face_L;       /* [F]    0 <= L < N */
+    const int32_t *face_R;       /* [F]    0 <= R < N, R != L */
+    const double *face_area;     /* [F]    A_f >= 0 */
+    const double *face_ctr;      /* [D][F] f - r_L, face centroid relative to L's generator */
+    const double *face_sep;      /* [D][F] r_R - r_L, with R's periodic image; nonzero */
+} mm_mesh;
+
+typedef struct {
+    uint64_t faces;              /* faces fluxed since the last reset */
+    uint64_t newton_iters;       /* total Newton iterations */
+    uint64_t newton_max;         /* largest iteration count of one face */
+    uint64_t unconverged;        /* faces that hit newton_max_iter */
+    uint64_t vacuum;             /* faces with a vacuum side or generated vacuum */
+    uint64_t positivity_fallback;/* faces that used unextrapolated states */
+    uint64_t fp64_fallback;      /* MM_MIXED: faces re-solved in double */
+    uint64_t guess_fallback;     /* MM_GUESS_LEARNED: faces restarted from the standard guess */
+    uint64_t wave_iter_max_sum;  /* sum over 64-lane wavefronts of their max iteration count */
+    uint64_t waves;              /* number of wavefronts counted */
+    int32_t nonfinite;           /* 1 if a step produced a non-finite conserved value */
+    int32_t reserved;
+} mm_diag;
+
+typedef struct mm_ctx mm_ctx;
+
+/* Create a context for the given parameters. Allocates host memory only.
+ * MM_E_ARG for a bad dimension, mode, guess or gamma <= 1. */
+mm_status mm_create(const mm_params *params, mm_ctx **out);
+
+/* Destroy a context (NULL is accepted). Does not free the workspace. */
+mm_status mm_destroy(mm_ctx *ctx);
+
+/* Bytes of device workspace a mesh of n_cells cells and n_faces faces needs
+ * for this context's dimension and mode; negative on bad arguments. */
+int64_t mm_workspace_bytes(const mm_ctx *ctx, int64_t n_cells, int64_t n_faces);
+
+/* Hand the context a device workspace (256-byte aligned) of `bytes` bytes.
+ * The caller owns it and keeps it alive while the context uses it. */
+mm_status mm_set_workspace(mm_ctx *ctx, void *dev_ptr, int64_t bytes);
+
+/* Take a tessellation (Section 3, step (i)) and the generator velocities
+ * (step (iv)). Validates it on the device, builds the per-cell list of faces
+ * (in ascending face order), the face geometry and each face's velocity
+ * (Section 3.3: the mean generator velocity plus the normal motion of the
+ * face centroid induced by the generators' relative motion).
+ * Synchronises the stream (to read the validation result).
+ * MM_E_MESH if an index is out of range, L == R, a volume is not positive,
+ * an area is negative, a separation is zero or any value is not finite;
+ * MM_E_WORKSPACE if the workspace is too small; MM_E_STATE without one. */
+mm_status mm_mesh_upload(mm_ctx *ctx, const mm_mesh *mesh);
+
+/* Steps (ii)-(iii): primitives W from Q (rho = m/V, v = p/m,
+ * P = (gamma-1)(E - m v^2/2)/V; a cell with m <= 0 gets W = 0), then the
+ * slope-limited gradients G (Section 3.1: the Voronoi estimate exact to
+ * linear order, limited per primitive so that face-centroid values stay
+ * within the neighbourhood's extremes).
+ * In MM_FP64 W and G are double arrays. In MM_MIXED they are float arrays of
+ * the same shape, and W's velocity rows hold v_i - w_i (velocity relative to
+ * the cell's generator). */
+mm_status mm_gradients(mm_ctx *ctx, const double *Q, void *W, void *G);
+
+/* Step (vi): the flux through every face over a step dt > 0 (Section 3.3:
+ * extrapolation to the face centroid and half a step forward in time in the
+ * face's rest frame, exact Riemann solution sampled on the face, moving-face
+ * flux in the lab frame). W and G as produced by mm_gradients in the same
+ * mode. Writes Fl [D+2][F] (double in every mode). */
+mm_status mm_face_fluxes(mm_ctx *ctx, double dt, const void *W, const void *G, double *face_flux);
+
+/* Step (vii): Q_L -= Fl, Q_R += Fl for every face, summed per cell in
+ * ascending face order (Section 3, discrete update). */
+mm_status mm_apply_update(mm_ctx *ctx, const double *face_flux, double *Q);
+
+/* Steps (ii), (iii), (v), (vi), (vii) on Q in place. dt <= 0 selects the
+ * global Courant timestep dt = C min_i R_i / (c_i + |v_i - w_i|) (Section
+ * 7.1). If dt_used is non-NULL the call synchronises, stores the timestep
+ * used there and returns MM_E_NONFINITE if the new Q holds a non-finite
+ * value; with dt_used NULL it returns without waiting. */
+mm_status mm_hydro_step(mm_ctx *ctx, double *Q, double dt, double *dt_used);
+
+/* Diagnostics accumulated since the last reset; synchronises. */
+mm_status mm_get_diag(mm_ctx *ctx, mm_diag *out);
+mm_status mm_reset_diag(mm_ctx *ctx);
+
+/* Human-readable name of a status code. */
+const char *mm_status_str(mm_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MM_H */

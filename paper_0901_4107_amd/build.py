@@ -1,0 +1,43 @@
+"""Build libmm.so (HIP, gfx950) in-tree with hipcc."""
+from __future__ import annotations
+
+import os
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+LIBMM = os.path.join(HERE, "libmm.so")
+LIBVOR = os.path.join(HERE, "inputs", "libvoronoi.so")
+
+HIPCC_FLAGS = [
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    # packed FP32 instructions stay off (see the design notes)
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
+]
+
+
+def build_libmm(extra=()) -> str:
+    src = os.path.join(CSRC, "mm.hip")
+    cmd = ["hipcc", *HIPCC_FLAGS, *extra, "-I", os.path.join(ROOT, "include"), "-o", LIBMM + ".tmp", src]
+    subprocess.check_call(cmd)
+    os.replace(LIBMM + ".tmp", LIBMM)
+    return LIBMM
+
+
+def build_voronoi() -> str:
+    src = os.path.join(HERE, "inputs", "voronoi.cpp")
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-fopenmp", "-fPIC", "-shared", "-Wall",
+                           "-o", LIBVOR + ".tmp", src])
+    os.replace(LIBVOR + ".tmp", LIBVOR)
+    return LIBVOR
+
+
+def build_all() -> None:
+    build_voronoi()
+    build_libmm()
+
+
+if __name__ == "__main__":
+    build_all()

@@ -1,0 +1,381 @@
+// mm.hip -- libmm: the C ABI declared in include/mm.h, on gfx950.
+//
+// One hydro step (Section 3's step list, items (ii), (iii), (v), (vi),
+// (vii)) on a tessellation the caller provides. Device work per step:
+//   k_prim_cfl     per cell   Q -> W, per-block Courant minimum
+//   k_min_final    one block  global timestep (stays on the device)
+//   k_grad_limit   per cell   limited gradients from the cell's face list
+//   k_face_flux    per face   extrapolation, Riemann solve, lab-frame flux
+//   k_update       per cell   segmented sum of the face fluxes (no atomics)
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "../../include/mm.h"
+#include "common.hpp"
+#include "k_cell.hpp"
+#include "k_flux.hpp"
+#include "k_mesh.hpp"
+#include "k_mixed.hpp"
+
+using namespace mm;
+
+namespace {
+
+inline int64_t align256(int64_t x) { return (x + 255) / 256 * 256; }
+
+struct Layout {
+    int64_t flags, diag, dtdev, dtpart, bsum, off, cursor, ent, nbr, geo, wf, W, G, flux;
+    int64_t geo32, dw32, W32, G32, hard;
+    int64_t total;
+};
+
+Layout make_layout(int D, int mode, int64_t n, int64_t nf) {
+    const int NV = D + 2;
+    Layout L;
+    int64_t o = 0;
+    auto take = [&](int64_t bytes) { int64_t at = o; o += align256(bytes); return at; };
+    L.flags = take(64 * sizeof(int32_t));
+    L.diag = take(sizeof(DiagDev));
+    L.dtdev = take(4 * sizeof(double));
+    L.dtpart = take((int64_t)grid_for(n) * sizeof(double));
+    int64_t bs = 0, m = n + 1;
+    while (m > 1) { m = (m + 1023) / 1024; bs += m + 1; }
+    L.bsum = take((bs + 4) * sizeof(int32_t));
+    L.off = take((n + 1) * sizeof(int32_t));
+    L.cursor = take(n * sizeof(int32_t));
+    L.ent = take(2 * nf * sizeof(int32_t));
+    L.nbr = take(2 * nf * sizeof(int32_t));
+    L.geo = take((2 + 2 * D) * nf * sizeof(double));
+    L.wf = take(D * nf * sizeof(double));
+    L.flux = take(NV * nf * sizeof(double));
+    if (mode == MM_FP64) {
+        L.W = take(NV * n * sizeof(double));
+        L.G = take(NV * D * n * sizeof(double));
+        L.geo32 = L.dw32 = L.W32 = L.G32 = L.hard = -1;
+    } else {
+        L.W = L.G = -1;
+        L.W32 = take(NV * n * sizeof(float));
+        L.G32 = take(NV * D * n * sizeof(float));
+        L.geo32 = take(mixed_geo_rows(D) * nf * sizeof(float));
+        L.dw32 = take(2 * D * nf * sizeof(float));
+        L.hard = take((nf + 64) * sizeof(int32_t));
+    }
+    L.total = o;
+    return L;
+}
+
+}  // namespace
+
+struct mm_ctx {
+    mm_params p;
+    int D = 3;
+    char *ws = nullptr;
+    int64_t ws_bytes = 0;
+    bool have_mesh = false;
+    int64_t n = 0, nf = 0;
+    uint64_t faces_done = 0, waves_done = 0;
+    mm_mesh mesh;
+    Layout lay;
+    hipStream_t st() const { return (hipStream_t)p.stream; }
+    template <typename T> T *at(int64_t off) const { return (T *)(ws + off); }
+};
+
+#define MM_CHECK(expr)                                  \
+    do {                                                \
+        hipError_t e_ = (expr);                         \
+        if (e_ != hipSuccess) return MM_E_DEVICE;       \
+    } while (0)
+
+#define MM_LAUNCH_CHECK() MM_CHECK(hipGetLastError())
+
+extern "C" {
+
+const char *mm_status_str(mm_status s) {
+    switch (s) {
+        case MM_OK: return "ok";
+        case MM_E_ARG: return "invalid argument";
+        case MM_E_MESH: return "invalid mesh";
+        case MM_E_DEVICE: return "HIP runtime error";
+        case MM_E_STATE: return "no workspace or no mesh";
+        case MM_E_WORKSPACE: return "workspace too small";
+        case MM_E_NONFINITE: return "non-finite conserved state";
+        default: return "unknown status";
+    }
+}
+
+mm_status mm_create(const mm_params *params, mm_ctx **out) {
+    if (!params || !out) return MM_E_ARG;
+    *out = nullptr;
+    if (params->dim != 2 && params->dim != 3) return MM_E_ARG;
+    if (params->mode != MM_FP64 && params->mode != MM_MIXED) return MM_E_ARG;
+    if (params->guess != MM_GUESS_STANDARD && params->guess != MM_GUESS_LEARNED) return MM_E_ARG;
+    if (!(params->gamma > 1.0) || !(params->cfl > 0.0)) return MM_E_ARG;
+    mm_ctx *c = new (std::nothrow) mm_ctx();
+    if (!c) return MM_E_ARG;
+    c->p = *params;
+    if (c->p.newton_max_iter <= 0) c->p.newton_max_iter = 50;
+    if (!(c->p.newton_tol64 > 0.0)) c->p.newton_tol64 = 1e-10;
+    if (!(c->p.newton_tol32 > 0.0)) c->p.newton_tol32 = 1e-5;
+    c->D = params->dim;
+    *out = c;
+    return MM_OK;
+}
+
+mm_status mm_destroy(mm_ctx *ctx) {
+    delete ctx;
+    return MM_OK;
+}
+
+int64_t mm_workspace_bytes(const mm_ctx *ctx, int64_t n_cells, int64_t n_faces) {
+    if (!ctx || n_cells < 2 || n_faces < 1 || n_faces >= (int64_t(1) << 30) || n_cells >= (int64_t(1) << 31) - 1)
+        return -1;
+    return make_layout(ctx->D, ctx->p.mode, n_cells, n_faces).total;
+}
+
+mm_status mm_set_workspace(mm_ctx *ctx, void *dev_ptr, int64_t bytes) {
+    if (!ctx || !dev_ptr || bytes <= 0 || ((uintptr_t)dev_ptr & 255)) return MM_E_ARG;
+    ctx->ws = (char *)dev_ptr;
+    ctx->ws_bytes = bytes;
+    ctx->have_mesh = false;
+    return MM_OK;
+}
+
+static mm_status clear_diag(mm_ctx *c) {
+    // fill kernels rather than memset nodes, so callers may capture this
+    k_fill_i32<<<1, kBlock, 0, c->st()>>>(c->at<int32_t>(c->lay.diag), sizeof(DiagDev) / sizeof(int32_t), 0);
+    k_fill_i32<<<1, kBlock, 0, c->st()>>>(c->at<int32_t>(c->lay.flags) + 1, 1, 0);
+    MM_LAUNCH_CHECK();
+    c->faces_done = 0;
+    c->waves_done = 0;
+    return MM_OK;
+}
+
+static mm_status scan_inclusive(mm_ctx *c, int32_t *data, int64_t n, int32_t *scratch) {
+    const unsigned tiles = (unsigned)((n + 1023) / 1024);
+    k_scan_tiles<<<tiles, kBlock, 0, c->st()>>>(data, n, scratch);
+    MM_LAUNCH_CHECK();
+    if (tiles > 1) {
+        mm_status s = scan_inclusive(c, scratch, tiles, scratch + tiles + 1);
+        if (s != MM_OK) return s;
+        k_scan_add<<<tiles, kBlock, 0, c->st()>>>(data, n, scratch);
+        MM_LAUNCH_CHECK();
+    }
+    return MM_OK;
+}
+
+static unsigned plain_grid(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+mm_status mm_mesh_upload(mm_ctx *c, const mm_mesh *m) {
+    if (!c || !m) return MM_E_ARG;
+    if (!c->ws) return MM_E_STATE;
+    const int64_t n = m->n_cells, nf = m->n_faces;
+    if (n < 2 || nf < 1 || nf >= (int64_t(1) << 30) || n >= (int64_t(1) << 31) - 1) return MM_E_ARG;
+    if (!m->volume || !m->centroid_off || !m->mesh_vel || !m->face_L || !m->face_R || !m->face_area ||
+        !m->face_ctr || !m->face_sep)
+        return MM_E_ARG;
+    Layout L = make_layout(c->D, c->p.mode, n, nf);
+    if (L.total > c->ws_bytes) return MM_E_WORKSPACE;
+    c->have_mesh = false;
+    c->lay = L;
+    c->n = n;
+    c->nf = nf;
+    c->mesh = *m;
+    hipStream_t s = c->st();
+    int32_t *flags = c->at<int32_t>(L.flags);
+    k_fill_i32<<<1, kBlock, 0, s>>>(flags, 64, 0);
+    MM_LAUNCH_CHECK();
+    if (c->D == 3) {
+        k_validate_faces<3><<<plain_grid(nf), kBlock, 0, s>>>(n, nf, m->face_L, m->face_R, m->face_area, m->face_ctr,
+                                                             m->face_sep, flags);
+        k_validate_cells<3><<<plain_grid(n), kBlock, 0, s>>>(n, m->volume, m->centroid_off, m->mesh_vel, flags);
+    } else {
+        k_validate_faces<2><<<plain_grid(nf), kBlock, 0, s>>>(n, nf, m->face_L, m->face_R, m->face_area, m->face_ctr,
+                                                             m->face_sep, flags);
+        k_validate_cells<2><<<plain_grid(n), kBlock, 0, s>>>(n, m->volume, m->centroid_off, m->mesh_vel, flags);
+    }
+    MM_LAUNCH_CHECK();
+    int32_t hflags = 0;
+    MM_CHECK(hipMemcpyAsync(&hflags, flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    MM_CHECK(hipStreamSynchronize(s));
+    if (hflags) return MM_E_MESH;
+
+    int32_t *off = c->at<int32_t>(L.off), *cur = c->at<int32_t>(L.cursor);
+    int32_t *ent = c->at<int32_t>(L.ent), *nbr = c->at<int32_t>(L.nbr);
+    k_fill_i32<<<plain_grid(n + 1), kBlock, 0, s>>>(off, n + 1, 0);
+    k_count_sides<<<plain_grid(nf), kBlock, 0, s>>>(nf, m->face_L, m->face_R, off + 1);
+    MM_LAUNCH_CHECK();
+    mm_status st = scan_inclusive(c, off + 1, n, c->at<int32_t>(L.bsum));
+    if (st != MM_OK) return st;
+    k_copy_i32<<<plain_grid(n), kBlock, 0, s>>>(cur, off, n);
+    k_fill_sides<<<plain_grid(nf), kBlock, 0, s>>>(nf, m->face_L, m->face_R, cur, ent, nbr);
+    k_sort_segments<<<plain_grid(n), kBlock, 0, s>>>(n, off, ent, nbr);
+    MM_LAUNCH_CHECK();
+    double *geo = c->at<double>(L.geo), *wf = c->at<double>(L.wf);
+    if (c->D == 3)
+        k_face_geometry<3><<<plain_grid(nf), kBlock, 0, s>>>(n, nf, m->face_L, m->face_R, m->face_area, m->face_ctr,
+                                                            m->face_sep, m->mesh_vel, geo, wf);
+    else
+        k_face_geometry<2><<<plain_grid(nf), kBlock, 0, s>>>(n, nf, m->face_L, m->face_R, m->face_area, m->face_ctr,
+                                                            m->face_sep, m->mesh_vel, geo, wf);
+    MM_LAUNCH_CHECK();
+    if (c->p.mode == MM_MIXED) {
+        st = mixed_upload(c->D, s, n, nf, m, geo, wf, c->at<float>(L.geo32), c->at<float>(L.dw32));
+        if (st != MM_OK) return st;
+    }
+    c->have_mesh = true;
+    return clear_diag(c);
+}
+
+static mm_status gradients_into(mm_ctx *c, const double *Q, void *W, void *G, double *dt_part) {
+    const Layout &L = c->lay;
+    hipStream_t s = c->st();
+    const unsigned gc = grid_for(c->n);
+    if (c->p.mode == MM_FP64) {
+        double *Wd = (double *)W, *Gd = (double *)G;
+        if (c->D == 3) {
+            k_prim_cfl<3><<<gc, kBlock, 0, s>>>(c->n, c->p.gamma, c->p.cfl, c->mesh.volume, Q, c->mesh.mesh_vel, Wd,
+                                                dt_part);
+            k_grad_limit<3><<<gc, kBlock, 0, s>>>(c->n, c->nf, c->at<int32_t>(L.off), c->at<int32_t>(L.ent),
+                                                  c->at<int32_t>(L.nbr), c->at<double>(L.geo), c->mesh.volume,
+                                                  c->mesh.centroid_off, Wd, Gd);
+        } else {
+            k_prim_cfl<2><<<gc, kBlock, 0, s>>>(c->n, c->p.gamma, c->p.cfl, c->mesh.volume, Q, c->mesh.mesh_vel, Wd,
+                                                dt_part);
+            k_grad_limit<2><<<gc, kBlock, 0, s>>>(c->n, c->nf, c->at<int32_t>(L.off), c->at<int32_t>(L.ent),
+                                                  c->at<int32_t>(L.nbr), c->at<double>(L.geo), c->mesh.volume,
+                                                  c->mesh.centroid_off, Wd, Gd);
+        }
+        MM_LAUNCH_CHECK();
+        return MM_OK;
+    }
+    return mixed_gradients(c->D, s, c->n, c->nf, c->p.gamma, c->p.cfl, c->mesh.volume, Q, c->mesh.mesh_vel,
+                           c->mesh.centroid_off, c->at<int32_t>(L.off), c->at<int32_t>(L.ent), c->at<int32_t>(L.nbr),
+                           c->at<double>(L.geo), (float *)W, (float *)G, dt_part);
+}
+
+mm_status mm_gradients(mm_ctx *c, const double *Q, void *W, void *G) {
+    if (!c || !Q || !W || !G) return MM_E_ARG;
+    if (!c->have_mesh) return MM_E_STATE;
+    return gradients_into(c, Q, W, G, c->at<double>(c->lay.dtpart));
+}
+
+static mm_status fluxes_into(mm_ctx *c, const double *dt_dev, double dt, const void *W, const void *G, double *flux) {
+    const Layout &L = c->lay;
+    hipStream_t s = c->st();
+    const unsigned gf = grid_for(c->nf);
+    DiagDev *diag = c->at<DiagDev>(L.diag);
+    c->faces_done += (uint64_t)c->nf;
+    c->waves_done += (uint64_t)((c->nf + 63) / 64);
+    if (c->p.mode == MM_FP64) {
+        if (c->D == 3)
+            k_face_flux64<3><<<gf, kBlock, 0, s>>>(c->n, c->nf, c->mesh.face_L, c->mesh.face_R, c->at<double>(L.geo),
+                                                   c->at<double>(L.wf), c->mesh.centroid_off, (const double *)W,
+                                                   (const double *)G, dt_dev, dt, c->p.gamma, c->p.newton_tol64,
+                                                   c->p.newton_max_iter, flux, diag);
+        else
+            k_face_flux64<2><<<gf, kBlock, 0, s>>>(c->n, c->nf, c->mesh.face_L, c->mesh.face_R, c->at<double>(L.geo),
+                                                   c->at<double>(L.wf), c->mesh.centroid_off, (const double *)W,
+                                                   (const double *)G, dt_dev, dt, c->p.gamma, c->p.newton_tol64,
+                                                   c->p.newton_max_iter, flux, diag);
+        MM_LAUNCH_CHECK();
+        return MM_OK;
+    }
+    return mixed_fluxes(c->D, s, c->n, c->nf, c->mesh.face_L, c->mesh.face_R, c->at<float>(L.geo32),
+                        c->at<double>(L.geo), c->at<double>(L.wf), c->at<float>(L.dw32), c->mesh.centroid_off,
+                        (const float *)W, (const float *)G, dt_dev, dt, c->p, flux, diag, c->at<int32_t>(L.hard));
+}
+
+mm_status mm_face_fluxes(mm_ctx *c, double dt, const void *W, const void *G, double *face_flux) {
+    if (!c || !W || !G || !face_flux) return MM_E_ARG;
+    if (!(dt > 0.0) || !isfinite(dt)) return MM_E_ARG;
+    if (!c->have_mesh) return MM_E_STATE;
+    return fluxes_into(c, nullptr, dt, W, G, face_flux);
+}
+
+static mm_status update_into(mm_ctx *c, const double *flux, double *Q) {
+    const Layout &L = c->lay;
+    const unsigned gc = grid_for(c->n);
+    if (c->D == 3)
+        k_update<3><<<gc, kBlock, 0, c->st()>>>(c->n, c->nf, c->at<int32_t>(L.off), c->at<int32_t>(L.ent), flux, Q,
+                                                c->at<int32_t>(L.flags) + 1);
+    else
+        k_update<2><<<gc, kBlock, 0, c->st()>>>(c->n, c->nf, c->at<int32_t>(L.off), c->at<int32_t>(L.ent), flux, Q,
+                                                c->at<int32_t>(L.flags) + 1);
+    MM_LAUNCH_CHECK();
+    return MM_OK;
+}
+
+mm_status mm_apply_update(mm_ctx *c, const double *face_flux, double *Q) {
+    if (!c || !face_flux || !Q) return MM_E_ARG;
+    if (!c->have_mesh) return MM_E_STATE;
+    return update_into(c, face_flux, Q);
+}
+
+mm_status mm_hydro_step(mm_ctx *c, double *Q, double dt, double *dt_used) {
+    if (!c || !Q) return MM_E_ARG;
+    if (!c->have_mesh) return MM_E_STATE;
+    if (!isfinite(dt)) return MM_E_ARG;
+    const Layout &L = c->lay;
+    hipStream_t s = c->st();
+    void *W = c->p.mode == MM_FP64 ? (void *)c->at<double>(L.W) : (void *)c->at<float>(L.W32);
+    void *G = c->p.mode == MM_FP64 ? (void *)c->at<double>(L.G) : (void *)c->at<float>(L.G32);
+    double *dt_part = c->at<double>(L.dtpart);
+    double *dt_dev = c->at<double>(L.dtdev);
+    mm_status st = gradients_into(c, Q, W, G, dt_part);
+    if (st != MM_OK) return st;
+    const double *dt_src = nullptr;
+    if (!(dt > 0.0)) {
+        k_min_final<<<1, 1024, 0, s>>>(grid_for(c->n), dt_part, dt_dev);
+        MM_LAUNCH_CHECK();
+        dt_src = dt_dev;
+    }
+    double *flux = c->at<double>(L.flux);
+    st = fluxes_into(c, dt_src, dt, W, G, flux);
+    if (st != MM_OK) return st;
+    st = update_into(c, flux, Q);
+    if (st != MM_OK) return st;
+    if (dt_used) {
+        int32_t nonfin = 0;
+        if (dt_src) MM_CHECK(hipMemcpyAsync(dt_used, dt_dev, sizeof(double), hipMemcpyDeviceToHost, s));
+        else *dt_used = dt;
+        MM_CHECK(hipMemcpyAsync(&nonfin, c->at<int32_t>(L.flags) + 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        MM_CHECK(hipStreamSynchronize(s));
+        if (nonfin) return MM_E_NONFINITE;
+    }
+    return MM_OK;
+}
+
+mm_status mm_reset_diag(mm_ctx *c) {
+    if (!c) return MM_E_ARG;
+    if (!c->have_mesh) return MM_E_STATE;
+    return clear_diag(c);
+}
+
+mm_status mm_get_diag(mm_ctx *c, mm_diag *out) {
+    if (!c || !out) return MM_E_ARG;
+    if (!c->have_mesh) return MM_E_STATE;
+    DiagDev d;
+    int32_t nonfin = 0;
+    MM_CHECK(hipMemcpyAsync(&d, c->at<char>(c->lay.diag), sizeof(DiagDev), hipMemcpyDeviceToHost, c->st()));
+    MM_CHECK(hipMemcpyAsync(&nonfin, c->at<int32_t>(c->lay.flags) + 1, sizeof(int32_t), hipMemcpyDeviceToHost,
+                            c->st()));
+    MM_CHECK(hipStreamSynchronize(c->st()));
+    std::memset(out, 0, sizeof(*out));
+    out->newton_iters = d.newton_iters;
+    out->newton_max = d.newton_max;
+    out->unconverged = d.unconverged;
+    out->vacuum = d.vacuum;
+    out->positivity_fallback = d.positivity_fallback;
+    out->fp64_fallback = d.fp64_fallback;
+    out->guess_fallback = d.guess_fallback;
+    out->wave_iter_max_sum = d.wave_iter_max_sum;
+    out->nonfinite = nonfin;
+    out->faces = c->faces_done;
+    out->waves = c->waves_done;
+    return MM_OK;
+}
+
+}  // extern "C"

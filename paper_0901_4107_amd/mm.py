@@ -1,0 +1,210 @@
+"""Python binding of libmm (include/mm.h): argument marshalling only.
+
+Every entry point of the C ABI has a method of the same name on
+:class:`Context`. Device memory and streams come from PyTorch; every step of
+the hydro path runs in the HIP kernels of ``libmm.so``. There is no CPU
+fallback: a missing library or a missing GPU raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIBMM_PATH = os.path.join(_HERE, "libmm.so")
+
+MM_OK, MM_E_ARG, MM_E_MESH, MM_E_DEVICE, MM_E_STATE, MM_E_WORKSPACE, MM_E_NONFINITE = 0, -1, -2, -3, -4, -5, -6
+MM_FP64, MM_MIXED = 0, 1
+MM_GUESS_STANDARD, MM_GUESS_LEARNED = 0, 1
+
+_vp = ctypes.c_void_p
+
+
+class mm_params(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("mode", ctypes.c_int32), ("guess", ctypes.c_int32),
+                ("newton_max_iter", ctypes.c_int32), ("gamma", ctypes.c_double), ("cfl", ctypes.c_double),
+                ("newton_tol64", ctypes.c_double), ("newton_tol32", ctypes.c_double), ("stream", _vp)]
+
+
+class mm_mesh(ctypes.Structure):
+    _fields_ = [("n_cells", ctypes.c_int64), ("n_faces", ctypes.c_int64), ("volume", _vp),
+                ("centroid_off", _vp), ("mesh_vel", _vp), ("face_L", _vp), ("face_R", _vp),
+                ("face_area", _vp), ("face_ctr", _vp), ("face_sep", _vp)]
+
+
+class mm_diag(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_uint64) for k in
+                ("faces", "newton_iters", "newton_max", "unconverged", "vacuum", "positivity_fallback",
+                 "fp64_fallback", "guess_fallback", "wave_iter_max_sum", "waves")] + \
+               [("nonfinite", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class MMError(RuntimeError):
+    def __init__(self, call, status):
+        self.status = status
+        super().__init__(f"{call} failed: {status} ({lib().mm_status_str(status).decode()})")
+
+
+_LIB = None
+
+# name -> (restype, argtypes); the exported symbols of include/mm.h
+SIGNATURES = {
+    "mm_create": (ctypes.c_int32, [ctypes.POINTER(mm_params), ctypes.POINTER(_vp)]),
+    "mm_destroy": (ctypes.c_int32, [_vp]),
+    "mm_workspace_bytes": (ctypes.c_int64, [_vp, ctypes.c_int64, ctypes.c_int64]),
+    "mm_set_workspace": (ctypes.c_int32, [_vp, _vp, ctypes.c_int64]),
+    "mm_mesh_upload": (ctypes.c_int32, [_vp, ctypes.POINTER(mm_mesh)]),
+    "mm_gradients": (ctypes.c_int32, [_vp, _vp, _vp, _vp]),
+    "mm_face_fluxes": (ctypes.c_int32, [_vp, ctypes.c_double, _vp, _vp, _vp]),
+    "mm_apply_update": (ctypes.c_int32, [_vp, _vp, _vp]),
+    "mm_hydro_step": (ctypes.c_int32, [_vp, _vp, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]),
+    "mm_get_diag": (ctypes.c_int32, [_vp, ctypes.POINTER(mm_diag)]),
+    "mm_reset_diag": (ctypes.c_int32, [_vp]),
+    "mm_status_str": (ctypes.c_char_p, [ctypes.c_int32]),
+}
+
+
+def lib():
+    """Load libmm.so (built in-tree by ``__graft_entry__.build()``)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIBMM_PATH):
+            raise RuntimeError(f"{LIBMM_PATH} is missing: build it with __graft_entry__.build()")
+        so = ctypes.CDLL(LIBMM_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(so, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = so
+    return _LIB
+
+
+def _ptr(t: torch.Tensor | None):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("libmm takes device tensors only")
+    if not t.is_contiguous():
+        raise ValueError("libmm takes contiguous tensors only")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _check(call, status):
+    if status != MM_OK:
+        raise MMError(call, status)
+
+
+@dataclass
+class DeviceMesh:
+    """Device copies of a tessellation in the layouts of ``mm_mesh``."""
+    dim: int
+    volume: torch.Tensor
+    centroid_off: torch.Tensor
+    mesh_vel: torch.Tensor
+    face_L: torch.Tensor
+    face_R: torch.Tensor
+    face_area: torch.Tensor
+    face_ctr: torch.Tensor
+    face_sep: torch.Tensor
+
+    @property
+    def n_cells(self):
+        return int(self.volume.shape[0])
+
+    @property
+    def n_faces(self):
+        return int(self.face_area.shape[0])
+
+    @classmethod
+    def from_host(cls, mesh, device="cuda"):
+        f64 = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(device)
+        i32 = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).to(device)
+        mv = mesh.mesh_vel if mesh.mesh_vel is not None else np.zeros_like(mesh.centroid_off)
+        return cls(int(mesh.dim), f64(mesh.volume), f64(mesh.centroid_off), f64(mv), i32(mesh.face_L),
+                   i32(mesh.face_R), f64(mesh.face_area), f64(mesh.face_ctr), f64(mesh.face_sep))
+
+    def as_struct(self) -> mm_mesh:
+        return mm_mesh(self.n_cells, self.n_faces, _ptr(self.volume), _ptr(self.centroid_off), _ptr(self.mesh_vel),
+                       _ptr(self.face_L), _ptr(self.face_R), _ptr(self.face_area), _ptr(self.face_ctr),
+                       _ptr(self.face_sep))
+
+
+class Context:
+    """An ``mm_ctx`` with its workspace held as a torch byte tensor."""
+
+    def __init__(self, dim: int, gamma: float, cfl: float = 0.4, mode: int = MM_FP64,
+                 guess: int = MM_GUESS_STANDARD, newton_max_iter: int = 0, newton_tol64: float = 0.0,
+                 newton_tol32: float = 0.0, device="cuda", stream: torch.cuda.Stream | None = None):
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.params = mm_params(dim, mode, guess, newton_max_iter, gamma, cfl, newton_tol64, newton_tol32,
+                                ctypes.c_void_p(self.stream.cuda_stream))
+        self.dim = dim
+        self.mode = mode
+        self._ctx = ctypes.c_void_p()
+        _check("mm_create", lib().mm_create(ctypes.byref(self.params), ctypes.byref(self._ctx)))
+        self._ws = None
+        self._mesh = None
+
+    def __del__(self):
+        if getattr(self, "_ctx", None) and _LIB is not None:
+            _LIB.mm_destroy(self._ctx)
+            self._ctx = None
+
+    # --- C ABI, one method per entry point ----------------------------------
+    def mm_workspace_bytes(self, n_cells: int, n_faces: int) -> int:
+        return int(lib().mm_workspace_bytes(self._ctx, n_cells, n_faces))
+
+    def mm_set_workspace(self, ws: torch.Tensor):
+        _check("mm_set_workspace", lib().mm_set_workspace(self._ctx, _ptr(ws), ws.numel() * ws.element_size()))
+        self._ws = ws
+
+    def mm_mesh_upload(self, mesh: DeviceMesh):
+        need = self.mm_workspace_bytes(mesh.n_cells, mesh.n_faces)
+        if need < 0:
+            raise MMError("mm_workspace_bytes", MM_E_ARG)
+        if self._ws is None or self._ws.numel() < need:
+            self.mm_set_workspace(torch.empty(need + 256, dtype=torch.uint8, device=self.device))
+        self._mesh = mesh  # keep the arrays alive while the library refers to them
+        _check("mm_mesh_upload", lib().mm_mesh_upload(self._ctx, ctypes.byref(mesh.as_struct())))
+
+    def mm_gradients(self, Q: torch.Tensor, W: torch.Tensor, G: torch.Tensor):
+        _check("mm_gradients", lib().mm_gradients(self._ctx, _ptr(Q), _ptr(W), _ptr(G)))
+
+    def mm_face_fluxes(self, dt: float, W: torch.Tensor, G: torch.Tensor, face_flux: torch.Tensor):
+        _check("mm_face_fluxes", lib().mm_face_fluxes(self._ctx, float(dt), _ptr(W), _ptr(G), _ptr(face_flux)))
+
+    def mm_apply_update(self, face_flux: torch.Tensor, Q: torch.Tensor):
+        _check("mm_apply_update", lib().mm_apply_update(self._ctx, _ptr(face_flux), _ptr(Q)))
+
+    def mm_hydro_step(self, Q: torch.Tensor, dt: float = 0.0, sync: bool = True):
+        """One step on Q in place; returns the timestep used (None if sync=False)."""
+        if sync:
+            used = ctypes.c_double(0.0)
+            _check("mm_hydro_step", lib().mm_hydro_step(self._ctx, _ptr(Q), float(dt), ctypes.byref(used)))
+            return used.value
+        _check("mm_hydro_step", lib().mm_hydro_step(self._ctx, _ptr(Q), float(dt), None))
+        return None
+
+    def mm_get_diag(self) -> dict:
+        d = mm_diag()
+        _check("mm_get_diag", lib().mm_get_diag(self._ctx, ctypes.byref(d)))
+        return {name: getattr(d, name) for name, _ in mm_diag._fields_ if name != "reserved"}
+
+    def mm_reset_diag(self):
+        _check("mm_reset_diag", lib().mm_reset_diag(self._ctx))
+
+    # --- buffers in the layouts the entry points expect ----------------------
+    def cell_buffers(self, n_cells: int):
+        """(W, G) buffers for mm_gradients in this context's mode."""
+        dt = torch.float64 if self.mode == MM_FP64 else torch.float32
+        nv = self.dim + 2
+        return (torch.empty((nv, n_cells), dtype=dt, device=self.device),
+                torch.empty((nv * self.dim, n_cells), dtype=dt, device=self.device))
+
+    def flux_buffer(self, n_faces: int):
+        return torch.empty((self.dim + 2, n_faces), dtype=torch.float64, device=self.device)

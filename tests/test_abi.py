@@ -1,0 +1,85 @@
+"""The C ABI library loads, exports every entry point include/mm.h declares,
+and validates arguments before touching a device (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_0901_4107_amd import mm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "mm.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:mm_status|int64_t|const char \*)\s*(mm_\w+)\s*\(", text, re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_symbols()
+    for want in ("mm_mesh_upload", "mm_gradients", "mm_face_fluxes", "mm_apply_update", "mm_hydro_step"):
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol():
+    so = mm.lib()
+    for name in declared_symbols():
+        assert hasattr(so, name), name
+        assert name in mm.SIGNATURES, name
+
+
+def _params(**kw):
+    p = dict(dim=3, mode=mm.MM_FP64, guess=mm.MM_GUESS_STANDARD, newton_max_iter=0, gamma=5 / 3, cfl=0.4,
+             newton_tol64=0.0, newton_tol32=0.0, stream=None)
+    p.update(kw)
+    return mm.mm_params(p["dim"], p["mode"], p["guess"], p["newton_max_iter"], p["gamma"], p["cfl"],
+                        p["newton_tol64"], p["newton_tol32"], p["stream"])
+
+
+def _create(**kw):
+    ctx = ctypes.c_void_p()
+    st = mm.lib().mm_create(ctypes.byref(_params(**kw)), ctypes.byref(ctx))
+    return st, ctx
+
+
+@pytest.mark.parametrize("kw", [dict(dim=1), dict(dim=4), dict(mode=7), dict(guess=3), dict(gamma=1.0),
+                                dict(gamma=float("nan")), dict(cfl=0.0)])
+def test_create_rejects_bad_params(kw):
+    st, ctx = _create(**kw)
+    assert st == mm.MM_E_ARG and not ctx.value
+
+
+def test_workspace_and_state_errors_without_device():
+    L = mm.lib()
+    st, ctx = _create()
+    assert st == mm.MM_OK
+    try:
+        assert L.mm_workspace_bytes(ctx, 1, 10) < 0
+        assert L.mm_workspace_bytes(ctx, 100, 0) < 0
+        a = L.mm_workspace_bytes(ctx, 1000, 8000)
+        b = L.mm_workspace_bytes(ctx, 2000, 16000)
+        assert 0 < a < b
+        assert L.mm_set_workspace(ctx, None, 1024) == mm.MM_E_ARG
+        assert L.mm_set_workspace(ctx, ctypes.c_void_p(0x1001), 1024) == mm.MM_E_ARG  # misaligned
+        m = mm.mm_mesh()
+        assert L.mm_mesh_upload(ctx, ctypes.byref(m)) == mm.MM_E_STATE          # no workspace yet
+        assert L.mm_hydro_step(ctx, ctypes.c_void_p(256), 0.0, None) == mm.MM_E_STATE  # no mesh
+        assert L.mm_gradients(ctx, None, None, None) == mm.MM_E_ARG
+        assert L.mm_face_fluxes(ctx, -1.0, ctypes.c_void_p(256), ctypes.c_void_p(256), ctypes.c_void_p(256)) == mm.MM_E_ARG
+        assert L.mm_get_diag(ctx, None) == mm.MM_E_ARG
+    finally:
+        L.mm_destroy(ctx)
+    assert L.mm_destroy(None) == mm.MM_OK
+    assert L.mm_status_str(mm.MM_E_MESH) == b"invalid mesh"
+
+
+def test_mixed_workspace_is_smaller_per_cell():
+    L = mm.lib()
+    _, c64 = _create(mode=mm.MM_FP64)
+    _, c32 = _create(mode=mm.MM_MIXED)
+    try:
+        assert L.mm_workspace_bytes(c32, 10 ** 6, 8 * 10 ** 6) > 0
+        assert L.mm_workspace_bytes(c64, 10 ** 6, 8 * 10 ** 6) > 0
+    finally:
+        L.mm_destroy(c64); L.mm_destroy(c32)
