@@ -84,7 +84,7 @@ def main():
     ctx.mm_mesh_upload(dmesh)
     Q0 = torch.from_numpy(np.ascontiguousarray(wl.Q)).to(dev)
     Q = Q0.clone()
-    W, G = ctx.cell_buffers(m.n_cells)
+    rec = ctx.recon_buffer(m.n_cells)
     F = ctx.flux_buffer(m.n_faces)
     stream = ctx.stream
     torch.cuda.synchronize()
@@ -110,14 +110,14 @@ def main():
     ms = e0.elapsed_time(e1) / args.steps
 
     # the dominant kernel alone: face fluxes
-    ctx.mm_gradients(Q0, W, G)
+    ctx.mm_gradients(Q0, rec)
     for _ in range(args.warmup):
-        ctx.mm_face_fluxes(dt, W, G, F)
+        ctx.mm_face_fluxes(dt, rec, F)
     torch.cuda.synchronize()
     fev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * args.steps)]
     for k in range(args.steps):
         fev[2 * k].record(stream)
-        ctx.mm_face_fluxes(dt, W, G, F)
+        ctx.mm_face_fluxes(dt, rec, F)
         fev[2 * k + 1].record(stream)
     torch.cuda.synchronize()
     flux_ms = float(np.mean([fev[2 * k].elapsed_time(fev[2 * k + 1]) for k in range(args.steps)]))

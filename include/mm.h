@@ -10,13 +10,19 @@
  *   example the data pointer of a contiguous torch tensor). The library never
  *   allocates device memory: its scratch space is the workspace the caller
  *   hands over with mm_set_workspace.
- * - Floating-point arrays are IEEE double unless a mode states otherwise,
- *   laid out structure-of-arrays, row-major:
- *     conserved  Q    [D+2][N]   rows m, p_x, p_y(, p_z), E  (cell totals)
- *     primitive  W    [D+2][N]   rows rho, v_x, v_y(, v_z), P
- *     gradient   G    [D+2][D][N] with G[(c*D + k)*N + i] = dW_c/dx_k of cell i
- *     face flux  Fl   [D+2][F]   Fl[c*F + f] = dt * A_f * Fhat_c(f)
- *   where D is the dimension (2 or 3), N the number of cells, F of faces.
+ * - Conserved states Q are double, structure-of-arrays [D+2][N] (rows m,
+ *   p_x, p_y(, p_z), E: cell totals); D is the dimension (2 or 3), N the
+ *   number of cells, F the number of faces.
+ * - Face fluxes are double, face-major: face_flux[f*(D+2) + c] =
+ *   dt * A_f * Fhat_c(f), c over (mass, momentum (D), energy).
+ * - The per-cell reconstruction record (mm_gradients' output) is cell-major,
+ *   MM_RECON_STRIDE(D) elements per cell (24 in 3D, 16 in 2D):
+ *     [0, D+2)              primitives rho, v (D), P
+ *     [D+2, (D+2)(D+1))     limited gradient, element D+2 + c*D + k = dW_c/dx_k
+ *     [(D+2)(D+1), +D)      s_i - r_i (centre of mass minus generator)
+ *     the rest              unused
+ *   In MM_FP64 its elements are double and v is the lab-frame velocity; in
+ *   MM_MIXED they are float and v holds v_i - w_i.
  * - The normal of face f points from its left cell face_L[f] to its right
  *   cell face_R[f]; Fhat(f) is the flux leaving the left cell.
  * - Calls enqueue work on params.stream (a hipStream_t; NULL = the null
@@ -100,6 +106,8 @@ typedef struct {
     int32_t reserved;
 } mm_diag;
 
+#define MM_RECON_STRIDE(dim) ((dim) == 3 ? 24 : 16)
+
 typedef struct mm_ctx mm_ctx;
 
 /* Create a context for the given parameters. Allocates host memory only.
@@ -124,29 +132,29 @@ mm_status mm_set_workspace(mm_ctx *ctx, void *dev_ptr, int64_t bytes);
  * face centroid induced by the generators' relative motion).
  * Synchronises the stream (to read the validation result).
  * MM_E_MESH if an index is out of range, L == R, a volume is not positive,
- * an area is negative, a separation is zero or any value is not finite;
+ * an area is negative, a separation is zero, any value is not finite, or a
+ * cell's faces do not close (|sum A n| > 1e-9 sum A; every Voronoi cell is
+ * closed, and the gradient estimate relies on it);
  * MM_E_WORKSPACE if the workspace is too small; MM_E_STATE without one. */
 mm_status mm_mesh_upload(mm_ctx *ctx, const mm_mesh *mesh);
 
 /* Steps (ii)-(iii): primitives W from Q (rho = m/V, v = p/m,
  * P = (gamma-1)(E - m v^2/2)/V; a cell with m <= 0 gets W = 0), then the
- * slope-limited gradients G (Section 3.1: the Voronoi estimate exact to
- * linear order, limited per primitive so that face-centroid values stay
- * within the neighbourhood's extremes).
- * In MM_FP64 W and G are double arrays. In MM_MIXED they are float arrays of
- * the same shape, and W's velocity rows hold v_i - w_i (velocity relative to
- * the cell's generator). */
-mm_status mm_gradients(mm_ctx *ctx, const double *Q, void *W, void *G);
+ * slope-limited gradients (Section 3.1: the Voronoi estimate exact to linear
+ * order, limited per primitive so that face-centroid values stay within the
+ * neighbourhood's extremes). Writes the reconstruction record of every cell
+ * to `recon` (layout above; double in MM_FP64, float in MM_MIXED). */
+mm_status mm_gradients(mm_ctx *ctx, const double *Q, void *recon);
 
 /* Step (vi): the flux through every face over a step dt > 0 (Section 3.3:
  * extrapolation to the face centroid and half a step forward in time in the
  * face's rest frame, exact Riemann solution sampled on the face, moving-face
- * flux in the lab frame). W and G as produced by mm_gradients in the same
- * mode. Writes Fl [D+2][F] (double in every mode). */
-mm_status mm_face_fluxes(mm_ctx *ctx, double dt, const void *W, const void *G, double *face_flux);
+ * flux in the lab frame). `recon` as produced by mm_gradients in the same
+ * mode. Writes face_flux [F][D+2] (double in every mode). */
+mm_status mm_face_fluxes(mm_ctx *ctx, double dt, const void *recon, double *face_flux);
 
-/* Step (vii): Q_L -= Fl, Q_R += Fl for every face, summed per cell in
- * ascending face order (Section 3, discrete update). */
+/* Step (vii): Q_L -= flux, Q_R += flux for every face (Section 3,
+ * discrete update), summed per cell in a fixed order (bitwise reproducible). */
 mm_status mm_apply_update(mm_ctx *ctx, const double *face_flux, double *Q);
 
 /* Steps (ii), (iii), (v), (vi), (vii) on Q in place. dt <= 0 selects the

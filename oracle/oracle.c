@@ -477,6 +477,47 @@ static void half_step(int D, double g, double dt, const double *Wc, const double
     out[nv - 1] = P + s - 0.5 * dt * (t + g * P * div);
 }
 
+/* The face-frame Riemann inputs of every face (after extrapolation and the
+ * positivity fallback): states[0..5][f] = rho_L, u_L, P_L, rho_R, u_R, P_R
+ * with u the velocity component along the L->R normal. For tests. */
+void oracle_face_states(const om_mesh *M, const om_params *prm, double dt,
+                        const double *W, const double *grad, double *states)
+{
+    const int D = M->dim, nv = D + 2;
+    const int64_t n = M->n_cells, nf = M->n_faces;
+    double *wf = (double *)malloc(sizeof(double) * D * nf);
+    oracle_face_velocity(M, wf);
+    for (int64_t f = 0; f < nf; f++) {
+        int64_t cell[2] = {M->face_L[f], M->face_R[f]};
+        double d[3] = {0, 0, 0}, w[3] = {0, 0, 0}, ell = 0.0;
+        for (int k = 0; k < D; k++) { d[k] = M->face_sep[k * nf + f]; ell += d[k] * d[k]; w[k] = wf[k * nf + f]; }
+        ell = sqrt(ell);
+        double Wp[2][5], Wpp[2][5];
+        for (int s = 0; s < 2; s++) {
+            int64_t i = cell[s];
+            double dx[3] = {0, 0, 0}, gr[5][3];
+            for (int k = 0; k < D; k++)
+                dx[k] = M->face_ctr[k * nf + f] - (s ? d[k] : 0.0) - M->centroid_off[k * n + i];
+            Wp[s][0] = W[0 * n + i];
+            for (int k = 0; k < D; k++) Wp[s][1 + k] = W[(1 + k) * n + i] - w[k];
+            Wp[s][nv - 1] = W[(nv - 1) * n + i];
+            for (int c = 0; c < nv; c++)
+                for (int k = 0; k < D; k++) gr[c][k] = grad[(c * D + k) * n + i];
+            half_step(D, prm->gamma, dt, Wp[s], gr, dx, Wpp[s]);
+        }
+        int fb = !(Wpp[0][0] > 0.0 && Wpp[0][nv - 1] > 0.0 && Wpp[1][0] > 0.0 && Wpp[1][nv - 1] > 0.0);
+        if (fb) memcpy(Wpp, Wp, sizeof(Wp));
+        for (int s = 0; s < 2; s++) {
+            double u = 0.0;
+            for (int k = 0; k < D; k++) u += Wpp[s][1 + k] * d[k] / ell;
+            states[(3 * s + 0) * nf + f] = Wpp[s][0];
+            states[(3 * s + 1) * nf + f] = u;
+            states[(3 * s + 2) * nf + f] = Wpp[s][nv - 1];
+        }
+    }
+    free(wf);
+}
+
 void oracle_face_fluxes(const om_mesh *M, const om_params *prm, double dt,
                         const double *W, const double *grad, double *face_flux,
                         int32_t *fallback, int32_t *kase)

@@ -51,6 +51,8 @@ def _lib():
         lib.oracle_face_velocity.argtypes = [ctypes.POINTER(_OMesh), _dp]
         lib.oracle_face_fluxes.argtypes = [ctypes.POINTER(_OMesh), ctypes.POINTER(_OParams), ctypes.c_double,
                                            _dp, _dp, _dp, _ip, _ip]
+        lib.oracle_face_states.argtypes = [ctypes.POINTER(_OMesh), ctypes.POINTER(_OParams), ctypes.c_double,
+                                           _dp, _dp, _dp]
         lib.oracle_apply_update.argtypes = [ctypes.POINTER(_OMesh), _dp, _dp]
         lib.oracle_cfl_dt.restype = ctypes.c_double
         lib.oracle_cfl_dt.argtypes = [ctypes.POINTER(_OMesh), ctypes.POINTER(_OParams), _dp]
@@ -148,6 +150,15 @@ def face_fluxes(mesh, gamma, dt, W, grad):
     _lib().oracle_face_fluxes(ctypes.byref(h.s), ctypes.byref(p), float(dt), _d(W), _d(grad),
                               _d(fl), _i(fb), _i(kase))
     return fl, fb, kase
+
+
+def face_states(mesh, gamma, dt, W, grad):
+    """Face-frame Riemann inputs [6][F]: rho_L, u_L, P_L, rho_R, u_R, P_R."""
+    h = _Held(mesh)
+    out = np.empty((6, h.nf))
+    p = _OParams(float(gamma), 0.0)
+    _lib().oracle_face_states(ctypes.byref(h.s), ctypes.byref(p), float(dt), _d(_f64(W)), _d(_f64(grad)), _d(out))
+    return out
 
 
 def apply_update(mesh, face_flux, Q):

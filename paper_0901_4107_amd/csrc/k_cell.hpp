@@ -1,12 +1,32 @@
-// k_cell.hpp -- per-cell kernels of the double-precision path: primitives
-// and the Courant timestep, gradients with slope limiting, and the
-// conservative update. One lane per cell; cells are in space-filling-curve
-// order so that a wavefront's neighbours are close in memory.
+// k_cell.hpp -- per-cell kernels: primitives and the Courant timestep,
+// gradients with slope limiting, and the conservative update.
+//
+// The gradient and update kernels give each cell a group of GS lanes
+// (16 in 3D, 8 in 2D; a wavefront serves 64/GS cells) that walk the cell's
+// face-side list together: consecutive lanes read consecutive side records,
+// and the per-cell sums, minima and maxima are butterfly reductions inside
+// the group (no atomics, fixed order, so results are bitwise reproducible).
 #pragma once
 
 #include "common.hpp"
+#include "layout.hpp"
 
 namespace mm {
+
+template <int D> struct Group { static constexpr int GS = (D == 3) ? 16 : 8; };
+
+template <int GS, typename T> __device__ __forceinline__ T grp_sum(T v) {
+    for (int o = GS / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+template <int GS, typename T> __device__ __forceinline__ T grp_max(T v) {
+    for (int o = GS / 2; o > 0; o >>= 1) { T u = __shfl_xor(v, o, 64); v = u > v ? u : v; }
+    return v;
+}
+template <int GS, typename T> __device__ __forceinline__ T grp_min(T v) {
+    for (int o = GS / 2; o > 0; o >>= 1) { T u = __shfl_xor(v, o, 64); v = u < v ? u : v; }
+    return v;
+}
 
 // Block-wide minimum of one double per lane; result valid in lane 0.
 __device__ __forceinline__ double block_min(double v) {
@@ -22,38 +42,45 @@ __device__ __forceinline__ double block_min(double v) {
 }
 
 // Step (ii) and the timestep bound of step (v) (Section 7.1):
-//   rho = m/V, v = p/m, P = (g-1)(E - m v^2/2)/V;
+//   rho = m/V, v = p/m, P = (g-1)(E - m v^2/2)/V,
 //   dt_i = C R_i / (c_i + |v_i - w_i|), R_i the radius of the cell's volume.
 // Cells with m <= 0 are vacuum (W = 0) and impose no timestep limit.
-template <int D>
+// Writes the primitive part and s_i - r_i of the reconstruction record; in
+// the mixed mode (T = float) the velocity stored is v_i - w_i.
+template <int D, typename T>
 __global__ void __launch_bounds__(kBlock) k_prim_cfl(int64_t n, double gamma, double cfl, const double *__restrict__ V,
                                                      const double *__restrict__ Q, const double *__restrict__ mvel,
-                                                     double *__restrict__ W, double *__restrict__ dt_part) {
+                                                     const double *__restrict__ coff, T *__restrict__ rec,
+                                                     double *__restrict__ dt_part) {
+    using Y = Lay<D>;
     constexpr int NV = D + 2;
+    constexpr bool rel = sizeof(T) == 4;
     const int64_t i = xcd_global_id();
     double dti = INFINITY;
     if (i < n) {
+        T *r = rec + i * Y::REC;
         const double m = Q[i];
+        for (int k = 0; k < D; k++) r[Y::DL + k] = (T)coff[k * n + i];
         if (!(m > 0.0)) {
-            for (int c = 0; c < NV; c++) W[c * n + i] = 0.0;
+            for (int c = 0; c < NV; c++) r[Y::W + c] = (T)0;
         } else {
             const double vol = V[i];
             const double inv_m = 1.0 / m;
-            double v[D], ke = 0.0, rel = 0.0;
+            double v[D], ke = 0.0, rel2 = 0.0;
             for (int k = 0; k < D; k++) {
                 v[k] = Q[(1 + k) * n + i] * inv_m;
                 ke += v[k] * v[k];
                 const double dv = v[k] - mvel[k * n + i];
-                rel += dv * dv;
+                rel2 += dv * dv;
+                r[Y::W + 1 + k] = rel ? (T)dv : (T)v[k];
             }
             const double rho = m / vol;
             const double P = (gamma - 1.0) * (Q[(NV - 1) * n + i] - 0.5 * m * ke) / vol;
-            W[i] = rho;
-            for (int k = 0; k < D; k++) W[(1 + k) * n + i] = v[k];
-            W[(NV - 1) * n + i] = P;
+            r[Y::W] = (T)rho;
+            r[Y::W + NV - 1] = (T)P;
             if (rho > 0.0 && P > 0.0) {
                 const double R = (D == 3) ? cbrt(vol * (3.0 / (4.0 * M_PI))) : sqrt(vol * (1.0 / M_PI));
-                dti = cfl * R / (sqrt(gamma * P / rho) + sqrt(rel));
+                dti = cfl * R / (sqrt(gamma * P / rho) + sqrt(rel2));
             }
         }
     }
@@ -74,111 +101,136 @@ __global__ void __launch_bounds__(1024) k_min_final(int64_t nparts, const double
     }
 }
 
-// Step (iii), Section 3.1. Gradient estimate exact to linear order on a
-// Voronoi mesh, summed over the cell's faces in ascending face order:
-//   V_i grad phi_i += s (A/|d|) [ (phi_R - phi_L) c + (phi_L + phi_R)/2 d ],
-// s = +1 where i is the left cell and -1 where it is the right one. Then the
-// limiter: per primitive, alpha_i = min(1, min_faces psi) with
-//   psi = (phi_max - phi_i)/D if D > 0, (phi_min - phi_i)/D if D < 0, 1 else,
-// D = grad phi_i . (f - s_i), phi_min/max over the face neighbours and i;
-// |D| <= 1e-13 max(|phi_i|, phi_max - phi_min) counts as D = 0.
-// f - s_i = c + d/2 - delta_i for the left cell, c - d/2 - delta_i for the right.
-template <int D>
-__global__ void __launch_bounds__(kBlock) k_grad_limit(int64_t n, int64_t nf, const int32_t *__restrict__ off,
-                                                       const int32_t *__restrict__ ent, const int32_t *__restrict__ nbr,
-                                                       const double *__restrict__ geo, const double *__restrict__ V,
-                                                       const double *__restrict__ coff, const double *__restrict__ W,
-                                                       double *__restrict__ G) {
+// Step (iii), Section 3.1, gradient and limiter of one cell per lane group.
+// The Voronoi gradient estimate (exact to linear order)
+//   V_i grad phi_i = sum_j A_ij ([phi_j - phi_i] c_ij - (phi_i + phi_j)/2 r_ij) / |r_ij|
+// is evaluated in its difference form
+//   V_i grad phi_i = sum_j (A_ij/|r_ij|) (phi_j - phi_i) (f_ij - r_i),
+// equal to it because every Voronoi cell is closed (sum_j A_ij r_ij/|r_ij| = 0,
+// checked at upload): the phi_i parts of the two sums cancel, and
+// c_ij + (r_j - r_i)/2 = f_ij - r_i. Only differences of primitives enter,
+// so a bulk velocity costs no precision.
+// Limiter, per primitive: alpha = min(1, min_faces psi) with
+//   psi = (phi_max - phi_i)/Dl if Dl > tol, (phi_min - phi_i)/Dl if Dl < -tol, 1 else,
+// Dl = grad phi_i . (f - s_i) = grad phi_i . ((f - r_i) - (s_i - r_i)), the
+// extremes over the face neighbours and i itself, and
+// tol = eps_t max(|phi_i|, phi_max - phi_min) (a |Dl| at round-off level counts
+// as zero). Since phi_max - phi_i >= 0 is fixed per cell and rounded
+// division is monotone, the minimum over faces of (phi_max - phi_i)/Dl is
+// (phi_max - phi_i)/max Dl, so two divisions per primitive suffice.
+// Mixed mode (T = float): velocities in the record are relative to the
+// cell's generator, so the side record's w_j - w_i restores v_j - v_i.
+template <int D, typename T>
+__global__ void __launch_bounds__(kBlock) k_grad_limit(int64_t n, const int32_t *__restrict__ off,
+                                                       const int32_t *__restrict__ nbr, const T *__restrict__ srec,
+                                                       const double *__restrict__ V, T *__restrict__ rec) {
+    using Y = Lay<D>;
     constexpr int NV = D + 2;
-    const int64_t i = xcd_global_id();
-    if (i >= n) return;
-    double wi[NV], mn[NV], mx[NV], acc[NV][D];
+    constexpr int GS = Group<D>::GS;
+    constexpr bool mixed = sizeof(T) == 4;
+    constexpr int SR = mixed ? Y::SREC32 : Y::SREC64;
+    const T eps_t = mixed ? (T)1e-6 : (T)1e-13;
+    const int lane = threadIdx.x % GS;
+    const int64_t i = xcd_tile() * (kBlock / GS) + threadIdx.x / GS;
+    if (i >= n) return;  // whole groups leave together
+    const T *ri = rec + i * Y::REC;
+    T wi[NV], dl[D];
+    for (int c = 0; c < NV; c++) wi[c] = ri[Y::W + c];
+    for (int k = 0; k < D; k++) dl[k] = ri[Y::DL + k];
+    T acc[NV][D], dmx[NV], dmn[NV];
     for (int c = 0; c < NV; c++) {
-        wi[c] = W[c * n + i];
-        mn[c] = wi[c];
-        mx[c] = wi[c];
-        for (int k = 0; k < D; k++) acc[c][k] = 0.0;
+        dmx[c] = (T)0;
+        dmn[c] = (T)0;
+        for (int k = 0; k < D; k++) acc[c][k] = (T)0;
     }
     const int32_t b = off[i], e = off[i + 1];
-    for (int32_t q = b; q < e; q++) {
-        const int32_t en = ent[q];
-        const int64_t f = en >> 1;
-        const bool right = en & 1;
-        const int32_t j = nbr[q];
-        const double a = geo[f] * geo[nf + f];
-        double d[D], cc[D];
-        for (int k = 0; k < D; k++) {
-            d[k] = geo[(2 + k) * nf + f];
-            cc[k] = geo[(2 + D + k) * nf + f];
-        }
+    for (int32_t q = b + lane; q < e; q += GS) {
+        const T *s = srec + (int64_t)q * SR;
+        const T a = s[0];
+        T g[D];
+        for (int k = 0; k < D; k++) g[k] = s[1 + k];
+        const T *rj = rec + (int64_t)nbr[q] * Y::REC;
         for (int c = 0; c < NV; c++) {
-            const double wj = W[c * n + j];
-            const double pl = right ? wj : wi[c];
-            const double pr = right ? wi[c] : wj;
-            const double dp = pr - pl, sp = 0.5 * (pl + pr);
-            for (int k = 0; k < D; k++) {
-                const double g = a * (dp * cc[k] + sp * d[k]);
-                acc[c][k] = right ? acc[c][k] - g : acc[c][k] + g;
-            }
-            mn[c] = fmin(mn[c], wj);
-            mx[c] = fmax(mx[c], wj);
+            T dphi = rj[Y::W + c] - wi[c];
+            if (mixed && c >= 1 && c <= D) dphi += s[1 + D + (c - 1)];
+            const T ad = a * dphi;
+            for (int k = 0; k < D; k++) acc[c][k] += ad * g[k];
+            dmx[c] = dphi > dmx[c] ? dphi : dmx[c];
+            dmn[c] = dphi < dmn[c] ? dphi : dmn[c];
         }
     }
-    const double inv_v = 1.0 / V[i];
-    double dl[D], alpha[NV];
-    for (int k = 0; k < D; k++) dl[k] = coff[k * n + i];
+    const T inv_v = (T)(1.0 / V[i]);
     for (int c = 0; c < NV; c++) {
-        alpha[c] = 1.0;
-        for (int k = 0; k < D; k++) acc[c][k] *= inv_v;
+        for (int k = 0; k < D; k++) acc[c][k] = grp_sum<GS>(acc[c][k]) * inv_v;
+        dmx[c] = grp_max<GS>(dmx[c]);
+        dmn[c] = grp_min<GS>(dmn[c]);
     }
-    for (int32_t q = b; q < e; q++) {
-        const int32_t en = ent[q];
-        const int64_t f = en >> 1;
-        const double h = (en & 1) ? -0.5 : 0.5;
-        double dx[D];
-        for (int k = 0; k < D; k++) dx[k] = geo[(2 + D + k) * nf + f] + h * geo[(2 + k) * nf + f] - dl[k];
+    T up[NV], dn[NV], tol[NV];
+    for (int c = 0; c < NV; c++) {
+        up[c] = (T)0;
+        dn[c] = (T)0;
+        const T a = wi[c] < (T)0 ? -wi[c] : wi[c];
+        const T range = dmx[c] - dmn[c];
+        tol[c] = eps_t * (a > range ? a : range);
+    }
+    for (int32_t q = b + lane; q < e; q += GS) {
+        const T *s = srec + (int64_t)q * SR;
+        T dx[D];
+        for (int k = 0; k < D; k++) dx[k] = s[1 + k] - dl[k];
         for (int c = 0; c < NV; c++) {
-            double dphi = 0.0;
+            T dphi = (T)0;
             for (int k = 0; k < D; k++) dphi += acc[c][k] * dx[k];
-            const double tol = 1e-13 * fmax(fabs(wi[c]), mx[c] - mn[c]);
-            double psi = 1.0;
-            if (dphi > tol) psi = (mx[c] - wi[c]) / dphi;
-            else if (dphi < -tol) psi = (mn[c] - wi[c]) / dphi;
-            alpha[c] = fmin(alpha[c], psi);
+            if (dphi > tol[c]) up[c] = dphi > up[c] ? dphi : up[c];
+            else if (dphi < -tol[c]) dn[c] = -dphi > dn[c] ? -dphi : dn[c];
         }
     }
-    for (int c = 0; c < NV; c++)
-        for (int k = 0; k < D; k++) G[(c * D + k) * n + i] = alpha[c] * acc[c][k];
+    T alpha[NV];
+    for (int c = 0; c < NV; c++) {
+        up[c] = grp_max<GS>(up[c]);
+        dn[c] = grp_max<GS>(dn[c]);
+        T al = (T)1;
+        if (up[c] > (T)0) { T p = dmx[c] / up[c]; al = p < al ? p : al; }
+        if (dn[c] > (T)0) { T p = -dmn[c] / dn[c]; al = p < al ? p : al; }
+        alpha[c] = al;
+    }
+    if (lane == 0) {
+        T *ro = rec + i * Y::REC;
+        for (int c = 0; c < NV; c++)
+            for (int k = 0; k < D; k++) ro[Y::G + c * D + k] = alpha[c] * acc[c][k];
+    }
 }
 
-// Step (vii): Q_i <- Q_i - sum over faces where i is left + sum where i is
-// right, in ascending face order (Section 3, discrete update). A non-finite
-// result raises the flag.
+// Step (vii): Q_i <- Q_i - sum of the fluxes of faces where i is left
+// + sum where i is right (Section 3, discrete update), the face sums taken
+// by the cell's lane group. A non-finite result raises the flag.
 template <int D>
-__global__ void __launch_bounds__(kBlock) k_update(int64_t n, int64_t nf, const int32_t *__restrict__ off,
+__global__ void __launch_bounds__(kBlock) k_update(int64_t n, const int32_t *__restrict__ off,
                                                    const int32_t *__restrict__ ent, const double *__restrict__ flux,
                                                    double *__restrict__ Q, int32_t *__restrict__ flags) {
     constexpr int NV = D + 2;
-    const int64_t i = xcd_global_id();
+    constexpr int GS = Group<D>::GS;
+    const int lane = threadIdx.x % GS;
+    const int64_t i = xcd_tile() * (kBlock / GS) + threadIdx.x / GS;
     if (i >= n) return;
     double acc[NV];
-    for (int c = 0; c < NV; c++) acc[c] = Q[c * n + i];
+    for (int c = 0; c < NV; c++) acc[c] = 0.0;
     const int32_t b = off[i], e = off[i + 1];
-    for (int32_t q = b; q < e; q++) {
+    for (int32_t q = b + lane; q < e; q += GS) {
         const int32_t en = ent[q];
-        const int64_t f = en >> 1;
-        if (en & 1) {
-            for (int c = 0; c < NV; c++) acc[c] += flux[c * nf + f];
-        } else {
-            for (int c = 0; c < NV; c++) acc[c] -= flux[c * nf + f];
+        const double *F = flux + (int64_t)(en >> 1) * NV;
+        const double sg = (en & 1) ? 1.0 : -1.0;
+        for (int c = 0; c < NV; c++) acc[c] += sg * F[c];
+    }
+    for (int c = 0; c < NV; c++) acc[c] = grp_sum<GS>(acc[c]);
+    if (lane == 0) {
+        bool fin = true;
+        for (int c = 0; c < NV; c++) {
+            const double q = Q[c * n + i] + acc[c];
+            Q[c * n + i] = q;
+            fin = fin && isfinite(q);
         }
+        if (!fin) atomicOr(flags, 1);
     }
-    bool fin = true;
-    for (int c = 0; c < NV; c++) {
-        Q[c * n + i] = acc[c];
-        fin = fin && isfinite(acc[c]);
-    }
-    if (!fin) atomicOr(flags, 1);
 }
 
 }  // namespace mm

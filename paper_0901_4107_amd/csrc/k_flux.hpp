@@ -1,8 +1,23 @@
-// k_flux.hpp -- the face-flux kernel of the double-precision path, one lane
-// per face (Section 3.3), and the block-level diagnostics it feeds.
+// k_flux.hpp -- the face-flux kernels, one lane per face (Section 3.3), in
+// double precision and in the mixed form, and the block-level diagnostics
+// they feed.
+//
+// Per face: gather the two cells' reconstruction records, go to the face's
+// rest frame, extrapolate each side to the face centroid and half a step
+// forward in time, split velocities into the component along the L->R
+// normal and the transverse rest, solve the Riemann problem exactly and
+// sample it at x/t = 0, take the transverse velocity from the upwind side,
+// and form the moving-face flux in the lab frame
+//   (m_f, Pi + m_f w, eps + Pi.w + m_f |w|^2/2),
+//   m_f = rho_F u_F, Pi = m_f v_F + P_F n, eps = m_f |v_F|^2/2 + u_F P_F g/(g-1).
+// If an extrapolated density or pressure is not positive on either side,
+// both sides use their unextrapolated face-frame states (counted).
+// Output: flux[f][c] = dt A_f Fhat_c.
 #pragma once
 
 #include "common.hpp"
+#include "layout.hpp"
+#include "mlp.hpp"
 #include "riemann.hpp"
 
 namespace mm {
@@ -13,7 +28,6 @@ struct DiagDev {
         guess_fallback, wave_iter_max_sum;
 };
 
-// Per-lane counters reduced over the block and added once per block.
 struct LaneDiag {
     unsigned iters = 0, unconv = 0, vacuum = 0, posfb = 0, fp64fb = 0, guessfb = 0;
 };
@@ -27,28 +41,28 @@ __device__ __forceinline__ unsigned wave_max(unsigned v) {
     return v;
 }
 
-__device__ __forceinline__ void flush_diag(const LaneDiag &d, bool active, DiagDev *out) {
-    __shared__ unsigned red[kBlock / 64][8];
-    const unsigned it = active ? d.iters : 0u;
-    const unsigned s_it = wave_sum(it), m_it = wave_max(it);
+// Reduce the lanes' counters over the block; one set of atomics per block.
+__device__ __forceinline__ void flush_diag(const LaneDiag &d, DiagDev *out) {
+    __shared__ unsigned red[kBlock / 64][7];
+    const unsigned s_it = wave_sum(d.iters), m_it = wave_max(d.iters);
     const unsigned s_un = wave_sum(d.unconv), s_va = wave_sum(d.vacuum), s_pf = wave_sum(d.posfb);
     const unsigned s_64 = wave_sum(d.fp64fb), s_gf = wave_sum(d.guessfb);
     const int w = threadIdx.x / 64;
     if ((threadIdx.x & 63) == 0) {
         red[w][0] = s_it; red[w][1] = m_it; red[w][2] = s_un; red[w][3] = s_va;
-        red[w][4] = s_pf; red[w][5] = s_64; red[w][6] = s_gf; red[w][7] = m_it;
+        red[w][4] = s_pf; red[w][5] = s_64; red[w][6] = s_gf;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned long long t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        unsigned long long t[7] = {0, 0, 0, 0, 0, 0, 0};
         unsigned mx = 0;
         for (int k = 0; k < kBlock / 64; k++) {
-            for (int q = 0; q < 8; q++) t[q] += red[k][q];
+            for (int q = 0; q < 7; q++) t[q] += red[k][q];
             mx = red[k][1] > mx ? red[k][1] : mx;
         }
         atomicAdd(&out->newton_iters, t[0]);
         atomicMax(&out->newton_max, (unsigned long long)mx);
-        atomicAdd(&out->wave_iter_max_sum, t[7]);
+        atomicAdd(&out->wave_iter_max_sum, t[1]);
         if (t[2]) atomicAdd(&out->unconverged, t[2]);
         if (t[3]) atomicAdd(&out->vacuum, t[3]);
         if (t[4]) atomicAdd(&out->positivity_fallback, t[4]);
@@ -57,36 +71,38 @@ __device__ __forceinline__ void flush_diag(const LaneDiag &d, bool active, DiagD
     }
 }
 
-// Linear extrapolation to the face centroid and half a step forward in time
-// in the face frame (Section 3.3): with v' = v - w_f and dx = f - s_K,
+// Face-frame extrapolation of one side from its reconstruction record:
+// with v' the face-frame velocity and dx = f - s_K,
 //   rho'' = rho + grad rho.dx - dt/2 (v'.grad rho + rho div v)
 //   v''   = v'  + (grad v) dx  - dt/2 ((v'.grad) v + grad P / rho)
 //   P''   = P   + grad P.dx    - dt/2 (v'.grad P + gamma P div v),
-// the time derivative taken from the primitive Euler equations at the
-// cell's own face-frame state.
-template <int D>
-__device__ __forceinline__ void half_step64(const double *__restrict__ W, const double *__restrict__ G, int64_t n,
-                                            int64_t i, const double *wf, const double *dx, double gamma, double hdt,
-                                            double out[D + 2], double cen[D + 2]) {
+// the time derivative from the primitive Euler equations at the cell's own
+// face-frame state. cen receives that unextrapolated state.
+template <int D, typename T>
+__device__ __forceinline__ void half_step(const T *__restrict__ r, const T *vface, const T *gfr, T gamma, T hdt,
+                                          T out[D + 2], T cen[D + 2]) {
+    using Y = Lay<D>;
     constexpr int NV = D + 2;
-    double g[NV][D];
+    T g[NV][D], dx[D], v[D];
     for (int c = 0; c < NV; c++)
-        for (int k = 0; k < D; k++) g[c][k] = G[(c * D + k) * n + i];
-    const double rho = W[i], P = W[(NV - 1) * n + i];
-    double v[D];
-    for (int k = 0; k < D; k++) v[k] = W[(1 + k) * n + i] - wf[k];
-    double div = 0.0;
+        for (int k = 0; k < D; k++) g[c][k] = r[Y::G + c * D + k];
+    for (int k = 0; k < D; k++) {
+        dx[k] = gfr[k] - r[Y::DL + k];
+        v[k] = vface[k];
+    }
+    const T rho = r[Y::W], P = r[Y::W + NV - 1];
+    T div = (T)0;
     for (int k = 0; k < D; k++) div += g[1 + k][k];
-    double s = 0.0, t = 0.0;
+    T s = (T)0, t = (T)0;
     for (int k = 0; k < D; k++) { s += g[0][k] * dx[k]; t += v[k] * g[0][k]; }
     out[0] = rho + s - hdt * (t + rho * div);
-    const double inv_rho = 1.0 / rho;
+    const T inv_rho = (T)1 / rho;
     for (int a = 0; a < D; a++) {
-        s = 0.0; t = 0.0;
+        s = (T)0; t = (T)0;
         for (int k = 0; k < D; k++) { s += g[1 + a][k] * dx[k]; t += v[k] * g[1 + a][k]; }
         out[1 + a] = v[a] + s - hdt * (t + g[NV - 1][a] * inv_rho);
     }
-    s = 0.0; t = 0.0;
+    s = (T)0; t = (T)0;
     for (int k = 0; k < D; k++) { s += g[NV - 1][k] * dx[k]; t += v[k] * g[NV - 1][k]; }
     out[NV - 1] = P + s - hdt * (t + gamma * P * div);
     cen[0] = rho;
@@ -94,87 +110,198 @@ __device__ __forceinline__ void half_step64(const double *__restrict__ W, const 
     cen[NV - 1] = P;
 }
 
-// Steps (vi) of Section 3 for one face per lane, all in double:
-// face-frame extrapolation of both sides (positivity fallback to the
-// unextrapolated face-frame states if a density or pressure would not be
-// positive), normal/transverse split, exact Riemann solution at x/t = 0,
-// upwind transverse velocity, and the moving-face flux in the lab frame
-//   (m_f, Pi + m_f w, eps + Pi.w + m_f |w|^2/2),
-//   m_f = rho_F u_F, Pi = m_f v_F + P_F n, eps = m_f |v_F|^2/2 + u_F P_F g/(g-1).
-// Output: flux[c][f] = dt A_f Fhat_c.
+// Solve one face's Riemann problem in precision T with the standard or the
+// learned starting guess. Returns the sampled state; fills the counters.
+// `hard` (mixed path only) reports a face that needs the double solve: a
+// strong rarefaction or near-vacuum problem, a tiny guess, or no convergence.
+template <typename T>
+__device__ __forceinline__ FaceState<T> solve_face(T rhoL, T uL, T PL, T rhoR, T uR, T PR, const GasConst<T> &kg,
+                                                   T tol, int maxit, T p_learned, bool check_hard,
+                                                   LaneDiag &ld, bool &hard) {
+    hard = false;
+    const bool lvac = !(rhoL > (T)0 && PL > (T)0);
+    const bool rvac = !(rhoR > (T)0 && PR > (T)0);
+    Side<T> SL = make_side<T>(lvac ? (T)1 : rhoL, uL, lvac ? (T)1 : PL, kg);
+    Side<T> SR = make_side<T>(rvac ? (T)1 : rhoR, uR, rvac ? (T)1 : PR, kg);
+    FaceState<T> fs;
+    int kase = RC_NORMAL;
+    T vac_num = (T)0;
+    if (vacuum_cases<T>(rhoL, uL, PL, rhoR, uR, PR, kg, SL, SR, lvac, rvac, fs, kase, vac_num)) {
+        ld.vacuum = 1;
+        return fs;
+    }
+    const T p_std = standard_guess<T>(SL, SR, kg, vac_num);
+    const bool learned = p_learned > (T)0;
+    const T p0 = learned ? p_learned : p_std;
+    if (check_hard) {
+        const T pmin = SL.P < SR.P ? SL.P : SR.P;
+        if (vac_num < (T)0.5 * (SL.c + SR.c) || p0 < (T)1e-3 * pmin) { hard = true; return fs; }
+    }
+    T ps;
+    bool conv;
+    int it = newton_star<T>(SL, SR, kg, p0, tol, maxit, ps, conv);
+    if (!conv && learned) {
+        // the learned guess failed: restart from the standard guess
+        ld.guessfb = 1;
+        const int it2 = newton_star<T>(SL, SR, kg, p_std, tol, maxit, ps, conv);
+        it += it2;
+    }
+    ld.iters += it;
+    if (!conv) {
+        if (check_hard) { hard = true; return fs; }
+        ld.unconv = 1;
+    }
+    const T us = star_velocity<T>(SL, SR, ps, kg);
+    return sample0<T>(SL, SR, ps, us, kg);
+}
+
+// Lab-frame moving-face flux in double from the sampled face-frame state
+// (rho_F, u_F, P_F), the upwind transverse velocity tv, the normal n and
+// the face velocity w.
 template <int D>
-__global__ void __launch_bounds__(kBlock) k_face_flux64(int64_t n, int64_t nf, const int32_t *__restrict__ fL,
-                                                        const int32_t *__restrict__ fR, const double *__restrict__ geo,
-                                                        const double *__restrict__ wfa, const double *__restrict__ coff,
-                                                        const double *__restrict__ W, const double *__restrict__ G,
-                                                        const double *__restrict__ dt_ptr, double dt_val, double gamma,
-                                                        double tol, int maxit, double *__restrict__ flux, DiagDev *diag) {
+__device__ __forceinline__ void lab_flux(double rho, double u, double P, const double *tv, const double *nrm,
+                                         const double *w, double g_over_gm1, double scale, double *out) {
+    constexpr int NV = D + 2;
+    const double mf = rho * u;
+    double v2 = 0.0, w2 = 0.0, Piw = 0.0, Pi[D];
+    for (int k = 0; k < D; k++) {
+        const double vF = u * nrm[k] + tv[k];
+        v2 += vF * vF;
+        w2 += w[k] * w[k];
+        Pi[k] = mf * vF + P * nrm[k];
+        Piw += Pi[k] * w[k];
+    }
+    const double eps = mf * 0.5 * v2 + u * P * g_over_gm1;
+    out[0] = scale * mf;
+    for (int k = 0; k < D; k++) out[1 + k] = scale * (Pi[k] + mf * w[k]);
+    out[NV - 1] = scale * (eps + Piw + 0.5 * mf * w2);
+}
+
+// Double-precision face flux.
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_face_flux64(int64_t nf, const int32_t *__restrict__ fL,
+                                                        const int32_t *__restrict__ fR, const double *__restrict__ frec,
+                                                        const double *__restrict__ rec, const double *__restrict__ dt_ptr,
+                                                        double dt_val, double gamma, double tol, int maxit,
+                                                        const MlpGuess *mlp, double *__restrict__ flux, DiagDev *diag) {
+    using Y = Lay<D>;
     constexpr int NV = D + 2;
     const int64_t f = xcd_global_id();
-    const bool active = f < nf;
     LaneDiag ld;
-    if (active) {
+    if (f < nf) {
         const double dt = dt_ptr ? *dt_ptr : dt_val;
         const double hdt = 0.5 * dt;
-        const int32_t l = fL[f], r = fR[f];
-        const double A = geo[f], inv = geo[nf + f];
-        double d[D], cc[D], nrm[D], w[D];
+        const double *fr = frec + f * Y::FREC;
+        const double A = fr[Y::FA], hl = 0.5 * fr[Y::FELL];
+        double nrm[D], w[D], gL[D], gR[D];
         for (int k = 0; k < D; k++) {
-            d[k] = geo[(2 + k) * nf + f];
-            cc[k] = geo[(2 + D + k) * nf + f];
-            nrm[k] = d[k] * inv;
-            w[k] = wfa[k * nf + f];
+            nrm[k] = fr[Y::FN + k];
+            w[k] = fr[Y::FW + k];
+            const double c = fr[Y::FC + k];
+            gL[k] = c + hl * nrm[k];   // f - r_L
+            gR[k] = c - hl * nrm[k];   // f - r_R
         }
-        double xl[NV], xr[NV], cl[NV], cr[NV], dx[D];
-        for (int k = 0; k < D; k++) dx[k] = cc[k] + 0.5 * d[k] - coff[k * n + l];
-        half_step64<D>(W, G, n, l, w, dx, gamma, hdt, xl, cl);
-        for (int k = 0; k < D; k++) dx[k] = cc[k] - 0.5 * d[k] - coff[k * n + r];
-        half_step64<D>(W, G, n, r, w, dx, gamma, hdt, xr, cr);
+        const double *rl = rec + (int64_t)fL[f] * Y::REC;
+        const double *rr = rec + (int64_t)fR[f] * Y::REC;
+        double xl[NV], xr[NV], cl[NV], cr[NV], vf[D];
+        for (int k = 0; k < D; k++) vf[k] = rl[Y::W + 1 + k] - w[k];
+        half_step<D, double>(rl, vf, gL, gamma, hdt, xl, cl);
+        for (int k = 0; k < D; k++) vf[k] = rr[Y::W + 1 + k] - w[k];
+        half_step<D, double>(rr, vf, gR, gamma, hdt, xr, cr);
         if (!(xl[0] > 0.0 && xl[NV - 1] > 0.0 && xr[0] > 0.0 && xr[NV - 1] > 0.0)) {
             for (int c = 0; c < NV; c++) { xl[c] = cl[c]; xr[c] = cr[c]; }
             ld.posfb = 1;
         }
         double uL = 0.0, uR = 0.0;
         for (int k = 0; k < D; k++) { uL += xl[1 + k] * nrm[k]; uR += xr[1 + k] * nrm[k]; }
-
         const GasConst<double> kg(gamma);
-        const bool lvac = !(xl[0] > 0.0 && xl[NV - 1] > 0.0);
-        const bool rvac = !(xr[0] > 0.0 && xr[NV - 1] > 0.0);
-        Side<double> SL = make_side<double>(lvac ? 1.0 : xl[0], uL, lvac ? 1.0 : xl[NV - 1], kg);
-        Side<double> SR = make_side<double>(rvac ? 1.0 : xr[0], uR, rvac ? 1.0 : xr[NV - 1], kg);
-        FaceState<double> fs;
-        int kase = RC_NORMAL;
-        if (!vacuum_cases<double>(xl[0], uL, xl[NV - 1], xr[0], uR, xr[NV - 1], kg, SL, SR, lvac, rvac, fs, kase)) {
-            double ps;
-            bool conv;
-            const double p0 = standard_guess<double>(SL, SR, kg);
-            const int it = newton_star<double>(SL, SR, kg, p0, tol, maxit, ps, conv);
-            ld.iters = it;
-            ld.unconv = conv ? 0 : 1;
-            const double us = star_velocity<double>(SL, SR, ps, kg);
-            fs = sample0<double>(SL, SR, ps, us, kg);
-        } else {
-            ld.vacuum = 1;
-        }
-        // lab-frame moving-face flux
+        bool hard;
+        const double pl = mlp ? (double)mlp_guess_lane(*mlp, xl[0], uL, xl[NV - 1], xr[0], uR, xr[NV - 1], gamma)
+                              : -1.0;
+        FaceState<double> fs = solve_face<double>(xl[0], uL, xl[NV - 1], xr[0], uR, xr[NV - 1], kg, tol, maxit,
+                                                  pl, false, ld, hard);
         const double *xs = fs.side ? xr : xl;
-        const double us_side = fs.side ? uR : uL;
-        double vF[D], v2 = 0.0, w2 = 0.0, Piw = 0.0, Pi[D];
-        const double mf = fs.rho * fs.u;
-        for (int k = 0; k < D; k++) {
-            vF[k] = fs.u * nrm[k] + (xs[1 + k] - us_side * nrm[k]);
-            v2 += vF[k] * vF[k];
-            w2 += w[k] * w[k];
-            Pi[k] = mf * vF[k] + fs.P * nrm[k];
-            Piw += Pi[k] * w[k];
-        }
-        const double eps = mf * 0.5 * v2 + fs.u * fs.P * kg.g_over_gm1;
-        const double scale = dt * A;
-        flux[f] = scale * mf;
-        for (int k = 0; k < D; k++) flux[(1 + k) * nf + f] = scale * (Pi[k] + mf * w[k]);
-        flux[(NV - 1) * nf + f] = scale * (eps + Piw + 0.5 * mf * w2);
+        const double un = fs.side ? uR : uL;
+        double tv[D];
+        for (int k = 0; k < D; k++) tv[k] = xs[1 + k] - un * nrm[k];
+        lab_flux<D>(fs.rho, fs.u, fs.P, tv, nrm, w, kg.g_over_gm1, dt * A, flux + f * NV);
     }
-    if (diag) flush_diag(ld, active, diag);
+    if (diag) flush_diag(ld, diag);
+}
+
+// Mixed-precision face flux: reconstruction, frame transform and Newton in
+// float on velocities relative to the face (the record holds v_i - w_i and
+// the face record w_K - w_f, so v - w_f = (v_K - w_K) + (w_K - w_f) never
+// forms a lab-frame velocity); hard faces are re-solved in double from the
+// same face states; the lab-frame flux and everything after it in double.
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_face_flux_mixed(int64_t nf, const int32_t *__restrict__ fL,
+                                                            const int32_t *__restrict__ fR,
+                                                            const float *__restrict__ mrec,
+                                                            const double *__restrict__ wf64,
+                                                            const float *__restrict__ rec,
+                                                            const double *__restrict__ dt_ptr, double dt_val,
+                                                            double gamma, double tol32, double tol64, int maxit,
+                                                            const MlpGuess *mlp, double *__restrict__ flux,
+                                                            DiagDev *diag) {
+    using Y = Lay<D>;
+    constexpr int NV = D + 2;
+    const int64_t f = xcd_global_id();
+    LaneDiag ld;
+    if (f < nf) {
+        const double dt = dt_ptr ? *dt_ptr : dt_val;
+        const float hdt = (float)(0.5 * dt);
+        const float *fr = mrec + f * Y::MREC;
+        const float A = fr[Y::FA], hl = 0.5f * fr[Y::FELL];
+        float nrm[D], gL[D], gR[D];
+        for (int k = 0; k < D; k++) {
+            nrm[k] = fr[Y::FN + k];
+            const float c = fr[Y::FC + k];
+            gL[k] = c + hl * nrm[k];
+            gR[k] = c - hl * nrm[k];
+        }
+        const float *rl = rec + (int64_t)fL[f] * Y::REC;
+        const float *rr = rec + (int64_t)fR[f] * Y::REC;
+        const float gf = (float)gamma;
+        float xl[NV], xr[NV], cl[NV], cr[NV], vf[D];
+        for (int k = 0; k < D; k++) vf[k] = rl[Y::W + 1 + k] + fr[Y::MDWL + k];
+        half_step<D, float>(rl, vf, gL, gf, hdt, xl, cl);
+        for (int k = 0; k < D; k++) vf[k] = rr[Y::W + 1 + k] + fr[Y::MDWR + k];
+        half_step<D, float>(rr, vf, gR, gf, hdt, xr, cr);
+        if (!(xl[0] > 0.0f && xl[NV - 1] > 0.0f && xr[0] > 0.0f && xr[NV - 1] > 0.0f)) {
+            for (int c = 0; c < NV; c++) { xl[c] = cl[c]; xr[c] = cr[c]; }
+            ld.posfb = 1;
+        }
+        float uL = 0.0f, uR = 0.0f;
+        for (int k = 0; k < D; k++) { uL += xl[1 + k] * nrm[k]; uR += xr[1 + k] * nrm[k]; }
+        const GasConst<float> kf(gamma);
+        bool hard;
+        const float pl = mlp ? mlp_guess_lane(*mlp, xl[0], uL, xl[NV - 1], xr[0], uR, xr[NV - 1], gamma) : -1.0f;
+        FaceState<float> fs = solve_face<float>(xl[0], uL, xl[NV - 1], xr[0], uR, xr[NV - 1], kf, (float)tol32,
+                                                maxit, pl, true, ld, hard);
+        double rho, u, P;
+        int side;
+        if (hard) {
+            ld.fp64fb = 1;
+            const GasConst<double> kg(gamma);
+            bool h2;
+            FaceState<double> fd = solve_face<double>(xl[0], uL, xl[NV - 1], xr[0], uR, xr[NV - 1], kg, tol64,
+                                                      50, -1.0, false, ld, h2);
+            rho = fd.rho; u = fd.u; P = fd.P; side = fd.side;
+        } else {
+            rho = fs.rho; u = fs.u; P = fs.P; side = fs.side;
+        }
+        const float *xs = side ? xr : xl;
+        const float un = side ? uR : uL;
+        double tv[D], nd[D], w[D];
+        for (int k = 0; k < D; k++) {
+            tv[k] = (double)(xs[1 + k] - un * nrm[k]);
+            nd[k] = (double)nrm[k];
+            w[k] = wf64[f * Y::WSTRIDE + k];
+        }
+        lab_flux<D>(rho, u, P, tv, nd, w, gamma / (gamma - 1.0), dt * (double)A, flux + f * NV);
+    }
+    if (diag) flush_diag(ld, diag);
 }
 
 }  // namespace mm

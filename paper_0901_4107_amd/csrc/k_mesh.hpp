@@ -4,12 +4,13 @@
 #pragma once
 
 #include "common.hpp"
+#include "layout.hpp"
 
 namespace mm {
 
 enum MeshFlag : int {
     MF_INDEX = 1, MF_SELF = 2, MF_VOLUME = 4, MF_AREA = 8, MF_SEP = 16, MF_CTR = 32,
-    MF_CENTROID = 64, MF_MESHVEL = 128
+    MF_CENTROID = 64, MF_MESHVEL = 128, MF_OPEN = 256
 };
 
 __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
@@ -146,31 +147,104 @@ __global__ void k_sort_segments(int64_t n, const int32_t *off, int32_t *ent, int
     }
 }
 
-// Face geometry rows: 0 A, 1 1/|d|, 2..2+D-1 d = r_R - r_L,
-// 2+D..2+2D-1 c = f - (r_L + r_R)/2. Face velocity (Section 3.3):
-//   w_f = (w_L + w_R)/2 + [(w_L - w_R) . c / |d|] d/|d|.
+// Face records (Section 3.3 geometry and face velocity):
+//   n = d/|d|, c = f - (r_L + r_R)/2 = g - d/2,
+//   w_f = (w_L + w_R)/2 + [(w_L - w_R) . c / |d|] n.
+// The double record always; the mixed record (float geometry, the
+// generators' velocities relative to the face) and the double face velocity
+// when mixed != 0.
 template <int D>
-__global__ void __launch_bounds__(kBlock) k_face_geometry(int64_t n, int64_t nf, const int32_t *L, const int32_t *R,
-                                                          const double *area, const double *ctr, const double *sep,
-                                                          const double *mvel, double *geo, double *wf) {
+__global__ void __launch_bounds__(kBlock) k_face_records(int64_t n, int64_t nf, const int32_t *L, const int32_t *R,
+                                                         const double *area, const double *ctr, const double *sep,
+                                                         const double *mvel, double *frec, int mixed, float *mrec,
+                                                         double *wf64) {
+    using Y = Lay<D>;
     int64_t f = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (f >= nf) return;
     int32_t l = L[f], r = R[f];
-    double d[D], c[D], s2 = 0.0, proj = 0.0;
+    double d[D], c[D], wl[D], wr[D], s2 = 0.0, proj = 0.0;
     for (int k = 0; k < D; k++) {
         d[k] = sep[k * nf + f];
         c[k] = ctr[k * nf + f] - 0.5 * d[k];
         s2 += d[k] * d[k];
+        wl[k] = mvel[k * n + l];
+        wr[k] = mvel[k * n + r];
     }
-    for (int k = 0; k < D; k++) proj += (mvel[k * n + l] - mvel[k * n + r]) * c[k];
-    double inv = 1.0 / sqrt(s2);
-    geo[0 * nf + f] = area[f];
-    geo[1 * nf + f] = inv;
+    for (int k = 0; k < D; k++) proj += (wl[k] - wr[k]) * c[k];
+    const double ell = sqrt(s2);
+    const double inv = 1.0 / ell;
+    double *o = frec + f * Y::FREC;
+    o[Y::FA] = area[f];
+    o[Y::FELL] = ell;
+    double w[D];
     for (int k = 0; k < D; k++) {
-        geo[(2 + k) * nf + f] = d[k];
-        geo[(2 + D + k) * nf + f] = c[k];
-        wf[k * nf + f] = 0.5 * (mvel[k * n + l] + mvel[k * n + r]) + proj * d[k] / s2;
+        o[Y::FN + k] = d[k] * inv;
+        o[Y::FC + k] = c[k];
+        w[k] = 0.5 * (wl[k] + wr[k]) + proj * d[k] / s2;
+        o[Y::FW + k] = w[k];
     }
+    for (int k = Y::FW + D; k < Y::FREC; k++) o[k] = 0.0;
+    if (mixed) {
+        float *m = mrec + f * Y::MREC;
+        m[Y::FA] = (float)area[f];
+        m[Y::FELL] = (float)ell;
+        for (int k = 0; k < D; k++) {
+            m[Y::FN + k] = (float)(d[k] * inv);
+            m[Y::FC + k] = (float)c[k];
+            m[Y::MDWL + k] = (float)(wl[k] - w[k]);
+            m[Y::MDWR + k] = (float)(wr[k] - w[k]);
+            wf64[f * Y::WSTRIDE + k] = w[k];
+        }
+        for (int k = Y::MDWR + D; k < Y::MREC; k++) m[k] = 0.0f;
+        for (int k = D; k < Y::WSTRIDE; k++) wf64[f * Y::WSTRIDE + k] = 0.0;
+    }
+}
+
+// Side records in CSR order, one lane per cell: A/|d| and f - r_i (plus
+// w_j - w_i for the mixed path), and the closure test of each cell,
+// |sum_faces A n_out| <= 1e-9 sum_faces A. A closed surface is a property of
+// every Voronoi cell; the gradient kernels rely on it.
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_side_records(int64_t n, int64_t nf, const int32_t *off,
+                                                         const int32_t *ent, const int32_t *nbr, const double *area,
+                                                         const double *ctr, const double *sep, const double *mvel,
+                                                         double *srec, int mixed, float *srec32, int32_t *flags) {
+    using Y = Lay<D>;
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    double clo[D], asum = 0.0;
+    for (int k = 0; k < D; k++) clo[k] = 0.0;
+    for (int32_t q = off[i]; q < off[i + 1]; q++) {
+        const int32_t en = ent[q];
+        const int64_t f = en >> 1;
+        const double sg = (en & 1) ? -1.0 : 1.0;  // outward separation e = sg * d
+        double d[D], s2 = 0.0;
+        for (int k = 0; k < D; k++) { d[k] = sep[k * nf + f]; s2 += d[k] * d[k]; }
+        const double ell = sqrt(s2), A = area[f];
+        double *o = srec + (int64_t)q * Y::SREC64;
+        o[0] = A / ell;
+        const int32_t j = nbr[q];
+        for (int k = 0; k < D; k++) {
+            const double c = ctr[k * nf + f] - 0.5 * d[k];
+            const double g = c + 0.5 * sg * d[k];
+            o[1 + k] = g;
+            clo[k] += A * sg * d[k] / ell;
+        }
+        for (int k = 1 + D; k < Y::SREC64; k++) o[k] = 0.0;
+        asum += A;
+        if (mixed) {
+            float *m = srec32 + (int64_t)q * Y::SREC32;
+            m[0] = (float)(A / ell);
+            for (int k = 0; k < D; k++) {
+                m[1 + k] = (float)o[1 + k];
+                m[1 + D + k] = (float)(mvel[k * n + j] - mvel[k * n + i]);
+            }
+            for (int k = 1 + 2 * D; k < Y::SREC32; k++) m[k] = 0.0f;
+        }
+    }
+    double cl2 = 0.0;
+    for (int k = 0; k < D; k++) cl2 += clo[k] * clo[k];
+    if (!(sqrt(cl2) <= 1e-9 * asum)) atomicOr(flags, MF_OPEN);
 }
 
 }  // namespace mm

@@ -2,11 +2,12 @@
 //
 // One hydro step (Section 3's step list, items (ii), (iii), (v), (vi),
 // (vii)) on a tessellation the caller provides. Device work per step:
-//   k_prim_cfl     per cell   Q -> W, per-block Courant minimum
-//   k_min_final    one block  global timestep (stays on the device)
-//   k_grad_limit   per cell   limited gradients from the cell's face list
-//   k_face_flux    per face   extrapolation, Riemann solve, lab-frame flux
-//   k_update       per cell   segmented sum of the face fluxes (no atomics)
+//   k_prim_cfl     per cell        Q -> primitives in the cell records,
+//                                  per-block Courant minimum
+//   k_min_final    one block       global timestep (stays on the device)
+//   k_grad_limit   lane group/cell limited gradients from the side records
+//   k_face_flux*   per face        extrapolation, Riemann solve, lab-frame flux
+//   k_update       lane group/cell segmented sum of the face fluxes
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -18,7 +19,7 @@
 #include "k_cell.hpp"
 #include "k_flux.hpp"
 #include "k_mesh.hpp"
-#include "k_mixed.hpp"
+#include "layout.hpp"
 
 using namespace mm;
 
@@ -27,13 +28,17 @@ namespace {
 inline int64_t align256(int64_t x) { return (x + 255) / 256 * 256; }
 
 struct Layout {
-    int64_t flags, diag, dtdev, dtpart, bsum, off, cursor, ent, nbr, geo, wf, W, G, flux;
-    int64_t geo32, dw32, W32, G32, hard;
+    int64_t flags, diag, dtdev, dtpart, bsum, off, cursor, ent, nbr;
+    int64_t srec, frec, rec, flux;          // double path (frec always)
+    int64_t srec32, mrec, wf64, rec32;      // mixed path
     int64_t total;
 };
 
 Layout make_layout(int D, int mode, int64_t n, int64_t nf) {
     const int NV = D + 2;
+    const int REC = (D == 3) ? Lay<3>::REC : Lay<2>::REC;
+    const int FREC = (D == 3) ? Lay<3>::FREC : Lay<2>::FREC;
+    const int WS = (D == 3) ? Lay<3>::WSTRIDE : Lay<2>::WSTRIDE;
     Layout L;
     int64_t o = 0;
     auto take = [&](int64_t bytes) { int64_t at = o; o += align256(bytes); return at; };
@@ -48,20 +53,17 @@ Layout make_layout(int D, int mode, int64_t n, int64_t nf) {
     L.cursor = take(n * sizeof(int32_t));
     L.ent = take(2 * nf * sizeof(int32_t));
     L.nbr = take(2 * nf * sizeof(int32_t));
-    L.geo = take((2 + 2 * D) * nf * sizeof(double));
-    L.wf = take(D * nf * sizeof(double));
-    L.flux = take(NV * nf * sizeof(double));
+    L.frec = take(nf * FREC * sizeof(double));
+    L.flux = take(nf * NV * sizeof(double));
+    L.srec = take(2 * nf * Lay<3>::SREC64 * sizeof(double));
+    L.srec32 = L.mrec = L.wf64 = L.rec32 = L.rec = -1;
     if (mode == MM_FP64) {
-        L.W = take(NV * n * sizeof(double));
-        L.G = take(NV * D * n * sizeof(double));
-        L.geo32 = L.dw32 = L.W32 = L.G32 = L.hard = -1;
+        L.rec = take(n * REC * sizeof(double));
     } else {
-        L.W = L.G = -1;
-        L.W32 = take(NV * n * sizeof(float));
-        L.G32 = take(NV * D * n * sizeof(float));
-        L.geo32 = take(mixed_geo_rows(D) * nf * sizeof(float));
-        L.dw32 = take(2 * D * nf * sizeof(float));
-        L.hard = take((nf + 64) * sizeof(int32_t));
+        L.srec32 = take(2 * nf * Lay<3>::SREC32 * sizeof(float));
+        L.mrec = take(nf * Lay<3>::MREC * sizeof(float));
+        L.wf64 = take(nf * WS * sizeof(double));
+        L.rec32 = take(n * REC * sizeof(float));
     }
     L.total = o;
     return L;
@@ -91,7 +93,17 @@ struct mm_ctx {
 
 #define MM_LAUNCH_CHECK() MM_CHECK(hipGetLastError())
 
-extern "C" {
+static unsigned plain_grid(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+// Grid for the lane-group kernels: kBlock / GS cells per block.
+static unsigned group_grid(int D, int64_t n) {
+    const int64_t per = kBlock / (D == 3 ? Group<3>::GS : Group<2>::GS);
+    int64_t b = (n + per - 1) / per;
+    b = (b + kXcd - 1) / kXcd * kXcd;
+    return (unsigned)b;
+}
+
+// The entry points keep C linkage from their declarations in mm.h.
 
 const char *mm_status_str(mm_status s) {
     switch (s) {
@@ -166,7 +178,24 @@ static mm_status scan_inclusive(mm_ctx *c, int32_t *data, int64_t n, int32_t *sc
     return MM_OK;
 }
 
-static unsigned plain_grid(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+template <int D> static void launch_validate(mm_ctx *c, const mm_mesh *m, int32_t *flags) {
+    k_validate_faces<D><<<plain_grid(m->n_faces), kBlock, 0, c->st()>>>(
+        m->n_cells, m->n_faces, m->face_L, m->face_R, m->face_area, m->face_ctr, m->face_sep, flags);
+    k_validate_cells<D><<<plain_grid(m->n_cells), kBlock, 0, c->st()>>>(m->n_cells, m->volume, m->centroid_off,
+                                                                        m->mesh_vel, flags);
+}
+
+template <int D> static void launch_records(mm_ctx *c, const mm_mesh *m, int32_t *flags) {
+    const Layout &L = c->lay;
+    const int mixed = c->p.mode == MM_MIXED;
+    k_face_records<D><<<plain_grid(m->n_faces), kBlock, 0, c->st()>>>(
+        m->n_cells, m->n_faces, m->face_L, m->face_R, m->face_area, m->face_ctr, m->face_sep, m->mesh_vel,
+        c->at<double>(L.frec), mixed, mixed ? c->at<float>(L.mrec) : nullptr, mixed ? c->at<double>(L.wf64) : nullptr);
+    k_side_records<D><<<plain_grid(m->n_cells), kBlock, 0, c->st()>>>(
+        m->n_cells, m->n_faces, c->at<int32_t>(L.off), c->at<int32_t>(L.ent), c->at<int32_t>(L.nbr), m->face_area,
+        m->face_ctr, m->face_sep, m->mesh_vel, c->at<double>(L.srec), mixed,
+        mixed ? c->at<float>(L.srec32) : nullptr, flags);
+}
 
 mm_status mm_mesh_upload(mm_ctx *c, const mm_mesh *m) {
     if (!c || !m) return MM_E_ARG;
@@ -187,15 +216,8 @@ mm_status mm_mesh_upload(mm_ctx *c, const mm_mesh *m) {
     int32_t *flags = c->at<int32_t>(L.flags);
     k_fill_i32<<<1, kBlock, 0, s>>>(flags, 64, 0);
     MM_LAUNCH_CHECK();
-    if (c->D == 3) {
-        k_validate_faces<3><<<plain_grid(nf), kBlock, 0, s>>>(n, nf, m->face_L, m->face_R, m->face_area, m->face_ctr,
-                                                             m->face_sep, flags);
-        k_validate_cells<3><<<plain_grid(n), kBlock, 0, s>>>(n, m->volume, m->centroid_off, m->mesh_vel, flags);
-    } else {
-        k_validate_faces<2><<<plain_grid(nf), kBlock, 0, s>>>(n, nf, m->face_L, m->face_R, m->face_area, m->face_ctr,
-                                                             m->face_sep, flags);
-        k_validate_cells<2><<<plain_grid(n), kBlock, 0, s>>>(n, m->volume, m->centroid_off, m->mesh_vel, flags);
-    }
+    if (c->D == 3) launch_validate<3>(c, m, flags);
+    else launch_validate<2>(c, m, flags);
     MM_LAUNCH_CHECK();
     int32_t hflags = 0;
     MM_CHECK(hipMemcpyAsync(&hflags, flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -213,97 +235,82 @@ mm_status mm_mesh_upload(mm_ctx *c, const mm_mesh *m) {
     k_fill_sides<<<plain_grid(nf), kBlock, 0, s>>>(nf, m->face_L, m->face_R, cur, ent, nbr);
     k_sort_segments<<<plain_grid(n), kBlock, 0, s>>>(n, off, ent, nbr);
     MM_LAUNCH_CHECK();
-    double *geo = c->at<double>(L.geo), *wf = c->at<double>(L.wf);
-    if (c->D == 3)
-        k_face_geometry<3><<<plain_grid(nf), kBlock, 0, s>>>(n, nf, m->face_L, m->face_R, m->face_area, m->face_ctr,
-                                                            m->face_sep, m->mesh_vel, geo, wf);
-    else
-        k_face_geometry<2><<<plain_grid(nf), kBlock, 0, s>>>(n, nf, m->face_L, m->face_R, m->face_area, m->face_ctr,
-                                                            m->face_sep, m->mesh_vel, geo, wf);
+    if (c->D == 3) launch_records<3>(c, m, flags);
+    else launch_records<2>(c, m, flags);
     MM_LAUNCH_CHECK();
-    if (c->p.mode == MM_MIXED) {
-        st = mixed_upload(c->D, s, n, nf, m, geo, wf, c->at<float>(L.geo32), c->at<float>(L.dw32));
-        if (st != MM_OK) return st;
-    }
+    MM_CHECK(hipMemcpyAsync(&hflags, flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    MM_CHECK(hipStreamSynchronize(s));
+    if (hflags) return MM_E_MESH;
     c->have_mesh = true;
     return clear_diag(c);
 }
 
-static mm_status gradients_into(mm_ctx *c, const double *Q, void *W, void *G, double *dt_part) {
+template <int D, typename T> static mm_status gradients_t(mm_ctx *c, const double *Q, T *rec, double *dt_part) {
     const Layout &L = c->lay;
     hipStream_t s = c->st();
-    const unsigned gc = grid_for(c->n);
-    if (c->p.mode == MM_FP64) {
-        double *Wd = (double *)W, *Gd = (double *)G;
-        if (c->D == 3) {
-            k_prim_cfl<3><<<gc, kBlock, 0, s>>>(c->n, c->p.gamma, c->p.cfl, c->mesh.volume, Q, c->mesh.mesh_vel, Wd,
-                                                dt_part);
-            k_grad_limit<3><<<gc, kBlock, 0, s>>>(c->n, c->nf, c->at<int32_t>(L.off), c->at<int32_t>(L.ent),
-                                                  c->at<int32_t>(L.nbr), c->at<double>(L.geo), c->mesh.volume,
-                                                  c->mesh.centroid_off, Wd, Gd);
-        } else {
-            k_prim_cfl<2><<<gc, kBlock, 0, s>>>(c->n, c->p.gamma, c->p.cfl, c->mesh.volume, Q, c->mesh.mesh_vel, Wd,
-                                                dt_part);
-            k_grad_limit<2><<<gc, kBlock, 0, s>>>(c->n, c->nf, c->at<int32_t>(L.off), c->at<int32_t>(L.ent),
-                                                  c->at<int32_t>(L.nbr), c->at<double>(L.geo), c->mesh.volume,
-                                                  c->mesh.centroid_off, Wd, Gd);
-        }
-        MM_LAUNCH_CHECK();
-        return MM_OK;
-    }
-    return mixed_gradients(c->D, s, c->n, c->nf, c->p.gamma, c->p.cfl, c->mesh.volume, Q, c->mesh.mesh_vel,
-                           c->mesh.centroid_off, c->at<int32_t>(L.off), c->at<int32_t>(L.ent), c->at<int32_t>(L.nbr),
-                           c->at<double>(L.geo), (float *)W, (float *)G, dt_part);
+    const T *srec = sizeof(T) == 8 ? (const T *)c->at<double>(L.srec) : (const T *)c->at<float>(L.srec32);
+    k_prim_cfl<D, T><<<grid_for(c->n), kBlock, 0, s>>>(c->n, c->p.gamma, c->p.cfl, c->mesh.volume, Q,
+                                                      c->mesh.mesh_vel, c->mesh.centroid_off, rec, dt_part);
+    k_grad_limit<D, T><<<group_grid(D, c->n), kBlock, 0, s>>>(c->n, c->at<int32_t>(L.off), c->at<int32_t>(L.nbr),
+                                                              srec, c->mesh.volume, rec);
+    MM_LAUNCH_CHECK();
+    return MM_OK;
 }
 
-mm_status mm_gradients(mm_ctx *c, const double *Q, void *W, void *G) {
-    if (!c || !Q || !W || !G) return MM_E_ARG;
+static mm_status gradients_into(mm_ctx *c, const double *Q, void *rec, double *dt_part) {
+    const bool f64 = c->p.mode == MM_FP64;
+    if (c->D == 3)
+        return f64 ? gradients_t<3, double>(c, Q, (double *)rec, dt_part) : gradients_t<3, float>(c, Q, (float *)rec, dt_part);
+    return f64 ? gradients_t<2, double>(c, Q, (double *)rec, dt_part) : gradients_t<2, float>(c, Q, (float *)rec, dt_part);
+}
+
+mm_status mm_gradients(mm_ctx *c, const double *Q, void *recon) {
+    if (!c || !Q || !recon) return MM_E_ARG;
     if (!c->have_mesh) return MM_E_STATE;
-    return gradients_into(c, Q, W, G, c->at<double>(c->lay.dtpart));
+    return gradients_into(c, Q, recon, c->at<double>(c->lay.dtpart));
 }
 
-static mm_status fluxes_into(mm_ctx *c, const double *dt_dev, double dt, const void *W, const void *G, double *flux) {
+template <int D>
+static mm_status fluxes_t(mm_ctx *c, const double *dt_dev, double dt, const void *rec, double *flux) {
     const Layout &L = c->lay;
     hipStream_t s = c->st();
-    const unsigned gf = grid_for(c->nf);
     DiagDev *diag = c->at<DiagDev>(L.diag);
+    const MlpGuess *mlp = nullptr;
+    if (c->p.mode == MM_FP64)
+        k_face_flux64<D><<<grid_for(c->nf), kBlock, 0, s>>>(c->nf, c->mesh.face_L, c->mesh.face_R,
+                                                            c->at<double>(L.frec), (const double *)rec, dt_dev, dt,
+                                                            c->p.gamma, c->p.newton_tol64, c->p.newton_max_iter, mlp,
+                                                            flux, diag);
+    else
+        k_face_flux_mixed<D><<<grid_for(c->nf), kBlock, 0, s>>>(
+            c->nf, c->mesh.face_L, c->mesh.face_R, c->at<float>(L.mrec), c->at<double>(L.wf64), (const float *)rec,
+            dt_dev, dt, c->p.gamma, c->p.newton_tol32, c->p.newton_tol64, c->p.newton_max_iter, mlp, flux, diag);
+    MM_LAUNCH_CHECK();
+    return MM_OK;
+}
+
+static mm_status fluxes_into(mm_ctx *c, const double *dt_dev, double dt, const void *rec, double *flux) {
     c->faces_done += (uint64_t)c->nf;
     c->waves_done += (uint64_t)((c->nf + 63) / 64);
-    if (c->p.mode == MM_FP64) {
-        if (c->D == 3)
-            k_face_flux64<3><<<gf, kBlock, 0, s>>>(c->n, c->nf, c->mesh.face_L, c->mesh.face_R, c->at<double>(L.geo),
-                                                   c->at<double>(L.wf), c->mesh.centroid_off, (const double *)W,
-                                                   (const double *)G, dt_dev, dt, c->p.gamma, c->p.newton_tol64,
-                                                   c->p.newton_max_iter, flux, diag);
-        else
-            k_face_flux64<2><<<gf, kBlock, 0, s>>>(c->n, c->nf, c->mesh.face_L, c->mesh.face_R, c->at<double>(L.geo),
-                                                   c->at<double>(L.wf), c->mesh.centroid_off, (const double *)W,
-                                                   (const double *)G, dt_dev, dt, c->p.gamma, c->p.newton_tol64,
-                                                   c->p.newton_max_iter, flux, diag);
-        MM_LAUNCH_CHECK();
-        return MM_OK;
-    }
-    return mixed_fluxes(c->D, s, c->n, c->nf, c->mesh.face_L, c->mesh.face_R, c->at<float>(L.geo32),
-                        c->at<double>(L.geo), c->at<double>(L.wf), c->at<float>(L.dw32), c->mesh.centroid_off,
-                        (const float *)W, (const float *)G, dt_dev, dt, c->p, flux, diag, c->at<int32_t>(L.hard));
+    return c->D == 3 ? fluxes_t<3>(c, dt_dev, dt, rec, flux) : fluxes_t<2>(c, dt_dev, dt, rec, flux);
 }
 
-mm_status mm_face_fluxes(mm_ctx *c, double dt, const void *W, const void *G, double *face_flux) {
-    if (!c || !W || !G || !face_flux) return MM_E_ARG;
+mm_status mm_face_fluxes(mm_ctx *c, double dt, const void *recon, double *face_flux) {
+    if (!c || !recon || !face_flux) return MM_E_ARG;
     if (!(dt > 0.0) || !isfinite(dt)) return MM_E_ARG;
     if (!c->have_mesh) return MM_E_STATE;
-    return fluxes_into(c, nullptr, dt, W, G, face_flux);
+    return fluxes_into(c, nullptr, dt, recon, face_flux);
 }
 
 static mm_status update_into(mm_ctx *c, const double *flux, double *Q) {
     const Layout &L = c->lay;
-    const unsigned gc = grid_for(c->n);
+    const unsigned g = group_grid(c->D, c->n);
     if (c->D == 3)
-        k_update<3><<<gc, kBlock, 0, c->st()>>>(c->n, c->nf, c->at<int32_t>(L.off), c->at<int32_t>(L.ent), flux, Q,
-                                                c->at<int32_t>(L.flags) + 1);
+        k_update<3><<<g, kBlock, 0, c->st()>>>(c->n, c->at<int32_t>(L.off), c->at<int32_t>(L.ent), flux, Q,
+                                              c->at<int32_t>(L.flags) + 1);
     else
-        k_update<2><<<gc, kBlock, 0, c->st()>>>(c->n, c->nf, c->at<int32_t>(L.off), c->at<int32_t>(L.ent), flux, Q,
-                                                c->at<int32_t>(L.flags) + 1);
+        k_update<2><<<g, kBlock, 0, c->st()>>>(c->n, c->at<int32_t>(L.off), c->at<int32_t>(L.ent), flux, Q,
+                                              c->at<int32_t>(L.flags) + 1);
     MM_LAUNCH_CHECK();
     return MM_OK;
 }
@@ -320,11 +327,10 @@ mm_status mm_hydro_step(mm_ctx *c, double *Q, double dt, double *dt_used) {
     if (!isfinite(dt)) return MM_E_ARG;
     const Layout &L = c->lay;
     hipStream_t s = c->st();
-    void *W = c->p.mode == MM_FP64 ? (void *)c->at<double>(L.W) : (void *)c->at<float>(L.W32);
-    void *G = c->p.mode == MM_FP64 ? (void *)c->at<double>(L.G) : (void *)c->at<float>(L.G32);
+    void *rec = c->p.mode == MM_FP64 ? (void *)c->at<double>(L.rec) : (void *)c->at<float>(L.rec32);
     double *dt_part = c->at<double>(L.dtpart);
     double *dt_dev = c->at<double>(L.dtdev);
-    mm_status st = gradients_into(c, Q, W, G, dt_part);
+    mm_status st = gradients_into(c, Q, rec, dt_part);
     if (st != MM_OK) return st;
     const double *dt_src = nullptr;
     if (!(dt > 0.0)) {
@@ -333,7 +339,7 @@ mm_status mm_hydro_step(mm_ctx *c, double *Q, double dt, double *dt_used) {
         dt_src = dt_dev;
     }
     double *flux = c->at<double>(L.flux);
-    st = fluxes_into(c, dt_src, dt, W, G, flux);
+    st = fluxes_into(c, dt_src, dt, rec, flux);
     if (st != MM_OK) return st;
     st = update_into(c, flux, Q);
     if (st != MM_OK) return st;
@@ -364,6 +370,7 @@ mm_status mm_get_diag(mm_ctx *c, mm_diag *out) {
                             c->st()));
     MM_CHECK(hipStreamSynchronize(c->st()));
     std::memset(out, 0, sizeof(*out));
+    out->faces = c->faces_done;
     out->newton_iters = d.newton_iters;
     out->newton_max = d.newton_max;
     out->unconverged = d.unconverged;
@@ -372,10 +379,8 @@ mm_status mm_get_diag(mm_ctx *c, mm_diag *out) {
     out->fp64_fallback = d.fp64_fallback;
     out->guess_fallback = d.guess_fallback;
     out->wave_iter_max_sum = d.wave_iter_max_sum;
-    out->nonfinite = nonfin;
-    out->faces = c->faces_done;
     out->waves = c->waves_done;
+    out->nonfinite = nonfin;
     return MM_OK;
 }
 
-}  // extern "C"

@@ -86,8 +86,11 @@ __device__ __forceinline__ void side_fn(T p, const Side<T> &s, const GasConst<T>
 // Adaptive non-iterative starting guess: the primitive-variable estimate
 // when the pressure ratio is mild and it falls between the two pressures,
 // else the two-rarefaction estimate (below) or the two-shock estimate (above).
+// vac_num = c_L + c_R - (g-1)/2 (u_R - u_L): the vacuum test (vac_num <= 0)
+// and the two-rarefaction estimate use this one value, so that a problem
+// judged free of vacuum always has a positive two-rarefaction estimate.
 template <typename T>
-__device__ __forceinline__ T standard_guess(const Side<T> &L, const Side<T> &R, const GasConst<T> &k) {
+__device__ __forceinline__ T standard_guess(const Side<T> &L, const Side<T> &R, const GasConst<T> &k, T vac_num) {
     T du = R.u - L.u;
     T ppv = (T)0.5 * (L.P + R.P) - (T)0.125 * du * (L.rho + R.rho) * (L.c + R.c);
     ppv = ppv > (T)0 ? ppv : (T)0;
@@ -95,9 +98,9 @@ __device__ __forceinline__ T standard_guess(const Side<T> &L, const Side<T> &R, 
     T pmax = L.P < R.P ? R.P : L.P;
     if (pmax <= (T)2 * pmin && ppv >= pmin && ppv <= pmax) return ppv;
     if (ppv < pmin) {
-        T num = L.c + R.c - k.gm1_over_2 * du;
         T den = L.c * mm_pow(L.inv_P, k.z) + R.c * mm_pow(R.inv_P, k.z);
-        return mm_pow(num / den, k.inv_z);
+        T ptr = mm_pow(vac_num / den, k.inv_z);
+        return ptr > (T)0 ? ptr : (T)1e-30 * pmin;
     }
     T gL = mm_sqrt(L.A / (ppv + L.B));
     T gR = mm_sqrt(R.A / (ppv + R.B));
@@ -106,7 +109,10 @@ __device__ __forceinline__ T standard_guess(const Side<T> &L, const Side<T> &R, 
 }
 
 // Newton iteration on the pressure function. Returns the iteration count;
-// *conv tells whether the relative step fell below tol.
+// *conv tells whether it converged: the relative step fell below tol, or
+// f(p) vanished to within the rounding of its own terms (near vacuum the
+// root can be ~1e-30 of the side pressures, where f' p is so small that
+// rounding noise in f alone moves p by more than tol).
 template <typename T>
 __device__ __forceinline__ int newton_star(const Side<T> &L, const Side<T> &R, const GasConst<T> &k,
                                            T p, T tol, int maxit, T &pstar, bool &conv) {
@@ -114,14 +120,17 @@ __device__ __forceinline__ int newton_star(const Side<T> &L, const Side<T> &R, c
     int it = 0;
     conv = false;
     if (!(p > (T)0)) p = (T)0.5 * (L.P + R.P);
+    const T noise = (T)8 * (sizeof(T) == 8 ? (T)2.220446049250313e-16 : (T)1.1920929e-7);
     while (it < maxit) {
         T fl, dfl, fr, dfr;
         side_fn(p, L, k, fl, dfl);
         side_fn(p, R, k, fr, dfr);
-        T pn = p - (fl + fr + du) / (dfl + dfr);
+        const T fsum = fl + fr + du;
+        T pn = p - fsum / (dfl + dfr);
         if (!(pn > (T)0)) pn = (T)0.1 * p;
         it++;
-        bool done = fabs(pn - p) <= tol * (T)0.5 * (pn + p);
+        bool done = fabs(pn - p) <= tol * (T)0.5 * (pn + p) ||
+                    fabs(fsum) <= noise * (fabs(fl) + fabs(fr) + fabs(du));
         p = pn;
         if (done) { conv = true; break; }
     }
@@ -161,7 +170,7 @@ __device__ __forceinline__ FaceState<T> vac(int side) {
 template <typename T>
 __device__ __forceinline__ bool vacuum_cases(T rhoL, T uL, T PL, T rhoR, T uR, T PR, const GasConst<T> &k,
                                              const Side<T> &L, const Side<T> &R, bool lvac, bool rvac,
-                                             FaceState<T> &o, int &kase) {
+                                             FaceState<T> &o, int &kase, T &vac_num) {
     if (lvac && rvac) { o = vac<T>(0); kase = RC_BOTH_VACUUM; return true; }
     if (lvac) {
         kase = RC_LEFT_VACUUM;
@@ -177,7 +186,8 @@ __device__ __forceinline__ bool vacuum_cases(T rhoL, T uL, T PL, T rhoR, T uR, T
         else o = fan0(L, true, k);
         return true;
     }
-    if (R.u - L.u >= k.two_over_gm1 * (L.c + R.c)) {
+    vac_num = L.c + R.c - k.gm1_over_2 * (R.u - L.u);
+    if (!(vac_num > (T)0)) {
         kase = RC_VACUUM_GENERATED;
         T frontL = L.u + k.two_over_gm1 * L.c;
         T frontR = R.u - k.two_over_gm1 * R.c;

@@ -58,8 +58,8 @@ SIGNATURES = {
     "mm_workspace_bytes": (ctypes.c_int64, [_vp, ctypes.c_int64, ctypes.c_int64]),
     "mm_set_workspace": (ctypes.c_int32, [_vp, _vp, ctypes.c_int64]),
     "mm_mesh_upload": (ctypes.c_int32, [_vp, ctypes.POINTER(mm_mesh)]),
-    "mm_gradients": (ctypes.c_int32, [_vp, _vp, _vp, _vp]),
-    "mm_face_fluxes": (ctypes.c_int32, [_vp, ctypes.c_double, _vp, _vp, _vp]),
+    "mm_gradients": (ctypes.c_int32, [_vp, _vp, _vp]),
+    "mm_face_fluxes": (ctypes.c_int32, [_vp, ctypes.c_double, _vp, _vp]),
     "mm_apply_update": (ctypes.c_int32, [_vp, _vp, _vp]),
     "mm_hydro_step": (ctypes.c_int32, [_vp, _vp, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]),
     "mm_get_diag": (ctypes.c_int32, [_vp, ctypes.POINTER(mm_diag)]),
@@ -172,11 +172,11 @@ class Context:
         self._mesh = mesh  # keep the arrays alive while the library refers to them
         _check("mm_mesh_upload", lib().mm_mesh_upload(self._ctx, ctypes.byref(mesh.as_struct())))
 
-    def mm_gradients(self, Q: torch.Tensor, W: torch.Tensor, G: torch.Tensor):
-        _check("mm_gradients", lib().mm_gradients(self._ctx, _ptr(Q), _ptr(W), _ptr(G)))
+    def mm_gradients(self, Q: torch.Tensor, recon: torch.Tensor):
+        _check("mm_gradients", lib().mm_gradients(self._ctx, _ptr(Q), _ptr(recon)))
 
-    def mm_face_fluxes(self, dt: float, W: torch.Tensor, G: torch.Tensor, face_flux: torch.Tensor):
-        _check("mm_face_fluxes", lib().mm_face_fluxes(self._ctx, float(dt), _ptr(W), _ptr(G), _ptr(face_flux)))
+    def mm_face_fluxes(self, dt: float, recon: torch.Tensor, face_flux: torch.Tensor):
+        _check("mm_face_fluxes", lib().mm_face_fluxes(self._ctx, float(dt), _ptr(recon), _ptr(face_flux)))
 
     def mm_apply_update(self, face_flux: torch.Tensor, Q: torch.Tensor):
         _check("mm_apply_update", lib().mm_apply_update(self._ctx, _ptr(face_flux), _ptr(Q)))
@@ -199,12 +199,23 @@ class Context:
         _check("mm_reset_diag", lib().mm_reset_diag(self._ctx))
 
     # --- buffers in the layouts the entry points expect ----------------------
-    def cell_buffers(self, n_cells: int):
-        """(W, G) buffers for mm_gradients in this context's mode."""
+    def recon_buffer(self, n_cells: int):
+        """Reconstruction records [N][MM_RECON_STRIDE] for mm_gradients in
+        this context's mode (double in MM_FP64, float in MM_MIXED)."""
         dt = torch.float64 if self.mode == MM_FP64 else torch.float32
-        nv = self.dim + 2
-        return (torch.empty((nv, n_cells), dtype=dt, device=self.device),
-                torch.empty((nv * self.dim, n_cells), dtype=dt, device=self.device))
+        return torch.empty((n_cells, recon_stride(self.dim)), dtype=dt, device=self.device)
 
     def flux_buffer(self, n_faces: int):
-        return torch.empty((self.dim + 2, n_faces), dtype=torch.float64, device=self.device)
+        """Face fluxes [F][D+2] (double)."""
+        return torch.empty((n_faces, self.dim + 2), dtype=torch.float64, device=self.device)
+
+
+def recon_stride(dim: int) -> int:
+    return 24 if dim == 3 else 16
+
+
+def split_recon(rec, dim: int):
+    """(W [D+2][N], G [(D+2)*D][N], s - r [D][N]) views of reconstruction
+    records in the oracle's structure-of-arrays layout (numpy or torch)."""
+    nv = dim + 2
+    return rec[:, :nv].T, rec[:, nv:nv + nv * dim].T, rec[:, nv + nv * dim:nv + nv * dim + dim].T

@@ -36,18 +36,20 @@ class Run:
         self.dm = mm.DeviceMesh.from_host(m)
         self.ctx.mm_mesh_upload(self.dm)
         self.Q = torch.from_numpy(np.ascontiguousarray(wl.Q)).cuda()
-        self.W, self.G = self.ctx.cell_buffers(m.n_cells)
+        self.rec = self.ctx.recon_buffer(m.n_cells)
         self.F = self.ctx.flux_buffer(m.n_faces)
 
     def gradients(self):
-        self.ctx.mm_gradients(self.Q, self.W, self.G)
+        self.ctx.mm_gradients(self.Q, self.rec)
         torch.cuda.synchronize()
-        return self.W.cpu().numpy(), self.G.cpu().numpy()
+        W, G, dl = mm.split_recon(self.rec.cpu().numpy(), self.wl.mesh.dim)
+        assert np.array_equal(dl, self.wl.mesh.centroid_off)
+        return W, G
 
     def fluxes(self, dt):
-        self.ctx.mm_face_fluxes(dt, self.W, self.G, self.F)
+        self.ctx.mm_face_fluxes(dt, self.rec, self.F)
         torch.cuda.synchronize()
-        return self.F.cpu().numpy()
+        return self.F.cpu().numpy().T
 
 
 def assert_close(got, want, tol, what, floor=None):

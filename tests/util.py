@@ -27,3 +27,19 @@ def l1_rel(a, b):
     den = np.sum(np.abs(b), axis=1)
     den = np.where(den > 0, den, 1.0)
     return np.sum(np.abs(a - b), axis=1) / den
+
+
+def l1_state(a, b):
+    """L1 error of conserved states [D+2][N] per component: mass and energy as
+    sum_i |a - b| / sum_i |b|; each momentum component against the L1 norm of
+    the momentum vector, sum_i |a_k - b_k| / sum_i ||p_i||, so that a
+    component that is analytically ~0 (p_z of a 2D flow in 3D) is measured
+    against the momentum scale, not against its own round-off."""
+    a = np.asarray(a); b = np.asarray(b)
+    D = b.shape[0] - 2
+    num = np.sum(np.abs(a - b), axis=1)
+    den = np.sum(np.abs(b), axis=1)
+    pmag = np.sum(np.sqrt(np.sum(b[1:1 + D] ** 2, axis=0)))
+    den[1:1 + D] = pmag
+    den = np.where(den > 0, den, 1.0)
+    return num / den
