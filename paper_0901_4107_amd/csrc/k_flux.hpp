@@ -22,7 +22,11 @@
 
 namespace mm {
 
-// Device-side diagnostic accumulators (mirrors mm_diag's counters).
+// Device-side diagnostic accumulators (mirrors mm_diag's counters). Each
+// block adds into one of kDiagSlots copies (chosen by block index) so that
+// the per-block atomics spread over many addresses instead of serialising
+// on one; the host sums the slots.
+constexpr int kDiagSlots = 256;
 struct DiagDev {
     unsigned long long newton_iters, newton_max, unconverged, vacuum, positivity_fallback, fp64_fallback,
         guess_fallback, wave_iter_max_sum;
@@ -42,7 +46,8 @@ __device__ __forceinline__ unsigned wave_max(unsigned v) {
 }
 
 // Reduce the lanes' counters over the block; one set of atomics per block.
-__device__ __forceinline__ void flush_diag(const LaneDiag &d, DiagDev *out) {
+__device__ __forceinline__ void flush_diag(const LaneDiag &d, DiagDev *slots) {
+    DiagDev *out = slots + (blockIdx.x & (kDiagSlots - 1));
     __shared__ unsigned red[kBlock / 64][7];
     const unsigned s_it = wave_sum(d.iters), m_it = wave_max(d.iters);
     const unsigned s_un = wave_sum(d.unconv), s_va = wave_sum(d.vacuum), s_pf = wave_sum(d.posfb);
@@ -124,9 +129,8 @@ __device__ __forceinline__ FaceState<T> solve_face(T rhoL, T uL, T PL, T rhoR, T
     Side<T> SL = make_side<T>(lvac ? (T)1 : rhoL, uL, lvac ? (T)1 : PL, kg);
     Side<T> SR = make_side<T>(rvac ? (T)1 : rhoR, uR, rvac ? (T)1 : PR, kg);
     FaceState<T> fs;
-    int kase = RC_NORMAL;
     T vac_num = (T)0;
-    if (vacuum_cases<T>(rhoL, uL, PL, rhoR, uR, PR, kg, SL, SR, lvac, rvac, fs, kase, vac_num)) {
+    if (vacuum_cases<T>(kg, SL, SR, lvac, rvac, fs, vac_num)) {
         ld.vacuum = 1;
         return fs;
     }
@@ -137,22 +141,20 @@ __device__ __forceinline__ FaceState<T> solve_face(T rhoL, T uL, T PL, T rhoR, T
         const T pmin = SL.P < SR.P ? SL.P : SR.P;
         if (vac_num < (T)0.5 * (SL.c + SR.c) || p0 < (T)1e-3 * pmin) { hard = true; return fs; }
     }
-    T ps;
-    bool conv;
-    int it = newton_star<T>(SL, SR, kg, p0, tol, maxit, ps, conv);
-    if (!conv && learned) {
+    Star<T> st = newton_star<T>(SL, SR, kg, p0, tol, maxit);
+    int it = st.iters;
+    if (!st.conv && learned) {
         // the learned guess failed: restart from the standard guess
         ld.guessfb = 1;
-        const int it2 = newton_star<T>(SL, SR, kg, p_std, tol, maxit, ps, conv);
-        it += it2;
+        st = newton_star<T>(SL, SR, kg, p_std, tol, maxit);
+        it += st.iters;
     }
     ld.iters += it;
-    if (!conv) {
+    if (!st.conv) {
         if (check_hard) { hard = true; return fs; }
         ld.unconv = 1;
     }
-    const T us = star_velocity<T>(SL, SR, ps, kg);
-    return sample0<T>(SL, SR, ps, us, kg);
+    return sample0<T>(SL, SR, st, kg);
 }
 
 // Lab-frame moving-face flux in double from the sampled face-frame state
@@ -182,7 +184,7 @@ template <int D>
 __global__ void __launch_bounds__(kBlock) k_face_flux64(int64_t nf, const int32_t *__restrict__ fL,
                                                         const int32_t *__restrict__ fR, const double *__restrict__ frec,
                                                         const double *__restrict__ rec, const double *__restrict__ dt_ptr,
-                                                        double dt_val, double gamma, double tol, int maxit,
+                                                        double dt_val, GasConst<double> kg, double tol, int maxit,
                                                         const MlpGuess *mlp, double *__restrict__ flux, DiagDev *diag) {
     using Y = Lay<D>;
     constexpr int NV = D + 2;
@@ -205,18 +207,17 @@ __global__ void __launch_bounds__(kBlock) k_face_flux64(int64_t nf, const int32_
         const double *rr = rec + (int64_t)fR[f] * Y::REC;
         double xl[NV], xr[NV], cl[NV], cr[NV], vf[D];
         for (int k = 0; k < D; k++) vf[k] = rl[Y::W + 1 + k] - w[k];
-        half_step<D, double>(rl, vf, gL, gamma, hdt, xl, cl);
+        half_step<D, double>(rl, vf, gL, kg.g, hdt, xl, cl);
         for (int k = 0; k < D; k++) vf[k] = rr[Y::W + 1 + k] - w[k];
-        half_step<D, double>(rr, vf, gR, gamma, hdt, xr, cr);
+        half_step<D, double>(rr, vf, gR, kg.g, hdt, xr, cr);
         if (!(xl[0] > 0.0 && xl[NV - 1] > 0.0 && xr[0] > 0.0 && xr[NV - 1] > 0.0)) {
             for (int c = 0; c < NV; c++) { xl[c] = cl[c]; xr[c] = cr[c]; }
             ld.posfb = 1;
         }
         double uL = 0.0, uR = 0.0;
         for (int k = 0; k < D; k++) { uL += xl[1 + k] * nrm[k]; uR += xr[1 + k] * nrm[k]; }
-        const GasConst<double> kg(gamma);
         bool hard;
-        const double pl = mlp ? (double)mlp_guess_lane(*mlp, xl[0], uL, xl[NV - 1], xr[0], uR, xr[NV - 1], gamma)
+        const double pl = mlp ? (double)mlp_guess_lane(*mlp, xl[0], uL, xl[NV - 1], xr[0], uR, xr[NV - 1], kg.g)
                               : -1.0;
         FaceState<double> fs = solve_face<double>(xl[0], uL, xl[NV - 1], xr[0], uR, xr[NV - 1], kg, tol, maxit,
                                                   pl, false, ld, hard);
@@ -229,11 +230,69 @@ __global__ void __launch_bounds__(kBlock) k_face_flux64(int64_t nf, const int32_
     if (diag) flush_diag(ld, diag);
 }
 
-// Mixed-precision face flux: reconstruction, frame transform and Newton in
-// float on velocities relative to the face (the record holds v_i - w_i and
-// the face record w_K - w_f, so v - w_f = (v_K - w_K) + (w_K - w_f) never
-// forms a lab-frame velocity); hard faces are re-solved in double from the
-// same face states; the lab-frame flux and everything after it in double.
+// Float face-frame states of one face for the mixed path: reconstruction,
+// frame transform and half step on velocities relative to the face (the
+// record holds v_i - w_i and the face record w_K - w_f, so
+// v - w_f = (v_K - w_K) + (w_K - w_f) never forms a lab-frame velocity).
+template <int D> struct MixedFace {
+    float xl[D + 2], xr[D + 2], uL, uR, nrm[D], A;
+    bool posfb;
+};
+
+template <int D>
+__device__ __forceinline__ MixedFace<D> mixed_face_states(int64_t f, const int32_t *__restrict__ fL,
+                                                          const int32_t *__restrict__ fR,
+                                                          const float *__restrict__ mrec,
+                                                          const float *__restrict__ rec, float hdt, float gam) {
+    using Y = Lay<D>;
+    constexpr int NV = D + 2;
+    MixedFace<D> o;
+    const float *fr = mrec + f * Y::MREC;
+    o.A = fr[Y::FA];
+    const float hl = 0.5f * fr[Y::FELL];
+    float gL[D], gR[D], cl[NV], cr[NV], vf[D];
+    for (int k = 0; k < D; k++) {
+        o.nrm[k] = fr[Y::FN + k];
+        const float c = fr[Y::FC + k];
+        gL[k] = c + hl * o.nrm[k];
+        gR[k] = c - hl * o.nrm[k];
+    }
+    const float *rl = rec + (int64_t)fL[f] * Y::REC;
+    const float *rr = rec + (int64_t)fR[f] * Y::REC;
+    for (int k = 0; k < D; k++) vf[k] = rl[Y::W + 1 + k] + fr[Y::MDWL + k];
+    half_step<D, float>(rl, vf, gL, gam, hdt, o.xl, cl);
+    for (int k = 0; k < D; k++) vf[k] = rr[Y::W + 1 + k] + fr[Y::MDWR + k];
+    half_step<D, float>(rr, vf, gR, gam, hdt, o.xr, cr);
+    o.posfb = !(o.xl[0] > 0.0f && o.xl[NV - 1] > 0.0f && o.xr[0] > 0.0f && o.xr[NV - 1] > 0.0f);
+    if (o.posfb)
+        for (int c = 0; c < NV; c++) { o.xl[c] = cl[c]; o.xr[c] = cr[c]; }
+    o.uL = 0.0f;
+    o.uR = 0.0f;
+    for (int k = 0; k < D; k++) { o.uL += o.xl[1 + k] * o.nrm[k]; o.uR += o.xr[1 + k] * o.nrm[k]; }
+    return o;
+}
+
+template <int D>
+__device__ __forceinline__ void mixed_lab_flux(const MixedFace<D> &m, double rho, double u, double P, int side,
+                                               const double *__restrict__ wf64, int64_t f, double g_over_gm1,
+                                               double dt, double *__restrict__ out) {
+    using Y = Lay<D>;
+    const float *xs = side ? m.xr : m.xl;
+    const float un = side ? m.uR : m.uL;
+    double tv[D], nd[D], w[D];
+    for (int k = 0; k < D; k++) {
+        tv[k] = (double)(xs[1 + k] - un * m.nrm[k]);
+        nd[k] = (double)m.nrm[k];
+        w[k] = wf64[f * Y::WSTRIDE + k];
+    }
+    lab_flux<D>(rho, u, P, tv, nd, w, g_over_gm1, dt * (double)m.A, out);
+}
+
+// Mixed-precision face flux: float face states and float Newton; the
+// lab-frame flux and everything after it in double. Faces the float solve
+// judges hard (strong rarefaction or near vacuum, tiny guess, no
+// convergence) are appended to a compact list (wave-aggregated) and left to
+// k_face_flux_hard.
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_face_flux_mixed(int64_t nf, const int32_t *__restrict__ fL,
                                                             const int32_t *__restrict__ fR,
@@ -241,65 +300,66 @@ __global__ void __launch_bounds__(kBlock) k_face_flux_mixed(int64_t nf, const in
                                                             const double *__restrict__ wf64,
                                                             const float *__restrict__ rec,
                                                             const double *__restrict__ dt_ptr, double dt_val,
-                                                            double gamma, double tol32, double tol64, int maxit,
-                                                            const MlpGuess *mlp, double *__restrict__ flux,
+                                                            GasConst<float> kf, double g_over_gm1, float tol32,
+                                                            int maxit, const MlpGuess *mlp,
+                                                            double *__restrict__ flux, int32_t *__restrict__ hard_list,
                                                             DiagDev *diag) {
-    using Y = Lay<D>;
-    constexpr int NV = D + 2;
     const int64_t f = xcd_global_id();
     LaneDiag ld;
+    bool hard = false;
     if (f < nf) {
         const double dt = dt_ptr ? *dt_ptr : dt_val;
-        const float hdt = (float)(0.5 * dt);
-        const float *fr = mrec + f * Y::MREC;
-        const float A = fr[Y::FA], hl = 0.5f * fr[Y::FELL];
-        float nrm[D], gL[D], gR[D];
-        for (int k = 0; k < D; k++) {
-            nrm[k] = fr[Y::FN + k];
-            const float c = fr[Y::FC + k];
-            gL[k] = c + hl * nrm[k];
-            gR[k] = c - hl * nrm[k];
-        }
-        const float *rl = rec + (int64_t)fL[f] * Y::REC;
-        const float *rr = rec + (int64_t)fR[f] * Y::REC;
-        const float gf = (float)gamma;
-        float xl[NV], xr[NV], cl[NV], cr[NV], vf[D];
-        for (int k = 0; k < D; k++) vf[k] = rl[Y::W + 1 + k] + fr[Y::MDWL + k];
-        half_step<D, float>(rl, vf, gL, gf, hdt, xl, cl);
-        for (int k = 0; k < D; k++) vf[k] = rr[Y::W + 1 + k] + fr[Y::MDWR + k];
-        half_step<D, float>(rr, vf, gR, gf, hdt, xr, cr);
-        if (!(xl[0] > 0.0f && xl[NV - 1] > 0.0f && xr[0] > 0.0f && xr[NV - 1] > 0.0f)) {
-            for (int c = 0; c < NV; c++) { xl[c] = cl[c]; xr[c] = cr[c]; }
-            ld.posfb = 1;
-        }
-        float uL = 0.0f, uR = 0.0f;
-        for (int k = 0; k < D; k++) { uL += xl[1 + k] * nrm[k]; uR += xr[1 + k] * nrm[k]; }
-        const GasConst<float> kf(gamma);
-        bool hard;
-        const float pl = mlp ? mlp_guess_lane(*mlp, xl[0], uL, xl[NV - 1], xr[0], uR, xr[NV - 1], gamma) : -1.0f;
-        FaceState<float> fs = solve_face<float>(xl[0], uL, xl[NV - 1], xr[0], uR, xr[NV - 1], kf, (float)tol32,
+        const MixedFace<D> m = mixed_face_states<D>(f, fL, fR, mrec, rec, (float)(0.5 * dt), kf.g);
+        ld.posfb = m.posfb;
+        constexpr int NV = D + 2;
+        const float pl = mlp ? mlp_guess_lane(*mlp, m.xl[0], m.uL, m.xl[NV - 1], m.xr[0], m.uR, m.xr[NV - 1], kf.g)
+                             : -1.0f;
+        FaceState<float> fs = solve_face<float>(m.xl[0], m.uL, m.xl[NV - 1], m.xr[0], m.uR, m.xr[NV - 1], kf, tol32,
                                                 maxit, pl, true, ld, hard);
-        double rho, u, P;
-        int side;
+        if (!hard) mixed_lab_flux<D>(m, fs.rho, fs.u, fs.P, fs.side, wf64, f, g_over_gm1, dt, flux + f * NV);
+    }
+    // wave-aggregated append of the hard faces
+    const unsigned long long mask = __ballot(hard);
+    if (mask) {
+        const int lane = threadIdx.x & 63;
+        int base = 0;
+        if (lane == __ffsll((long long)mask) - 1) base = atomicAdd(hard_list, __popcll(mask));
+        base = __shfl(base, __ffsll((long long)mask) - 1, 64);
         if (hard) {
-            ld.fp64fb = 1;
-            const GasConst<double> kg(gamma);
-            bool h2;
-            FaceState<double> fd = solve_face<double>(xl[0], uL, xl[NV - 1], xr[0], uR, xr[NV - 1], kg, tol64,
-                                                      50, -1.0, false, ld, h2);
-            rho = fd.rho; u = fd.u; P = fd.P; side = fd.side;
-        } else {
-            rho = fs.rho; u = fs.u; P = fs.P; side = fs.side;
+            const int rank = __popcll(mask & ((1ull << lane) - 1ull));
+            hard_list[1 + base + rank] = (int32_t)f;
         }
-        const float *xs = side ? xr : xl;
-        const float un = side ? uR : uL;
-        double tv[D], nd[D], w[D];
-        for (int k = 0; k < D; k++) {
-            tv[k] = (double)(xs[1 + k] - un * nrm[k]);
-            nd[k] = (double)nrm[k];
-            w[k] = wf64[f * Y::WSTRIDE + k];
-        }
-        lab_flux<D>(rho, u, P, tv, nd, w, gamma / (gamma - 1.0), dt * (double)A, flux + f * NV);
+    }
+    if (diag) flush_diag(ld, diag);
+}
+
+// Double re-solve of the hard faces listed by k_face_flux_mixed (count in
+// hard_list[0], faces after it). A fixed grid strides over the list, so the
+// launch needs no host-side count; the float face states are recomputed by
+// the same code, hence identical.
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_face_flux_hard(const int32_t *__restrict__ fL,
+                                                           const int32_t *__restrict__ fR,
+                                                           const float *__restrict__ mrec,
+                                                           const double *__restrict__ wf64,
+                                                           const float *__restrict__ rec,
+                                                           const double *__restrict__ dt_ptr, double dt_val,
+                                                           float gam, GasConst<double> kg, double tol64,
+                                                           const int32_t *__restrict__ hard_list,
+                                                           double *__restrict__ flux, DiagDev *diag) {
+    constexpr int NV = D + 2;
+    const int count = hard_list[0];
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    const double dt = dt_ptr ? *dt_ptr : dt_val;
+    LaneDiag ld;
+    for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < count; q += stride) {
+        const int64_t f = hard_list[1 + q];
+        const MixedFace<D> m = mixed_face_states<D>(f, fL, fR, mrec, rec, (float)(0.5 * dt), gam);
+        bool h2;
+        FaceState<double> fd = solve_face<double>(m.xl[0], m.uL, m.xl[NV - 1], m.xr[0], m.uR, m.xr[NV - 1], kg,
+                                                  tol64, 50, -1.0, false, ld, h2);
+        ld.fp64fb += 1;
+        mixed_lab_flux<D>(m, fd.rho, fd.u, fd.P, fd.side, wf64, f, kg.g_over_gm1, dt, flux + f * NV);
     }
     if (diag) flush_diag(ld, diag);
 }

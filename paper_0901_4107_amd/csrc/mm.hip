@@ -30,7 +30,7 @@ inline int64_t align256(int64_t x) { return (x + 255) / 256 * 256; }
 struct Layout {
     int64_t flags, diag, dtdev, dtpart, bsum, off, cursor, ent, nbr;
     int64_t srec, frec, rec, flux;          // double path (frec always)
-    int64_t srec32, mrec, wf64, rec32;      // mixed path
+    int64_t srec32, mrec, wf64, rec32, hard; // mixed path
     int64_t total;
 };
 
@@ -43,7 +43,7 @@ Layout make_layout(int D, int mode, int64_t n, int64_t nf) {
     int64_t o = 0;
     auto take = [&](int64_t bytes) { int64_t at = o; o += align256(bytes); return at; };
     L.flags = take(64 * sizeof(int32_t));
-    L.diag = take(sizeof(DiagDev));
+    L.diag = take(kDiagSlots * sizeof(DiagDev));
     L.dtdev = take(4 * sizeof(double));
     L.dtpart = take((int64_t)grid_for(n) * sizeof(double));
     int64_t bs = 0, m = n + 1;
@@ -56,7 +56,7 @@ Layout make_layout(int D, int mode, int64_t n, int64_t nf) {
     L.frec = take(nf * FREC * sizeof(double));
     L.flux = take(nf * NV * sizeof(double));
     L.srec = take(2 * nf * Lay<3>::SREC64 * sizeof(double));
-    L.srec32 = L.mrec = L.wf64 = L.rec32 = L.rec = -1;
+    L.srec32 = L.mrec = L.wf64 = L.rec32 = L.rec = L.hard = -1;
     if (mode == MM_FP64) {
         L.rec = take(n * REC * sizeof(double));
     } else {
@@ -64,6 +64,7 @@ Layout make_layout(int D, int mode, int64_t n, int64_t nf) {
         L.mrec = take(nf * Lay<3>::MREC * sizeof(float));
         L.wf64 = take(nf * WS * sizeof(double));
         L.rec32 = take(n * REC * sizeof(float));
+        L.hard = take((nf + 1) * sizeof(int32_t));
     }
     L.total = o;
     return L;
@@ -92,6 +93,9 @@ struct mm_ctx {
     } while (0)
 
 #define MM_LAUNCH_CHECK() MM_CHECK(hipGetLastError())
+
+// Fixed grid of the hard-face pass (it strides over a device-side list).
+constexpr unsigned kHardGrid = 2048;
 
 static unsigned plain_grid(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
@@ -157,7 +161,8 @@ mm_status mm_set_workspace(mm_ctx *ctx, void *dev_ptr, int64_t bytes) {
 
 static mm_status clear_diag(mm_ctx *c) {
     // fill kernels rather than memset nodes, so callers may capture this
-    k_fill_i32<<<1, kBlock, 0, c->st()>>>(c->at<int32_t>(c->lay.diag), sizeof(DiagDev) / sizeof(int32_t), 0);
+    const int64_t nd = kDiagSlots * sizeof(DiagDev) / sizeof(int32_t);
+    k_fill_i32<<<plain_grid(nd), kBlock, 0, c->st()>>>(c->at<int32_t>(c->lay.diag), nd, 0);
     k_fill_i32<<<1, kBlock, 0, c->st()>>>(c->at<int32_t>(c->lay.flags) + 1, 1, 0);
     MM_LAUNCH_CHECK();
     c->faces_done = 0;
@@ -276,15 +281,23 @@ static mm_status fluxes_t(mm_ctx *c, const double *dt_dev, double dt, const void
     hipStream_t s = c->st();
     DiagDev *diag = c->at<DiagDev>(L.diag);
     const MlpGuess *mlp = nullptr;
+    const GasConst<double> kg(c->p.gamma);
+    const GasConst<float> kf(c->p.gamma);
     if (c->p.mode == MM_FP64)
         k_face_flux64<D><<<grid_for(c->nf), kBlock, 0, s>>>(c->nf, c->mesh.face_L, c->mesh.face_R,
                                                             c->at<double>(L.frec), (const double *)rec, dt_dev, dt,
-                                                            c->p.gamma, c->p.newton_tol64, c->p.newton_max_iter, mlp,
+                                                            kg, c->p.newton_tol64, c->p.newton_max_iter, mlp,
                                                             flux, diag);
-    else
+    else {
+        int32_t *hard = c->at<int32_t>(L.hard);
+        k_fill_i32<<<1, kBlock, 0, s>>>(hard, 1, 0);
         k_face_flux_mixed<D><<<grid_for(c->nf), kBlock, 0, s>>>(
             c->nf, c->mesh.face_L, c->mesh.face_R, c->at<float>(L.mrec), c->at<double>(L.wf64), (const float *)rec,
-            dt_dev, dt, c->p.gamma, c->p.newton_tol32, c->p.newton_tol64, c->p.newton_max_iter, mlp, flux, diag);
+            dt_dev, dt, kf, kg.g_over_gm1, (float)c->p.newton_tol32, c->p.newton_max_iter, mlp, flux, hard, diag);
+        k_face_flux_hard<D><<<kHardGrid, kBlock, 0, s>>>(c->mesh.face_L, c->mesh.face_R, c->at<float>(L.mrec),
+                                                        c->at<double>(L.wf64), (const float *)rec, dt_dev, dt, kf.g,
+                                                        kg, c->p.newton_tol64, hard, flux, diag);
+    }
     MM_LAUNCH_CHECK();
     return MM_OK;
 }
@@ -363,12 +376,24 @@ mm_status mm_reset_diag(mm_ctx *c) {
 mm_status mm_get_diag(mm_ctx *c, mm_diag *out) {
     if (!c || !out) return MM_E_ARG;
     if (!c->have_mesh) return MM_E_STATE;
-    DiagDev d;
+    DiagDev slots[kDiagSlots];
     int32_t nonfin = 0;
-    MM_CHECK(hipMemcpyAsync(&d, c->at<char>(c->lay.diag), sizeof(DiagDev), hipMemcpyDeviceToHost, c->st()));
+    MM_CHECK(hipMemcpyAsync(slots, c->at<char>(c->lay.diag), sizeof(slots), hipMemcpyDeviceToHost, c->st()));
     MM_CHECK(hipMemcpyAsync(&nonfin, c->at<int32_t>(c->lay.flags) + 1, sizeof(int32_t), hipMemcpyDeviceToHost,
                             c->st()));
     MM_CHECK(hipStreamSynchronize(c->st()));
+    DiagDev d;
+    std::memset(&d, 0, sizeof(d));
+    for (int k = 0; k < kDiagSlots; k++) {
+        d.newton_iters += slots[k].newton_iters;
+        d.newton_max = slots[k].newton_max > d.newton_max ? slots[k].newton_max : d.newton_max;
+        d.unconverged += slots[k].unconverged;
+        d.vacuum += slots[k].vacuum;
+        d.positivity_fallback += slots[k].positivity_fallback;
+        d.fp64_fallback += slots[k].fp64_fallback;
+        d.guess_fallback += slots[k].guess_fallback;
+        d.wave_iter_max_sum += slots[k].wave_iter_max_sum;
+    }
     std::memset(out, 0, sizeof(*out));
     out->faces = c->faces_done;
     out->newton_iters = d.newton_iters;

@@ -9,6 +9,13 @@
 // method from any positive start lands at or below the root after one step
 // and then rises monotonically to it; a step that lands at p <= 0 is
 // replaced by a tenth of the previous iterate.
+//
+// Cost notes (gfx950): powers are exp2(y log2 x) (hardware v_exp/v_log in
+// float; the library's double log2/exp2, whose combined error |y log2 x|
+// ulp stays far below the parity bound, in double). u* and the star-state
+// powers reuse the last Newton evaluation with a first-order correction in
+// the final step (error O(step^2), below 1e-18 relative at convergence), and
+// integer exponents 2/(g-1) (3 for g = 5/3, 5 for g = 7/5) are multiplied out.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -19,32 +26,43 @@ namespace mm {
 enum RiemannCase : int { RC_NORMAL = 0, RC_LEFT_VACUUM = 1, RC_RIGHT_VACUUM = 2,
                          RC_VACUUM_GENERATED = 3, RC_BOTH_VACUUM = 4 };
 
+// Constants of the equation of state, built once on the host.
 template <typename T> struct GasConst {
-    T g, gm1, gp1, z, inv_z, zs1, zs2, gm_ratio, inv_g, two_over_gm1, two_over_gp1,
-      gm1_over_2, exp_rho, exp_P, g_over_gm1;
-    __device__ __forceinline__ explicit GasConst(double gamma) {
+    T g, z, inv_z, zs1, zs2, gm_ratio, two_over_gm1, two_over_gp1, gm1_over_2, g_over_gm1, exp_rho;
+    int iexp_rho;   // 2/(g-1) when it is a small integer, else 0
+    __host__ __device__ GasConst() {}
+    __host__ explicit GasConst(double gamma) {
         g = (T)gamma;
-        gm1 = (T)(gamma - 1.0);
-        gp1 = (T)(gamma + 1.0);
         z = (T)((gamma - 1.0) / (2.0 * gamma));
         inv_z = (T)(2.0 * gamma / (gamma - 1.0));
         zs1 = (T)((gamma + 1.0) / (2.0 * gamma));
         zs2 = (T)((gamma - 1.0) / (2.0 * gamma));
         gm_ratio = (T)((gamma - 1.0) / (gamma + 1.0));
-        inv_g = (T)(1.0 / gamma);
         two_over_gm1 = (T)(2.0 / (gamma - 1.0));
         two_over_gp1 = (T)(2.0 / (gamma + 1.0));
         gm1_over_2 = (T)(0.5 * (gamma - 1.0));
-        exp_rho = (T)(2.0 / (gamma - 1.0));
-        exp_P = (T)(2.0 * gamma / (gamma - 1.0));
         g_over_gm1 = (T)(gamma / (gamma - 1.0));
+        const double e = 2.0 / (gamma - 1.0);
+        exp_rho = (T)e;
+        const double r = (double)(long)(e + 0.5);
+        iexp_rho = (r >= 1.0 && r <= 8.0 && (e - r) < 1e-12 && (r - e) < 1e-12) ? (int)r : 0;
     }
 };
 
-__device__ __forceinline__ double mm_pow(double x, double y) { return pow(x, y); }
+__device__ __forceinline__ double mm_pow(double x, double y) { return exp2(y * log2(x)); }
 __device__ __forceinline__ float mm_pow(float x, float y) { return __builtin_amdgcn_exp2f(y * __builtin_amdgcn_logf(x)); }
 __device__ __forceinline__ double mm_sqrt(double x) { return sqrt(x); }
 __device__ __forceinline__ float mm_sqrt(float x) { return __builtin_sqrtf(x); }
+
+// x^(2/(g-1)): multiplied out for integer exponents.
+template <typename T> __device__ __forceinline__ T pow_rho(T x, const GasConst<T> &k) {
+    if (k.iexp_rho > 0) {
+        T r = x;
+        for (int q = 1; q < k.iexp_rho; q++) r *= x;
+        return r;
+    }
+    return mm_pow(x, k.exp_rho);
+}
 
 // One side of the Riemann problem with the constants of its pressure branch.
 template <typename T> struct Side {
@@ -68,16 +86,18 @@ __device__ __forceinline__ Side<T> make_side(T rho, T u, T P, const GasConst<T> 
     return s;
 }
 
+// f_K(p) and f_K'(p); pw receives (p/p_K)^z on the isentropic branch.
 template <typename T>
-__device__ __forceinline__ void side_fn(T p, const Side<T> &s, const GasConst<T> &k, T &f, T &df) {
+__device__ __forceinline__ void side_fn(T p, const Side<T> &s, const GasConst<T> &k, T &f, T &df, T &pw) {
     if (p > s.P) {
         T pb = p + s.B;
         T q = mm_sqrt(s.A / pb);
         f = (p - s.P) * q;
         df = q * ((T)1 - (T)0.5 * (p - s.P) / pb);
+        pw = (T)-1;
     } else {
         T r = p * s.inv_P;
-        T pw = mm_pow(r, k.z);
+        pw = mm_pow(r, k.z);
         f = s.fc * (pw - (T)1);
         df = s.inv_rc * pw / r;
     }
@@ -108,49 +128,74 @@ __device__ __forceinline__ T standard_guess(const Side<T> &L, const Side<T> &R, 
     return pts > (T)0 ? pts : ppv;
 }
 
-// Newton iteration on the pressure function. Returns the iteration count;
-// *conv tells whether it converged: the relative step fell below tol, or
-// f(p) vanished to within the rounding of its own terms (near vacuum the
+// Result of the Newton iteration: the star state and the side powers
+// (p*/p_K)^z of isentropic sides, for sampling.
+template <typename T> struct Star {
+    T ps, us, pwL, pwR;
+    int iters;
+    bool conv;
+};
+
+// Newton iteration on the pressure function, then u* = (u_L+u_R)/2 +
+// (f_R(p*) - f_L(p*))/2. Converged when the relative step falls below tol or
+// f(p) vanishes to within the rounding of its own terms (near vacuum the
 // root can be ~1e-30 of the side pressures, where f' p is so small that
 // rounding noise in f alone moves p by more than tol).
 template <typename T>
-__device__ __forceinline__ int newton_star(const Side<T> &L, const Side<T> &R, const GasConst<T> &k,
-                                           T p, T tol, int maxit, T &pstar, bool &conv) {
-    T du = R.u - L.u;
-    int it = 0;
-    conv = false;
-    if (!(p > (T)0)) p = (T)0.5 * (L.P + R.P);
+__device__ __forceinline__ Star<T> newton_star(const Side<T> &L, const Side<T> &R, const GasConst<T> &k, T p,
+                                               T tol, int maxit) {
+    const T du = R.u - L.u;
     const T noise = (T)8 * (sizeof(T) == 8 ? (T)2.220446049250313e-16 : (T)1.1920929e-7);
-    while (it < maxit) {
-        T fl, dfl, fr, dfr;
-        side_fn(p, L, k, fl, dfl);
-        side_fn(p, R, k, fr, dfr);
+    Star<T> st;
+    st.iters = 0;
+    st.conv = false;
+    if (!(p > (T)0)) p = (T)0.5 * (L.P + R.P);
+    T fl = 0, fr = 0, dfl = 1, dfr = 1, pwl = -1, pwr = -1, plast = p;
+    while (st.iters < maxit) {
+        side_fn(p, L, k, fl, dfl, pwl);
+        side_fn(p, R, k, fr, dfr, pwr);
         const T fsum = fl + fr + du;
         T pn = p - fsum / (dfl + dfr);
         if (!(pn > (T)0)) pn = (T)0.1 * p;
-        it++;
-        bool done = fabs(pn - p) <= tol * (T)0.5 * (pn + p) ||
-                    fabs(fsum) <= noise * (fabs(fl) + fabs(fr) + fabs(du));
+        st.iters++;
+        const bool done = fabs(pn - p) <= tol * (T)0.5 * (pn + p) ||
+                          fabs(fsum) <= noise * (fabs(fl) + fabs(fr) + fabs(du));
+        plast = p;
         p = pn;
-        if (done) { conv = true; break; }
+        if (done) { st.conv = true; break; }
     }
-    pstar = p;
-    return it;
+    st.ps = p;
+    const T dlt = p - plast;
+    const bool small = fabs(dlt) <= (T)1e-6 * plast;
+    if (small) {
+        st.us = (T)0.5 * (L.u + R.u) + (T)0.5 * ((fr + dfr * dlt) - (fl + dfl * dlt));
+    } else {
+        T a, b, c2, d2, e1, e2;
+        side_fn(p, L, k, a, b, e1);
+        side_fn(p, R, k, c2, d2, e2);
+        st.us = (T)0.5 * (L.u + R.u) + (T)0.5 * (c2 - a);
+    }
+    const T corr = (T)1 + k.z * dlt / plast;
+    st.pwL = (p <= L.P) ? ((small && pwl > (T)0) ? pwl * corr : mm_pow(p * L.inv_P, k.z)) : (T)-1;
+    st.pwR = (p <= R.P) ? ((small && pwr > (T)0) ? pwr * corr : mm_pow(p * R.inv_P, k.z)) : (T)-1;
+    return st;
 }
 
 template <typename T> struct FaceState { T rho, u, P; int side; };
 
 // Rarefaction fan of side K sampled at x/t = 0; `left` selects the
 // characteristic family (u - c for the left state, u + c for the right).
+// rho = rho_K (c/c_K)^(2/(g-1)), P = P_K (c/c_K)^(2g/(g-1)) = P_K (c/c_K)^(2/(g-1)) (c/c_K)^2.
 template <typename T>
 __device__ __forceinline__ FaceState<T> fan0(const Side<T> &K, bool left, const GasConst<T> &k) {
     FaceState<T> o;
     T c = left ? k.two_over_gp1 * (K.c + k.gm1_over_2 * K.u)
                : k.two_over_gp1 * (K.c - k.gm1_over_2 * K.u);
     T ratio = c / K.c;
-    o.rho = K.rho * mm_pow(ratio, k.exp_rho);
+    T pr = pow_rho(ratio, k);
+    o.rho = K.rho * pr;
     o.u = left ? c : -c;
-    o.P = K.P * mm_pow(ratio, k.exp_P);
+    o.P = K.P * pr * ratio * ratio;
     o.side = left ? 0 : 1;
     return o;
 }
@@ -166,21 +211,18 @@ __device__ __forceinline__ FaceState<T> vac(int side) {
 }
 
 // Vacuum cases that need no star pressure. Returns true (and fills *o) if
-// the problem is one of them.
+// the problem is one of them; otherwise leaves vac_num for the guess.
 template <typename T>
-__device__ __forceinline__ bool vacuum_cases(T rhoL, T uL, T PL, T rhoR, T uR, T PR, const GasConst<T> &k,
-                                             const Side<T> &L, const Side<T> &R, bool lvac, bool rvac,
-                                             FaceState<T> &o, int &kase, T &vac_num) {
-    if (lvac && rvac) { o = vac<T>(0); kase = RC_BOTH_VACUUM; return true; }
+__device__ __forceinline__ bool vacuum_cases(const GasConst<T> &k, const Side<T> &L, const Side<T> &R, bool lvac,
+                                             bool rvac, FaceState<T> &o, T &vac_num) {
+    if (lvac && rvac) { o = vac<T>(0); return true; }
     if (lvac) {
-        kase = RC_LEFT_VACUUM;
         if ((T)0 >= R.u + R.c) o = undisturbed(R, 1);
         else if ((T)0 <= R.u - k.two_over_gm1 * R.c) o = vac<T>(1);
         else o = fan0(R, false, k);
         return true;
     }
     if (rvac) {
-        kase = RC_RIGHT_VACUUM;
         if ((T)0 <= L.u - L.c) o = undisturbed(L, 0);
         else if ((T)0 >= L.u + k.two_over_gm1 * L.c) o = vac<T>(0);
         else o = fan0(L, true, k);
@@ -188,7 +230,6 @@ __device__ __forceinline__ bool vacuum_cases(T rhoL, T uL, T PL, T rhoR, T uR, T
     }
     vac_num = L.c + R.c - k.gm1_over_2 * (R.u - L.u);
     if (!(vac_num > (T)0)) {
-        kase = RC_VACUUM_GENERATED;
         T frontL = L.u + k.two_over_gm1 * L.c;
         T frontR = R.u - k.two_over_gm1 * R.c;
         if ((T)0 <= frontL) o = ((T)0 <= L.u - L.c) ? undisturbed(L, 0) : fan0(L, true, k);
@@ -199,51 +240,45 @@ __device__ __forceinline__ bool vacuum_cases(T rhoL, T uL, T PL, T rhoR, T uR, T
     return false;
 }
 
-// Sample the solution with known star state at x/t = 0.
+// Sample the solution with known star state at x/t = 0. s.pwK = (p*/p_K)^z
+// on an isentropic side.
 template <typename T>
-__device__ __forceinline__ FaceState<T> sample0(const Side<T> &L, const Side<T> &R, T ps, T us,
+__device__ __forceinline__ FaceState<T> sample0(const Side<T> &L, const Side<T> &R, const Star<T> &s,
                                                 const GasConst<T> &k) {
+    const T ps = s.ps, us = s.us;
+    FaceState<T> o;
+    o.u = us;
+    o.P = ps;
     if ((T)0 <= us) {
+        o.side = 0;
         if (ps > L.P) {
             T SL = L.u - L.c * mm_sqrt(k.zs1 * ps * L.inv_P + k.zs2);
             if ((T)0 <= SL) return undisturbed(L, 0);
             T r = ps * L.inv_P;
-            FaceState<T> o; o.rho = L.rho * (r + k.gm_ratio) / (k.gm_ratio * r + (T)1); o.u = us; o.P = ps; o.side = 0;
+            o.rho = L.rho * (r + k.gm_ratio) / (k.gm_ratio * r + (T)1);
             return o;
         }
         if ((T)0 <= L.u - L.c) return undisturbed(L, 0);
-        T r = ps * L.inv_P;
-        T cs = L.c * mm_pow(r, k.z);
-        if ((T)0 >= us - cs) {
-            FaceState<T> o; o.rho = L.rho * mm_pow(r, k.inv_g); o.u = us; o.P = ps; o.side = 0;
+        if ((T)0 >= us - L.c * s.pwL) {
+            o.rho = L.rho * pow_rho(s.pwL, k);   // (p*/p_L)^(1/g) = ((p*/p_L)^z)^(2/(g-1))
             return o;
         }
         return fan0(L, true, k);
     }
+    o.side = 1;
     if (ps > R.P) {
         T SR = R.u + R.c * mm_sqrt(k.zs1 * ps * R.inv_P + k.zs2);
         if ((T)0 >= SR) return undisturbed(R, 1);
         T r = ps * R.inv_P;
-        FaceState<T> o; o.rho = R.rho * (r + k.gm_ratio) / (k.gm_ratio * r + (T)1); o.u = us; o.P = ps; o.side = 1;
+        o.rho = R.rho * (r + k.gm_ratio) / (k.gm_ratio * r + (T)1);
         return o;
     }
     if ((T)0 >= R.u + R.c) return undisturbed(R, 1);
-    T r = ps * R.inv_P;
-    T cs = R.c * mm_pow(r, k.z);
-    if ((T)0 <= us + cs) {
-        FaceState<T> o; o.rho = R.rho * mm_pow(r, k.inv_g); o.u = us; o.P = ps; o.side = 1;
+    if ((T)0 <= us + R.c * s.pwR) {
+        o.rho = R.rho * pow_rho(s.pwR, k);
         return o;
     }
     return fan0(R, false, k);
-}
-
-// u* from the converged star pressure.
-template <typename T>
-__device__ __forceinline__ T star_velocity(const Side<T> &L, const Side<T> &R, T ps, const GasConst<T> &k) {
-    T fl, dfl, fr, dfr;
-    side_fn(ps, L, k, fl, dfl);
-    side_fn(ps, R, k, fr, dfr);
-    return (T)0.5 * (L.u + R.u) + (T)0.5 * (fr - fl);
 }
 
 }  // namespace mm

@@ -42,6 +42,7 @@ def test_kh3d_boosted_l1(n_points):
     assert np.all(err <= L1_BOUND), err
     # conservation is exact up to double rounding in every mode
     scale = np.abs(wl.Q).sum(axis=1)
+    scale[1:4] = np.sum(np.sqrt(np.sum(wl.Q[1:4] ** 2, axis=0)))  # momentum scale
     assert np.all(np.abs(Qm.sum(axis=1) - wl.Q.sum(axis=1)) <= 1e-13 * scale)
 
 
