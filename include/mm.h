@@ -164,6 +164,65 @@ mm_status mm_apply_update(mm_ctx *ctx, const double *face_flux, double *Q);
  * value; with dt_used NULL it returns without waiting. */
 mm_status mm_hydro_step(mm_ctx *ctx, double *Q, double dt, double *dt_used);
 
+/* ------------------------------------------------------------------------
+ * Learned starting guess for the Newton iteration on the star pressure
+ * (a 3 -> 64 -> 64 -> 1 ReLU network; not part of the paper's method, which
+ * leaves the guess to its cited exact solver). The parameter vector is
+ * MM_MLP_PARAMS floats on the device:
+ *   W1 [3][64] (input-major), b1 [64], W2 [64][64] (input-major), b2 [64],
+ *   w3 [64], b3 [1].
+ * Inputs x = (ln(rho_R/rho_L)/5, ln(P_R/P_L)/5, (u_R - u_L)/(c_L + c_R)/2),
+ * output y = predicted ln(p* / p_std) with p_std the standard guess, so the
+ * learned guess is p = p_std exp(y). The guess only changes where Newton
+ * starts: every face still converges to tolerance, and a face whose
+ * iteration does not converge from it restarts from the standard guess.
+ * ------------------------------------------------------------------------ */
+#define MM_MLP_PARAMS 4481
+
+/* Pack a trained parameter vector (device floats) into the context's
+ * workspace in bf16 matrix-core operand order. With params.guess ==
+ * MM_GUESS_LEARNED, later flux calls use it for faces outside the regime
+ * where the standard guess is its primitive-variable estimate. Needs a
+ * workspace (mm_set_workspace; mm_workspace_bytes(ctx, 2, 1) suffices). */
+mm_status mm_mlp_load(mm_ctx *ctx, const float *params);
+
+/* Fused bf16 inference of the loaded network on features X [n][3] -> Y [n]
+ * (the same device code the flux kernels run; for tests). */
+mm_status mm_mlp_infer(mm_ctx *ctx, int64_t n, const float *X, float *Y);
+
+/* fp32 reference forward of a parameter vector: X [n][3] -> Y [n]. */
+mm_status mm_mlp_forward(const float *params, int64_t n, const float *X, float *Y, void *stream);
+
+/* Training: gradient of the loss sum_s (y_s - T_s)^2 / n_total over the n
+ * samples X [n][3], T [n], written to grad [MM_MLP_PARAMS + 1] (the last
+ * element is the loss). scratch is device memory of
+ * mm_mlp_grad_scratch_bytes(n) bytes. Deterministic (fixed summation order). */
+int64_t mm_mlp_grad_scratch_bytes(int64_t n);
+mm_status mm_mlp_grad(const float *params, int64_t n, int64_t n_total, const float *X, const float *T,
+                      void *scratch, float *grad, void *stream);
+
+/* One Adam step (bias-corrected with step >= 1) on params from grad, with
+ * first and second moment buffers m1, m2 [MM_MLP_PARAMS]. */
+mm_status mm_mlp_adam(float *params, const float *grad, float *m1, float *m2, float lr, float beta1,
+                      float beta2, float eps, int32_t step, void *stream);
+
+/* n independent 1D Riemann problems, states [6][n] double (rho_L, u_L, P_L,
+ * rho_R, u_R, P_R), solved exactly with the context's mode (MM_FP64: double;
+ * MM_MIXED: float, hard problems re-solved in double) and guess, sampled at
+ * x/t = 0: out [n][5] double = (rho_F, u_F, P_F, p*, p_std), p* the star
+ * pressure and p_std the standard starting guess (both -1 where the problem
+ * has no star state: vacuum); iters [n] (optional) the Newton
+ * iterations of each problem. Counts into the diagnostics. Needs a
+ * workspace, not a mesh. */
+mm_status mm_riemann_batch(mm_ctx *ctx, int64_t n, const double *states, double *out, int32_t *iters);
+
+/* The face-frame Riemann inputs of every face of the uploaded mesh for a
+ * step dt > 0 from double reconstruction records (MM_FP64 contexts only):
+ * out [6][F] float = (rho_L, u_L, P_L, rho_R, u_R, P_R) after extrapolation,
+ * u along the L->R normal. Harvests training problems from the method's own
+ * runs. */
+mm_status mm_face_states(mm_ctx *ctx, double dt, const void *recon, float *out);
+
 /* Diagnostics accumulated since the last reset; synchronises. */
 mm_status mm_get_diag(mm_ctx *ctx, mm_diag *out);
 mm_status mm_reset_diag(mm_ctx *ctx);

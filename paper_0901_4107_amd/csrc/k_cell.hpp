@@ -13,19 +13,41 @@
 
 namespace mm {
 
-template <int D> struct Group { static constexpr int GS = (D == 3) ? 16 : 8; };
+template <int D> struct Group { static constexpr int GS = (D == 3) ? 8 : 4; };
 
-template <int GS, typename T> __device__ __forceinline__ T grp_sum(T v) {
-    for (int o = GS / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+// Cross-lane moves inside 16-lane rows by DPP (no LDS round trip):
+// quad_perm xor 1 and xor 2, then row_half_mirror (lane i <- 7 - i within 8)
+// and row_mirror (i <- 15 - i). After the quad steps every lane of a quad
+// holds the quad's result, so the mirrors combine whole quads and halves:
+// all GS lanes of a group end with the group's result.
+enum : int { DPP_XOR1 = 0xB1, DPP_XOR2 = 0x4E, DPP_HALF_MIRROR = 0x141, DPP_MIRROR = 0x140 };
+
+template <int CTRL> __device__ __forceinline__ float dpp(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL> __device__ __forceinline__ double dpp(double v) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+template <int GS, typename T, typename Op> __device__ __forceinline__ T grp_reduce(T v, Op op) {
+    static_assert(GS == 4 || GS == 8 || GS == 16, "group size");
+    v = op(v, dpp<DPP_XOR1>(v));
+    v = op(v, dpp<DPP_XOR2>(v));
+    if (GS >= 8) v = op(v, dpp<DPP_HALF_MIRROR>(v));
+    if (GS >= 16) v = op(v, dpp<DPP_MIRROR>(v));
     return v;
+}
+template <int GS, typename T> __device__ __forceinline__ T grp_sum(T v) {
+    return grp_reduce<GS>(v, [](T a, T b) { return a + b; });
 }
 template <int GS, typename T> __device__ __forceinline__ T grp_max(T v) {
-    for (int o = GS / 2; o > 0; o >>= 1) { T u = __shfl_xor(v, o, 64); v = u > v ? u : v; }
-    return v;
+    return grp_reduce<GS>(v, [](T a, T b) { return a > b ? a : b; });
 }
 template <int GS, typename T> __device__ __forceinline__ T grp_min(T v) {
-    for (int o = GS / 2; o > 0; o >>= 1) { T u = __shfl_xor(v, o, 64); v = u < v ? u : v; }
-    return v;
+    return grp_reduce<GS>(v, [](T a, T b) { return a < b ? a : b; });
 }
 
 // Block-wide minimum of one double per lane; result valid in lane 0.

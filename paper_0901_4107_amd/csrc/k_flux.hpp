@@ -116,12 +116,14 @@ __device__ __forceinline__ void half_step(const T *__restrict__ r, const T *vfac
 }
 
 // Solve one face's Riemann problem in precision T with the standard or the
-// learned starting guess. Returns the sampled state; fills the counters.
-// `hard` (mixed path only) reports a face that needs the double solve: a
-// strong rarefaction or near-vacuum problem, a tiny guess, or no convergence.
+// learned starting guess. The learned guess is the standard one times
+// exp(corr), corr the network's output (NaN: no learned guess). Returns the
+// sampled state; fills the counters. `hard` (mixed path only) reports a face
+// that needs the double solve: a strong rarefaction or near-vacuum problem,
+// a tiny guess, or no convergence.
 template <typename T>
 __device__ __forceinline__ FaceState<T> solve_face(T rhoL, T uL, T PL, T rhoR, T uR, T PR, const GasConst<T> &kg,
-                                                   T tol, int maxit, T p_learned, bool check_hard,
+                                                   T tol, int maxit, T corr, bool check_hard,
                                                    LaneDiag &ld, bool &hard) {
     hard = false;
     const bool lvac = !(rhoL > (T)0 && PL > (T)0);
@@ -132,11 +134,14 @@ __device__ __forceinline__ FaceState<T> solve_face(T rhoL, T uL, T PL, T rhoR, T
     T vac_num = (T)0;
     if (vacuum_cases<T>(kg, SL, SR, lvac, rvac, fs, vac_num)) {
         ld.vacuum = 1;
+        fs.pstar = (T)-1;
+        fs.pstd = (T)-1;
         return fs;
     }
     const T p_std = standard_guess<T>(SL, SR, kg, vac_num);
-    const bool learned = p_learned > (T)0;
-    const T p0 = learned ? p_learned : p_std;
+    const bool learned = corr == corr;
+    const T p0 = learned ? p_std * (T)__expf((float)corr) : p_std;
+    fs.pstd = p_std;
     if (check_hard) {
         const T pmin = SL.P < SR.P ? SL.P : SR.P;
         if (vac_num < (T)0.5 * (SL.c + SR.c) || p0 < (T)1e-3 * pmin) { hard = true; return fs; }
@@ -154,7 +159,53 @@ __device__ __forceinline__ FaceState<T> solve_face(T rhoL, T uL, T PL, T rhoR, T
         if (check_hard) { hard = true; return fs; }
         ld.unconv = 1;
     }
-    return sample0<T>(SL, SR, st, kg);
+    fs = sample0<T>(SL, SR, st, kg);
+    fs.pstar = st.ps;
+    fs.pstd = p_std;
+    return fs;
+}
+
+template <typename T> __device__ __forceinline__ T no_guess() { return (T)__builtin_nan(""); }
+
+// Whether a problem takes the learned guess: both sides non-vacuum, no
+// vacuum generated, and a standard guess that is not already good: neither
+// the primitive-variable estimate in its accepted regime (mild pressure
+// ratio, estimate between the pressures) nor the two-rarefaction estimate
+// when both waves are rarefactions (then it is the exact root; that case is
+// f(p_min) >= 0, f increasing, where only the higher-pressure side
+// contributes: (2 c_max/(g-1)) ((p_min/p_max)^z - 1) + u_R - u_L >= 0).
+template <typename T>
+__device__ __forceinline__ bool wants_learned(T rhoL, T uL, T PL, T rhoR, T uR, T PR, T gamma) {
+    if (!(rhoL > (T)0 && PL > (T)0 && rhoR > (T)0 && PR > (T)0)) return false;
+    const T cL = mm_sqrt(gamma * PL / rhoL), cR = mm_sqrt(gamma * PR / rhoR);
+    const T du = uR - uL;
+    if (!(cL + cR - (T)0.5 * (gamma - (T)1) * du > (T)0)) return false;
+    const T ppv = (T)0.5 * (PL + PR) - (T)0.125 * du * (rhoL + rhoR) * (cL + cR);
+    const T pmin = PL < PR ? PL : PR, pmax = PL < PR ? PR : PL;
+    if (pmax <= (T)2 * pmin && ppv >= pmin && ppv <= pmax) return false;
+    if (ppv < pmin) {
+        const T cmax = PL < PR ? cR : cL;
+        const T z = (gamma - (T)1) / ((T)2 * gamma);
+        const T fmin = (T)2 * cmax / (gamma - (T)1) * (mm_pow(pmin / pmax, z) - (T)1) + du;
+        if (fmin >= (T)0) return false;
+    }
+    return true;
+}
+
+// The learned guess for a wavefront of problems (every lane must call;
+// lanes with want = false get -1). A wavefront where no lane wants a guess
+// skips the network.
+template <typename T>
+__device__ __forceinline__ T learned_guess(const MlpPacked *P, bool want, T rhoL, T uL, T PL, T rhoR, T uR, T PR,
+                                           float gamma) {
+    if (P == nullptr || __ballot(want) == 0ull) return no_guess<T>();
+    float x0 = 0.0f, x1 = 0.0f, x2 = 0.0f;
+    if (want) mlp_features((float)rhoL, (float)uL, (float)PL, (float)rhoR, (float)uR, (float)PR, gamma, x0, x1, x2);
+    const float y = mlp_wave_infer(P, x0, x1, x2);
+    if (!want) return no_guess<T>();
+    // the network predicts ln(p* / p_standard) / kMlpScaleY
+    const float corr = kMlpScaleY * y;
+    return (corr > -20.0f && corr < 20.0f) ? (T)corr : no_guess<T>();
 }
 
 // Lab-frame moving-face flux in double from the sampled face-frame state
@@ -179,23 +230,28 @@ __device__ __forceinline__ void lab_flux(double rho, double u, double P, const d
     out[NV - 1] = scale * (eps + Piw + 0.5 * mf * w2);
 }
 
-// Double-precision face flux.
-template <int D>
+// Double-precision face flux. LEARNED compiles the fused network in; the
+// standard-guess instantiation carries none of its registers.
+template <int D, bool LEARNED>
 __global__ void __launch_bounds__(kBlock) k_face_flux64(int64_t nf, const int32_t *__restrict__ fL,
                                                         const int32_t *__restrict__ fR, const double *__restrict__ frec,
                                                         const double *__restrict__ rec, const double *__restrict__ dt_ptr,
                                                         double dt_val, GasConst<double> kg, double tol, int maxit,
-                                                        const MlpGuess *mlp, double *__restrict__ flux, DiagDev *diag) {
+                                                        const MlpPacked *mlp, double *__restrict__ flux, DiagDev *diag) {
     using Y = Lay<D>;
     constexpr int NV = D + 2;
     const int64_t f = xcd_global_id();
+    const bool active = f < nf;
     LaneDiag ld;
-    if (f < nf) {
-        const double dt = dt_ptr ? *dt_ptr : dt_val;
+    const double dt = dt_ptr ? *dt_ptr : dt_val;
+    double A = 0.0, nrm[D], w[D], xl[NV], xr[NV], uL = 0.0, uR = 0.0;
+    for (int c = 0; c < NV; c++) { xl[c] = 1.0; xr[c] = 1.0; }
+    if (active) {
         const double hdt = 0.5 * dt;
         const double *fr = frec + f * Y::FREC;
-        const double A = fr[Y::FA], hl = 0.5 * fr[Y::FELL];
-        double nrm[D], w[D], gL[D], gR[D];
+        A = fr[Y::FA];
+        const double hl = 0.5 * fr[Y::FELL];
+        double gL[D], gR[D];
         for (int k = 0; k < D; k++) {
             nrm[k] = fr[Y::FN + k];
             w[k] = fr[Y::FW + k];
@@ -205,7 +261,7 @@ __global__ void __launch_bounds__(kBlock) k_face_flux64(int64_t nf, const int32_
         }
         const double *rl = rec + (int64_t)fL[f] * Y::REC;
         const double *rr = rec + (int64_t)fR[f] * Y::REC;
-        double xl[NV], xr[NV], cl[NV], cr[NV], vf[D];
+        double cl[NV], cr[NV], vf[D];
         for (int k = 0; k < D; k++) vf[k] = rl[Y::W + 1 + k] - w[k];
         half_step<D, double>(rl, vf, gL, kg.g, hdt, xl, cl);
         for (int k = 0; k < D; k++) vf[k] = rr[Y::W + 1 + k] - w[k];
@@ -214,11 +270,16 @@ __global__ void __launch_bounds__(kBlock) k_face_flux64(int64_t nf, const int32_
             for (int c = 0; c < NV; c++) { xl[c] = cl[c]; xr[c] = cr[c]; }
             ld.posfb = 1;
         }
-        double uL = 0.0, uR = 0.0;
         for (int k = 0; k < D; k++) { uL += xl[1 + k] * nrm[k]; uR += xr[1 + k] * nrm[k]; }
+    }
+    // learned guess: the whole wavefront evaluates the network together
+    double pl = no_guess<double>();
+    if constexpr (LEARNED) {
+        const bool want = active && wants_learned<double>(xl[0], uL, xl[NV - 1], xr[0], uR, xr[NV - 1], kg.g);
+        pl = learned_guess<double>(mlp, want, xl[0], uL, xl[NV - 1], xr[0], uR, xr[NV - 1], (float)kg.g);
+    }
+    if (active) {
         bool hard;
-        const double pl = mlp ? (double)mlp_guess_lane(*mlp, xl[0], uL, xl[NV - 1], xr[0], uR, xr[NV - 1], kg.g)
-                              : -1.0;
         FaceState<double> fs = solve_face<double>(xl[0], uL, xl[NV - 1], xr[0], uR, xr[NV - 1], kg, tol, maxit,
                                                   pl, false, ld, hard);
         const double *xs = fs.side ? xr : xl;
@@ -292,8 +353,8 @@ __device__ __forceinline__ void mixed_lab_flux(const MixedFace<D> &m, double rho
 // lab-frame flux and everything after it in double. Faces the float solve
 // judges hard (strong rarefaction or near vacuum, tiny guess, no
 // convergence) are appended to a compact list (wave-aggregated) and left to
-// k_face_flux_hard.
-template <int D>
+// k_face_flux_hard. LEARNED as for the double kernel.
+template <int D, bool LEARNED>
 __global__ void __launch_bounds__(kBlock) k_face_flux_mixed(int64_t nf, const int32_t *__restrict__ fL,
                                                             const int32_t *__restrict__ fR,
                                                             const float *__restrict__ mrec,
@@ -301,19 +362,32 @@ __global__ void __launch_bounds__(kBlock) k_face_flux_mixed(int64_t nf, const in
                                                             const float *__restrict__ rec,
                                                             const double *__restrict__ dt_ptr, double dt_val,
                                                             GasConst<float> kf, double g_over_gm1, float tol32,
-                                                            int maxit, const MlpGuess *mlp,
+                                                            int maxit, const MlpPacked *mlp,
                                                             double *__restrict__ flux, int32_t *__restrict__ hard_list,
                                                             DiagDev *diag) {
+    constexpr int NV = D + 2;
     const int64_t f = xcd_global_id();
+    const bool active = f < nf;
     LaneDiag ld;
     bool hard = false;
-    if (f < nf) {
-        const double dt = dt_ptr ? *dt_ptr : dt_val;
-        const MixedFace<D> m = mixed_face_states<D>(f, fL, fR, mrec, rec, (float)(0.5 * dt), kf.g);
+    const double dt = dt_ptr ? *dt_ptr : dt_val;
+    MixedFace<D> m;
+    if (active) {
+        m = mixed_face_states<D>(f, fL, fR, mrec, rec, (float)(0.5 * dt), kf.g);
         ld.posfb = m.posfb;
-        constexpr int NV = D + 2;
-        const float pl = mlp ? mlp_guess_lane(*mlp, m.xl[0], m.uL, m.xl[NV - 1], m.xr[0], m.uR, m.xr[NV - 1], kf.g)
-                             : -1.0f;
+    } else {
+        for (int c = 0; c < NV; c++) { m.xl[c] = 1.0f; m.xr[c] = 1.0f; }
+        m.uL = 0.0f;
+        m.uR = 0.0f;
+    }
+    // learned guess: the whole wavefront evaluates the network together
+    float pl = no_guess<float>();
+    if constexpr (LEARNED) {
+        const bool want =
+            active && wants_learned<float>(m.xl[0], m.uL, m.xl[NV - 1], m.xr[0], m.uR, m.xr[NV - 1], kf.g);
+        pl = learned_guess<float>(mlp, want, m.xl[0], m.uL, m.xl[NV - 1], m.xr[0], m.uR, m.xr[NV - 1], kf.g);
+    }
+    if (active) {
         FaceState<float> fs = solve_face<float>(m.xl[0], m.uL, m.xl[NV - 1], m.xr[0], m.uR, m.xr[NV - 1], kf, tol32,
                                                 maxit, pl, true, ld, hard);
         if (!hard) mixed_lab_flux<D>(m, fs.rho, fs.u, fs.P, fs.side, wf64, f, g_over_gm1, dt, flux + f * NV);
@@ -357,7 +431,7 @@ __global__ void __launch_bounds__(kBlock) k_face_flux_hard(const int32_t *__rest
         const MixedFace<D> m = mixed_face_states<D>(f, fL, fR, mrec, rec, (float)(0.5 * dt), gam);
         bool h2;
         FaceState<double> fd = solve_face<double>(m.xl[0], m.uL, m.xl[NV - 1], m.xr[0], m.uR, m.xr[NV - 1], kg,
-                                                  tol64, 50, -1.0, false, ld, h2);
+                                                  tol64, 50, no_guess<double>(), false, ld, h2);
         ld.fp64fb += 1;
         mixed_lab_flux<D>(m, fd.rho, fd.u, fd.P, fd.side, wf64, f, kg.g_over_gm1, dt, flux + f * NV);
     }

@@ -18,6 +18,7 @@
 #include "common.hpp"
 #include "k_cell.hpp"
 #include "k_flux.hpp"
+#include "k_learn.hpp"
 #include "k_mesh.hpp"
 #include "layout.hpp"
 
@@ -28,7 +29,7 @@ namespace {
 inline int64_t align256(int64_t x) { return (x + 255) / 256 * 256; }
 
 struct Layout {
-    int64_t flags, diag, dtdev, dtpart, bsum, off, cursor, ent, nbr;
+    int64_t flags, diag, mlp, dtdev, dtpart, bsum, off, cursor, ent, nbr;
     int64_t srec, frec, rec, flux;          // double path (frec always)
     int64_t srec32, mrec, wf64, rec32, hard; // mixed path
     int64_t total;
@@ -42,8 +43,10 @@ Layout make_layout(int D, int mode, int64_t n, int64_t nf) {
     Layout L;
     int64_t o = 0;
     auto take = [&](int64_t bytes) { int64_t at = o; o += align256(bytes); return at; };
+    // fixed-size regions first: their offsets do not depend on the mesh
     L.flags = take(64 * sizeof(int32_t));
     L.diag = take(kDiagSlots * sizeof(DiagDev));
+    L.mlp = take(sizeof(MlpPacked));
     L.dtdev = take(4 * sizeof(double));
     L.dtpart = take((int64_t)grid_for(n) * sizeof(double));
     int64_t bs = 0, m = n + 1;
@@ -78,6 +81,8 @@ struct mm_ctx {
     char *ws = nullptr;
     int64_t ws_bytes = 0;
     bool have_mesh = false;
+    bool mlp_ready = false;
+    bool diag_ready = false;
     int64_t n = 0, nf = 0;
     uint64_t faces_done = 0, waves_done = 0;
     mm_mesh mesh;
@@ -156,6 +161,11 @@ mm_status mm_set_workspace(mm_ctx *ctx, void *dev_ptr, int64_t bytes) {
     ctx->ws = (char *)dev_ptr;
     ctx->ws_bytes = bytes;
     ctx->have_mesh = false;
+    ctx->mlp_ready = false;
+    ctx->diag_ready = false;
+    // fixed-size regions (flags, diagnostics, network) sit at offsets that
+    // no mesh changes
+    ctx->lay = make_layout(ctx->D, ctx->p.mode, 2, 1);
     return MM_OK;
 }
 
@@ -167,7 +177,19 @@ static mm_status clear_diag(mm_ctx *c) {
     MM_LAUNCH_CHECK();
     c->faces_done = 0;
     c->waves_done = 0;
+    c->diag_ready = true;
     return MM_OK;
+}
+
+// Workspace present and its fixed regions initialised.
+static mm_status need_ws(mm_ctx *c) {
+    if (!c->ws || c->ws_bytes < make_layout(c->D, c->p.mode, 2, 1).total) return MM_E_STATE;
+    if (!c->diag_ready) return clear_diag(c);
+    return MM_OK;
+}
+
+static const MlpPacked *active_mlp(const mm_ctx *c) {
+    return (c->p.guess == MM_GUESS_LEARNED && c->mlp_ready) ? c->at<MlpPacked>(c->lay.mlp) : nullptr;
 }
 
 static mm_status scan_inclusive(mm_ctx *c, int32_t *data, int64_t n, int32_t *scratch) {
@@ -280,20 +302,22 @@ static mm_status fluxes_t(mm_ctx *c, const double *dt_dev, double dt, const void
     const Layout &L = c->lay;
     hipStream_t s = c->st();
     DiagDev *diag = c->at<DiagDev>(L.diag);
-    const MlpGuess *mlp = nullptr;
+    const MlpPacked *mlp = active_mlp(c);
     const GasConst<double> kg(c->p.gamma);
     const GasConst<float> kf(c->p.gamma);
-    if (c->p.mode == MM_FP64)
-        k_face_flux64<D><<<grid_for(c->nf), kBlock, 0, s>>>(c->nf, c->mesh.face_L, c->mesh.face_R,
-                                                            c->at<double>(L.frec), (const double *)rec, dt_dev, dt,
-                                                            kg, c->p.newton_tol64, c->p.newton_max_iter, mlp,
-                                                            flux, diag);
-    else {
+    if (c->p.mode == MM_FP64) {
+        auto kern = mlp ? k_face_flux64<D, true> : k_face_flux64<D, false>;
+        kern<<<grid_for(c->nf), kBlock, 0, s>>>(c->nf, c->mesh.face_L, c->mesh.face_R, c->at<double>(L.frec),
+                                                (const double *)rec, dt_dev, dt, kg, c->p.newton_tol64,
+                                                c->p.newton_max_iter, mlp, flux, diag);
+    } else {
         int32_t *hard = c->at<int32_t>(L.hard);
         k_fill_i32<<<1, kBlock, 0, s>>>(hard, 1, 0);
-        k_face_flux_mixed<D><<<grid_for(c->nf), kBlock, 0, s>>>(
-            c->nf, c->mesh.face_L, c->mesh.face_R, c->at<float>(L.mrec), c->at<double>(L.wf64), (const float *)rec,
-            dt_dev, dt, kf, kg.g_over_gm1, (float)c->p.newton_tol32, c->p.newton_max_iter, mlp, flux, hard, diag);
+        auto kern = mlp ? k_face_flux_mixed<D, true> : k_face_flux_mixed<D, false>;
+        kern<<<grid_for(c->nf), kBlock, 0, s>>>(c->nf, c->mesh.face_L, c->mesh.face_R, c->at<float>(L.mrec),
+                                                c->at<double>(L.wf64), (const float *)rec, dt_dev, dt, kf,
+                                                kg.g_over_gm1, (float)c->p.newton_tol32, c->p.newton_max_iter, mlp,
+                                                flux, hard, diag);
         k_face_flux_hard<D><<<kHardGrid, kBlock, 0, s>>>(c->mesh.face_L, c->mesh.face_R, c->at<float>(L.mrec),
                                                         c->at<double>(L.wf64), (const float *)rec, dt_dev, dt, kf.g,
                                                         kg, c->p.newton_tol64, hard, flux, diag);
@@ -369,13 +393,102 @@ mm_status mm_hydro_step(mm_ctx *c, double *Q, double dt, double *dt_used) {
 
 mm_status mm_reset_diag(mm_ctx *c) {
     if (!c) return MM_E_ARG;
-    if (!c->have_mesh) return MM_E_STATE;
+    if (!c->ws) return MM_E_STATE;
     return clear_diag(c);
+}
+
+mm_status mm_mlp_load(mm_ctx *c, const float *params) {
+    if (!c || !params) return MM_E_ARG;
+    mm_status st = need_ws(c);
+    if (st != MM_OK) return st;
+    k_mlp_pack<<<1, kBlock, 0, c->st()>>>(params, c->at<MlpPacked>(c->lay.mlp));
+    MM_LAUNCH_CHECK();
+    c->mlp_ready = true;
+    return MM_OK;
+}
+
+mm_status mm_mlp_infer(mm_ctx *c, int64_t n, const float *X, float *Y) {
+    if (!c || !X || !Y || n < 1) return MM_E_ARG;
+    if (!c->mlp_ready) return MM_E_STATE;
+    k_mlp_infer<<<plain_grid(n), kBlock, 0, c->st()>>>(n, c->at<MlpPacked>(c->lay.mlp), X, Y);
+    MM_LAUNCH_CHECK();
+    return MM_OK;
+}
+
+mm_status mm_mlp_forward(const float *params, int64_t n, const float *X, float *Y, void *stream) {
+    if (!params || !X || !Y || n < 1) return MM_E_ARG;
+    k_mlp_forward<<<plain_grid(n), kBlock, 0, (hipStream_t)stream>>>(n, params, X, Y);
+    MM_LAUNCH_CHECK();
+    return MM_OK;
+}
+
+int64_t mm_mlp_grad_scratch_bytes(int64_t n) {
+    if (n < 1) return -1;
+    return ((n + kMlpTile - 1) / kMlpTile) * (int64_t)(kMlpParams + 1) * (int64_t)sizeof(float);
+}
+
+mm_status mm_mlp_grad(const float *params, int64_t n, int64_t n_total, const float *X, const float *T, void *scratch,
+                      float *grad, void *stream) {
+    if (!params || !X || !T || !scratch || !grad || n < 1 || n_total < 1) return MM_E_ARG;
+    const int64_t nb = (n + kMlpTile - 1) / kMlpTile;
+    hipStream_t s = (hipStream_t)stream;
+    k_mlp_grad_partial<<<(unsigned)nb, kBlock, 0, s>>>(n, 1.0f / (float)n_total, params, X, T, (float *)scratch);
+    k_mlp_reduce<<<plain_grid(kMlpParams + 1), kBlock, 0, s>>>(nb, (const float *)scratch, grad);
+    MM_LAUNCH_CHECK();
+    return MM_OK;
+}
+
+mm_status mm_mlp_adam(float *params, const float *grad, float *m1, float *m2, float lr, float beta1, float beta2,
+                      float eps, int32_t step, void *stream) {
+    if (!params || !grad || !m1 || !m2 || step < 1) return MM_E_ARG;
+    const float c1 = 1.0f - powf(beta1, (float)step), c2 = 1.0f - powf(beta2, (float)step);
+    k_mlp_adam<<<plain_grid(kMlpParams), kBlock, 0, (hipStream_t)stream>>>(params, grad, m1, m2, lr, beta1, beta2, eps,
+                                                                          c1, c2);
+    MM_LAUNCH_CHECK();
+    return MM_OK;
+}
+
+mm_status mm_riemann_batch(mm_ctx *c, int64_t n, const double *states, double *out, int32_t *iters) {
+    if (!c || !states || !out || n < 1) return MM_E_ARG;
+    mm_status st = need_ws(c);
+    if (st != MM_OK) return st;
+    DiagDev *diag = c->at<DiagDev>(c->lay.diag);
+    const MlpPacked *mlp = active_mlp(c);
+    const GasConst<double> kg(c->p.gamma);
+    c->faces_done += (uint64_t)n;
+    c->waves_done += (uint64_t)((n + 63) / 64);
+    if (c->p.mode == MM_FP64)
+        k_riemann_batch<double><<<plain_grid(n), kBlock, 0, c->st()>>>(n, states, kg, kg, c->p.newton_tol64,
+                                                                       c->p.newton_tol64, c->p.newton_max_iter, mlp,
+                                                                       out, iters, diag);
+    else
+        k_riemann_batch<float><<<plain_grid(n), kBlock, 0, c->st()>>>(
+            n, states, GasConst<float>(c->p.gamma), kg, (float)c->p.newton_tol32, c->p.newton_tol64,
+            c->p.newton_max_iter, mlp, out, iters, diag);
+    MM_LAUNCH_CHECK();
+    return MM_OK;
+}
+
+mm_status mm_face_states(mm_ctx *c, double dt, const void *recon, float *out) {
+    if (!c || !recon || !out || !(dt > 0.0) || !isfinite(dt)) return MM_E_ARG;
+    if (c->p.mode != MM_FP64) return MM_E_ARG;
+    if (!c->have_mesh) return MM_E_STATE;
+    if (c->D == 3)
+        k_face_states64<3><<<plain_grid(c->nf), kBlock, 0, c->st()>>>(c->nf, c->mesh.face_L, c->mesh.face_R,
+                                                                      c->at<double>(c->lay.frec),
+                                                                      (const double *)recon, dt, c->p.gamma, out);
+    else
+        k_face_states64<2><<<plain_grid(c->nf), kBlock, 0, c->st()>>>(c->nf, c->mesh.face_L, c->mesh.face_R,
+                                                                      c->at<double>(c->lay.frec),
+                                                                      (const double *)recon, dt, c->p.gamma, out);
+    MM_LAUNCH_CHECK();
+    return MM_OK;
 }
 
 mm_status mm_get_diag(mm_ctx *c, mm_diag *out) {
     if (!c || !out) return MM_E_ARG;
-    if (!c->have_mesh) return MM_E_STATE;
+    mm_status st0 = need_ws(c);
+    if (st0 != MM_OK) return st0;
     DiagDev slots[kDiagSlots];
     int32_t nonfin = 0;
     MM_CHECK(hipMemcpyAsync(slots, c->at<char>(c->lay.diag), sizeof(slots), hipMemcpyDeviceToHost, c->st()));

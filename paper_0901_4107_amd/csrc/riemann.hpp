@@ -181,7 +181,10 @@ __device__ __forceinline__ Star<T> newton_star(const Side<T> &L, const Side<T> &
     return st;
 }
 
-template <typename T> struct FaceState { T rho, u, P; int side; };
+// Sampled face state; pstar is the star pressure and pstd the standard
+// starting guess (both -1 where the problem has no star state, i.e.
+// vacuum), filled by the caller of sample0.
+template <typename T> struct FaceState { T rho, u, P; int side; T pstar, pstd; };
 
 // Rarefaction fan of side K sampled at x/t = 0; `left` selects the
 // characteristic family (u - c for the left state, u + c for the right).

@@ -1,0 +1,236 @@
+"""The learned Newton starting guess: harvest Riemann problems from the
+method's own runs, label them with the library's double exact solver, train
+the 3 -> 64 -> 64 -> 1 network with the library's HIP training kernels
+(forward/backward and Adam through the C ABI), and store the result.
+
+Every numeric step runs in libmm; this module only orchestrates and moves
+tensors. The trained parameter vector lives in ``data/`` next to this file
+with a JSON note of how it was made.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+
+import numpy as np
+import torch
+
+from . import mm
+from .inputs import configs
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DATA = os.path.join(HERE, "data")
+
+# feature and target scales (mirror csrc/mlp.hpp)
+S_RHO, S_P, S_U, S_Y = 0.2, 0.2, 0.5, 1.0
+
+
+def weights_path(gamma: float) -> str:
+    return os.path.join(DATA, f"mlp_gamma_{gamma:.6f}.f32")
+
+
+def features(states: torch.Tensor, gamma: float):
+    """[6][n] -> X [n][3] float32 (device), in the network's scaling."""
+    rL, uL, PL, rR, uR, PR = [states[k].double() for k in range(6)]
+    cL = torch.sqrt(gamma * PL / rL)
+    cR = torch.sqrt(gamma * PR / rR)
+    X = torch.stack([S_RHO * torch.log(rR / rL), S_P * torch.log(PR / PL), S_U * (uR - uL) / (cL + cR)], dim=1)
+    return X.float().contiguous()
+
+
+def wants_learned(states: torch.Tensor, gamma: float) -> torch.Tensor:
+    """The problems the learned guess serves (the library's own selection,
+    restated on tensors): no vacuum, and a standard guess that is neither
+    the primitive-variable estimate in its accepted regime nor the exact
+    two-rarefaction root."""
+    rL, uL, PL, rR, uR, PR = [states[k].double() for k in range(6)]
+    ok = (rL > 0) & (PL > 0) & (rR > 0) & (PR > 0)
+    cL = torch.sqrt(gamma * PL / rL.clamp_min(1e-300))
+    cR = torch.sqrt(gamma * PR / rR.clamp_min(1e-300))
+    du = uR - uL
+    ok &= (cL + cR - 0.5 * (gamma - 1) * du) > 0
+    ppv = 0.5 * (PL + PR) - 0.125 * du * (rL + rR) * (cL + cR)
+    pmin, pmax = torch.minimum(PL, PR), torch.maximum(PL, PR)
+    pv = (pmax <= 2 * pmin) & (ppv >= pmin) & (ppv <= pmax)
+    cmax = torch.where(PL < PR, cR, cL)
+    z = (gamma - 1) / (2 * gamma)
+    two_rare = (ppv < pmin) & (2 * cmax / (gamma - 1) * ((pmin / pmax) ** z - 1) + du >= 0)
+    return ok & ~pv & ~two_rare
+
+
+def harvest(wl, steps: int = 1, device="cuda") -> torch.Tensor:
+    """Face-frame Riemann problems [6][F*steps] (float32, device) from
+    `steps` double-precision hydro steps of workload `wl` on its mesh."""
+    m = wl.mesh
+    ctx = mm.Context(m.dim, wl.gamma, wl.cfl, mode=mm.MM_FP64, device=device)
+    ctx.mm_mesh_upload(mm.DeviceMesh.from_host(m, device))
+    Q = torch.from_numpy(np.ascontiguousarray(wl.Q)).to(device)
+    rec = ctx.recon_buffer(m.n_cells)
+    out = []
+    for _ in range(steps):
+        ctx.mm_gradients(Q, rec)
+        dt = ctx.mm_hydro_step(Q.clone())  # the Courant step of this state
+        st = torch.empty((6, m.n_faces), dtype=torch.float32, device=device)
+        ctx.mm_face_states(dt, rec, st)
+        out.append(st)
+        ctx.mm_hydro_step(Q, dt=dt)
+    torch.cuda.synchronize()
+    return torch.cat(out, dim=1)
+
+
+def tails(n: int, gamma: float, rng: np.random.Generator) -> np.ndarray:
+    """Problems from the hard tails [6][n] (double): half near vacuum
+    (velocity jump 80-99.5% of the vacuum threshold 2(c_L+c_R)/(g-1)), half
+    strong shocks (pressure ratios up to 1e6 in either order, colliding
+    flows)."""
+    h = n // 2
+    rho = 10 ** rng.uniform(-2, 2, (2, n))
+    P = 10 ** rng.uniform(-2, 2, (2, n))
+    c = np.sqrt(gamma * P / rho)
+    u = np.zeros((2, n))
+    thr = 2 * (c[0] + c[1]) / (gamma - 1)
+    jump = rng.uniform(0.8, 0.995, h) * thr[:h]
+    u[0, :h] = -0.5 * jump
+    u[1, :h] = 0.5 * jump
+    ratio = 10 ** rng.uniform(2, 6, n - h) * rng.choice([-1, 1], n - h)
+    P[1, h:] = np.where(ratio > 0, P[0, h:] * np.abs(ratio), P[0, h:] / np.abs(ratio))
+    c = np.sqrt(gamma * P / rho)
+    coll = rng.uniform(0, 3, n - h) * (c[0, h:] + c[1, h:])
+    u[0, h:] = 0.5 * coll
+    u[1, h:] = -0.5 * coll
+    return np.stack([rho[0], u[0], P[0], rho[1], u[1], P[1]])
+
+
+def label(states: torch.Tensor, gamma: float, device="cuda"):
+    """Exact star pressures and the standard guesses (double) of [6][n]
+    problems, from the library's batched solver."""
+    ctx = mm.Context(3, gamma, mode=mm.MM_FP64, device=device)
+    s64 = states.double().contiguous()
+    out = torch.empty((s64.shape[1], 5), dtype=torch.float64, device=device)
+    ctx.mm_riemann_batch(s64, out)
+    return out[:, 3], out[:, 4]
+
+
+def build_dataset(gamma: float = 5.0 / 3.0, seed: int = 7, device="cuda", small: bool = False, log=print):
+    """Training problems harvested from the random-state, Kelvin-Helmholtz
+    and Sedov workloads (a few steps each) plus the hard tails, restricted to
+    the problems the learned guess serves, and their targets."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    side = 24 if small else 48
+    for wl, steps in ((configs.random3d(n_side=side, seed=seed + 1), 2),
+                      (configs.kh3d(n_points=side ** 3, seed=seed + 2), 2),
+                      (configs.sedov3d(n_side=side, seed=seed + 3), 6 if small else 12)):
+        t = time.time()
+        st = harvest(wl, steps, device)
+        keep = wants_learned(st, gamma)
+        parts.append(st[:, keep])
+        log(f"harvest {wl.name}: {st.shape[1]} faces, {int(keep.sum())} outside the PV regime "
+            f"({time.time() - t:.1f}s)")
+    harvested = torch.cat(parts, dim=1)
+    nt = max(harvested.shape[1] // 19, 1000)   # 5% tails
+    tl = torch.from_numpy(tails(nt, gamma, rng)).to(device)
+    states = torch.cat([harvested.double(), tl], dim=1)
+    states = states[:, wants_learned(states, gamma)]
+    ps, pstd = label(states, gamma, device)
+    good = (ps > 0) & (pstd > 0)
+    states, ps, pstd = states[:, good], ps[good], pstd[good]
+    X = features(states, gamma)
+    T = (torch.log(ps / pstd) / S_Y).float().contiguous()   # the standard guess's log error
+    # mirror augmentation: swapping the sides (x0, x1 -> -x0, -x1) keeps p*
+    Xm = X.clone()
+    Xm[:, 0] *= -1
+    Xm[:, 1] *= -1
+    X = torch.cat([X, Xm]).contiguous()
+    T = torch.cat([T, T]).contiguous()
+    log(f"dataset: {X.shape[0]} samples (with mirror augmentation)")
+    return X, T, states
+
+
+def init_params(rng: np.random.Generator) -> np.ndarray:
+    """He-uniform initial weights, zero biases, in the library's layout."""
+    H = 64
+    W1 = rng.uniform(-1, 1, (3, H)) * np.sqrt(6 / 3)
+    W2 = rng.uniform(-1, 1, (H, H)) * np.sqrt(6 / H)
+    w3 = rng.uniform(-1, 1, H) * np.sqrt(3 / H)
+    return np.concatenate([W1.ravel(), np.zeros(H), W2.ravel(), np.zeros(H), w3, np.zeros(1)]).astype(np.float32)
+
+
+def train(X: torch.Tensor, T: torch.Tensor, steps: int = 3000, batch: int = 16384, lr: float = 3e-3,
+          seed: int = 11, log=print) -> torch.Tensor:
+    """Adam on the MSE of the scaled log star pressure, all on the GPU."""
+    dev = X.device
+    rng = np.random.default_rng(seed)
+    params = torch.from_numpy(init_params(rng)).to(dev)
+    m1 = torch.zeros_like(params)
+    m2 = torch.zeros_like(params)
+    grad = torch.empty(mm.MM_MLP_PARAMS + 1, dtype=torch.float32, device=dev)
+    scratch = torch.empty(mm.mm_mlp_grad_scratch_bytes(batch), dtype=torch.uint8, device=dev)
+    n = X.shape[0]
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed)
+    t0 = time.time()
+    for step in range(1, steps + 1):
+        idx = torch.randint(0, n, (batch,), device=dev, generator=gen)
+        xb, tb = X[idx].contiguous(), T[idx].contiguous()
+        mm.mm_mlp_grad(params, xb, tb, scratch, grad)
+        rate = lr * (0.003 ** (step / steps))   # exponential decay to 0.3% of lr
+        mm.mm_mlp_adam(params, grad, m1, m2, rate, 0.9, 0.999, 1e-8, step)
+        if step % max(steps // 10, 1) == 0 or step == 1:
+            log(f"step {step}: loss {float(grad[mm.MM_MLP_PARAMS]):.3e} ({time.time() - t0:.1f}s)")
+    torch.cuda.synchronize()
+    return params
+
+
+def evaluate(params: torch.Tensor, X: torch.Tensor, T: torch.Tensor) -> dict:
+    Y = torch.empty_like(T)
+    mm.mm_mlp_forward(params, X, Y)
+    err = (Y - T).abs() * S_Y   # error in ln p*
+    return {"rms_ln_p": float(torch.sqrt(torch.mean(err * err))), "max_ln_p": float(err.max()),
+            "p90_ln_p": float(torch.quantile(err[: min(len(err), 1 << 20)], 0.9))}
+
+
+def save(params: torch.Tensor, gamma: float, meta: dict) -> str:
+    os.makedirs(DATA, exist_ok=True)
+    path = weights_path(gamma)
+    params.detach().cpu().numpy().astype("<f4").tofile(path)
+    with open(path + ".json", "w") as fh:
+        json.dump(dict(meta, gamma=gamma, params=mm.MM_MLP_PARAMS), fh, indent=1)
+    return path
+
+
+def load(gamma: float, device="cuda") -> torch.Tensor | None:
+    path = weights_path(gamma)
+    if not os.path.exists(path):
+        return None
+    a = np.fromfile(path, dtype="<f4")
+    if a.size != mm.MM_MLP_PARAMS:
+        raise RuntimeError(f"{path}: {a.size} values, expected {mm.MM_MLP_PARAMS}")
+    return torch.from_numpy(a).to(device)
+
+
+def main():
+    import argparse
+    ap = argparse.ArgumentParser(description="harvest, label and train the learned Newton guess")
+    ap.add_argument("--gamma", type=float, default=5.0 / 3.0)
+    ap.add_argument("--steps", type=int, default=100000)
+    ap.add_argument("--small", action="store_true")
+    args = ap.parse_args()
+    t = time.time()
+    X, T, _ = build_dataset(args.gamma, small=args.small)
+    perm = torch.randperm(X.shape[0], device=X.device, generator=torch.Generator(device=X.device).manual_seed(3))
+    nval = max(X.shape[0] // 10, 1)
+    Xv, Tv = X[perm[:nval]].contiguous(), T[perm[:nval]].contiguous()
+    Xt, Tt = X[perm[nval:]].contiguous(), T[perm[nval:]].contiguous()
+    params = train(Xt, Tt, steps=args.steps)
+    ev = evaluate(params, Xv, Tv)
+    print(f"validation: {ev}")
+    path = save(params, args.gamma, {"train_samples": int(Xt.shape[0]), "val_samples": int(nval),
+                                     "steps": args.steps, "validation": ev, "seconds": time.time() - t,
+                                     "recipe": "paper_0901_4107_amd.learned.main"})
+    print(f"saved {path}")
+
+
+if __name__ == "__main__":
+    main()

@@ -65,7 +65,18 @@ SIGNATURES = {
     "mm_get_diag": (ctypes.c_int32, [_vp, ctypes.POINTER(mm_diag)]),
     "mm_reset_diag": (ctypes.c_int32, [_vp]),
     "mm_status_str": (ctypes.c_char_p, [ctypes.c_int32]),
+    "mm_mlp_load": (ctypes.c_int32, [_vp, _vp]),
+    "mm_mlp_infer": (ctypes.c_int32, [_vp, ctypes.c_int64, _vp, _vp]),
+    "mm_mlp_forward": (ctypes.c_int32, [_vp, ctypes.c_int64, _vp, _vp, _vp]),
+    "mm_mlp_grad_scratch_bytes": (ctypes.c_int64, [ctypes.c_int64]),
+    "mm_mlp_grad": (ctypes.c_int32, [_vp, ctypes.c_int64, ctypes.c_int64, _vp, _vp, _vp, _vp, _vp]),
+    "mm_mlp_adam": (ctypes.c_int32, [_vp, _vp, _vp, _vp, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                     ctypes.c_float, ctypes.c_int32, _vp]),
+    "mm_riemann_batch": (ctypes.c_int32, [_vp, ctypes.c_int64, _vp, _vp, _vp]),
+    "mm_face_states": (ctypes.c_int32, [_vp, ctypes.c_double, _vp, _vp]),
 }
+
+MM_MLP_PARAMS = 4481
 
 
 def lib():
@@ -149,6 +160,7 @@ class Context:
         _check("mm_create", lib().mm_create(ctypes.byref(self.params), ctypes.byref(self._ctx)))
         self._ws = None
         self._mesh = None
+        self._mlp = None
 
     def __del__(self):
         if getattr(self, "_ctx", None) and _LIB is not None:
@@ -169,6 +181,8 @@ class Context:
             raise MMError("mm_workspace_bytes", MM_E_ARG)
         if self._ws is None or self._ws.numel() < need:
             self.mm_set_workspace(torch.empty(need + 256, dtype=torch.uint8, device=self.device))
+            if self._mlp is not None:  # a new workspace holds no packed network yet
+                _check("mm_mlp_load", lib().mm_mlp_load(self._ctx, _ptr(self._mlp)))
         self._mesh = mesh  # keep the arrays alive while the library refers to them
         _check("mm_mesh_upload", lib().mm_mesh_upload(self._ctx, ctypes.byref(mesh.as_struct())))
 
@@ -198,7 +212,30 @@ class Context:
     def mm_reset_diag(self):
         _check("mm_reset_diag", lib().mm_reset_diag(self._ctx))
 
-    # --- buffers in the layouts the entry points expect ----------------------
+    def ensure_workspace(self):
+        """A workspace large enough for the mesh-free entry points."""
+        if self._ws is None:
+            need = self.mm_workspace_bytes(2, 1)
+            self.mm_set_workspace(torch.empty(need + 256, dtype=torch.uint8, device=self.device))
+
+    def mm_mlp_load(self, params: torch.Tensor):
+        self.ensure_workspace()
+        _check("mm_mlp_load", lib().mm_mlp_load(self._ctx, _ptr(params)))
+        self._mlp = params
+
+    def mm_mlp_infer(self, X: torch.Tensor, Y: torch.Tensor):
+        _check("mm_mlp_infer", lib().mm_mlp_infer(self._ctx, X.shape[0], _ptr(X), _ptr(Y)))
+
+    def mm_riemann_batch(self, states: torch.Tensor, out: torch.Tensor, iters: torch.Tensor | None = None):
+        """states [6][n] double -> out [n][4] (rho_F, u_F, P_F, p*), iters [n]."""
+        self.ensure_workspace()
+        _check("mm_riemann_batch", lib().mm_riemann_batch(self._ctx, states.shape[1], _ptr(states), _ptr(out),
+                                                          _ptr(iters)))
+
+    def mm_face_states(self, dt: float, recon: torch.Tensor, out: torch.Tensor):
+        _check("mm_face_states", lib().mm_face_states(self._ctx, float(dt), _ptr(recon), _ptr(out)))
+
+
     def recon_buffer(self, n_cells: int):
         """Reconstruction records [N][MM_RECON_STRIDE] for mm_gradients in
         this context's mode (double in MM_FP64, float in MM_MIXED)."""
@@ -209,6 +246,30 @@ class Context:
         """Face fluxes [F][D+2] (double)."""
         return torch.empty((n_faces, self.dim + 2), dtype=torch.float64, device=self.device)
 
+
+
+def _stream_ptr(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def mm_mlp_forward(params: torch.Tensor, X: torch.Tensor, Y: torch.Tensor, stream=None):
+    _check("mm_mlp_forward", lib().mm_mlp_forward(_ptr(params), X.shape[0], _ptr(X), _ptr(Y), _stream_ptr(stream)))
+
+
+def mm_mlp_grad_scratch_bytes(n: int) -> int:
+    return int(lib().mm_mlp_grad_scratch_bytes(n))
+
+
+def mm_mlp_grad(params, X, T, scratch, grad, n_total=None, stream=None):
+    n = X.shape[0]
+    _check("mm_mlp_grad", lib().mm_mlp_grad(_ptr(params), n, n if n_total is None else n_total, _ptr(X), _ptr(T),
+                                            _ptr(scratch), _ptr(grad), _stream_ptr(stream)))
+
+
+def mm_mlp_adam(params, grad, m1, m2, lr, beta1, beta2, eps, step, stream=None):
+    _check("mm_mlp_adam", lib().mm_mlp_adam(_ptr(params), _ptr(grad), _ptr(m1), _ptr(m2), lr, beta1, beta2, eps,
+                                            step, _stream_ptr(stream)))
 
 def recon_stride(dim: int) -> int:
     return 24 if dim == 3 else 16

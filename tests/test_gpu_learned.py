@@ -1,0 +1,187 @@
+"""The learned Newton guess on the GPU: training kernels against the CPU MLP
+oracle, the fused bf16 matrix-core inference against the fp32 reference,
+the batched exact solver against the oracle's Riemann solver, and what a
+trained network gains (Newton iterations) without changing any result."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import mlp as M
+from oracle import oracle as O
+from paper_0901_4107_amd import learned, mm
+from paper_0901_4107_amd.inputs.configs import random3d
+from tests.util import normwise_rel
+
+pytestmark = pytest.mark.gpu
+
+G = 5.0 / 3.0
+
+
+def note(msg):
+    print(msg, flush=True)
+
+
+def rand_params(seed, scale=0.3):
+    rng = np.random.default_rng(seed)
+    return rng.normal(0, scale, M.N_PARAMS).astype(np.float32)
+
+
+def test_mlp_gradient_matches_oracle():
+    rng = np.random.default_rng(2)
+    theta = rand_params(3)
+    X = rng.normal(size=(1000, 3)).astype(np.float32)
+    T = rng.normal(size=1000).astype(np.float32)
+    p = torch.from_numpy(theta).cuda()
+    Xd, Td = torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda()
+    grad = torch.empty(M.N_PARAMS + 1, dtype=torch.float32, device="cuda")
+    scratch = torch.empty(mm.mm_mlp_grad_scratch_bytes(1000), dtype=torch.uint8, device="cuda")
+    mm.mm_mlp_grad(p, Xd, Td, scratch, grad)
+    g = grad.cpu().numpy().astype(np.float64)
+    loss, go = M.loss_and_grad(theta.astype(np.float64), X.astype(np.float64), T.astype(np.float64))
+    assert abs(g[-1] - loss) <= 1e-5 * loss
+    err = np.max(np.abs(g[:-1] - go)) / np.max(np.abs(go))
+    note(f"mlp gradient: loss {g[-1]:.6e} vs {loss:.6e}; normwise gradient error {err:.2e}")
+    assert err <= 1e-5
+    # deterministic: the same call gives the same bits
+    g2 = torch.empty_like(grad)
+    mm.mm_mlp_grad(p, Xd, Td, scratch, g2)
+    assert torch.equal(grad, g2)
+
+
+def test_adam_step():
+    rng = np.random.default_rng(5)
+    theta = rand_params(6)
+    g = rng.normal(size=M.N_PARAMS).astype(np.float32)
+    m1 = rng.normal(size=M.N_PARAMS).astype(np.float32) * 0.1
+    m2 = np.abs(rng.normal(size=M.N_PARAMS)).astype(np.float32) * 0.01
+    d = [torch.from_numpy(a.copy()).cuda() for a in (theta, g, m1, m2)]
+    mm.mm_mlp_adam(d[0], d[1], d[2], d[3], 1e-3, 0.9, 0.999, 1e-8, 7)
+    a = 0.9 * m1 + 0.1 * g
+    b = 0.999 * m2 + 0.001 * g * g
+    want = theta - 1e-3 * (a / (1 - 0.9 ** 7)) / (np.sqrt(b / (1 - 0.999 ** 7)) + 1e-8)
+    assert np.allclose(d[0].cpu().numpy(), want, rtol=1e-6, atol=1e-7)
+
+
+def test_forward_and_fused_bf16_inference():
+    """fp32 forward vs the oracle; the fused matrix-core inference (which
+    also checks the operand lane layouts) vs the oracle within bf16
+    rounding of weights and activations."""
+    rng = np.random.default_rng(8)
+    theta = rand_params(9, 0.2)
+    n = 1000  # several waves and a ragged tail
+    X = rng.uniform(-2, 2, (n, 3)).astype(np.float32)
+    yo = M.forward(theta.astype(np.float64), X.astype(np.float64))[0]
+    p = torch.from_numpy(theta).cuda()
+    Xd = torch.from_numpy(X).cuda()
+    Y = torch.empty(n, dtype=torch.float32, device="cuda")
+    mm.mm_mlp_forward(p, Xd, Y)
+    assert np.max(np.abs(Y.cpu().numpy() - yo)) <= 1e-5 * (1 + np.max(np.abs(yo)))
+    ctx = mm.Context(3, G, mode=mm.MM_MIXED, guess=mm.MM_GUESS_LEARNED)
+    ctx.mm_mlp_load(p)
+    Yb = torch.empty(n, dtype=torch.float32, device="cuda")
+    ctx.mm_mlp_infer(Xd, Yb)
+    err = np.abs(Yb.cpu().numpy() - yo)
+    scale = np.max(np.abs(yo))
+    note(f"bf16 inference: max |dy| {err.max():.3e}, rms {np.sqrt(np.mean(err**2)):.3e}, |y| max {scale:.2f}")
+    assert err.max() <= 0.03 * scale
+    # a permutation of the inputs permutes the outputs (no cross-lane mixing)
+    perm = rng.permutation(n)
+    Yp = torch.empty_like(Yb)
+    ctx.mm_mlp_infer(Xd[perm].contiguous(), Yp)
+    assert np.array_equal(Yp.cpu().numpy(), Yb.cpu().numpy()[perm])
+
+
+def random_problems(n, rng):
+    rho = 10 ** rng.uniform(-2, 2, (2, n))
+    P = 10 ** rng.uniform(-2, 2, (2, n))
+    c = np.sqrt(G * P / rho)
+    u = rng.normal(0, 1, (2, n)) * 2 * c
+    s = np.stack([rho[0], u[0], P[0], rho[1], u[1], P[1]])
+    tl = learned.tails(n // 10, G, rng)
+    return np.ascontiguousarray(np.concatenate([s, tl], axis=1))
+
+
+def test_riemann_batch_parity():
+    rng = np.random.default_rng(12)
+    S = random_problems(20000, rng)
+    S[:, :50] = S[:, :50] * 0  # both-vacuum problems
+    S[0, 50:80] = 0.0          # left vacuum
+    ctx = mm.Context(3, G, mode=mm.MM_FP64)
+    out = torch.empty((S.shape[1], 5), dtype=torch.float64, device="cuda")
+    it = torch.empty(S.shape[1], dtype=torch.int32, device="cuda")
+    ctx.mm_riemann_batch(torch.from_numpy(S).cuda(), out, it)
+    o = out.cpu().numpy()
+    r = O.riemann(G, *S)
+    with np.errstate(all="ignore"):
+        c = np.nan_to_num(np.sqrt(G * S[2] / S[0])) + np.nan_to_num(np.sqrt(G * S[5] / S[3]))
+    for k, key in enumerate(("rho", "u", "P")):
+        ref = r[key]
+        scale = np.abs(ref) + np.abs(S[k]) + np.abs(S[k + 3]) + (c if k == 1 else 0.0)
+        assert np.all(np.abs(o[:, k] - ref) <= 1e-12 * scale + 1e-300), key
+    has = r["case"] == 0
+    assert np.allclose(o[has, 3], r["pstar"][has], rtol=1e-12, atol=0)
+    assert np.all(o[~has, 3] == -1)
+    d = ctx.mm_get_diag()
+    note(f"batch fp64: mean iterations {d['newton_iters'] / S.shape[1]:.2f}, unconverged {d['unconverged']}")
+    assert d["unconverged"] == 0
+
+
+@pytest.fixture(scope="module")
+def trained():
+    """A network trained by the library's kernels on a small harvested set."""
+    X, T, states = learned.build_dataset(G, small=True, log=note)
+    params = learned.train(X, T, steps=30000, log=note)
+    return params, states
+
+
+def iterations(ctx_mode, guess, params, S):
+    ctx = mm.Context(3, G, mode=ctx_mode, guess=guess)
+    if params is not None:
+        ctx.mm_mlp_load(params)
+    out = torch.empty((S.shape[1], 5), dtype=torch.float64, device="cuda")
+    it = torch.empty(S.shape[1], dtype=torch.int32, device="cuda")
+    ctx.mm_riemann_batch(S, out, it)
+    d = ctx.mm_get_diag()
+    return out.cpu().numpy(), it.cpu().numpy(), d
+
+
+def test_learned_guess_gains_iterations(trained):
+    """On hard problems (outside the regime where the standard guess is its
+    primitive-variable estimate), the trained network's guess needs fewer
+    Newton iterations, in mean and per wavefront maximum, and the solution
+    is the same (double: to round-off; float: to the float tolerance)."""
+    params, _ = trained
+    rng = np.random.default_rng(99)   # held-out problems, not the training set
+    S = torch.from_numpy(random_problems(200000, rng)).cuda()
+    S = S[:, learned.wants_learned(S, G)].contiguous()
+    for mode, tol in ((mm.MM_FP64, 1e-12), (mm.MM_MIXED, 2e-5)):
+        o_std, it_std, d_std = iterations(mode, mm.MM_GUESS_STANDARD, None, S)
+        o_ml, it_ml, d_ml = iterations(mode, mm.MM_GUESS_LEARNED, params, S)
+        ok = o_std[:, 3] > 0
+        rel = np.abs(o_ml[ok, 3] - o_std[ok, 3]) / o_std[ok, 3]
+        wave = lambda it: np.mean(np.max(np.pad(it, (0, (-len(it)) % 64)).reshape(-1, 64), axis=1))
+        note(f"mode {mode}: mean iterations standard {it_std.mean():.3f} learned {it_ml.mean():.3f}; "
+             f"wave max {wave(it_std):.3f} vs {wave(it_ml):.3f}; guess fallbacks {d_ml['guess_fallback']}; "
+             f"max rel p* change {rel.max():.2e}")
+        assert it_ml.mean() < it_std.mean()
+        assert wave(it_ml) <= wave(it_std)
+        assert rel.max() <= tol
+
+
+def test_learned_guess_keeps_fp64_parity(trained):
+    """The guess only moves Newton's start: the double flux path with the
+    learned guess still matches the oracle to the parity bound."""
+    params, _ = trained
+    wl = random3d(n_side=20, seed=321)
+    m = wl.mesh
+    ctx = mm.Context(3, wl.gamma, wl.cfl, mode=mm.MM_FP64, guess=mm.MM_GUESS_LEARNED)
+    ctx.mm_mesh_upload(mm.DeviceMesh.from_host(m))
+    ctx.mm_mlp_load(params)
+    Q = torch.from_numpy(wl.Q.copy()).cuda()
+    used = ctx.mm_hydro_step(Q)
+    Qo, dto = O.hydro_step(m, wl.gamma, wl.cfl, wl.Q)
+    err = normwise_rel(Q.cpu().numpy(), Qo)
+    d = ctx.mm_get_diag()
+    note(f"learned fp64 step: normwise error {err.max():.2e}; diag {d}")
+    assert np.all(err <= 1e-12)
+    assert d["unconverged"] == 0
