@@ -5,12 +5,17 @@ the Courant timestep, limited gradients, face fluxes (extrapolation, face
 frame, exact Riemann solve, lab-frame flux) and the conservative update,
 through ``mm_hydro_step``. The headline workload is the 3D Kelvin-Helmholtz
 shear layer on 128^3 Poisson points with a bulk boost of ten sound speeds
-and a comoving mesh; its inputs are resident in HBM before timing starts.
+and a comoving mesh, run in the mixed form with the learned Newton guess;
+the double-precision path is timed beside it on the same inputs, and the
+error of the headline form against it after one step (rest-frame L1 per
+conserved component) is reported with the speedup. Inputs are resident in
+HBM before any timed region.
 
 Prints ONE JSON line: face fluxes per second of the whole step (value), the
-roofline of the dominant kernel (the face-flux kernel, timed on its own
-with HIP events on the library's stream) and the CPU oracle's rate on the
-host (cpu_baseline).
+roofline of the dominant kernel (the face-flux kernel, timed on its own with
+HIP events on the library's stream) and the CPU oracle's rate on the host
+(cpu_baseline). ``--workload riemann`` instead times the batched exact
+solver on 2^24 independent Riemann problems (standard vs learned guess).
 """
 from __future__ import annotations
 
@@ -27,44 +32,115 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Riemann face fluxes/sec, 3D 128³ Voronoi; mixed+learned vs FP64 at set error"
 HBM_PEAK_GBS = 8000.0
+SET_ERROR = 1e-6   # rest-frame L1 per conserved component, mixed forms vs double
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def flux_kernel_bytes(dim, n_cells, n_faces, mode):
-    """Algorithmic HBM bytes of one face-flux launch: per face the two cell
-    indices, the face geometry and velocity, and the flux written; per cell
-    (each read once under ideal reuse) primitives, gradients and the
-    centre-of-mass offset."""
+def flux_kernel_bytes(dim, n_cells, n_faces, mixed):
+    """Algorithmic HBM bytes of one face-flux launch. Per face: the two cell
+    indices, the face geometry (A, |d|, n, c) and velocity, and the flux
+    written; per cell (each gathered once under ideal reuse) its
+    reconstruction record (primitives, gradients, s - r). Double: all double;
+    mixed: float geometry, float w_K - w_f, double w_f, float records."""
     nv = dim + 2
-    if mode == "fp64":
-        per_face = 2 * 4 + (2 + 2 * dim) * 8 + dim * 8 + nv * 8
+    if not mixed:
+        per_face = 2 * 4 + (2 + 3 * dim) * 8 + nv * 8
         per_cell = (nv + nv * dim + dim) * 8
     else:
-        per_face = 2 * 4 + (2 + 2 * dim) * 4 + 2 * dim * 4 + 8 + dim * 8 + nv * 8
-        per_cell = (nv + nv * dim) * 4 + dim * 8
+        per_face = 2 * 4 + (2 + 4 * dim) * 4 + dim * 8 + nv * 8
+        per_cell = (nv + nv * dim + dim) * 4
     return n_faces * per_face + n_cells * per_cell, per_face, per_cell
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="kh3d", choices=["kh3d", "random3d", "sedov3d"])
-    ap.add_argument("--size", type=int, default=0, help="points per axis (lattice) or cube root of the point count")
-    ap.add_argument("--mode", default="fp64", choices=["fp64", "mixed"])
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--threads", type=int, default=0, help="host threads for the mesh builder")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
-        sys.exit(2)
+def l1_rest(a, b, boost):
+    """Rest-frame L1 per component (momentum against the momentum vector's
+    L1 norm), after the Galilean boost by -v0."""
+    D = a.shape[0] - 2
 
+    def unboost(Q):
+        out = Q.copy()
+        out[1:1 + D] = Q[1:1 + D] - Q[0][None] * boost[:, None]
+        out[D + 1] = Q[D + 1] - np.sum(Q[1:1 + D] * boost[:, None], axis=0) + 0.5 * Q[0] * float(boost @ boost)
+        return out
+    a, b = unboost(a), unboost(b)
+    num = np.sum(np.abs(a - b), axis=1)
+    den = np.sum(np.abs(b), axis=1)
+    den[1:1 + D] = np.sum(np.sqrt(np.sum(b[1:1 + D] ** 2, axis=0)))
+    return num / np.where(den > 0, den, 1.0)
+
+
+def make_context(mm, learned, m, wl, form, dev):
+    mode = mm.MM_FP64 if form.startswith("fp64") else mm.MM_MIXED
+    guess = mm.MM_GUESS_LEARNED if form.endswith("learned") else mm.MM_GUESS_STANDARD
+    ctx = mm.Context(m.dim, wl.gamma, wl.cfl, mode=mode, guess=guess, device=dev)
+    if guess == mm.MM_GUESS_LEARNED:
+        params = learned.load(wl.gamma, dev)
+        if params is None:
+            raise RuntimeError("no trained network for this gamma: run python -m paper_0901_4107_amd.learned")
+        ctx.mm_mlp_load(params)
+    return ctx
+
+
+def time_form(mm, learned, torch, wl, dmesh, form, steps, warmup, dev):
+    m = wl.mesh
+    ctx = make_context(mm, learned, m, wl, form, dev)
+    ctx.mm_mesh_upload(dmesh)
+    Q0 = torch.from_numpy(np.ascontiguousarray(wl.Q)).to(dev)
+    Q = Q0.clone()
+    rec = ctx.recon_buffer(m.n_cells)
+    F = ctx.flux_buffer(m.n_faces)
+    stream = ctx.stream
+    torch.cuda.synchronize()
+    dt = ctx.mm_hydro_step(Q)          # Courant step of the initial state
+    Q.copy_(Q0)
+    # W untimed steps, then exactly K timed consecutive steps (Courant
+    # timestep recomputed on the device each step), bracketed by device
+    # synchronisation
+    for _ in range(warmup):
+        ctx.mm_hydro_step(Q, sync=False)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t_wall = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        ctx.mm_hydro_step(Q, sync=False)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t_wall) * 1e3 / steps
+    ms = e0.elapsed_time(e1) / steps
+    # the dominant kernel alone, on the initial state's records
+    ctx.mm_gradients(Q0, rec)
+    for _ in range(warmup):
+        ctx.mm_face_fluxes(dt, rec, F)
+    torch.cuda.synchronize()
+    fev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * steps)]
+    for k in range(steps):
+        fev[2 * k].record(stream)
+        ctx.mm_face_fluxes(dt, rec, F)
+        fev[2 * k + 1].record(stream)
+    torch.cuda.synchronize()
+    flux_ms = float(np.mean([fev[2 * k].elapsed_time(fev[2 * k + 1]) for k in range(steps)]))
+    # one step from the initial state at the common timestep, for the error
+    Q1 = Q0.clone()
+    ctx.mm_reset_diag()
+    ctx.mm_hydro_step(Q1, dt=dt)
+    diag = ctx.mm_get_diag()
+    return {"ms": ms, "wall_ms": wall_ms, "flux_ms": flux_ms, "dt": dt, "Q1": Q1.cpu().numpy(), "diag": diag}
+
+
+def newton_summary(d):
+    return {"iters_mean": d["newton_iters"] / max(1, d["faces"]),
+            "wave_max_mean": d["wave_iter_max_sum"] / max(1, d["waves"]), "max": d["newton_max"],
+            "vacuum": d["vacuum"], "positivity_fallback": d["positivity_fallback"],
+            "fp64_fallback": d["fp64_fallback"], "guess_fallback": d["guess_fallback"]}
+
+
+def bench_step(args):
     import torch
-    from paper_0901_4107_amd import mm
+    from paper_0901_4107_amd import learned, mm
     from paper_0901_4107_amd.inputs import configs
 
     t0 = time.time()
@@ -76,83 +152,47 @@ def main():
         wl = configs.sedov3d(n_side=args.size or 256, nthreads=args.threads)
     m = wl.mesh
     log(f"workload {wl.name}: N={m.n_cells} F={m.n_faces} built in {time.time() - t0:.1f}s")
-
-    mode = mm.MM_FP64 if args.mode == "fp64" else mm.MM_MIXED
     dev = torch.device("cuda:0")
-    ctx = mm.Context(m.dim, wl.gamma, wl.cfl, mode=mode, device=dev)
     dmesh = mm.DeviceMesh.from_host(m, dev)
-    ctx.mm_mesh_upload(dmesh)
-    Q0 = torch.from_numpy(np.ascontiguousarray(wl.Q)).to(dev)
-    Q = Q0.clone()
-    rec = ctx.recon_buffer(m.n_cells)
-    F = ctx.flux_buffer(m.n_faces)
-    stream = ctx.stream
-    torch.cuda.synchronize()
-
-    # timestep of the first step, used for the isolated flux-kernel timing
-    dt = ctx.mm_hydro_step(Q)
-    Q.copy_(Q0)
-
-    # whole step: W untimed steps, then exactly K timed consecutive steps
-    # (Courant timestep computed on the device each step), bracketed by
-    # device synchronisation
-    for _ in range(args.warmup):
-        ctx.mm_hydro_step(Q, sync=False)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t_wall = time.perf_counter()
-    e0.record(stream)
-    for _ in range(args.steps):
-        ctx.mm_hydro_step(Q, sync=False)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall_ms = (time.perf_counter() - t_wall) * 1e3 / args.steps
-    ms = e0.elapsed_time(e1) / args.steps
-
-    # the dominant kernel alone: face fluxes
-    ctx.mm_gradients(Q0, rec)
-    for _ in range(args.warmup):
-        ctx.mm_face_fluxes(dt, rec, F)
-    torch.cuda.synchronize()
-    fev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * args.steps)]
-    for k in range(args.steps):
-        fev[2 * k].record(stream)
-        ctx.mm_face_fluxes(dt, rec, F)
-        fev[2 * k + 1].record(stream)
-    torch.cuda.synchronize()
-    flux_ms = float(np.mean([fev[2 * k].elapsed_time(fev[2 * k + 1]) for k in range(args.steps)]))
-    ctx.mm_reset_diag()
-    ctx.mm_hydro_step(Q0.clone())
-    diag = ctx.mm_get_diag()
-
-    nbytes, per_face, per_cell = flux_kernel_bytes(m.dim, m.n_cells, m.n_faces, args.mode)
-    achieved = nbytes / (flux_ms * 1e-3) / 1e9
+    head = time_form(mm, learned, torch, wl, dmesh, args.mode, args.steps, args.warmup, dev)
+    log(f"{args.mode}: {head['ms']:.3f} ms/step, flux kernel {head['flux_ms']:.3f} ms")
+    mixed = args.mode.startswith("mixed")
     out = {
         "metric": METRIC,
-        "value": m.n_faces / (ms * 1e-3),
+        "value": m.n_faces / (head["ms"] * 1e-3),
         "unit": "face-fluxes/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms,
-        "wall_ms_per_step": wall_ms,
+        "ms_per_step": head["ms"],
+        "wall_ms_per_step": head["wall_ms"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.mode == "fp64" else "f32+f64",
+        "dtype": "f32+f64" if mixed else "f64",
         "data": "synthetic",
-        "config": {"workload": wl.name, "n_cells": m.n_cells, "n_faces": m.n_faces, "mode": args.mode,
-                   "guess": "standard", "gamma": wl.gamma, "cfl": wl.cfl, "seed": wl.seed},
-        "flux_kernel": {"ms": flux_ms, "face_fluxes_per_s": m.n_faces / (flux_ms * 1e-3)},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_face_flux", "bytes_per_face": per_face, "bytes_per_cell": per_cell},
-        "newton": {"iters_mean": diag["newton_iters"] / max(1, diag["faces"]),
-                   "wave_max_mean": diag["wave_iter_max_sum"] / max(1, diag["waves"]),
-                   "max": diag["newton_max"], "vacuum": diag["vacuum"],
-                   "positivity_fallback": diag["positivity_fallback"], "fp64_fallback": diag["fp64_fallback"]},
+        "config": {"workload": wl.name, "n_cells": m.n_cells, "n_faces": m.n_faces, "form": args.mode,
+                   "gamma": wl.gamma, "cfl": wl.cfl, "seed": wl.seed, "boost": list(map(float, wl.boost))},
+        "flux_kernel": {"ms": head["flux_ms"], "face_fluxes_per_s": m.n_faces / (head["flux_ms"] * 1e-3)},
+        "newton": newton_summary(head["diag"]),
     }
-
+    nbytes, per_face, per_cell = flux_kernel_bytes(m.dim, m.n_cells, m.n_faces, mixed)
+    achieved = nbytes / (head["flux_ms"] * 1e-3) / 1e9
+    out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                       "kernel": "k_face_flux_mixed" if mixed else "k_face_flux64",
+                       "bytes_per_face": per_face, "bytes_per_cell": per_cell}
+    if args.mode != "fp64" and not args.no_compare:
+        base = time_form(mm, learned, torch, wl, dmesh, "fp64", args.steps, args.warmup, dev)
+        log(f"fp64: {base['ms']:.3f} ms/step, flux kernel {base['flux_ms']:.3f} ms")
+        err = l1_rest(head["Q1"], base["Q1"], np.asarray(wl.boost, dtype=np.float64))
+        out["fp64"] = {"ms_per_step": base["ms"], "face_fluxes_per_s": m.n_faces / (base["ms"] * 1e-3),
+                       "flux_kernel_ms": base["flux_ms"],
+                       "flux_kernel_face_fluxes_per_s": m.n_faces / (base["flux_ms"] * 1e-3),
+                       "newton": newton_summary(base["diag"])}
+        out["speedup_vs_fp64"] = {"step": base["ms"] / head["ms"], "flux_kernel": base["flux_ms"] / head["flux_ms"],
+                                  "l1_rest_frame_vs_fp64": [float(x) for x in err],
+                                  "set_error": SET_ERROR, "within_set_error": bool(np.all(err <= SET_ERROR))}
     if not args.no_cpu_baseline:
         from oracle import oracle as O
         log("cpu baseline: oracle hydro step on the full workload (1 thread)")
@@ -162,6 +202,87 @@ def main():
         out["cpu_baseline"] = {"value": m.n_faces / el, "unit": "face-fluxes/s", "cores": 1, "kind": "oracle",
                                "sample": f"one full oracle hydro step on the whole {wl.name} workload "
                                          f"({m.n_faces} faces), single thread, {el:.1f} s"}
+    return out
+
+
+def bench_riemann(args):
+    """2^24 independent Riemann problems: Newton iterations and throughput
+    of the batched exact solver, standard vs learned guess, double and float."""
+    import torch
+    from paper_0901_4107_amd import learned, mm
+    from paper_0901_4107_amd.inputs import configs
+
+    gamma = 5.0 / 3.0
+    n = args.size or (1 << 24)
+    t0 = time.time()
+    S = torch.from_numpy(configs.riemann_problems(n, nthreads=args.threads)).cuda()
+    log(f"riemann workload: {n} problems built in {time.time() - t0:.1f}s")
+    params = learned.load(gamma)
+    res = {}
+    for form in ("fp64", "fp64+learned", "mixed", "mixed+learned"):
+        mode = mm.MM_FP64 if form.startswith("fp64") else mm.MM_MIXED
+        guess = mm.MM_GUESS_LEARNED if form.endswith("learned") else mm.MM_GUESS_STANDARD
+        ctx = mm.Context(3, gamma, mode=mode, guess=guess)
+        if guess == mm.MM_GUESS_LEARNED:
+            ctx.mm_mlp_load(params)
+        out = torch.empty((n, 5), dtype=torch.float64, device="cuda")
+        it = torch.empty(n, dtype=torch.int32, device="cuda")
+        ctx.mm_riemann_batch(S, out, it)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(ctx.stream)
+        for _ in range(args.steps):
+            ctx.mm_riemann_batch(S, out, None)
+        e1.record(ctx.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        itn = it.cpu().numpy()
+        waves = np.max(np.pad(itn, (0, (-n) % 64)).reshape(-1, 64), axis=1)
+        d = ctx.mm_get_diag()
+        res[form] = {"ms": ms, "problems_per_s": n / (ms * 1e-3), "iters_mean": float(itn.mean()),
+                     "iters_p99": float(np.percentile(itn, 99)), "wave_max_mean": float(waves.mean()),
+                     "fp64_fallback": d["fp64_fallback"] // (args.steps + 1),
+                     "guess_fallback": d["guess_fallback"] // (args.steps + 1)}
+        log(f"{form}: {ms:.3f} ms, iterations mean {itn.mean():.3f} wave-max {waves.mean():.3f}")
+    return {"metric": "Riemann problems/sec (2^24 problems, exact solver)",
+            "value": res["mixed+learned"]["problems_per_s"], "unit": "problems/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": 1, "ms_per_step": res["mixed+learned"]["ms"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+            "config": {"workload": f"riemann_{n}", "gamma": gamma}, "forms": res}
+
+
+def calibrate_copy(mb):
+    """A plain device copy of known size, for scaling the rocprof FETCH_SIZE
+    and WRITE_SIZE counters."""
+    import torch
+    x = torch.ones(mb * (1 << 20) // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": x.numel() * 8, "copy_bytes_written": y.numel() * 8, "launches": 5}))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="kh3d", choices=["kh3d", "random3d", "sedov3d", "riemann"])
+    ap.add_argument("--size", type=int, default=0, help="points per axis (lattice) or cube root of the point count")
+    ap.add_argument("--mode", default="mixed+learned", choices=["fp64", "fp64+learned", "mixed", "mixed+learned"])
+    ap.add_argument("--no-compare", action="store_true", help="skip the double-precision comparison run")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--threads", type=int, default=0, help="host threads for the mesh builder")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MB")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
+        return
+    out = bench_riemann(args) if args.workload == "riemann" else bench_step(args)
     print(json.dumps(out), flush=True)
 
 

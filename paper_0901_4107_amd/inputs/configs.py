@@ -34,6 +34,7 @@ class Workload:
     cfl: float
     boost: np.ndarray      # [D] uniform bulk velocity added to the flow (zeros if none)
     seed: int
+    prim: tuple = None     # (rho [N], vel [D][N], P [N]) the initial primitive fields
 
     @property
     def dim(self) -> int:
@@ -84,7 +85,7 @@ def kh2d(n_side: int = 64, jitter: float = 0.05, seed: int = 1000, nthreads: int
     vel = np.stack([vx, vy])
     Q = conserved_from_primitive(mesh.volume, rho, vel, P, gamma)
     mesh.with_velocity(vel.copy())
-    return Workload("kh2d_64x64", mesh, Q, gamma, 0.4, np.zeros(2), seed)
+    return Workload("kh2d_64x64", mesh, Q, gamma, 0.4, np.zeros(2), seed, (rho, vel, P))
 
 
 def random_states(n: int, dim: int, gamma: float, rng):
@@ -103,7 +104,7 @@ def random3d(n_side: int = 64, jitter: float = 0.1, seed: int = 1001, nthreads: 
     mesh = build_mesh(jittered_lattice(n_side, 3, jitter, rng), nthreads)
     rho, vel, P = random_states(mesh.n_cells, 3, gamma, rng)
     Q = conserved_from_primitive(mesh.volume, rho, vel, P, gamma)
-    return Workload(f"random3d_{n_side}^3", mesh, Q, gamma, 0.4, np.zeros(3), seed)
+    return Workload(f"random3d_{n_side}^3", mesh, Q, gamma, 0.4, np.zeros(3), seed, (rho, vel, P))
 
 
 def kh3d(n_points: int = 128 ** 3, seed: int = 1002, boost_mach: float = 10.0,
@@ -127,7 +128,7 @@ def kh3d(n_points: int = 128 ** 3, seed: int = 1002, boost_mach: float = 10.0,
     vel = np.stack([vx, vy, np.zeros_like(vx)]) + boost[:, None]
     Q = conserved_from_primitive(mesh.volume, rho, vel, P, gamma)
     mesh.with_velocity(vel.copy())
-    return Workload(f"kh3d_poisson_{n_points}", mesh, Q, gamma, 0.4, boost, seed)
+    return Workload(f"kh3d_poisson_{n_points}", mesh, Q, gamma, 0.4, boost, seed, (rho, vel, P))
 
 
 def sedov3d(n_side: int = 256, jitter: float = 0.1, seed: int = 1004, n_hot: int = 32,
@@ -147,5 +148,65 @@ def sedov3d(n_side: int = 256, jitter: float = 0.1, seed: int = 1004, n_hot: int
     r2 = np.sum((mesh.positions - 0.5) ** 2, axis=1)
     hot = np.lexsort((np.arange(n), r2))[:n_hot]
     Q[4, hot] += energy / n_hot
+    P[hot] += (gamma - 1.0) * (energy / n_hot) / mesh.volume[hot]   # the added thermal energy
     mesh.with_velocity(vel.copy())
-    return Workload(f"sedov3d_{n_side}^3", mesh, Q, gamma, 0.4, np.zeros(3), seed)
+    return Workload(f"sedov3d_{n_side}^3", mesh, Q, gamma, 0.4, np.zeros(3), seed, (rho, vel, P))
+
+
+def riemann_tails(n: int, gamma: float, rng) -> np.ndarray:
+    """Hard-tail Riemann problems [6][n] (rho_L, u_L, P_L, rho_R, u_R, P_R):
+    half near vacuum (velocity jump 80-99.5% of the vacuum threshold
+    2 (c_L + c_R)/(g-1)), half strong shocks (pressure ratios 1e2-1e6 in
+    either order, colliding flows)."""
+    h = n // 2
+    rho = 10 ** rng.uniform(-2, 2, (2, n))
+    P = 10 ** rng.uniform(-2, 2, (2, n))
+    c = np.sqrt(gamma * P / rho)
+    u = np.zeros((2, n))
+    thr = 2 * (c[0] + c[1]) / (gamma - 1)
+    jump = rng.uniform(0.8, 0.995, h) * thr[:h]
+    u[0, :h] = -0.5 * jump
+    u[1, :h] = 0.5 * jump
+    ratio = 10 ** rng.uniform(2, 6, n - h) * rng.choice([-1, 1], n - h)
+    P[1, h:] = np.where(ratio > 0, P[0, h:] * np.abs(ratio), P[0, h:] / np.abs(ratio))
+    c = np.sqrt(gamma * P / rho)
+    coll = rng.uniform(0, 3, n - h) * (c[0, h:] + c[1, h:])
+    u[0, h:] = 0.5 * coll
+    u[1, h:] = -0.5 * coll
+    return np.stack([rho[0], u[0], P[0], rho[1], u[1], P[1]])
+
+
+def face_pair_problems(wl: Workload) -> np.ndarray:
+    """The Riemann problems [6][F] posed by the cell-centre states on the two
+    sides of every face of a workload: density, velocity along the L->R
+    normal, pressure."""
+    rho, vel, P = wl.prim
+    m = wl.mesh
+    n = m.face_sep / np.sqrt(np.sum(m.face_sep ** 2, axis=0))
+    uL = np.sum(vel[:, m.face_L] * n, axis=0)
+    uR = np.sum(vel[:, m.face_R] * n, axis=0)
+    return np.stack([rho[m.face_L], uL, P[m.face_L], rho[m.face_R], uR, P[m.face_R]])
+
+
+def riemann_problems(n: int = 1 << 24, seed: int = 1003, side: int = 64, nthreads: int = 0) -> np.ndarray:
+    """16M-style batch of independent 1D Riemann problems [6][n]: face-pair
+    problems of the random-state, boosted Kelvin-Helmholtz and Sedov
+    workloads (side^3 cells each) resampled with replacement to 95% of n,
+    plus 5% hard tails (riemann_tails). The Sedov pairs are taken where the
+    two sides differ (the blast region)."""
+    rng = np.random.default_rng(seed)
+    gamma = 5.0 / 3.0
+    pools = []
+    for wl in (random3d(n_side=side, seed=seed + 1, nthreads=nthreads),
+               kh3d(n_points=side ** 3, seed=seed + 2, nthreads=nthreads),
+               sedov3d(n_side=side, seed=seed + 3, nthreads=nthreads)):
+        s = face_pair_problems(wl)
+        if wl.name.startswith("sedov"):
+            s = s[:, np.abs(s[2] - s[5]) > 1e-12]
+        pools.append(s)
+    n_tail = n // 20
+    n_body = n - n_tail
+    per = [n_body // 3, n_body // 3, n_body - 2 * (n_body // 3)]
+    body = [p[:, rng.integers(0, p.shape[1], k)] for p, k in zip(pools, per)]
+    out = np.concatenate(body + [riemann_tails(n_tail, gamma, rng)], axis=1)
+    return np.ascontiguousarray(out[:, rng.permutation(n)])

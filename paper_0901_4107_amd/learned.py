@@ -80,26 +80,8 @@ def harvest(wl, steps: int = 1, device="cuda") -> torch.Tensor:
 
 
 def tails(n: int, gamma: float, rng: np.random.Generator) -> np.ndarray:
-    """Problems from the hard tails [6][n] (double): half near vacuum
-    (velocity jump 80-99.5% of the vacuum threshold 2(c_L+c_R)/(g-1)), half
-    strong shocks (pressure ratios up to 1e6 in either order, colliding
-    flows)."""
-    h = n // 2
-    rho = 10 ** rng.uniform(-2, 2, (2, n))
-    P = 10 ** rng.uniform(-2, 2, (2, n))
-    c = np.sqrt(gamma * P / rho)
-    u = np.zeros((2, n))
-    thr = 2 * (c[0] + c[1]) / (gamma - 1)
-    jump = rng.uniform(0.8, 0.995, h) * thr[:h]
-    u[0, :h] = -0.5 * jump
-    u[1, :h] = 0.5 * jump
-    ratio = 10 ** rng.uniform(2, 6, n - h) * rng.choice([-1, 1], n - h)
-    P[1, h:] = np.where(ratio > 0, P[0, h:] * np.abs(ratio), P[0, h:] / np.abs(ratio))
-    c = np.sqrt(gamma * P / rho)
-    coll = rng.uniform(0, 3, n - h) * (c[0, h:] + c[1, h:])
-    u[0, h:] = 0.5 * coll
-    u[1, h:] = -0.5 * coll
-    return np.stack([rho[0], u[0], P[0], rho[1], u[1], P[1]])
+    """Hard-tail problems (the input generator's recipe)."""
+    return configs.riemann_tails(n, gamma, rng)
 
 
 def label(states: torch.Tensor, gamma: float, device="cuda"):
