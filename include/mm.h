@@ -100,8 +100,9 @@ typedef struct {
     uint64_t positivity_fallback;/* faces that used unextrapolated states */
     uint64_t fp64_fallback;      /* MM_MIXED: faces re-solved in double */
     uint64_t guess_fallback;     /* MM_GUESS_LEARNED: faces restarted from the standard guess */
-    uint64_t wave_iter_max_sum;  /* sum over 64-lane wavefronts of their max iteration count */
-    uint64_t waves;              /* number of wavefronts counted */
+    uint64_t wave_iter_max_sum;  /* sum over 64-lane wavefronts of their max iteration count,
+                                    the wavefronts of the double re-solve pass included */
+    uint64_t waves;              /* number of wavefronts of the main pass (faces or problems / 64) */
     int32_t nonfinite;           /* 1 if a step produced a non-finite conserved value */
     int32_t reserved;
 } mm_diag;
@@ -208,7 +209,8 @@ mm_status mm_mlp_adam(float *params, const float *grad, float *m1, float *m2, fl
 
 /* n independent 1D Riemann problems, states [6][n] double (rho_L, u_L, P_L,
  * rho_R, u_R, P_R), solved exactly with the context's mode (MM_FP64: double;
- * MM_MIXED: float, hard problems re-solved in double) and guess, sampled at
+ * MM_MIXED: float, hard problems re-solved in double by a second pass, in
+ * chunks of 2^22 problems) and guess, sampled at
  * x/t = 0: out [n][5] double = (rho_F, u_F, P_F, p*, p_std), p* the star
  * pressure and p_std the standard starting guess (both -1 where the problem
  * has no star state: vacuum); iters [n] (optional) the Newton

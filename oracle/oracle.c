@@ -7,8 +7,7 @@
  * test suite, the smoke check and the CPU-baseline leg of the benchmark may
  * load it. It shares no source with the GPU library and includes none of its
  * headers. Every function names the passage of the paper it follows; where
- * the paper is silent the reading taken is stated in the comment and listed
- * in the design notes.
+ * the paper is silent the reading taken is stated in the comment.
  *
  * Layouts (identical to the public ABI so that tests can pass the same
  * arrays to both sides, but re-declared here on purpose):

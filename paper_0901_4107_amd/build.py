@@ -12,8 +12,12 @@ LIBVOR = os.path.join(HERE, "inputs", "libvoronoi.so")
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
-    # packed FP32 instructions stay off (see the design notes)
+    # packed FP32 instructions stay off: some of their forms have been seen
+    # to give wrong results without an error on this hardware
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # matrix-core accumulators in ordinary VGPRs: the fused network then
+    # shares the register file with the flux code instead of adding AGPRs
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
 ]
 

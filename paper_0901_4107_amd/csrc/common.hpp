@@ -7,6 +7,9 @@
 namespace mm {
 
 constexpr int kBlock = 256;   // 4 wavefronts of 64 lanes
+// Batched Riemann problems are solved in chunks of this many, the size of
+// the hard-problem list of a mixed-precision context.
+constexpr int64_t kBatchChunk = int64_t(1) << 22;
 constexpr int kXcd = 8;       // MI355X: workgroups are dealt round-robin to 8 XCDs
 
 // Grid size for n items, rounded up to a multiple of the XCD count so that
@@ -30,6 +33,47 @@ __device__ __forceinline__ int64_t xcd_tile() {
 
 __device__ __forceinline__ int64_t xcd_global_id() {
     return xcd_tile() * kBlock + threadIdx.x;
+}
+
+// A list of flagged items (hard faces or problems) split into kLists
+// sub-lists, one per residue of the producing block index, each with its
+// own counter on its own 128-byte line: appends from different blocks
+// rarely meet on one atomic. Sub-list c holds the items of the blocks with
+// blockIdx % kLists == c, at most list_cap(grid) of them.
+// Layout (int32): kLists counters kListPad apart, then kLists item arrays.
+constexpr int kLists = 256;
+constexpr int kListPad = 32;
+__host__ __device__ inline int64_t list_cap(int64_t grid) { return (grid + kLists - 1) / kLists * kBlock; }
+inline int64_t list_ints(int64_t grid) { return (int64_t)kLists * kListPad + kLists * list_cap(grid); }
+
+// Wave-aggregated append of `item` where `flag` is set; every lane of the
+// wavefront calls it.
+__device__ __forceinline__ void list_append(int32_t *list, int64_t cap, bool flag, int32_t item) {
+    const unsigned long long mask = __ballot(flag);
+    if (!mask) return;
+    const int c = blockIdx.x % kLists;
+    const int lane = threadIdx.x & 63;
+    const int first = __ffsll((long long)mask) - 1;
+    int base = 0;
+    if (lane == first) base = atomicAdd(list + c * kListPad, __popcll(mask));
+    base = __shfl(base, first, 64);
+    if (flag) list[(int64_t)kLists * kListPad + c * cap + base + __popcll(mask & ((1ull << lane) - 1ull))] = item;
+}
+
+// Consumer side: a grid of a multiple of kLists blocks; block b walks
+// sub-list b % kLists together with the other blocks of that residue.
+struct ListWalk {
+    const int32_t *items;
+    int64_t count, start, stride;
+};
+__device__ __forceinline__ ListWalk list_walk(const int32_t *list, int64_t cap) {
+    const int c = blockIdx.x % kLists;
+    ListWalk w;
+    w.items = list + (int64_t)kLists * kListPad + c * cap;
+    w.count = list[c * kListPad];
+    w.start = (int64_t)(blockIdx.x / kLists) * kBlock + threadIdx.x;
+    w.stride = (int64_t)(gridDim.x / kLists) * kBlock;
+    return w;
 }
 
 }  // namespace mm

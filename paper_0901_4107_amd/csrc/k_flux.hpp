@@ -168,20 +168,28 @@ __device__ __forceinline__ FaceState<T> solve_face(T rhoL, T uL, T PL, T rhoR, T
 template <typename T> __device__ __forceinline__ T no_guess() { return (T)__builtin_nan(""); }
 
 // Whether a problem takes the learned guess: both sides non-vacuum, no
-// vacuum generated, and a standard guess that is not already good: neither
-// the primitive-variable estimate in its accepted regime (mild pressure
-// ratio, estimate between the pressures) nor the two-rarefaction estimate
-// when both waves are rarefactions (then it is the exact root; that case is
-// f(p_min) >= 0, f increasing, where only the higher-pressure side
-// contributes: (2 c_max/(g-1)) ((p_min/p_max)^z - 1) + u_R - u_L >= 0).
+// vacuum generated, a strong problem (a density or pressure ratio of at
+// least e, or a velocity jump of at least 0.4 (c_L + c_R): below that every
+// scaled feature is under 0.2, where the standard guess is already far more
+// accurate than the network), and a standard guess that is not already
+// good: neither the primitive-variable estimate in its accepted regime
+// (mild pressure ratio, estimate between the pressures) nor the
+// two-rarefaction estimate when both waves are rarefactions (then it is the
+// exact root; that case is f(p_min) >= 0, f increasing, where only the
+// higher-pressure side contributes:
+// (2 c_max/(g-1)) ((p_min/p_max)^z - 1) + u_R - u_L >= 0).
 template <typename T>
 __device__ __forceinline__ bool wants_learned(T rhoL, T uL, T PL, T rhoR, T uR, T PR, T gamma) {
     if (!(rhoL > (T)0 && PL > (T)0 && rhoR > (T)0 && PR > (T)0)) return false;
     const T cL = mm_sqrt(gamma * PL / rhoL), cR = mm_sqrt(gamma * PR / rhoR);
     const T du = uR - uL;
     if (!(cL + cR - (T)0.5 * (gamma - (T)1) * du > (T)0)) return false;
-    const T ppv = (T)0.5 * (PL + PR) - (T)0.125 * du * (rhoL + rhoR) * (cL + cR);
     const T pmin = PL < PR ? PL : PR, pmax = PL < PR ? PR : PL;
+    const T rmin = rhoL < rhoR ? rhoL : rhoR, rmax = rhoL < rhoR ? rhoR : rhoL;
+    const T adu = du < (T)0 ? -du : du;
+    if (!(rmax >= (T)kMlpGateRatio * rmin || pmax >= (T)kMlpGateRatio * pmin || adu >= (T)kMlpGateDu * (cL + cR)))
+        return false;
+    const T ppv = (T)0.5 * (PL + PR) - (T)0.125 * du * (rhoL + rhoR) * (cL + cR);
     if (pmax <= (T)2 * pmin && ppv >= pmin && ppv <= pmax) return false;
     if (ppv < pmin) {
         const T cmax = PL < PR ? cR : cL;
@@ -192,19 +200,53 @@ __device__ __forceinline__ bool wants_learned(T rhoL, T uL, T PL, T rhoR, T uR, 
     return true;
 }
 
-// The learned guess for a wavefront of problems (every lane must call;
-// lanes with want = false get -1). A wavefront where no lane wants a guess
-// skips the network.
+// Block-wide staging of the learned guess: the problems of a block that
+// want the network are compacted, so only ceil(count / 64) wavefronts
+// evaluate it, each for 64 problems.
+struct LearnLds {
+    float x[3][kBlock];
+    float y[kBlock];
+    int cnt[kBlock / 64];
+};
+
+// The learned guess for the problems of a block. Every thread of the block
+// must call it (it holds barriers); threads with want = false get NaN. The
+// result is the network's ln(p* / p_standard), or NaN when out of range.
 template <typename T>
 __device__ __forceinline__ T learned_guess(const MlpPacked *P, bool want, T rhoL, T uL, T PL, T rhoR, T uR, T PR,
                                            float gamma) {
-    if (P == nullptr || __ballot(want) == 0ull) return no_guess<T>();
-    float x0 = 0.0f, x1 = 0.0f, x2 = 0.0f;
-    if (want) mlp_features((float)rhoL, (float)uL, (float)PL, (float)rhoR, (float)uR, (float)PR, gamma, x0, x1, x2);
-    const float y = mlp_wave_infer(P, x0, x1, x2);
+    __shared__ LearnLds sh;
+    if (P == nullptr) return no_guess<T>();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const unsigned long long m = __ballot(want);
+    if (lane == 0) sh.cnt[wv] = __popcll(m);
+    __syncthreads();
+    int base = 0, total = 0;
+    for (int w = 0; w < kBlock / 64; w++) {
+        const int c = sh.cnt[w];
+        base += w < wv ? c : 0;
+        total += c;
+    }
+    if (total == 0) return no_guess<T>();   // the same for the whole block
+    const int slot = base + __popcll(m & ((1ull << lane) - 1ull));
+    if (want) {
+        float x0, x1, x2;
+        mlp_features((float)rhoL, (float)uL, (float)PL, (float)rhoR, (float)uR, (float)PR, gamma, x0, x1, x2);
+        sh.x[0][slot] = x0;
+        sh.x[1][slot] = x1;
+        sh.x[2][slot] = x2;
+    }
+    __syncthreads();
+    if (wv * 64 < total) {   // uniform per wavefront
+        const int k = wv * 64 + lane;
+        const bool ok = k < total;
+        const float y = mlp_wave_infer(P, ok ? sh.x[0][k] : 0.0f, ok ? sh.x[1][k] : 0.0f, ok ? sh.x[2][k] : 0.0f);
+        if (ok) sh.y[k] = y;
+    }
+    __syncthreads();
     if (!want) return no_guess<T>();
     // the network predicts ln(p* / p_standard) / kMlpScaleY
-    const float corr = kMlpScaleY * y;
+    const float corr = kMlpScaleY * sh.y[slot];
     return (corr > -20.0f && corr < 20.0f) ? (T)corr : no_guess<T>();
 }
 
@@ -364,6 +406,7 @@ __global__ void __launch_bounds__(kBlock) k_face_flux_mixed(int64_t nf, const in
                                                             GasConst<float> kf, double g_over_gm1, float tol32,
                                                             int maxit, const MlpPacked *mlp,
                                                             double *__restrict__ flux, int32_t *__restrict__ hard_list,
+                                                            int64_t cap,
                                                             DiagDev *diag) {
     constexpr int NV = D + 2;
     const int64_t f = xcd_global_id();
@@ -392,23 +435,12 @@ __global__ void __launch_bounds__(kBlock) k_face_flux_mixed(int64_t nf, const in
                                                 maxit, pl, true, ld, hard);
         if (!hard) mixed_lab_flux<D>(m, fs.rho, fs.u, fs.P, fs.side, wf64, f, g_over_gm1, dt, flux + f * NV);
     }
-    // wave-aggregated append of the hard faces
-    const unsigned long long mask = __ballot(hard);
-    if (mask) {
-        const int lane = threadIdx.x & 63;
-        int base = 0;
-        if (lane == __ffsll((long long)mask) - 1) base = atomicAdd(hard_list, __popcll(mask));
-        base = __shfl(base, __ffsll((long long)mask) - 1, 64);
-        if (hard) {
-            const int rank = __popcll(mask & ((1ull << lane) - 1ull));
-            hard_list[1 + base + rank] = (int32_t)f;
-        }
-    }
+    list_append(hard_list, cap, hard, (int32_t)f);
     if (diag) flush_diag(ld, diag);
 }
 
 // Double re-solve of the hard faces listed by k_face_flux_mixed (count in
-// hard_list[0], faces after it). A fixed grid strides over the list, so the
+// a split list of sub-list capacity cap). A fixed grid walks the list, so the
 // launch needs no host-side count; the float face states are recomputed by
 // the same code, hence identical.
 template <int D>
@@ -419,15 +451,14 @@ __global__ void __launch_bounds__(kBlock) k_face_flux_hard(const int32_t *__rest
                                                            const float *__restrict__ rec,
                                                            const double *__restrict__ dt_ptr, double dt_val,
                                                            float gam, GasConst<double> kg, double tol64,
-                                                           const int32_t *__restrict__ hard_list,
+                                                           const int32_t *__restrict__ hard_list, int64_t cap,
                                                            double *__restrict__ flux, DiagDev *diag) {
     constexpr int NV = D + 2;
-    const int count = hard_list[0];
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    const ListWalk lw = list_walk(hard_list, cap);
     const double dt = dt_ptr ? *dt_ptr : dt_val;
     LaneDiag ld;
-    for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < count; q += stride) {
-        const int64_t f = hard_list[1 + q];
+    for (int64_t q = lw.start; q < lw.count; q += lw.stride) {
+        const int64_t f = lw.items[q];
         const MixedFace<D> m = mixed_face_states<D>(f, fL, fR, mrec, rec, (float)(0.5 * dt), gam);
         bool h2;
         FaceState<double> fd = solve_face<double>(m.xl[0], m.uL, m.xl[NV - 1], m.xr[0], m.uR, m.xr[NV - 1], kg,

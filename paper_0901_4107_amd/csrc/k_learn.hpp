@@ -171,14 +171,11 @@ __global__ void k_mlp_pack(const float *__restrict__ prm, MlpPacked *__restrict_
         }
         out->a1[t][l] = v;
     }
-    for (int q = threadIdx.x; q < 16 * 64; q += blockDim.x) {
-        const int t = q / 256, s = (q / 64) % 4, l = q % 64;
+    for (int q = threadIdx.x; q < 8 * 64; q += blockDim.x) {
+        const int t = q / 128, s = (q / 64) % 2, l = q % 64;
         const int hout = 16 * t + (l & 15);
-        bf16x4_t v;
-        for (int j = 0; j < 4; j++) {
-            const int hin = 16 * s + 4 * (l >> 4) + j;
-            v[j] = f2bf(prm[kMlpOffW2 + hin * kMlpHidden + hout]);
-        }
+        bf16x8_t v;
+        for (int j = 0; j < 8; j++) v[j] = (__bf16)prm[kMlpOffW2 + mlp_l2_unit(s, l >> 4, j) * kMlpHidden + hout];
         out->a2[t][s][l] = v;
     }
     for (int h = threadIdx.x; h < kMlpHidden; h += blockDim.x) {
@@ -199,40 +196,68 @@ __global__ void __launch_bounds__(kBlock) k_mlp_infer(int64_t n, const MlpPacked
 }
 
 // Batched 1D Riemann problems: states [6][n] (rho_L, u_L, P_L, rho_R, u_R,
-// P_R, double), solved in precision T with the standard or learned guess;
-// out [n][4] = (rho_F, u_F, P_F, p*) with p* = -1 where no star state
-// exists (vacuum); iters [n] optional. In float, hard problems are re-solved
-// in double.
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_riemann_batch(int64_t n, const double *__restrict__ st, GasConst<T> kt,
-                                                          GasConst<double> kd, T tol, double tol64, int maxit,
-                                                          const MlpPacked *mlp, double *__restrict__ out,
-                                                          int32_t *__restrict__ iters, DiagDev *diag) {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const bool ok = i < n;
+// P_R, double), problems [i0, i0 + nc) of them solved in precision T with
+// the standard or learned guess; out [n][5] = (rho_F, u_F, P_F, p*, p_std)
+// with p* = -1 where no star state exists (vacuum); iters [n] optional. In
+// float, hard problems (as for faces) are appended to hard_list (a split
+// list of chunk-local indices, sub-list capacity cap) for k_riemann_hard.
+template <typename T, bool LEARNED>
+__global__ void __launch_bounds__(kBlock) k_riemann_batch(int64_t n, int64_t i0, int64_t nc,
+                                                          const double *__restrict__ st, GasConst<T> kt, T tol,
+                                                          int maxit, const MlpPacked *mlp, double *__restrict__ out,
+                                                          int32_t *__restrict__ iters, int32_t *__restrict__ hard_list,
+                                                          int64_t cap, DiagDev *diag) {
+    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const bool ok = q < nc;
+    const int64_t i = i0 + q;
     T s[6];
-    for (int q = 0; q < 6; q++) s[q] = ok ? (T)st[q * n + i] : (T)1;
-    const bool want = mlp != nullptr && ok && wants_learned<T>(s[0], s[1], s[2], s[3], s[4], s[5], kt.g);
-    const T pl = learned_guess<T>(mlp, want, s[0], s[1], s[2], s[3], s[4], s[5], (float)kt.g);
+    for (int k = 0; k < 6; k++) s[k] = ok ? (T)st[k * n + i] : (T)1;
+    T pl = no_guess<T>();
+    if constexpr (LEARNED) {
+        const bool want = ok && wants_learned<T>(s[0], s[1], s[2], s[3], s[4], s[5], kt.g);
+        pl = learned_guess<T>(mlp, want, s[0], s[1], s[2], s[3], s[4], s[5], (float)kt.g);
+    }
     LaneDiag ld;
+    bool hard = false;
     if (ok) {
-        bool hard = false;
         const bool f32 = sizeof(T) == 4;
         FaceState<T> fs = solve_face<T>(s[0], s[1], s[2], s[3], s[4], s[5], kt, tol, maxit, pl, f32, ld, hard);
-        double rho = fs.rho, u = fs.u, P = fs.P, ps = fs.pstar, pg = fs.pstd;
-        if (hard) {
-            ld.fp64fb = 1;
-            bool h2;
-            FaceState<double> fd = solve_face<double>(st[i], st[n + i], st[2 * n + i], st[3 * n + i], st[4 * n + i],
-                                                      st[5 * n + i], kd, tol64, 50, no_guess<double>(), false, ld, h2);
-            rho = fd.rho; u = fd.u; P = fd.P; ps = fd.pstar; pg = fd.pstd;
+        if (!hard) {
+            out[i * 5 + 0] = fs.rho;
+            out[i * 5 + 1] = fs.u;
+            out[i * 5 + 2] = fs.P;
+            out[i * 5 + 3] = fs.pstar;
+            out[i * 5 + 4] = fs.pstd;
         }
-        out[i * 5 + 0] = rho;
-        out[i * 5 + 1] = u;
-        out[i * 5 + 2] = P;
-        out[i * 5 + 3] = ps;
-        out[i * 5 + 4] = pg;
         if (iters) iters[i] = (int32_t)ld.iters;
+    }
+    if constexpr (sizeof(T) == 4) list_append(hard_list, cap, hard, (int32_t)q);
+    if (diag) flush_diag(ld, diag);
+}
+
+// Double re-solve of the hard problems listed by k_riemann_batch<float>
+// (from the double inputs, standard guess); their iteration counts add to
+// the float ones. A fixed grid (a multiple of kLists blocks) walks the list.
+__global__ void __launch_bounds__(kBlock) k_riemann_hard(int64_t n, int64_t i0, const double *__restrict__ st,
+                                                         GasConst<double> kd, double tol64,
+                                                         const int32_t *__restrict__ hard_list, int64_t cap,
+                                                         double *__restrict__ out, int32_t *__restrict__ iters,
+                                                         DiagDev *diag) {
+    const ListWalk lw = list_walk(hard_list, cap);
+    LaneDiag ld;
+    for (int64_t q = lw.start; q < lw.count; q += lw.stride) {
+        const int64_t i = i0 + lw.items[q];
+        const uint32_t before = ld.iters;
+        bool h2;
+        FaceState<double> fd = solve_face<double>(st[i], st[n + i], st[2 * n + i], st[3 * n + i], st[4 * n + i],
+                                                  st[5 * n + i], kd, tol64, 50, no_guess<double>(), false, ld, h2);
+        ld.fp64fb += 1;
+        out[i * 5 + 0] = fd.rho;
+        out[i * 5 + 1] = fd.u;
+        out[i * 5 + 2] = fd.P;
+        out[i * 5 + 3] = fd.pstar;
+        out[i * 5 + 4] = fd.pstd;
+        if (iters) iters[i] += (int32_t)(ld.iters - before);
     }
     if (diag) flush_diag(ld, diag);
 }

@@ -12,13 +12,18 @@
 // bf16 rounding of the network scales with that correction, not with p*.
 //
 // The network runs transposed, H^T = W^T X^T (rows = hidden units, columns =
-// faces), on v_mfma_f32_16x16x16_bf16. For that instruction lane l holds
-//   A[m][k]: m = l%16, k = 4(l/16)+j;  B[k][n]: n = l%16, k = 4(l/16)+j;
-//   C[m][n]: n = l%16, m = 4(l/16)+i   (j, i = 0..3),
-// so the accumulator of hidden tile t is, lane for lane, the B operand of
-// k-step t of the next layer: no data moves between layers 1 and 2. The
-// wave's 64 faces form four 16-face column tiles; the bias of layer 1 rides
-// in k = 3 (feature 1), the rest of k = 4..15 is zero.
+// faces). Layer 1 (K = 3 features + bias, padded to 16) runs on
+// v_mfma_f32_16x16x16_bf16, layer 2 (K = 64) on v_mfma_f32_16x16x32_bf16.
+// For these instructions lane l holds
+//   16x16x16  A[m][k]: m = l%16, k = 4(l/16)+j;  B[k][n]: n = l%16, k = 4(l/16)+j
+//   16x16x32  A[m][k]: m = l%16, k = 8(l/16)+j;  B[k][n]: n = l%16, k = 8(l/16)+j
+//   both      C[m][n]: n = l%16, m = 4(l/16)+i   (i = 0..3)
+// The accumulators of hidden tiles 2s and 2s+1 of layer 1, side by side,
+// are lane for lane the B operand of k-step s of layer 2 once the input
+// units of that step are numbered (g = l/16, slot j) -> 32s + 4g + (j%4) +
+// 16(j/4); the packed A operand of layer 2 uses the same numbering, so no
+// data moves between the layers. The wave's 64 faces form four 16-face
+// column tiles; the bias of layer 1 rides in k = 3, the rest of k is zero.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -26,6 +31,7 @@
 namespace mm {
 
 typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
 constexpr int kMlpHidden = 64;
@@ -34,24 +40,34 @@ constexpr int kMlpHidden = 64;
 constexpr int kMlpOffW1 = 0, kMlpOffB1 = 192, kMlpOffW2 = 256, kMlpOffB2 = 4352, kMlpOffW3 = 4416,
               kMlpOffB3 = 4480, kMlpParams = 4481;
 constexpr float kMlpScaleRho = 0.2f, kMlpScaleP = 0.2f, kMlpScaleU = 0.5f, kMlpScaleY = 1.0f;
+// Strength gate of the learned guess: a density or pressure ratio of at
+// least e (scaled log feature >= 0.2) or a velocity jump of at least
+// 0.4 (c_L + c_R) (scaled feature >= 0.2).
+constexpr double kMlpGateRatio = 2.718281828459045, kMlpGateDu = 0.4;
 
 // Packed inference form (device, built by k_mlp_pack): per (tile, k-step)
 // the A operand of every lane (4 bf16 = 8 bytes), then the fp32 biases.
 struct MlpPacked {
     bf16x4_t a1[4][64];          // layer 1: hidden tile t, lane l
-    bf16x4_t a2[4][4][64];       // layer 2: hidden tile t, k-step s, lane l
+    bf16x8_t a2[4][2][64];       // layer 2: output tile t, k-step s, lane l
     float b2[64], w3[64], b3;
 };
+
+// Input unit of layer 2 held in slot j of lane group g at k-step s.
+__host__ __device__ constexpr int mlp_l2_unit(int s, int g, int j) { return 32 * s + 4 * g + (j & 3) + 16 * (j >> 2); }
 
 struct MlpGuess {
     const MlpPacked *p;
 };
 
-__device__ __forceinline__ short f2bf(float x) {
-    // round to nearest even (finite inputs)
-    unsigned u = __builtin_bit_cast(unsigned, x);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (short)(u >> 16);
+// float -> bf16, round to nearest even (one v_cvt_pk_bf16_f32 per pair)
+__device__ __forceinline__ short f2bf(float x) { return __builtin_bit_cast(short, (__bf16)x); }
+
+// max(x, 0) as one integer max on the bit pattern: a float with the sign bit
+// set is a negative integer (-0 included), so it maps to +0.
+__device__ __forceinline__ float relu(float x) {
+    const int b = __builtin_bit_cast(int, x);
+    return __builtin_bit_cast(float, b > 0 ? b : 0);
 }
 
 // Features of one problem; valid = false gives zeros.
@@ -65,58 +81,55 @@ __device__ __forceinline__ void mlp_features(float rhoL, float uL, float PL, flo
 
 // Whole-wavefront inference: every lane of the wave must call this (full
 // exec mask); lane l supplies the features of its face and receives y.
+// Each weight is read once per wavefront: layer 1 runs for the four column
+// tiles, then layer 2 and 3 one output tile at a time over all columns. The
+// scheduling barriers keep each tile's weight loads next to their use, so
+// at most one tile of weights is live on top of the hidden activations.
 __device__ __forceinline__ float mlp_wave_infer(const MlpPacked *__restrict__ P, float x0, float x1, float x2) {
     const int lane = threadIdx.x & 63;
     const int src = lane & 15;
     const bool low = lane < 16;
-    // layer 1 B operands: column tile n holds faces 16n..16n+15
-    bf16x4_t xb[4];
+    const int rbase = 4 * (lane >> 4);
+    // layer 1 -> relu -> bf16; h1[s][n] is the B operand of k-step s of
+    // layer 2 for column tile n (faces 16n..16n+15): tiles 2s and 2s+1
+    // side by side
+    bf16x8_t h1[2][4];
+    bf16x4_t a1[4];
+    for (int t = 0; t < 4; t++) a1[t] = P->a1[t][lane];
     for (int n = 0; n < 4; n++) {
         const float a = __shfl(x0, 16 * n + src, 64);
         const float b = __shfl(x1, 16 * n + src, 64);
         const float c = __shfl(x2, 16 * n + src, 64);
-        bf16x4_t v;
-        v[0] = low ? f2bf(a) : (short)0;
-        v[1] = low ? f2bf(b) : (short)0;
-        v[2] = low ? f2bf(c) : (short)0;
-        v[3] = low ? f2bf(1.0f) : (short)0;
-        xb[n] = v;
-    }
-    // layer 1 -> h1 (relu, bf16), kept as the B operands of layer 2
-    bf16x4_t h1[4][4];  // [hidden tile t][column tile n]
-    for (int t = 0; t < 4; t++) {
-        const bf16x4_t a = P->a1[t][lane];
-        for (int n = 0; n < 4; n++) {
+        bf16x4_t xb;
+        xb[0] = low ? f2bf(a) : (short)0;
+        xb[1] = low ? f2bf(b) : (short)0;
+        xb[2] = low ? f2bf(c) : (short)0;
+        xb[3] = low ? f2bf(1.0f) : (short)0;
+        for (int t = 0; t < 4; t++) {
             f32x4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, xb[n], acc, 0, 0, 0);
-            bf16x4_t h;
-            for (int i = 0; i < 4; i++) h[i] = f2bf(acc[i] > 0.0f ? acc[i] : 0.0f);
-            h1[t][n] = h;
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1[t], xb, acc, 0, 0, 0);
+            for (int i = 0; i < 4; i++) h1[t >> 1][n][4 * (t & 1) + i] = (__bf16)relu(acc[i]);
         }
     }
-    // layer 2 (+ b2, relu) and layer 3 (w3 dot, + b3), one hidden tile at a time
+    // layer 2 (+ b2, relu) and layer 3 (w3 dot), one output tile at a time
     float y[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-    const int rbase = 4 * (lane >> 4);
     for (int t = 0; t < 4; t++) {
-        f32x4_t acc[4];
-        for (int n = 0; n < 4; n++)
-            for (int i = 0; i < 4; i++) acc[n][i] = P->b2[16 * t + rbase + i];
-        for (int s = 0; s < 4; s++) {
-            const bf16x4_t a = P->a2[t][s][lane];
-            for (int n = 0; n < 4; n++) acc[n] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, h1[s][n], acc[n], 0, 0, 0);
+        __builtin_amdgcn_sched_barrier(0);
+        const bf16x8_t w0 = P->a2[t][0][lane], w1 = P->a2[t][1][lane];
+        const f32x4_t bias = *reinterpret_cast<const f32x4_t *>(P->b2 + 16 * t + rbase);
+        const f32x4_t w3 = *reinterpret_cast<const f32x4_t *>(P->w3 + 16 * t + rbase);
+        for (int n = 0; n < 4; n++) {
+            f32x4_t acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w0, h1[0][n], bias, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1, h1[1][n], acc, 0, 0, 0);
+            for (int i = 0; i < 4; i++) y[n] += w3[i] * relu(acc[i]);
         }
-        for (int n = 0; n < 4; n++)
-            for (int i = 0; i < 4; i++) {
-                const float h = acc[n][i] > 0.0f ? acc[n][i] : 0.0f;
-                y[n] += P->w3[16 * t + rbase + i] * h;
-            }
     }
-    // sum the four row groups of each column (lanes l, l^16, l^32, l^48)
+    // sum the four row groups of each column (lanes l, l^16, l^32, l^48);
+    // lane l's face is column l%16 of tile l/16
     for (int n = 0; n < 4; n++) {
         y[n] += __shfl_xor(y[n], 16, 64);
         y[n] += __shfl_xor(y[n], 32, 64);
     }
-    // lane l's face is column l%16 of tile l/16
     const int me = lane >> 4;
     const float yy = me == 0 ? y[0] : me == 1 ? y[1] : me == 2 ? y[2] : y[3];
     return yy + P->b3;

@@ -29,7 +29,7 @@ namespace {
 inline int64_t align256(int64_t x) { return (x + 255) / 256 * 256; }
 
 struct Layout {
-    int64_t flags, diag, mlp, dtdev, dtpart, bsum, off, cursor, ent, nbr;
+    int64_t flags, diag, mlp, dtdev, bhard, dtpart, bsum, off, cursor, ent, nbr;
     int64_t srec, frec, rec, flux;          // double path (frec always)
     int64_t srec32, mrec, wf64, rec32, hard; // mixed path
     int64_t total;
@@ -48,6 +48,7 @@ Layout make_layout(int D, int mode, int64_t n, int64_t nf) {
     L.diag = take(kDiagSlots * sizeof(DiagDev));
     L.mlp = take(sizeof(MlpPacked));
     L.dtdev = take(4 * sizeof(double));
+    L.bhard = mode == MM_FP64 ? -1 : take(list_ints((kBatchChunk + kBlock - 1) / kBlock) * sizeof(int32_t));
     L.dtpart = take((int64_t)grid_for(n) * sizeof(double));
     int64_t bs = 0, m = n + 1;
     while (m > 1) { m = (m + 1023) / 1024; bs += m + 1; }
@@ -67,7 +68,7 @@ Layout make_layout(int D, int mode, int64_t n, int64_t nf) {
         L.mrec = take(nf * Lay<3>::MREC * sizeof(float));
         L.wf64 = take(nf * WS * sizeof(double));
         L.rec32 = take(n * REC * sizeof(float));
-        L.hard = take((nf + 1) * sizeof(int32_t));
+        L.hard = take(list_ints(grid_for(nf)) * sizeof(int32_t));
     }
     L.total = o;
     return L;
@@ -100,7 +101,7 @@ struct mm_ctx {
 #define MM_LAUNCH_CHECK() MM_CHECK(hipGetLastError())
 
 // Fixed grid of the hard-face pass (it strides over a device-side list).
-constexpr unsigned kHardGrid = 2048;
+constexpr unsigned kHardGrid = 8 * kLists;   // walks of the split hard lists
 
 static unsigned plain_grid(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
@@ -312,15 +313,16 @@ static mm_status fluxes_t(mm_ctx *c, const double *dt_dev, double dt, const void
                                                 c->p.newton_max_iter, mlp, flux, diag);
     } else {
         int32_t *hard = c->at<int32_t>(L.hard);
-        k_fill_i32<<<1, kBlock, 0, s>>>(hard, 1, 0);
+        const int64_t cap = list_cap(grid_for(c->nf));
+        k_fill_i32<<<kLists * kListPad / kBlock, kBlock, 0, s>>>(hard, kLists * kListPad, 0);
         auto kern = mlp ? k_face_flux_mixed<D, true> : k_face_flux_mixed<D, false>;
         kern<<<grid_for(c->nf), kBlock, 0, s>>>(c->nf, c->mesh.face_L, c->mesh.face_R, c->at<float>(L.mrec),
                                                 c->at<double>(L.wf64), (const float *)rec, dt_dev, dt, kf,
                                                 kg.g_over_gm1, (float)c->p.newton_tol32, c->p.newton_max_iter, mlp,
-                                                flux, hard, diag);
+                                                flux, hard, cap, diag);
         k_face_flux_hard<D><<<kHardGrid, kBlock, 0, s>>>(c->mesh.face_L, c->mesh.face_R, c->at<float>(L.mrec),
                                                         c->at<double>(L.wf64), (const float *)rec, dt_dev, dt, kf.g,
-                                                        kg, c->p.newton_tol64, hard, flux, diag);
+                                                        kg, c->p.newton_tol64, hard, cap, flux, diag);
     }
     MM_LAUNCH_CHECK();
     return MM_OK;
@@ -457,14 +459,24 @@ mm_status mm_riemann_batch(mm_ctx *c, int64_t n, const double *states, double *o
     const GasConst<double> kg(c->p.gamma);
     c->faces_done += (uint64_t)n;
     c->waves_done += (uint64_t)((n + 63) / 64);
-    if (c->p.mode == MM_FP64)
-        k_riemann_batch<double><<<plain_grid(n), kBlock, 0, c->st()>>>(n, states, kg, kg, c->p.newton_tol64,
-                                                                       c->p.newton_tol64, c->p.newton_max_iter, mlp,
-                                                                       out, iters, diag);
-    else
-        k_riemann_batch<float><<<plain_grid(n), kBlock, 0, c->st()>>>(
-            n, states, GasConst<float>(c->p.gamma), kg, (float)c->p.newton_tol32, c->p.newton_tol64,
-            c->p.newton_max_iter, mlp, out, iters, diag);
+    for (int64_t i0 = 0; i0 < n; i0 += kBatchChunk) {
+        const int64_t nc = n - i0 < kBatchChunk ? n - i0 : kBatchChunk;
+        if (c->p.mode == MM_FP64) {
+            auto kern = mlp ? k_riemann_batch<double, true> : k_riemann_batch<double, false>;
+            kern<<<plain_grid(nc), kBlock, 0, c->st()>>>(n, i0, nc, states, kg, c->p.newton_tol64,
+                                                         c->p.newton_max_iter, mlp, out, iters, nullptr, 0, diag);
+        } else {
+            int32_t *hard = c->at<int32_t>(c->lay.bhard);
+            const int64_t cap = list_cap(plain_grid(nc));
+            k_fill_i32<<<kLists * kListPad / kBlock, kBlock, 0, c->st()>>>(hard, kLists * kListPad, 0);
+            auto kern = mlp ? k_riemann_batch<float, true> : k_riemann_batch<float, false>;
+            kern<<<plain_grid(nc), kBlock, 0, c->st()>>>(n, i0, nc, states, GasConst<float>(c->p.gamma),
+                                                         (float)c->p.newton_tol32, c->p.newton_max_iter, mlp, out,
+                                                         iters, hard, cap, diag);
+            k_riemann_hard<<<kHardGrid, kBlock, 0, c->st()>>>(n, i0, states, kg, c->p.newton_tol64, hard, cap, out,
+                                                              iters, diag);
+        }
+    }
     MM_LAUNCH_CHECK();
     return MM_OK;
 }

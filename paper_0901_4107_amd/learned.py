@@ -39,17 +39,25 @@ def features(states: torch.Tensor, gamma: float):
     return X.float().contiguous()
 
 
+# strength gate (mirrors kMlpGateRatio, kMlpGateDu)
+GATE_RATIO, GATE_DU = float(np.e), 0.4
+
+
 def wants_learned(states: torch.Tensor, gamma: float) -> torch.Tensor:
     """The problems the learned guess serves (the library's own selection,
-    restated on tensors): no vacuum, and a standard guess that is neither
-    the primitive-variable estimate in its accepted regime nor the exact
-    two-rarefaction root."""
+    restated on tensors): no vacuum, a strong problem (density or pressure
+    ratio >= e, or |u_R - u_L| >= 0.4 (c_L + c_R)), and a standard guess
+    that is neither the primitive-variable estimate in its accepted regime
+    nor the exact two-rarefaction root."""
     rL, uL, PL, rR, uR, PR = [states[k].double() for k in range(6)]
     ok = (rL > 0) & (PL > 0) & (rR > 0) & (PR > 0)
     cL = torch.sqrt(gamma * PL / rL.clamp_min(1e-300))
     cR = torch.sqrt(gamma * PR / rR.clamp_min(1e-300))
     du = uR - uL
     ok &= (cL + cR - 0.5 * (gamma - 1) * du) > 0
+    rmin, rmax = torch.minimum(rL, rR), torch.maximum(rL, rR)
+    ok &= ((rmax >= GATE_RATIO * rmin) | (torch.maximum(PL, PR) >= GATE_RATIO * torch.minimum(PL, PR))
+           | (du.abs() >= GATE_DU * (cL + cR)))
     ppv = 0.5 * (PL + PR) - 0.125 * du * (rL + rR) * (cL + cR)
     pmin, pmax = torch.minimum(PL, PR), torch.maximum(PL, PR)
     pv = (pmax <= 2 * pmin) & (ppv >= pmin) & (ppv <= pmax)
@@ -198,6 +206,7 @@ def main():
     ap.add_argument("--gamma", type=float, default=5.0 / 3.0)
     ap.add_argument("--steps", type=int, default=100000)
     ap.add_argument("--small", action="store_true")
+    ap.add_argument("--copy-to", default=None, help="also copy the weights and note to this directory")
     args = ap.parse_args()
     t = time.time()
     X, T, _ = build_dataset(args.gamma, small=args.small)
@@ -212,6 +221,11 @@ def main():
                                      "steps": args.steps, "validation": ev, "seconds": time.time() - t,
                                      "recipe": "paper_0901_4107_amd.learned.main"})
     print(f"saved {path}")
+    if args.copy_to:
+        import shutil
+        os.makedirs(args.copy_to, exist_ok=True)
+        for p in (path, path + ".json"):
+            shutil.copy(p, args.copy_to)
 
 
 if __name__ == "__main__":
