@@ -24,6 +24,7 @@
 #include <cstring>
 #include <vector>
 #include <omp.h>
+#include <cstdio>
 
 namespace {
 
@@ -387,7 +388,9 @@ void *vor_build(int32_t dim, int64_t n, const double *pos, int32_t nthreads) {
     if (nthreads > 0) omp_set_num_threads(nthreads);
     Grid G; G.build(pos, n, dim, 2.0);
     std::vector<CellOut> cells(n);
-    std::atomic<int64_t> bad{0};
+    std::atomic<int64_t> bad{0}, done{0};
+    // large builds (minutes) report each tenth of the cells on stderr
+    const bool report = n >= (int64_t(1) << 22);
 #pragma omp parallel
     {
         Poly3 A, B; std::vector<Cand> cands; std::vector<V3> cut; std::vector<double> sv;
@@ -396,6 +399,13 @@ void *vor_build(int32_t dim, int64_t n, const double *pos, int32_t nthreads) {
             if (dim == 3) build_cell3(G, i, A, B, cands, cut, sv, cells[i]);
             else build_cell2(G, i, cands, cells[i]);
             if (cells[i].status) bad++;
+            if (report) {
+                const int64_t d = ++done;
+                if (d % ((n + 9) / 10) == 0) {
+                    fprintf(stderr, "voronoi: %lld of %lld cells\n", (long long)d, (long long)n);
+                    fflush(stderr);
+                }
+            }
         }
     }
     Result *res = new Result();
