@@ -44,13 +44,13 @@ def flux_kernel_bytes(dim, n_cells, n_faces, mixed):
     indices, the face geometry (A, |d|, n, c) and velocity, and the flux
     written; per cell (each gathered once under ideal reuse) its
     reconstruction record (primitives, gradients, s - r). Double: all double;
-    mixed: float geometry, float w_K - w_f, double w_f, float records."""
+    mixed: float geometry and w_L - w_R, double w_f, float records."""
     nv = dim + 2
     if not mixed:
         per_face = 2 * 4 + (2 + 3 * dim) * 8 + nv * 8
         per_cell = (nv + nv * dim + dim) * 8
     else:
-        per_face = 2 * 4 + (2 + 4 * dim) * 4 + dim * 8 + nv * 8
+        per_face = 2 * 4 + (2 + 3 * dim) * 4 + dim * 8 + nv * 8
         per_cell = (nv + nv * dim + dim) * 4
     return n_faces * per_face + n_cells * per_cell, per_face, per_cell
 

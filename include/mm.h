@@ -15,12 +15,14 @@
  *   number of cells, F the number of faces.
  * - Face fluxes are double, face-major: face_flux[f*(D+2) + c] =
  *   dt * A_f * Fhat_c(f), c over (mass, momentum (D), energy).
- * - The per-cell reconstruction record (mm_gradients' output) is cell-major,
- *   MM_RECON_STRIDE(D) elements per cell (24 in 3D, 16 in 2D):
- *     [0, D+2)              primitives rho, v (D), P
- *     [D+2, (D+2)(D+1))     limited gradient, element D+2 + c*D + k = dW_c/dx_k
- *     [(D+2)(D+1), +D)      s_i - r_i (centre of mass minus generator)
- *     the rest              unused
+ * - The reconstruction buffer (mm_gradients' output) holds
+ *   MM_RECON_STRIDE(D) elements per cell (24 in 3D, 16 in 2D) as two
+ *   blocks:
+ *     primitive block P [N][8]:  rho, v (D), P, s_i - r_i (D) (centre of mass
+ *                                minus generator), padding
+ *     gradient block  G [N][16] (3D) / [N][8] (2D), starting at element 8N:
+ *                                limited gradient, element c*D + k =
+ *                                dW_c/dx_k, padding
  *   In MM_FP64 its elements are double and v is the lab-frame velocity; in
  *   MM_MIXED they are float and v holds v_i - w_i.
  * - The normal of face f points from its left cell face_L[f] to its right
@@ -155,7 +157,8 @@ mm_status mm_gradients(mm_ctx *ctx, const double *Q, void *recon);
 mm_status mm_face_fluxes(mm_ctx *ctx, double dt, const void *recon, double *face_flux);
 
 /* Step (vii): Q_L -= flux, Q_R += flux for every face (Section 3,
- * discrete update), summed per cell in a fixed order (bitwise reproducible). */
+ * discrete update), summed per cell in a fixed order (bitwise reproducible);
+ * face_flux [F][D+2] as written by mm_face_fluxes. */
 mm_status mm_apply_update(mm_ctx *ctx, const double *face_flux, double *Q);
 
 /* Steps (ii), (iii), (v), (vi), (vii) on Q in place. dt <= 0 selects the

@@ -35,6 +35,36 @@ __device__ __forceinline__ int64_t xcd_global_id() {
     return xcd_tile() * kBlock + threadIdx.x;
 }
 
+// Records of N elements moved with 16-byte accesses (one memory instruction
+// per 16 bytes, the remainder in single elements). The vector types carry
+// the element's alignment only: the hardware takes 16-byte global accesses
+// at any element-aligned address, so records need no padding to 16 bytes.
+typedef float f32x4u __attribute__((ext_vector_type(4), aligned(4)));
+typedef double f64x2u __attribute__((ext_vector_type(2), aligned(8)));
+template <typename T> struct Vec16;
+template <> struct Vec16<float> { typedef f32x4u type; static constexpr int n = 4; };
+template <> struct Vec16<double> { typedef f64x2u type; static constexpr int n = 2; };
+
+template <int N, typename T> __device__ __forceinline__ void load_rec(const T *__restrict__ p, T (&o)[N]) {
+    using V = typename Vec16<T>::type;
+    constexpr int per = Vec16<T>::n;
+    for (int i = 0; i < N / per; i++) {
+        const V v = *reinterpret_cast<const V *>(p + i * per);
+        for (int j = 0; j < per; j++) o[i * per + j] = v[j];
+    }
+    for (int k = N / per * per; k < N; k++) o[k] = p[k];
+}
+template <int N, typename T> __device__ __forceinline__ void store_rec(T *__restrict__ p, const T (&o)[N]) {
+    using V = typename Vec16<T>::type;
+    constexpr int per = Vec16<T>::n;
+    for (int i = 0; i < N / per; i++) {
+        V v;
+        for (int j = 0; j < per; j++) v[j] = o[i * per + j];
+        *reinterpret_cast<V *>(p + i * per) = v;
+    }
+    for (int k = N / per * per; k < N; k++) p[k] = o[k];
+}
+
 // A list of flagged items (hard faces or problems) split into kLists
 // sub-lists, one per residue of the producing block index, each with its
 // own counter on its own 128-byte line: appends from different blocks

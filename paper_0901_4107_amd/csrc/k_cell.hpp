@@ -67,12 +67,12 @@ __device__ __forceinline__ double block_min(double v) {
 //   rho = m/V, v = p/m, P = (g-1)(E - m v^2/2)/V,
 //   dt_i = C R_i / (c_i + |v_i - w_i|), R_i the radius of the cell's volume.
 // Cells with m <= 0 are vacuum (W = 0) and impose no timestep limit.
-// Writes the primitive part and s_i - r_i of the reconstruction record; in
-// the mixed mode (T = float) the velocity stored is v_i - w_i.
+// Writes the primitive record (W and s_i - r_i, whole); in the mixed mode
+// (T = float) the velocity stored is v_i - w_i.
 template <int D, typename T>
 __global__ void __launch_bounds__(kBlock) k_prim_cfl(int64_t n, double gamma, double cfl, const double *__restrict__ V,
                                                      const double *__restrict__ Q, const double *__restrict__ mvel,
-                                                     const double *__restrict__ coff, T *__restrict__ rec,
+                                                     const double *__restrict__ coff, T *__restrict__ prim,
                                                      double *__restrict__ dt_part) {
     using Y = Lay<D>;
     constexpr int NV = D + 2;
@@ -80,12 +80,11 @@ __global__ void __launch_bounds__(kBlock) k_prim_cfl(int64_t n, double gamma, do
     const int64_t i = xcd_global_id();
     double dti = INFINITY;
     if (i < n) {
-        T *r = rec + i * Y::REC;
+        T r[Y::PREC];
+        for (int k = 0; k < Y::PREC; k++) r[k] = (T)0;
         const double m = Q[i];
         for (int k = 0; k < D; k++) r[Y::DL + k] = (T)coff[k * n + i];
-        if (!(m > 0.0)) {
-            for (int c = 0; c < NV; c++) r[Y::W + c] = (T)0;
-        } else {
+        if (m > 0.0) {
             const double vol = V[i];
             const double inv_m = 1.0 / m;
             double v[D], ke = 0.0, rel2 = 0.0;
@@ -105,6 +104,7 @@ __global__ void __launch_bounds__(kBlock) k_prim_cfl(int64_t n, double gamma, do
                 dti = cfl * R / (sqrt(gamma * P / rho) + sqrt(rel2));
             }
         }
+        store_rec<Y::PREC>(prim + i * Y::PREC, r);
     }
     dti = block_min(dti);
     if (threadIdx.x == 0) dt_part[xcd_tile()] = dti;
@@ -142,69 +142,108 @@ __global__ void __launch_bounds__(1024) k_min_final(int64_t nparts, const double
 // (phi_max - phi_i)/max Dl, so two divisions per primitive suffice.
 // Mixed mode (T = float): velocities in the record are relative to the
 // cell's generator, so the side record's w_j - w_i restores v_j - v_i.
+// Each lane keeps its first KR sides (A/|r|, f - r_i) in registers for the
+// limiter pass and issues their loads together; sides beyond GS*KR (rare)
+// are walked by a loop that re-reads them.
+template <int D, typename T> struct SideAcc {
+    static constexpr int NV = D + 2;
+    T acc[NV][D], dmx[NV], dmn[NV];
+};
+
+template <int D, typename T, bool MIXED>
+__device__ __forceinline__ void grad_side(const T *s, const T *pj, const T *wi, SideAcc<D, T> &a) {
+    constexpr int NV = D + 2;
+    const T w = s[0];
+    for (int c = 0; c < NV; c++) {
+        T dphi = pj[c] - wi[c];
+        if (MIXED && c >= 1 && c <= D) dphi += s[1 + D + (c - 1)];
+        const T ad = w * dphi;
+        for (int k = 0; k < D; k++) a.acc[c][k] += ad * s[1 + k];
+        a.dmx[c] = dphi > a.dmx[c] ? dphi : a.dmx[c];
+        a.dmn[c] = dphi < a.dmn[c] ? dphi : a.dmn[c];
+    }
+}
+
+template <int D, typename T>
+__device__ __forceinline__ void limit_side(const T *g, const T *dl, const T (&grad)[D + 2][D], const T *tol, T *up,
+                                           T *dn) {
+    constexpr int NV = D + 2;
+    T dx[D];
+    for (int k = 0; k < D; k++) dx[k] = g[k] - dl[k];
+    for (int c = 0; c < NV; c++) {
+        T dphi = (T)0;
+        for (int k = 0; k < D; k++) dphi += grad[c][k] * dx[k];
+        if (dphi > tol[c]) up[c] = dphi > up[c] ? dphi : up[c];
+        else if (dphi < -tol[c]) dn[c] = -dphi > dn[c] ? -dphi : dn[c];
+    }
+}
+
 template <int D, typename T>
 __global__ void __launch_bounds__(kBlock) k_grad_limit(int64_t n, const int32_t *__restrict__ off,
                                                        const int32_t *__restrict__ nbr, const T *__restrict__ srec,
-                                                       const double *__restrict__ V, T *__restrict__ rec) {
+                                                       const double *__restrict__ V, const T *__restrict__ prim,
+                                                       T *__restrict__ grad_out) {
     using Y = Lay<D>;
     constexpr int NV = D + 2;
     constexpr int GS = Group<D>::GS;
+    constexpr int KR = 3;
     constexpr bool mixed = sizeof(T) == 4;
     constexpr int SR = mixed ? Y::SREC32 : Y::SREC64;
     const T eps_t = mixed ? (T)1e-6 : (T)1e-13;
     const int lane = threadIdx.x % GS;
     const int64_t i = xcd_tile() * (kBlock / GS) + threadIdx.x / GS;
     if (i >= n) return;  // whole groups leave together
-    const T *ri = rec + i * Y::REC;
-    T wi[NV], dl[D];
-    for (int c = 0; c < NV; c++) wi[c] = ri[Y::W + c];
-    for (int k = 0; k < D; k++) dl[k] = ri[Y::DL + k];
-    T acc[NV][D], dmx[NV], dmn[NV];
-    for (int c = 0; c < NV; c++) {
-        dmx[c] = (T)0;
-        dmn[c] = (T)0;
-        for (int k = 0; k < D; k++) acc[c][k] = (T)0;
-    }
     const int32_t b = off[i], e = off[i + 1];
-    for (int32_t q = b + lane; q < e; q += GS) {
-        const T *s = srec + (int64_t)q * SR;
-        const T a = s[0];
-        T g[D];
-        for (int k = 0; k < D; k++) g[k] = s[1 + k];
-        const T *rj = rec + (int64_t)nbr[q] * Y::REC;
-        for (int c = 0; c < NV; c++) {
-            T dphi = rj[Y::W + c] - wi[c];
-            if (mixed && c >= 1 && c <= D) dphi += s[1 + D + (c - 1)];
-            const T ad = a * dphi;
-            for (int k = 0; k < D; k++) acc[c][k] += ad * g[k];
-            dmx[c] = dphi > dmx[c] ? dphi : dmx[c];
-            dmn[c] = dphi < dmn[c] ? dphi : dmn[c];
-        }
+    // the lane's first KR sides: side records and neighbour indices, then
+    // the neighbours' primitive records, all in flight together (an absent
+    // side reads record 0 of the arrays and is skipped)
+    T sr[KR][SR], pj[KR][Y::PREC];
+    bool has[KR];
+    for (int r = 0; r < KR; r++) {
+        const int32_t q = b + lane + r * GS;
+        has[r] = q < e;
+        const int32_t qq = has[r] ? q : 0;
+        load_rec<SR>(srec + (int64_t)qq * SR, sr[r]);
+        load_rec<Y::PREC>(prim + (int64_t)nbr[qq] * Y::PREC, pj[r]);
+    }
+    T pi[Y::PREC];
+    load_rec<Y::PREC>(prim + i * Y::PREC, pi);
+    const T *wi = pi + Y::W, *dl = pi + Y::DL;
+    SideAcc<D, T> a;
+    for (int c = 0; c < NV; c++) {
+        a.dmx[c] = (T)0;
+        a.dmn[c] = (T)0;
+        for (int k = 0; k < D; k++) a.acc[c][k] = (T)0;
+    }
+    for (int r = 0; r < KR; r++)
+        if (has[r]) grad_side<D, T, mixed>(sr[r], pj[r] + Y::W, wi, a);
+    for (int32_t q = b + lane + KR * GS; q < e; q += GS) {
+        T s2[SR], p2[Y::PREC];
+        load_rec<SR>(srec + (int64_t)q * SR, s2);
+        load_rec<Y::PREC>(prim + (int64_t)nbr[q] * Y::PREC, p2);
+        grad_side<D, T, mixed>(s2, p2 + Y::W, wi, a);
     }
     const T inv_v = (T)(1.0 / V[i]);
+    T grad[NV][D], dmx[NV], dmn[NV];
     for (int c = 0; c < NV; c++) {
-        for (int k = 0; k < D; k++) acc[c][k] = grp_sum<GS>(acc[c][k]) * inv_v;
-        dmx[c] = grp_max<GS>(dmx[c]);
-        dmn[c] = grp_min<GS>(dmn[c]);
+        for (int k = 0; k < D; k++) grad[c][k] = grp_sum<GS>(a.acc[c][k]) * inv_v;
+        dmx[c] = grp_max<GS>(a.dmx[c]);
+        dmn[c] = grp_min<GS>(a.dmn[c]);
     }
     T up[NV], dn[NV], tol[NV];
     for (int c = 0; c < NV; c++) {
         up[c] = (T)0;
         dn[c] = (T)0;
-        const T a = wi[c] < (T)0 ? -wi[c] : wi[c];
+        const T av = wi[c] < (T)0 ? -wi[c] : wi[c];
         const T range = dmx[c] - dmn[c];
-        tol[c] = eps_t * (a > range ? a : range);
+        tol[c] = eps_t * (av > range ? av : range);
     }
-    for (int32_t q = b + lane; q < e; q += GS) {
-        const T *s = srec + (int64_t)q * SR;
-        T dx[D];
-        for (int k = 0; k < D; k++) dx[k] = s[1 + k] - dl[k];
-        for (int c = 0; c < NV; c++) {
-            T dphi = (T)0;
-            for (int k = 0; k < D; k++) dphi += acc[c][k] * dx[k];
-            if (dphi > tol[c]) up[c] = dphi > up[c] ? dphi : up[c];
-            else if (dphi < -tol[c]) dn[c] = -dphi > dn[c] ? -dphi : dn[c];
-        }
+    for (int r = 0; r < KR; r++)
+        if (has[r]) limit_side<D, T>(sr[r] + 1, dl, grad, tol, up, dn);
+    for (int32_t q = b + lane + KR * GS; q < e; q += GS) {
+        T s2[SR];
+        load_rec<SR>(srec + (int64_t)q * SR, s2);
+        limit_side<D, T>(s2 + 1, dl, grad, tol, up, dn);
     }
     T alpha[NV];
     for (int c = 0; c < NV; c++) {
@@ -216,9 +255,11 @@ __global__ void __launch_bounds__(kBlock) k_grad_limit(int64_t n, const int32_t 
         alpha[c] = al;
     }
     if (lane == 0) {
-        T *ro = rec + i * Y::REC;
+        T go[Y::GREC];
+        for (int k = 0; k < Y::GREC; k++) go[k] = (T)0;
         for (int c = 0; c < NV; c++)
-            for (int k = 0; k < D; k++) ro[Y::G + c * D + k] = alpha[c] * acc[c][k];
+            for (int k = 0; k < D; k++) go[c * D + k] = alpha[c] * grad[c][k];
+        store_rec<Y::GREC>(grad_out + i * Y::GREC, go);
     }
 }
 
@@ -229,19 +270,35 @@ template <int D>
 __global__ void __launch_bounds__(kBlock) k_update(int64_t n, const int32_t *__restrict__ off,
                                                    const int32_t *__restrict__ ent, const double *__restrict__ flux,
                                                    double *__restrict__ Q, int32_t *__restrict__ flags) {
+    using Y = Lay<D>;
     constexpr int NV = D + 2;
+    constexpr int FS = Y::FSTRIDE;
     constexpr int GS = Group<D>::GS;
+    constexpr int KR = 3;
     const int lane = threadIdx.x % GS;
     const int64_t i = xcd_tile() * (kBlock / GS) + threadIdx.x / GS;
     if (i >= n) return;
     double acc[NV];
     for (int c = 0; c < NV; c++) acc[c] = 0.0;
     const int32_t b = off[i], e = off[i + 1];
-    for (int32_t q = b + lane; q < e; q += GS) {
+    // the lane's first KR sides with their flux records in flight together
+    // (an absent side reads record 0 and adds nothing), then the rare rest
+    double F[KR][FS], sg[KR];
+    for (int r = 0; r < KR; r++) {
+        const int32_t q = b + lane + r * GS;
+        const int32_t en = q < e ? ent[q] : 0;
+        sg[r] = q < e ? ((en & 1) ? 1.0 : -1.0) : 0.0;
+        load_rec<FS>(flux + (int64_t)(en >> 1) * FS, F[r]);
+    }
+    for (int r = 0; r < KR; r++)
+        if (sg[r] != 0.0)
+            for (int c = 0; c < NV; c++) acc[c] += sg[r] * F[r][c];
+    for (int32_t q = b + lane + KR * GS; q < e; q += GS) {
         const int32_t en = ent[q];
-        const double *F = flux + (int64_t)(en >> 1) * NV;
-        const double sg = (en & 1) ? 1.0 : -1.0;
-        for (int c = 0; c < NV; c++) acc[c] += sg * F[c];
+        double Fq[FS];
+        load_rec<FS>(flux + (int64_t)(en >> 1) * FS, Fq);
+        const double s1 = (en & 1) ? 1.0 : -1.0;
+        for (int c = 0; c < NV; c++) acc[c] += s1 * Fq[c];
     }
     for (int c = 0; c < NV; c++) acc[c] = grp_sum<GS>(acc[c]);
     if (lane == 0) {

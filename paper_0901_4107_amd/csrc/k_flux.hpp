@@ -83,19 +83,33 @@ __device__ __forceinline__ void flush_diag(const LaneDiag &d, DiagDev *slots) {
 //   P''   = P   + grad P.dx    - dt/2 (v'.grad P + gamma P div v),
 // the time derivative from the primitive Euler equations at the cell's own
 // face-frame state. cen receives that unextrapolated state.
+template <int D, typename T> struct CellRec {
+    T p[Lay<D>::PREC];   // primitive record
+    T g[Lay<D>::GREC];   // gradient record
+};
+
+// Gather one cell's records with 16-byte loads.
 template <int D, typename T>
-__device__ __forceinline__ void half_step(const T *__restrict__ r, const T *vface, const T *gfr, T gamma, T hdt,
+__device__ __forceinline__ CellRec<D, T> load_cell(const T *__restrict__ prim, const T *__restrict__ grad, int64_t i) {
+    CellRec<D, T> c;
+    load_rec<Lay<D>::PREC>(prim + i * Lay<D>::PREC, c.p);
+    load_rec<Lay<D>::GREC>(grad + i * Lay<D>::GREC, c.g);
+    return c;
+}
+
+template <int D, typename T>
+__device__ __forceinline__ void half_step(const CellRec<D, T> &r, const T *vface, const T *gfr, T gamma, T hdt,
                                           T out[D + 2], T cen[D + 2]) {
     using Y = Lay<D>;
     constexpr int NV = D + 2;
     T g[NV][D], dx[D], v[D];
     for (int c = 0; c < NV; c++)
-        for (int k = 0; k < D; k++) g[c][k] = r[Y::G + c * D + k];
+        for (int k = 0; k < D; k++) g[c][k] = r.g[c * D + k];
     for (int k = 0; k < D; k++) {
-        dx[k] = gfr[k] - r[Y::DL + k];
+        dx[k] = gfr[k] - r.p[Y::DL + k];
         v[k] = vface[k];
     }
-    const T rho = r[Y::W], P = r[Y::W + NV - 1];
+    const T rho = r.p[Y::W], P = r.p[Y::W + NV - 1];
     T div = (T)0;
     for (int k = 0; k < D; k++) div += g[1 + k][k];
     T s = (T)0, t = (T)0;
@@ -252,11 +266,12 @@ __device__ __forceinline__ T learned_guess(const MlpPacked *P, bool want, T rhoL
 
 // Lab-frame moving-face flux in double from the sampled face-frame state
 // (rho_F, u_F, P_F), the upwind transverse velocity tv, the normal n and
-// the face velocity w.
+// the face velocity w; stores the face's flux record.
 template <int D>
 __device__ __forceinline__ void lab_flux(double rho, double u, double P, const double *tv, const double *nrm,
-                                         const double *w, double g_over_gm1, double scale, double *out) {
+                                         const double *w, double g_over_gm1, double scale, double *rec_out) {
     constexpr int NV = D + 2;
+    double out[Lay<D>::FSTRIDE];
     const double mf = rho * u;
     double v2 = 0.0, w2 = 0.0, Piw = 0.0, Pi[D];
     for (int k = 0; k < D; k++) {
@@ -270,6 +285,7 @@ __device__ __forceinline__ void lab_flux(double rho, double u, double P, const d
     out[0] = scale * mf;
     for (int k = 0; k < D; k++) out[1 + k] = scale * (Pi[k] + mf * w[k]);
     out[NV - 1] = scale * (eps + Piw + 0.5 * mf * w2);
+    store_rec<Lay<D>::FSTRIDE>(rec_out, out);
 }
 
 // Double-precision face flux. LEARNED compiles the fused network in; the
@@ -277,8 +293,9 @@ __device__ __forceinline__ void lab_flux(double rho, double u, double P, const d
 template <int D, bool LEARNED>
 __global__ void __launch_bounds__(kBlock) k_face_flux64(int64_t nf, const int32_t *__restrict__ fL,
                                                         const int32_t *__restrict__ fR, const double *__restrict__ frec,
-                                                        const double *__restrict__ rec, const double *__restrict__ dt_ptr,
-                                                        double dt_val, GasConst<double> kg, double tol, int maxit,
+                                                        const double *__restrict__ prim, const double *__restrict__ grad,
+                                                        const double *__restrict__ dt_ptr, double dt_val,
+                                                        GasConst<double> kg, double tol, int maxit,
                                                         const MlpPacked *mlp, double *__restrict__ flux, DiagDev *diag) {
     using Y = Lay<D>;
     constexpr int NV = D + 2;
@@ -290,7 +307,10 @@ __global__ void __launch_bounds__(kBlock) k_face_flux64(int64_t nf, const int32_
     for (int c = 0; c < NV; c++) { xl[c] = 1.0; xr[c] = 1.0; }
     if (active) {
         const double hdt = 0.5 * dt;
-        const double *fr = frec + f * Y::FREC;
+        double fr[Y::FREC];
+        load_rec<Y::FREC>(frec + f * Y::FREC, fr);
+        const CellRec<D, double> rl = load_cell<D>(prim, grad, fL[f]);
+        const CellRec<D, double> rr = load_cell<D>(prim, grad, fR[f]);
         A = fr[Y::FA];
         const double hl = 0.5 * fr[Y::FELL];
         double gL[D], gR[D];
@@ -301,12 +321,10 @@ __global__ void __launch_bounds__(kBlock) k_face_flux64(int64_t nf, const int32_
             gL[k] = c + hl * nrm[k];   // f - r_L
             gR[k] = c - hl * nrm[k];   // f - r_R
         }
-        const double *rl = rec + (int64_t)fL[f] * Y::REC;
-        const double *rr = rec + (int64_t)fR[f] * Y::REC;
         double cl[NV], cr[NV], vf[D];
-        for (int k = 0; k < D; k++) vf[k] = rl[Y::W + 1 + k] - w[k];
+        for (int k = 0; k < D; k++) vf[k] = rl.p[Y::W + 1 + k] - w[k];
         half_step<D, double>(rl, vf, gL, kg.g, hdt, xl, cl);
-        for (int k = 0; k < D; k++) vf[k] = rr[Y::W + 1 + k] - w[k];
+        for (int k = 0; k < D; k++) vf[k] = rr.p[Y::W + 1 + k] - w[k];
         half_step<D, double>(rr, vf, gR, kg.g, hdt, xr, cr);
         if (!(xl[0] > 0.0 && xl[NV - 1] > 0.0 && xr[0] > 0.0 && xr[NV - 1] > 0.0)) {
             for (int c = 0; c < NV; c++) { xl[c] = cl[c]; xr[c] = cr[c]; }
@@ -328,7 +346,7 @@ __global__ void __launch_bounds__(kBlock) k_face_flux64(int64_t nf, const int32_
         const double un = fs.side ? uR : uL;
         double tv[D];
         for (int k = 0; k < D; k++) tv[k] = xs[1 + k] - un * nrm[k];
-        lab_flux<D>(fs.rho, fs.u, fs.P, tv, nrm, w, kg.g_over_gm1, dt * A, flux + f * NV);
+        lab_flux<D>(fs.rho, fs.u, fs.P, tv, nrm, w, kg.g_over_gm1, dt * A, flux + f * Y::FSTRIDE);
     }
     if (diag) flush_diag(ld, diag);
 }
@@ -346,25 +364,31 @@ template <int D>
 __device__ __forceinline__ MixedFace<D> mixed_face_states(int64_t f, const int32_t *__restrict__ fL,
                                                           const int32_t *__restrict__ fR,
                                                           const float *__restrict__ mrec,
-                                                          const float *__restrict__ rec, float hdt, float gam) {
+                                                          const float *__restrict__ prim,
+                                                          const float *__restrict__ grad, float hdt, float gam) {
     using Y = Lay<D>;
     constexpr int NV = D + 2;
     MixedFace<D> o;
-    const float *fr = mrec + f * Y::MREC;
+    float fr[Y::MREC];
+    load_rec<Y::MREC>(mrec + f * Y::MREC, fr);
+    const CellRec<D, float> rl = load_cell<D>(prim, grad, fL[f]);
+    const CellRec<D, float> rr = load_cell<D>(prim, grad, fR[f]);
     o.A = fr[Y::FA];
     const float hl = 0.5f * fr[Y::FELL];
-    float gL[D], gR[D], cl[NV], cr[NV], vf[D];
+    float gL[D], gR[D], cl[NV], cr[NV], vf[D], dw[D], proj = 0.0f;
     for (int k = 0; k < D; k++) {
         o.nrm[k] = fr[Y::FN + k];
         const float c = fr[Y::FC + k];
         gL[k] = c + hl * o.nrm[k];
         gR[k] = c - hl * o.nrm[k];
+        dw[k] = fr[Y::MDW + k];
+        proj += dw[k] * c;
     }
-    const float *rl = rec + (int64_t)fL[f] * Y::REC;
-    const float *rr = rec + (int64_t)fR[f] * Y::REC;
-    for (int k = 0; k < D; k++) vf[k] = rl[Y::W + 1 + k] + fr[Y::MDWL + k];
+    // w_L - w_f = dw/2 - (dw.c/|d|) n and w_R - w_f = -dw/2 - (dw.c/|d|) n
+    proj *= 0.5f / hl;
+    for (int k = 0; k < D; k++) vf[k] = rl.p[Y::W + 1 + k] + (0.5f * dw[k] - proj * o.nrm[k]);
     half_step<D, float>(rl, vf, gL, gam, hdt, o.xl, cl);
-    for (int k = 0; k < D; k++) vf[k] = rr[Y::W + 1 + k] + fr[Y::MDWR + k];
+    for (int k = 0; k < D; k++) vf[k] = rr.p[Y::W + 1 + k] + (-0.5f * dw[k] - proj * o.nrm[k]);
     half_step<D, float>(rr, vf, gR, gam, hdt, o.xr, cr);
     o.posfb = !(o.xl[0] > 0.0f && o.xl[NV - 1] > 0.0f && o.xr[0] > 0.0f && o.xr[NV - 1] > 0.0f);
     if (o.posfb)
@@ -382,11 +406,12 @@ __device__ __forceinline__ void mixed_lab_flux(const MixedFace<D> &m, double rho
     using Y = Lay<D>;
     const float *xs = side ? m.xr : m.xl;
     const float un = side ? m.uR : m.uL;
-    double tv[D], nd[D], w[D];
+    double tv[D], nd[D], wr[Y::WSTRIDE];
+    load_rec<Y::WSTRIDE>(wf64 + f * Y::WSTRIDE, wr);
+    const double *w = wr;
     for (int k = 0; k < D; k++) {
         tv[k] = (double)(xs[1 + k] - un * m.nrm[k]);
         nd[k] = (double)m.nrm[k];
-        w[k] = wf64[f * Y::WSTRIDE + k];
     }
     lab_flux<D>(rho, u, P, tv, nd, w, g_over_gm1, dt * (double)m.A, out);
 }
@@ -401,7 +426,8 @@ __global__ void __launch_bounds__(kBlock) k_face_flux_mixed(int64_t nf, const in
                                                             const int32_t *__restrict__ fR,
                                                             const float *__restrict__ mrec,
                                                             const double *__restrict__ wf64,
-                                                            const float *__restrict__ rec,
+                                                            const float *__restrict__ prim,
+                                                            const float *__restrict__ grad,
                                                             const double *__restrict__ dt_ptr, double dt_val,
                                                             GasConst<float> kf, double g_over_gm1, float tol32,
                                                             int maxit, const MlpPacked *mlp,
@@ -416,7 +442,7 @@ __global__ void __launch_bounds__(kBlock) k_face_flux_mixed(int64_t nf, const in
     const double dt = dt_ptr ? *dt_ptr : dt_val;
     MixedFace<D> m;
     if (active) {
-        m = mixed_face_states<D>(f, fL, fR, mrec, rec, (float)(0.5 * dt), kf.g);
+        m = mixed_face_states<D>(f, fL, fR, mrec, prim, grad, (float)(0.5 * dt), kf.g);
         ld.posfb = m.posfb;
     } else {
         for (int c = 0; c < NV; c++) { m.xl[c] = 1.0f; m.xr[c] = 1.0f; }
@@ -433,7 +459,8 @@ __global__ void __launch_bounds__(kBlock) k_face_flux_mixed(int64_t nf, const in
     if (active) {
         FaceState<float> fs = solve_face<float>(m.xl[0], m.uL, m.xl[NV - 1], m.xr[0], m.uR, m.xr[NV - 1], kf, tol32,
                                                 maxit, pl, true, ld, hard);
-        if (!hard) mixed_lab_flux<D>(m, fs.rho, fs.u, fs.P, fs.side, wf64, f, g_over_gm1, dt, flux + f * NV);
+        if (!hard)
+            mixed_lab_flux<D>(m, fs.rho, fs.u, fs.P, fs.side, wf64, f, g_over_gm1, dt, flux + f * Lay<D>::FSTRIDE);
     }
     list_append(hard_list, cap, hard, (int32_t)f);
     if (diag) flush_diag(ld, diag);
@@ -448,7 +475,8 @@ __global__ void __launch_bounds__(kBlock) k_face_flux_hard(const int32_t *__rest
                                                            const int32_t *__restrict__ fR,
                                                            const float *__restrict__ mrec,
                                                            const double *__restrict__ wf64,
-                                                           const float *__restrict__ rec,
+                                                           const float *__restrict__ prim,
+                                                           const float *__restrict__ grad,
                                                            const double *__restrict__ dt_ptr, double dt_val,
                                                            float gam, GasConst<double> kg, double tol64,
                                                            const int32_t *__restrict__ hard_list, int64_t cap,
@@ -459,12 +487,12 @@ __global__ void __launch_bounds__(kBlock) k_face_flux_hard(const int32_t *__rest
     LaneDiag ld;
     for (int64_t q = lw.start; q < lw.count; q += lw.stride) {
         const int64_t f = lw.items[q];
-        const MixedFace<D> m = mixed_face_states<D>(f, fL, fR, mrec, rec, (float)(0.5 * dt), gam);
+        const MixedFace<D> m = mixed_face_states<D>(f, fL, fR, mrec, prim, grad, (float)(0.5 * dt), gam);
         bool h2;
         FaceState<double> fd = solve_face<double>(m.xl[0], m.uL, m.xl[NV - 1], m.xr[0], m.uR, m.xr[NV - 1], kg,
                                                   tol64, 50, no_guess<double>(), false, ld, h2);
         ld.fp64fb += 1;
-        mixed_lab_flux<D>(m, fd.rho, fd.u, fd.P, fd.side, wf64, f, kg.g_over_gm1, dt, flux + f * NV);
+        mixed_lab_flux<D>(m, fd.rho, fd.u, fd.P, fd.side, wf64, f, kg.g_over_gm1, dt, flux + f * Lay<D>::FSTRIDE);
     }
     if (diag) flush_diag(ld, diag);
 }

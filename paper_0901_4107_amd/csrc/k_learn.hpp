@@ -269,13 +269,15 @@ template <int D>
 __global__ void __launch_bounds__(kBlock) k_face_states64(int64_t nf, const int32_t *__restrict__ fL,
                                                           const int32_t *__restrict__ fR,
                                                           const double *__restrict__ frec,
-                                                          const double *__restrict__ rec, double dt, double gamma,
+                                                          const double *__restrict__ prim,
+                                                          const double *__restrict__ grad, double dt, double gamma,
                                                           float *__restrict__ out) {
     using Y = Lay<D>;
     constexpr int NV = D + 2;
     const int64_t f = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (f >= nf) return;
-    const double *fr = frec + f * Y::FREC;
+    double fr[Y::FREC];
+    load_rec<Y::FREC>(frec + f * Y::FREC, fr);
     const double hl = 0.5 * fr[Y::FELL];
     double nrm[D], w[D], gL[D], gR[D];
     for (int k = 0; k < D; k++) {
@@ -284,12 +286,12 @@ __global__ void __launch_bounds__(kBlock) k_face_states64(int64_t nf, const int3
         gL[k] = fr[Y::FC + k] + hl * nrm[k];
         gR[k] = fr[Y::FC + k] - hl * nrm[k];
     }
-    const double *rl = rec + (int64_t)fL[f] * Y::REC;
-    const double *rr = rec + (int64_t)fR[f] * Y::REC;
+    const CellRec<D, double> rl = load_cell<D>(prim, grad, fL[f]);
+    const CellRec<D, double> rr = load_cell<D>(prim, grad, fR[f]);
     double xl[NV], xr[NV], cl[NV], cr[NV], vf[D];
-    for (int k = 0; k < D; k++) vf[k] = rl[Y::W + 1 + k] - w[k];
+    for (int k = 0; k < D; k++) vf[k] = rl.p[Y::W + 1 + k] - w[k];
     half_step<D, double>(rl, vf, gL, gamma, 0.5 * dt, xl, cl);
-    for (int k = 0; k < D; k++) vf[k] = rr[Y::W + 1 + k] - w[k];
+    for (int k = 0; k < D; k++) vf[k] = rr.p[Y::W + 1 + k] - w[k];
     half_step<D, double>(rr, vf, gR, gamma, 0.5 * dt, xr, cr);
     if (!(xl[0] > 0.0 && xl[NV - 1] > 0.0 && xr[0] > 0.0 && xr[NV - 1] > 0.0))
         for (int c = 0; c < NV; c++) { xl[c] = cl[c]; xr[c] = cr[c]; }

@@ -183,7 +183,6 @@ __global__ void __launch_bounds__(kBlock) k_face_records(int64_t n, int64_t nf, 
         w[k] = 0.5 * (wl[k] + wr[k]) + proj * d[k] / s2;
         o[Y::FW + k] = w[k];
     }
-    for (int k = Y::FW + D; k < Y::FREC; k++) o[k] = 0.0;
     if (mixed) {
         float *m = mrec + f * Y::MREC;
         m[Y::FA] = (float)area[f];
@@ -191,12 +190,10 @@ __global__ void __launch_bounds__(kBlock) k_face_records(int64_t n, int64_t nf, 
         for (int k = 0; k < D; k++) {
             m[Y::FN + k] = (float)(d[k] * inv);
             m[Y::FC + k] = (float)c[k];
-            m[Y::MDWL + k] = (float)(wl[k] - w[k]);
-            m[Y::MDWR + k] = (float)(wr[k] - w[k]);
+            m[Y::MDW + k] = (float)(wl[k] - wr[k]);
             wf64[f * Y::WSTRIDE + k] = w[k];
         }
-        for (int k = Y::MDWR + D; k < Y::MREC; k++) m[k] = 0.0f;
-        for (int k = D; k < Y::WSTRIDE; k++) wf64[f * Y::WSTRIDE + k] = 0.0;
+
     }
 }
 

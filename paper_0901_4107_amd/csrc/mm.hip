@@ -58,7 +58,7 @@ Layout make_layout(int D, int mode, int64_t n, int64_t nf) {
     L.ent = take(2 * nf * sizeof(int32_t));
     L.nbr = take(2 * nf * sizeof(int32_t));
     L.frec = take(nf * FREC * sizeof(double));
-    L.flux = take(nf * NV * sizeof(double));
+    L.flux = take(nf * ((D == 3) ? Lay<3>::FSTRIDE : Lay<2>::FSTRIDE) * sizeof(double));
     L.srec = take(2 * nf * Lay<3>::SREC64 * sizeof(double));
     L.srec32 = L.mrec = L.wf64 = L.rec32 = L.rec = L.hard = -1;
     if (mode == MM_FP64) {
@@ -273,6 +273,10 @@ mm_status mm_mesh_upload(mm_ctx *c, const mm_mesh *m) {
     return clear_diag(c);
 }
 
+// The reconstruction buffer holds the primitive block [N][PREC] followed by
+// the gradient block [N][GREC].
+template <int D, typename T> static T *grad_block(const mm_ctx *c, T *rec) { return rec + c->n * Lay<D>::PREC; }
+
 template <int D, typename T> static mm_status gradients_t(mm_ctx *c, const double *Q, T *rec, double *dt_part) {
     const Layout &L = c->lay;
     hipStream_t s = c->st();
@@ -280,7 +284,7 @@ template <int D, typename T> static mm_status gradients_t(mm_ctx *c, const doubl
     k_prim_cfl<D, T><<<grid_for(c->n), kBlock, 0, s>>>(c->n, c->p.gamma, c->p.cfl, c->mesh.volume, Q,
                                                       c->mesh.mesh_vel, c->mesh.centroid_off, rec, dt_part);
     k_grad_limit<D, T><<<group_grid(D, c->n), kBlock, 0, s>>>(c->n, c->at<int32_t>(L.off), c->at<int32_t>(L.nbr),
-                                                              srec, c->mesh.volume, rec);
+                                                              srec, c->mesh.volume, rec, grad_block<D>(c, rec));
     MM_LAUNCH_CHECK();
     return MM_OK;
 }
@@ -308,20 +312,23 @@ static mm_status fluxes_t(mm_ctx *c, const double *dt_dev, double dt, const void
     const GasConst<float> kf(c->p.gamma);
     if (c->p.mode == MM_FP64) {
         auto kern = mlp ? k_face_flux64<D, true> : k_face_flux64<D, false>;
-        kern<<<grid_for(c->nf), kBlock, 0, s>>>(c->nf, c->mesh.face_L, c->mesh.face_R, c->at<double>(L.frec),
-                                                (const double *)rec, dt_dev, dt, kg, c->p.newton_tol64,
+        const double *prim = (const double *)rec;
+        kern<<<grid_for(c->nf), kBlock, 0, s>>>(c->nf, c->mesh.face_L, c->mesh.face_R, c->at<double>(L.frec), prim,
+                                                grad_block<D>(c, prim), dt_dev, dt, kg, c->p.newton_tol64,
                                                 c->p.newton_max_iter, mlp, flux, diag);
     } else {
         int32_t *hard = c->at<int32_t>(L.hard);
         const int64_t cap = list_cap(grid_for(c->nf));
         k_fill_i32<<<kLists * kListPad / kBlock, kBlock, 0, s>>>(hard, kLists * kListPad, 0);
         auto kern = mlp ? k_face_flux_mixed<D, true> : k_face_flux_mixed<D, false>;
+        const float *prim = (const float *)rec;
         kern<<<grid_for(c->nf), kBlock, 0, s>>>(c->nf, c->mesh.face_L, c->mesh.face_R, c->at<float>(L.mrec),
-                                                c->at<double>(L.wf64), (const float *)rec, dt_dev, dt, kf,
+                                                c->at<double>(L.wf64), prim, grad_block<D>(c, prim), dt_dev, dt, kf,
                                                 kg.g_over_gm1, (float)c->p.newton_tol32, c->p.newton_max_iter, mlp,
                                                 flux, hard, cap, diag);
         k_face_flux_hard<D><<<kHardGrid, kBlock, 0, s>>>(c->mesh.face_L, c->mesh.face_R, c->at<float>(L.mrec),
-                                                        c->at<double>(L.wf64), (const float *)rec, dt_dev, dt, kf.g,
+                                                        c->at<double>(L.wf64), prim, grad_block<D>(c, prim), dt_dev,
+                                                        dt, kf.g,
                                                         kg, c->p.newton_tol64, hard, cap, flux, diag);
     }
     MM_LAUNCH_CHECK();
@@ -486,13 +493,13 @@ mm_status mm_face_states(mm_ctx *c, double dt, const void *recon, float *out) {
     if (c->p.mode != MM_FP64) return MM_E_ARG;
     if (!c->have_mesh) return MM_E_STATE;
     if (c->D == 3)
-        k_face_states64<3><<<plain_grid(c->nf), kBlock, 0, c->st()>>>(c->nf, c->mesh.face_L, c->mesh.face_R,
-                                                                      c->at<double>(c->lay.frec),
-                                                                      (const double *)recon, dt, c->p.gamma, out);
+        k_face_states64<3><<<plain_grid(c->nf), kBlock, 0, c->st()>>>(
+            c->nf, c->mesh.face_L, c->mesh.face_R, c->at<double>(c->lay.frec), (const double *)recon,
+            grad_block<3>(c, (const double *)recon), dt, c->p.gamma, out);
     else
-        k_face_states64<2><<<plain_grid(c->nf), kBlock, 0, c->st()>>>(c->nf, c->mesh.face_L, c->mesh.face_R,
-                                                                      c->at<double>(c->lay.frec),
-                                                                      (const double *)recon, dt, c->p.gamma, out);
+        k_face_states64<2><<<plain_grid(c->nf), kBlock, 0, c->st()>>>(
+            c->nf, c->mesh.face_L, c->mesh.face_R, c->at<double>(c->lay.frec), (const double *)recon,
+            grad_block<2>(c, (const double *)recon), dt, c->p.gamma, out);
     MM_LAUNCH_CHECK();
     return MM_OK;
 }

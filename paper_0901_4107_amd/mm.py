@@ -237,10 +237,11 @@ class Context:
 
 
     def recon_buffer(self, n_cells: int):
-        """Reconstruction records [N][MM_RECON_STRIDE] for mm_gradients in
-        this context's mode (double in MM_FP64, float in MM_MIXED)."""
+        """Reconstruction buffer for mm_gradients in this context's mode
+        (double in MM_FP64, float in MM_MIXED): N * MM_RECON_STRIDE elements,
+        the primitive block [N][8] then the gradient block [N][16 or 8]."""
         dt = torch.float64 if self.mode == MM_FP64 else torch.float32
-        return torch.empty((n_cells, recon_stride(self.dim)), dtype=dt, device=self.device)
+        return torch.empty(n_cells * recon_stride(self.dim), dtype=dt, device=self.device)
 
     def flux_buffer(self, n_faces: int):
         """Face fluxes [F][D+2] (double)."""
@@ -272,11 +273,16 @@ def mm_mlp_adam(params, grad, m1, m2, lr, beta1, beta2, eps, step, stream=None):
                                             step, _stream_ptr(stream)))
 
 def recon_stride(dim: int) -> int:
+    """MM_RECON_STRIDE: elements per cell of the reconstruction buffer."""
     return 24 if dim == 3 else 16
 
 
 def split_recon(rec, dim: int):
-    """(W [D+2][N], G [(D+2)*D][N], s - r [D][N]) views of reconstruction
-    records in the oracle's structure-of-arrays layout (numpy or torch)."""
+    """(W [D+2][N], G [(D+2)*D][N], s - r [D][N]) views of a reconstruction
+    buffer in the oracle's structure-of-arrays layout (numpy or torch)."""
     nv = dim + 2
-    return rec[:, :nv].T, rec[:, nv:nv + nv * dim].T, rec[:, nv + nv * dim:nv + nv * dim + dim].T
+    n = rec.shape[0] // recon_stride(dim)
+    grec = 16 if dim == 3 else 8
+    prim = rec[:n * 8].reshape(n, 8)
+    grad = rec[n * 8:].reshape(n, grec)
+    return prim[:, :nv].T, grad[:, :nv * dim].T, prim[:, nv:nv + dim].T
