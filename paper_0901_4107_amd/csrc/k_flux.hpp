@@ -216,21 +216,21 @@ __device__ __forceinline__ bool wants_learned(T rhoL, T uL, T PL, T rhoR, T uR, 
 
 // Block-wide staging of the learned guess: the problems of a block that
 // want the network are compacted, so only ceil(count / 64) wavefronts
-// evaluate it, each for 64 problems.
+// evaluate it, each for 64 problems. Every thread of the block takes part
+// in each phase (they hold barriers):
+//   learn_count  how many threads of the block want the network (the same
+//                for the whole block), and this thread's slot among them;
+//   learn_put    a wanting thread stores its features in its slot;
+//   learn_run    the network over the stored features;
+//   learn_get    the network's ln(p* / p_standard) for a wanting thread
+//                (NaN when out of range or not wanted).
 struct LearnLds {
     float x[3][kBlock];
     float y[kBlock];
     int cnt[kBlock / 64];
 };
 
-// The learned guess for the problems of a block. Every thread of the block
-// must call it (it holds barriers); threads with want = false get NaN. The
-// result is the network's ln(p* / p_standard), or NaN when out of range.
-template <typename T>
-__device__ __forceinline__ T learned_guess(const MlpPacked *P, bool want, T rhoL, T uL, T PL, T rhoR, T uR, T PR,
-                                           float gamma) {
-    __shared__ LearnLds sh;
-    if (P == nullptr) return no_guess<T>();
+__device__ __forceinline__ int learn_count(LearnLds &sh, bool want, int &slot) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const unsigned long long m = __ballot(want);
     if (lane == 0) sh.cnt[wv] = __popcll(m);
@@ -241,16 +241,23 @@ __device__ __forceinline__ T learned_guess(const MlpPacked *P, bool want, T rhoL
         base += w < wv ? c : 0;
         total += c;
     }
-    if (total == 0) return no_guess<T>();   // the same for the whole block
-    const int slot = base + __popcll(m & ((1ull << lane) - 1ull));
-    if (want) {
-        float x0, x1, x2;
-        mlp_features((float)rhoL, (float)uL, (float)PL, (float)rhoR, (float)uR, (float)PR, gamma, x0, x1, x2);
-        sh.x[0][slot] = x0;
-        sh.x[1][slot] = x1;
-        sh.x[2][slot] = x2;
-    }
+    slot = base + __popcll(m & ((1ull << lane) - 1ull));
+    return total;
+}
+
+template <typename T>
+__device__ __forceinline__ void learn_put(LearnLds &sh, int slot, T rhoL, T uL, T PL, T rhoR, T uR, T PR,
+                                          float gamma) {
+    float x0, x1, x2;
+    mlp_features((float)rhoL, (float)uL, (float)PL, (float)rhoR, (float)uR, (float)PR, gamma, x0, x1, x2);
+    sh.x[0][slot] = x0;
+    sh.x[1][slot] = x1;
+    sh.x[2][slot] = x2;
+}
+
+__device__ __forceinline__ void learn_run(LearnLds &sh, const MlpPacked *P, int total) {
     __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     if (wv * 64 < total) {   // uniform per wavefront
         const int k = wv * 64 + lane;
         const bool ok = k < total;
@@ -258,10 +265,28 @@ __device__ __forceinline__ T learned_guess(const MlpPacked *P, bool want, T rhoL
         if (ok) sh.y[k] = y;
     }
     __syncthreads();
+}
+
+template <typename T> __device__ __forceinline__ T learn_get(const LearnLds &sh, bool want, int slot) {
     if (!want) return no_guess<T>();
     // the network predicts ln(p* / p_standard) / kMlpScaleY
     const float corr = kMlpScaleY * sh.y[slot];
     return (corr > -20.0f && corr < 20.0f) ? (T)corr : no_guess<T>();
+}
+
+// The learned guess for the problems of a block in one call (every thread
+// of the block calls it); NaN for threads with want = false.
+template <typename T>
+__device__ __forceinline__ T learned_guess(const MlpPacked *P, bool want, T rhoL, T uL, T PL, T rhoR, T uR, T PR,
+                                           float gamma) {
+    __shared__ LearnLds sh;
+    if (P == nullptr) return no_guess<T>();
+    int slot;
+    const int total = learn_count(sh, want, slot);
+    if (total == 0) return no_guess<T>();   // the same for the whole block
+    if (want) learn_put<T>(sh, slot, rhoL, uL, PL, rhoR, uR, PR, gamma);
+    learn_run(sh, P, total);
+    return learn_get<T>(sh, want, slot);
 }
 
 // Lab-frame moving-face flux in double from the sampled face-frame state
@@ -449,12 +474,32 @@ __global__ void __launch_bounds__(kBlock) k_face_flux_mixed(int64_t nf, const in
         m.uL = 0.0f;
         m.uR = 0.0f;
     }
-    // learned guess: the whole wavefront evaluates the network together
+    // learned guess for the block's compacted problems. While the network
+    // runs, the face states wait in LDS, so the network's registers come
+    // on top of few live values.
     float pl = no_guess<float>();
     if constexpr (LEARNED) {
+        __shared__ LearnLds sh;
+        __shared__ float stash[2 * NV + D + 1][kBlock];
         const bool want =
             active && wants_learned<float>(m.xl[0], m.uL, m.xl[NV - 1], m.xr[0], m.uR, m.xr[NV - 1], kf.g);
-        pl = learned_guess<float>(mlp, want, m.xl[0], m.uL, m.xl[NV - 1], m.xr[0], m.uR, m.xr[NV - 1], kf.g);
+        int slot = 0;
+        const int total = mlp ? learn_count(sh, want, slot) : 0;
+        if (total > 0) {   // the same for the whole block
+            if (want) learn_put<float>(sh, slot, m.xl[0], m.uL, m.xl[NV - 1], m.xr[0], m.uR, m.xr[NV - 1], kf.g);
+            const int t = threadIdx.x;
+            for (int c = 0; c < NV; c++) { stash[c][t] = m.xl[c]; stash[NV + c][t] = m.xr[c]; }
+            for (int k = 0; k < D; k++) stash[2 * NV + k][t] = m.nrm[k];
+            stash[2 * NV + D][t] = m.A;
+            learn_run(sh, mlp, total);
+            pl = learn_get<float>(sh, want, slot);
+            for (int c = 0; c < NV; c++) { m.xl[c] = stash[c][t]; m.xr[c] = stash[NV + c][t]; }
+            for (int k = 0; k < D; k++) m.nrm[k] = stash[2 * NV + k][t];
+            m.A = stash[2 * NV + D][t];
+            m.uL = 0.0f;
+            m.uR = 0.0f;
+            for (int k = 0; k < D; k++) { m.uL += m.xl[1 + k] * m.nrm[k]; m.uR += m.xr[1 + k] * m.nrm[k]; }
+        }
     }
     if (active) {
         FaceState<float> fs = solve_face<float>(m.xl[0], m.uL, m.xl[NV - 1], m.xr[0], m.uR, m.xr[NV - 1], kf, tol32,

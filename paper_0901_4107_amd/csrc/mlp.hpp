@@ -81,57 +81,65 @@ __device__ __forceinline__ void mlp_features(float rhoL, float uL, float PL, flo
 
 // Whole-wavefront inference: every lane of the wave must call this (full
 // exec mask); lane l supplies the features of its face and receives y.
-// Each weight is read once per wavefront: layer 1 runs for the four column
-// tiles, then layer 2 and 3 one output tile at a time over all columns. The
-// scheduling barriers keep each tile's weight loads next to their use, so
-// at most one tile of weights is live on top of the hidden activations.
+// The four 16-face column tiles go in two passes of two: layer 1 for the
+// pass's columns, then layers 2 and 3 one output tile at a time. Each weight
+// is read twice per wavefront (L1 hits); the scheduling barriers keep each
+// tile's weight loads next to their use, so the network adds few registers
+// to the flux code's.
 __device__ __forceinline__ float mlp_wave_infer(const MlpPacked *__restrict__ P, float x0, float x1, float x2) {
     const int lane = threadIdx.x & 63;
     const int src = lane & 15;
     const bool low = lane < 16;
     const int rbase = 4 * (lane >> 4);
-    // layer 1 -> relu -> bf16; h1[s][n] is the B operand of k-step s of
-    // layer 2 for column tile n (faces 16n..16n+15): tiles 2s and 2s+1
-    // side by side
-    bf16x8_t h1[2][4];
-    bf16x4_t a1[4];
-    for (int t = 0; t < 4; t++) a1[t] = P->a1[t][lane];
-    for (int n = 0; n < 4; n++) {
-        const float a = __shfl(x0, 16 * n + src, 64);
-        const float b = __shfl(x1, 16 * n + src, 64);
-        const float c = __shfl(x2, 16 * n + src, 64);
-        bf16x4_t xb;
-        xb[0] = low ? f2bf(a) : (short)0;
-        xb[1] = low ? f2bf(b) : (short)0;
-        xb[2] = low ? f2bf(c) : (short)0;
-        xb[3] = low ? f2bf(1.0f) : (short)0;
+    float yy = 0.0f;
+#pragma unroll 1
+    for (int pass = 0; pass < 2; pass++) {
+        // the weights are re-read in each pass rather than held in
+        // registers across both: the empty asm makes the offset opaque, so
+        // the loads stay inside the pass
+        int zero = 0;
+        asm volatile("" : "+s"(zero));
+        const MlpPacked *Q = P + zero;
+        // layer 1 -> relu -> bf16; h1[s][j] is the B operand of k-step s of
+        // layer 2 for column tile 2 pass + j: tiles 2s and 2s+1 side by side
+        bf16x8_t h1[2][2];
+        for (int j = 0; j < 2; j++) {
+            const int n = 2 * pass + j;
+            const float a = __shfl(x0, 16 * n + src, 64);
+            const float b = __shfl(x1, 16 * n + src, 64);
+            const float c = __shfl(x2, 16 * n + src, 64);
+            bf16x4_t xb;
+            xb[0] = low ? f2bf(a) : (short)0;
+            xb[1] = low ? f2bf(b) : (short)0;
+            xb[2] = low ? f2bf(c) : (short)0;
+            xb[3] = low ? f2bf(1.0f) : (short)0;
+            for (int t = 0; t < 4; t++) {
+                f32x4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(Q->a1[t][lane], xb, acc, 0, 0, 0);
+                for (int i = 0; i < 4; i++) h1[t >> 1][j][4 * (t & 1) + i] = (__bf16)relu(acc[i]);
+            }
+        }
+        // layer 2 (+ b2, relu) and layer 3 (w3 dot), one output tile at a time
+        float yp[2] = {0.0f, 0.0f};
         for (int t = 0; t < 4; t++) {
-            f32x4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1[t], xb, acc, 0, 0, 0);
-            for (int i = 0; i < 4; i++) h1[t >> 1][n][4 * (t & 1) + i] = (__bf16)relu(acc[i]);
+            __builtin_amdgcn_sched_barrier(0);
+            const bf16x8_t w0 = Q->a2[t][0][lane], w1 = Q->a2[t][1][lane];
+            const f32x4_t bias = *reinterpret_cast<const f32x4_t *>(Q->b2 + 16 * t + rbase);
+            const f32x4_t w3 = *reinterpret_cast<const f32x4_t *>(Q->w3 + 16 * t + rbase);
+            for (int j = 0; j < 2; j++) {
+                f32x4_t acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w0, h1[0][j], bias, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1, h1[1][j], acc, 0, 0, 0);
+                for (int i = 0; i < 4; i++) yp[j] += w3[i] * relu(acc[i]);
+            }
+        }
+        // sum the four row groups of each column (lanes l, l^16, l^32, l^48);
+        // lane l's face is column l%16 of tile l/16
+        for (int j = 0; j < 2; j++) {
+            yp[j] += __shfl_xor(yp[j], 16, 64);
+            yp[j] += __shfl_xor(yp[j], 32, 64);
+            yy = (lane >> 4) == 2 * pass + j ? yp[j] : yy;
         }
     }
-    // layer 2 (+ b2, relu) and layer 3 (w3 dot), one output tile at a time
-    float y[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-    for (int t = 0; t < 4; t++) {
-        __builtin_amdgcn_sched_barrier(0);
-        const bf16x8_t w0 = P->a2[t][0][lane], w1 = P->a2[t][1][lane];
-        const f32x4_t bias = *reinterpret_cast<const f32x4_t *>(P->b2 + 16 * t + rbase);
-        const f32x4_t w3 = *reinterpret_cast<const f32x4_t *>(P->w3 + 16 * t + rbase);
-        for (int n = 0; n < 4; n++) {
-            f32x4_t acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w0, h1[0][n], bias, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1, h1[1][n], acc, 0, 0, 0);
-            for (int i = 0; i < 4; i++) y[n] += w3[i] * relu(acc[i]);
-        }
-    }
-    // sum the four row groups of each column (lanes l, l^16, l^32, l^48);
-    // lane l's face is column l%16 of tile l/16
-    for (int n = 0; n < 4; n++) {
-        y[n] += __shfl_xor(y[n], 16, 64);
-        y[n] += __shfl_xor(y[n], 32, 64);
-    }
-    const int me = lane >> 4;
-    const float yy = me == 0 ? y[0] : me == 1 ? y[1] : me == 2 ? y[2] : y[3];
     return yy + P->b3;
 }
 
