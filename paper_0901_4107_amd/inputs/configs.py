@@ -153,6 +153,35 @@ def sedov3d(n_side: int = 256, jitter: float = 0.1, seed: int = 1004, n_hot: int
     return Workload(f"sedov3d_{n_side}^3", mesh, Q, gamma, 0.4, np.zeros(3), seed, (rho, vel, P))
 
 
+def blast_shell_states(mesh, gamma: float = 5.0 / 3.0, r_shock: float = 0.15, rho0: float = 1.0,
+                       p0: float = 1e-5, energy: float = 1.0):
+    """Primitive states (rho, vel [3][N], P) of an approximate point
+    explosion grown to shock radius r_shock around the box centre: a stand-in
+    for the states a Sedov run passes through, with their structure (a
+    strong shock, a hot rarefied interior, the cold ambient gas), not the
+    exact self-similar solution. Shock speed from the similarity scaling
+    R = xi0 (E t^2 / rho0)^(1/5) with xi0 = 1.15 (gamma = 5/3), so
+    v_s = (2/5) R / t; post-shock state from the strong-shock jump
+    conditions (rho (g+1)/(g-1), velocity 2 v_s/(g+1), pressure
+    2 rho0 v_s^2/(g+1)); inside, for x = r/R: rho ~ x^(3/(g-1)), v ~ x,
+    P ~ 0.3 + 0.7 x^5 (power-law shapes of the interior)."""
+    xi0 = 1.15
+    t = (r_shock / xi0) ** 2.5 * np.sqrt(rho0 / energy)
+    vs = 0.4 * r_shock / t
+    rho2 = rho0 * (gamma + 1.0) / (gamma - 1.0)
+    v2 = 2.0 * vs / (gamma + 1.0)
+    p2 = 2.0 * rho0 * vs * vs / (gamma + 1.0)
+    d = mesh.positions - 0.5
+    r = np.sqrt(np.sum(d * d, axis=1))
+    x = r / r_shock
+    inside = x < 1.0
+    rho = np.where(inside, np.maximum(rho2 * x ** (3.0 / (gamma - 1.0)), 1e-6 * rho2), rho0)
+    P = np.where(inside, p2 * (0.3 + 0.7 * x ** 5), p0)
+    vr = np.where(inside, v2 * x, 0.0)
+    vel = (d / np.maximum(r, 1e-300)[:, None] * vr[:, None]).T
+    return rho, np.ascontiguousarray(vel), P
+
+
 def riemann_tails(n: int, gamma: float, rng) -> np.ndarray:
     """Hard-tail Riemann problems [6][n] (rho_L, u_L, P_L, rho_R, u_R, P_R):
     half near vacuum (velocity jump 80-99.5% of the vacuum threshold
@@ -190,19 +219,22 @@ def face_pair_problems(wl: Workload) -> np.ndarray:
 
 def riemann_problems(n: int = 1 << 24, seed: int = 1003, side: int = 64, nthreads: int = 0) -> np.ndarray:
     """16M-style batch of independent 1D Riemann problems [6][n]: face-pair
-    problems of the random-state, boosted Kelvin-Helmholtz and Sedov
-    workloads (side^3 cells each) resampled with replacement to 95% of n,
-    plus 5% hard tails (riemann_tails). The Sedov pairs are taken where the
-    two sides differ (the blast region)."""
+    problems of the random-state and boosted Kelvin-Helmholtz workloads and
+    of a grown blast (blast_shell_states on the Sedov mesh; side^3 cells
+    each), resampled with replacement to 95% of n, plus 5% hard tails
+    (riemann_tails). The blast pairs are taken where the two sides differ
+    (the blast region)."""
     rng = np.random.default_rng(seed)
     gamma = 5.0 / 3.0
     pools = []
     for wl in (random3d(n_side=side, seed=seed + 1, nthreads=nthreads),
                kh3d(n_points=side ** 3, seed=seed + 2, nthreads=nthreads),
                sedov3d(n_side=side, seed=seed + 3, nthreads=nthreads)):
+        if wl.name.startswith("sedov"):
+            wl.prim = blast_shell_states(wl.mesh, wl.gamma)
         s = face_pair_problems(wl)
         if wl.name.startswith("sedov"):
-            s = s[:, np.abs(s[2] - s[5]) > 1e-12]
+            s = s[:, (s[0] != s[3]) | (s[1] != s[4]) | (s[2] != s[5])]
         pools.append(s)
     n_tail = n // 20
     n_body = n - n_tail

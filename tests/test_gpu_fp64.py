@@ -13,7 +13,7 @@ import torch
 from oracle import oracle as O
 from paper_0901_4107_amd import mm
 from paper_0901_4107_amd.inputs import build_mesh
-from paper_0901_4107_amd.inputs.configs import kh2d, random3d, conserved_from_primitive, poisson_points
+from paper_0901_4107_amd.inputs.configs import kh2d, random3d, sedov3d, conserved_from_primitive, poisson_points
 from tests.util import boost, normwise_rel
 
 pytestmark = pytest.mark.gpu
@@ -112,6 +112,12 @@ def test_kh2d_one_step():
 def test_random3d_small(side):
     """Several tiles and a ragged tail (13^3 = 2197 cells, ~17k faces)."""
     check_one_step(random3d(n_side=side, seed=500 + side))
+
+
+def test_sedov3d_small():
+    """The point explosion (pressure ratio 1e7 at the hot cells) on a
+    20^3 jittered lattice."""
+    check_one_step(sedov3d(n_side=20, seed=777))
 
 
 def test_random3d_full_64():

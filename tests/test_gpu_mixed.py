@@ -14,7 +14,8 @@ import torch
 
 from oracle import oracle as O
 from paper_0901_4107_amd import mm
-from paper_0901_4107_amd.inputs.configs import kh3d, random3d, kh2d
+from paper_0901_4107_amd import learned
+from paper_0901_4107_amd.inputs.configs import kh3d, random3d, kh2d, sedov3d
 from tests.util import boost, l1_state
 
 pytestmark = pytest.mark.gpu
@@ -22,9 +23,11 @@ pytestmark = pytest.mark.gpu
 L1_BOUND = 1e-6
 
 
-def mixed_step(wl, dt=0.0):
+def mixed_step(wl, dt=0.0, guess=mm.MM_GUESS_STANDARD):
     m = wl.mesh
-    ctx = mm.Context(m.dim, wl.gamma, wl.cfl, mode=mm.MM_MIXED)
+    ctx = mm.Context(m.dim, wl.gamma, wl.cfl, mode=mm.MM_MIXED, guess=guess)
+    if guess == mm.MM_GUESS_LEARNED:
+        ctx.mm_mlp_load(learned.load(wl.gamma))
     ctx.mm_mesh_upload(mm.DeviceMesh.from_host(m))
     Q = torch.from_numpy(np.ascontiguousarray(wl.Q)).cuda()
     used = ctx.mm_hydro_step(Q, dt=dt)
@@ -44,6 +47,21 @@ def test_kh3d_boosted_l1(n_points):
     scale = np.abs(wl.Q).sum(axis=1)
     scale[1:4] = np.sum(np.sqrt(np.sum(wl.Q[1:4] ** 2, axis=0)))  # momentum scale
     assert np.all(np.abs(Qm.sum(axis=1) - wl.Q.sum(axis=1)) <= 1e-13 * scale)
+
+
+def test_sedov_mixed_learned_l1():
+    """The point explosion in the mixed form with the stored trained
+    network, three steps against the oracle's three steps."""
+    wl = sedov3d(n_side=20, seed=778)
+    Qm = wl.Q.copy()
+    Qo = wl.Q.copy()
+    for k in range(3):
+        Qo, dto = O.hydro_step(wl.mesh, wl.gamma, wl.cfl, Qo)
+        wl.Q = Qm
+        Qm, used, diag = mixed_step(wl, dt=dto, guess=mm.MM_GUESS_LEARNED)
+    err = l1_state(Qm, Qo)
+    print(f"sedov 20^3, 3 steps: L1 per component {err}; diag {diag}", flush=True)
+    assert np.all(err <= L1_BOUND), err
 
 
 def test_kh2d_mixed_l1():
