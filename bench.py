@@ -192,9 +192,14 @@ def bench_step(args):
     }
     nbytes, per_face, per_cell = flux_kernel_bytes(m.dim, m.n_cells, m.n_faces, mixed)
     achieved = nbytes / (head["flux_ms"] * 1e-3) / 1e9
+    kname = (f"k_face_flux_mixed<{m.dim}, {'true' if args.mode.endswith('learned') else 'false'}>" if mixed
+             else f"k_face_flux64<{m.dim}, {'true' if args.mode.endswith('learned') else 'false'}>")
+    from paper_0901_4107_amd.prof_summary import read_traffic
+    traffic = read_traffic(os.path.join(ROOT, "profiles"), kname, wl.name)
     out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                       "kernel": "k_face_flux_mixed" if mixed else "k_face_flux64",
+                       "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                       "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE, WRITE_SIZE, copy-scaled)",
+                       "kernel": kname, "algorithmic_bytes": nbytes,
                        "bytes_per_face": per_face, "bytes_per_cell": per_cell}
     if args.mode != "fp64" and not args.no_compare:
         base = time_form(mm, learned, torch, wl, dmesh, "fp64", args.steps, args.warmup, dev)

@@ -22,6 +22,20 @@ HIPCC_FLAGS = [
 ]
 
 
+def source_hash() -> str:
+    """Short hash of the kernel sources and flags libmm is built from; tags
+    measurements taken from a particular build of the kernels."""
+    import hashlib
+    h = hashlib.sha256(" ".join(HIPCC_FLAGS).encode())
+    for name in sorted(os.listdir(CSRC)):
+        with open(os.path.join(CSRC, name), "rb") as fh:
+            h.update(name.encode())
+            h.update(fh.read())
+    with open(os.path.join(ROOT, "include", "mm.h"), "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def build_libmm(extra=()) -> str:
     src = os.path.join(CSRC, "mm.hip")
     cmd = ["hipcc", *HIPCC_FLAGS, *extra, "-I", os.path.join(ROOT, "include"), "-o", LIBMM + ".tmp", src]
