@@ -33,7 +33,17 @@ struct DiagDev {
 };
 
 struct LaneDiag {
-    unsigned iters = 0, unconv = 0, vacuum = 0, posfb = 0, fp64fb = 0, guessfb = 0;
+    unsigned iters = 0, itmax = 0, unconv = 0, vacuum = 0, posfb = 0, fp64fb = 0, guessfb = 0;
+    // add another lane record's counts
+    __device__ void add(const LaneDiag &o) {
+        iters += o.iters;
+        itmax = o.itmax > itmax ? o.itmax : itmax;
+        unconv += o.unconv;
+        vacuum += o.vacuum;
+        posfb += o.posfb;
+        fp64fb += o.fp64fb;
+        guessfb += o.guessfb;
+    }
 };
 
 __device__ __forceinline__ unsigned wave_sum(unsigned v) {
@@ -46,16 +56,18 @@ __device__ __forceinline__ unsigned wave_max(unsigned v) {
 }
 
 // Reduce the lanes' counters over the block; one set of atomics per block.
+// The wavefront maximum of the lanes' iteration counts goes to
+// wave_iter_max_sum, the largest count of a single problem to newton_max.
 __device__ __forceinline__ void flush_diag(const LaneDiag &d, DiagDev *slots) {
     DiagDev *out = slots + (blockIdx.x & (kDiagSlots - 1));
-    __shared__ unsigned red[kBlock / 64][7];
-    const unsigned s_it = wave_sum(d.iters), m_it = wave_max(d.iters);
+    __shared__ unsigned red[kBlock / 64][8];
+    const unsigned s_it = wave_sum(d.iters), m_it = wave_max(d.iters), m_one = wave_max(d.itmax);
     const unsigned s_un = wave_sum(d.unconv), s_va = wave_sum(d.vacuum), s_pf = wave_sum(d.posfb);
     const unsigned s_64 = wave_sum(d.fp64fb), s_gf = wave_sum(d.guessfb);
     const int w = threadIdx.x / 64;
     if ((threadIdx.x & 63) == 0) {
         red[w][0] = s_it; red[w][1] = m_it; red[w][2] = s_un; red[w][3] = s_va;
-        red[w][4] = s_pf; red[w][5] = s_64; red[w][6] = s_gf;
+        red[w][4] = s_pf; red[w][5] = s_64; red[w][6] = s_gf; red[w][7] = m_one;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -63,7 +75,7 @@ __device__ __forceinline__ void flush_diag(const LaneDiag &d, DiagDev *slots) {
         unsigned mx = 0;
         for (int k = 0; k < kBlock / 64; k++) {
             for (int q = 0; q < 7; q++) t[q] += red[k][q];
-            mx = red[k][1] > mx ? red[k][1] : mx;
+            mx = red[k][7] > mx ? red[k][7] : mx;
         }
         atomicAdd(&out->newton_iters, t[0]);
         atomicMax(&out->newton_max, (unsigned long long)mx);
@@ -147,7 +159,7 @@ __device__ __forceinline__ FaceState<T> solve_face(T rhoL, T uL, T PL, T rhoR, T
     FaceState<T> fs;
     T vac_num = (T)0;
     if (vacuum_cases<T>(kg, SL, SR, lvac, rvac, fs, vac_num)) {
-        ld.vacuum = 1;
+        ld.vacuum += 1;
         fs.pstar = (T)-1;
         fs.pstd = (T)-1;
         return fs;
@@ -164,14 +176,15 @@ __device__ __forceinline__ FaceState<T> solve_face(T rhoL, T uL, T PL, T rhoR, T
     int it = st.iters;
     if (!st.conv && learned) {
         // the learned guess failed: restart from the standard guess
-        ld.guessfb = 1;
+        ld.guessfb += 1;
         st = newton_star<T>(SL, SR, kg, p_std, tol, maxit);
         it += st.iters;
     }
     ld.iters += it;
+    ld.itmax = (unsigned)it > ld.itmax ? (unsigned)it : ld.itmax;
     if (!st.conv) {
         if (check_hard) { hard = true; return fs; }
-        ld.unconv = 1;
+        ld.unconv += 1;
     }
     fs = sample0<T>(SL, SR, st, kg);
     fs.pstar = st.ps;
@@ -283,20 +296,23 @@ __device__ __forceinline__ T learned_guess(const MlpPacked *P, bool want, T rhoL
     if (P == nullptr) return no_guess<T>();
     int slot;
     const int total = learn_count(sh, want, slot);
-    if (total == 0) return no_guess<T>();   // the same for the whole block
-    if (want) learn_put<T>(sh, slot, rhoL, uL, PL, rhoR, uR, PR, gamma);
-    learn_run(sh, P, total);
-    return learn_get<T>(sh, want, slot);
+    T corr = no_guess<T>();
+    if (total > 0) {   // the same for the whole block
+        if (want) learn_put<T>(sh, slot, rhoL, uL, PL, rhoR, uR, PR, gamma);
+        learn_run(sh, P, total);
+        corr = learn_get<T>(sh, want, slot);
+    }
+    __syncthreads();   // every thread has read the staging before a next call rewrites it
+    return corr;
 }
 
 // Lab-frame moving-face flux in double from the sampled face-frame state
 // (rho_F, u_F, P_F), the upwind transverse velocity tv, the normal n and
-// the face velocity w; stores the face's flux record.
+// the face velocity w, times scale (dt A).
 template <int D>
 __device__ __forceinline__ void lab_flux(double rho, double u, double P, const double *tv, const double *nrm,
-                                         const double *w, double g_over_gm1, double scale, double *rec_out) {
+                                         const double *w, double g_over_gm1, double scale, double (&out)[D + 2]) {
     constexpr int NV = D + 2;
-    double out[Lay<D>::FSTRIDE];
     const double mf = rho * u;
     double v2 = 0.0, w2 = 0.0, Piw = 0.0, Pi[D];
     for (int k = 0; k < D; k++) {
@@ -310,24 +326,21 @@ __device__ __forceinline__ void lab_flux(double rho, double u, double P, const d
     out[0] = scale * mf;
     for (int k = 0; k < D; k++) out[1 + k] = scale * (Pi[k] + mf * w[k]);
     out[NV - 1] = scale * (eps + Piw + 0.5 * mf * w2);
-    store_rec<Lay<D>::FSTRIDE>(rec_out, out);
 }
 
-// Double-precision face flux. LEARNED compiles the fused network in; the
+// Double-precision flux of face f (dt A Fhat into F), shared by the face
+// kernel and the cell-centric step kernel so that both give the same bits.
+// Every thread of the block calls it (the learned staging holds barriers);
+// active = false does no face. LEARNED compiles the fused network in; the
 // standard-guess instantiation carries none of its registers.
 template <int D, bool LEARNED>
-__global__ void __launch_bounds__(kBlock) k_face_flux64(int64_t nf, const int32_t *__restrict__ fL,
-                                                        const int32_t *__restrict__ fR, const double *__restrict__ frec,
-                                                        const double *__restrict__ prim, const double *__restrict__ grad,
-                                                        const double *__restrict__ dt_ptr, double dt_val,
-                                                        GasConst<double> kg, double tol, int maxit,
-                                                        const MlpPacked *mlp, double *__restrict__ flux, DiagDev *diag) {
+__device__ __forceinline__ void face_flux64(bool active, int64_t f, const int32_t *__restrict__ fL,
+                                            const int32_t *__restrict__ fR, const double *__restrict__ frec,
+                                            const double *__restrict__ prim, const double *__restrict__ grad,
+                                            double dt, const GasConst<double> &kg, double tol, int maxit,
+                                            const MlpPacked *mlp, LaneDiag &ld, double (&F)[D + 2]) {
     using Y = Lay<D>;
     constexpr int NV = D + 2;
-    const int64_t f = xcd_global_id();
-    const bool active = f < nf;
-    LaneDiag ld;
-    const double dt = dt_ptr ? *dt_ptr : dt_val;
     double A = 0.0, nrm[D], w[D], xl[NV], xr[NV], uL = 0.0, uR = 0.0;
     for (int c = 0; c < NV; c++) { xl[c] = 1.0; xr[c] = 1.0; }
     if (active) {
@@ -353,11 +366,11 @@ __global__ void __launch_bounds__(kBlock) k_face_flux64(int64_t nf, const int32_
         half_step<D, double>(rr, vf, gR, kg.g, hdt, xr, cr);
         if (!(xl[0] > 0.0 && xl[NV - 1] > 0.0 && xr[0] > 0.0 && xr[NV - 1] > 0.0)) {
             for (int c = 0; c < NV; c++) { xl[c] = cl[c]; xr[c] = cr[c]; }
-            ld.posfb = 1;
+            ld.posfb += 1;
         }
         for (int k = 0; k < D; k++) { uL += xl[1 + k] * nrm[k]; uR += xr[1 + k] * nrm[k]; }
     }
-    // learned guess: the whole wavefront evaluates the network together
+    // learned guess for the block's compacted problems
     double pl = no_guess<double>();
     if constexpr (LEARNED) {
         const bool want = active && wants_learned<double>(xl[0], uL, xl[NV - 1], xr[0], uR, xr[NV - 1], kg.g);
@@ -371,8 +384,27 @@ __global__ void __launch_bounds__(kBlock) k_face_flux64(int64_t nf, const int32_
         const double un = fs.side ? uR : uL;
         double tv[D];
         for (int k = 0; k < D; k++) tv[k] = xs[1 + k] - un * nrm[k];
-        lab_flux<D>(fs.rho, fs.u, fs.P, tv, nrm, w, kg.g_over_gm1, dt * A, flux + f * Y::FSTRIDE);
+        lab_flux<D>(fs.rho, fs.u, fs.P, tv, nrm, w, kg.g_over_gm1, dt * A, F);
     }
+}
+
+// Double-precision face flux kernel: one lane per face, fluxes stored
+// face-major.
+template <int D, bool LEARNED>
+__global__ void __launch_bounds__(kBlock) k_face_flux64(int64_t nf, const int32_t *__restrict__ fL,
+                                                        const int32_t *__restrict__ fR, const double *__restrict__ frec,
+                                                        const double *__restrict__ prim, const double *__restrict__ grad,
+                                                        const double *__restrict__ dt_ptr, double dt_val,
+                                                        GasConst<double> kg, double tol, int maxit,
+                                                        const MlpPacked *mlp, double *__restrict__ flux, DiagDev *diag) {
+    constexpr int NV = D + 2;
+    const int64_t f = xcd_global_id();
+    const bool active = f < nf;
+    LaneDiag ld;
+    const double dt = dt_ptr ? *dt_ptr : dt_val;
+    double F[NV];
+    face_flux64<D, LEARNED>(active, f, fL, fR, frec, prim, grad, dt, kg, tol, maxit, mlp, ld, F);
+    if (active) store_rec<NV>(flux + f * NV, F);
     if (diag) flush_diag(ld, diag);
 }
 
@@ -427,7 +459,7 @@ __device__ __forceinline__ MixedFace<D> mixed_face_states(int64_t f, const int32
 template <int D>
 __device__ __forceinline__ void mixed_lab_flux(const MixedFace<D> &m, double rho, double u, double P, int side,
                                                const double *__restrict__ wf64, int64_t f, double g_over_gm1,
-                                               double dt, double *__restrict__ out) {
+                                               double dt, double (&out)[D + 2]) {
     using Y = Lay<D>;
     const float *xs = side ? m.xr : m.xl;
     const float un = side ? m.uR : m.uL;
@@ -441,42 +473,33 @@ __device__ __forceinline__ void mixed_lab_flux(const MixedFace<D> &m, double rho
     lab_flux<D>(rho, u, P, tv, nd, w, g_over_gm1, dt * (double)m.A, out);
 }
 
-// Mixed-precision face flux: float face states and float Newton; the
-// lab-frame flux and everything after it in double. Faces the float solve
-// judges hard (strong rarefaction or near vacuum, tiny guess, no
-// convergence) are appended to a compact list (wave-aggregated) and left to
-// k_face_flux_hard. LEARNED as for the double kernel.
+// Mixed-precision flux of face f (dt A Fhat into F): float face states and
+// float Newton; the lab-frame flux and everything after it in double. Faces
+// the float solve judges hard (strong rarefaction or near vacuum, tiny
+// guess, no convergence) come back with hard = true and no flux. Shared by
+// the face kernel and the cell-centric step kernel so that both give the
+// same bits. Every thread of the block calls it (the learned staging holds
+// barriers); active = false does no face. While the network runs, the face
+// states wait in LDS, so the network's registers come on top of few live
+// values.
 template <int D, bool LEARNED>
-__global__ void __launch_bounds__(kBlock) k_face_flux_mixed(int64_t nf, const int32_t *__restrict__ fL,
-                                                            const int32_t *__restrict__ fR,
-                                                            const float *__restrict__ mrec,
-                                                            const double *__restrict__ wf64,
-                                                            const float *__restrict__ prim,
-                                                            const float *__restrict__ grad,
-                                                            const double *__restrict__ dt_ptr, double dt_val,
-                                                            GasConst<float> kf, double g_over_gm1, float tol32,
-                                                            int maxit, const MlpPacked *mlp,
-                                                            double *__restrict__ flux, int32_t *__restrict__ hard_list,
-                                                            int64_t cap,
-                                                            DiagDev *diag) {
+__device__ __forceinline__ void face_flux_mixed(bool active, int64_t f, const int32_t *__restrict__ fL,
+                                                const int32_t *__restrict__ fR, const float *__restrict__ mrec,
+                                                const double *__restrict__ wf64, const float *__restrict__ prim,
+                                                const float *__restrict__ grad, double dt, const GasConst<float> &kf,
+                                                double g_over_gm1, float tol32, int maxit, const MlpPacked *mlp,
+                                                LaneDiag &ld, bool &hard, double (&F)[D + 2]) {
     constexpr int NV = D + 2;
-    const int64_t f = xcd_global_id();
-    const bool active = f < nf;
-    LaneDiag ld;
-    bool hard = false;
-    const double dt = dt_ptr ? *dt_ptr : dt_val;
+    hard = false;
     MixedFace<D> m;
     if (active) {
         m = mixed_face_states<D>(f, fL, fR, mrec, prim, grad, (float)(0.5 * dt), kf.g);
-        ld.posfb = m.posfb;
+        ld.posfb += m.posfb ? 1 : 0;
     } else {
         for (int c = 0; c < NV; c++) { m.xl[c] = 1.0f; m.xr[c] = 1.0f; }
         m.uL = 0.0f;
         m.uR = 0.0f;
     }
-    // learned guess for the block's compacted problems. While the network
-    // runs, the face states wait in LDS, so the network's registers come
-    // on top of few live values.
     float pl = no_guess<float>();
     if constexpr (LEARNED) {
         __shared__ LearnLds sh;
@@ -500,13 +523,40 @@ __global__ void __launch_bounds__(kBlock) k_face_flux_mixed(int64_t nf, const in
             m.uR = 0.0f;
             for (int k = 0; k < D; k++) { m.uL += m.xl[1 + k] * m.nrm[k]; m.uR += m.xr[1 + k] * m.nrm[k]; }
         }
+        // every thread has read the staging before a next call rewrites it
+        if (mlp) __syncthreads();
     }
     if (active) {
         FaceState<float> fs = solve_face<float>(m.xl[0], m.uL, m.xl[NV - 1], m.xr[0], m.uR, m.xr[NV - 1], kf, tol32,
                                                 maxit, pl, true, ld, hard);
-        if (!hard)
-            mixed_lab_flux<D>(m, fs.rho, fs.u, fs.P, fs.side, wf64, f, g_over_gm1, dt, flux + f * Lay<D>::FSTRIDE);
+        if (!hard) mixed_lab_flux<D>(m, fs.rho, fs.u, fs.P, fs.side, wf64, f, g_over_gm1, dt, F);
     }
+}
+
+// Mixed-precision face flux kernel: one lane per face; hard faces are
+// appended to a split list (wave-aggregated) and left to k_face_flux_hard.
+template <int D, bool LEARNED>
+__global__ void __launch_bounds__(kBlock) k_face_flux_mixed(int64_t nf, const int32_t *__restrict__ fL,
+                                                            const int32_t *__restrict__ fR,
+                                                            const float *__restrict__ mrec,
+                                                            const double *__restrict__ wf64,
+                                                            const float *__restrict__ prim,
+                                                            const float *__restrict__ grad,
+                                                            const double *__restrict__ dt_ptr, double dt_val,
+                                                            GasConst<float> kf, double g_over_gm1, float tol32,
+                                                            int maxit, const MlpPacked *mlp,
+                                                            double *__restrict__ flux, int32_t *__restrict__ hard_list,
+                                                            int64_t cap, DiagDev *diag) {
+    constexpr int NV = D + 2;
+    const int64_t f = xcd_global_id();
+    const bool active = f < nf;
+    LaneDiag ld;
+    bool hard;
+    const double dt = dt_ptr ? *dt_ptr : dt_val;
+    double F[NV];
+    face_flux_mixed<D, LEARNED>(active, f, fL, fR, mrec, wf64, prim, grad, dt, kf, g_over_gm1, tol32, maxit, mlp,
+                                ld, hard, F);
+    if (active && !hard) store_rec<NV>(flux + f * NV, F);
     list_append(hard_list, cap, hard, (int32_t)f);
     if (diag) flush_diag(ld, diag);
 }
@@ -537,7 +587,9 @@ __global__ void __launch_bounds__(kBlock) k_face_flux_hard(const int32_t *__rest
         FaceState<double> fd = solve_face<double>(m.xl[0], m.uL, m.xl[NV - 1], m.xr[0], m.uR, m.xr[NV - 1], kg,
                                                   tol64, 50, no_guess<double>(), false, ld, h2);
         ld.fp64fb += 1;
-        mixed_lab_flux<D>(m, fd.rho, fd.u, fd.P, fd.side, wf64, f, kg.g_over_gm1, dt, flux + f * Lay<D>::FSTRIDE);
+        double F[NV];
+        mixed_lab_flux<D>(m, fd.rho, fd.u, fd.P, fd.side, wf64, f, kg.g_over_gm1, dt, F);
+        store_rec<NV>(flux + f * NV, F);
     }
     if (diag) flush_diag(ld, diag);
 }
