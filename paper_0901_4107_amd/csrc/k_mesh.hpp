@@ -197,8 +197,9 @@ __global__ void __launch_bounds__(kBlock) k_face_records(int64_t n, int64_t nf, 
     }
 }
 
-// Side records in CSR order, one lane per cell: A/|d| and f - r_i (plus
-// w_j - w_i for the mixed path), and the closure test of each cell,
+// Side records in CSR order, one lane per cell: A/|d| and f - r_i in double
+// for the double path, with w_j - w_i in float for the mixed path, and the
+// closure test of each cell,
 // |sum_faces A n_out| <= 1e-9 sum_faces A. A closed surface is a property of
 // every Voronoi cell; the gradient kernels rely on it.
 template <int D>
@@ -218,16 +219,17 @@ __global__ void __launch_bounds__(kBlock) k_side_records(int64_t n, int64_t nf, 
         double d[D], s2 = 0.0;
         for (int k = 0; k < D; k++) { d[k] = sep[k * nf + f]; s2 += d[k] * d[k]; }
         const double ell = sqrt(s2), A = area[f];
-        double *o = srec + (int64_t)q * Y::SREC64;
+        double o[Y::SREC64];
         o[0] = A / ell;
         const int32_t j = nbr[q];
         for (int k = 0; k < D; k++) {
             const double c = ctr[k * nf + f] - 0.5 * d[k];
-            const double g = c + 0.5 * sg * d[k];
-            o[1 + k] = g;
+            o[1 + k] = c + 0.5 * sg * d[k];
             clo[k] += A * sg * d[k] / ell;
         }
         for (int k = 1 + D; k < Y::SREC64; k++) o[k] = 0.0;
+        if (!mixed)
+            for (int k = 0; k < Y::SREC64; k++) srec[(int64_t)q * Y::SREC64 + k] = o[k];
         asum += A;
         if (mixed) {
             float *m = srec32 + (int64_t)q * Y::SREC32;

@@ -59,9 +59,9 @@ Layout make_layout(int D, int mode, int64_t n, int64_t nf) {
     L.nbr = take(2 * nf * sizeof(int32_t));
     L.frec = take(nf * FREC * sizeof(double));
     L.flux = take(nf * ((D == 3) ? Lay<3>::FSTRIDE : Lay<2>::FSTRIDE) * sizeof(double));
-    L.srec = take(2 * nf * Lay<3>::SREC64 * sizeof(double));
-    L.srec32 = L.mrec = L.wf64 = L.rec32 = L.rec = L.hard = -1;
+    L.srec = L.srec32 = L.mrec = L.wf64 = L.rec32 = L.rec = L.hard = -1;
     if (mode == MM_FP64) {
+        L.srec = take(2 * nf * Lay<3>::SREC64 * sizeof(double));
         L.rec = take(n * REC * sizeof(double));
     } else {
         L.srec32 = take(2 * nf * Lay<3>::SREC32 * sizeof(float));
@@ -221,7 +221,7 @@ template <int D> static void launch_records(mm_ctx *c, const mm_mesh *m, int32_t
         c->at<double>(L.frec), mixed, mixed ? c->at<float>(L.mrec) : nullptr, mixed ? c->at<double>(L.wf64) : nullptr);
     k_side_records<D><<<plain_grid(m->n_cells), kBlock, 0, c->st()>>>(
         m->n_cells, m->n_faces, c->at<int32_t>(L.off), c->at<int32_t>(L.ent), c->at<int32_t>(L.nbr), m->face_area,
-        m->face_ctr, m->face_sep, m->mesh_vel, c->at<double>(L.srec), mixed,
+        m->face_ctr, m->face_sep, m->mesh_vel, mixed ? nullptr : c->at<double>(L.srec), mixed,
         mixed ? c->at<float>(L.srec32) : nullptr, flags);
 }
 
