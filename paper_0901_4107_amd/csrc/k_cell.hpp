@@ -186,8 +186,8 @@ __global__ void __launch_bounds__(kBlock) k_grad_limit(int64_t n, const int32_t 
     using Y = Lay<D>;
     constexpr int NV = D + 2;
     constexpr int GS = Group<D>::GS;
-    constexpr int KR = 3;
     constexpr bool mixed = sizeof(T) == 4;
+    constexpr int KR = mixed ? 3 : 2;   // sides per lane held in registers
     constexpr int SR = mixed ? Y::SREC32 : Y::SREC64;
     const T eps_t = mixed ? (T)1e-6 : (T)1e-13;
     const int lane = threadIdx.x % GS;
@@ -197,14 +197,14 @@ __global__ void __launch_bounds__(kBlock) k_grad_limit(int64_t n, const int32_t 
     // the lane's first KR sides: side records and neighbour indices, then
     // the neighbours' primitive records, all in flight together (an absent
     // side reads record 0 of the arrays and is skipped)
-    T sr[KR][SR], pj[KR][Y::PREC];
+    T sr[KR][SR], pj[KR][NV];   // of a neighbour's record only W is needed
     bool has[KR];
     for (int r = 0; r < KR; r++) {
         const int32_t q = b + lane + r * GS;
         has[r] = q < e;
         const int32_t qq = has[r] ? q : 0;
         load_rec<SR>(srec + (int64_t)qq * SR, sr[r]);
-        load_rec<Y::PREC>(prim + (int64_t)nbr[qq] * Y::PREC, pj[r]);
+        load_rec<NV>(prim + (int64_t)nbr[qq] * Y::PREC + Y::W, pj[r]);
     }
     T pi[Y::PREC];
     load_rec<Y::PREC>(prim + i * Y::PREC, pi);
@@ -216,12 +216,12 @@ __global__ void __launch_bounds__(kBlock) k_grad_limit(int64_t n, const int32_t 
         for (int k = 0; k < D; k++) a.acc[c][k] = (T)0;
     }
     for (int r = 0; r < KR; r++)
-        if (has[r]) grad_side<D, T, mixed>(sr[r], pj[r] + Y::W, wi, a);
+        if (has[r]) grad_side<D, T, mixed>(sr[r], pj[r], wi, a);
     for (int32_t q = b + lane + KR * GS; q < e; q += GS) {
-        T s2[SR], p2[Y::PREC];
+        T s2[SR], p2[NV];
         load_rec<SR>(srec + (int64_t)q * SR, s2);
-        load_rec<Y::PREC>(prim + (int64_t)nbr[q] * Y::PREC, p2);
-        grad_side<D, T, mixed>(s2, p2 + Y::W, wi, a);
+        load_rec<NV>(prim + (int64_t)nbr[q] * Y::PREC + Y::W, p2);
+        grad_side<D, T, mixed>(s2, p2, wi, a);
     }
     const T inv_v = (T)(1.0 / V[i]);
     T grad[NV][D], dmx[NV], dmn[NV];
