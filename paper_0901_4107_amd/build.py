@@ -23,16 +23,23 @@ HIPCC_FLAGS = [
 
 
 def source_hash() -> str:
-    """Short hash of the kernel sources and flags libmm is built from; tags
+    """Short hash of the code of the kernel sources (comments and layout
+    whitespace removed) and the flags libmm is built from; tags
     measurements taken from a particular build of the kernels."""
     import hashlib
+    import re
+
+    def code(text: str) -> str:
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        return " ".join(text.split())
+
     h = hashlib.sha256(" ".join(HIPCC_FLAGS).encode())
-    for name in sorted(os.listdir(CSRC)):
-        with open(os.path.join(CSRC, name), "rb") as fh:
-            h.update(name.encode())
-            h.update(fh.read())
-    with open(os.path.join(ROOT, "include", "mm.h"), "rb") as fh:
-        h.update(fh.read())
+    files = [os.path.join(CSRC, name) for name in sorted(os.listdir(CSRC))]
+    for path in files + [os.path.join(ROOT, "include", "mm.h")]:
+        with open(path) as fh:
+            h.update(os.path.basename(path).encode())
+            h.update(code(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

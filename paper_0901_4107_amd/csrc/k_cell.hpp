@@ -2,7 +2,7 @@
 // gradients with slope limiting, and the conservative update.
 //
 // The gradient and update kernels give each cell a group of GS lanes
-// (16 in 3D, 8 in 2D; a wavefront serves 64/GS cells) that walk the cell's
+// (8 in 3D, 4 in 2D; a wavefront serves 64/GS cells) that walk the cell's
 // face-side list together: consecutive lanes read consecutive side records,
 // and the per-cell sums, minima and maxima are butterfly reductions inside
 // the group (no atomics, fixed order, so results are bitwise reproducible).

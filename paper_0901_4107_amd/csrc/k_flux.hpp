@@ -410,8 +410,9 @@ __global__ void __launch_bounds__(kBlock) k_face_flux64(int64_t nf, const int32_
 
 // Float face-frame states of one face for the mixed path: reconstruction,
 // frame transform and half step on velocities relative to the face (the
-// record holds v_i - w_i and the face record w_K - w_f, so
-// v - w_f = (v_K - w_K) + (w_K - w_f) never forms a lab-frame velocity).
+// cell record holds v_i - w_i and w_K - w_f follows from the face record's
+// w_L - w_R, so v - w_f = (v_K - w_K) + (w_K - w_f) never forms a lab-frame
+// velocity).
 template <int D> struct MixedFace {
     float xl[D + 2], xr[D + 2], uL, uR, nrm[D], A;
     bool posfb;
@@ -561,8 +562,8 @@ __global__ void __launch_bounds__(kBlock) k_face_flux_mixed(int64_t nf, const in
     if (diag) flush_diag(ld, diag);
 }
 
-// Double re-solve of the hard faces listed by k_face_flux_mixed (count in
-// a split list of sub-list capacity cap). A fixed grid walks the list, so the
+// Double re-solve of the hard faces listed by k_face_flux_mixed (a split
+// list of sub-list capacity cap). A fixed grid walks the list, so the
 // launch needs no host-side count; the float face states are recomputed by
 // the same code, hence identical.
 template <int D>
