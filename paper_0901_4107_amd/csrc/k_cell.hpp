@@ -2,7 +2,7 @@
 // gradients with slope limiting, and the conservative update.
 //
 // The gradient and update kernels give each cell a group of GS lanes
-// (8 in 3D, 4 in 2D; a wavefront serves 64/GS cells) that walk the cell's
+// (4; a wavefront serves 16 cells) that walk the cell's
 // face-side list together: consecutive lanes read consecutive side records,
 // and the per-cell sums, minima and maxima are butterfly reductions inside
 // the group (no atomics, fixed order, so results are bitwise reproducible).
@@ -13,7 +13,7 @@
 
 namespace mm {
 
-template <int D> struct Group { static constexpr int GS = (D == 3) ? 8 : 4; };
+template <int D> struct Group { static constexpr int GS = 4; };
 
 // Cross-lane moves inside 16-lane rows by DPP (no LDS round trip):
 // quad_perm xor 1 and xor 2, then row_half_mirror (lane i <- 7 - i within 8)
@@ -187,7 +187,7 @@ __global__ void __launch_bounds__(kBlock) k_grad_limit(int64_t n, const int32_t 
     constexpr int NV = D + 2;
     constexpr int GS = Group<D>::GS;
     constexpr bool mixed = sizeof(T) == 4;
-    constexpr int KR = mixed ? 3 : 2;   // sides per lane held in registers
+    constexpr int KR = mixed ? 5 : 3;   // sides per lane held in registers
     constexpr int SR = mixed ? Y::SREC32 : Y::SREC64;
     const T eps_t = mixed ? (T)1e-6 : (T)1e-13;
     const int lane = threadIdx.x % GS;
@@ -274,7 +274,7 @@ __global__ void __launch_bounds__(kBlock) k_update(int64_t n, const int32_t *__r
     constexpr int NV = D + 2;
     constexpr int FS = Y::FSTRIDE;
     constexpr int GS = Group<D>::GS;
-    constexpr int KR = 3;
+    constexpr int KR = 5;
     const int lane = threadIdx.x % GS;
     const int64_t i = xcd_tile() * (kBlock / GS) + threadIdx.x / GS;
     if (i >= n) return;
