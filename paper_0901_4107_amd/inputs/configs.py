@@ -8,13 +8,13 @@ into cell totals ``Q = (m, p, E)`` with ``m = rho V``, ``p = m v`` and
 ideal-gas law, Section 3). Nothing here evaluates any step of the scheme.
 
 Workloads
-  kh2d       2D Kelvin-Helmholtz (Section 8.6), 64x64 jittered lattice.
+  kh2d       2D Kelvin-Helmholtz (Section 8.7), 64x64 jittered lattice.
   random3d   3D random states on a 64^3 jittered lattice (log-uniform density
              and pressure, Gaussian velocities of three sound speeds), fixed
              mesh; stresses the Riemann solver.
   kh3d       3D Kelvin-Helmholtz shear layer on Poisson points with a uniform
              bulk boost and a comoving mesh (Galilean-invariance workload).
-  sedov3d    3D Sedov-Taylor blast on a jittered lattice (Section 8.5).
+  sedov3d    3D Sedov-Taylor blast on a jittered lattice (Section 8.4).
 """
 from __future__ import annotations
 

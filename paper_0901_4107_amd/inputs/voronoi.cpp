@@ -8,7 +8,7 @@
 // by the bisector planes of candidate neighbours taken in order of distance;
 // the search stops once every vertex of the cell lies closer than half the
 // distance to the next unexamined candidate, which is the completeness test
-// the paper uses for its ghost-point search (Section 2.5): a point farther
+// the paper uses for its ghost-point search (Section 2.4): a point farther
 // than twice the largest vertex distance cannot cut the cell. Periodicity is
 // handled by searching buckets of a wrapped grid and carrying the image
 // shift into the separation vector.

@@ -50,7 +50,7 @@ def test_golden_star_states():
 
 
 def test_paper_shock_tube_mach():
-    """Section 8.3: rho,P = 1,1 | 0.25,0.1795, gamma 1.4 gives a shock of Mach
+    """Section 8.2: rho,P = 1,1 | 0.25,0.1795, gamma 1.4 gives a shock of Mach
     number 1.48 running into the right state; the post-shock density jump
     must match the paper's f_rho(M) = (g+1) M^2 / ((g-1) M^2 + 2)."""
     g = 1.4

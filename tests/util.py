@@ -43,3 +43,24 @@ def l1_state(a, b):
     den[1:1 + D] = pmag
     den = np.where(den > 0, den, 1.0)
     return num / den
+
+
+def blast_radius(mesh, rho, centre=0.5):
+    """Shock radius of a spherical blast about `centre`: cell densities
+    averaged over radial shells half a mean cell spacing thick (radii of
+    the cell centroids), then the densest shell's radius refined by the
+    vertex of the parabola through it and its two neighbours. Returns
+    (radius, density of the densest shell)."""
+    D = mesh.dim
+    cen = np.mod(mesh.positions.T + mesh.centroid_off, 1.0)
+    r = np.sqrt(np.sum((cen - centre) ** 2, axis=0))
+    h = 0.5 * (1.0 / mesh.n_cells) ** (1.0 / D)
+    nb = int(0.5 / h)
+    idx = np.minimum((r / h).astype(np.int64), nb)
+    cnt = np.bincount(idx, minlength=nb + 1)[:nb]
+    prof = np.bincount(idx, weights=rho, minlength=nb + 1)[:nb] / np.maximum(cnt, 1)
+    i = int(np.clip(np.argmax(prof), 1, nb - 2))
+    y0, y1, y2 = prof[i - 1:i + 2]
+    curv = y0 - 2.0 * y1 + y2
+    off = 0.5 * (y0 - y2) / curv if curv < 0 else 0.0
+    return (i + 0.5 + off) * h, float(y1)
