@@ -178,8 +178,12 @@ __device__ __forceinline__ void limit_side(const T *g, const T *dl, const T (&gr
     }
 }
 
+// The gather-bound gradient kernel gains from one more wavefront per SIMD
+// than the register count the compiler picks on its own (5 float / 4 double,
+// without spills, about 7-9% faster).
 template <int D, typename T>
-__global__ void __launch_bounds__(kBlock) k_grad_limit(int64_t n, const int32_t *__restrict__ off,
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 4)))
+k_grad_limit(int64_t n, const int32_t *__restrict__ off,
                                                        const int32_t *__restrict__ nbr, const T *__restrict__ srec,
                                                        const double *__restrict__ V, const T *__restrict__ prim,
                                                        T *__restrict__ grad_out) {

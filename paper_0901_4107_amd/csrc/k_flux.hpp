@@ -536,8 +536,9 @@ __device__ __forceinline__ void face_flux_mixed(bool active, int64_t f, const in
 
 // Mixed-precision face flux kernel: one lane per face; hard faces are
 // appended to a split list (wave-aggregated) and left to k_face_flux_hard.
+// Held to 7 wavefronts per SIMD (72 registers, no spills).
 template <int D, bool LEARNED>
-__global__ void __launch_bounds__(kBlock) k_face_flux_mixed(int64_t nf, const int32_t *__restrict__ fL,
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) k_face_flux_mixed(int64_t nf, const int32_t *__restrict__ fL,
                                                             const int32_t *__restrict__ fR,
                                                             const float *__restrict__ mrec,
                                                             const double *__restrict__ wf64,
