@@ -18,6 +18,12 @@ HIPCC_FLAGS = [
     # matrix-core accumulators in ordinary VGPRs: the fused network then
     # shares the register file with the flux code instead of adding AGPRs
     "-mllvm", "-amdgpu-mfma-vgpr-form",
+    # single precision only (the double path compiles to the same code):
+    # float division and square root by the hardware reciprocal and root
+    # (about 1 ulp) instead of correctly rounded sequences, float denormals
+    # flushed. The float path's error budget is the 1e-6 L1 of the mixed
+    # form, far above these roundings; its states never approach 1e-38.
+    "-fno-hip-fp32-correctly-rounded-divide-sqrt", "-fgpu-flush-denormals-to-zero",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
 ]
 
