@@ -44,10 +44,10 @@ template <int GS, typename T> __device__ __forceinline__ T grp_sum(T v) {
     return grp_reduce<GS>(v, [](T a, T b) { return a + b; });
 }
 template <int GS, typename T> __device__ __forceinline__ T grp_max(T v) {
-    return grp_reduce<GS>(v, [](T a, T b) { return a > b ? a : b; });
+    return grp_reduce<GS>(v, [](T a, T b) { return fmax(a, b); });
 }
 template <int GS, typename T> __device__ __forceinline__ T grp_min(T v) {
-    return grp_reduce<GS>(v, [](T a, T b) { return a < b ? a : b; });
+    return grp_reduce<GS>(v, [](T a, T b) { return fmin(a, b); });
 }
 
 // Block-wide minimum of one double per lane; result valid in lane 0.
@@ -139,7 +139,10 @@ __global__ void __launch_bounds__(1024) k_min_final(int64_t nparts, const double
 // tol = eps_t max(|phi_i|, phi_max - phi_min) (a |Dl| at round-off level counts
 // as zero). Since phi_max - phi_i >= 0 is fixed per cell and rounded
 // division is monotone, the minimum over faces of (phi_max - phi_i)/Dl is
-// (phi_max - phi_i)/max Dl, so two divisions per primitive suffice.
+// (phi_max - phi_i)/max Dl, so two divisions per primitive suffice; and the
+// sides with |Dl| <= tol never hold that maximum unless no side exceeds tol,
+// so the lanes keep plain maxima and minima of Dl and the tolerance is
+// applied once per cell.
 // Mixed mode (T = float): velocities in the record are relative to the
 // cell's generator, so the side record's w_j - w_i restores v_j - v_i.
 // Each lane keeps its first KR sides (A/|r|, f - r_i) in registers for the
@@ -159,22 +162,21 @@ __device__ __forceinline__ void grad_side(const T *s, const T *pj, const T *wi, 
         if (MIXED && c >= 1 && c <= D) dphi += s[1 + D + (c - 1)];
         const T ad = w * dphi;
         for (int k = 0; k < D; k++) a.acc[c][k] += ad * s[1 + k];
-        a.dmx[c] = dphi > a.dmx[c] ? dphi : a.dmx[c];
-        a.dmn[c] = dphi < a.dmn[c] ? dphi : a.dmn[c];
+        a.dmx[c] = fmax(a.dmx[c], dphi);
+        a.dmn[c] = fmin(a.dmn[c], dphi);
     }
 }
 
 template <int D, typename T>
-__device__ __forceinline__ void limit_side(const T *g, const T *dl, const T (&grad)[D + 2][D], const T *tol, T *up,
-                                           T *dn) {
+__device__ __forceinline__ void limit_side(const T *g, const T *dl, const T (&grad)[D + 2][D], T *up, T *dn) {
     constexpr int NV = D + 2;
     T dx[D];
     for (int k = 0; k < D; k++) dx[k] = g[k] - dl[k];
     for (int c = 0; c < NV; c++) {
         T dphi = (T)0;
         for (int k = 0; k < D; k++) dphi += grad[c][k] * dx[k];
-        if (dphi > tol[c]) up[c] = dphi > up[c] ? dphi : up[c];
-        else if (dphi < -tol[c]) dn[c] = -dphi > dn[c] ? -dphi : dn[c];
+        up[c] = fmax(up[c], dphi);
+        dn[c] = fmin(dn[c], dphi);
     }
 }
 
@@ -243,19 +245,19 @@ k_grad_limit(int64_t n, const int32_t *__restrict__ off,
         tol[c] = eps_t * (av > range ? av : range);
     }
     for (int r = 0; r < KR; r++)
-        if (has[r]) limit_side<D, T>(sr[r] + 1, dl, grad, tol, up, dn);
+        if (has[r]) limit_side<D, T>(sr[r] + 1, dl, grad, up, dn);
     for (int32_t q = b + lane + KR * GS; q < e; q += GS) {
         T s2[SR];
         load_rec<SR>(srec + (int64_t)q * SR, s2);
-        limit_side<D, T>(s2 + 1, dl, grad, tol, up, dn);
+        limit_side<D, T>(s2 + 1, dl, grad, up, dn);
     }
     T alpha[NV];
     for (int c = 0; c < NV; c++) {
-        up[c] = grp_max<GS>(up[c]);
-        dn[c] = grp_max<GS>(dn[c]);
+        up[c] = grp_max<GS>(up[c]);   // max Dl (>= 0)
+        dn[c] = grp_min<GS>(dn[c]);   // min Dl (<= 0)
         T al = (T)1;
-        if (up[c] > (T)0) { T p = dmx[c] / up[c]; al = p < al ? p : al; }
-        if (dn[c] > (T)0) { T p = -dmn[c] / dn[c]; al = p < al ? p : al; }
+        if (up[c] > tol[c]) { T p = dmx[c] / up[c]; al = p < al ? p : al; }
+        if (dn[c] < -tol[c]) { T p = dmn[c] / dn[c]; al = p < al ? p : al; }
         alpha[c] = al;
     }
     if (lane == 0) {
