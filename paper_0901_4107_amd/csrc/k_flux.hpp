@@ -46,13 +46,29 @@ struct LaneDiag {
     }
 };
 
+// Wavefront reductions with DPP moves (every lane of the wavefront active):
+// quad swaps, half-row and row mirrors leave each 16-lane row's total in
+// all its lanes; the row broadcasts (lane 15 into rows 1 and 3, lane 31 into
+// rows 2 and 3) then accumulate the whole wavefront in row 3, read from
+// lane 63. Rows a broadcast does not write keep 'old' = 0, the identity of
+// both operations.
+template <int CTRL, int ROWS> __device__ __forceinline__ unsigned dpp_u32(unsigned v) {
+    return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xF, false);
+}
+template <typename Op> __device__ __forceinline__ unsigned wave_reduce(unsigned v, Op op) {
+    v = op(v, dpp_u32<0xB1, 0xF>(v));    // quad_perm [1,0,3,2]
+    v = op(v, dpp_u32<0x4E, 0xF>(v));    // quad_perm [2,3,0,1]
+    v = op(v, dpp_u32<0x141, 0xF>(v));   // row_half_mirror
+    v = op(v, dpp_u32<0x140, 0xF>(v));   // row_mirror
+    v = op(v, dpp_u32<0x142, 0xA>(v));   // row_bcast:15
+    v = op(v, dpp_u32<0x143, 0xC>(v));   // row_bcast:31
+    return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
+}
 __device__ __forceinline__ unsigned wave_sum(unsigned v) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    return wave_reduce(v, [](unsigned a, unsigned b) { return a + b; });
 }
 __device__ __forceinline__ unsigned wave_max(unsigned v) {
-    for (int off = 32; off > 0; off >>= 1) { unsigned o = __shfl_xor(v, off, 64); v = o > v ? o : v; }
-    return v;
+    return wave_reduce(v, [](unsigned a, unsigned b) { return a > b ? a : b; });
 }
 
 // Reduce the lanes' counters over the block; one set of atomics per block.

@@ -124,6 +124,14 @@ def test_riemann_batch_parity():
     d = ctx.mm_get_diag()
     note(f"batch fp64: mean iterations {d['newton_iters'] / S.shape[1]:.2f}, unconverged {d['unconverged']}")
     assert d["unconverged"] == 0
+    # the wavefront and block reductions of the diagnostics, exactly: one
+    # problem per lane, wavefronts of 64 consecutive problems
+    itn = it.cpu().numpy().astype(np.int64)
+    waves = np.concatenate([itn, np.zeros((-len(itn)) % 64, np.int64)]).reshape(-1, 64)
+    assert d["newton_iters"] == int(itn.sum())
+    assert d["newton_max"] == int(itn.max())
+    assert d["wave_iter_max_sum"] == int(waves.max(axis=1).sum())
+    assert d["vacuum"] == int(np.sum(r["case"] != 0))
 
 
 @pytest.fixture(scope="module")
