@@ -10,9 +10,9 @@
 // and then rises monotonically to it; a step that lands at p <= 0 is
 // replaced by a tenth of the previous iterate.
 //
-// Cost notes (gfx950): powers are exp2(y log2 x) (hardware v_exp/v_log in
-// float; the library's double log2/exp2, whose combined error |y log2 x|
-// ulp stays far below the parity bound, in double). u* and the star-state
+// Cost notes (gfx950): powers are exp2(y log2 x) with the hardware v_exp/v_log
+// in float, and exp(y ln x) from short series in double (mm_pow below; a
+// few ulp, far below the parity bound). u* and the star-state
 // powers reuse the last Newton evaluation with a first-order correction in
 // the final step (error O(step^2), below 1e-18 relative at convergence), and
 // integer exponents 2/(g-1) (3 for g = 5/3, 5 for g = 7/5) are multiplied out.
@@ -49,7 +49,39 @@ template <typename T> struct GasConst {
     }
 };
 
-__device__ __forceinline__ double mm_pow(double x, double y) { return exp2(y * log2(x)); }
+// x^y in double as exp(y ln x) for y > 0, the powers of the gas constants
+// the solver takes of positive ratios (a few ulp; x = 0 gives 0, x = inf
+// gives inf, negative x or NaN give NaN):
+//   ln x = e ln2 + 2 atanh(s), x = m 2^e, m in [1/sqrt2, sqrt2),
+//   s = (m - 1)/(m + 1), |s| < 0.1716, atanh by its power series through
+//   s^21 (the first omitted term is below 2^-55 of the sum);
+//   exp t = 2^n exp(r), n = rint(t / ln2), r = t - n ln2 with ln2 split in a
+//   33-bit head and a tail (Cody and Waite's reduction; n times the head is
+//   exact for |n| < 2^20),
+//   exp(r) by its Taylor series through r^13 (omitted part below 2^-56).
+__device__ __forceinline__ double mm_pow(double x, double y) {
+    constexpr double ln2_hi = 0x1.62e42fee00000p-1, ln2_lo = 0x1.a39ef35793c76p-33;
+    int e;
+    double m = frexp(x, &e);               // m in [1/2, 1)
+    if (m < 0.70710678118654752440) { m *= 2.0; e -= 1; }
+    const double sa = (m - 1.0) / (m + 1.0), z = sa * sa;
+    double q = 1.0 / 21.0;
+    q = fma(q, z, 1.0 / 19.0); q = fma(q, z, 1.0 / 17.0); q = fma(q, z, 1.0 / 15.0);
+    q = fma(q, z, 1.0 / 13.0); q = fma(q, z, 1.0 / 11.0); q = fma(q, z, 1.0 / 9.0);
+    q = fma(q, z, 1.0 / 7.0); q = fma(q, z, 1.0 / 5.0); q = fma(q, z, 1.0 / 3.0); q = fma(q, z, 1.0);
+    const double de = (double)e;
+    const double lnx = fma(de, ln2_hi, fma(de, ln2_lo, 2.0 * sa * q));
+    const double t = y * lnx;
+    const double n = rint(t * 1.44269504088896340736);
+    const double r = fma(-n, ln2_lo, fma(-n, ln2_hi, t));
+    double pe = 1.0 / 6227020800.0;         // 1/13!
+    pe = fma(pe, r, 1.0 / 479001600.0); pe = fma(pe, r, 1.0 / 39916800.0); pe = fma(pe, r, 1.0 / 3628800.0);
+    pe = fma(pe, r, 1.0 / 362880.0); pe = fma(pe, r, 1.0 / 40320.0); pe = fma(pe, r, 1.0 / 5040.0);
+    pe = fma(pe, r, 1.0 / 720.0); pe = fma(pe, r, 1.0 / 120.0); pe = fma(pe, r, 1.0 / 24.0);
+    pe = fma(pe, r, 1.0 / 6.0); pe = fma(pe, r, 0.5); pe = fma(pe, r, 1.0); pe = fma(pe, r, 1.0);
+    const double res = ldexp(pe, (int)n);
+    return x > 0.0 ? (x < (double)INFINITY ? res : x) : (x == 0.0 ? 0.0 : (double)NAN);
+}
 __device__ __forceinline__ float mm_pow(float x, float y) { return __builtin_amdgcn_exp2f(y * __builtin_amdgcn_logf(x)); }
 __device__ __forceinline__ double mm_sqrt(double x) { return sqrt(x); }
 __device__ __forceinline__ float mm_sqrt(float x) { return __builtin_sqrtf(x); }
