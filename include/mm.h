@@ -164,8 +164,9 @@ mm_status mm_apply_update(mm_ctx *ctx, const double *face_flux, double *Q);
 /* Steps (ii), (iii), (v), (vi), (vii) on Q in place. dt <= 0 selects the
  * global Courant timestep dt = C min_i R_i / (c_i + |v_i - w_i|) (Section
  * 7.1). If dt_used is non-NULL the call synchronises, stores the timestep
- * used there and returns MM_E_NONFINITE if the new Q holds a non-finite
- * value; with dt_used NULL it returns without waiting. */
+ * used there and returns MM_E_NONFINITE if this step left a non-finite
+ * value in Q (the diagnostics' nonfinite flag keeps any such step until
+ * mm_reset_diag); with dt_used NULL it returns without waiting. */
 mm_status mm_hydro_step(mm_ctx *ctx, double *Q, double dt, double *dt_used);
 
 /* ------------------------------------------------------------------------

@@ -68,16 +68,18 @@ __device__ __forceinline__ double block_min(double v) {
 //   dt_i = C R_i / (c_i + |v_i - w_i|), R_i the radius of the cell's volume.
 // Cells with m <= 0 are vacuum (W = 0) and impose no timestep limit.
 // Writes the primitive record (W and s_i - r_i, whole); in the mixed mode
-// (T = float) the velocity stored is v_i - w_i.
+// (T = float) the velocity stored is v_i - w_i. As the first kernel of a
+// step it clears the step's non-finite flag (step_flag, may be null).
 template <int D, typename T>
 __global__ void __launch_bounds__(kBlock) k_prim_cfl(int64_t n, double gamma, double cfl, const double *__restrict__ V,
                                                      const double *__restrict__ Q, const double *__restrict__ mvel,
                                                      const double *__restrict__ coff, T *__restrict__ prim,
-                                                     double *__restrict__ dt_part) {
+                                                     double *__restrict__ dt_part, int32_t *step_flag) {
     using Y = Lay<D>;
     constexpr int NV = D + 2;
     constexpr bool rel = sizeof(T) == 4;
     const int64_t i = xcd_global_id();
+    if (step_flag && blockIdx.x == 0 && threadIdx.x == 0) *step_flag = 0;
     double dti = INFINITY;
     if (i < n) {
         T r[Y::PREC];
@@ -271,7 +273,8 @@ k_grad_limit(int64_t n, const int32_t *__restrict__ off,
 
 // Step (vii): Q_i <- Q_i - sum of the fluxes of faces where i is left
 // + sum where i is right (Section 3, discrete update), the face sums taken
-// by the cell's lane group. A non-finite result raises the flag.
+// by the cell's lane group. A non-finite result raises flags[0] (kept until
+// the diagnostics are reset) and flags[1] (this step's).
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_update(int64_t n, const int32_t *__restrict__ off,
                                                    const int32_t *__restrict__ ent, const double *__restrict__ flux,
@@ -314,7 +317,10 @@ __global__ void __launch_bounds__(kBlock) k_update(int64_t n, const int32_t *__r
             Q[c * n + i] = q;
             fin = fin && isfinite(q);
         }
-        if (!fin) atomicOr(flags, 1);
+        if (!fin) {
+            atomicOr(flags, 1);       // since the last diagnostics reset
+            atomicOr(flags + 1, 1);   // this step
+        }
     }
 }
 

@@ -174,7 +174,7 @@ static mm_status clear_diag(mm_ctx *c) {
     // fill kernels rather than memset nodes, so callers may capture this
     const int64_t nd = kDiagSlots * sizeof(DiagDev) / sizeof(int32_t);
     k_fill_i32<<<plain_grid(nd), kBlock, 0, c->st()>>>(c->at<int32_t>(c->lay.diag), nd, 0);
-    k_fill_i32<<<1, kBlock, 0, c->st()>>>(c->at<int32_t>(c->lay.flags) + 1, 1, 0);
+    k_fill_i32<<<1, kBlock, 0, c->st()>>>(c->at<int32_t>(c->lay.flags) + 1, 2, 0);
     MM_LAUNCH_CHECK();
     c->faces_done = 0;
     c->waves_done = 0;
@@ -282,7 +282,8 @@ template <int D, typename T> static mm_status gradients_t(mm_ctx *c, const doubl
     hipStream_t s = c->st();
     const T *srec = sizeof(T) == 8 ? (const T *)c->at<double>(L.srec) : (const T *)c->at<float>(L.srec32);
     k_prim_cfl<D, T><<<grid_for(c->n), kBlock, 0, s>>>(c->n, c->p.gamma, c->p.cfl, c->mesh.volume, Q,
-                                                      c->mesh.mesh_vel, c->mesh.centroid_off, rec, dt_part);
+                                                      c->mesh.mesh_vel, c->mesh.centroid_off, rec, dt_part,
+                                                      c->at<int32_t>(L.flags) + 2);
     k_grad_limit<D, T><<<group_grid(D, c->n), kBlock, 0, s>>>(c->n, c->at<int32_t>(L.off), c->at<int32_t>(L.nbr),
                                                               srec, c->mesh.volume, rec, grad_block<D>(c, rec));
     MM_LAUNCH_CHECK();
@@ -393,7 +394,7 @@ mm_status mm_hydro_step(mm_ctx *c, double *Q, double dt, double *dt_used) {
         int32_t nonfin = 0;
         if (dt_src) MM_CHECK(hipMemcpyAsync(dt_used, dt_dev, sizeof(double), hipMemcpyDeviceToHost, s));
         else *dt_used = dt;
-        MM_CHECK(hipMemcpyAsync(&nonfin, c->at<int32_t>(L.flags) + 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        MM_CHECK(hipMemcpyAsync(&nonfin, c->at<int32_t>(L.flags) + 2, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         MM_CHECK(hipStreamSynchronize(s));
         if (nonfin) return MM_E_NONFINITE;
     }

@@ -196,6 +196,26 @@ def test_vacuum_cells():
     assert r.ctx.mm_get_diag()["vacuum"] > 0
 
 
+@pytest.mark.parametrize("mode", [mm.MM_FP64, mm.MM_MIXED])
+def test_nonfinite_step_is_reported(mode):
+    """A NaN in one cell's energy: the step runs to its end (every loop of
+    the kernels is bounded) and reports MM_E_NONFINITE; the next step, on a
+    finite state, reports nothing, while the diagnostics keep the event
+    until they are reset."""
+    wl = random3d(n_side=13, seed=91)
+    r = Run(wl, mode=mode)
+    bad = r.Q.clone()
+    bad[4, 100] = float("nan")
+    with pytest.raises(mm.MMError) as e:
+        r.ctx.mm_hydro_step(bad)
+    assert e.value.status == mm.MM_E_NONFINITE
+    used = r.ctx.mm_hydro_step(r.Q)
+    assert used > 0 and bool(torch.isfinite(r.Q).all())
+    assert r.ctx.mm_get_diag()["nonfinite"] == 1
+    r.ctx.mm_reset_diag()
+    assert r.ctx.mm_get_diag()["nonfinite"] == 0
+
+
 def test_invalid_meshes_are_rejected():
     rng = np.random.default_rng(4)
     mesh = build_mesh(poisson_points(500, 3, rng))
