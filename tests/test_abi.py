@@ -68,6 +68,20 @@ def test_workspace_and_state_errors_without_device():
         assert L.mm_gradients(ctx, None, None, None) == mm.MM_E_ARG
         assert L.mm_face_fluxes(ctx, -1.0, ctypes.c_void_p(256), ctypes.c_void_p(256), ctypes.c_void_p(256)) == mm.MM_E_ARG
         assert L.mm_get_diag(ctx, None) == mm.MM_E_ARG
+        # the largest accepted mesh, and the first refused sizes
+        assert L.mm_workspace_bytes(ctx, (1 << 31) - 2, (1 << 30) - 1) > 0
+        assert L.mm_workspace_bytes(ctx, (1 << 31) - 1, 100) < 0
+        assert L.mm_workspace_bytes(ctx, 100, 1 << 30) < 0
+        # sizes and pointers are checked before anything reaches the device
+        # (the workspace pointer is only recorded, never dereferenced here)
+        assert L.mm_set_workspace(ctx, ctypes.c_void_p(1 << 20), a) == mm.MM_OK
+        def mesh(n, nf, ptr=1 << 21, idx=1 << 22):
+            return mm.mm_mesh(n, nf, ptr, ptr, ptr, idx, idx, ptr, ptr, ptr)
+        for n, nf in [(1, 10), (1000, 0), (0, 0), (1000, 1 << 30), (-5, 10)]:
+            assert L.mm_mesh_upload(ctx, ctypes.byref(mesh(n, nf))) == mm.MM_E_ARG, (n, nf)
+        assert L.mm_mesh_upload(ctx, ctypes.byref(mesh(1000, 8000, idx=None))) == mm.MM_E_ARG
+        assert L.mm_mesh_upload(ctx, ctypes.byref(mesh(2000, 16000))) == mm.MM_E_WORKSPACE
+        assert L.mm_hydro_step(ctx, ctypes.c_void_p(256), 0.0, None) == mm.MM_E_STATE  # still no mesh
     finally:
         L.mm_destroy(ctx)
     assert L.mm_destroy(None) == mm.MM_OK
