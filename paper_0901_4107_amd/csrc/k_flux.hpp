@@ -344,9 +344,8 @@ __device__ __forceinline__ void lab_flux(double rho, double u, double P, const d
     out[NV - 1] = scale * (eps + Piw + 0.5 * mf * w2);
 }
 
-// Double-precision flux of face f (dt A Fhat into F), shared by the face
-// kernel and the cell-centric step kernel so that both give the same bits.
-// Every thread of the block calls it (the learned staging holds barriers);
+// Double-precision flux of face f (dt A Fhat into F), the body of the face
+// kernel. Every thread of the block calls it (the learned staging holds barriers);
 // active = false does no face. LEARNED compiles the fused network in; the
 // standard-guess instantiation carries none of its registers.
 template <int D, bool LEARNED>
@@ -493,9 +492,8 @@ __device__ __forceinline__ void mixed_lab_flux(const MixedFace<D> &m, double rho
 // Mixed-precision flux of face f (dt A Fhat into F): float face states and
 // float Newton; the lab-frame flux and everything after it in double. Faces
 // the float solve judges hard (strong rarefaction or near vacuum, tiny
-// guess, no convergence) come back with hard = true and no flux. Shared by
-// the face kernel and the cell-centric step kernel so that both give the
-// same bits. Every thread of the block calls it (the learned staging holds
+// guess, no convergence) come back with hard = true and no flux. The body
+// of the face kernel. Every thread of the block calls it (the learned staging holds
 // barriers); active = false does no face. While the network runs, the face
 // states wait in LDS, so the network's registers come on top of few live
 // values.
