@@ -11,7 +11,8 @@
  *
  * Layouts (identical to the public ABI so that tests can pass the same
  * arrays to both sides, but re-declared here on purpose):
- *   conserved  Q [D+2][N]  rows m, p_x, p_y(, p_z), E      (cell totals)
+ *   conserved  Q [D+2][N]  rows m, p_x, p_y(, p_z), E      (cell totals);
+ *              [D+3][N] with the total entropy S as last row (Section 3.5)
  *   primitive  W [D+2][N]  rows rho, v_x, v_y(, v_z), P
  *   gradient   G [D+2][D][N]  G[(c*D + k)*N + i] = d W_c / d x_k in cell i
  *   per-face vectors [D][F]; per-cell vectors [D][N]
@@ -517,9 +518,45 @@ void oracle_face_states(const om_mesh *M, const om_params *prm, double dt,
     free(wf);
 }
 
+/* Section 3.5 (poorly resolved cold flows), per face:
+ *   entropy flux  m_F A_U with A_U = P_U / rho_U^g the entropic function of
+ *                 the upwind side of the Riemann problem, the side the
+ *                 solution at the face is sampled from (the sign of the
+ *                 normal face velocity selects it); zero mass flux gives zero;
+ *   shock Mach    for a side K whose pressure the star pressure exceeds (a
+ *                 shock moves into K), the shock speed relative to the
+ *                 unshocked gas over c_K, sqrt((g+1)/(2g) p* / p_K + (g-1)/(2g));
+ *                 the face takes the larger of its two shocks, 0 without one.
+ * s_flux [F] receives dt A m_F A_U, mach [F] the Mach number (both may be
+ * NULL). */
+void oracle_face_fluxes_ex(const om_mesh *M, const om_params *prm, double dt,
+                           const double *W, const double *grad, double *face_flux,
+                           int32_t *fallback, int32_t *kase, double *s_flux, double *mach);
+
+/* The face rule for the Mach number, given the Riemann case and p*. */
+static double riemann_shock_mach(double g, const double *L, const double *R, int kase, double ps)
+{
+    if (kase != OR_NORMAL) return 0.0;
+    double mx = 0.0;
+    const double *K[2] = {L, R};
+    for (int s = 0; s < 2; s++)
+        if (ps > K[s][2]) {
+            double m2 = sqrt((g + 1.0) / (2.0 * g) * ps / K[s][2] + (g - 1.0) / (2.0 * g));
+            if (m2 > mx) mx = m2;
+        }
+    return mx;
+}
+
 void oracle_face_fluxes(const om_mesh *M, const om_params *prm, double dt,
                         const double *W, const double *grad, double *face_flux,
                         int32_t *fallback, int32_t *kase)
+{
+    oracle_face_fluxes_ex(M, prm, dt, W, grad, face_flux, fallback, kase, NULL, NULL);
+}
+
+void oracle_face_fluxes_ex(const om_mesh *M, const om_params *prm, double dt,
+                           const double *W, const double *grad, double *face_flux,
+                           int32_t *fallback, int32_t *kase, double *s_flux, double *mach)
 {
     const int D = M->dim, nv = D + 2;
     const int64_t n = M->n_cells, nf = M->n_faces;
@@ -582,6 +619,11 @@ void oracle_face_fluxes(const om_mesh *M, const om_params *prm, double dt,
         face_flux[0 * nf + f] = scale * mf;
         for (int k = 0; k < D; k++) face_flux[(1 + k) * nf + f] = scale * (Pi[k] + mf * w[k]);
         face_flux[(nv - 1) * nf + f] = scale * (eps + Piw + 0.5 * mf * w2);
+        if (s_flux) {
+            const double *U = side ? Rs : Ls;
+            s_flux[f] = (mf != 0.0) ? scale * mf * (U[2] / pow(U[0], g)) : 0.0;
+        }
+        if (mach) mach[f] = riemann_shock_mach(g, Ls, Rs, k0, st[0]);
     }
     free(wf);
 }
@@ -651,4 +693,83 @@ double oracle_hydro_step(const om_mesh *M, const om_params *prm, double dt, doub
     oracle_apply_update(M, fl, Q);
     free(W); free(gr); free(gl); free(fl);
     return dt;
+}
+
+/* ------------------------------------------------------------------ */
+/* Section 3.5: the total entropy S_i = M_i A_i, A = P / rho^g, carried  */
+/* as one more conserved row of Q ([D+3][N], S last) and advected by the */
+/* entropy fluxes. After the conservative update of all rows, a cell     */
+/* whose surrounding Riemann problems hold no shock of Mach number       */
+/* mach_thresh or more keeps its advected entropy: its pressure follows  */
+/* from it, P = (S/M) rho^g, and its total energy is rebuilt as          */
+/* P V/(g-1) + |p|^2/(2M). Every other cell discards the advected value  */
+/* and takes S = M P / rho^g of its updated state. Reading: a cell keeps */
+/* only with positive new mass and entropy; mach_thresh <= 0 never keeps.*/
+/* kept [N] (may be NULL) receives 1 where the entropy was kept.         */
+/* ------------------------------------------------------------------ */
+void oracle_apply_update_entropy(const om_mesh *M, const om_params *prm, const double *face_flux,
+                                 const double *s_flux, const double *mach, double mach_thresh,
+                                 double *Q, int32_t *kept)
+{
+    const int D = M->dim, nv = D + 2;
+    const int64_t n = M->n_cells, nf = M->n_faces;
+    const double g = prm->gamma;
+    double *mmax = (double *)calloc((size_t)n, sizeof(double));
+    oracle_apply_update(M, face_flux, Q);
+    for (int64_t f = 0; f < nf; f++) {
+        int64_t l = M->face_L[f], r = M->face_R[f];
+        Q[nv * n + l] -= s_flux[f];
+        Q[nv * n + r] += s_flux[f];
+        if (mach[f] > mmax[l]) mmax[l] = mach[f];
+        if (mach[f] > mmax[r]) mmax[r] = mach[f];
+    }
+    for (int64_t i = 0; i < n; i++) {
+        const double m = Q[i], V = M->volume[i], S = Q[nv * n + i];
+        double p2 = 0.0;
+        for (int k = 0; k < D; k++) p2 += Q[(1 + k) * n + i] * Q[(1 + k) * n + i];
+        const int keep = mmax[i] < mach_thresh && m > 0.0 && S > 0.0;
+        if (kept) kept[i] = keep;
+        if (!(m > 0.0)) { Q[nv * n + i] = 0.0; continue; }
+        const double rho = m / V, ke = 0.5 * p2 / m;
+        if (keep) {
+            const double P = (S / m) * pow(rho, g);
+            Q[(nv - 1) * n + i] = P * V / (g - 1.0) + ke;
+        } else {
+            const double P = (g - 1.0) * (Q[(nv - 1) * n + i] - ke) / V;
+            Q[nv * n + i] = m * P / pow(rho, g);
+        }
+    }
+    free(mmax);
+}
+
+/* The step with the entropy row: primitives, gradients, timestep and     */
+/* face states exactly as oracle_hydro_step (from the first D+2 rows),   */
+/* then the entropy update above.                                        */
+double oracle_hydro_step_entropy(const om_mesh *M, const om_params *prm, double dt, double mach_thresh,
+                                 double *Q, int32_t *kept)
+{
+    const int D = M->dim, nv = D + 2;
+    const int64_t n = M->n_cells, nf = M->n_faces;
+    double *W = (double *)malloc(sizeof(double) * nv * n);
+    double *gr = (double *)malloc(sizeof(double) * nv * D * n);
+    double *gl = (double *)malloc(sizeof(double) * nv * D * n);
+    double *fl = (double *)malloc(sizeof(double) * nv * nf);
+    double *sf = (double *)malloc(sizeof(double) * nf);
+    double *mc = (double *)malloc(sizeof(double) * nf);
+    oracle_prim(D, n, prm->gamma, M->volume, Q, W);
+    oracle_gradients(M, W, gr, gl, NULL);
+    if (!(dt > 0.0)) dt = oracle_cfl_dt(M, prm, W);
+    oracle_face_fluxes_ex(M, prm, dt, W, gl, fl, NULL, NULL, sf, mc);
+    oracle_apply_update_entropy(M, prm, fl, sf, mc, mach_thresh, Q, kept);
+    free(W); free(gr); free(gl); free(fl); free(sf); free(mc);
+    return dt;
+}
+
+/* The largest shock Mach number of one Riemann problem (the face rule    */
+/* above), with its star pressure; for tests.                            */
+double oracle_shock_mach(double g, const double *L, const double *R)
+{
+    double out[4], st[2];
+    int k = oracle_riemann(g, L, R, out, st, NULL);
+    return riemann_shock_mach(g, L, R, k, st[0]);
 }

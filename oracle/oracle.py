@@ -58,6 +58,15 @@ def _lib():
         lib.oracle_cfl_dt.argtypes = [ctypes.POINTER(_OMesh), ctypes.POINTER(_OParams), _dp]
         lib.oracle_hydro_step.restype = ctypes.c_double
         lib.oracle_hydro_step.argtypes = [ctypes.POINTER(_OMesh), ctypes.POINTER(_OParams), ctypes.c_double, _dp]
+        lib.oracle_face_fluxes_ex.argtypes = [ctypes.POINTER(_OMesh), ctypes.POINTER(_OParams), ctypes.c_double,
+                                              _dp, _dp, _dp, _ip, _ip, _dp, _dp]
+        lib.oracle_apply_update_entropy.argtypes = [ctypes.POINTER(_OMesh), ctypes.POINTER(_OParams), _dp, _dp, _dp,
+                                                    ctypes.c_double, _dp, _ip]
+        lib.oracle_hydro_step_entropy.restype = ctypes.c_double
+        lib.oracle_hydro_step_entropy.argtypes = [ctypes.POINTER(_OMesh), ctypes.POINTER(_OParams), ctypes.c_double,
+                                                  ctypes.c_double, _dp, _ip]
+        lib.oracle_shock_mach.restype = ctypes.c_double
+        lib.oracle_shock_mach.argtypes = [ctypes.c_double, _dp, _dp]
         _LIB = lib
     return _LIB
 
@@ -150,6 +159,47 @@ def face_fluxes(mesh, gamma, dt, W, grad):
     _lib().oracle_face_fluxes(ctypes.byref(h.s), ctypes.byref(p), float(dt), _d(W), _d(grad),
                               _d(fl), _i(fb), _i(kase))
     return fl, fb, kase
+
+
+def face_fluxes_entropy(mesh, gamma, dt, W, grad):
+    """face_fluxes plus, per face, the entropy flux dt A m_F A_U and the
+    largest shock Mach number of the face's Riemann solution (Section 3.5)."""
+    h = _Held(mesh)
+    W = _f64(W); grad = _f64(grad)
+    fl = np.empty((h.dim + 2, h.nf))
+    sf = np.empty(h.nf)
+    mach = np.empty(h.nf)
+    p = _OParams(float(gamma), 0.0)
+    _lib().oracle_face_fluxes_ex(ctypes.byref(h.s), ctypes.byref(p), float(dt), _d(W), _d(grad),
+                                 _d(fl), None, None, _d(sf), _d(mach))
+    return fl, sf, mach
+
+
+def apply_update_entropy(mesh, gamma, face_flux, s_flux, mach, mach_thresh, Q):
+    """Conservative update of Q [D+3][N] (entropy last) with the Mach
+    switch; returns (Q_new, kept [N])."""
+    h = _Held(mesh)
+    Q = _f64(Q).copy()
+    kept = np.empty(h.n, dtype=np.int32)
+    p = _OParams(float(gamma), 0.0)
+    _lib().oracle_apply_update_entropy(ctypes.byref(h.s), ctypes.byref(p), _d(_f64(face_flux)), _d(_f64(s_flux)),
+                                       _d(_f64(mach)), float(mach_thresh), _d(Q), _i(kept))
+    return Q, kept
+
+
+def hydro_step_entropy(mesh, gamma, cfl, Q, mach_thresh, dt=0.0):
+    """One step with the entropy row (Q [D+3][N]); returns (Q_new, dt_used, kept)."""
+    h = _Held(mesh)
+    Q = _f64(Q).copy()
+    kept = np.empty(h.n, dtype=np.int32)
+    p = _OParams(float(gamma), float(cfl))
+    used = _lib().oracle_hydro_step_entropy(ctypes.byref(h.s), ctypes.byref(p), float(dt), float(mach_thresh),
+                                            _d(Q), _i(kept))
+    return Q, used, kept
+
+
+def shock_mach(gamma, L, R):
+    return _lib().oracle_shock_mach(float(gamma), _d(_f64(L)), _d(_f64(R)))
 
 
 def face_states(mesh, gamma, dt, W, grad):

@@ -49,6 +49,19 @@ def conserved_from_primitive(volume, rho, vel, P, gamma):
     return np.ascontiguousarray(np.concatenate([m[None], p, E[None]], axis=0))
 
 
+def total_entropy(volume, rho, P, gamma):
+    """Total entropy of a cell, S = M A with M = rho V and the entropic
+    function A = P / rho^gamma (the definition of Section 3.5)."""
+    return rho * volume * P / rho ** gamma
+
+
+def with_entropy(wl: "Workload") -> np.ndarray:
+    """The workload's conserved state with the total entropy appended as the
+    last row, [D+3][N], from its initial primitive fields."""
+    rho, _, P = wl.prim
+    return np.ascontiguousarray(np.concatenate([wl.Q, total_entropy(wl.mesh.volume, rho, P, wl.gamma)[None]]))
+
+
 def jittered_lattice(n_side: int, dim: int, jitter: float, rng) -> np.ndarray:
     """Lattice points (i+1/2)/n with each coordinate displaced by
     U(-jitter, +jitter) lattice spacings, in Morton order."""
