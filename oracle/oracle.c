@@ -525,8 +525,13 @@ void oracle_face_states(const om_mesh *M, const om_params *prm, double dt,
  *                 normal face velocity selects it); zero mass flux gives zero;
  *   shock Mach    for a side K whose pressure the star pressure exceeds (a
  *                 shock moves into K), the shock speed relative to the
- *                 unshocked gas over c_K, sqrt((g+1)/(2g) p* / p_K + (g-1)/(2g));
- *                 the face takes the larger of its two shocks, 0 without one.
+ *                 unshocked gas over c_K, sqrt((g+1)/(2g) p* / p_K + (g-1)/(2g)).
+ *                 Reading: the same expression is taken on both sides (on a
+ *                 rarefied side it is below 1), so that the face value, the
+ *                 larger of the two, is continuous where p* crosses p_K and
+ *                 round-off there cannot switch it between 0 and 1; it is the
+ *                 strongest shock's Mach number whenever that exceeds 1, and
+ *                 0 for the vacuum cases (no star state).
  * s_flux [F] receives dt A m_F A_U, mach [F] the Mach number (both may be
  * NULL). */
 void oracle_face_fluxes_ex(const om_mesh *M, const om_params *prm, double dt,
@@ -539,11 +544,10 @@ static double riemann_shock_mach(double g, const double *L, const double *R, int
     if (kase != OR_NORMAL) return 0.0;
     double mx = 0.0;
     const double *K[2] = {L, R};
-    for (int s = 0; s < 2; s++)
-        if (ps > K[s][2]) {
-            double m2 = sqrt((g + 1.0) / (2.0 * g) * ps / K[s][2] + (g - 1.0) / (2.0 * g));
-            if (m2 > mx) mx = m2;
-        }
+    for (int s = 0; s < 2; s++) {
+        double m2 = sqrt((g + 1.0) / (2.0 * g) * ps / K[s][2] + (g - 1.0) / (2.0 * g));
+        if (m2 > mx) mx = m2;
+    }
     return mx;
 }
 
