@@ -12,9 +12,12 @@
  *   hands over with mm_set_workspace.
  * - Conserved states Q are double, structure-of-arrays [D+2][N] (rows m,
  *   p_x, p_y(, p_z), E: cell totals); D is the dimension (2 or 3), N the
- *   number of cells, F the number of faces.
- * - Face fluxes are double, face-major: face_flux[f*(D+2) + c] =
- *   dt * A_f * Fhat_c(f), c over (mass, momentum (D), energy).
+ *   number of cells, F the number of faces. With MM_ENTROPY_MACH, Q is
+ *   [D+3][N], the total entropy S as last row.
+ * - Face fluxes are double, face-major: face_flux[f*FS + c] =
+ *   dt * A_f * Fhat_c(f), c over (mass, momentum (D), energy), FS =
+ *   MM_FLUX_STRIDE(D, entropy) (with the entropy row, then the entropy
+ *   flux and the face's shock Mach number).
  * - The reconstruction buffer (mm_gradients' output) holds
  *   MM_RECON_STRIDE(D) elements per cell (24 in 3D, 16 in 2D) as two
  *   blocks:
@@ -60,6 +63,19 @@ typedef int32_t mm_status;
                         face; double-precision accumulation, lab-frame
                         transform, and Newton for hard faces */
 
+/* Entropy treatment for poorly resolved cold flows (Section 3.5). With
+ * MM_ENTROPY_MACH, Q carries the total entropy S_i = M_i P_i / rho_i^gamma
+ * as one more row ([D+3][N], S last), advected by the entropy flux
+ * m_F A_U of every face (A_U = P / rho^gamma of the upwind side of the
+ * face's Riemann problem). After the update, a cell whose faces' Riemann
+ * solutions hold no shock of Mach number mach_thresh or more (and whose new
+ * mass and entropy are positive) keeps the advected entropy: its pressure
+ * becomes (S/M) rho^gamma and its total energy P V/(gamma-1) + |p|^2/(2M),
+ * so total energy is then not conserved. Every other cell takes
+ * S = M P / rho^gamma of its conservatively updated state. */
+#define MM_ENTROPY_OFF  0
+#define MM_ENTROPY_MACH 1
+
 /* Starting guess of the Newton iteration for the star pressure. */
 #define MM_GUESS_STANDARD 0  /* adaptive PVRS / two-rarefaction / two-shock */
 #define MM_GUESS_LEARNED  1  /* MLP loaded with mm_mlp_load */
@@ -74,7 +90,20 @@ typedef struct {
     double newton_tol64;      /* relative Newton step tolerance, double; <= 0: 1e-10 */
     double newton_tol32;      /* same for the single-precision solve; <= 0: 1e-5 */
     void *stream;             /* hipStream_t */
+    int32_t entropy;          /* MM_ENTROPY_OFF or MM_ENTROPY_MACH */
+    int32_t reserved;
+    double mach_thresh;       /* MM_ENTROPY_MACH: cells whose largest face shock Mach
+                                 number is below this keep their entropy (the paper
+                                 suggests about 1.1); <= 0 never keeps; not NaN */
 } mm_params;
+
+/* Doubles per face record of the face-flux array: the D+2 fluxes
+ * dt A Fhat, then with the entropy row the entropy flux dt A m_F A_U and
+ * the face's Mach number: the larger over its sides of
+ * sqrt((g+1)/(2g) p* / p_K + (g-1)/(2g)), the Mach number of the shock into
+ * side K where p* > p_K and below 1 on a rarefied side; 0 without a star
+ * state. */
+#define MM_FLUX_STRIDE(dim, entropy) ((dim) + 2 + ((entropy) ? 2 : 0))
 
 /* The given tessellation (Section 3, step list item (i)) and the generator
  * velocities w_i (item (iv)). All device pointers, all kept by reference
@@ -105,6 +134,7 @@ typedef struct {
     uint64_t wave_iter_max_sum;  /* sum over 64-lane wavefronts of their max iteration count,
                                     the wavefronts of the double re-solve pass included */
     uint64_t waves;              /* number of wavefronts of the main pass (faces or problems / 64) */
+    uint64_t entropy_kept;       /* MM_ENTROPY_MACH: cell updates that kept the advected entropy */
     int32_t nonfinite;           /* 1 if a step produced a non-finite conserved value */
     int32_t reserved;
 } mm_diag;
@@ -153,12 +183,15 @@ mm_status mm_gradients(mm_ctx *ctx, const double *Q, void *recon);
  * extrapolation to the face centroid and half a step forward in time in the
  * face's rest frame, exact Riemann solution sampled on the face, moving-face
  * flux in the lab frame). `recon` as produced by mm_gradients in the same
- * mode. Writes face_flux [F][D+2] (double in every mode). */
+ * mode. Writes face_flux [F][MM_FLUX_STRIDE] (double in every mode). */
 mm_status mm_face_fluxes(mm_ctx *ctx, double dt, const void *recon, double *face_flux);
 
 /* Step (vii): Q_L -= flux, Q_R += flux for every face (Section 3,
  * discrete update), summed per cell in a fixed order (bitwise reproducible);
- * face_flux [F][D+2] as written by mm_face_fluxes. */
+ * face_flux [F][MM_FLUX_STRIDE] as written by mm_face_fluxes. With
+ * MM_ENTROPY_MACH the entropy row is updated by its fluxes too and each
+ * cell then keeps or re-derives its entropy as described at
+ * MM_ENTROPY_MACH. */
 mm_status mm_apply_update(mm_ctx *ctx, const double *face_flux, double *Q);
 
 /* Steps (ii), (iii), (v), (vi), (vii) on Q in place. dt <= 0 selects the
@@ -168,6 +201,12 @@ mm_status mm_apply_update(mm_ctx *ctx, const double *face_flux, double *Q);
  * value in Q (the diagnostics' nonfinite flag keeps any such step until
  * mm_reset_diag); with dt_used NULL it returns without waiting. */
 mm_status mm_hydro_step(mm_ctx *ctx, double *Q, double dt, double *dt_used);
+
+/* MM_ENTROPY_MACH only (MM_E_ARG otherwise; MM_E_STATE without a mesh):
+ * fill the entropy row of Q [D+3][N] from its other rows, S_i =
+ * M_i P_i / rho_i^gamma with P from the total energy (Section 3.5's
+ * definition; 0 where M_i <= 0). */
+mm_status mm_entropy_init(mm_ctx *ctx, double *Q);
 
 /* ------------------------------------------------------------------------
  * Learned starting guess for the Newton iteration on the star pressure

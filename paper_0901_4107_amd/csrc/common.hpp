@@ -65,6 +65,16 @@ template <int N, typename T> __device__ __forceinline__ void store_rec(T *__rest
     for (int k = N / per * per; k < N; k++) p[k] = o[k];
 }
 
+// Device-side diagnostic accumulators (mirrors mm_diag's counters). Each
+// block adds into one of kDiagSlots copies (chosen by block index) so that
+// the per-block atomics spread over many addresses instead of serialising
+// on one; the host sums the slots.
+constexpr int kDiagSlots = 256;
+struct DiagDev {
+    unsigned long long newton_iters, newton_max, unconverged, vacuum, positivity_fallback, fp64_fallback,
+        guess_fallback, wave_iter_max_sum, entropy_kept;
+};
+
 // A list of flagged items (hard faces or problems) split into kLists
 // sub-lists, one per residue of the producing block index, each with its
 // own counter on its own 128-byte line: appends from different blocks

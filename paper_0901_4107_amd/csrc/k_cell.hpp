@@ -10,6 +10,7 @@
 
 #include "common.hpp"
 #include "layout.hpp"
+#include "riemann.hpp"
 
 namespace mm {
 
@@ -275,20 +276,29 @@ k_grad_limit(int64_t n, const int32_t *__restrict__ off,
 // + sum where i is right (Section 3, discrete update), the face sums taken
 // by the cell's lane group. A non-finite result raises flags[0] (kept until
 // the diagnostics are reset) and flags[1] (this step's).
-template <int D>
+// ENT (Section 3.5): Q has the total entropy S as row D+2 and each flux
+// record carries the face's entropy flux and shock Mach number. S is
+// updated by its flux sum like the other rows; then a cell whose faces'
+// largest Mach number is below mach_thresh, with positive new mass and
+// entropy, keeps it: P = (S/M) rho^gamma and E = P V/(gamma-1) + |p|^2/(2M).
+// Every other cell takes S = M P / rho^gamma of its updated state (0 for
+// M <= 0). The cells that keep are counted in entropy_kept.
+template <int D, bool ENT>
 __global__ void __launch_bounds__(kBlock) k_update(int64_t n, const int32_t *__restrict__ off,
                                                    const int32_t *__restrict__ ent, const double *__restrict__ flux,
-                                                   double *__restrict__ Q, int32_t *__restrict__ flags) {
-    using Y = Lay<D>;
+                                                   double *__restrict__ Q, int32_t *__restrict__ flags,
+                                                   const double *__restrict__ V, double gamma, double mach_thresh,
+                                                   DiagDev *diag) {
     constexpr int NV = D + 2;
-    constexpr int FS = Y::FSTRIDE;
+    constexpr int FS = NV + (ENT ? 2 : 0);   // record stride
+    constexpr int NS = NV + (ENT ? 1 : 0);   // summed rows
     constexpr int GS = Group<D>::GS;
-    constexpr int KR = 5;
+    constexpr int KR = ENT ? 4 : 5;
     const int lane = threadIdx.x % GS;
     const int64_t i = xcd_tile() * (kBlock / GS) + threadIdx.x / GS;
     if (i >= n) return;
-    double acc[NV];
-    for (int c = 0; c < NV; c++) acc[c] = 0.0;
+    double acc[NS], mx = 0.0;
+    for (int c = 0; c < NS; c++) acc[c] = 0.0;
     const int32_t b = off[i], e = off[i + 1];
     // the lane's first KR sides with their flux records in flight together
     // (an absent side reads record 0 and adds nothing), then the rare rest
@@ -300,28 +310,80 @@ __global__ void __launch_bounds__(kBlock) k_update(int64_t n, const int32_t *__r
         load_rec<FS>(flux + (int64_t)(en >> 1) * FS, F[r]);
     }
     for (int r = 0; r < KR; r++)
-        if (sg[r] != 0.0)
-            for (int c = 0; c < NV; c++) acc[c] += sg[r] * F[r][c];
+        if (sg[r] != 0.0) {
+            for (int c = 0; c < NS; c++) acc[c] += sg[r] * F[r][c];
+            if constexpr (ENT) mx = fmax(mx, F[r][NV + 1]);
+        }
     for (int32_t q = b + lane + KR * GS; q < e; q += GS) {
         const int32_t en = ent[q];
         double Fq[FS];
         load_rec<FS>(flux + (int64_t)(en >> 1) * FS, Fq);
         const double s1 = (en & 1) ? 1.0 : -1.0;
-        for (int c = 0; c < NV; c++) acc[c] += s1 * Fq[c];
+        for (int c = 0; c < NS; c++) acc[c] += s1 * Fq[c];
+        if constexpr (ENT) mx = fmax(mx, Fq[NV + 1]);
     }
-    for (int c = 0; c < NV; c++) acc[c] = grp_sum<GS>(acc[c]);
+    for (int c = 0; c < NS; c++) acc[c] = grp_sum<GS>(acc[c]);
+    if constexpr (ENT) mx = grp_max<GS>(mx);
+    bool keep = false;
     if (lane == 0) {
+        double q[NS];
+        for (int c = 0; c < NS; c++) q[c] = Q[c * n + i] + acc[c];
+        if constexpr (ENT) {
+            const double m = q[0], S = q[NV];
+            keep = mx < mach_thresh && m > 0.0 && S > 0.0;
+            if (!(m > 0.0)) {
+                q[NV] = 0.0;
+            } else {
+                double p2 = 0.0;
+                for (int k = 0; k < D; k++) p2 += q[1 + k] * q[1 + k];
+                const double vol = V[i], rho = m / vol, ke = 0.5 * p2 / m;
+                if (keep) {
+                    const double P = (S / m) * mm_pow(rho, gamma);
+                    q[NV - 1] = P * vol / (gamma - 1.0) + ke;
+                } else {
+                    const double P = (gamma - 1.0) * (q[NV - 1] - ke) / vol;
+                    q[NV] = m * P / mm_pow(rho, gamma);
+                }
+            }
+        }
         bool fin = true;
-        for (int c = 0; c < NV; c++) {
-            const double q = Q[c * n + i] + acc[c];
-            Q[c * n + i] = q;
-            fin = fin && isfinite(q);
+        for (int c = 0; c < NS; c++) {
+            Q[c * n + i] = q[c];
+            fin = fin && isfinite(q[c]);
         }
         if (!fin) {
             atomicOr(flags, 1);       // since the last diagnostics reset
             atomicOr(flags + 1, 1);   // this step
         }
     }
+    if constexpr (ENT) {
+        // every lane of the wavefront whose group is live takes part; lane 0
+        // of the wavefront holds the lowest cell index, so it is live too
+        const unsigned long long kb = __ballot(keep);
+        if (diag && (threadIdx.x & 63) == 0 && kb)
+            atomicAdd(&diag[blockIdx.x & (kDiagSlots - 1)].entropy_kept, (unsigned long long)__popcll(kb));
+    }
+}
+
+// The total entropy of every cell from its conserved state (Section 3.5):
+// S = M P / rho^gamma with P = (gamma-1)(E - |p|^2/(2M))/V; 0 for M <= 0.
+// Q is [D+3][N], row D+2 written.
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_entropy_init(int64_t n, const double *__restrict__ V, double gamma,
+                                                         double *__restrict__ Q) {
+    constexpr int NV = D + 2;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const double m = Q[i];
+    double S = 0.0;
+    if (m > 0.0) {
+        double p2 = 0.0;
+        for (int k = 0; k < D; k++) p2 += Q[(1 + k) * n + i] * Q[(1 + k) * n + i];
+        const double vol = V[i], rho = m / vol;
+        const double P = (gamma - 1.0) * (Q[(NV - 1) * n + i] - 0.5 * p2 / m) / vol;
+        S = m * P / mm_pow(rho, gamma);
+    }
+    Q[NV * n + i] = S;
 }
 
 }  // namespace mm

@@ -22,15 +22,6 @@
 
 namespace mm {
 
-// Device-side diagnostic accumulators (mirrors mm_diag's counters). Each
-// block adds into one of kDiagSlots copies (chosen by block index) so that
-// the per-block atomics spread over many addresses instead of serialising
-// on one; the host sums the slots.
-constexpr int kDiagSlots = 256;
-struct DiagDev {
-    unsigned long long newton_iters, newton_max, unconverged, vacuum, positivity_fallback, fp64_fallback,
-        guess_fallback, wave_iter_max_sum;
-};
 
 struct LaneDiag {
     unsigned iters = 0, itmax = 0, unconv = 0, vacuum = 0, posfb = 0, fp64fb = 0, guessfb = 0;
@@ -322,6 +313,36 @@ __device__ __forceinline__ T learned_guess(const MlpPacked *P, bool want, T rhoL
     return corr;
 }
 
+// Section 3.5 (poorly resolved cold flows), per face: the entropy flux is
+// the mass flux times A_U = P_U / rho_U^gamma of the upwind side of the
+// Riemann problem, the side the face state is sampled from (AU = 0 for a
+// vacuum side, whose mass flux vanishes). The face's Mach number is the
+// larger over its two sides of sqrt((g+1)/(2g) p*/p_K + (g-1)/(2g)): on a
+// side the star pressure exceeds, the Mach number of the shock moving into
+// it; on a rarefied side below 1, which keeps the value continuous where
+// p* crosses p_K. 0 without a star state (vacuum cases).
+template <typename T>
+__device__ __forceinline__ void entropy_terms(const FaceState<T> &fs, T rhoL, T PL, T rhoR, T PR,
+                                              const GasConst<T> &k, T &AU, T &mach) {
+    const T rhoU = fs.side ? rhoR : rhoL, PU = fs.side ? PR : PL;
+    AU = rhoU > (T)0 ? PU / mm_pow(rhoU, k.g) : (T)0;
+    mach = (T)0;
+    if (fs.pstar > (T)0) {
+        const T mL = mm_sqrt(k.zs1 * fs.pstar / PL + k.zs2), mR = mm_sqrt(k.zs1 * fs.pstar / PR + k.zs2);
+        mach = mL > mR ? mL : mR;
+    }
+}
+
+// One face's record: the NV fluxes, then (FS = NV + 2) the entropy flux and
+// the Mach number.
+template <int NV, int FS>
+__device__ __forceinline__ void store_face(double *p, const double (&F)[NV], const double (&X)[2]) {
+    double r[FS];
+    for (int c = 0; c < NV; c++) r[c] = F[c];
+    for (int c = NV; c < FS; c++) r[c] = X[c - NV];
+    store_rec<FS>(p, r);
+}
+
 // Lab-frame moving-face flux in double from the sampled face-frame state
 // (rho_F, u_F, P_F), the upwind transverse velocity tv, the normal n and
 // the face velocity w, times scale (dt A).
@@ -347,13 +368,14 @@ __device__ __forceinline__ void lab_flux(double rho, double u, double P, const d
 // Double-precision flux of face f (dt A Fhat into F), the body of the face
 // kernel. Every thread of the block calls it (the learned staging holds barriers);
 // active = false does no face. LEARNED compiles the fused network in; the
-// standard-guess instantiation carries none of its registers.
-template <int D, bool LEARNED>
+// standard-guess instantiation carries none of its registers. ENT adds the
+// entropy flux and the shock Mach number (X).
+template <int D, bool LEARNED, bool ENT>
 __device__ __forceinline__ void face_flux64(bool active, int64_t f, const int32_t *__restrict__ fL,
                                             const int32_t *__restrict__ fR, const double *__restrict__ frec,
                                             const double *__restrict__ prim, const double *__restrict__ grad,
                                             double dt, const GasConst<double> &kg, double tol, int maxit,
-                                            const MlpPacked *mlp, LaneDiag &ld, double (&F)[D + 2]) {
+                                            const MlpPacked *mlp, LaneDiag &ld, double (&F)[D + 2], double (&X)[2]) {
     using Y = Lay<D>;
     constexpr int NV = D + 2;
     double A = 0.0, nrm[D], w[D], xl[NV], xr[NV], uL = 0.0, uR = 0.0;
@@ -400,12 +422,19 @@ __device__ __forceinline__ void face_flux64(bool active, int64_t f, const int32_
         double tv[D];
         for (int k = 0; k < D; k++) tv[k] = xs[1 + k] - un * nrm[k];
         lab_flux<D>(fs.rho, fs.u, fs.P, tv, nrm, w, kg.g_over_gm1, dt * A, F);
+        if constexpr (ENT) {
+            double AU, mach;
+            entropy_terms<double>(fs, xl[0], xl[NV - 1], xr[0], xr[NV - 1], kg, AU, mach);
+            X[0] = F[0] * AU;
+            X[1] = mach;
+        }
     }
 }
 
 // Double-precision face flux kernel: one lane per face, fluxes stored
-// face-major.
-template <int D, bool LEARNED>
+// face-major (ENT: each record followed by the entropy flux and the Mach
+// number).
+template <int D, bool LEARNED, bool ENT>
 __global__ void __launch_bounds__(kBlock) k_face_flux64(int64_t nf, const int32_t *__restrict__ fL,
                                                         const int32_t *__restrict__ fR, const double *__restrict__ frec,
                                                         const double *__restrict__ prim, const double *__restrict__ grad,
@@ -413,13 +442,14 @@ __global__ void __launch_bounds__(kBlock) k_face_flux64(int64_t nf, const int32_
                                                         GasConst<double> kg, double tol, int maxit,
                                                         const MlpPacked *mlp, double *__restrict__ flux, DiagDev *diag) {
     constexpr int NV = D + 2;
+    constexpr int FS = NV + (ENT ? 2 : 0);
     const int64_t f = xcd_global_id();
     const bool active = f < nf;
     LaneDiag ld;
     const double dt = dt_ptr ? *dt_ptr : dt_val;
-    double F[NV];
-    face_flux64<D, LEARNED>(active, f, fL, fR, frec, prim, grad, dt, kg, tol, maxit, mlp, ld, F);
-    if (active) store_rec<NV>(flux + f * NV, F);
+    double F[NV], X[2];
+    face_flux64<D, LEARNED, ENT>(active, f, fL, fR, frec, prim, grad, dt, kg, tol, maxit, mlp, ld, F, X);
+    if (active) store_face<NV, FS>(flux + f * FS, F, X);
     if (diag) flush_diag(ld, diag);
 }
 
@@ -497,13 +527,13 @@ __device__ __forceinline__ void mixed_lab_flux(const MixedFace<D> &m, double rho
 // barriers); active = false does no face. While the network runs, the face
 // states wait in LDS, so the network's registers come on top of few live
 // values.
-template <int D, bool LEARNED>
+template <int D, bool LEARNED, bool ENT>
 __device__ __forceinline__ void face_flux_mixed(bool active, int64_t f, const int32_t *__restrict__ fL,
                                                 const int32_t *__restrict__ fR, const float *__restrict__ mrec,
                                                 const double *__restrict__ wf64, const float *__restrict__ prim,
                                                 const float *__restrict__ grad, double dt, const GasConst<float> &kf,
                                                 double g_over_gm1, float tol32, int maxit, const MlpPacked *mlp,
-                                                LaneDiag &ld, bool &hard, double (&F)[D + 2]) {
+                                                LaneDiag &ld, bool &hard, double (&F)[D + 2], double (&X)[2]) {
     constexpr int NV = D + 2;
     hard = false;
     MixedFace<D> m;
@@ -544,14 +574,22 @@ __device__ __forceinline__ void face_flux_mixed(bool active, int64_t f, const in
     if (active) {
         FaceState<float> fs = solve_face<float>(m.xl[0], m.uL, m.xl[NV - 1], m.xr[0], m.uR, m.xr[NV - 1], kf, tol32,
                                                 maxit, pl, true, ld, hard);
-        if (!hard) mixed_lab_flux<D>(m, fs.rho, fs.u, fs.P, fs.side, wf64, f, g_over_gm1, dt, F);
+        if (!hard) {
+            mixed_lab_flux<D>(m, fs.rho, fs.u, fs.P, fs.side, wf64, f, g_over_gm1, dt, F);
+            if constexpr (ENT) {
+                float AU, mach;
+                entropy_terms<float>(fs, m.xl[0], m.xl[NV - 1], m.xr[0], m.xr[NV - 1], kf, AU, mach);
+                X[0] = F[0] * (double)AU;
+                X[1] = (double)mach;
+            }
+        }
     }
 }
 
 // Mixed-precision face flux kernel: one lane per face; hard faces are
 // appended to a split list (wave-aggregated) and left to k_face_flux_hard.
 // Held to 7 wavefronts per SIMD (72 registers, no spills).
-template <int D, bool LEARNED>
+template <int D, bool LEARNED, bool ENT>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) k_face_flux_mixed(int64_t nf, const int32_t *__restrict__ fL,
                                                             const int32_t *__restrict__ fR,
                                                             const float *__restrict__ mrec,
@@ -564,15 +602,16 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))
                                                             double *__restrict__ flux, int32_t *__restrict__ hard_list,
                                                             int64_t cap, DiagDev *diag) {
     constexpr int NV = D + 2;
+    constexpr int FS = NV + (ENT ? 2 : 0);
     const int64_t f = xcd_global_id();
     const bool active = f < nf;
     LaneDiag ld;
     bool hard;
     const double dt = dt_ptr ? *dt_ptr : dt_val;
-    double F[NV];
-    face_flux_mixed<D, LEARNED>(active, f, fL, fR, mrec, wf64, prim, grad, dt, kf, g_over_gm1, tol32, maxit, mlp,
-                                ld, hard, F);
-    if (active && !hard) store_rec<NV>(flux + f * NV, F);
+    double F[NV], X[2];
+    face_flux_mixed<D, LEARNED, ENT>(active, f, fL, fR, mrec, wf64, prim, grad, dt, kf, g_over_gm1, tol32, maxit,
+                                     mlp, ld, hard, F, X);
+    if (active && !hard) store_face<NV, FS>(flux + f * FS, F, X);
     list_append(hard_list, cap, hard, (int32_t)f);
     if (diag) flush_diag(ld, diag);
 }
@@ -581,7 +620,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))
 // list of sub-list capacity cap). A fixed grid walks the list, so the
 // launch needs no host-side count; the float face states are recomputed by
 // the same code, hence identical.
-template <int D>
+template <int D, bool ENT>
 __global__ void __launch_bounds__(kBlock) k_face_flux_hard(const int32_t *__restrict__ fL,
                                                            const int32_t *__restrict__ fR,
                                                            const float *__restrict__ mrec,
@@ -593,6 +632,7 @@ __global__ void __launch_bounds__(kBlock) k_face_flux_hard(const int32_t *__rest
                                                            const int32_t *__restrict__ hard_list, int64_t cap,
                                                            double *__restrict__ flux, DiagDev *diag) {
     constexpr int NV = D + 2;
+    constexpr int FS = NV + (ENT ? 2 : 0);
     const ListWalk lw = list_walk(hard_list, cap);
     const double dt = dt_ptr ? *dt_ptr : dt_val;
     LaneDiag ld;
@@ -603,9 +643,16 @@ __global__ void __launch_bounds__(kBlock) k_face_flux_hard(const int32_t *__rest
         FaceState<double> fd = solve_face<double>(m.xl[0], m.uL, m.xl[NV - 1], m.xr[0], m.uR, m.xr[NV - 1], kg,
                                                   tol64, 50, no_guess<double>(), false, ld, h2);
         ld.fp64fb += 1;
-        double F[NV];
+        double F[NV], X[2];
         mixed_lab_flux<D>(m, fd.rho, fd.u, fd.P, fd.side, wf64, f, kg.g_over_gm1, dt, F);
-        store_rec<NV>(flux + f * NV, F);
+        if constexpr (ENT) {
+            double AU, mach;
+            entropy_terms<double>(fd, (double)m.xl[0], (double)m.xl[NV - 1], (double)m.xr[0], (double)m.xr[NV - 1],
+                                  kg, AU, mach);
+            X[0] = F[0] * AU;
+            X[1] = mach;
+        }
+        store_face<NV, FS>(flux + f * FS, F, X);
     }
     if (diag) flush_diag(ld, diag);
 }

@@ -35,7 +35,7 @@ struct Layout {
     int64_t total;
 };
 
-Layout make_layout(int D, int mode, int64_t n, int64_t nf) {
+Layout make_layout(int D, int mode, bool ent, int64_t n, int64_t nf) {
     const int NV = D + 2;
     const int REC = (D == 3) ? Lay<3>::REC : Lay<2>::REC;
     const int FREC = (D == 3) ? Lay<3>::FREC : Lay<2>::FREC;
@@ -58,7 +58,7 @@ Layout make_layout(int D, int mode, int64_t n, int64_t nf) {
     L.ent = take(2 * nf * sizeof(int32_t));
     L.nbr = take(2 * nf * sizeof(int32_t));
     L.frec = take(nf * FREC * sizeof(double));
-    L.flux = take(nf * ((D == 3) ? Lay<3>::FSTRIDE : Lay<2>::FSTRIDE) * sizeof(double));
+    L.flux = take(nf * (NV + (ent ? 2 : 0)) * sizeof(double));
     L.srec = L.srec32 = L.mrec = L.wf64 = L.rec32 = L.rec = L.hard = -1;
     if (mode == MM_FP64) {
         L.srec = take(2 * nf * Lay<3>::SREC64 * sizeof(double));
@@ -135,6 +135,8 @@ mm_status mm_create(const mm_params *params, mm_ctx **out) {
     if (params->mode != MM_FP64 && params->mode != MM_MIXED) return MM_E_ARG;
     if (params->guess != MM_GUESS_STANDARD && params->guess != MM_GUESS_LEARNED) return MM_E_ARG;
     if (!(params->gamma > 1.0) || !(params->cfl > 0.0)) return MM_E_ARG;
+    if (params->entropy != MM_ENTROPY_OFF && params->entropy != MM_ENTROPY_MACH) return MM_E_ARG;
+    if (params->entropy != MM_ENTROPY_OFF && params->mach_thresh != params->mach_thresh) return MM_E_ARG;
     mm_ctx *c = new (std::nothrow) mm_ctx();
     if (!c) return MM_E_ARG;
     c->p = *params;
@@ -154,7 +156,7 @@ mm_status mm_destroy(mm_ctx *ctx) {
 int64_t mm_workspace_bytes(const mm_ctx *ctx, int64_t n_cells, int64_t n_faces) {
     if (!ctx || n_cells < 2 || n_faces < 1 || n_faces >= (int64_t(1) << 30) || n_cells >= (int64_t(1) << 31) - 1)
         return -1;
-    return make_layout(ctx->D, ctx->p.mode, n_cells, n_faces).total;
+    return make_layout(ctx->D, ctx->p.mode, ctx->p.entropy != 0, n_cells, n_faces).total;
 }
 
 mm_status mm_set_workspace(mm_ctx *ctx, void *dev_ptr, int64_t bytes) {
@@ -166,7 +168,7 @@ mm_status mm_set_workspace(mm_ctx *ctx, void *dev_ptr, int64_t bytes) {
     ctx->diag_ready = false;
     // fixed-size regions (flags, diagnostics, network) sit at offsets that
     // no mesh changes
-    ctx->lay = make_layout(ctx->D, ctx->p.mode, 2, 1);
+    ctx->lay = make_layout(ctx->D, ctx->p.mode, ctx->p.entropy != 0, 2, 1);
     return MM_OK;
 }
 
@@ -184,7 +186,7 @@ static mm_status clear_diag(mm_ctx *c) {
 
 // Workspace present and its fixed regions initialised.
 static mm_status need_ws(mm_ctx *c) {
-    if (!c->ws || c->ws_bytes < make_layout(c->D, c->p.mode, 2, 1).total) return MM_E_STATE;
+    if (!c->ws || c->ws_bytes < make_layout(c->D, c->p.mode, c->p.entropy != 0, 2, 1).total) return MM_E_STATE;
     if (!c->diag_ready) return clear_diag(c);
     return MM_OK;
 }
@@ -233,7 +235,7 @@ mm_status mm_mesh_upload(mm_ctx *c, const mm_mesh *m) {
     if (!m->volume || !m->centroid_off || !m->mesh_vel || !m->face_L || !m->face_R || !m->face_area ||
         !m->face_ctr || !m->face_sep)
         return MM_E_ARG;
-    Layout L = make_layout(c->D, c->p.mode, n, nf);
+    Layout L = make_layout(c->D, c->p.mode, c->p.entropy != 0, n, nf);
     if (L.total > c->ws_bytes) return MM_E_WORKSPACE;
     c->have_mesh = false;
     c->lay = L;
@@ -303,7 +305,7 @@ mm_status mm_gradients(mm_ctx *c, const double *Q, void *recon) {
     return gradients_into(c, Q, recon, c->at<double>(c->lay.dtpart));
 }
 
-template <int D>
+template <int D, bool ENT>
 static mm_status fluxes_t(mm_ctx *c, const double *dt_dev, double dt, const void *rec, double *flux) {
     const Layout &L = c->lay;
     hipStream_t s = c->st();
@@ -312,7 +314,7 @@ static mm_status fluxes_t(mm_ctx *c, const double *dt_dev, double dt, const void
     const GasConst<double> kg(c->p.gamma);
     const GasConst<float> kf(c->p.gamma);
     if (c->p.mode == MM_FP64) {
-        auto kern = mlp ? k_face_flux64<D, true> : k_face_flux64<D, false>;
+        auto kern = mlp ? k_face_flux64<D, true, ENT> : k_face_flux64<D, false, ENT>;
         const double *prim = (const double *)rec;
         kern<<<grid_for(c->nf), kBlock, 0, s>>>(c->nf, c->mesh.face_L, c->mesh.face_R, c->at<double>(L.frec), prim,
                                                 grad_block<D>(c, prim), dt_dev, dt, kg, c->p.newton_tol64,
@@ -321,13 +323,13 @@ static mm_status fluxes_t(mm_ctx *c, const double *dt_dev, double dt, const void
         int32_t *hard = c->at<int32_t>(L.hard);
         const int64_t cap = list_cap(grid_for(c->nf));
         k_fill_i32<<<kLists * kListPad / kBlock, kBlock, 0, s>>>(hard, kLists * kListPad, 0);
-        auto kern = mlp ? k_face_flux_mixed<D, true> : k_face_flux_mixed<D, false>;
+        auto kern = mlp ? k_face_flux_mixed<D, true, ENT> : k_face_flux_mixed<D, false, ENT>;
         const float *prim = (const float *)rec;
         kern<<<grid_for(c->nf), kBlock, 0, s>>>(c->nf, c->mesh.face_L, c->mesh.face_R, c->at<float>(L.mrec),
                                                 c->at<double>(L.wf64), prim, grad_block<D>(c, prim), dt_dev, dt, kf,
                                                 kg.g_over_gm1, (float)c->p.newton_tol32, c->p.newton_max_iter, mlp,
                                                 flux, hard, cap, diag);
-        k_face_flux_hard<D><<<kHardGrid, kBlock, 0, s>>>(c->mesh.face_L, c->mesh.face_R, c->at<float>(L.mrec),
+        k_face_flux_hard<D, ENT><<<kHardGrid, kBlock, 0, s>>>(c->mesh.face_L, c->mesh.face_R, c->at<float>(L.mrec),
                                                         c->at<double>(L.wf64), prim, grad_block<D>(c, prim), dt_dev,
                                                         dt, kf.g,
                                                         kg, c->p.newton_tol64, hard, cap, flux, diag);
@@ -339,7 +341,9 @@ static mm_status fluxes_t(mm_ctx *c, const double *dt_dev, double dt, const void
 static mm_status fluxes_into(mm_ctx *c, const double *dt_dev, double dt, const void *rec, double *flux) {
     c->faces_done += (uint64_t)c->nf;
     c->waves_done += (uint64_t)((c->nf + 63) / 64);
-    return c->D == 3 ? fluxes_t<3>(c, dt_dev, dt, rec, flux) : fluxes_t<2>(c, dt_dev, dt, rec, flux);
+    if (c->p.entropy)
+        return c->D == 3 ? fluxes_t<3, true>(c, dt_dev, dt, rec, flux) : fluxes_t<2, true>(c, dt_dev, dt, rec, flux);
+    return c->D == 3 ? fluxes_t<3, false>(c, dt_dev, dt, rec, flux) : fluxes_t<2, false>(c, dt_dev, dt, rec, flux);
 }
 
 mm_status mm_face_fluxes(mm_ctx *c, double dt, const void *recon, double *face_flux) {
@@ -349,15 +353,31 @@ mm_status mm_face_fluxes(mm_ctx *c, double dt, const void *recon, double *face_f
     return fluxes_into(c, nullptr, dt, recon, face_flux);
 }
 
-static mm_status update_into(mm_ctx *c, const double *flux, double *Q) {
+template <int D, bool ENT> static void launch_update(mm_ctx *c, const double *flux, double *Q) {
     const Layout &L = c->lay;
-    const unsigned g = group_grid(c->D, c->n);
-    if (c->D == 3)
-        k_update<3><<<g, kBlock, 0, c->st()>>>(c->n, c->at<int32_t>(L.off), c->at<int32_t>(L.ent), flux, Q,
-                                              c->at<int32_t>(L.flags) + 1);
-    else
-        k_update<2><<<g, kBlock, 0, c->st()>>>(c->n, c->at<int32_t>(L.off), c->at<int32_t>(L.ent), flux, Q,
-                                              c->at<int32_t>(L.flags) + 1);
+    k_update<D, ENT><<<group_grid(D, c->n), kBlock, 0, c->st()>>>(
+        c->n, c->at<int32_t>(L.off), c->at<int32_t>(L.ent), flux, Q, c->at<int32_t>(L.flags) + 1, c->mesh.volume,
+        c->p.gamma, c->p.mach_thresh, c->at<DiagDev>(L.diag));
+}
+
+static mm_status update_into(mm_ctx *c, const double *flux, double *Q) {
+    if (c->p.entropy) {
+        if (c->D == 3) launch_update<3, true>(c, flux, Q);
+        else launch_update<2, true>(c, flux, Q);
+    } else {
+        if (c->D == 3) launch_update<3, false>(c, flux, Q);
+        else launch_update<2, false>(c, flux, Q);
+    }
+    MM_LAUNCH_CHECK();
+    return MM_OK;
+}
+
+mm_status mm_entropy_init(mm_ctx *c, double *Q) {
+    if (!c || !Q) return MM_E_ARG;
+    if (!c->p.entropy) return MM_E_ARG;
+    if (!c->have_mesh) return MM_E_STATE;
+    if (c->D == 3) k_entropy_init<3><<<plain_grid(c->n), kBlock, 0, c->st()>>>(c->n, c->mesh.volume, c->p.gamma, Q);
+    else k_entropy_init<2><<<plain_grid(c->n), kBlock, 0, c->st()>>>(c->n, c->mesh.volume, c->p.gamma, Q);
     MM_LAUNCH_CHECK();
     return MM_OK;
 }
@@ -526,6 +546,7 @@ mm_status mm_get_diag(mm_ctx *c, mm_diag *out) {
         d.fp64_fallback += slots[k].fp64_fallback;
         d.guess_fallback += slots[k].guess_fallback;
         d.wave_iter_max_sum += slots[k].wave_iter_max_sum;
+        d.entropy_kept += slots[k].entropy_kept;
     }
     std::memset(out, 0, sizeof(*out));
     out->faces = c->faces_done;
@@ -537,6 +558,7 @@ mm_status mm_get_diag(mm_ctx *c, mm_diag *out) {
     out->fp64_fallback = d.fp64_fallback;
     out->guess_fallback = d.guess_fallback;
     out->wave_iter_max_sum = d.wave_iter_max_sum;
+    out->entropy_kept = d.entropy_kept;
     out->waves = c->waves_done;
     out->nonfinite = nonfin;
     return MM_OK;

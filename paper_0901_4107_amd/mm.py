@@ -20,6 +20,7 @@ LIBMM_PATH = os.path.join(_HERE, "libmm.so")
 MM_OK, MM_E_ARG, MM_E_MESH, MM_E_DEVICE, MM_E_STATE, MM_E_WORKSPACE, MM_E_NONFINITE = 0, -1, -2, -3, -4, -5, -6
 MM_FP64, MM_MIXED = 0, 1
 MM_GUESS_STANDARD, MM_GUESS_LEARNED = 0, 1
+MM_ENTROPY_OFF, MM_ENTROPY_MACH = 0, 1
 
 _vp = ctypes.c_void_p
 
@@ -27,7 +28,8 @@ _vp = ctypes.c_void_p
 class mm_params(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("mode", ctypes.c_int32), ("guess", ctypes.c_int32),
                 ("newton_max_iter", ctypes.c_int32), ("gamma", ctypes.c_double), ("cfl", ctypes.c_double),
-                ("newton_tol64", ctypes.c_double), ("newton_tol32", ctypes.c_double), ("stream", _vp)]
+                ("newton_tol64", ctypes.c_double), ("newton_tol32", ctypes.c_double), ("stream", _vp),
+                ("entropy", ctypes.c_int32), ("reserved", ctypes.c_int32), ("mach_thresh", ctypes.c_double)]
 
 
 class mm_mesh(ctypes.Structure):
@@ -39,7 +41,7 @@ class mm_mesh(ctypes.Structure):
 class mm_diag(ctypes.Structure):
     _fields_ = [(k, ctypes.c_uint64) for k in
                 ("faces", "newton_iters", "newton_max", "unconverged", "vacuum", "positivity_fallback",
-                 "fp64_fallback", "guess_fallback", "wave_iter_max_sum", "waves")] + \
+                 "fp64_fallback", "guess_fallback", "wave_iter_max_sum", "waves", "entropy_kept")] + \
                [("nonfinite", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
@@ -74,6 +76,7 @@ SIGNATURES = {
                                      ctypes.c_float, ctypes.c_int32, _vp]),
     "mm_riemann_batch": (ctypes.c_int32, [_vp, ctypes.c_int64, _vp, _vp, _vp]),
     "mm_face_states": (ctypes.c_int32, [_vp, ctypes.c_double, _vp, _vp]),
+    "mm_entropy_init": (ctypes.c_int32, [_vp, _vp]),
 }
 
 MM_MLP_PARAMS = 4481
@@ -149,13 +152,15 @@ class Context:
 
     def __init__(self, dim: int, gamma: float, cfl: float = 0.4, mode: int = MM_FP64,
                  guess: int = MM_GUESS_STANDARD, newton_max_iter: int = 0, newton_tol64: float = 0.0,
-                 newton_tol32: float = 0.0, device="cuda", stream: torch.cuda.Stream | None = None):
+                 newton_tol32: float = 0.0, device="cuda", stream: torch.cuda.Stream | None = None,
+                 entropy: int = MM_ENTROPY_OFF, mach_thresh: float = 1.1):
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.params = mm_params(dim, mode, guess, newton_max_iter, gamma, cfl, newton_tol64, newton_tol32,
-                                ctypes.c_void_p(self.stream.cuda_stream))
+                                ctypes.c_void_p(self.stream.cuda_stream), entropy, 0, mach_thresh)
         self.dim = dim
         self.mode = mode
+        self.entropy = entropy
         self._ctx = ctypes.c_void_p()
         _check("mm_create", lib().mm_create(ctypes.byref(self.params), ctypes.byref(self._ctx)))
         self._ws = None
@@ -235,6 +240,9 @@ class Context:
     def mm_face_states(self, dt: float, recon: torch.Tensor, out: torch.Tensor):
         _check("mm_face_states", lib().mm_face_states(self._ctx, float(dt), _ptr(recon), _ptr(out)))
 
+    def mm_entropy_init(self, Q: torch.Tensor):
+        _check("mm_entropy_init", lib().mm_entropy_init(self._ctx, _ptr(Q)))
+
 
     def recon_buffer(self, n_cells: int):
         """Reconstruction buffer for mm_gradients in this context's mode
@@ -244,8 +252,9 @@ class Context:
         return torch.empty(n_cells * recon_stride(self.dim), dtype=dt, device=self.device)
 
     def flux_buffer(self, n_faces: int):
-        """Face fluxes [F][D+2] (double)."""
-        return torch.empty((n_faces, self.dim + 2), dtype=torch.float64, device=self.device)
+        """Face fluxes [F][MM_FLUX_STRIDE] (double): D+2 fluxes, then with the
+        entropy row the entropy flux and the face's shock Mach number."""
+        return torch.empty((n_faces, flux_stride(self.dim, self.entropy)), dtype=torch.float64, device=self.device)
 
 
 
@@ -271,6 +280,11 @@ def mm_mlp_grad(params, X, T, scratch, grad, n_total=None, stream=None):
 def mm_mlp_adam(params, grad, m1, m2, lr, beta1, beta2, eps, step, stream=None):
     _check("mm_mlp_adam", lib().mm_mlp_adam(_ptr(params), _ptr(grad), _ptr(m1), _ptr(m2), lr, beta1, beta2, eps,
                                             step, _stream_ptr(stream)))
+
+def flux_stride(dim: int, entropy: int = MM_ENTROPY_OFF) -> int:
+    """MM_FLUX_STRIDE: doubles per face record of the face-flux array."""
+    return dim + 2 + (2 if entropy else 0)
+
 
 def recon_stride(dim: int) -> int:
     """MM_RECON_STRIDE: elements per cell of the reconstruction buffer."""

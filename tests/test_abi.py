@@ -31,10 +31,10 @@ def test_library_exports_every_declared_symbol():
 
 def _params(**kw):
     p = dict(dim=3, mode=mm.MM_FP64, guess=mm.MM_GUESS_STANDARD, newton_max_iter=0, gamma=5 / 3, cfl=0.4,
-             newton_tol64=0.0, newton_tol32=0.0, stream=None)
+             newton_tol64=0.0, newton_tol32=0.0, stream=None, entropy=mm.MM_ENTROPY_OFF, mach_thresh=1.1)
     p.update(kw)
     return mm.mm_params(p["dim"], p["mode"], p["guess"], p["newton_max_iter"], p["gamma"], p["cfl"],
-                        p["newton_tol64"], p["newton_tol32"], p["stream"])
+                        p["newton_tol64"], p["newton_tol32"], p["stream"], p["entropy"], 0, p["mach_thresh"])
 
 
 def _create(**kw):
@@ -44,7 +44,8 @@ def _create(**kw):
 
 
 @pytest.mark.parametrize("kw", [dict(dim=1), dict(dim=4), dict(mode=7), dict(guess=3), dict(gamma=1.0),
-                                dict(gamma=float("nan")), dict(cfl=0.0)])
+                                dict(gamma=float("nan")), dict(cfl=0.0), dict(entropy=2),
+                                dict(entropy=mm.MM_ENTROPY_MACH, mach_thresh=float("nan"))])
 def test_create_rejects_bad_params(kw):
     st, ctx = _create(**kw)
     assert st == mm.MM_E_ARG and not ctx.value
@@ -86,6 +87,22 @@ def test_workspace_and_state_errors_without_device():
         L.mm_destroy(ctx)
     assert L.mm_destroy(None) == mm.MM_OK
     assert L.mm_status_str(mm.MM_E_MESH) == b"invalid mesh"
+
+
+def test_entropy_mode_widens_the_flux_records():
+    """The face-flux array of the entropy mode holds two more doubles per
+    face (entropy flux, Mach number); its entry point needs the mode."""
+    L = mm.lib()
+    _, c0 = _create()
+    _, c1 = _create(entropy=mm.MM_ENTROPY_MACH)
+    try:
+        n, nf = 100000, 800000
+        assert L.mm_workspace_bytes(c1, n, nf) - L.mm_workspace_bytes(c0, n, nf) >= 2 * 8 * nf
+        assert mm.flux_stride(3, mm.MM_ENTROPY_MACH) == 7 and mm.flux_stride(2) == 4
+        assert L.mm_entropy_init(c0, ctypes.c_void_p(256)) == mm.MM_E_ARG    # not in entropy mode
+        assert L.mm_entropy_init(c1, ctypes.c_void_p(256)) == mm.MM_E_STATE  # no mesh
+    finally:
+        L.mm_destroy(c0); L.mm_destroy(c1)
 
 
 def test_mixed_workspace_is_smaller_per_cell():

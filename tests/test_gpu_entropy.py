@@ -1,0 +1,159 @@
+"""The entropy scheme for poorly resolved cold flows (Section 3.5) through
+the C ABI, against the oracle:
+
+- face records of the entropy mode (fluxes, entropy flux, shock Mach
+  number) element by element, double path;
+- whole steps with the entropy row: double to 1e-12 norm-wise per row with
+  the same keep / re-derive decisions (the decision compares a Mach number
+  with the threshold, so cells within round-off of it are listed and
+  checked for validity instead); the mixed and mixed + learned forms within
+  the stated L1 of 1e-6 on the cells whose decision is not within 1e-3 of
+  the threshold;
+- mm_entropy_init against the definition S = M P / rho^gamma.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_0901_4107_amd import learned, mm
+from paper_0901_4107_amd.inputs.configs import kh2d, kh3d, random3d, sedov3d, total_entropy, with_entropy
+from tests.util import boost, l1_rel, normwise_rel
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+L1_BOUND = 1e-6
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def context(wl, mode=mm.MM_FP64, guess=mm.MM_GUESS_STANDARD, thr=1.1):
+    ctx = mm.Context(wl.mesh.dim, wl.gamma, wl.cfl, mode=mode, guess=guess, entropy=mm.MM_ENTROPY_MACH,
+                     mach_thresh=thr)
+    if guess == mm.MM_GUESS_LEARNED:
+        ctx.mm_mlp_load(learned.load(wl.gamma))
+    ctx.mm_mesh_upload(mm.DeviceMesh.from_host(wl.mesh))
+    return ctx
+
+
+def cell_max(mesh, face_values):
+    out = np.zeros(mesh.n_cells)
+    np.maximum.at(out, mesh.face_L, face_values)
+    np.maximum.at(out, mesh.face_R, face_values)
+    return out
+
+
+@pytest.mark.parametrize("make", [lambda: random3d(n_side=13, seed=501), lambda: kh2d(),
+                                  lambda: sedov3d(n_side=14, seed=502)])
+def test_entropy_face_records(make):
+    wl = make()
+    m, g = wl.mesh, wl.gamma
+    D = m.dim
+    Q = with_entropy(wl)
+    ctx = context(wl)
+    Qd = torch.from_numpy(Q).cuda()
+    rec = ctx.recon_buffer(m.n_cells)
+    ctx.mm_gradients(Qd, rec)
+    W = O.prim(D, g, m.volume, wl.Q)
+    dt = O.cfl_dt(m, g, wl.cfl, W)
+    F = ctx.flux_buffer(m.n_faces)
+    assert F.shape[1] == D + 4
+    ctx.mm_face_fluxes(dt, rec, F)
+    torch.cuda.synchronize()
+    Fg = F.cpu().numpy().T
+    _, grad, _ = O.gradients(m, W)
+    fl, sf, mach = O.face_fluxes_entropy(m, g, dt, W, grad)
+    err = normwise_rel(Fg[:D + 3], np.concatenate([fl, sf[None]]))
+    note(f"{wl.name}: face records norm-wise error {err}; faces with a shock above 1.1: {(mach > 1.1).sum()}")
+    assert np.all(err <= TOL), err
+    assert np.allclose(Fg[D + 3], mach, rtol=1e-9, atol=1e-12)
+
+
+@pytest.mark.parametrize("make,thr", [(lambda: random3d(n_side=13, seed=503), 1.1),
+                                      (lambda: random3d(n_side=13, seed=504), None),
+                                      (lambda: kh2d(), 1.1),
+                                      (lambda: sedov3d(n_side=16, seed=505), 1.1)])
+def test_entropy_step_double(make, thr):
+    """thr None: the median face Mach number, so that both decisions are
+    common."""
+    wl = make()
+    m, g = wl.mesh, wl.gamma
+    D = m.dim
+    Q = with_entropy(wl)
+    W = O.prim(D, g, m.volume, wl.Q)
+    _, grad, _ = O.gradients(m, W)
+    dto = O.cfl_dt(m, g, wl.cfl, W)
+    _, _, mach = O.face_fluxes_entropy(m, g, dto, W, grad)
+    if thr is None:
+        thr = float(np.median(mach[mach > 0]))
+    Qo, dto2, kept = O.hydro_step_entropy(m, g, wl.cfl, Q, thr)
+    cm = cell_max(m, mach)
+    near = np.abs(cm - thr) <= 1e-9 * thr
+    ctx = context(wl, thr=thr)
+    Qd = torch.from_numpy(Q).cuda()
+    used = ctx.mm_hydro_step(Qd)
+    assert abs(used - dto) <= 1e-14 * dto
+    Qg = Qd.cpu().numpy()
+    d = ctx.mm_get_diag()
+    ok = ~near
+    err = normwise_rel(Qg[:, ok], Qo[:, ok])
+    note(f"{wl.name} thr {thr:.4g}: kept {kept.sum()} of {m.n_cells} (GPU {d['entropy_kept']}), "
+         f"near the threshold {near.sum()}; norm-wise error per row {err}")
+    assert np.all(err <= TOL), err
+    assert np.all(np.isfinite(Qg))
+    if not near.any():
+        assert d["entropy_kept"] == int(kept.sum())
+
+
+@pytest.mark.parametrize("guess", [mm.MM_GUESS_STANDARD, mm.MM_GUESS_LEARNED])
+def test_entropy_step_mixed(guess):
+    """The boosted 3D KH (rest-frame comparison) and a point explosion, in
+    the mixed form."""
+    for wl in (kh3d(n_points=24 ** 3, seed=506), sedov3d(n_side=16, seed=507)):
+        m, g = wl.mesh, wl.gamma
+        D = m.dim
+        Q = with_entropy(wl)
+        W = O.prim(D, g, m.volume, wl.Q)
+        _, grad, _ = O.gradients(m, W)
+        dto = O.cfl_dt(m, g, wl.cfl, W)
+        _, _, mach = O.face_fluxes_entropy(m, g, dto, W, grad)
+        thr = 1.1
+        Qo, _, kept = O.hydro_step_entropy(m, g, wl.cfl, Q, thr, dt=dto)
+        near = np.abs(cell_max(m, mach) - thr) <= 1e-3 * thr
+        ctx = context(wl, mode=mm.MM_MIXED, guess=guess, thr=thr)
+        Qd = torch.from_numpy(Q).cuda()
+        ctx.mm_hydro_step(Qd, dt=dto)
+        Qg = Qd.cpu().numpy()
+        ok = ~near
+        v0 = -wl.boost
+        rest_g = boost(Qg[:D + 2], v0)[:, ok]
+        rest_o = boost(Qo[:D + 2], v0)[:, ok]
+        from tests.util import l1_state
+        l1 = l1_state(rest_g, rest_o)
+        l1s = l1_rel(Qg[D + 2:, ok], Qo[D + 2:, ok])
+        note(f"{wl.name} mixed guess {guess}: kept {kept.sum()} of {m.n_cells}, near the threshold {near.sum()}; "
+             f"rest-frame L1 {l1}, entropy L1 {l1s}")
+        assert np.all(l1 <= L1_BOUND), l1
+        assert np.all(l1s <= L1_BOUND), l1s
+        assert np.all(np.isfinite(Qg))
+
+
+def test_entropy_init_is_the_definition():
+    wl = random3d(n_side=12, seed=508)
+    m = wl.mesh
+    ctx = context(wl)
+    Q = with_entropy(wl)
+    Qd = torch.from_numpy(Q).cuda()
+    Qd[5].zero_()
+    ctx.mm_entropy_init(Qd)
+    S = Qd[5].cpu().numpy()
+    rho, _, P = wl.prim
+    want = total_entropy(m.volume, rho, P, wl.gamma)
+    assert np.abs(S - want).max() <= 1e-12 * np.abs(want).max()
+    assert np.array_equal(Qd[:5].cpu().numpy(), wl.Q)
