@@ -14,8 +14,11 @@ HBM before any timed region.
 Prints ONE JSON line: face fluxes per second of the whole step (value), the
 roofline of the dominant kernel (the face-flux kernel, timed on its own with
 HIP events on the library's stream) and the CPU oracle's rate on the host
-(cpu_baseline). ``--workload riemann`` instead times the batched exact
-solver on 2^24 independent Riemann problems (standard vs learned guess).
+(cpu_baseline). The same form is also timed with the entropy scheme for
+cold flows (Section 3.5: entropy row, Mach switch at --mach-thresh) and
+reported under "entropy". ``--workload riemann`` instead times the batched
+exact solver on 2^24 independent Riemann problems (standard vs learned
+guess).
 """
 from __future__ import annotations
 
@@ -72,10 +75,11 @@ def l1_rest(a, b, boost):
     return num / np.where(den > 0, den, 1.0)
 
 
-def make_context(mm, learned, m, wl, form, dev):
+def make_context(mm, learned, m, wl, form, dev, mach_thresh=None):
     mode = mm.MM_FP64 if form.startswith("fp64") else mm.MM_MIXED
     guess = mm.MM_GUESS_LEARNED if form.endswith("learned") else mm.MM_GUESS_STANDARD
-    ctx = mm.Context(m.dim, wl.gamma, wl.cfl, mode=mode, guess=guess, device=dev)
+    ent = {} if mach_thresh is None else {"entropy": mm.MM_ENTROPY_MACH, "mach_thresh": mach_thresh}
+    ctx = mm.Context(m.dim, wl.gamma, wl.cfl, mode=mode, guess=guess, device=dev, **ent)
     if guess == mm.MM_GUESS_LEARNED:
         params = learned.load(wl.gamma, dev)
         if params is None:
@@ -84,11 +88,14 @@ def make_context(mm, learned, m, wl, form, dev):
     return ctx
 
 
-def time_form(mm, learned, torch, wl, dmesh, form, steps, warmup, dev):
+def time_form(mm, learned, torch, wl, dmesh, form, steps, warmup, dev, mach_thresh=None):
+    """Time `form` on the workload; with mach_thresh, the entropy scheme
+    for cold flows (entropy row in Q, Mach switch at that threshold)."""
+    from paper_0901_4107_amd.inputs.configs import with_entropy
     m = wl.mesh
-    ctx = make_context(mm, learned, m, wl, form, dev)
+    ctx = make_context(mm, learned, m, wl, form, dev, mach_thresh)
     ctx.mm_mesh_upload(dmesh)
-    Q0 = torch.from_numpy(np.ascontiguousarray(wl.Q)).to(dev)
+    Q0 = torch.from_numpy(with_entropy(wl) if mach_thresh is not None else np.ascontiguousarray(wl.Q)).to(dev)
     Q = Q0.clone()
     rec = ctx.recon_buffer(m.n_cells)
     F = ctx.flux_buffer(m.n_faces)
@@ -212,6 +219,14 @@ def bench_step(args):
         out["speedup_vs_fp64"] = {"step": base["ms"] / head["ms"], "flux_kernel": base["flux_ms"] / head["flux_ms"],
                                   "l1_rest_frame_vs_fp64": [float(x) for x in err],
                                   "set_error": SET_ERROR, "within_set_error": bool(np.all(err <= SET_ERROR))}
+    if not args.no_entropy:
+        ent = time_form(mm, learned, torch, wl, dmesh, args.mode, args.steps, args.warmup, dev,
+                        mach_thresh=args.mach_thresh)
+        log(f"{args.mode} with the entropy scheme: {ent['ms']:.3f} ms/step, flux kernel {ent['flux_ms']:.3f} ms")
+        out["entropy"] = {"form": args.mode, "mach_thresh": args.mach_thresh, "ms_per_step": ent["ms"],
+                          "face_fluxes_per_s": m.n_faces / (ent["ms"] * 1e-3), "flux_kernel_ms": ent["flux_ms"],
+                          "kept_fraction": ent["diag"]["entropy_kept"] / m.n_cells,
+                          "step_time_vs_plain": ent["ms"] / head["ms"]}
     if not args.no_cpu_baseline:
         from oracle import oracle as O
         log("cpu baseline: oracle hydro step on the full workload (1 thread)")
@@ -292,6 +307,8 @@ def main():
     ap.add_argument("--mode", default="mixed+learned", choices=["fp64", "fp64+learned", "mixed", "mixed+learned"])
     ap.add_argument("--no-compare", action="store_true", help="skip the double-precision comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-entropy", action="store_true", help="skip the run with the entropy scheme for cold flows")
+    ap.add_argument("--mach-thresh", type=float, default=1.1, help="Mach switch of the entropy scheme")
     ap.add_argument("--threads", type=int, default=0, help="host threads for the mesh builder")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MB")
     args = ap.parse_args()
