@@ -157,3 +157,58 @@ def test_entropy_init_is_the_definition():
     want = total_entropy(m.volume, rho, P, wl.gamma)
     assert np.abs(S - want).max() <= 1e-12 * np.abs(want).max()
     assert np.array_equal(Qd[:5].cpu().numpy(), wl.Q)
+
+
+def test_cold_supersonic_flow():
+    """Cold gas moving at about 77 sound speeds over a fixed 32^2 lattice
+    with a smooth velocity perturbation (the oracle pin of the same name):
+    every double step restarted from the oracle's state matches it to
+    10 eps E_kin / E_th (7.5e-12 here, the rounding of a pressure formed as a
+    difference of much larger energies); run alone for 30 steps, the entropy scheme keeps P / rho^gamma
+    within 1e-5 of its initial value in both forms, while the plain double
+    step heats the gas by more than 1e-3."""
+    from tests.test_oracle_entropy import cold_flow
+    g = 5.0 / 3.0
+    mesh, Qp0, Qe0 = cold_flow(32, g)
+    from paper_0901_4107_amd.inputs.configs import Workload
+    wl = Workload("cold", mesh, Qp0, g, 0.4, np.zeros(2), 0)
+    plain = mm.Context(2, g, 0.4)
+    plain.mm_mesh_upload(mm.DeviceMesh.from_host(mesh))
+    ent64 = context(wl)
+    ent32 = context(wl, mode=mm.MM_MIXED, guess=mm.MM_GUESS_LEARNED)
+    Qo = Qe0.copy()
+    Qp = torch.from_numpy(Qp0.copy()).cuda()
+    Q64 = torch.from_numpy(Qe0.copy()).cuda()
+    Q32 = torch.from_numpy(Qe0.copy()).cuda()
+    # the pressure of this gas is a difference of energies some 3000 times
+    # larger than it (E - M v^2/2), so both sides carry relative errors of
+    # eps E_kin / E_th in P and in everything derived from it (A_U, S)
+    V = mesh.volume
+    ekin = 0.5 * (Qp0[1] ** 2 + Qp0[2] ** 2) / Qp0[0]
+    ratio = float(np.max(ekin / (Qp0[3] - ekin)))
+    tol = max(TOL, 10 * np.finfo(float).eps * ratio)
+    worst = 0.0
+    for _ in range(30):
+        Qn, dto, kept = O.hydro_step_entropy(mesh, g, 0.4, Qo, 1.1)
+        Qr = torch.from_numpy(Qo).cuda()
+        used = ent64.mm_hydro_step(Qr)
+        assert abs(used - dto) <= 1e-13 * dto   # a few ulp: |v - w| dominates the signal speed
+        err = normwise_rel(Qr.cpu().numpy(), Qn)
+        worst = max(worst, float(err.max()))
+        assert np.all(err <= tol), (err, tol)
+        Qo = Qn
+        dt = plain.mm_hydro_step(Qp)
+        ent64.mm_hydro_step(Q64, dt=dt)
+        ent32.mm_hydro_step(Q32, dt=dt)
+    A0 = 1e-4
+
+    def A(Q):
+        W = O.prim(2, g, mesh.volume, Q[:4])
+        return W[3] / W[0] ** g
+    ap, a64, a32 = A(Qp.cpu().numpy()), A(Q64.cpu().numpy()), A(Q32.cpu().numpy())
+    note(f"cold flow, 30 steps: worst restarted double error {worst:.2e} (bound {tol:.1e}); max A/A0 - 1: plain {ap.max() / A0 - 1:.2e}, "
+         f"entropy double {np.abs(a64 / A0 - 1).max():.2e}, entropy mixed+learned {np.abs(a32 / A0 - 1).max():.2e}")
+    assert ap.max() / A0 - 1.0 > 1e-3
+    assert np.abs(a64 / A0 - 1.0).max() < 1e-5
+    assert np.abs(a32 / A0 - 1.0).max() < 1e-5
+    assert ent64.mm_get_diag()["entropy_kept"] == 60 * mesh.n_cells

@@ -4,6 +4,7 @@ configuration bench.py times, through the C ABI:
 - the boosted 3D Kelvin-Helmholtz step on 128^3 Poisson points
   (16.3M faces): the double path element by element against the oracle's
   whole step, the mixed + learned form within the stated rest-frame L1;
+  the same with the entropy scheme for cold flows;
 - the 2^24-problem Riemann batch: a seeded sample of 2^17 problems solved
   one by one by the oracle against the double and the mixed + learned
   batches, every output of the batch finite, the learned guess's iteration
@@ -50,9 +51,14 @@ def step(wl, mode, guess, dt=0.0):
     return out, used, diag
 
 
-def test_kh3d_128_headline():
+@pytest.fixture(scope="module")
+def kh3d_128():
     note("building kh3d 128^3")
-    wl = configs.kh3d(nthreads=16)
+    return configs.kh3d(nthreads=16)
+
+
+def test_kh3d_128_headline(kh3d_128):
+    wl = kh3d_128
     m = wl.mesh
     note(f"kh3d: N={m.n_cells} F={m.n_faces}; oracle step")
     Qo, dto = O.hydro_step(m, wl.gamma, wl.cfl, wl.Q)
@@ -72,6 +78,57 @@ def test_kh3d_128_headline():
     scale = np.abs(wl.Q).sum(axis=1)
     scale[1:4] = np.sum(np.sqrt(np.sum(wl.Q[1:4] ** 2, axis=0)))
     assert np.all(np.abs(Qm.sum(axis=1) - wl.Q.sum(axis=1)) <= 1e-13 * scale)
+
+
+def test_kh3d_128_entropy(kh3d_128):
+    """The headline workload with the entropy scheme (Mach switch 1.1), in
+    the forms the benchmark times: double against the oracle to 1e-12 with
+    the same keep decisions, mixed + learned within the stated rest-frame
+    L1, on the cells whose largest face Mach number is not within 1e-3 of
+    the threshold (listed)."""
+    wl = kh3d_128
+    m, g = wl.mesh, wl.gamma
+    thr = 1.1
+    Q = configs.with_entropy(wl)
+    note("oracle entropy step")
+    W = O.prim(3, g, m.volume, wl.Q)
+    _, grad, _ = O.gradients(m, W)
+    dto = O.cfl_dt(m, g, wl.cfl, W)
+    fl, sf, mach = O.face_fluxes_entropy(m, g, dto, W, grad)
+    Qo, kept = O.apply_update_entropy(m, g, fl, sf, mach, thr, Q)
+    cm = np.zeros(m.n_cells)
+    np.maximum.at(cm, m.face_L, mach)
+    np.maximum.at(cm, m.face_R, mach)
+    res = {}
+    for name, mode, guess, band in (("double", mm.MM_FP64, mm.MM_GUESS_STANDARD, 1e-9),
+                                    ("mixed+learned", mm.MM_MIXED, mm.MM_GUESS_LEARNED, 1e-3)):
+        ctx = mm.Context(3, g, wl.cfl, mode=mode, guess=guess, entropy=mm.MM_ENTROPY_MACH, mach_thresh=thr)
+        if guess == mm.MM_GUESS_LEARNED:
+            ctx.mm_mlp_load(learned.load(g))
+        ctx.mm_mesh_upload(mm.DeviceMesh.from_host(m))
+        Qd = torch.from_numpy(Q).cuda()
+        ctx.mm_hydro_step(Qd, dt=dto)
+        Qg = Qd.cpu().numpy()
+        d = ctx.mm_get_diag()
+        del ctx, Qd
+        torch.cuda.empty_cache()
+        ok = np.abs(cm - thr) > band * thr
+        res[name] = (Qg, ok, d)
+        note(f"{name}: kept {d['entropy_kept']} (oracle {kept.sum()} of {m.n_cells}); "
+             f"cells near the threshold {(~ok).sum()}")
+    Q64, ok64, d64 = res["double"]
+    err = normwise_rel(Q64[:, ok64], Qo[:, ok64])
+    note(f"double entropy step vs oracle: normwise {err}")
+    assert np.all(err <= TOL64), err
+    if ok64.all():
+        assert d64["entropy_kept"] == int(kept.sum())
+    Qm, okm, _ = res["mixed+learned"]
+    l1 = l1_state(boost(Qm[:5, okm], -wl.boost), boost(Qo[:5, okm], -wl.boost))
+    l1s = np.sum(np.abs(Qm[5, okm] - Qo[5, okm])) / np.sum(np.abs(Qo[5, okm]))
+    note(f"mixed + learned entropy step vs oracle: rest-frame L1 {l1}, entropy L1 {l1s:.3e}")
+    assert np.all(l1 <= L1_BOUND), l1
+    assert l1s <= L1_BOUND
+    assert np.all(np.isfinite(Qm))
 
 
 def batch(S, mode, guess, gamma):
