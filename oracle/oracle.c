@@ -777,3 +777,75 @@ double oracle_shock_mach(double g, const double *L, const double *R)
     int k = oracle_riemann(g, L, R, out, st, NULL);
     return riemann_shock_mach(g, L, R, k, st[0]);
 }
+
+/* ------------------------------------------------------------------ */
+/* Mesh motion (Section 3.2 and Section 4.1). The generators move with   */
+/* their cell's fluid velocity, w_i = v_i (eq. eqnvelmesh), plus the     */
+/* roundness correction of eq. EqnShapeCorrVel: with d_i = |s_i - r_i|,  */
+/* R_i = (3 V_i / 4 pi)^(1/3) in 3D ((V_i / pi)^(1/2) in 2D) and         */
+/* x = d_i / (eta R_i), add chi times                                    */
+/*   0                                            for x < 0.9            */
+/*   c_i (s_i - r_i)/d_i (d_i - 0.9 eta R_i)/(0.2 eta R_i)  0.9 <= x < 1.1*/
+/*   c_i (s_i - r_i)/d_i                          for 1.1 <= x           */
+/* with c_i the cell's sound speed, or, when dt_lloyd > 0, the paper's   */
+/* alternative (s_i - r_i)/dt_lloyd in place of c_i (s_i - r_i)/d_i.     */
+/* W are primitives; a vacuum cell (rho <= 0 or P <= 0) has c_i = 0.     */
+/* w_out [D][N].                                                         */
+/* ------------------------------------------------------------------ */
+void oracle_mesh_velocity(const om_mesh *M, const om_params *prm, const double *W, double eta, double chi,
+                          double dt_lloyd, double *w_out)
+{
+    const int D = M->dim;
+    const int64_t n = M->n_cells;
+    for (int64_t i = 0; i < n; i++) {
+        double sr[3] = {0, 0, 0}, d = 0.0;
+        for (int k = 0; k < D; k++) { sr[k] = M->centroid_off[k * n + i]; d += sr[k] * sr[k]; }
+        d = sqrt(d);
+        const double V = M->volume[i];
+        const double R = (D == 3) ? cbrt(3.0 * V / (4.0 * PI_D)) : sqrt(V / PI_D);
+        const double rho = W[i], P = W[(D + 1) * n + i];
+        const double c = (rho > 0.0 && P > 0.0) ? sqrt(prm->gamma * P / rho) : 0.0;
+        const double x = d / (eta * R);
+        double frac = 0.0;
+        if (x >= 1.1) frac = 1.0;
+        else if (x >= 0.9) frac = (d - 0.9 * eta * R) / (0.2 * eta * R);
+        for (int k = 0; k < D; k++) {
+            double corr = 0.0;
+            if (frac > 0.0) corr = (dt_lloyd > 0.0) ? sr[k] / dt_lloyd : c * sr[k] / d;
+            w_out[k * n + i] = W[(1 + k) * n + i] + chi * frac * corr;
+        }
+    }
+}
+
+/* Rate of change of each cell's volume from the generator velocities    */
+/* (Section 3.3, eq. eqnvolchange), summed over the cell's faces as      */
+/* printed: dV_i/dt = - sum_j A_ij [ c_ij/r_ij . (w_j - w_i)             */
+/*                                   + r_ij/(2 r_ij) . (w_j + w_i) ],    */
+/* r_ij = r_i - r_j (periodic image), c_ij = f_ij - (r_i + r_j)/2.       */
+/* rate [N].                                                             */
+void oracle_volume_rate(const om_mesh *M, double *rate)
+{
+    const int D = M->dim;
+    const int64_t n = M->n_cells, nf = M->n_faces;
+    for (int64_t i = 0; i < n; i++) rate[i] = 0.0;
+    for (int64_t f = 0; f < nf; f++) {
+        const int64_t cell[2] = {M->face_L[f], M->face_R[f]};
+        double d[3] = {0, 0, 0}, cc[3] = {0, 0, 0}, len = 0.0;
+        for (int k = 0; k < D; k++) {
+            d[k] = M->face_sep[k * nf + f];                 /* r_R - r_L */
+            cc[k] = M->face_ctr[k * nf + f] - 0.5 * d[k];   /* f - (r_L + r_R)/2 */
+            len += d[k] * d[k];
+        }
+        len = sqrt(len);
+        for (int s = 0; s < 2; s++) {
+            const int64_t i = cell[s], j = cell[1 - s];
+            double term = 0.0;
+            for (int k = 0; k < D; k++) {
+                const double rij = s == 0 ? -d[k] : d[k];      /* r_i - r_j */
+                const double wi = M->mesh_vel[k * n + i], wj = M->mesh_vel[k * n + j];
+                term += cc[k] / len * (wj - wi) + rij / (2.0 * len) * (wj + wi);
+            }
+            rate[i] -= M->face_area[f] * term;
+        }
+    }
+}

@@ -65,6 +65,9 @@ def _lib():
         lib.oracle_hydro_step_entropy.restype = ctypes.c_double
         lib.oracle_hydro_step_entropy.argtypes = [ctypes.POINTER(_OMesh), ctypes.POINTER(_OParams), ctypes.c_double,
                                                   ctypes.c_double, _dp, _ip]
+        lib.oracle_mesh_velocity.argtypes = [ctypes.POINTER(_OMesh), ctypes.POINTER(_OParams), _dp, ctypes.c_double,
+                                             ctypes.c_double, ctypes.c_double, _dp]
+        lib.oracle_volume_rate.argtypes = [ctypes.POINTER(_OMesh), _dp]
         lib.oracle_shock_mach.restype = ctypes.c_double
         lib.oracle_shock_mach.argtypes = [ctypes.c_double, _dp, _dp]
         _LIB = lib
@@ -196,6 +199,25 @@ def hydro_step_entropy(mesh, gamma, cfl, Q, mach_thresh, dt=0.0):
     used = _lib().oracle_hydro_step_entropy(ctypes.byref(h.s), ctypes.byref(p), float(dt), float(mach_thresh),
                                             _d(Q), _i(kept))
     return Q, used, kept
+
+
+def mesh_velocity(mesh, gamma, W, eta=0.25, chi=1.0, dt_lloyd=0.0):
+    """Generator velocities [D][N]: w = v plus the roundness correction of
+    Section 4.1 (sound-speed form, or (s - r)/dt_lloyd when dt_lloyd > 0)."""
+    h = _Held(mesh)
+    w = np.empty((h.dim, h.n))
+    p = _OParams(float(gamma), 0.0)
+    _lib().oracle_mesh_velocity(ctypes.byref(h.s), ctypes.byref(p), _d(_f64(W)), float(eta), float(chi),
+                                float(dt_lloyd), _d(w))
+    return w
+
+
+def volume_rate(mesh):
+    """dV_i/dt from the generator velocities (eq. eqnvolchange) [N]."""
+    h = _Held(mesh)
+    out = np.empty(h.n)
+    _lib().oracle_volume_rate(ctypes.byref(h.s), _d(out))
+    return out
 
 
 def shock_mach(gamma, L, R):
