@@ -208,6 +208,36 @@ mm_status mm_hydro_step(mm_ctx *ctx, double *Q, double dt, double *dt_used);
  * definition; 0 where M_i <= 0). */
 mm_status mm_entropy_init(mm_ctx *ctx, double *Q);
 
+/* Mesh motion for the next tessellation (Section 3.2, eq. eqnvelmesh, and
+ * Section 4.1, eq. EqnShapeCorrVel), on the uploaded mesh: w_out [D][N]
+ * (double) receives each generator's velocity, the cell's fluid velocity
+ * p/m (0 where m <= 0) plus chi times a pull towards the cell's centre of
+ * mass s_i. With d = |s_i - r_i|, R_i = (3V/4pi)^(1/3) in 3D ((V/pi)^(1/2)
+ * in 2D) and x = d/(eta R_i), the pull is 0 for x < 0.9, c_i (s_i - r_i)/d
+ * for x >= 1.1 (c_i the cell's sound speed, 0 in a vacuum cell) and that
+ * times (d - 0.9 eta R_i)/(0.2 eta R_i) in between; with dt_lloyd > 0,
+ * (s_i - r_i)/dt_lloyd replaces c_i (s_i - r_i)/d (the paper's timestep
+ * form; chi = 1 then moves every pulled generator onto its centre of mass
+ * in dt_lloyd). The paper's usual choice is eta = 0.25, chi = 1. MM_E_ARG
+ * for eta <= 0, chi < 0, dt_lloyd < 0 or non-finite values; MM_E_STATE
+ * without a mesh. */
+mm_status mm_mesh_velocity(mm_ctx *ctx, const double *Q, double eta, double chi, double dt_lloyd,
+                           double *w_out);
+
+/* The rate of change of every cell's volume implied by the uploaded mesh's
+ * generator velocities (Section 3.3, eq. eqnvolchange): rate [N] (double)
+ * = the sum over the cell's faces of A_f w_f . n_f, the face normal taken
+ * out of the cell. MM_E_STATE without a mesh. */
+mm_status mm_volume_rate(mm_ctx *ctx, double *rate);
+
+/* Replace the uploaded mesh's generator velocities by mesh_vel [D][N]
+ * (device, kept by reference like the mesh's arrays; for example the output
+ * of mm_mesh_velocity) and recompute the face velocities and the side
+ * records that depend on them, without re-sorting the mesh. Synchronises.
+ * MM_E_MESH if a velocity is not finite (the context then has no mesh);
+ * MM_E_STATE without a mesh. */
+mm_status mm_mesh_set_velocity(mm_ctx *ctx, const double *mesh_vel);
+
 /* ------------------------------------------------------------------------
  * Learned starting guess for the Newton iteration on the star pressure
  * (a 3 -> 64 -> 64 -> 1 ReLU network; not part of the paper's method, which

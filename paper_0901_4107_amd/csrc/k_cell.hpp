@@ -386,4 +386,75 @@ __global__ void __launch_bounds__(kBlock) k_entropy_init(int64_t n, const double
     Q[NV * n + i] = S;
 }
 
+// Mesh motion (Section 3.2, eq. eqnvelmesh, and Section 4.1, eq.
+// EqnShapeCorrVel): each generator moves with its cell's fluid velocity,
+// w_i = v_i (0 in a vacuum cell), plus chi times a pull towards the cell's
+// centre of mass: with d = |s_i - r_i|, R_i the radius of a sphere (3D) or
+// disc (2D) of the cell's volume and x = d / (eta R_i), none for x < 0.9,
+// c_i (s_i - r_i)/d scaled by (d - 0.9 eta R_i)/(0.2 eta R_i) for
+// 0.9 <= x < 1.1, and c_i (s_i - r_i)/d above, c_i the sound speed (0 in a
+// vacuum cell); with dt_lloyd > 0, (s_i - r_i)/dt_lloyd replaces
+// c_i (s_i - r_i)/d. w_out [D][N].
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_mesh_velocity(int64_t n, const double *__restrict__ Q,
+                                                          const double *__restrict__ V,
+                                                          const double *__restrict__ coff, double gamma, double eta,
+                                                          double chi, double dt_lloyd, double *__restrict__ w_out) {
+    constexpr int NV = D + 2;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const double m = Q[i], vol = V[i];
+    double v[D], sr[D], d2 = 0.0, c = 0.0;
+    for (int k = 0; k < D; k++) {
+        sr[k] = coff[k * n + i];
+        d2 += sr[k] * sr[k];
+        v[k] = 0.0;
+    }
+    if (m > 0.0) {
+        double p2 = 0.0;
+        for (int k = 0; k < D; k++) {
+            v[k] = Q[(1 + k) * n + i] / m;
+            p2 += v[k] * v[k];
+        }
+        const double rho = m / vol;
+        const double P = (gamma - 1.0) * (Q[(NV - 1) * n + i] - 0.5 * m * p2) / vol;
+        if (rho > 0.0 && P > 0.0) c = sqrt(gamma * P / rho);
+    }
+    const double d = sqrt(d2);
+    const double R = (D == 3) ? cbrt(3.0 * vol / (4.0 * M_PI)) : sqrt(vol / M_PI);
+    const double x = d / (eta * R);
+    const double frac = x >= 1.1 ? 1.0 : (x >= 0.9 ? (d - 0.9 * eta * R) / (0.2 * eta * R) : 0.0);
+    for (int k = 0; k < D; k++) {
+        double corr = 0.0;
+        if (frac > 0.0) corr = dt_lloyd > 0.0 ? sr[k] / dt_lloyd : c * sr[k] / d;
+        w_out[k * n + i] = v[k] + chi * frac * corr;
+    }
+}
+
+// Volume rate of every cell from the face velocities of the uploaded mesh
+// (Section 3.3, eq. eqnvolchange): dV_i/dt = sum over the cell's faces of
+// +- A_f w_f . n_f, + where the cell is the face's left cell (the normal
+// points out of it). One lane group per cell, a fixed summation order.
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_volume_rate(int64_t n, const int32_t *__restrict__ off,
+                                                        const int32_t *__restrict__ ent,
+                                                        const double *__restrict__ frec, double *__restrict__ rate) {
+    using Y = Lay<D>;
+    constexpr int GS = Group<D>::GS;
+    const int lane = threadIdx.x % GS;
+    const int64_t i = xcd_tile() * (kBlock / GS) + threadIdx.x / GS;
+    if (i >= n) return;
+    double acc = 0.0;
+    for (int32_t q = off[i] + lane; q < off[i + 1]; q += GS) {
+        const int32_t en = ent[q];
+        double fr[Y::FREC];
+        load_rec<Y::FREC>(frec + (int64_t)(en >> 1) * Y::FREC, fr);
+        double wn = 0.0;
+        for (int k = 0; k < D; k++) wn += fr[Y::FW + k] * fr[Y::FN + k];
+        acc += ((en & 1) ? -1.0 : 1.0) * fr[Y::FA] * wn;
+    }
+    acc = grp_sum<GS>(acc);
+    if (lane == 0) rate[i] = acc;
+}
+
 }  // namespace mm

@@ -275,6 +275,33 @@ mm_status mm_mesh_upload(mm_ctx *c, const mm_mesh *m) {
     return clear_diag(c);
 }
 
+mm_status mm_mesh_set_velocity(mm_ctx *c, const double *mesh_vel) {
+    if (!c || !mesh_vel) return MM_E_ARG;
+    if (!c->have_mesh) return MM_E_STATE;
+    c->have_mesh = false;
+    c->mesh.mesh_vel = mesh_vel;
+    const mm_mesh *m = &c->mesh;
+    hipStream_t s = c->st();
+    int32_t *flags = c->at<int32_t>(c->lay.flags);
+    k_fill_i32<<<1, kBlock, 0, s>>>(flags, 1, 0);
+    if (c->D == 3) {
+        k_validate_cells<3><<<plain_grid(m->n_cells), kBlock, 0, s>>>(m->n_cells, m->volume, m->centroid_off,
+                                                                      m->mesh_vel, flags);
+        launch_records<3>(c, m, flags);
+    } else {
+        k_validate_cells<2><<<plain_grid(m->n_cells), kBlock, 0, s>>>(m->n_cells, m->volume, m->centroid_off,
+                                                                      m->mesh_vel, flags);
+        launch_records<2>(c, m, flags);
+    }
+    MM_LAUNCH_CHECK();
+    int32_t hflags = 0;
+    MM_CHECK(hipMemcpyAsync(&hflags, flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    MM_CHECK(hipStreamSynchronize(s));
+    if (hflags) return MM_E_MESH;
+    c->have_mesh = true;
+    return MM_OK;
+}
+
 // The reconstruction buffer holds the primitive block [N][PREC] followed by
 // the gradient block [N][GREC].
 template <int D, typename T> static T *grad_block(const mm_ctx *c, T *rec) { return rec + c->n * Lay<D>::PREC; }
@@ -368,6 +395,35 @@ static mm_status update_into(mm_ctx *c, const double *flux, double *Q) {
         if (c->D == 3) launch_update<3, false>(c, flux, Q);
         else launch_update<2, false>(c, flux, Q);
     }
+    MM_LAUNCH_CHECK();
+    return MM_OK;
+}
+
+mm_status mm_mesh_velocity(mm_ctx *c, const double *Q, double eta, double chi, double dt_lloyd, double *w_out) {
+    if (!c || !Q || !w_out) return MM_E_ARG;
+    if (!(eta > 0.0) || !(chi >= 0.0) || !isfinite(eta) || !isfinite(chi) || !(dt_lloyd >= 0.0) || !isfinite(dt_lloyd))
+        return MM_E_ARG;
+    if (!c->have_mesh) return MM_E_STATE;
+    if (c->D == 3)
+        k_mesh_velocity<3><<<plain_grid(c->n), kBlock, 0, c->st()>>>(c->n, Q, c->mesh.volume, c->mesh.centroid_off,
+                                                                     c->p.gamma, eta, chi, dt_lloyd, w_out);
+    else
+        k_mesh_velocity<2><<<plain_grid(c->n), kBlock, 0, c->st()>>>(c->n, Q, c->mesh.volume, c->mesh.centroid_off,
+                                                                     c->p.gamma, eta, chi, dt_lloyd, w_out);
+    MM_LAUNCH_CHECK();
+    return MM_OK;
+}
+
+mm_status mm_volume_rate(mm_ctx *c, double *rate) {
+    if (!c || !rate) return MM_E_ARG;
+    if (!c->have_mesh) return MM_E_STATE;
+    const Layout &L = c->lay;
+    if (c->D == 3)
+        k_volume_rate<3><<<group_grid(3, c->n), kBlock, 0, c->st()>>>(c->n, c->at<int32_t>(L.off),
+                                                                      c->at<int32_t>(L.ent), c->at<double>(L.frec), rate);
+    else
+        k_volume_rate<2><<<group_grid(2, c->n), kBlock, 0, c->st()>>>(c->n, c->at<int32_t>(L.off),
+                                                                      c->at<int32_t>(L.ent), c->at<double>(L.frec), rate);
     MM_LAUNCH_CHECK();
     return MM_OK;
 }

@@ -77,6 +77,9 @@ SIGNATURES = {
     "mm_riemann_batch": (ctypes.c_int32, [_vp, ctypes.c_int64, _vp, _vp, _vp]),
     "mm_face_states": (ctypes.c_int32, [_vp, ctypes.c_double, _vp, _vp]),
     "mm_entropy_init": (ctypes.c_int32, [_vp, _vp]),
+    "mm_mesh_velocity": (ctypes.c_int32, [_vp, _vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, _vp]),
+    "mm_volume_rate": (ctypes.c_int32, [_vp, _vp]),
+    "mm_mesh_set_velocity": (ctypes.c_int32, [_vp, _vp]),
 }
 
 MM_MLP_PARAMS = 4481
@@ -239,6 +242,18 @@ class Context:
 
     def mm_face_states(self, dt: float, recon: torch.Tensor, out: torch.Tensor):
         _check("mm_face_states", lib().mm_face_states(self._ctx, float(dt), _ptr(recon), _ptr(out)))
+
+    def mm_mesh_velocity(self, Q: torch.Tensor, w_out: torch.Tensor, eta: float = 0.25, chi: float = 1.0,
+                         dt_lloyd: float = 0.0):
+        _check("mm_mesh_velocity", lib().mm_mesh_velocity(self._ctx, _ptr(Q), float(eta), float(chi),
+                                                          float(dt_lloyd), _ptr(w_out)))
+
+    def mm_mesh_set_velocity(self, w: torch.Tensor):
+        _check("mm_mesh_set_velocity", lib().mm_mesh_set_velocity(self._ctx, _ptr(w)))
+        self._mesh_vel = w  # kept alive while the library refers to it
+
+    def mm_volume_rate(self, rate: torch.Tensor):
+        _check("mm_volume_rate", lib().mm_volume_rate(self._ctx, _ptr(rate)))
 
     def mm_entropy_init(self, Q: torch.Tensor):
         _check("mm_entropy_init", lib().mm_entropy_init(self._ctx, _ptr(Q)))

@@ -83,6 +83,15 @@ def test_workspace_and_state_errors_without_device():
         assert L.mm_mesh_upload(ctx, ctypes.byref(mesh(1000, 8000, idx=None))) == mm.MM_E_ARG
         assert L.mm_mesh_upload(ctx, ctypes.byref(mesh(2000, 16000))) == mm.MM_E_WORKSPACE
         assert L.mm_hydro_step(ctx, ctypes.c_void_p(256), 0.0, None) == mm.MM_E_STATE  # still no mesh
+        # mesh motion: arguments first, then the missing mesh
+        P = ctypes.c_void_p(1 << 21)
+        for eta, chi, dtl in [(0.0, 1.0, 0.0), (0.25, -1.0, 0.0), (0.25, 1.0, -1.0), (float("nan"), 1.0, 0.0),
+                              (0.25, float("inf"), 0.0)]:
+            assert L.mm_mesh_velocity(ctx, P, eta, chi, dtl, P) == mm.MM_E_ARG, (eta, chi, dtl)
+        assert L.mm_mesh_velocity(ctx, P, 0.25, 1.0, 0.0, P) == mm.MM_E_STATE
+        assert L.mm_volume_rate(ctx, P) == mm.MM_E_STATE
+        assert L.mm_mesh_set_velocity(ctx, P) == mm.MM_E_STATE
+        assert L.mm_volume_rate(ctx, None) == mm.MM_E_ARG
     finally:
         L.mm_destroy(ctx)
     assert L.mm_destroy(None) == mm.MM_OK
