@@ -16,7 +16,9 @@ roofline of the dominant kernel (the face-flux kernel, timed on its own with
 HIP events on the library's stream) and the CPU oracle's rate on the host
 (cpu_baseline). The same form is also timed with the entropy scheme for
 cold flows (Section 3.5: entropy row, Mach switch at --mach-thresh) and
-reported under "entropy". ``--workload riemann`` instead times the batched
+reported under "entropy"; the mesh-motion entry points (Section 4.1
+generator velocities, volume rate, velocity replacement) are timed on the
+same mesh under "mesh_motion". ``--workload riemann`` instead times the batched
 exact solver on 2^24 independent Riemann problems (standard vs learned
 guess).
 """
@@ -148,6 +150,40 @@ def time_form(mm, learned, torch, wl, dmesh, form, steps, warmup, dev, mach_thre
             "workspace_gb": ctx._ws.numel() / 1e9}
 
 
+def time_mesh_motion(mm, torch, wl, dmesh, steps, dev):
+    """The mesh-motion entry points on the workload's mesh: generator
+    velocities with the roundness correction (eta 0.25, chi 1), the volume
+    rate, and the replacement of the mesh's velocities (which rebuilds the
+    face and side records and synchronises)."""
+    m = wl.mesh
+    ctx = mm.Context(m.dim, wl.gamma, wl.cfl, mode=mm.MM_MIXED, device=dev)
+    ctx.mm_mesh_upload(dmesh)
+    Q = torch.from_numpy(np.ascontiguousarray(wl.Q)).to(dev)
+    w = torch.empty((m.dim, m.n_cells), dtype=torch.float64, device=dev)
+    rate = torch.empty(m.n_cells, dtype=torch.float64, device=dev)
+    stream = ctx.stream
+
+    def events(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+    vel_ms = events(lambda: ctx.mm_mesh_velocity(Q, w))
+    rate_ms = events(lambda: ctx.mm_volume_rate(rate))
+    ctx.mm_mesh_set_velocity(w)
+    t = time.perf_counter()
+    for _ in range(steps):
+        ctx.mm_mesh_set_velocity(w)
+    set_ms = (time.perf_counter() - t) * 1e3 / steps
+    return {"mesh_velocity_ms": vel_ms, "volume_rate_ms": rate_ms, "set_velocity_wall_ms": set_ms,
+            "cells_per_s_mesh_velocity": m.n_cells / (vel_ms * 1e-3)}
+
+
 def newton_summary(d):
     return {"iters_mean": d["newton_iters"] / max(1, d["faces"]),
             "wave_max_mean": d["wave_iter_max_sum"] / max(1, d["waves"]), "max": d["newton_max"],
@@ -227,6 +263,9 @@ def bench_step(args):
                           "face_fluxes_per_s": m.n_faces / (ent["ms"] * 1e-3), "flux_kernel_ms": ent["flux_ms"],
                           "kept_fraction": ent["diag"]["entropy_kept"] / m.n_cells,
                           "step_time_vs_plain": ent["ms"] / head["ms"]}
+    if not args.no_entropy:
+        out["mesh_motion"] = time_mesh_motion(mm, torch, wl, dmesh, args.steps, dev)
+        log(f"mesh motion: {out['mesh_motion']}")
     if not args.no_cpu_baseline:
         from oracle import oracle as O
         log("cpu baseline: oracle hydro step on the full workload (1 thread)")

@@ -537,6 +537,9 @@ void oracle_face_states(const om_mesh *M, const om_params *prm, double dt,
 void oracle_face_fluxes_ex(const om_mesh *M, const om_params *prm, double dt,
                            const double *W, const double *grad, double *face_flux,
                            int32_t *fallback, int32_t *kase, double *s_flux, double *mach);
+void oracle_face_fluxes_full(const om_mesh *M, const om_params *prm, double dt, const double *accel,
+                             const double *W, const double *grad, double *face_flux,
+                             int32_t *fallback, int32_t *kase, double *s_flux, double *mach);
 
 /* The face rule for the Mach number, given the Riemann case and p*. */
 static double riemann_shock_mach(double g, const double *L, const double *R, int kase, double ps)
@@ -561,6 +564,19 @@ void oracle_face_fluxes(const om_mesh *M, const om_params *prm, double dt,
 void oracle_face_fluxes_ex(const om_mesh *M, const om_params *prm, double dt,
                            const double *W, const double *grad, double *face_flux,
                            int32_t *fallback, int32_t *kase, double *s_flux, double *mach)
+{
+    oracle_face_fluxes_full(M, prm, dt, NULL, W, grad, face_flux, fallback, kase, s_flux, mach);
+}
+
+/* With an external static gravitational field (Section 5.2, the standard */
+/* coupling, applied to a field given per cell): accel [D][N] holds        */
+/* g_i = -grad Phi at each cell, and the half-step prediction of each      */
+/* side's velocity gains (dt/2) g_K. Reading: the kick belongs to the      */
+/* extrapolated prediction, so a face that falls back to unextrapolated    */
+/* states (non-positive prediction) takes none. accel NULL: no field.      */
+void oracle_face_fluxes_full(const om_mesh *M, const om_params *prm, double dt, const double *accel,
+                             const double *W, const double *grad, double *face_flux,
+                             int32_t *fallback, int32_t *kase, double *s_flux, double *mach)
 {
     const int D = M->dim, nv = D + 2;
     const int64_t n = M->n_cells, nf = M->n_faces;
@@ -587,6 +603,8 @@ void oracle_face_fluxes_ex(const om_mesh *M, const om_params *prm, double dt,
             for (int c = 0; c < nv; c++)
                 for (int k = 0; k < D; k++) gr[c][k] = grad[(c * D + k) * n + i];
             half_step(D, g, dt, Wp[s], gr, dx, Wpp[s]);
+            if (accel)
+                for (int k = 0; k < D; k++) Wpp[s][1 + k] += 0.5 * dt * accel[k * n + i];
         }
         int fb = !(Wpp[0][0] > 0.0 && Wpp[0][nv - 1] > 0.0 && Wpp[1][0] > 0.0 && Wpp[1][nv - 1] > 0.0);
         if (fb) memcpy(Wpp, Wp, sizeof(Wp));
@@ -711,15 +729,52 @@ double oracle_hydro_step(const om_mesh *M, const om_params *prm, double dt, doub
 /* only with positive new mass and entropy; mach_thresh <= 0 never keeps.*/
 /* kept [N] (may be NULL) receives 1 where the entropy was kept.         */
 /* ------------------------------------------------------------------ */
+void oracle_update_full(const om_mesh *M, const om_params *prm, double dt, const double *accel,
+                        const double *face_flux, const double *s_flux, const double *mach, double mach_thresh,
+                        double *Q, int32_t *kept);
+
 void oracle_apply_update_entropy(const om_mesh *M, const om_params *prm, const double *face_flux,
                                  const double *s_flux, const double *mach, double mach_thresh,
                                  double *Q, int32_t *kept)
 {
+    oracle_update_full(M, prm, 0.0, NULL, face_flux, s_flux, mach, mach_thresh, Q, kept);
+}
+
+/* The update with the optional parts: after the conservative sums of all */
+/* rows, the gravitational source terms of Section 5.2 for a static field */
+/* g_i (accel, may be NULL), with m_i^(n+1) from the mass fluxes:          */
+/*   p_i += (dt/2) (m_i^(n) + m_i^(n+1)) g_i,                              */
+/*   E_i += (dt/2) (p_i^(n) + p_i^(n+1)) . g_i  (m v at both ends),        */
+/* then, with s_flux (may be NULL), the entropy treatment above.          */
+void oracle_update_full(const om_mesh *M, const om_params *prm, double dt, const double *accel,
+                        const double *face_flux, const double *s_flux, const double *mach, double mach_thresh,
+                        double *Q, int32_t *kept)
+{
     const int D = M->dim, nv = D + 2;
     const int64_t n = M->n_cells, nf = M->n_faces;
     const double g = prm->gamma;
-    double *mmax = (double *)calloc((size_t)n, sizeof(double));
+    double *old = NULL;
+    if (accel) {
+        old = (double *)malloc(sizeof(double) * (D + 1) * n);
+        memcpy(old, Q, sizeof(double) * (D + 1) * n);        /* m, p at the start */
+    }
     oracle_apply_update(M, face_flux, Q);
+    if (accel) {
+        for (int64_t i = 0; i < n; i++) {
+            const double m0 = old[i], m1 = Q[i];
+            double work = 0.0;
+            for (int k = 0; k < D; k++) {
+                const double gk = accel[k * n + i], p0 = old[(1 + k) * n + i];
+                const double p1 = Q[(1 + k) * n + i] + 0.5 * dt * (m0 + m1) * gk;
+                Q[(1 + k) * n + i] = p1;
+                work += (p0 + p1) * gk;
+            }
+            Q[(nv - 1) * n + i] += 0.5 * dt * work;
+        }
+        free(old);
+    }
+    if (!s_flux) return;
+    double *mmax = (double *)calloc((size_t)n, sizeof(double));
     for (int64_t f = 0; f < nf; f++) {
         int64_t l = M->face_L[f], r = M->face_R[f];
         Q[nv * n + l] -= s_flux[f];
@@ -848,4 +903,26 @@ void oracle_volume_rate(const om_mesh *M, double *rate)
             rate[i] -= M->face_area[f] * term;
         }
     }
+}
+
+/* The step with every option: static gravity (accel [D][N] or NULL) and */
+/* the entropy row (entropy != 0: Q is [D+3][N]).                         */
+double oracle_hydro_step_full(const om_mesh *M, const om_params *prm, double dt, const double *accel,
+                              int entropy, double mach_thresh, double *Q, int32_t *kept)
+{
+    const int D = M->dim, nv = D + 2;
+    const int64_t n = M->n_cells, nf = M->n_faces;
+    double *W = (double *)malloc(sizeof(double) * nv * n);
+    double *gr = (double *)malloc(sizeof(double) * nv * D * n);
+    double *gl = (double *)malloc(sizeof(double) * nv * D * n);
+    double *fl = (double *)malloc(sizeof(double) * nv * nf);
+    double *sf = entropy ? (double *)malloc(sizeof(double) * nf) : NULL;
+    double *mc = entropy ? (double *)malloc(sizeof(double) * nf) : NULL;
+    oracle_prim(D, n, prm->gamma, M->volume, Q, W);
+    oracle_gradients(M, W, gr, gl, NULL);
+    if (!(dt > 0.0)) dt = oracle_cfl_dt(M, prm, W);
+    oracle_face_fluxes_full(M, prm, dt, accel, W, gl, fl, NULL, NULL, sf, mc);
+    oracle_update_full(M, prm, dt, accel, fl, sf, mc, mach_thresh, Q, kept);
+    free(W); free(gr); free(gl); free(fl); free(sf); free(mc);
+    return dt;
 }

@@ -68,6 +68,11 @@ def _lib():
         lib.oracle_mesh_velocity.argtypes = [ctypes.POINTER(_OMesh), ctypes.POINTER(_OParams), _dp, ctypes.c_double,
                                              ctypes.c_double, ctypes.c_double, _dp]
         lib.oracle_volume_rate.argtypes = [ctypes.POINTER(_OMesh), _dp]
+        lib.oracle_face_fluxes_full.argtypes = [ctypes.POINTER(_OMesh), ctypes.POINTER(_OParams), ctypes.c_double,
+                                                _dp, _dp, _dp, _dp, _ip, _ip, _dp, _dp]
+        lib.oracle_hydro_step_full.restype = ctypes.c_double
+        lib.oracle_hydro_step_full.argtypes = [ctypes.POINTER(_OMesh), ctypes.POINTER(_OParams), ctypes.c_double,
+                                               _dp, ctypes.c_int32, ctypes.c_double, _dp, _ip]
         lib.oracle_shock_mach.restype = ctypes.c_double
         lib.oracle_shock_mach.argtypes = [ctypes.c_double, _dp, _dp]
         _LIB = lib
@@ -199,6 +204,33 @@ def hydro_step_entropy(mesh, gamma, cfl, Q, mach_thresh, dt=0.0):
     used = _lib().oracle_hydro_step_entropy(ctypes.byref(h.s), ctypes.byref(p), float(dt), float(mach_thresh),
                                             _d(Q), _i(kept))
     return Q, used, kept
+
+
+def face_fluxes_gravity(mesh, gamma, dt, W, grad, accel):
+    """face_fluxes with the half-step kick of a static field accel [D][N]
+    (Section 5.2)."""
+    h = _Held(mesh)
+    fl = np.empty((h.dim + 2, h.nf))
+    p = _OParams(float(gamma), 0.0)
+    _lib().oracle_face_fluxes_full(ctypes.byref(h.s), ctypes.byref(p), float(dt), _d(_f64(accel)), _d(_f64(W)),
+                                   _d(_f64(grad)), _d(fl), None, None, None, None)
+    return fl
+
+
+def hydro_step_full(mesh, gamma, cfl, Q, dt=0.0, accel=None, mach_thresh=None):
+    """One step with the options: a static field accel [D][N] (Section 5.2)
+    and, with mach_thresh, the entropy row (Q [D+3][N], Section 3.5).
+    Returns (Q_new, dt_used, kept or None)."""
+    h = _Held(mesh)
+    Q = _f64(Q).copy()
+    ent = mach_thresh is not None
+    kept = np.empty(h.n, dtype=np.int32)
+    p = _OParams(float(gamma), float(cfl))
+    acc = _f64(accel) if accel is not None else None
+    used = _lib().oracle_hydro_step_full(ctypes.byref(h.s), ctypes.byref(p), float(dt),
+                                         _d(acc) if acc is not None else None, int(ent),
+                                         float(mach_thresh) if ent else 0.0, _d(Q), _i(kept))
+    return Q, used, (kept if ent else None)
 
 
 def mesh_velocity(mesh, gamma, W, eta=0.25, chi=1.0, dt_lloyd=0.0):
