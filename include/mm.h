@@ -238,6 +238,18 @@ mm_status mm_volume_rate(mm_ctx *ctx, double *rate);
  * MM_E_STATE without a mesh. */
 mm_status mm_mesh_set_velocity(mm_ctx *ctx, const double *mesh_vel);
 
+/* An external static gravitational field for the uploaded mesh (Section
+ * 5.2, the standard coupling): accel [D][N] (device, kept by reference
+ * until the next mm_mesh_upload, which clears it) holds g_i = -grad Phi at
+ * every cell; NULL switches the field off. With a field, the face-flux pass
+ * adds (dt/2) g_K to each side's predicted velocity (not to faces that fall
+ * back to unextrapolated states), and the update adds
+ * (dt/2)(m^n + m^(n+1)) g_i to the momentum and (dt/2)(p^n + p^(n+1)).g_i
+ * to the energy, dt being that of the last face-flux pass (mm_apply_update
+ * returns MM_E_STATE if none has run since the upload). The field is held
+ * fixed over the step. MM_E_STATE without a mesh. */
+mm_status mm_set_gravity(mm_ctx *ctx, const double *accel);
+
 /* ------------------------------------------------------------------------
  * Learned starting guess for the Newton iteration on the star pressure
  * (a 3 -> 64 -> 64 -> 1 ReLU network; not part of the paper's method, which

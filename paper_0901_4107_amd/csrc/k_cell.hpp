@@ -283,12 +283,16 @@ k_grad_limit(int64_t n, const int32_t *__restrict__ off,
 // entropy, keeps it: P = (S/M) rho^gamma and E = P V/(gamma-1) + |p|^2/(2M).
 // Every other cell takes S = M P / rho^gamma of its updated state (0 for
 // M <= 0). The cells that keep are counted in entropy_kept.
-template <int D, bool ENT>
+// GRAV (Section 5.2, a static field g = accel [D][n]): before the entropy
+// treatment, p += (dt/2)(M^n + M^(n+1)) g and E += (dt/2)(p^n + p^(n+1)).g,
+// dt from dt_ptr when it is set, else dt_val.
+template <int D, bool ENT, bool GRAV>
 __global__ void __launch_bounds__(kBlock) k_update(int64_t n, const int32_t *__restrict__ off,
                                                    const int32_t *__restrict__ ent, const double *__restrict__ flux,
                                                    double *__restrict__ Q, int32_t *__restrict__ flags,
                                                    const double *__restrict__ V, double gamma, double mach_thresh,
-                                                   DiagDev *diag) {
+                                                   DiagDev *diag, const double *__restrict__ accel,
+                                                   const double *__restrict__ dt_ptr, double dt_val) {
     constexpr int NV = D + 2;
     constexpr int FS = NV + (ENT ? 2 : 0);   // record stride
     constexpr int NS = NV + (ENT ? 1 : 0);   // summed rows
@@ -328,6 +332,16 @@ __global__ void __launch_bounds__(kBlock) k_update(int64_t n, const int32_t *__r
     if (lane == 0) {
         double q[NS];
         for (int c = 0; c < NS; c++) q[c] = Q[c * n + i] + acc[c];
+        if constexpr (GRAV) {
+            const double hdt = 0.5 * (dt_ptr ? *dt_ptr : dt_val), m0 = Q[i];
+            double work = 0.0;
+            for (int k = 0; k < D; k++) {
+                const double gk = accel[k * n + i], p0 = Q[(1 + k) * n + i];
+                q[1 + k] += hdt * (m0 + q[0]) * gk;
+                work += (p0 + q[1 + k]) * gk;
+            }
+            q[NV - 1] += hdt * work;
+        }
         if constexpr (ENT) {
             const double m = q[0], S = q[NV];
             keep = mx < mach_thresh && m > 0.0 && S > 0.0;

@@ -369,13 +369,17 @@ __device__ __forceinline__ void lab_flux(double rho, double u, double P, const d
 // kernel. Every thread of the block calls it (the learned staging holds barriers);
 // active = false does no face. LEARNED compiles the fused network in; the
 // standard-guess instantiation carries none of its registers. ENT adds the
-// entropy flux and the shock Mach number (X).
-template <int D, bool LEARNED, bool ENT>
+// entropy flux and the shock Mach number (X). GRAV adds the half-step kick
+// (dt/2) g_K of a static field (Section 5.2; accel [D][n], g = -grad Phi)
+// to each side's predicted velocity; a face that falls back to its
+// unextrapolated states takes none.
+template <int D, bool LEARNED, bool ENT, bool GRAV>
 __device__ __forceinline__ void face_flux64(bool active, int64_t f, const int32_t *__restrict__ fL,
                                             const int32_t *__restrict__ fR, const double *__restrict__ frec,
                                             const double *__restrict__ prim, const double *__restrict__ grad,
                                             double dt, const GasConst<double> &kg, double tol, int maxit,
-                                            const MlpPacked *mlp, LaneDiag &ld, double (&F)[D + 2], double (&X)[2]) {
+                                            const MlpPacked *mlp, const double *__restrict__ accel, int64_t n,
+                                            LaneDiag &ld, double (&F)[D + 2], double (&X)[2]) {
     using Y = Lay<D>;
     constexpr int NV = D + 2;
     double A = 0.0, nrm[D], w[D], xl[NV], xr[NV], uL = 0.0, uR = 0.0;
@@ -401,6 +405,13 @@ __device__ __forceinline__ void face_flux64(bool active, int64_t f, const int32_
         half_step<D, double>(rl, vf, gL, kg.g, hdt, xl, cl);
         for (int k = 0; k < D; k++) vf[k] = rr.p[Y::W + 1 + k] - w[k];
         half_step<D, double>(rr, vf, gR, kg.g, hdt, xr, cr);
+        if constexpr (GRAV) {
+            const int64_t l = fL[f], r = fR[f];
+            for (int k = 0; k < D; k++) {
+                xl[1 + k] += hdt * accel[k * n + l];
+                xr[1 + k] += hdt * accel[k * n + r];
+            }
+        }
         if (!(xl[0] > 0.0 && xl[NV - 1] > 0.0 && xr[0] > 0.0 && xr[NV - 1] > 0.0)) {
             for (int c = 0; c < NV; c++) { xl[c] = cl[c]; xr[c] = cr[c]; }
             ld.posfb += 1;
@@ -434,13 +445,14 @@ __device__ __forceinline__ void face_flux64(bool active, int64_t f, const int32_
 // Double-precision face flux kernel: one lane per face, fluxes stored
 // face-major (ENT: each record followed by the entropy flux and the Mach
 // number).
-template <int D, bool LEARNED, bool ENT>
+template <int D, bool LEARNED, bool ENT, bool GRAV>
 __global__ void __launch_bounds__(kBlock) k_face_flux64(int64_t nf, const int32_t *__restrict__ fL,
                                                         const int32_t *__restrict__ fR, const double *__restrict__ frec,
                                                         const double *__restrict__ prim, const double *__restrict__ grad,
                                                         const double *__restrict__ dt_ptr, double dt_val,
                                                         GasConst<double> kg, double tol, int maxit,
-                                                        const MlpPacked *mlp, double *__restrict__ flux, DiagDev *diag) {
+                                                        const MlpPacked *mlp, double *__restrict__ flux, DiagDev *diag,
+                                                        const double *__restrict__ accel, int64_t n) {
     constexpr int NV = D + 2;
     constexpr int FS = NV + (ENT ? 2 : 0);
     const int64_t f = xcd_global_id();
@@ -448,7 +460,8 @@ __global__ void __launch_bounds__(kBlock) k_face_flux64(int64_t nf, const int32_
     LaneDiag ld;
     const double dt = dt_ptr ? *dt_ptr : dt_val;
     double F[NV], X[2];
-    face_flux64<D, LEARNED, ENT>(active, f, fL, fR, frec, prim, grad, dt, kg, tol, maxit, mlp, ld, F, X);
+    face_flux64<D, LEARNED, ENT, GRAV>(active, f, fL, fR, frec, prim, grad, dt, kg, tol, maxit, mlp, accel, n, ld,
+                                       F, X);
     if (active) store_face<NV, FS>(flux + f * FS, F, X);
     if (diag) flush_diag(ld, diag);
 }
@@ -463,12 +476,13 @@ template <int D> struct MixedFace {
     bool posfb;
 };
 
-template <int D>
+template <int D, bool GRAV>
 __device__ __forceinline__ MixedFace<D> mixed_face_states(int64_t f, const int32_t *__restrict__ fL,
                                                           const int32_t *__restrict__ fR,
                                                           const float *__restrict__ mrec,
                                                           const float *__restrict__ prim,
-                                                          const float *__restrict__ grad, float hdt, float gam) {
+                                                          const float *__restrict__ grad, float hdt, float gam,
+                                                          const double *__restrict__ accel, int64_t n) {
     using Y = Lay<D>;
     constexpr int NV = D + 2;
     MixedFace<D> o;
@@ -493,6 +507,13 @@ __device__ __forceinline__ MixedFace<D> mixed_face_states(int64_t f, const int32
     half_step<D, float>(rl, vf, gL, gam, hdt, o.xl, cl);
     for (int k = 0; k < D; k++) vf[k] = rr.p[Y::W + 1 + k] + (-0.5f * dw[k] - proj * o.nrm[k]);
     half_step<D, float>(rr, vf, gR, gam, hdt, o.xr, cr);
+    if constexpr (GRAV) {   // the half-step kick of a static field (Section 5.2)
+        const int64_t l = fL[f], r = fR[f];
+        for (int k = 0; k < D; k++) {
+            o.xl[1 + k] += hdt * (float)accel[k * n + l];
+            o.xr[1 + k] += hdt * (float)accel[k * n + r];
+        }
+    }
     o.posfb = !(o.xl[0] > 0.0f && o.xl[NV - 1] > 0.0f && o.xr[0] > 0.0f && o.xr[NV - 1] > 0.0f);
     if (o.posfb)
         for (int c = 0; c < NV; c++) { o.xl[c] = cl[c]; o.xr[c] = cr[c]; }
@@ -527,18 +548,19 @@ __device__ __forceinline__ void mixed_lab_flux(const MixedFace<D> &m, double rho
 // barriers); active = false does no face. While the network runs, the face
 // states wait in LDS, so the network's registers come on top of few live
 // values.
-template <int D, bool LEARNED, bool ENT>
+template <int D, bool LEARNED, bool ENT, bool GRAV>
 __device__ __forceinline__ void face_flux_mixed(bool active, int64_t f, const int32_t *__restrict__ fL,
                                                 const int32_t *__restrict__ fR, const float *__restrict__ mrec,
                                                 const double *__restrict__ wf64, const float *__restrict__ prim,
                                                 const float *__restrict__ grad, double dt, const GasConst<float> &kf,
                                                 double g_over_gm1, float tol32, int maxit, const MlpPacked *mlp,
+                                                const double *__restrict__ accel, int64_t n,
                                                 LaneDiag &ld, bool &hard, double (&F)[D + 2], double (&X)[2]) {
     constexpr int NV = D + 2;
     hard = false;
     MixedFace<D> m;
     if (active) {
-        m = mixed_face_states<D>(f, fL, fR, mrec, prim, grad, (float)(0.5 * dt), kf.g);
+        m = mixed_face_states<D, GRAV>(f, fL, fR, mrec, prim, grad, (float)(0.5 * dt), kf.g, accel, n);
         ld.posfb += m.posfb ? 1 : 0;
     } else {
         for (int c = 0; c < NV; c++) { m.xl[c] = 1.0f; m.xr[c] = 1.0f; }
@@ -589,7 +611,7 @@ __device__ __forceinline__ void face_flux_mixed(bool active, int64_t f, const in
 // Mixed-precision face flux kernel: one lane per face; hard faces are
 // appended to a split list (wave-aggregated) and left to k_face_flux_hard.
 // Held to 7 wavefronts per SIMD (72 registers, no spills).
-template <int D, bool LEARNED, bool ENT>
+template <int D, bool LEARNED, bool ENT, bool GRAV>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) k_face_flux_mixed(int64_t nf, const int32_t *__restrict__ fL,
                                                             const int32_t *__restrict__ fR,
                                                             const float *__restrict__ mrec,
@@ -600,7 +622,8 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))
                                                             GasConst<float> kf, double g_over_gm1, float tol32,
                                                             int maxit, const MlpPacked *mlp,
                                                             double *__restrict__ flux, int32_t *__restrict__ hard_list,
-                                                            int64_t cap, DiagDev *diag) {
+                                                            int64_t cap, DiagDev *diag,
+                                                            const double *__restrict__ accel, int64_t n) {
     constexpr int NV = D + 2;
     constexpr int FS = NV + (ENT ? 2 : 0);
     const int64_t f = xcd_global_id();
@@ -609,8 +632,8 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))
     bool hard;
     const double dt = dt_ptr ? *dt_ptr : dt_val;
     double F[NV], X[2];
-    face_flux_mixed<D, LEARNED, ENT>(active, f, fL, fR, mrec, wf64, prim, grad, dt, kf, g_over_gm1, tol32, maxit,
-                                     mlp, ld, hard, F, X);
+    face_flux_mixed<D, LEARNED, ENT, GRAV>(active, f, fL, fR, mrec, wf64, prim, grad, dt, kf, g_over_gm1, tol32,
+                                           maxit, mlp, accel, n, ld, hard, F, X);
     if (active && !hard) store_face<NV, FS>(flux + f * FS, F, X);
     list_append(hard_list, cap, hard, (int32_t)f);
     if (diag) flush_diag(ld, diag);
@@ -620,7 +643,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))
 // list of sub-list capacity cap). A fixed grid walks the list, so the
 // launch needs no host-side count; the float face states are recomputed by
 // the same code, hence identical.
-template <int D, bool ENT>
+template <int D, bool ENT, bool GRAV>
 __global__ void __launch_bounds__(kBlock) k_face_flux_hard(const int32_t *__restrict__ fL,
                                                            const int32_t *__restrict__ fR,
                                                            const float *__restrict__ mrec,
@@ -630,7 +653,8 @@ __global__ void __launch_bounds__(kBlock) k_face_flux_hard(const int32_t *__rest
                                                            const double *__restrict__ dt_ptr, double dt_val,
                                                            float gam, GasConst<double> kg, double tol64,
                                                            const int32_t *__restrict__ hard_list, int64_t cap,
-                                                           double *__restrict__ flux, DiagDev *diag) {
+                                                           double *__restrict__ flux, DiagDev *diag,
+                                                           const double *__restrict__ accel, int64_t n) {
     constexpr int NV = D + 2;
     constexpr int FS = NV + (ENT ? 2 : 0);
     const ListWalk lw = list_walk(hard_list, cap);
@@ -638,7 +662,7 @@ __global__ void __launch_bounds__(kBlock) k_face_flux_hard(const int32_t *__rest
     LaneDiag ld;
     for (int64_t q = lw.start; q < lw.count; q += lw.stride) {
         const int64_t f = lw.items[q];
-        const MixedFace<D> m = mixed_face_states<D>(f, fL, fR, mrec, prim, grad, (float)(0.5 * dt), gam);
+        const MixedFace<D> m = mixed_face_states<D, GRAV>(f, fL, fR, mrec, prim, grad, (float)(0.5 * dt), gam, accel, n);
         bool h2;
         FaceState<double> fd = solve_face<double>(m.xl[0], m.uL, m.xl[NV - 1], m.xr[0], m.uR, m.xr[NV - 1], kg,
                                                   tol64, 50, no_guess<double>(), false, ld, h2);

@@ -87,6 +87,10 @@ struct mm_ctx {
     int64_t n = 0, nf = 0;
     uint64_t faces_done = 0, waves_done = 0;
     mm_mesh mesh;
+    const double *accel = nullptr;        // static gravitational field [D][N], or none
+    const double *last_dt_dev = nullptr;  // timestep of the last face-flux pass (device) ...
+    double last_dt = 0.0;                 // ... or its value
+    bool have_dt = false;
     Layout lay;
     hipStream_t st() const { return (hipStream_t)p.stream; }
     template <typename T> T *at(int64_t off) const { return (T *)(ws + off); }
@@ -238,6 +242,8 @@ mm_status mm_mesh_upload(mm_ctx *c, const mm_mesh *m) {
     Layout L = make_layout(c->D, c->p.mode, c->p.entropy != 0, n, nf);
     if (L.total > c->ws_bytes) return MM_E_WORKSPACE;
     c->have_mesh = false;
+    c->accel = nullptr;   // a field belongs to the mesh it was set for
+    c->have_dt = false;
     c->lay = L;
     c->n = n;
     c->nf = nf;
@@ -332,7 +338,7 @@ mm_status mm_gradients(mm_ctx *c, const double *Q, void *recon) {
     return gradients_into(c, Q, recon, c->at<double>(c->lay.dtpart));
 }
 
-template <int D, bool ENT>
+template <int D, bool ENT, bool GRAV>
 static mm_status fluxes_t(mm_ctx *c, const double *dt_dev, double dt, const void *rec, double *flux) {
     const Layout &L = c->lay;
     hipStream_t s = c->st();
@@ -341,25 +347,26 @@ static mm_status fluxes_t(mm_ctx *c, const double *dt_dev, double dt, const void
     const GasConst<double> kg(c->p.gamma);
     const GasConst<float> kf(c->p.gamma);
     if (c->p.mode == MM_FP64) {
-        auto kern = mlp ? k_face_flux64<D, true, ENT> : k_face_flux64<D, false, ENT>;
+        auto kern = mlp ? k_face_flux64<D, true, ENT, GRAV> : k_face_flux64<D, false, ENT, GRAV>;
         const double *prim = (const double *)rec;
         kern<<<grid_for(c->nf), kBlock, 0, s>>>(c->nf, c->mesh.face_L, c->mesh.face_R, c->at<double>(L.frec), prim,
                                                 grad_block<D>(c, prim), dt_dev, dt, kg, c->p.newton_tol64,
-                                                c->p.newton_max_iter, mlp, flux, diag);
+                                                c->p.newton_max_iter, mlp, flux, diag, c->accel, c->n);
     } else {
         int32_t *hard = c->at<int32_t>(L.hard);
         const int64_t cap = list_cap(grid_for(c->nf));
         k_fill_i32<<<kLists * kListPad / kBlock, kBlock, 0, s>>>(hard, kLists * kListPad, 0);
-        auto kern = mlp ? k_face_flux_mixed<D, true, ENT> : k_face_flux_mixed<D, false, ENT>;
+        auto kern = mlp ? k_face_flux_mixed<D, true, ENT, GRAV> : k_face_flux_mixed<D, false, ENT, GRAV>;
         const float *prim = (const float *)rec;
         kern<<<grid_for(c->nf), kBlock, 0, s>>>(c->nf, c->mesh.face_L, c->mesh.face_R, c->at<float>(L.mrec),
                                                 c->at<double>(L.wf64), prim, grad_block<D>(c, prim), dt_dev, dt, kf,
                                                 kg.g_over_gm1, (float)c->p.newton_tol32, c->p.newton_max_iter, mlp,
-                                                flux, hard, cap, diag);
-        k_face_flux_hard<D, ENT><<<kHardGrid, kBlock, 0, s>>>(c->mesh.face_L, c->mesh.face_R, c->at<float>(L.mrec),
+                                                flux, hard, cap, diag, c->accel, c->n);
+        k_face_flux_hard<D, ENT, GRAV><<<kHardGrid, kBlock, 0, s>>>(c->mesh.face_L, c->mesh.face_R, c->at<float>(L.mrec),
                                                         c->at<double>(L.wf64), prim, grad_block<D>(c, prim), dt_dev,
                                                         dt, kf.g,
-                                                        kg, c->p.newton_tol64, hard, cap, flux, diag);
+                                                        kg, c->p.newton_tol64, hard, cap, flux, diag, c->accel,
+                                                        c->n);
     }
     MM_LAUNCH_CHECK();
     return MM_OK;
@@ -368,9 +375,16 @@ static mm_status fluxes_t(mm_ctx *c, const double *dt_dev, double dt, const void
 static mm_status fluxes_into(mm_ctx *c, const double *dt_dev, double dt, const void *rec, double *flux) {
     c->faces_done += (uint64_t)c->nf;
     c->waves_done += (uint64_t)((c->nf + 63) / 64);
-    if (c->p.entropy)
-        return c->D == 3 ? fluxes_t<3, true>(c, dt_dev, dt, rec, flux) : fluxes_t<2, true>(c, dt_dev, dt, rec, flux);
-    return c->D == 3 ? fluxes_t<3, false>(c, dt_dev, dt, rec, flux) : fluxes_t<2, false>(c, dt_dev, dt, rec, flux);
+    c->last_dt_dev = dt_dev;
+    c->last_dt = dt;
+    c->have_dt = true;
+    const bool e = c->p.entropy != 0, g = c->accel != nullptr;
+    if (c->D == 3) {
+        if (e) return g ? fluxes_t<3, true, true>(c, dt_dev, dt, rec, flux) : fluxes_t<3, true, false>(c, dt_dev, dt, rec, flux);
+        return g ? fluxes_t<3, false, true>(c, dt_dev, dt, rec, flux) : fluxes_t<3, false, false>(c, dt_dev, dt, rec, flux);
+    }
+    if (e) return g ? fluxes_t<2, true, true>(c, dt_dev, dt, rec, flux) : fluxes_t<2, true, false>(c, dt_dev, dt, rec, flux);
+    return g ? fluxes_t<2, false, true>(c, dt_dev, dt, rec, flux) : fluxes_t<2, false, false>(c, dt_dev, dt, rec, flux);
 }
 
 mm_status mm_face_fluxes(mm_ctx *c, double dt, const void *recon, double *face_flux) {
@@ -380,22 +394,31 @@ mm_status mm_face_fluxes(mm_ctx *c, double dt, const void *recon, double *face_f
     return fluxes_into(c, nullptr, dt, recon, face_flux);
 }
 
-template <int D, bool ENT> static void launch_update(mm_ctx *c, const double *flux, double *Q) {
+template <int D, bool ENT, bool GRAV> static void launch_update(mm_ctx *c, const double *flux, double *Q) {
     const Layout &L = c->lay;
-    k_update<D, ENT><<<group_grid(D, c->n), kBlock, 0, c->st()>>>(
+    k_update<D, ENT, GRAV><<<group_grid(D, c->n), kBlock, 0, c->st()>>>(
         c->n, c->at<int32_t>(L.off), c->at<int32_t>(L.ent), flux, Q, c->at<int32_t>(L.flags) + 1, c->mesh.volume,
-        c->p.gamma, c->p.mach_thresh, c->at<DiagDev>(L.diag));
+        c->p.gamma, c->p.mach_thresh, c->at<DiagDev>(L.diag), c->accel, c->last_dt_dev, c->last_dt);
+}
+
+template <int D> static void launch_update_d(mm_ctx *c, const double *flux, double *Q) {
+    const bool e = c->p.entropy != 0, g = c->accel != nullptr;
+    if (e) g ? launch_update<D, true, true>(c, flux, Q) : launch_update<D, true, false>(c, flux, Q);
+    else g ? launch_update<D, false, true>(c, flux, Q) : launch_update<D, false, false>(c, flux, Q);
 }
 
 static mm_status update_into(mm_ctx *c, const double *flux, double *Q) {
-    if (c->p.entropy) {
-        if (c->D == 3) launch_update<3, true>(c, flux, Q);
-        else launch_update<2, true>(c, flux, Q);
-    } else {
-        if (c->D == 3) launch_update<3, false>(c, flux, Q);
-        else launch_update<2, false>(c, flux, Q);
-    }
+    if (c->accel && !c->have_dt) return MM_E_STATE;   // the source terms need the flux pass's timestep
+    if (c->D == 3) launch_update_d<3>(c, flux, Q);
+    else launch_update_d<2>(c, flux, Q);
     MM_LAUNCH_CHECK();
+    return MM_OK;
+}
+
+mm_status mm_set_gravity(mm_ctx *c, const double *accel) {
+    if (!c) return MM_E_ARG;
+    if (!c->have_mesh) return MM_E_STATE;
+    c->accel = accel;
     return MM_OK;
 }
 

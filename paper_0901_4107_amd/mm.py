@@ -80,6 +80,7 @@ SIGNATURES = {
     "mm_mesh_velocity": (ctypes.c_int32, [_vp, _vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, _vp]),
     "mm_volume_rate": (ctypes.c_int32, [_vp, _vp]),
     "mm_mesh_set_velocity": (ctypes.c_int32, [_vp, _vp]),
+    "mm_set_gravity": (ctypes.c_int32, [_vp, _vp]),
 }
 
 MM_MLP_PARAMS = 4481
@@ -251,6 +252,10 @@ class Context:
     def mm_mesh_set_velocity(self, w: torch.Tensor):
         _check("mm_mesh_set_velocity", lib().mm_mesh_set_velocity(self._ctx, _ptr(w)))
         self._mesh_vel = w  # kept alive while the library refers to it
+
+    def mm_set_gravity(self, accel: torch.Tensor | None):
+        _check("mm_set_gravity", lib().mm_set_gravity(self._ctx, _ptr(accel)))
+        self._accel = accel  # kept alive while the library refers to it
 
     def mm_volume_rate(self, rate: torch.Tensor):
         _check("mm_volume_rate", lib().mm_volume_rate(self._ctx, _ptr(rate)))

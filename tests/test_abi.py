@@ -91,6 +91,7 @@ def test_workspace_and_state_errors_without_device():
         assert L.mm_mesh_velocity(ctx, P, 0.25, 1.0, 0.0, P) == mm.MM_E_STATE
         assert L.mm_volume_rate(ctx, P) == mm.MM_E_STATE
         assert L.mm_mesh_set_velocity(ctx, P) == mm.MM_E_STATE
+        assert L.mm_set_gravity(ctx, P) == mm.MM_E_STATE
         assert L.mm_volume_rate(ctx, None) == mm.MM_E_ARG
     finally:
         L.mm_destroy(ctx)
