@@ -236,7 +236,8 @@ def bench_step(args):
     nbytes, per_face, per_cell = flux_kernel_bytes(m.dim, m.n_cells, m.n_faces, mixed)
     achieved = nbytes / (head["flux_ms"] * 1e-3) / 1e9
     lrn = 'true' if args.mode.endswith('learned') else 'false'
-    kname = (f"k_face_flux_mixed<{m.dim}, {lrn}, false>" if mixed else f"k_face_flux64<{m.dim}, {lrn}, false>")
+    kname = (f"k_face_flux_mixed<{m.dim}, {lrn}, false, false>" if mixed
+             else f"k_face_flux64<{m.dim}, {lrn}, false, false>")
     from paper_0901_4107_amd.prof_summary import read_traffic
     traffic = read_traffic(os.path.join(ROOT, "profiles"), kname, wl.name)
     out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

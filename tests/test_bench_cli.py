@@ -30,10 +30,10 @@ def test_flux_byte_model():
 
 
 def test_traffic_record_follows_the_kernel_sources(tmp_path):
-    good = (f"traffic: kernel=k_face_flux_mixed<3, true, false> workload=w read_bytes=100 written_bytes=20 "
+    good = (f"traffic: kernel=k_face_flux_mixed<3, true, false, false> workload=w read_bytes=100 written_bytes=20 "
             f"source={source_hash()}\n")
-    stale = "traffic: kernel=k_face_flux64<3, false, false> workload=w read_bytes=7 written_bytes=1 source=0000000000000000\n"
+    stale = "traffic: kernel=k_face_flux64<3, false, false, false> workload=w read_bytes=7 written_bytes=1 source=0000000000000000\n"
     (tmp_path / "t.md").write_text("# summary\n\n" + good + stale)
-    assert read_traffic(str(tmp_path), "k_face_flux_mixed<3, true, false>", "w") == 120.0
-    assert read_traffic(str(tmp_path), "k_face_flux64<3, false, false>", "w") is None    # other sources
-    assert read_traffic(str(tmp_path), "k_face_flux_mixed<3, true, false>", "other") is None
+    assert read_traffic(str(tmp_path), "k_face_flux_mixed<3, true, false, false>", "w") == 120.0
+    assert read_traffic(str(tmp_path), "k_face_flux64<3, false, false, false>", "w") is None    # other sources
+    assert read_traffic(str(tmp_path), "k_face_flux_mixed<3, true, false, false>", "other") is None
