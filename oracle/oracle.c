@@ -574,78 +574,97 @@ void oracle_face_fluxes_ex(const om_mesh *M, const om_params *prm, double dt,
 /* side's velocity gains (dt/2) g_K. Reading: the kick belongs to the      */
 /* extrapolated prediction, so a face that falls back to unextrapolated    */
 /* states (non-positive prediction) takes none. accel NULL: no field.      */
-void oracle_face_fluxes_full(const om_mesh *M, const om_params *prm, double dt, const double *accel,
-                             const double *W, const double *grad, double *face_flux,
-                             int32_t *fallback, int32_t *kase, double *s_flux, double *mach)
+/* One face f: the sides are predicted over pdt[s]/2 (each side's own
+ * prediction interval; pdt[s] = dt in a global step) and the flux is
+ * integrated over fdt: out[c] = fdt A_f Fhat_c. wf holds the face
+ * velocities. Returns the positivity fallback flag; the Riemann case, the
+ * entropy flux and the Mach number go to the pointers that are set. */
+static int face_flux_one(const om_mesh *M, const om_params *prm, const double *wf, int64_t f,
+                         const double pdt[2], double fdt, const double *accel, const double *W,
+                         const double *grad, double *out_flux, int32_t *kase_out, double *sflux_out,
+                         double *mach_out)
 {
     const int D = M->dim, nv = D + 2;
     const int64_t n = M->n_cells, nf = M->n_faces;
     const double g = prm->gamma;
-    double *wf = (double *)malloc(sizeof(double) * D * nf);
+    int64_t cell[2] = {M->face_L[f], M->face_R[f]};
+    double d[3] = {0, 0, 0}, w[3] = {0, 0, 0}, nrm[3] = {0, 0, 0}, ell = 0.0;
+    for (int k = 0; k < D; k++) { d[k] = M->face_sep[k * nf + f]; ell += d[k] * d[k]; w[k] = wf[k * nf + f]; }
+    ell = sqrt(ell);
+    for (int k = 0; k < D; k++) nrm[k] = d[k] / ell;
+
+    double Wp[2][5], Wpp[2][5];
+    for (int s = 0; s < 2; s++) {
+        int64_t i = cell[s];
+        double dx[3] = {0, 0, 0}, gr[5][3];
+        for (int k = 0; k < D; k++)
+            dx[k] = M->face_ctr[k * nf + f] - (s ? d[k] : 0.0) - M->centroid_off[k * n + i];
+        Wp[s][0] = W[0 * n + i];
+        for (int k = 0; k < D; k++) Wp[s][1 + k] = W[(1 + k) * n + i] - w[k];
+        Wp[s][nv - 1] = W[(nv - 1) * n + i];
+        for (int c = 0; c < nv; c++)
+            for (int k = 0; k < D; k++) gr[c][k] = grad[(c * D + k) * n + i];
+        half_step(D, g, pdt[s], Wp[s], gr, dx, Wpp[s]);
+        if (accel)
+            for (int k = 0; k < D; k++) Wpp[s][1 + k] += 0.5 * pdt[s] * accel[k * n + i];
+    }
+    int fb = !(Wpp[0][0] > 0.0 && Wpp[0][nv - 1] > 0.0 && Wpp[1][0] > 0.0 && Wpp[1][nv - 1] > 0.0);
+    if (fb) memcpy(Wpp, Wp, sizeof(Wp));
+
+    /* normal / transverse split */
+    double un[2], tr[2][3] = {{0, 0, 0}, {0, 0, 0}};
+    for (int s = 0; s < 2; s++) {
+        double u = 0.0;
+        for (int k = 0; k < D; k++) u += Wpp[s][1 + k] * nrm[k];
+        un[s] = u;
+        for (int k = 0; k < D; k++) tr[s][k] = Wpp[s][1 + k] - u * nrm[k];
+    }
+    double Ls[3] = {Wpp[0][0], un[0], Wpp[0][nv - 1]};
+    double Rs[3] = {Wpp[1][0], un[1], Wpp[1][nv - 1]};
+    double out[4], st[2];
+    int k0 = oracle_riemann(g, Ls, Rs, out, st, NULL);
+    if (kase_out) *kase_out = k0;
+    double rhoF = out[0], uF = out[1], PF = out[2];
+    int side = out[3] > 0.5;
+
+    double vF[3] = {0, 0, 0};
+    for (int k = 0; k < D; k++) vF[k] = uF * nrm[k] + tr[side][k];
+    double mf = rhoF * uF;
+    double v2 = 0.0, w2 = 0.0, Piw = 0.0, Pi[3] = {0, 0, 0};
+    for (int k = 0; k < D; k++) {
+        v2 += vF[k] * vF[k];
+        w2 += w[k] * w[k];
+        Pi[k] = mf * vF[k] + PF * nrm[k];
+        Piw += Pi[k] * w[k];
+    }
+    double eps = mf * 0.5 * v2 + uF * PF * g / (g - 1.0);
+    double scale = fdt * M->face_area[f];
+    out_flux[0] = scale * mf;
+    for (int k = 0; k < D; k++) out_flux[1 + k] = scale * (Pi[k] + mf * w[k]);
+    out_flux[nv - 1] = scale * (eps + Piw + 0.5 * mf * w2);
+    if (sflux_out) {
+        const double *U = side ? Rs : Ls;
+        *sflux_out = (mf != 0.0) ? scale * mf * (U[2] / pow(U[0], g)) : 0.0;
+    }
+    if (mach_out) *mach_out = riemann_shock_mach(g, Ls, Rs, k0, st[0]);
+    return fb;
+}
+
+void oracle_face_fluxes_full(const om_mesh *M, const om_params *prm, double dt, const double *accel,
+                             const double *W, const double *grad, double *face_flux,
+                             int32_t *fallback, int32_t *kase, double *s_flux, double *mach)
+{
+    const int nv = M->dim + 2;
+    const int64_t nf = M->n_faces;
+    const double pdt[2] = {dt, dt};
+    double *wf = (double *)malloc(sizeof(double) * M->dim * nf);
     oracle_face_velocity(M, wf);
-
     for (int64_t f = 0; f < nf; f++) {
-        int64_t cell[2] = {M->face_L[f], M->face_R[f]};
-        double d[3] = {0, 0, 0}, w[3] = {0, 0, 0}, nrm[3] = {0, 0, 0}, ell = 0.0;
-        for (int k = 0; k < D; k++) { d[k] = M->face_sep[k * nf + f]; ell += d[k] * d[k]; w[k] = wf[k * nf + f]; }
-        ell = sqrt(ell);
-        for (int k = 0; k < D; k++) nrm[k] = d[k] / ell;
-
-        double Wp[2][5], Wpp[2][5];
-        for (int s = 0; s < 2; s++) {
-            int64_t i = cell[s];
-            double dx[3] = {0, 0, 0}, gr[5][3];
-            for (int k = 0; k < D; k++)
-                dx[k] = M->face_ctr[k * nf + f] - (s ? d[k] : 0.0) - M->centroid_off[k * n + i];
-            Wp[s][0] = W[0 * n + i];
-            for (int k = 0; k < D; k++) Wp[s][1 + k] = W[(1 + k) * n + i] - w[k];
-            Wp[s][nv - 1] = W[(nv - 1) * n + i];
-            for (int c = 0; c < nv; c++)
-                for (int k = 0; k < D; k++) gr[c][k] = grad[(c * D + k) * n + i];
-            half_step(D, g, dt, Wp[s], gr, dx, Wpp[s]);
-            if (accel)
-                for (int k = 0; k < D; k++) Wpp[s][1 + k] += 0.5 * dt * accel[k * n + i];
-        }
-        int fb = !(Wpp[0][0] > 0.0 && Wpp[0][nv - 1] > 0.0 && Wpp[1][0] > 0.0 && Wpp[1][nv - 1] > 0.0);
-        if (fb) memcpy(Wpp, Wp, sizeof(Wp));
+        double F[5];
+        int fb = face_flux_one(M, prm, wf, f, pdt, dt, accel, W, grad, F, kase ? kase + f : NULL,
+                               s_flux ? s_flux + f : NULL, mach ? mach + f : NULL);
         if (fallback) fallback[f] = fb;
-
-        /* normal / transverse split */
-        double un[2], tr[2][3] = {{0, 0, 0}, {0, 0, 0}};
-        for (int s = 0; s < 2; s++) {
-            double u = 0.0;
-            for (int k = 0; k < D; k++) u += Wpp[s][1 + k] * nrm[k];
-            un[s] = u;
-            for (int k = 0; k < D; k++) tr[s][k] = Wpp[s][1 + k] - u * nrm[k];
-        }
-        double Ls[3] = {Wpp[0][0], un[0], Wpp[0][nv - 1]};
-        double Rs[3] = {Wpp[1][0], un[1], Wpp[1][nv - 1]};
-        double out[4], st[2];
-        int k0 = oracle_riemann(g, Ls, Rs, out, st, NULL);
-        if (kase) kase[f] = k0;
-        double rhoF = out[0], uF = out[1], PF = out[2];
-        int side = out[3] > 0.5;
-
-        double vF[3] = {0, 0, 0};
-        for (int k = 0; k < D; k++) vF[k] = uF * nrm[k] + tr[side][k];
-        double mf = rhoF * uF;
-        double v2 = 0.0, w2 = 0.0, Piw = 0.0, Pi[3] = {0, 0, 0};
-        for (int k = 0; k < D; k++) {
-            v2 += vF[k] * vF[k];
-            w2 += w[k] * w[k];
-            Pi[k] = mf * vF[k] + PF * nrm[k];
-            Piw += Pi[k] * w[k];
-        }
-        double eps = mf * 0.5 * v2 + uF * PF * g / (g - 1.0);
-        double scale = dt * M->face_area[f];
-        face_flux[0 * nf + f] = scale * mf;
-        for (int k = 0; k < D; k++) face_flux[(1 + k) * nf + f] = scale * (Pi[k] + mf * w[k]);
-        face_flux[(nv - 1) * nf + f] = scale * (eps + Piw + 0.5 * mf * w2);
-        if (s_flux) {
-            const double *U = side ? Rs : Ls;
-            s_flux[f] = (mf != 0.0) ? scale * mf * (U[2] / pow(U[0], g)) : 0.0;
-        }
-        if (mach) mach[f] = riemann_shock_mach(g, Ls, Rs, k0, st[0]);
+        for (int c = 0; c < nv; c++) face_flux[c * nf + f] = F[c];
     }
     free(wf);
 }
@@ -925,4 +944,179 @@ double oracle_hydro_step_full(const om_mesh *M, const om_params *prm, double dt,
     oracle_update_full(M, prm, dt, accel, fl, sf, mc, mach_thresh, Q, kept);
     free(W); free(gr); free(gl); free(fl); free(sf); free(mc);
     return dt;
+}
+
+/* ------------------------------------------------------------------ */
+/* Section 7.2, individual timesteps.                                    */
+/*                                                                       */
+/* Criterion (eq. EqnTiStepIndividual, with the minimum over j taken over */
+/* the Voronoi neighbours only; the paper's tree walk over all cells is   */
+/* not modelled):                                                        */
+/*   dt_i = C min(tau_i, R_i / (c_i + |v_i - w_i|)),                     */
+/*   tau_i = min_j r_ij / v_sig_ij,                                      */
+/*   v_sig_ij = c_i + c_j - (v_i - v_j).(r_i - r_j)/r_ij.                */
+/* For a face with normal n = d/|d| (L to R) the projection is the same   */
+/* from both sides, (v_i - v_j).(r_i - r_j)/r_ij = (v_R - v_L).n, so each */
+/* face has one signal speed. Readings: a pair with v_sig <= 0 (receding */
+/* faster than sound) sets no bound; a vacuum cell (rho <= 0 or P <= 0)   */
+/* has c = 0 and sets no local bound, like the global Courant step.       */
+/* dt_out [N].                                                           */
+/* ------------------------------------------------------------------ */
+void oracle_tb_criterion(const om_mesh *M, const om_params *prm, const double *W, double *dt_out)
+{
+    const int D = M->dim, nv = D + 2;
+    const int64_t n = M->n_cells, nf = M->n_faces;
+    double *c = (double *)malloc(sizeof(double) * n);
+    double *tau = (double *)malloc(sizeof(double) * n);
+    for (int64_t i = 0; i < n; i++) {
+        const double rho = W[i], P = W[(nv - 1) * n + i];
+        c[i] = (rho > 0.0 && P > 0.0) ? sqrt(prm->gamma * P / rho) : 0.0;
+        tau[i] = INFINITY;
+    }
+    for (int64_t f = 0; f < nf; f++) {
+        const int64_t l = M->face_L[f], r = M->face_R[f];
+        double ell = 0.0, du = 0.0;
+        for (int k = 0; k < D; k++) ell += M->face_sep[k * nf + f] * M->face_sep[k * nf + f];
+        ell = sqrt(ell);
+        for (int k = 0; k < D; k++)
+            du += (W[(1 + k) * n + r] - W[(1 + k) * n + l]) * (M->face_sep[k * nf + f] / ell);
+        const double vsig = (c[l] + c[r]) - du;
+        if (vsig > 0.0) {
+            const double t = ell / vsig;
+            if (t < tau[l]) tau[l] = t;
+            if (t < tau[r]) tau[r] = t;
+        }
+    }
+    for (int64_t i = 0; i < n; i++) {
+        const double rho = W[i], P = W[(nv - 1) * n + i];
+        double loc = INFINITY;
+        if (rho > 0.0 && P > 0.0) {
+            const double V = M->volume[i];
+            const double R = (D == 3) ? cbrt(3.0 * V / (4.0 * PI_D)) : sqrt(V / PI_D);
+            double rel = 0.0;
+            for (int k = 0; k < D; k++) {
+                const double dv = W[(1 + k) * n + i] - M->mesh_vel[k * n + i];
+                rel += dv * dv;
+            }
+            loc = R / (c[i] + sqrt(rel));
+        }
+        dt_out[i] = prm->cfl * (tau[i] < loc ? tau[i] : loc);
+    }
+    free(c);
+    free(tau);
+}
+
+/* ------------------------------------------------------------------ */
+/* One synchronisation point of the individual-timestep integration      */
+/* (Section 7.2). Time is counted in ticks of dt_max / 2^L; a cell in bin */
+/* b takes steps of 2^b ticks that start at multiples of 2^b (the power-  */
+/* of-two hierarchy; bin L is the step dt_max). At tick ti:              */
+/*  1. the cells whose step ends now (ti a multiple of 2^bin) are active: */
+/*     their primitives are recomputed from Q and stamped trec = ti;      */
+/*  2. each active cell takes the bin of the largest power-of-two         */
+/*     subdivision of dt_max not above its criterion dt_i; it may move    */
+/*     down any number of bins, but up by one bin only, and only when the */
+/*     higher bin starts a step at ti (at most every second step);        */
+/*  3. the gradients (with the limiter) of the active cells are rebuilt   */
+/*     from the stored primitives of all cells: fresh for the active,     */
+/*     those of the last active step for the rest;                       */
+/*  4. a face is active when the smaller step of its two cells starts at  */
+/*     ti; it is integrated over that step, fdt = 2^min(bL,bR) ticks, and */
+/*     each side is predicted from its stored record to the middle of the */
+/*     face's step, (ti - trec) ticks + fdt/2 after the record was made;  */
+/*     both cells exchange the time-integrated flux (conservative);       */
+/*  5. the next synchronisation point is the next multiple of the step of */
+/*     the smallest occupied bin.                                        */
+/* Arrays carried between calls: bin [N] (int8; all L before the first   */
+/* call, when every cell is due), trec [N], W [D+2][N], G [(D+2)D][N].   */
+/* face_dt [F] (may be NULL) receives fdt of the active faces, 0 for the  */
+/* others; pred [2][F] (may be NULL) the prediction interval of each side */
+/* (left, right) of the active faces; active [N] (may be NULL) 1 for the  */
+/* active cells. Returns 0, or                                           */
+/* 1 when an active cell's criterion falls below one tick (no bin fits):  */
+/* then steps 3-5 are not done and Q is untouched.                       */
+/* ------------------------------------------------------------------ */
+int oracle_tb_step(const om_mesh *M, const om_params *prm, double dt_max, int32_t L, int64_t ti,
+                   int8_t *bin, int64_t *trec, double *W, double *G, double *Q, double *face_dt,
+                   double *pred, int32_t *active, int64_t *next_ti, int64_t *n_active_faces)
+{
+    const int D = M->dim, nv = D + 2;
+    const int64_t n = M->n_cells, nf = M->n_faces;
+    const double tick = ldexp(dt_max, -L);
+    int8_t *act = (int8_t *)malloc(n);
+    double *Wn = (double *)malloc(sizeof(double) * nv * n);
+    double *dti = (double *)malloc(sizeof(double) * n);
+    int status = 0;
+
+    /* 1 */
+    oracle_prim(D, n, prm->gamma, M->volume, Q, Wn);
+    for (int64_t i = 0; i < n; i++) {
+        act[i] = (ti & ((INT64_C(1) << bin[i]) - 1)) == 0;
+        if (active) active[i] = act[i];
+        if (!act[i]) continue;
+        trec[i] = ti;
+        for (int c = 0; c < nv; c++) W[c * n + i] = Wn[c * n + i];
+    }
+    /* 2 */
+    oracle_tb_criterion(M, prm, W, dti);
+    for (int64_t i = 0; i < n; i++) {
+        if (!act[i]) continue;
+        if (!(dti[i] >= tick)) { status = 1; continue; }
+        int b = L;
+        while (b > 0 && ldexp(dt_max, b - L) > dti[i]) b--;
+        const int old = bin[i];
+        if (b <= old) bin[i] = (int8_t)b;
+        else if ((ti & ((INT64_C(1) << (old + 1)) - 1)) == 0) bin[i] = (int8_t)(old + 1);
+    }
+    if (status) goto done;
+    /* 3 */
+    {
+        double *gr = (double *)malloc(sizeof(double) * nv * D * n);
+        double *gl = (double *)malloc(sizeof(double) * nv * D * n);
+        oracle_gradients(M, W, gr, gl, NULL);
+        for (int64_t i = 0; i < n; i++)
+            if (act[i])
+                for (int c = 0; c < nv * D; c++) G[c * n + i] = gl[c * n + i];
+        free(gr);
+        free(gl);
+    }
+    /* 4 */
+    {
+        double *wf = (double *)malloc(sizeof(double) * D * nf);
+        oracle_face_velocity(M, wf);
+        int64_t na = 0;
+        for (int64_t f = 0; f < nf; f++) {
+            const int64_t cell[2] = {M->face_L[f], M->face_R[f]};
+            const int b = bin[cell[0]] < bin[cell[1]] ? bin[cell[0]] : bin[cell[1]];
+            if (face_dt) face_dt[f] = 0.0;
+            if (pred) { pred[f] = 0.0; pred[nf + f] = 0.0; }
+            if ((ti & ((INT64_C(1) << b) - 1)) != 0) continue;
+            const double fdt = ldexp(dt_max, b - L);
+            double pdt[2];
+            for (int s = 0; s < 2; s++) pdt[s] = 2.0 * ((double)(ti - trec[cell[s]]) * tick + 0.5 * fdt);
+            double F[5];
+            face_flux_one(M, prm, wf, f, pdt, fdt, NULL, W, G, F, NULL, NULL, NULL);
+            for (int c = 0; c < nv; c++) {
+                Q[c * n + cell[0]] -= F[c];
+                Q[c * n + cell[1]] += F[c];
+            }
+            if (face_dt) face_dt[f] = fdt;
+            if (pred) { pred[f] = 0.5 * pdt[0]; pred[nf + f] = 0.5 * pdt[1]; }
+            na++;
+        }
+        if (n_active_faces) *n_active_faces = na;
+        free(wf);
+    }
+    /* 5 */
+    {
+        int b0 = L;
+        for (int64_t i = 0; i < n; i++)
+            if (bin[i] < b0) b0 = bin[i];
+        if (next_ti) *next_ti = ((ti >> b0) + 1) << b0;
+    }
+done:
+    free(act);
+    free(Wn);
+    free(dti);
+    return status;
 }

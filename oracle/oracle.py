@@ -75,6 +75,12 @@ def _lib():
                                                _dp, ctypes.c_int32, ctypes.c_double, _dp, _ip]
         lib.oracle_shock_mach.restype = ctypes.c_double
         lib.oracle_shock_mach.argtypes = [ctypes.c_double, _dp, _dp]
+        lib.oracle_tb_criterion.argtypes = [ctypes.POINTER(_OMesh), ctypes.POINTER(_OParams), _dp, _dp]
+        lib.oracle_tb_step.restype = ctypes.c_int
+        lib.oracle_tb_step.argtypes = [ctypes.POINTER(_OMesh), ctypes.POINTER(_OParams), ctypes.c_double,
+                                       ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, _dp, _dp,
+                                       _dp, _dp, _dp, _ip, ctypes.POINTER(ctypes.c_int64),
+                                       ctypes.POINTER(ctypes.c_int64)]
         _LIB = lib
     return _LIB
 
@@ -285,3 +291,62 @@ def hydro_step(mesh, gamma, cfl, Q, dt=0.0):
     p = _OParams(float(gamma), float(cfl))
     used = _lib().oracle_hydro_step(ctypes.byref(h.s), ctypes.byref(p), float(dt), _d(Q))
     return Q, used
+
+
+def tb_criterion(mesh, gamma, cfl, W):
+    """Per-cell individual timestep bound [N] (Section 7.2,
+    eq. EqnTiStepIndividual over the Voronoi neighbours)."""
+    h = _Held(mesh)
+    out = np.empty(h.n)
+    p = _OParams(float(gamma), float(cfl))
+    _lib().oracle_tb_criterion(ctypes.byref(h.s), ctypes.byref(p), _d(_f64(W)), _d(out))
+    return out
+
+
+class Timeline:
+    """Individual power-of-two timesteps (Section 7.2) on a fixed mesh:
+    ticks of dt_max / 2^levels, per-cell bins, record times and stored
+    primitive and gradient records, advanced one synchronisation point per
+    call of ``step`` (see ``oracle_tb_step``)."""
+
+    def __init__(self, mesh, gamma, cfl, dt_max, levels):
+        self.h = _Held(mesh)
+        self.p = _OParams(float(gamma), float(cfl))
+        self.dt_max = float(dt_max)
+        self.levels = int(levels)
+        n, D = self.h.n, self.h.dim
+        self.bin = np.full(n, self.levels, dtype=np.int8)
+        self.trec = np.zeros(n, dtype=np.int64)
+        self.W = np.zeros((D + 2, n))
+        self.G = np.zeros(((D + 2) * D, n))
+        self.ti = 0
+
+    @property
+    def tick(self):
+        return np.ldexp(self.dt_max, -self.levels)
+
+    @property
+    def time(self):
+        return self.ti * self.tick
+
+    def step(self, Q):
+        """One synchronisation point on Q ([D+2][N], updated in place).
+        Returns a dict: status (0, or 1 when a criterion is below one tick),
+        ti (the tick of this point), next (the next point), active [N],
+        face_dt [F], pred [2][F] (each side's prediction interval),
+        n_faces (active faces)."""
+        assert Q.dtype == np.float64 and Q.flags.c_contiguous
+        h = self.h
+        face_dt = np.empty(h.nf)
+        pred = np.empty((2, h.nf))
+        active = np.empty(h.n, dtype=np.int32)
+        nxt = ctypes.c_int64(0)
+        na = ctypes.c_int64(0)
+        ti = self.ti
+        st = _lib().oracle_tb_step(ctypes.byref(h.s), ctypes.byref(self.p), self.dt_max, self.levels, ti,
+                                   self.bin.ctypes.data, self.trec.ctypes.data, _d(self.W), _d(self.G), _d(Q),
+                                   _d(face_dt), _d(pred), _i(active), ctypes.byref(nxt), ctypes.byref(na))
+        if st == 0:
+            self.ti = nxt.value
+        return dict(status=st, ti=ti, next=nxt.value if st == 0 else ti, active=active.astype(bool),
+                    face_dt=face_dt, pred=pred, n_faces=na.value)

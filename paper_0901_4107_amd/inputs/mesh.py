@@ -92,6 +92,19 @@ def build_mesh(points: np.ndarray, nthreads: int = 0) -> Mesh:
              mesh_vel=np.zeros((dim, n)), n_bad=int(counts[1]), n_asym=int(counts[2]))
     if m.n_bad:
         raise RuntimeError(f"{m.n_bad} Voronoi cells did not close; too few points for the box")
+    if m.n_asym:
+        # A face seen from one side only leaves a cell open unless it is of
+        # round-off size: every cell's sum of A n must vanish.
+        nrm = sep / np.sqrt(np.sum(sep * sep, axis=0))
+        acc = np.zeros((dim, n))
+        for k in range(dim):
+            np.add.at(acc[k], L, area * nrm[k])
+            np.add.at(acc[k], R, -area * nrm[k])
+        scale = vol ** ((dim - 1.0) / dim)
+        worst = float(np.max(np.sqrt(np.sum(acc * acc, axis=0)) / scale))
+        if worst > 1e-9:
+            raise RuntimeError(f"{m.n_asym} faces seen from one side only leave cells open "
+                               f"(largest |sum A n| {worst:.1e} of the cell's face scale)")
     return m
 
 
