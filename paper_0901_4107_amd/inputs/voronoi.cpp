@@ -222,8 +222,11 @@ static void build_cell3(const Grid &G, int64_t i, Poly3 &A, Poly3 &B, std::vecto
         bool done = false;
         while (idx < cands.size()) {
             const Cand &c = cands[idx];
-            if (c.dist2 > 4.0 * r2max) { done = true; break; }
+            // only a candidate inside the gathered radius is known to be the
+            // nearest unexamined point; beyond it the next ring may hold
+            // nearer ones
             if (c.dist2 >= covered * covered) break;
+            if (c.dist2 > 4.0 * r2max) { done = true; break; }
             double eps = 1e-12 * std::sqrt(r2max);
             clip3(*P, *Q, c.j, c.d, eps, cut, sv);
             std::swap(P, Q);
@@ -339,8 +342,8 @@ static void build_cell2(const Grid &G, int64_t i, std::vector<Cand> &cands, Cell
         bool done = false;
         while (idx < cands.size()) {
             const Cand &c = cands[idx];
+            if (c.dist2 >= covered * covered) break;   // as in 3D
             if (c.dist2 > 4.0 * r2max) { done = true; break; }
-            if (c.dist2 >= covered * covered) break;
             clip2(P, Q, c.j, c.d, 1e-12 * std::sqrt(r2max));
             std::swap(P, Q);
             r2max = r2();
