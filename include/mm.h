@@ -55,6 +55,8 @@ typedef int32_t mm_status;
 #define MM_E_STATE      -4  /* call out of order: no workspace or no mesh */
 #define MM_E_WORKSPACE  -5  /* workspace smaller than mm_workspace_bytes */
 #define MM_E_NONFINITE  -6  /* a conserved quantity became NaN or infinite */
+#define MM_E_RANGE      -7  /* a cell's timestep criterion is below the smallest
+                               step of an individual-timestep timeline */
 
 /* Arithmetic of the face-flux path. */
 #define MM_FP64   0  /* every step in double precision */
@@ -76,6 +78,13 @@ typedef int32_t mm_status;
 #define MM_ENTROPY_OFF  0
 #define MM_ENTROPY_MACH 1
 
+/* Timestep scheme (Section 7.2). MM_STEPS_INDIVIDUAL adds the arrays of a
+ * power-of-two timeline to the workspace (mm_tb_begin, mm_tb_step); the
+ * global step (mm_hydro_step) stays available. Not combined with the
+ * entropy row. */
+#define MM_STEPS_GLOBAL     0
+#define MM_STEPS_INDIVIDUAL 1
+
 /* Starting guess of the Newton iteration for the star pressure. */
 #define MM_GUESS_STANDARD 0  /* adaptive PVRS / two-rarefaction / two-shock */
 #define MM_GUESS_LEARNED  1  /* MLP loaded with mm_mlp_load */
@@ -91,7 +100,7 @@ typedef struct {
     double newton_tol32;      /* same for the single-precision solve; <= 0: 1e-5 */
     void *stream;             /* hipStream_t */
     int32_t entropy;          /* MM_ENTROPY_OFF or MM_ENTROPY_MACH */
-    int32_t reserved;
+    int32_t steps;            /* MM_STEPS_GLOBAL or MM_STEPS_INDIVIDUAL */
     double mach_thresh;       /* MM_ENTROPY_MACH: cells whose largest face shock Mach
                                  number is below this keep their entropy (the paper
                                  suggests about 1.1); <= 0 never keeps; not NaN */
@@ -144,7 +153,8 @@ typedef struct {
 typedef struct mm_ctx mm_ctx;
 
 /* Create a context for the given parameters. Allocates host memory only.
- * MM_E_ARG for a bad dimension, mode, guess or gamma <= 1. */
+ * MM_E_ARG for a bad dimension, mode, guess, entropy or steps value,
+ * gamma <= 1, or individual timesteps with the entropy row. */
 mm_status mm_create(const mm_params *params, mm_ctx **out);
 
 /* Destroy a context (NULL is accepted). Does not free the workspace. */
@@ -313,6 +323,67 @@ mm_status mm_face_states(mm_ctx *ctx, double dt, const void *recon, float *out);
 /* Diagnostics accumulated since the last reset; synchronises. */
 mm_status mm_get_diag(mm_ctx *ctx, mm_diag *out);
 mm_status mm_reset_diag(mm_ctx *ctx);
+
+/* ------------------------------------------------------------------------
+ * Individual power-of-two timesteps (Section 7.2), contexts created with
+ * steps = MM_STEPS_INDIVIDUAL, on the uploaded tessellation.
+ *
+ * Time runs in ticks of dt_max / 2^levels. Each cell sits in a bin b
+ * (0 <= b <= levels) and takes steps of 2^b ticks that start at multiples
+ * of 2^b. mm_tb_step performs one synchronisation point at the current
+ * tick ti:
+ *  - the cells whose step ends at ti recompute their primitive variables
+ *    and gradients from Q (the others keep the records of their last
+ *    active step) and choose a new bin: the largest b with
+ *    dt_max 2^(b - levels) <= dt_i, where
+ *      dt_i = cfl min(tau_i, R_i / (c_i + |v_i - w_i|)),
+ *      tau_i = min over the face neighbours j of
+ *              r_ij / (c_i + c_j - (v_i - v_j).(r_i - r_j)/r_ij)
+ *    (eq. EqnTiStepIndividual with the minimum over the Voronoi neighbours;
+ *    pairs whose signal speed is not positive set no bound). A cell may
+ *    move down any number of bins but up by one only, and only when the
+ *    higher bin starts a step at ti;
+ *  - every face whose smaller step (the smaller bin of its two cells)
+ *    starts at ti is integrated over that step: each side is predicted
+ *    from its cell's record to the middle of the face's step and both
+ *    cells exchange the time-integrated flux (conservative);
+ *  - the timeline advances to the next tick at which a step ends (the
+ *    next multiple of the smallest occupied bin's step).
+ * A global step on a context (mm_hydro_step, mm_gradients), a mesh upload
+ * or new generator velocities end the timeline (the cell records are
+ * shared); mm_tb_step then returns MM_E_STATE until the next mm_tb_begin.
+ * The tessellation stays fixed along the timeline; with moving generators
+ * the caller rebuilds and re-uploads the mesh and begins a new timeline.
+ * Static gravity is not combined with it (MM_E_STATE).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int64_t tick;          /* the point just performed (ticks) */
+    int64_t next_tick;     /* the next point */
+    int64_t active_cells;  /* cells whose step started at tick */
+    int64_t active_faces;  /* faces integrated at tick */
+    int32_t min_bin;       /* occupied bins after the point */
+    int32_t max_bin;
+    double next_time;      /* next_tick dt_max / 2^levels */
+} mm_tb_info;
+
+/* Start a timeline at tick 0 with every cell due (all cells take their
+ * bins from the criterion at the first point). 0 <= levels <= 30,
+ * dt_max > 0 and finite (MM_E_ARG otherwise); MM_E_STATE without a mesh
+ * or on a context not created with MM_STEPS_INDIVIDUAL. */
+mm_status mm_tb_begin(mm_ctx *ctx, double dt_max, int32_t levels);
+
+/* One synchronisation point on Q ([D+2][N] device, updated in place);
+ * info (host, may be NULL) receives the point's summary. Synchronises the
+ * stream. MM_E_RANGE when an active cell's criterion is below one tick:
+ * then Q is untouched, but the timeline has ended (bins and records of the
+ * point's active cells have changed; begin a new one). MM_E_NONFINITE when
+ * the point left a non-finite conserved value (the timeline advances). */
+mm_status mm_tb_step(mm_ctx *ctx, double *Q, mm_tb_info *info);
+
+/* Device copies of the timeline's per-cell bins [N] and the ticks at which
+ * their current steps started [N] (either pointer may be NULL). Stream-
+ * ordered, no synchronisation. MM_E_STATE without a timeline. */
+mm_status mm_tb_state(mm_ctx *ctx, int8_t *bins, int64_t *trec);
 
 /* Human-readable name of a status code. */
 const char *mm_status_str(mm_status s);

@@ -64,49 +64,68 @@ __device__ __forceinline__ double block_min(double v) {
     return v;
 }
 
-// Step (ii) and the timestep bound of step (v) (Section 7.1):
-//   rho = m/V, v = p/m, P = (g-1)(E - m v^2/2)/V,
-//   dt_i = C R_i / (c_i + |v_i - w_i|), R_i the radius of the cell's volume.
-// Cells with m <= 0 are vacuum (W = 0) and impose no timestep limit.
-// Writes the primitive record (W and s_i - r_i, whole); in the mixed mode
-// (T = float) the velocity stored is v_i - w_i. As the first kernel of a
-// step it clears the step's non-finite flag (step_flag, may be null).
+// Step (ii) for one cell (Section 3, state vector and equation of state):
+//   rho = m/V, v = p/m, P = (g-1)(E - m v^2/2)/V.
+// Fills the primitive record (W and s_i - r_i, whole); in the mixed mode
+// (T = float) the velocity stored is v_i - w_i. Returns the cell's sound
+// speed (0 unless rho > 0 and P > 0) and sets v (lab frame), |v - w|^2, the
+// radius R of the cell's volume and ok = (rho > 0 and P > 0). Cells with
+// m <= 0 are vacuum: W = 0, v = 0.
+template <int D, typename T>
+__device__ __forceinline__ double cell_prim(int64_t i, int64_t n, double gamma, const double *__restrict__ V,
+                                            const double *__restrict__ Q, const double *__restrict__ mvel,
+                                            const double *__restrict__ coff, T (&r)[Lay<D>::PREC], double (&v)[D],
+                                            double &rel2, double &R, bool &ok) {
+    using Y = Lay<D>;
+    constexpr int NV = D + 2;
+    constexpr bool rel = sizeof(T) == 4;
+    for (int k = 0; k < Y::PREC; k++) r[k] = (T)0;
+    for (int k = 0; k < D; k++) { r[Y::DL + k] = (T)coff[k * n + i]; v[k] = 0.0; }
+    rel2 = 0.0;
+    R = 0.0;
+    ok = false;
+    const double m = Q[i];
+    if (!(m > 0.0)) return 0.0;
+    const double vol = V[i];
+    const double inv_m = 1.0 / m;
+    double ke = 0.0;
+    for (int k = 0; k < D; k++) {
+        v[k] = Q[(1 + k) * n + i] * inv_m;
+        ke += v[k] * v[k];
+        const double dv = v[k] - mvel[k * n + i];
+        rel2 += dv * dv;
+        r[Y::W + 1 + k] = rel ? (T)dv : (T)v[k];
+    }
+    const double rho = m / vol;
+    const double P = (gamma - 1.0) * (Q[(NV - 1) * n + i] - 0.5 * m * ke) / vol;
+    r[Y::W] = (T)rho;
+    r[Y::W + NV - 1] = (T)P;
+    ok = rho > 0.0 && P > 0.0;
+    if (!ok) return 0.0;
+    R = (D == 3) ? cbrt(vol * (3.0 / (4.0 * M_PI))) : sqrt(vol * (1.0 / M_PI));
+    return sqrt(gamma * P / rho);
+}
+
+// Step (ii) and the timestep bound of step (v) (Section 7.1): the primitive
+// record of every cell (cell_prim) and the per-block minimum of
+//   dt_i = C R_i / (c_i + |v_i - w_i|), R_i the radius of the cell's volume;
+// vacuum cells impose no limit. As the first kernel of a step it clears the
+// step's non-finite flag (step_flag, may be null).
 template <int D, typename T>
 __global__ void __launch_bounds__(kBlock) k_prim_cfl(int64_t n, double gamma, double cfl, const double *__restrict__ V,
                                                      const double *__restrict__ Q, const double *__restrict__ mvel,
                                                      const double *__restrict__ coff, T *__restrict__ prim,
                                                      double *__restrict__ dt_part, int32_t *step_flag) {
     using Y = Lay<D>;
-    constexpr int NV = D + 2;
-    constexpr bool rel = sizeof(T) == 4;
     const int64_t i = xcd_global_id();
     if (step_flag && blockIdx.x == 0 && threadIdx.x == 0) *step_flag = 0;
     double dti = INFINITY;
     if (i < n) {
         T r[Y::PREC];
-        for (int k = 0; k < Y::PREC; k++) r[k] = (T)0;
-        const double m = Q[i];
-        for (int k = 0; k < D; k++) r[Y::DL + k] = (T)coff[k * n + i];
-        if (m > 0.0) {
-            const double vol = V[i];
-            const double inv_m = 1.0 / m;
-            double v[D], ke = 0.0, rel2 = 0.0;
-            for (int k = 0; k < D; k++) {
-                v[k] = Q[(1 + k) * n + i] * inv_m;
-                ke += v[k] * v[k];
-                const double dv = v[k] - mvel[k * n + i];
-                rel2 += dv * dv;
-                r[Y::W + 1 + k] = rel ? (T)dv : (T)v[k];
-            }
-            const double rho = m / vol;
-            const double P = (gamma - 1.0) * (Q[(NV - 1) * n + i] - 0.5 * m * ke) / vol;
-            r[Y::W] = (T)rho;
-            r[Y::W + NV - 1] = (T)P;
-            if (rho > 0.0 && P > 0.0) {
-                const double R = (D == 3) ? cbrt(vol * (3.0 / (4.0 * M_PI))) : sqrt(vol * (1.0 / M_PI));
-                dti = cfl * R / (sqrt(gamma * P / rho) + sqrt(rel2));
-            }
-        }
+        double v[D], rel2, R;
+        bool ok;
+        const double c = cell_prim<D, T>(i, n, gamma, V, Q, mvel, coff, r, v, rel2, R, ok);
+        if (ok) dti = cfl * R / (c + sqrt(rel2));
         store_rec<Y::PREC>(prim + i * Y::PREC, r);
     }
     dti = block_min(dti);
@@ -183,15 +202,13 @@ __device__ __forceinline__ void limit_side(const T *g, const T *dl, const T (&gr
     }
 }
 
-// The gather-bound gradient kernel gains from one more wavefront per SIMD
-// than the register count the compiler picks on its own (5 float / 4 double,
-// without spills, about 7-9% faster).
+// The gradient and limiter of cell i by its lane group (lane = index in
+// the group); every lane of the group calls it with the same i.
 template <int D, typename T>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 4)))
-k_grad_limit(int64_t n, const int32_t *__restrict__ off,
-                                                       const int32_t *__restrict__ nbr, const T *__restrict__ srec,
-                                                       const double *__restrict__ V, const T *__restrict__ prim,
-                                                       T *__restrict__ grad_out) {
+__device__ __forceinline__ void grad_cell(int64_t i, int lane, const int32_t *__restrict__ off,
+                                          const int32_t *__restrict__ nbr, const T *__restrict__ srec,
+                                          const double *__restrict__ V, const T *__restrict__ prim,
+                                          T *__restrict__ grad_out) {
     using Y = Lay<D>;
     constexpr int NV = D + 2;
     constexpr int GS = Group<D>::GS;
@@ -199,9 +216,6 @@ k_grad_limit(int64_t n, const int32_t *__restrict__ off,
     constexpr int KR = mixed ? 5 : 3;   // sides per lane held in registers
     constexpr int SR = mixed ? Y::SREC32 : Y::SREC64;
     const T eps_t = mixed ? (T)1e-6 : (T)1e-13;
-    const int lane = threadIdx.x % GS;
-    const int64_t i = xcd_tile() * (kBlock / GS) + threadIdx.x / GS;
-    if (i >= n) return;  // whole groups leave together
     const int32_t b = off[i], e = off[i + 1];
     // the lane's first KR sides: side records and neighbour indices, then
     // the neighbours' primitive records, all in flight together (an absent
@@ -270,6 +284,35 @@ k_grad_limit(int64_t n, const int32_t *__restrict__ off,
             for (int k = 0; k < D; k++) go[c * D + k] = alpha[c] * grad[c][k];
         store_rec<Y::GREC>(grad_out + i * Y::GREC, go);
     }
+}
+
+// The gather-bound gradient kernels gain from one more wavefront per SIMD
+// than the register count the compiler picks on its own (5 float / 4 double,
+// about 7-9% faster; the 3D double kernel spills a few bytes per lane).
+template <int D, typename T>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 4)))
+k_grad_limit(int64_t n, const int32_t *__restrict__ off, const int32_t *__restrict__ nbr, const T *__restrict__ srec,
+             const double *__restrict__ V, const T *__restrict__ prim, T *__restrict__ grad_out) {
+    constexpr int GS = Group<D>::GS;
+    const int64_t i = xcd_tile() * (kBlock / GS) + threadIdx.x / GS;
+    if (i >= n) return;  // whole groups leave together
+    grad_cell<D, T>(i, threadIdx.x % GS, off, nbr, srec, V, prim, grad_out);
+}
+
+// The same for the cells of a split list (the active cells of an
+// individual-timestep point): each lane group walks its block's sub-list.
+template <int D, typename T>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 3)))
+k_grad_limit_list(const int32_t *__restrict__ list, int64_t cap, const int32_t *__restrict__ off,
+                  const int32_t *__restrict__ nbr, const T *__restrict__ srec, const double *__restrict__ V,
+                  const T *__restrict__ prim, T *__restrict__ grad_out) {
+    constexpr int GS = Group<D>::GS, G = kBlock / GS;
+    const int c = blockIdx.x % kLists;
+    const int32_t *items = list + (int64_t)kLists * kListPad + c * cap;
+    const int64_t count = list[c * kListPad];
+    const int64_t stride = (int64_t)(gridDim.x / kLists) * G;
+    for (int64_t q = (int64_t)(blockIdx.x / kLists) * G + threadIdx.x / GS; q < count; q += stride)
+        grad_cell<D, T>(items[q], threadIdx.x % GS, off, nbr, srec, V, prim, grad_out);
 }
 
 // Step (vii): Q_i <- Q_i - sum of the fluxes of faces where i is left

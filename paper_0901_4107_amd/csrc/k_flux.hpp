@@ -343,6 +343,27 @@ __device__ __forceinline__ void store_face(double *p, const double (&F)[NV], con
     store_rec<FS>(p, r);
 }
 
+// One point of the individual-timestep integration (Section 7.2) as the
+// face kernels see it: per-cell bins and record times (in ticks), the
+// point's tick ti, and dt_max = 2^levels ticks.
+struct TbView {
+    const int8_t *bin;
+    const int64_t *trec;
+    int64_t ti;
+    double dt_max;
+    int32_t levels;
+    // Face (l, r) is integrated over fdt = 2^min(bin_l, bin_r) ticks; each
+    // side is predicted from its record to the middle of that step,
+    // (ti - trec) ticks + fdt/2.
+    __device__ __forceinline__ void face(int64_t l, int64_t r, double &fdt, double &hl, double &hr) const {
+        const int bl = bin[l], br = bin[r];
+        fdt = ldexp(dt_max, (bl < br ? bl : br) - levels);
+        const double tick = ldexp(dt_max, -levels);
+        hl = (double)(ti - trec[l]) * tick + 0.5 * fdt;
+        hr = (double)(ti - trec[r]) * tick + 0.5 * fdt;
+    }
+};
+
 // Lab-frame moving-face flux in double from the sampled face-frame state
 // (rho_F, u_F, P_F), the upwind transverse velocity tv, the normal n and
 // the face velocity w, times scale (dt A).
@@ -366,18 +387,21 @@ __device__ __forceinline__ void lab_flux(double rho, double u, double P, const d
 }
 
 // Double-precision flux of face f (dt A Fhat into F), the body of the face
-// kernel. Every thread of the block calls it (the learned staging holds barriers);
-// active = false does no face. LEARNED compiles the fused network in; the
-// standard-guess instantiation carries none of its registers. ENT adds the
-// entropy flux and the shock Mach number (X). GRAV adds the half-step kick
-// (dt/2) g_K of a static field (Section 5.2; accel [D][n], g = -grad Phi)
-// to each side's predicted velocity; a face that falls back to its
-// unextrapolated states takes none.
+// kernel. The left and right states are predicted over hdtL and hdtR (dt/2
+// each in a global step; with individual timesteps each side's record age
+// plus half the face's step). Every thread of the block calls it (the
+// learned staging holds barriers); active = false does no face. LEARNED
+// compiles the fused network in; the standard-guess instantiation carries
+// none of its registers. ENT adds the entropy flux and the shock Mach
+// number (X). GRAV adds the half-step kick hdt g_K of a static field
+// (Section 5.2; accel [D][n], g = -grad Phi) to each side's predicted
+// velocity; a face that falls back to its unextrapolated states takes none.
 template <int D, bool LEARNED, bool ENT, bool GRAV>
 __device__ __forceinline__ void face_flux64(bool active, int64_t f, const int32_t *__restrict__ fL,
                                             const int32_t *__restrict__ fR, const double *__restrict__ frec,
                                             const double *__restrict__ prim, const double *__restrict__ grad,
-                                            double dt, const GasConst<double> &kg, double tol, int maxit,
+                                            double dt, double hdtL, double hdtR, const GasConst<double> &kg,
+                                            double tol, int maxit,
                                             const MlpPacked *mlp, const double *__restrict__ accel, int64_t n,
                                             LaneDiag &ld, double (&F)[D + 2], double (&X)[2]) {
     using Y = Lay<D>;
@@ -385,7 +409,6 @@ __device__ __forceinline__ void face_flux64(bool active, int64_t f, const int32_
     double A = 0.0, nrm[D], w[D], xl[NV], xr[NV], uL = 0.0, uR = 0.0;
     for (int c = 0; c < NV; c++) { xl[c] = 1.0; xr[c] = 1.0; }
     if (active) {
-        const double hdt = 0.5 * dt;
         double fr[Y::FREC];
         load_rec<Y::FREC>(frec + f * Y::FREC, fr);
         const CellRec<D, double> rl = load_cell<D>(prim, grad, fL[f]);
@@ -402,14 +425,14 @@ __device__ __forceinline__ void face_flux64(bool active, int64_t f, const int32_
         }
         double cl[NV], cr[NV], vf[D];
         for (int k = 0; k < D; k++) vf[k] = rl.p[Y::W + 1 + k] - w[k];
-        half_step<D, double>(rl, vf, gL, kg.g, hdt, xl, cl);
+        half_step<D, double>(rl, vf, gL, kg.g, hdtL, xl, cl);
         for (int k = 0; k < D; k++) vf[k] = rr.p[Y::W + 1 + k] - w[k];
-        half_step<D, double>(rr, vf, gR, kg.g, hdt, xr, cr);
+        half_step<D, double>(rr, vf, gR, kg.g, hdtR, xr, cr);
         if constexpr (GRAV) {
             const int64_t l = fL[f], r = fR[f];
             for (int k = 0; k < D; k++) {
-                xl[1 + k] += hdt * accel[k * n + l];
-                xr[1 + k] += hdt * accel[k * n + r];
+                xl[1 + k] += hdtL * accel[k * n + l];
+                xr[1 + k] += hdtR * accel[k * n + r];
             }
         }
         if (!(xl[0] > 0.0 && xl[NV - 1] > 0.0 && xr[0] > 0.0 && xr[NV - 1] > 0.0)) {
@@ -460,8 +483,8 @@ __global__ void __launch_bounds__(kBlock) k_face_flux64(int64_t nf, const int32_
     LaneDiag ld;
     const double dt = dt_ptr ? *dt_ptr : dt_val;
     double F[NV], X[2];
-    face_flux64<D, LEARNED, ENT, GRAV>(active, f, fL, fR, frec, prim, grad, dt, kg, tol, maxit, mlp, accel, n, ld,
-                                       F, X);
+    face_flux64<D, LEARNED, ENT, GRAV>(active, f, fL, fR, frec, prim, grad, dt, 0.5 * dt, 0.5 * dt, kg, tol, maxit,
+                                       mlp, accel, n, ld, F, X);
     if (active) store_face<NV, FS>(flux + f * FS, F, X);
     if (diag) flush_diag(ld, diag);
 }
@@ -481,8 +504,8 @@ __device__ __forceinline__ MixedFace<D> mixed_face_states(int64_t f, const int32
                                                           const int32_t *__restrict__ fR,
                                                           const float *__restrict__ mrec,
                                                           const float *__restrict__ prim,
-                                                          const float *__restrict__ grad, float hdt, float gam,
-                                                          const double *__restrict__ accel, int64_t n) {
+                                                          const float *__restrict__ grad, float hdtL, float hdtR,
+                                                          float gam, const double *__restrict__ accel, int64_t n) {
     using Y = Lay<D>;
     constexpr int NV = D + 2;
     MixedFace<D> o;
@@ -504,14 +527,14 @@ __device__ __forceinline__ MixedFace<D> mixed_face_states(int64_t f, const int32
     // w_L - w_f = dw/2 - (dw.c/|d|) n and w_R - w_f = -dw/2 - (dw.c/|d|) n
     proj *= 0.5f / hl;
     for (int k = 0; k < D; k++) vf[k] = rl.p[Y::W + 1 + k] + (0.5f * dw[k] - proj * o.nrm[k]);
-    half_step<D, float>(rl, vf, gL, gam, hdt, o.xl, cl);
+    half_step<D, float>(rl, vf, gL, gam, hdtL, o.xl, cl);
     for (int k = 0; k < D; k++) vf[k] = rr.p[Y::W + 1 + k] + (-0.5f * dw[k] - proj * o.nrm[k]);
-    half_step<D, float>(rr, vf, gR, gam, hdt, o.xr, cr);
+    half_step<D, float>(rr, vf, gR, gam, hdtR, o.xr, cr);
     if constexpr (GRAV) {   // the half-step kick of a static field (Section 5.2)
         const int64_t l = fL[f], r = fR[f];
         for (int k = 0; k < D; k++) {
-            o.xl[1 + k] += hdt * (float)accel[k * n + l];
-            o.xr[1 + k] += hdt * (float)accel[k * n + r];
+            o.xl[1 + k] += hdtL * (float)accel[k * n + l];
+            o.xr[1 + k] += hdtR * (float)accel[k * n + r];
         }
     }
     o.posfb = !(o.xl[0] > 0.0f && o.xl[NV - 1] > 0.0f && o.xr[0] > 0.0f && o.xr[NV - 1] > 0.0f);
@@ -552,15 +575,16 @@ template <int D, bool LEARNED, bool ENT, bool GRAV>
 __device__ __forceinline__ void face_flux_mixed(bool active, int64_t f, const int32_t *__restrict__ fL,
                                                 const int32_t *__restrict__ fR, const float *__restrict__ mrec,
                                                 const double *__restrict__ wf64, const float *__restrict__ prim,
-                                                const float *__restrict__ grad, double dt, const GasConst<float> &kf,
-                                                double g_over_gm1, float tol32, int maxit, const MlpPacked *mlp,
+                                                const float *__restrict__ grad, double dt, double hdtL, double hdtR,
+                                                const GasConst<float> &kf, double g_over_gm1, float tol32, int maxit,
+                                                const MlpPacked *mlp,
                                                 const double *__restrict__ accel, int64_t n,
                                                 LaneDiag &ld, bool &hard, double (&F)[D + 2], double (&X)[2]) {
     constexpr int NV = D + 2;
     hard = false;
     MixedFace<D> m;
     if (active) {
-        m = mixed_face_states<D, GRAV>(f, fL, fR, mrec, prim, grad, (float)(0.5 * dt), kf.g, accel, n);
+        m = mixed_face_states<D, GRAV>(f, fL, fR, mrec, prim, grad, (float)hdtL, (float)hdtR, kf.g, accel, n);
         ld.posfb += m.posfb ? 1 : 0;
     } else {
         for (int c = 0; c < NV; c++) { m.xl[c] = 1.0f; m.xr[c] = 1.0f; }
@@ -632,8 +656,8 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))
     bool hard;
     const double dt = dt_ptr ? *dt_ptr : dt_val;
     double F[NV], X[2];
-    face_flux_mixed<D, LEARNED, ENT, GRAV>(active, f, fL, fR, mrec, wf64, prim, grad, dt, kf, g_over_gm1, tol32,
-                                           maxit, mlp, accel, n, ld, hard, F, X);
+    face_flux_mixed<D, LEARNED, ENT, GRAV>(active, f, fL, fR, mrec, wf64, prim, grad, dt, 0.5 * dt, 0.5 * dt, kf,
+                                           g_over_gm1, tol32, maxit, mlp, accel, n, ld, hard, F, X);
     if (active && !hard) store_face<NV, FS>(flux + f * FS, F, X);
     list_append(hard_list, cap, hard, (int32_t)f);
     if (diag) flush_diag(ld, diag);
@@ -642,7 +666,8 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))
 // Double re-solve of the hard faces listed by k_face_flux_mixed (a split
 // list of sub-list capacity cap). A fixed grid walks the list, so the
 // launch needs no host-side count; the float face states are recomputed by
-// the same code, hence identical.
+// the same code, hence identical. With tb.bin set (individual timesteps)
+// each face takes its step and prediction intervals from the timeline.
 template <int D, bool ENT, bool GRAV>
 __global__ void __launch_bounds__(kBlock) k_face_flux_hard(const int32_t *__restrict__ fL,
                                                            const int32_t *__restrict__ fR,
@@ -654,15 +679,17 @@ __global__ void __launch_bounds__(kBlock) k_face_flux_hard(const int32_t *__rest
                                                            float gam, GasConst<double> kg, double tol64,
                                                            const int32_t *__restrict__ hard_list, int64_t cap,
                                                            double *__restrict__ flux, DiagDev *diag,
-                                                           const double *__restrict__ accel, int64_t n) {
+                                                           const double *__restrict__ accel, int64_t n, TbView tb) {
     constexpr int NV = D + 2;
     constexpr int FS = NV + (ENT ? 2 : 0);
     const ListWalk lw = list_walk(hard_list, cap);
-    const double dt = dt_ptr ? *dt_ptr : dt_val;
     LaneDiag ld;
     for (int64_t q = lw.start; q < lw.count; q += lw.stride) {
         const int64_t f = lw.items[q];
-        const MixedFace<D> m = mixed_face_states<D, GRAV>(f, fL, fR, mrec, prim, grad, (float)(0.5 * dt), gam, accel, n);
+        double dt = dt_ptr ? *dt_ptr : dt_val, hl = 0.5 * dt, hr = 0.5 * dt;
+        if (tb.bin) tb.face(fL[f], fR[f], dt, hl, hr);
+        const MixedFace<D> m =
+            mixed_face_states<D, GRAV>(f, fL, fR, mrec, prim, grad, (float)hl, (float)hr, gam, accel, n);
         bool h2;
         FaceState<double> fd = solve_face<double>(m.xl[0], m.uL, m.xl[NV - 1], m.xr[0], m.uR, m.xr[NV - 1], kg,
                                                   tol64, 50, no_guess<double>(), false, ld, h2);
@@ -677,6 +704,73 @@ __global__ void __launch_bounds__(kBlock) k_face_flux_hard(const int32_t *__rest
             X[1] = mach;
         }
         store_face<NV, FS>(flux + f * FS, F, X);
+    }
+    if (diag) flush_diag(ld, diag);
+}
+
+// Individual timesteps: the active faces of a point, listed in a split
+// list, each integrated over its own step (TbView). Each block walks its
+// sub-list in block-uniform rounds, since the learned staging holds
+// barriers. Double path.
+template <int D, bool LEARNED>
+__global__ void __launch_bounds__(kBlock) k_face_flux64_list(const int32_t *__restrict__ list, int64_t cap,
+                                                             const int32_t *__restrict__ fL,
+                                                             const int32_t *__restrict__ fR,
+                                                             const double *__restrict__ frec,
+                                                             const double *__restrict__ prim,
+                                                             const double *__restrict__ grad, TbView tb,
+                                                             GasConst<double> kg, double tol, int maxit,
+                                                             const MlpPacked *mlp, double *__restrict__ flux,
+                                                             DiagDev *diag) {
+    constexpr int NV = D + 2;
+    const int c = blockIdx.x % kLists;
+    const int32_t *items = list + (int64_t)kLists * kListPad + c * cap;
+    const int64_t count = list[c * kListPad];
+    const int64_t stride = (int64_t)(gridDim.x / kLists) * kBlock;
+    LaneDiag ld;
+    for (int64_t base = (int64_t)(blockIdx.x / kLists) * kBlock; base < count; base += stride) {
+        const int64_t q = base + threadIdx.x;
+        const bool active = q < count;
+        const int64_t f = active ? items[q] : 0;
+        double fdt = 0.0, hl = 0.0, hr = 0.0;
+        if (active) tb.face(fL[f], fR[f], fdt, hl, hr);
+        double F[NV], X[2];
+        face_flux64<D, LEARNED, false, false>(active, f, fL, fR, frec, prim, grad, fdt, hl, hr, kg, tol, maxit, mlp,
+                                              nullptr, 0, ld, F, X);
+        if (active) store_face<NV, NV>(flux + f * NV, F, X);
+    }
+    if (diag) flush_diag(ld, diag);
+}
+
+// The same on the mixed path: hard faces go to the split hard list (the
+// sub-list of the block's residue, which holds at most as many items as
+// the face sub-list the block walks) for k_face_flux_hard.
+template <int D, bool LEARNED>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5)))
+k_face_flux_mixed_list(const int32_t *__restrict__ list, int64_t cap, const int32_t *__restrict__ fL,
+                       const int32_t *__restrict__ fR, const float *__restrict__ mrec,
+                       const double *__restrict__ wf64, const float *__restrict__ prim,
+                       const float *__restrict__ grad, TbView tb, GasConst<float> kf, double g_over_gm1,
+                       float tol32, int maxit, const MlpPacked *mlp, double *__restrict__ flux,
+                       int32_t *__restrict__ hard_list, DiagDev *diag) {
+    constexpr int NV = D + 2;
+    const int c = blockIdx.x % kLists;
+    const int32_t *items = list + (int64_t)kLists * kListPad + c * cap;
+    const int64_t count = list[c * kListPad];
+    const int64_t stride = (int64_t)(gridDim.x / kLists) * kBlock;
+    LaneDiag ld;
+    for (int64_t base = (int64_t)(blockIdx.x / kLists) * kBlock; base < count; base += stride) {
+        const int64_t q = base + threadIdx.x;
+        const bool active = q < count;
+        const int64_t f = active ? items[q] : 0;
+        double fdt = 0.0, hl = 0.0, hr = 0.0;
+        if (active) tb.face(fL[f], fR[f], fdt, hl, hr);
+        bool hard;
+        double F[NV], X[2];
+        face_flux_mixed<D, LEARNED, false, false>(active, f, fL, fR, mrec, wf64, prim, grad, fdt, hl, hr, kf,
+                                                  g_over_gm1, tol32, maxit, mlp, nullptr, 0, ld, hard, F, X);
+        if (active && !hard) store_face<NV, NV>(flux + f * NV, F, X);
+        list_append(hard_list, cap, active && hard, (int32_t)f);
     }
     if (diag) flush_diag(ld, diag);
 }

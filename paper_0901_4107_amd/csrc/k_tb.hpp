@@ -1,0 +1,259 @@
+// k_tb.hpp -- individual power-of-two timesteps (Section 7.2): the kernels
+// of one synchronisation point besides the gradient and flux passes, which
+// run the shared bodies over lists (k_grad_limit_list, k_face_flux*_list).
+//
+// Time is counted in ticks of dt_max / 2^levels. A cell in bin b takes
+// steps of 2^b ticks that start at multiples of 2^b. At tick ti:
+//   k_tb_open    per cell     the cells whose step ends now become active:
+//                             primitive and signal records, trec = ti, and
+//                             a split list of them
+//   k_tb_bins    active list  neighbour signal-speed criterion and the bin
+//                             rules; occupancy counts per bin
+//   (gradients of the active cells)
+//   k_tb_faces   per face     a face is active when the smaller step of its
+//                             cells starts now: split list, and both cells
+//                             stamped as touched
+//   (fluxes of the active faces, each over its own step)
+//   k_tb_update  lane group   touched cells add the signed, time-integrated
+//                per cell     fluxes of their active faces
+//   k_tb_finish  one block    list sizes for the host
+#pragma once
+
+#include "common.hpp"
+#include "k_cell.hpp"
+#include "layout.hpp"
+
+namespace mm {
+
+constexpr int kTbMaxLevels = 30;
+// Slots of the point's small info block (int32).
+enum : int { TB_ERR = 0, TB_CELLS = 1, TB_FACES = 2, TB_COUNTS = 8, TB_INFO_INTS = 64 };
+
+__device__ __forceinline__ bool tb_starts(int64_t ti, int b) { return (ti & ((int64_t(1) << b) - 1)) == 0; }
+
+// A fresh timeline: every cell in the top bin with its step starting at
+// tick 0 (so every cell is active at the first point), no cell touched.
+__global__ void __launch_bounds__(kBlock) k_tb_init(int64_t n, int32_t levels, int8_t *__restrict__ bin,
+                                                    int64_t *__restrict__ trec, int32_t *__restrict__ touch,
+                                                    int32_t *__restrict__ info) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) {
+        bin[i] = (int8_t)levels;
+        trec[i] = 0;
+        touch[i] = -1;
+    }
+    if (i < TB_INFO_INTS) info[i] = (i == TB_COUNTS + levels) ? (int32_t)n : 0;
+}
+
+// Opens the step of every cell whose step ends at ti: its primitive record
+// (as in the global step), its signal record (c, lab velocity, and the local
+// bound R / (c + |v - w|), infinite for vacuum), trec = ti, and a place in
+// the split list of active cells.
+template <int D, typename T>
+__global__ void __launch_bounds__(kBlock) k_tb_open(int64_t n, int64_t ti, const int8_t *__restrict__ bin,
+                                                    int64_t *__restrict__ trec, double gamma,
+                                                    const double *__restrict__ V, const double *__restrict__ Q,
+                                                    const double *__restrict__ mvel, const double *__restrict__ coff,
+                                                    T *__restrict__ prim, double *__restrict__ sig,
+                                                    int32_t *__restrict__ list, int64_t cap) {
+    using Y = Lay<D>;
+    constexpr int SG = D + 2;
+    const int64_t i = xcd_global_id();
+    bool act = false;
+    if (i < n) {
+        act = tb_starts(ti, bin[i]);
+        if (act) {
+            T r[Y::PREC];
+            double v[D], rel2, R;
+            bool ok;
+            const double c = cell_prim<D, T>(i, n, gamma, V, Q, mvel, coff, r, v, rel2, R, ok);
+            store_rec<Y::PREC>(prim + i * Y::PREC, r);
+            double s[SG];
+            s[0] = c;
+            for (int k = 0; k < D; k++) s[1 + k] = v[k];
+            s[D + 1] = ok ? R / (c + sqrt(rel2)) : INFINITY;
+            store_rec<SG>(sig + i * SG, s);
+            trec[i] = ti;
+        }
+    }
+    list_append(list, cap, act, (int32_t)i);
+}
+
+// The criterion and bin of each active cell (eq. EqnTiStepIndividual over
+// the Voronoi neighbours):
+//   dt_i = C min(tau_i, R_i / (c_i + |v_i - w_i|)),
+//   tau_i = min over faces of |d| / v_sig, v_sig = c_L + c_R - (v_R - v_L).n
+// (a face with v_sig <= 0 sets no bound). The bin is the largest b <= levels
+// with dt_max 2^(b - levels) <= dt_i; the cell takes it if it is not above
+// its old bin, else moves up one bin where that bin starts a step at ti, else
+// keeps its bin. A criterion below one tick raises info[TB_ERR] and leaves the
+// bin. Occupancy changes are gathered per block in LDS and added to the
+// counts once per block and bin.
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_tb_bins(const int32_t *__restrict__ list, int64_t cap, int64_t ti,
+                                                    double dt_max, int32_t levels, double cfl,
+                                                    const int32_t *__restrict__ off, const int32_t *__restrict__ ent,
+                                                    const int32_t *__restrict__ nbr, const double *__restrict__ frec,
+                                                    const double *__restrict__ sig, int8_t *__restrict__ bin,
+                                                    int32_t *__restrict__ info) {
+    using Y = Lay<D>;
+    constexpr int SG = D + 2;
+    __shared__ int32_t delta[kTbMaxLevels + 2];
+    if (threadIdx.x < kTbMaxLevels + 2) delta[threadIdx.x] = 0;
+    __syncthreads();
+    const ListWalk lw = list_walk(list, cap);
+    const double tick = ldexp(dt_max, -levels);
+    for (int64_t q = lw.start; q < lw.count; q += lw.stride) {
+        const int64_t i = lw.items[q];
+        double si[SG];
+        load_rec<SG>(sig + i * SG, si);
+        double tau = INFINITY;
+        for (int32_t e = off[i]; e < off[i + 1]; e++) {
+            const int32_t en = ent[e];
+            const int64_t f = en >> 1, j = nbr[e];
+            const bool i_right = en & 1;
+            double sj[SG];
+            load_rec<SG>(sig + j * SG, sj);
+            const double *fr = frec + f * Y::FREC;
+            double du = 0.0;
+            for (int k = 0; k < D; k++) {
+                const double vR = i_right ? si[1 + k] : sj[1 + k], vL = i_right ? sj[1 + k] : si[1 + k];
+                du += (vR - vL) * fr[Y::FN + k];
+            }
+            const double vsig = (si[0] + sj[0]) - du;
+            if (vsig > 0.0) tau = fmin(tau, fr[Y::FELL] / vsig);
+        }
+        const double dti = cfl * fmin(tau, si[D + 1]);
+        if (!(dti >= tick)) {
+            atomicOr(info + TB_ERR, 1);
+            continue;
+        }
+        int b = levels;
+        while (b > 0 && ldexp(dt_max, b - levels) > dti) b--;
+        const int old = bin[i];
+        int nb = old;
+        if (b <= old) nb = b;
+        else if (tb_starts(ti, old + 1)) nb = old + 1;
+        if (nb != old) {
+            bin[i] = (int8_t)nb;
+            atomicAdd(&delta[old], -1);
+            atomicAdd(&delta[nb], 1);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x <= (unsigned)levels && delta[threadIdx.x] != 0)
+        atomicAdd(info + TB_COUNTS + threadIdx.x, delta[threadIdx.x]);
+}
+
+// Active faces: the smaller step of the two cells starts at ti (then one of
+// them is active). Lists them and stamps both cells as touched at this
+// point (stamp cur). Lists nothing once a criterion failed.
+__global__ void __launch_bounds__(kBlock) k_tb_faces(int64_t nf, const int32_t *__restrict__ fL,
+                                                     const int32_t *__restrict__ fR, const int8_t *__restrict__ bin,
+                                                     int64_t ti, const int32_t *__restrict__ info,
+                                                     int32_t *__restrict__ touch, int32_t cur,
+                                                     int32_t *__restrict__ list, int64_t cap) {
+    const int64_t f = xcd_global_id();
+    bool act = false;
+    if (f < nf && info[TB_ERR] == 0) {
+        const int32_t l = fL[f], r = fR[f];
+        const int bl = bin[l], br = bin[r];
+        act = tb_starts(ti, bl < br ? bl : br);
+        if (act) {
+            touch[l] = cur;
+            touch[r] = cur;
+        }
+    }
+    list_append(list, cap, act, (int32_t)f);
+}
+
+// The update of the touched cells: Q_i gains the signed time-integrated
+// fluxes of its active faces (the same lane-group sums, in the same order, as
+// the global update, inactive faces adding nothing). A non-finite result
+// raises flags[0] and flags[1] like the global update.
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_tb_update(int64_t n, const int32_t *__restrict__ off,
+                                                      const int32_t *__restrict__ ent,
+                                                      const int32_t *__restrict__ nbr, const int8_t *__restrict__ bin,
+                                                      int64_t ti, const int32_t *__restrict__ touch, int32_t cur,
+                                                      const double *__restrict__ flux, double *__restrict__ Q,
+                                                      int32_t *__restrict__ flags) {
+    constexpr int NV = D + 2;
+    constexpr int GS = Group<D>::GS;
+    constexpr int KR = 5;
+    const int lane = threadIdx.x % GS;
+    const int64_t i = xcd_tile() * (kBlock / GS) + threadIdx.x / GS;
+    if (i >= n || touch[i] != cur) return;   // whole groups leave together
+    const int bi = bin[i];
+    double acc[NV];
+    for (int c = 0; c < NV; c++) acc[c] = 0.0;
+    const int32_t b = off[i], e = off[i + 1];
+    double F[KR][NV], sg[KR];
+    for (int r = 0; r < KR; r++) {
+        const int32_t q = b + lane + r * GS;
+        bool live = q < e;
+        int32_t en = 0;
+        if (live) {
+            en = ent[q];
+            const int bj = bin[nbr[q]];
+            live = tb_starts(ti, bi < bj ? bi : bj);
+        }
+        sg[r] = live ? ((en & 1) ? 1.0 : -1.0) : 0.0;
+        load_rec<NV>(flux + (int64_t)(live ? (en >> 1) : 0) * NV, F[r]);
+    }
+    for (int r = 0; r < KR; r++)
+        if (sg[r] != 0.0)
+            for (int c = 0; c < NV; c++) acc[c] += sg[r] * F[r][c];
+    for (int32_t q = b + lane + KR * GS; q < e; q += GS) {
+        const int32_t en = ent[q];
+        const int bj = bin[nbr[q]];
+        if (!tb_starts(ti, bi < bj ? bi : bj)) continue;
+        double Fq[NV];
+        load_rec<NV>(flux + (int64_t)(en >> 1) * NV, Fq);
+        const double s1 = (en & 1) ? 1.0 : -1.0;
+        for (int c = 0; c < NV; c++) acc[c] += s1 * Fq[c];
+    }
+    for (int c = 0; c < NV; c++) acc[c] = grp_sum<GS>(acc[c]);
+    if (lane == 0) {
+        bool fin = true;
+        for (int c = 0; c < NV; c++) {
+            const double qn = Q[c * n + i] + acc[c];
+            Q[c * n + i] = qn;
+            fin = fin && isfinite(qn);
+        }
+        if (!fin) {
+            atomicOr(flags, 1);
+            atomicOr(flags + 1, 1);
+        }
+    }
+}
+
+// Sizes of the point's two split lists into info[TB_CELLS], info[TB_FACES].
+__global__ void __launch_bounds__(kBlock) k_tb_finish(const int32_t *__restrict__ cells,
+                                                      const int32_t *__restrict__ faces, int32_t *__restrict__ info) {
+    __shared__ int32_t red[2][kBlock / 64];
+    int32_t a = 0, b = 0;
+    for (int c = threadIdx.x; c < kLists; c += kBlock) {
+        a += cells[c * kListPad];
+        b += faces[c * kListPad];
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o, 64);
+        b += __shfl_xor(b, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x / 64] = a;
+        red[1][threadIdx.x / 64] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kBlock / 64; w++) {
+            a += red[0][w];
+            b += red[1][w];
+        }
+        info[TB_CELLS] = a;
+        info[TB_FACES] = b;
+    }
+}
+
+}  // namespace mm

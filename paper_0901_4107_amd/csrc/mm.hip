@@ -8,6 +8,9 @@
 //   k_grad_limit   lane group/cell limited gradients from the side records
 //   k_face_flux*   per face        extrapolation, Riemann solve, lab-frame flux
 //   k_update       lane group/cell segmented sum of the face fluxes
+// Individual timesteps (Section 7.2, mm_tb_*) run one synchronisation point
+// per call with the kernels of k_tb.hpp around list-driven gradient and
+// flux passes.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -20,6 +23,7 @@
 #include "k_flux.hpp"
 #include "k_learn.hpp"
 #include "k_mesh.hpp"
+#include "k_tb.hpp"
 #include "layout.hpp"
 
 using namespace mm;
@@ -32,10 +36,11 @@ struct Layout {
     int64_t flags, diag, mlp, dtdev, bhard, dtpart, bsum, off, cursor, ent, nbr;
     int64_t srec, frec, rec, flux;          // double path (frec always)
     int64_t srec32, mrec, wf64, rec32, hard; // mixed path
+    int64_t tb_bin, tb_trec, tb_sig, tb_touch, tb_cells, tb_faces, tb_info;   // individual timesteps
     int64_t total;
 };
 
-Layout make_layout(int D, int mode, bool ent, int64_t n, int64_t nf) {
+Layout make_layout(int D, int mode, bool ent, bool tb, int64_t n, int64_t nf) {
     const int NV = D + 2;
     const int REC = (D == 3) ? Lay<3>::REC : Lay<2>::REC;
     const int FREC = (D == 3) ? Lay<3>::FREC : Lay<2>::FREC;
@@ -70,6 +75,16 @@ Layout make_layout(int D, int mode, bool ent, int64_t n, int64_t nf) {
         L.rec32 = take(n * REC * sizeof(float));
         L.hard = take(list_ints(grid_for(nf)) * sizeof(int32_t));
     }
+    L.tb_bin = L.tb_trec = L.tb_sig = L.tb_touch = L.tb_cells = L.tb_faces = L.tb_info = -1;
+    if (tb) {
+        L.tb_bin = take(n);
+        L.tb_trec = take(n * sizeof(int64_t));
+        L.tb_sig = take(n * (D + 2) * sizeof(double));
+        L.tb_touch = take(n * sizeof(int32_t));
+        L.tb_cells = take(list_ints(grid_for(n)) * sizeof(int32_t));
+        L.tb_faces = take(list_ints(grid_for(nf)) * sizeof(int32_t));
+        L.tb_info = take(TB_INFO_INTS * sizeof(int32_t));
+    }
     L.total = o;
     return L;
 }
@@ -91,6 +106,13 @@ struct mm_ctx {
     const double *last_dt_dev = nullptr;  // timestep of the last face-flux pass (device) ...
     double last_dt = 0.0;                 // ... or its value
     bool have_dt = false;
+    struct Timeline {
+        bool on = false;
+        double dt_max = 0.0;
+        int32_t levels = 0;
+        int64_t ti = 0;
+        int32_t cur = 0;   // stamp of the current point
+    } tb;
     Layout lay;
     hipStream_t st() const { return (hipStream_t)p.stream; }
     template <typename T> T *at(int64_t off) const { return (T *)(ws + off); }
@@ -128,6 +150,7 @@ const char *mm_status_str(mm_status s) {
         case MM_E_STATE: return "no workspace or no mesh";
         case MM_E_WORKSPACE: return "workspace too small";
         case MM_E_NONFINITE: return "non-finite conserved state";
+        case MM_E_RANGE: return "timestep criterion below the smallest step";
         default: return "unknown status";
     }
 }
@@ -141,6 +164,8 @@ mm_status mm_create(const mm_params *params, mm_ctx **out) {
     if (!(params->gamma > 1.0) || !(params->cfl > 0.0)) return MM_E_ARG;
     if (params->entropy != MM_ENTROPY_OFF && params->entropy != MM_ENTROPY_MACH) return MM_E_ARG;
     if (params->entropy != MM_ENTROPY_OFF && params->mach_thresh != params->mach_thresh) return MM_E_ARG;
+    if (params->steps != MM_STEPS_GLOBAL && params->steps != MM_STEPS_INDIVIDUAL) return MM_E_ARG;
+    if (params->steps == MM_STEPS_INDIVIDUAL && params->entropy != MM_ENTROPY_OFF) return MM_E_ARG;
     mm_ctx *c = new (std::nothrow) mm_ctx();
     if (!c) return MM_E_ARG;
     c->p = *params;
@@ -160,7 +185,7 @@ mm_status mm_destroy(mm_ctx *ctx) {
 int64_t mm_workspace_bytes(const mm_ctx *ctx, int64_t n_cells, int64_t n_faces) {
     if (!ctx || n_cells < 2 || n_faces < 1 || n_faces >= (int64_t(1) << 30) || n_cells >= (int64_t(1) << 31) - 1)
         return -1;
-    return make_layout(ctx->D, ctx->p.mode, ctx->p.entropy != 0, n_cells, n_faces).total;
+    return make_layout(ctx->D, ctx->p.mode, ctx->p.entropy != 0, ctx->p.steps != 0, n_cells, n_faces).total;
 }
 
 mm_status mm_set_workspace(mm_ctx *ctx, void *dev_ptr, int64_t bytes) {
@@ -172,7 +197,7 @@ mm_status mm_set_workspace(mm_ctx *ctx, void *dev_ptr, int64_t bytes) {
     ctx->diag_ready = false;
     // fixed-size regions (flags, diagnostics, network) sit at offsets that
     // no mesh changes
-    ctx->lay = make_layout(ctx->D, ctx->p.mode, ctx->p.entropy != 0, 2, 1);
+    ctx->lay = make_layout(ctx->D, ctx->p.mode, ctx->p.entropy != 0, ctx->p.steps != 0, 2, 1);
     return MM_OK;
 }
 
@@ -190,7 +215,7 @@ static mm_status clear_diag(mm_ctx *c) {
 
 // Workspace present and its fixed regions initialised.
 static mm_status need_ws(mm_ctx *c) {
-    if (!c->ws || c->ws_bytes < make_layout(c->D, c->p.mode, c->p.entropy != 0, 2, 1).total) return MM_E_STATE;
+    if (!c->ws || c->ws_bytes < make_layout(c->D, c->p.mode, c->p.entropy != 0, c->p.steps != 0, 2, 1).total) return MM_E_STATE;
     if (!c->diag_ready) return clear_diag(c);
     return MM_OK;
 }
@@ -239,9 +264,10 @@ mm_status mm_mesh_upload(mm_ctx *c, const mm_mesh *m) {
     if (!m->volume || !m->centroid_off || !m->mesh_vel || !m->face_L || !m->face_R || !m->face_area ||
         !m->face_ctr || !m->face_sep)
         return MM_E_ARG;
-    Layout L = make_layout(c->D, c->p.mode, c->p.entropy != 0, n, nf);
+    Layout L = make_layout(c->D, c->p.mode, c->p.entropy != 0, c->p.steps != 0, n, nf);
     if (L.total > c->ws_bytes) return MM_E_WORKSPACE;
     c->have_mesh = false;
+    c->tb.on = false;
     c->accel = nullptr;   // a field belongs to the mesh it was set for
     c->have_dt = false;
     c->lay = L;
@@ -285,6 +311,7 @@ mm_status mm_mesh_set_velocity(mm_ctx *c, const double *mesh_vel) {
     if (!c || !mesh_vel) return MM_E_ARG;
     if (!c->have_mesh) return MM_E_STATE;
     c->have_mesh = false;
+    c->tb.on = false;
     c->mesh.mesh_vel = mesh_vel;
     const mm_mesh *m = &c->mesh;
     hipStream_t s = c->st();
@@ -335,6 +362,7 @@ static mm_status gradients_into(mm_ctx *c, const double *Q, void *rec, double *d
 mm_status mm_gradients(mm_ctx *c, const double *Q, void *recon) {
     if (!c || !Q || !recon) return MM_E_ARG;
     if (!c->have_mesh) return MM_E_STATE;
+    c->tb.on = false;
     return gradients_into(c, Q, recon, c->at<double>(c->lay.dtpart));
 }
 
@@ -366,7 +394,7 @@ static mm_status fluxes_t(mm_ctx *c, const double *dt_dev, double dt, const void
                                                         c->at<double>(L.wf64), prim, grad_block<D>(c, prim), dt_dev,
                                                         dt, kf.g,
                                                         kg, c->p.newton_tol64, hard, cap, flux, diag, c->accel,
-                                                        c->n);
+                                                        c->n, TbView{});
     }
     MM_LAUNCH_CHECK();
     return MM_OK;
@@ -471,6 +499,7 @@ mm_status mm_hydro_step(mm_ctx *c, double *Q, double dt, double *dt_used) {
     if (!c || !Q) return MM_E_ARG;
     if (!c->have_mesh) return MM_E_STATE;
     if (!isfinite(dt)) return MM_E_ARG;
+    c->tb.on = false;   // the step rewrites the cell records a timeline keeps
     const Layout &L = c->lay;
     hipStream_t s = c->st();
     void *rec = c->p.mode == MM_FP64 ? (void *)c->at<double>(L.rec) : (void *)c->at<float>(L.rec32);
@@ -643,3 +672,138 @@ mm_status mm_get_diag(mm_ctx *c, mm_diag *out) {
     return MM_OK;
 }
 
+
+// ------------------------------------------------------------------------
+// Individual timesteps (Section 7.2).
+
+mm_status mm_tb_begin(mm_ctx *c, double dt_max, int32_t levels) {
+    if (!c) return MM_E_ARG;
+    if (c->p.steps != MM_STEPS_INDIVIDUAL) return MM_E_STATE;
+    if (!(dt_max > 0.0) || !isfinite(dt_max) || levels < 0 || levels > kTbMaxLevels) return MM_E_ARG;
+    if (!c->have_mesh) return MM_E_STATE;
+    const Layout &L = c->lay;
+    k_tb_init<<<plain_grid(c->n > TB_INFO_INTS ? c->n : TB_INFO_INTS), kBlock, 0, c->st()>>>(
+        c->n, levels, c->at<int8_t>(L.tb_bin), c->at<int64_t>(L.tb_trec), c->at<int32_t>(L.tb_touch),
+        c->at<int32_t>(L.tb_info));
+    MM_LAUNCH_CHECK();
+    c->tb.on = true;
+    c->tb.dt_max = dt_max;
+    c->tb.levels = levels;
+    c->tb.ti = 0;
+    c->tb.cur = 0;
+    return MM_OK;
+}
+
+template <int D, typename T> static void tb_point(mm_ctx *c, double *Q, T *rec) {
+    const Layout &L = c->lay;
+    hipStream_t s = c->st();
+    mm_ctx::Timeline &tb = c->tb;
+    int8_t *bin = c->at<int8_t>(L.tb_bin);
+    int64_t *trec = c->at<int64_t>(L.tb_trec);
+    double *sig = c->at<double>(L.tb_sig);
+    int32_t *touch = c->at<int32_t>(L.tb_touch);
+    int32_t *cells = c->at<int32_t>(L.tb_cells), *faces = c->at<int32_t>(L.tb_faces);
+    int32_t *info = c->at<int32_t>(L.tb_info);
+    int32_t *flags = c->at<int32_t>(L.flags);
+    const int64_t ccap = list_cap(grid_for(c->n)), fcap = list_cap(grid_for(c->nf));
+    const bool mixed = c->p.mode == MM_MIXED;
+    const T *srec = mixed ? (const T *)c->at<float>(L.srec32) : (const T *)c->at<double>(L.srec);
+    T *grad = grad_block<D>(c, rec);
+    const unsigned lg = kHardGrid;   // list-walking grids: a multiple of kLists
+    // per point: both list headers, the error slot and the step's non-finite flag
+    k_fill_i32<<<kLists * kListPad / kBlock, kBlock, 0, s>>>(cells, kLists * kListPad, 0);
+    k_fill_i32<<<kLists * kListPad / kBlock, kBlock, 0, s>>>(faces, kLists * kListPad, 0);
+    k_fill_i32<<<1, kBlock, 0, s>>>(info + TB_ERR, 1, 0);
+    k_fill_i32<<<1, kBlock, 0, s>>>(flags + 2, 1, 0);
+    k_tb_open<D, T><<<grid_for(c->n), kBlock, 0, s>>>(c->n, tb.ti, bin, trec, c->p.gamma, c->mesh.volume, Q,
+                                                      c->mesh.mesh_vel, c->mesh.centroid_off, rec, sig, cells, ccap);
+    k_tb_bins<D><<<lg, kBlock, 0, s>>>(cells, ccap, tb.ti, tb.dt_max, tb.levels, c->p.cfl, c->at<int32_t>(L.off),
+                                       c->at<int32_t>(L.ent), c->at<int32_t>(L.nbr), c->at<double>(L.frec), sig, bin,
+                                       info);
+    k_grad_limit_list<D, T><<<lg, kBlock, 0, s>>>(cells, ccap, c->at<int32_t>(L.off), c->at<int32_t>(L.nbr), srec,
+                                                  c->mesh.volume, rec, grad);
+    k_tb_faces<<<grid_for(c->nf), kBlock, 0, s>>>(c->nf, c->mesh.face_L, c->mesh.face_R, bin, tb.ti, info, touch,
+                                                  tb.cur, faces, fcap);
+    const TbView view{bin, trec, tb.ti, tb.dt_max, tb.levels};
+    DiagDev *diag = c->at<DiagDev>(L.diag);
+    const MlpPacked *mlp = active_mlp(c);
+    const GasConst<double> kg(c->p.gamma);
+    double *flux = c->at<double>(L.flux);
+    if (!mixed) {
+        auto kern = mlp ? k_face_flux64_list<D, true> : k_face_flux64_list<D, false>;
+        kern<<<lg, kBlock, 0, s>>>(faces, fcap, c->mesh.face_L, c->mesh.face_R, c->at<double>(L.frec),
+                                   (const double *)rec, (const double *)grad, view, kg, c->p.newton_tol64,
+                                   c->p.newton_max_iter, mlp, flux, diag);
+    } else {
+        const GasConst<float> kf(c->p.gamma);
+        int32_t *hard = c->at<int32_t>(L.hard);
+        k_fill_i32<<<kLists * kListPad / kBlock, kBlock, 0, s>>>(hard, kLists * kListPad, 0);
+        auto kern = mlp ? k_face_flux_mixed_list<D, true> : k_face_flux_mixed_list<D, false>;
+        kern<<<lg, kBlock, 0, s>>>(faces, fcap, c->mesh.face_L, c->mesh.face_R, c->at<float>(L.mrec),
+                                   c->at<double>(L.wf64), (const float *)rec, (const float *)grad, view, kf,
+                                   kg.g_over_gm1, (float)c->p.newton_tol32, c->p.newton_max_iter, mlp, flux, hard,
+                                   diag);
+        k_face_flux_hard<D, false, false><<<kHardGrid, kBlock, 0, s>>>(
+            c->mesh.face_L, c->mesh.face_R, c->at<float>(L.mrec), c->at<double>(L.wf64), (const float *)rec,
+            (const float *)grad, nullptr, 0.0, kf.g, kg, c->p.newton_tol64, hard, fcap, flux, diag, nullptr, c->n,
+            view);
+    }
+    k_tb_update<D><<<group_grid(D, c->n), kBlock, 0, s>>>(c->n, c->at<int32_t>(L.off), c->at<int32_t>(L.ent),
+                                                           c->at<int32_t>(L.nbr), bin, tb.ti, touch, tb.cur, flux, Q,
+                                                           flags + 1);
+    k_tb_finish<<<1, kBlock, 0, s>>>(cells, faces, info);
+}
+
+mm_status mm_tb_step(mm_ctx *c, double *Q, mm_tb_info *out) {
+    if (!c || !Q) return MM_E_ARG;
+    if (!c->have_mesh || !c->tb.on || c->accel) return MM_E_STATE;
+    const Layout &L = c->lay;
+    hipStream_t s = c->st();
+    const bool f64 = c->p.mode == MM_FP64;
+    void *rec = f64 ? (void *)c->at<double>(L.rec) : (void *)c->at<float>(L.rec32);
+    if (c->D == 3) f64 ? tb_point<3, double>(c, Q, (double *)rec) : tb_point<3, float>(c, Q, (float *)rec);
+    else f64 ? tb_point<2, double>(c, Q, (double *)rec) : tb_point<2, float>(c, Q, (float *)rec);
+    MM_LAUNCH_CHECK();
+    int32_t info[TB_INFO_INTS], nonfin = 0;
+    MM_CHECK(hipMemcpyAsync(info, c->at<int32_t>(L.tb_info), sizeof(info), hipMemcpyDeviceToHost, s));
+    MM_CHECK(hipMemcpyAsync(&nonfin, c->at<int32_t>(L.flags) + 2, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    MM_CHECK(hipStreamSynchronize(s));
+    mm_ctx::Timeline &tb = c->tb;
+    if (info[TB_ERR]) {
+        tb.on = false;   // bins and records of the active cells have moved on; Q has not
+        return MM_E_RANGE;
+    }
+    int lo = -1, hi = -1;
+    for (int b = 0; b <= tb.levels; b++)
+        if (info[TB_COUNTS + b] > 0) {
+            if (lo < 0) lo = b;
+            hi = b;
+        }
+    if (lo < 0) return MM_E_DEVICE;   // the counts always hold every cell
+    const int64_t next = ((tb.ti >> lo) + 1) << lo;
+    c->faces_done += (uint64_t)info[TB_FACES];
+    c->waves_done += (uint64_t)((info[TB_FACES] + 63) / 64);
+    if (out) {
+        out->tick = tb.ti;
+        out->next_tick = next;
+        out->active_cells = info[TB_CELLS];
+        out->active_faces = info[TB_FACES];
+        out->min_bin = lo;
+        out->max_bin = hi;
+        out->next_time = ldexp(tb.dt_max, -tb.levels) * (double)next;
+    }
+    tb.ti = next;
+    tb.cur += 1;
+    return nonfin ? MM_E_NONFINITE : MM_OK;
+}
+
+mm_status mm_tb_state(mm_ctx *c, int8_t *bins, int64_t *trec) {
+    if (!c) return MM_E_ARG;
+    if (!c->tb.on) return MM_E_STATE;
+    const Layout &L = c->lay;
+    if (bins) MM_CHECK(hipMemcpyAsync(bins, c->at<int8_t>(L.tb_bin), c->n, hipMemcpyDeviceToDevice, c->st()));
+    if (trec)
+        MM_CHECK(hipMemcpyAsync(trec, c->at<int64_t>(L.tb_trec), c->n * sizeof(int64_t), hipMemcpyDeviceToDevice,
+                                c->st()));
+    return MM_OK;
+}

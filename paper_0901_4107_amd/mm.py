@@ -18,9 +18,11 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIBMM_PATH = os.path.join(_HERE, "libmm.so")
 
 MM_OK, MM_E_ARG, MM_E_MESH, MM_E_DEVICE, MM_E_STATE, MM_E_WORKSPACE, MM_E_NONFINITE = 0, -1, -2, -3, -4, -5, -6
+MM_E_RANGE = -7
 MM_FP64, MM_MIXED = 0, 1
 MM_GUESS_STANDARD, MM_GUESS_LEARNED = 0, 1
 MM_ENTROPY_OFF, MM_ENTROPY_MACH = 0, 1
+MM_STEPS_GLOBAL, MM_STEPS_INDIVIDUAL = 0, 1
 
 _vp = ctypes.c_void_p
 
@@ -29,7 +31,7 @@ class mm_params(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("mode", ctypes.c_int32), ("guess", ctypes.c_int32),
                 ("newton_max_iter", ctypes.c_int32), ("gamma", ctypes.c_double), ("cfl", ctypes.c_double),
                 ("newton_tol64", ctypes.c_double), ("newton_tol32", ctypes.c_double), ("stream", _vp),
-                ("entropy", ctypes.c_int32), ("reserved", ctypes.c_int32), ("mach_thresh", ctypes.c_double)]
+                ("entropy", ctypes.c_int32), ("steps", ctypes.c_int32), ("mach_thresh", ctypes.c_double)]
 
 
 class mm_mesh(ctypes.Structure):
@@ -43,6 +45,12 @@ class mm_diag(ctypes.Structure):
                 ("faces", "newton_iters", "newton_max", "unconverged", "vacuum", "positivity_fallback",
                  "fp64_fallback", "guess_fallback", "wave_iter_max_sum", "waves", "entropy_kept")] + \
                [("nonfinite", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class mm_tb_info(ctypes.Structure):
+    _fields_ = [("tick", ctypes.c_int64), ("next_tick", ctypes.c_int64), ("active_cells", ctypes.c_int64),
+                ("active_faces", ctypes.c_int64), ("min_bin", ctypes.c_int32), ("max_bin", ctypes.c_int32),
+                ("next_time", ctypes.c_double)]
 
 
 class MMError(RuntimeError):
@@ -81,6 +89,9 @@ SIGNATURES = {
     "mm_volume_rate": (ctypes.c_int32, [_vp, _vp]),
     "mm_mesh_set_velocity": (ctypes.c_int32, [_vp, _vp]),
     "mm_set_gravity": (ctypes.c_int32, [_vp, _vp]),
+    "mm_tb_begin": (ctypes.c_int32, [_vp, ctypes.c_double, ctypes.c_int32]),
+    "mm_tb_step": (ctypes.c_int32, [_vp, _vp, ctypes.POINTER(mm_tb_info)]),
+    "mm_tb_state": (ctypes.c_int32, [_vp, _vp, _vp]),
 }
 
 MM_MLP_PARAMS = 4481
@@ -157,11 +168,11 @@ class Context:
     def __init__(self, dim: int, gamma: float, cfl: float = 0.4, mode: int = MM_FP64,
                  guess: int = MM_GUESS_STANDARD, newton_max_iter: int = 0, newton_tol64: float = 0.0,
                  newton_tol32: float = 0.0, device="cuda", stream: torch.cuda.Stream | None = None,
-                 entropy: int = MM_ENTROPY_OFF, mach_thresh: float = 1.1):
+                 entropy: int = MM_ENTROPY_OFF, mach_thresh: float = 1.1, steps: int = MM_STEPS_GLOBAL):
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.params = mm_params(dim, mode, guess, newton_max_iter, gamma, cfl, newton_tol64, newton_tol32,
-                                ctypes.c_void_p(self.stream.cuda_stream), entropy, 0, mach_thresh)
+                                ctypes.c_void_p(self.stream.cuda_stream), entropy, steps, mach_thresh)
         self.dim = dim
         self.mode = mode
         self.entropy = entropy
@@ -263,6 +274,25 @@ class Context:
     def mm_entropy_init(self, Q: torch.Tensor):
         _check("mm_entropy_init", lib().mm_entropy_init(self._ctx, _ptr(Q)))
 
+
+    def mm_tb_begin(self, dt_max: float, levels: int):
+        _check("mm_tb_begin", lib().mm_tb_begin(self._ctx, float(dt_max), int(levels)))
+
+    def mm_tb_step(self, Q: torch.Tensor) -> dict:
+        """One synchronisation point on Q in place; returns the point's
+        summary (tick, next_tick, active_cells, active_faces, min_bin,
+        max_bin, next_time)."""
+        info = mm_tb_info()
+        _check("mm_tb_step", lib().mm_tb_step(self._ctx, _ptr(Q), ctypes.byref(info)))
+        return {name: getattr(info, name) for name, _ in mm_tb_info._fields_}
+
+    def mm_tb_state(self, bins: torch.Tensor | None = None, trec: torch.Tensor | None = None):
+        """Copies of the bins (int8 [N]) and step start ticks (int64 [N])."""
+        if bins is not None and bins.dtype != torch.int8:
+            raise ValueError("bins must be int8")
+        if trec is not None and trec.dtype != torch.int64:
+            raise ValueError("trec must be int64")
+        _check("mm_tb_state", lib().mm_tb_state(self._ctx, _ptr(bins), _ptr(trec)))
 
     def recon_buffer(self, n_cells: int):
         """Reconstruction buffer for mm_gradients in this context's mode

@@ -31,10 +31,12 @@ def test_library_exports_every_declared_symbol():
 
 def _params(**kw):
     p = dict(dim=3, mode=mm.MM_FP64, guess=mm.MM_GUESS_STANDARD, newton_max_iter=0, gamma=5 / 3, cfl=0.4,
-             newton_tol64=0.0, newton_tol32=0.0, stream=None, entropy=mm.MM_ENTROPY_OFF, mach_thresh=1.1)
+             newton_tol64=0.0, newton_tol32=0.0, stream=None, entropy=mm.MM_ENTROPY_OFF, mach_thresh=1.1,
+             steps=mm.MM_STEPS_GLOBAL)
     p.update(kw)
     return mm.mm_params(p["dim"], p["mode"], p["guess"], p["newton_max_iter"], p["gamma"], p["cfl"],
-                        p["newton_tol64"], p["newton_tol32"], p["stream"], p["entropy"], 0, p["mach_thresh"])
+                        p["newton_tol64"], p["newton_tol32"], p["stream"], p["entropy"], p["steps"],
+                        p["mach_thresh"])
 
 
 def _create(**kw):
@@ -45,7 +47,8 @@ def _create(**kw):
 
 @pytest.mark.parametrize("kw", [dict(dim=1), dict(dim=4), dict(mode=7), dict(guess=3), dict(gamma=1.0),
                                 dict(gamma=float("nan")), dict(cfl=0.0), dict(entropy=2),
-                                dict(entropy=mm.MM_ENTROPY_MACH, mach_thresh=float("nan"))])
+                                dict(entropy=mm.MM_ENTROPY_MACH, mach_thresh=float("nan")), dict(steps=2),
+                                dict(steps=-1), dict(steps=mm.MM_STEPS_INDIVIDUAL, entropy=mm.MM_ENTROPY_MACH)])
 def test_create_rejects_bad_params(kw):
     st, ctx = _create(**kw)
     assert st == mm.MM_E_ARG and not ctx.value
@@ -111,6 +114,28 @@ def test_entropy_mode_widens_the_flux_records():
         assert mm.flux_stride(3, mm.MM_ENTROPY_MACH) == 7 and mm.flux_stride(2) == 4
         assert L.mm_entropy_init(c0, ctypes.c_void_p(256)) == mm.MM_E_ARG    # not in entropy mode
         assert L.mm_entropy_init(c1, ctypes.c_void_p(256)) == mm.MM_E_STATE  # no mesh
+    finally:
+        L.mm_destroy(c0); L.mm_destroy(c1)
+
+
+def test_individual_steps_widen_the_workspace():
+    """A context for individual timesteps holds per-cell bins, step starts,
+    signal records and touch stamps, and two split lists; its timeline entry
+    points check their arguments and state before touching the device."""
+    L = mm.lib()
+    _, c0 = _create()
+    _, c1 = _create(steps=mm.MM_STEPS_INDIVIDUAL)
+    try:
+        n, nf = 100000, 800000
+        assert L.mm_workspace_bytes(c1, n, nf) - L.mm_workspace_bytes(c0, n, nf) >= (1 + 8 + 5 * 8 + 4) * n + 4 * nf
+        assert L.mm_tb_begin(c0, 1e-3, 3) == mm.MM_E_STATE     # not an individual-timestep context
+        for dt, lv in ((1e-3, 31), (1e-3, -1), (0.0, 3), (float("inf"), 3), (float("nan"), 3)):
+            assert L.mm_tb_begin(c1, dt, lv) == mm.MM_E_ARG, (dt, lv)
+        assert L.mm_tb_begin(c1, 1e-3, 3) == mm.MM_E_STATE     # no mesh
+        assert L.mm_tb_step(c1, ctypes.c_void_p(256), None) == mm.MM_E_STATE
+        assert L.mm_tb_step(c1, None, None) == mm.MM_E_ARG
+        assert L.mm_tb_state(c1, None, None) == mm.MM_E_STATE
+        assert L.mm_status_str(mm.MM_E_RANGE) == b"timestep criterion below the smallest step"
     finally:
         L.mm_destroy(c0); L.mm_destroy(c1)
 

@@ -1,0 +1,223 @@
+"""Individual power-of-two timesteps (Section 7.2) through the C ABI against
+the oracle's timeline: one occupied bin equals the global step bit for bit;
+point by point over full cycles, the double path matches the oracle's ticks,
+active counts, bins and step starts exactly and its state to 1e-12; the
+mixed + learned form stays within the stated L1; and the error and state
+rules of the entry points."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_0901_4107_amd import learned, mm
+from paper_0901_4107_amd.inputs import build_mesh
+from paper_0901_4107_amd.inputs.configs import (conserved_from_primitive, kh2d, kh3d, poisson_points, random3d,
+                                                random_states)
+from tests.util import boost, l1_state, normwise_rel
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def min_criterion(wl, Q=None):
+    m = wl.mesh
+    Q = wl.Q if Q is None else Q
+    return O.tb_criterion(m, wl.gamma, wl.cfl, O.prim(m.dim, wl.gamma, m.volume, Q)).min()
+
+
+def context(wl, mode=mm.MM_FP64, guess=mm.MM_GUESS_STANDARD):
+    ctx = mm.Context(wl.mesh.dim, wl.gamma, wl.cfl, mode=mode, guess=guess, steps=mm.MM_STEPS_INDIVIDUAL)
+    if guess == mm.MM_GUESS_LEARNED:
+        ctx.mm_mlp_load(learned.load(wl.gamma))
+    ctx.mm_mesh_upload(mm.DeviceMesh.from_host(wl.mesh))
+    return ctx
+
+
+def state(ctx, n):
+    bins = torch.empty(n, dtype=torch.int8, device="cuda")
+    trec = torch.empty(n, dtype=torch.int64, device="cuda")
+    ctx.mm_tb_state(bins, trec)
+    return bins.cpu().numpy(), trec.cpu().numpy()
+
+
+@pytest.mark.parametrize("mode", [mm.MM_FP64, mm.MM_MIXED])
+@pytest.mark.parametrize("make", [lambda: random3d(n_side=12, seed=811), kh2d])
+def test_single_bin_is_the_global_step(make, mode):
+    """dt_max below every criterion: all cells in the top bin, one point is
+    the global step of length dt_max on the same records, bit for bit."""
+    wl = make()
+    dt_max = 0.5 * min_criterion(wl)
+    ctx = context(wl, mode)
+    ctx.mm_tb_begin(dt_max, 3)
+    Q = torch.from_numpy(np.ascontiguousarray(wl.Q)).cuda()
+    info = ctx.mm_tb_step(Q)
+    assert info["tick"] == 0 and info["next_tick"] == 8
+    assert info["active_cells"] == wl.mesh.n_cells and info["active_faces"] == wl.mesh.n_faces
+    assert info["min_bin"] == info["max_bin"] == 3
+    g = mm.Context(wl.mesh.dim, wl.gamma, wl.cfl, mode=mode)
+    g.mm_mesh_upload(mm.DeviceMesh.from_host(wl.mesh))
+    Qg = torch.from_numpy(np.ascontiguousarray(wl.Q)).cuda()
+    g.mm_hydro_step(Qg, dt=dt_max)
+    assert torch.equal(Q, Qg)
+
+
+def run_both(wl, Q0, levels, spread, cycles, check, mode=mm.MM_FP64, guess=mm.MM_GUESS_STANDARD):
+    """Runs the oracle's and the device's timelines side by side over whole
+    cycles; check(point, oracle result, device info, oracle Q, device Q,
+    oracle timeline, device context) after every point."""
+    m = wl.mesh
+    dt_max = np.ldexp(0.99 * spread * min_criterion(wl, Q0), levels)
+    tl = O.Timeline(m, wl.gamma, wl.cfl, dt_max, levels)
+    ctx = context(wl, mode, guess)
+    ctx.mm_tb_begin(dt_max, levels)
+    Qo = np.ascontiguousarray(Q0).copy()
+    Qd = torch.from_numpy(Qo.copy()).cuda()
+    k = 0
+    while tl.ti < cycles * 2 ** levels:
+        r = tl.step(Qo)
+        assert r["status"] == 0
+        info = ctx.mm_tb_step(Qd)
+        check(k, r, info, Qo, Qd, tl, ctx)
+        k += 1
+    return k, tl, ctx, Qo, Qd
+
+
+class Random:
+    """Random states on a Poisson mesh (cell sizes and sound speeds spread
+    over several bins)."""
+
+    def __init__(self, n, dim, seed):
+        rng = np.random.default_rng(seed)
+        self.mesh = build_mesh(poisson_points(n, dim, rng))
+        self.gamma, self.cfl = 5.0 / 3.0, 0.4
+        rho, vel, P = random_states(self.mesh.n_cells, dim, self.gamma, rng)
+        self.Q = conserved_from_primitive(self.mesh.volume, rho, 0.5 * vel, P, self.gamma)
+        self.name = f"random states {n} ({dim}D)"
+
+
+@pytest.mark.parametrize("make,levels,spread", [
+    (lambda: random3d(n_side=12, seed=812), 4, 0.25),
+    (lambda: kh3d(n_points=24 ** 3, seed=813), 5, 1.0),
+    (lambda: Random(3000, 2, 818), 4, 0.5),
+])
+def test_double_points_match_the_oracle(make, levels, spread):
+    wl = make()
+    n = wl.mesh.n_cells
+    worst = [0.0]
+
+    def check(k, r, info, Qo, Qd, tl, ctx):
+        assert info["tick"] == r["ti"] and info["next_tick"] == r["next"], (k, info, r["ti"], r["next"])
+        assert info["active_cells"] == r["active"].sum() and info["active_faces"] == r["n_faces"], (k, info)
+        bins, trec = state(ctx, n)
+        assert np.array_equal(bins, tl.bin) and np.array_equal(trec, tl.trec), k
+        err = normwise_rel(Qd.cpu().numpy(), Qo)
+        worst[0] = max(worst[0], float(err.max()))
+        assert np.all(err <= TOL), (k, err)
+    points, tl, _, _, _ = run_both(wl, wl.Q, levels, spread, 2, check)
+    note(f"{wl.name}: {points} points over two cycles, bins {np.bincount(tl.bin, minlength=levels + 1)}, "
+         f"worst norm-wise error {worst[0]:.2e}")
+    assert len(np.unique(tl.bin)) >= 2
+
+
+def test_mixed_learned_cycle():
+    """The mixed + learned form over a full cycle of four levels: at every
+    point the same ticks and counts as the oracle, the bins equal (decided in
+    double on both sides), and the rest-frame state within the stated L1."""
+    wl = kh3d(n_points=24 ** 3, seed=814)
+    worst = [0.0]
+
+    def check(k, r, info, Qo, Qd, tl, ctx):
+        assert info["tick"] == r["ti"] and info["next_tick"] == r["next"]
+        l1 = l1_state(boost(Qd.cpu().numpy(), -wl.boost), boost(Qo, -wl.boost))
+        worst[0] = max(worst[0], float(l1.max()))
+        assert np.all(l1 <= 1e-6), (k, l1)
+    points, tl, ctx, _, _ = run_both(wl, wl.Q, 4, 1.0, 1, check, mode=mm.MM_MIXED, guess=mm.MM_GUESS_LEARNED)
+    bins, _ = state(ctx, wl.mesh.n_cells)
+    note(f"{wl.name} mixed + learned: {points} points, worst rest-frame L1 {worst[0]:.2e}, "
+         f"diag {ctx.mm_get_diag()}")
+    assert np.array_equal(bins, tl.bin)
+
+
+def test_random_states_conserve():
+    """Random states over five levels and two cycles: the device's totals
+    of mass, momentum and energy stay at their initial values to round-off,
+    and match the oracle point by point."""
+    wl = Random(3000, 3, 815)
+    Q0 = wl.Q
+    tot0 = Q0.sum(axis=1)
+
+    def check(k, r, info, Qo, Qd, tl, ctx):
+        assert info["active_faces"] == r["n_faces"]
+        Qh = Qd.cpu().numpy()
+        assert np.allclose(Qh.sum(axis=1), tot0, rtol=0, atol=1e-13 * np.abs(Qh).sum())
+        assert np.all(normwise_rel(Qh, Qo) <= TOL)
+    run_both(wl, Q0, 5, 0.25, 2, check)
+
+
+def test_criterion_below_one_tick():
+    """A cell whose criterion is below one tick: MM_E_RANGE, Q untouched,
+    and the timeline ended (MM_E_STATE until a new begin)."""
+    wl = random3d(n_side=10, seed=816)
+    ctx = context(wl)
+    ctx.mm_tb_begin(4.0 * min_criterion(wl), 1)
+    Q = torch.from_numpy(np.ascontiguousarray(wl.Q)).cuda()
+    Q0 = Q.clone()
+    with pytest.raises(mm.MMError) as e:
+        ctx.mm_tb_step(Q)
+    assert e.value.status == mm.MM_E_RANGE
+    torch.cuda.synchronize()
+    assert torch.equal(Q, Q0)
+    with pytest.raises(mm.MMError) as e:
+        ctx.mm_tb_step(Q)
+    assert e.value.status == mm.MM_E_STATE
+    ctx.mm_tb_begin(0.5 * min_criterion(wl), 1)
+    ctx.mm_tb_step(Q)
+
+
+def test_entry_point_rules():
+    """Begin needs an individual-timestep context and a mesh, levels in
+    [0, 30] and a positive finite dt_max; a global step, a mesh upload or
+    new generator velocities end the timeline; a gravitational field
+    refuses it."""
+    wl = random3d(n_side=8, seed=817)
+    g = mm.Context(3, wl.gamma, wl.cfl)
+    g.mm_mesh_upload(mm.DeviceMesh.from_host(wl.mesh))
+    with pytest.raises(mm.MMError) as e:
+        g.mm_tb_begin(1e-3, 3)
+    assert e.value.status == mm.MM_E_STATE
+    ctx = context(wl)
+    for dt, lv in ((1e-3, 31), (1e-3, -1), (0.0, 3), (float("inf"), 3), (float("nan"), 3)):
+        with pytest.raises(mm.MMError) as e:
+            ctx.mm_tb_begin(dt, lv)
+        assert e.value.status == mm.MM_E_ARG
+    Q = torch.from_numpy(np.ascontiguousarray(wl.Q)).cuda()
+    with pytest.raises(mm.MMError) as e:
+        ctx.mm_tb_step(Q)
+    assert e.value.status == mm.MM_E_STATE
+    dt = 0.5 * min_criterion(wl)
+    ends = [lambda: ctx.mm_hydro_step(Q.clone(), dt=dt),
+            lambda: ctx.mm_mesh_upload(mm.DeviceMesh.from_host(wl.mesh)),
+            lambda: ctx.mm_mesh_set_velocity(torch.zeros((3, wl.mesh.n_cells), dtype=torch.float64,
+                                                         device="cuda"))]
+    for end in ends:
+        ctx.mm_tb_begin(dt, 2)
+        ctx.mm_tb_step(Q)
+        end()
+        with pytest.raises(mm.MMError) as e:
+            ctx.mm_tb_step(Q)
+        assert e.value.status == mm.MM_E_STATE
+    ctx.mm_tb_begin(dt, 2)
+    ctx.mm_set_gravity(torch.zeros((3, wl.mesh.n_cells), dtype=torch.float64, device="cuda"))
+    with pytest.raises(mm.MMError) as e:
+        ctx.mm_tb_step(Q)
+    assert e.value.status == mm.MM_E_STATE
+    ctx.mm_set_gravity(None)
+    ctx.mm_tb_step(Q)
