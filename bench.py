@@ -77,11 +77,11 @@ def l1_rest(a, b, boost):
     return num / np.where(den > 0, den, 1.0)
 
 
-def make_context(mm, learned, m, wl, form, dev, mach_thresh=None):
+def make_context(mm, learned, m, wl, form, dev, mach_thresh=None, steps=0):
     mode = mm.MM_FP64 if form.startswith("fp64") else mm.MM_MIXED
     guess = mm.MM_GUESS_LEARNED if form.endswith("learned") else mm.MM_GUESS_STANDARD
     ent = {} if mach_thresh is None else {"entropy": mm.MM_ENTROPY_MACH, "mach_thresh": mach_thresh}
-    ctx = mm.Context(m.dim, wl.gamma, wl.cfl, mode=mode, guess=guess, device=dev, **ent)
+    ctx = mm.Context(m.dim, wl.gamma, wl.cfl, mode=mode, guess=guess, device=dev, steps=steps, **ent)
     if guess == mm.MM_GUESS_LEARNED:
         params = learned.load(wl.gamma, dev)
         if params is None:
@@ -184,6 +184,66 @@ def time_mesh_motion(mm, torch, wl, dmesh, steps, dev):
             "cells_per_s_mesh_velocity": m.n_cells / (vel_ms * 1e-3)}
 
 
+def time_individual(mm, learned, torch, wl, dmesh, form, dt_courant, step_ms, dev):
+    """Individual power-of-two timesteps (Section 7.2) on the workload: one
+    full cycle of dt_max = 4 Courant steps of the initial state, with the
+    number of levels raised until every cell's criterion fits a bin (the
+    library answers MM_E_RANGE below that). Untimed: a first full cycle;
+    timed: a second one from the same initial state. Compared with a global
+    scheme whose step is the smallest occupied bin's (the paper's
+    comparison: a global step at the smallest individual criterion), whose
+    cost is estimated from the measured global step time, and with the
+    Courant-step global path per unit of simulated time."""
+    m = wl.mesh
+    ctx = make_context(mm, learned, m, wl, form, dev, steps=mm.MM_STEPS_INDIVIDUAL)
+    ctx.mm_mesh_upload(dmesh)
+    Q0 = torch.from_numpy(np.ascontiguousarray(wl.Q)).to(dev)
+    dt_max, levels = 4.0 * dt_courant, 6
+
+    def cycle(Q):
+        ctx.mm_tb_begin(dt_max, levels)
+        pts, faces, cells, b0, hi = 0, 0, 0, levels, 0
+        while True:
+            info = ctx.mm_tb_step(Q)
+            pts += 1
+            faces += info["active_faces"]
+            cells += info["active_cells"]
+            b0, hi = min(b0, info["min_bin"]), max(hi, info["max_bin"])
+            if info["next_tick"] >= 1 << levels:
+                return pts, faces, cells, b0, hi
+    while True:
+        try:
+            cycle(Q0.clone())
+            break
+        except mm.MMError as e:
+            if e.status != mm.MM_E_RANGE or levels >= 30:
+                raise
+            levels += 1
+    Q = Q0.clone()
+    torch.cuda.synchronize()
+    tot0 = Q.sum(dim=1)
+    t = time.perf_counter()
+    pts, faces, cells, b0, hi = cycle(Q)
+    torch.cuda.synchronize()
+    cycle_ms = (time.perf_counter() - t) * 1e3
+    tot1 = Q.sum(dim=1)
+    D = m.dim
+    scale = torch.abs(tot0).clone()
+    scale[1:1 + D] = torch.sqrt(torch.sum(Q[1:1 + D] ** 2, dim=0)).sum()
+    cons = (torch.abs(tot1 - tot0) / scale).cpu().numpy()
+    glob_steps = 1 << (levels - b0)
+    glob_ms = glob_steps * step_ms
+    return {"form": form, "levels": levels, "dt_max": dt_max, "dt_courant": dt_courant,
+            "smallest_bin": b0, "largest_bin": hi, "points_per_cycle": pts, "cycle_ms": cycle_ms,
+            "ms_per_point": cycle_ms / pts, "face_fluxes_per_cycle": faces, "cell_openings_per_cycle": cells,
+            "global_at_smallest_bin": {"steps": glob_steps, "face_fluxes": glob_steps * m.n_faces,
+                                       "ms_estimated": glob_ms},
+            "flux_ratio_vs_global_at_smallest_bin": glob_steps * m.n_faces / faces,
+            "speedup_vs_global_at_smallest_bin": glob_ms / cycle_ms,
+            "time_per_simulated_time_vs_courant_global": (cycle_ms / dt_max) / (step_ms / dt_courant),
+            "conservation_rel_change": [float(x) for x in cons]}
+
+
 def newton_summary(d):
     return {"iters_mean": d["newton_iters"] / max(1, d["faces"]),
             "wave_max_mean": d["wave_iter_max_sum"] / max(1, d["waves"]), "max": d["newton_max"],
@@ -267,6 +327,12 @@ def bench_step(args):
     if not args.no_entropy:
         out["mesh_motion"] = time_mesh_motion(mm, torch, wl, dmesh, args.steps, dev)
         log(f"mesh motion: {out['mesh_motion']}")
+    if not args.no_individual:
+        ind = time_individual(mm, learned, torch, wl, dmesh, args.mode, head["dt"], head["ms"], dev)
+        out["individual_timesteps"] = ind
+        log(f"individual timesteps: {ind['points_per_cycle']} points, {ind['cycle_ms']:.2f} ms per cycle of "
+            f"{2 ** ind['levels']} ticks; {ind['flux_ratio_vs_global_at_smallest_bin']:.1f}x fewer fluxes than a "
+            f"global step at the smallest bin")
     if not args.no_cpu_baseline:
         from oracle import oracle as O
         log("cpu baseline: oracle hydro step on the full workload (1 thread)")
@@ -349,6 +415,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-entropy", action="store_true", help="skip the run with the entropy scheme for cold flows")
     ap.add_argument("--mach-thresh", type=float, default=1.1, help="Mach switch of the entropy scheme")
+    ap.add_argument("--no-individual", action="store_true", help="skip the individual-timestep cycle")
     ap.add_argument("--threads", type=int, default=0, help="host threads for the mesh builder")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MB")
     args = ap.parse_args()

@@ -363,6 +363,10 @@ typedef struct {
     int64_t active_faces;  /* faces integrated at tick */
     int32_t min_bin;       /* occupied bins after the point */
     int32_t max_bin;
+    int32_t sparse;        /* 1: the point found its faces from the active cells'
+                              side lists (at most 1/8 of the cells due); 0: it
+                              scanned every face. Same results either way. */
+    int32_t reserved;
     double next_time;      /* next_tick dt_max / 2^levels */
 } mm_tb_info;
 

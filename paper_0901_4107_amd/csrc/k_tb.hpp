@@ -10,13 +10,18 @@
 //   k_tb_bins    active list  neighbour signal-speed criterion and the bin
 //                             rules; occupancy counts per bin
 //   (gradients of the active cells)
-//   k_tb_faces   per face     a face is active when the smaller step of its
-//                             cells starts now: split list, and both cells
-//                             stamped as touched
+//   k_tb_faces   per face     (dense points) a face is active when the
+//                             smaller step of its cells starts now: split
+//                             list, and both cells stamped as touched
+//   k_tb_claim   lane group   (sparse points) the same faces from the
+//                per active   active cells' side lists (every face of an
+//                cell         active cell is active), and a list of the
+//                             touched cells
 //   (fluxes of the active faces, each over its own step)
 //   k_tb_update  lane group   touched cells add the signed, time-integrated
-//                per cell     fluxes of their active faces
-//   k_tb_finish  one block    list sizes for the host
+//                per cell     fluxes of their active faces (all cells with
+//                             a stamp check, or the touched list)
+//   k_tb_finish  one block    list sizes and the non-finite flag for the host
 #pragma once
 
 #include "common.hpp"
@@ -27,9 +32,42 @@ namespace mm {
 
 constexpr int kTbMaxLevels = 30;
 // Slots of the point's small info block (int32).
-enum : int { TB_ERR = 0, TB_CELLS = 1, TB_FACES = 2, TB_COUNTS = 8, TB_INFO_INTS = 64 };
+enum : int { TB_ERR = 0, TB_CELLS = 1, TB_FACES = 2, TB_NONFIN = 3, TB_COUNTS = 8, TB_INFO_INTS = 64 };
 
 __device__ __forceinline__ bool tb_starts(int64_t ti, int b) { return (ti & ((int64_t(1) << b) - 1)) == 0; }
+
+// Start of a point: the counters of up to four split lists (null ones
+// skipped), the error slot and the point's non-finite flag.
+__global__ void __launch_bounds__(kBlock) k_tb_reset(int32_t *l0, int32_t *l1, int32_t *l2, int32_t *l3,
+                                                     int32_t *info, int32_t *step_flag) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t < kLists) {
+        if (l0) l0[t * kListPad] = 0;
+        if (l1) l1[t * kListPad] = 0;
+        if (l2) l2[t * kListPad] = 0;
+        if (l3) l3[t * kListPad] = 0;
+    }
+    if (t == 0) {
+        info[TB_ERR] = 0;
+        *step_flag = 0;
+    }
+}
+
+// Per residue class of the per-cell grid (the cells whose k_tb_open block
+// appends to active sub-list c), the sum of the cells' side counts and the
+// number of cells: bounds on what the sparse path appends to face and
+// touched sub-list c.
+__global__ void __launch_bounds__(kBlock) k_tb_bound(int64_t n, unsigned grid, const int32_t *__restrict__ off,
+                                                     int32_t *__restrict__ sides, int32_t *__restrict__ cells) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    // the block b of a grid of `grid` blocks whose xcd_tile() is i's tile
+    const int64_t t = i / kBlock, per = grid / kXcd;
+    const int64_t b = (t % per) * kXcd + t / per;
+    const int c = (int)(b % kLists);
+    atomicAdd(sides + c, off[i + 1] - off[i]);
+    atomicAdd(cells + c, 1);
+}
 
 // A fresh timeline: every cell in the top bin with its step starting at
 // tick 0 (so every cell is active at the first point), no cell touched.
@@ -83,11 +121,12 @@ __global__ void __launch_bounds__(kBlock) k_tb_open(int64_t n, int64_t ti, const
 // the Voronoi neighbours):
 //   dt_i = C min(tau_i, R_i / (c_i + |v_i - w_i|)),
 //   tau_i = min over faces of |d| / v_sig, v_sig = c_L + c_R - (v_R - v_L).n
-// (a face with v_sig <= 0 sets no bound). The bin is the largest b <= levels
-// with dt_max 2^(b - levels) <= dt_i; the cell takes it if it is not above
-// its old bin, else moves up one bin where that bin starts a step at ti, else
-// keeps its bin. A criterion below one tick raises info[TB_ERR] and leaves the
-// bin. Occupancy changes are gathered per block in LDS and added to the
+// (a face with v_sig <= 0 sets no bound), by a lane group per cell walking
+// the cell's sides. The bin is the largest b <= levels with
+// dt_max 2^(b - levels) <= dt_i; the cell takes it if it is not above its
+// old bin, else moves up one bin where that bin starts a step at ti, else
+// keeps its bin. A criterion below one tick raises info[TB_ERR] and leaves
+// the bin. Occupancy changes are gathered per block in LDS and added to the
 // counts once per block and bin.
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_tb_bins(const int32_t *__restrict__ list, int64_t cap, int64_t ti,
@@ -98,31 +137,38 @@ __global__ void __launch_bounds__(kBlock) k_tb_bins(const int32_t *__restrict__ 
                                                     int32_t *__restrict__ info) {
     using Y = Lay<D>;
     constexpr int SG = D + 2;
+    constexpr int GS = Group<D>::GS, G = kBlock / GS;
     __shared__ int32_t delta[kTbMaxLevels + 2];
     if (threadIdx.x < kTbMaxLevels + 2) delta[threadIdx.x] = 0;
     __syncthreads();
-    const ListWalk lw = list_walk(list, cap);
+    const int lane = threadIdx.x % GS;
+    const int c = blockIdx.x % kLists;
+    const int32_t *items = list + (int64_t)kLists * kListPad + c * cap;
+    const int64_t count = list[c * kListPad];
+    const int64_t stride = (int64_t)(gridDim.x / kLists) * G;
     const double tick = ldexp(dt_max, -levels);
-    for (int64_t q = lw.start; q < lw.count; q += lw.stride) {
-        const int64_t i = lw.items[q];
+    for (int64_t q = (int64_t)(blockIdx.x / kLists) * G + threadIdx.x / GS; q < count; q += stride) {
+        const int64_t i = items[q];
         double si[SG];
         load_rec<SG>(sig + i * SG, si);
         double tau = INFINITY;
-        for (int32_t e = off[i]; e < off[i + 1]; e++) {
+        for (int32_t e = off[i] + lane; e < off[i + 1]; e += GS) {
             const int32_t en = ent[e];
             const int64_t f = en >> 1, j = nbr[e];
             const bool i_right = en & 1;
-            double sj[SG];
+            double sj[SG], fr[1 + D];
             load_rec<SG>(sig + j * SG, sj);
-            const double *fr = frec + f * Y::FREC;
+            load_rec<1 + D>(frec + f * Y::FREC + Y::FELL, fr);   // |d|, n
             double du = 0.0;
             for (int k = 0; k < D; k++) {
                 const double vR = i_right ? si[1 + k] : sj[1 + k], vL = i_right ? sj[1 + k] : si[1 + k];
-                du += (vR - vL) * fr[Y::FN + k];
+                du += (vR - vL) * fr[1 + k];
             }
             const double vsig = (si[0] + sj[0]) - du;
-            if (vsig > 0.0) tau = fmin(tau, fr[Y::FELL] / vsig);
+            if (vsig > 0.0) tau = fmin(tau, fr[0] / vsig);
         }
+        tau = grp_min<GS>(tau);
+        if (lane != 0) continue;
         const double dti = cfl * fmin(tau, si[D + 1]);
         if (!(dti >= tick)) {
             atomicOr(info + TB_ERR, 1);
@@ -167,23 +213,63 @@ __global__ void __launch_bounds__(kBlock) k_tb_faces(int64_t nf, const int32_t *
     list_append(list, cap, act, (int32_t)f);
 }
 
-// The update of the touched cells: Q_i gains the signed time-integrated
-// fluxes of its active faces (the same lane-group sums, in the same order, as
-// the global update, inactive faces adding nothing). A non-finite result
-// raises flags[0] and flags[1] like the global update.
+// Sparse points: the active faces from the active cells' side lists (every
+// face of an active cell is active, since its smaller step divides the
+// active cell's). A face is listed by its active cell if the other cell is
+// inactive, else by its left cell. The active cells and the inactive
+// neighbours (once each, by the stamp exchanged to cur) go to the touched
+// list. A lane group per cell; the append rounds are wave-uniform.
 template <int D>
-__global__ void __launch_bounds__(kBlock) k_tb_update(int64_t n, const int32_t *__restrict__ off,
-                                                      const int32_t *__restrict__ ent,
-                                                      const int32_t *__restrict__ nbr, const int8_t *__restrict__ bin,
-                                                      int64_t ti, const int32_t *__restrict__ touch, int32_t cur,
-                                                      const double *__restrict__ flux, double *__restrict__ Q,
-                                                      int32_t *__restrict__ flags) {
+__global__ void __launch_bounds__(kBlock) k_tb_claim(const int32_t *__restrict__ list, int64_t cap, int64_t ti,
+                                                     const int32_t *__restrict__ off, const int32_t *__restrict__ ent,
+                                                     const int32_t *__restrict__ nbr, const int8_t *__restrict__ bin,
+                                                     const int32_t *__restrict__ info, int32_t *__restrict__ touch,
+                                                     int32_t cur, int32_t *__restrict__ faces, int64_t fcap,
+                                                     int32_t *__restrict__ touched, int64_t tcap) {
+    constexpr int GS = Group<D>::GS, G = kBlock / GS;
+    const int lane = threadIdx.x % GS;
+    const int c = blockIdx.x % kLists;
+    const int32_t *items = list + (int64_t)kLists * kListPad + c * cap;
+    const int64_t count = info[TB_ERR] ? 0 : list[c * kListPad];
+    const int64_t stride = (int64_t)(gridDim.x / kLists) * G;
+    for (int64_t base = (int64_t)(blockIdx.x / kLists) * G; base < count; base += stride) {
+        const int64_t q = base + threadIdx.x / GS;
+        const bool live = q < count;
+        const int64_t i = live ? items[q] : 0;
+        int32_t e = live ? off[i] + lane : 0;
+        const int32_t e1 = live ? off[i + 1] : 0;
+        list_append(touched, tcap, live && lane == 0, (int32_t)i);
+        while (__any(e < e1)) {
+            bool claim = false, fresh = false;
+            int32_t f = 0, j = 0;
+            if (e < e1) {
+                const int32_t en = ent[e];
+                f = en >> 1;
+                j = nbr[e];
+                const bool j_active = tb_starts(ti, bin[j]);
+                claim = !j_active || !(en & 1);
+                if (!j_active && touch[j] != cur) fresh = atomicExch(touch + j, cur) != cur;
+            }
+            list_append(faces, fcap, claim, f);
+            list_append(touched, tcap, fresh, j);
+            e += GS;
+        }
+    }
+}
+
+// The update of a touched cell i by its lane group: Q_i gains the signed
+// time-integrated fluxes of its active faces (the same lane-group sums, in
+// the same order, as the global update, inactive faces adding nothing). A
+// non-finite result raises flags[0] and flags[1] like the global update.
+template <int D>
+__device__ __forceinline__ void tb_update_cell(int64_t i, int lane, int64_t n, const int32_t *__restrict__ off,
+                                               const int32_t *__restrict__ ent, const int32_t *__restrict__ nbr,
+                                               const int8_t *__restrict__ bin, int64_t ti,
+                                               const double *__restrict__ flux, double *__restrict__ Q,
+                                               int32_t *__restrict__ flags) {
     constexpr int NV = D + 2;
     constexpr int GS = Group<D>::GS;
     constexpr int KR = 5;
-    const int lane = threadIdx.x % GS;
-    const int64_t i = xcd_tile() * (kBlock / GS) + threadIdx.x / GS;
-    if (i >= n || touch[i] != cur) return;   // whole groups leave together
     const int bi = bin[i];
     double acc[NV];
     for (int c = 0; c < NV; c++) acc[c] = 0.0;
@@ -228,9 +314,44 @@ __global__ void __launch_bounds__(kBlock) k_tb_update(int64_t n, const int32_t *
     }
 }
 
-// Sizes of the point's two split lists into info[TB_CELLS], info[TB_FACES].
+// Dense points: every cell, those not stamped cur leaving at once.
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_tb_update(int64_t n, const int32_t *__restrict__ off,
+                                                      const int32_t *__restrict__ ent,
+                                                      const int32_t *__restrict__ nbr, const int8_t *__restrict__ bin,
+                                                      int64_t ti, const int32_t *__restrict__ touch, int32_t cur,
+                                                      const double *__restrict__ flux, double *__restrict__ Q,
+                                                      int32_t *__restrict__ flags) {
+    constexpr int GS = Group<D>::GS;
+    const int64_t i = xcd_tile() * (kBlock / GS) + threadIdx.x / GS;
+    if (i >= n || touch[i] != cur) return;   // whole groups leave together
+    tb_update_cell<D>(i, threadIdx.x % GS, n, off, ent, nbr, bin, ti, flux, Q, flags);
+}
+
+// Sparse points: the cells of the touched list.
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_tb_update_list(const int32_t *__restrict__ list, int64_t cap, int64_t n,
+                                                           const int32_t *__restrict__ off,
+                                                           const int32_t *__restrict__ ent,
+                                                           const int32_t *__restrict__ nbr,
+                                                           const int8_t *__restrict__ bin, int64_t ti,
+                                                           const double *__restrict__ flux, double *__restrict__ Q,
+                                                           int32_t *__restrict__ flags) {
+    constexpr int GS = Group<D>::GS, G = kBlock / GS;
+    const int c = blockIdx.x % kLists;
+    const int32_t *items = list + (int64_t)kLists * kListPad + c * cap;
+    const int64_t count = list[c * kListPad];
+    const int64_t stride = (int64_t)(gridDim.x / kLists) * G;
+    for (int64_t q = (int64_t)(blockIdx.x / kLists) * G + threadIdx.x / GS; q < count; q += stride)
+        tb_update_cell<D>(items[q], threadIdx.x % GS, n, off, ent, nbr, bin, ti, flux, Q, flags);
+}
+
+// Sizes of the point's two split lists into info[TB_CELLS], info[TB_FACES],
+// and the point's non-finite flag into info[TB_NONFIN].
 __global__ void __launch_bounds__(kBlock) k_tb_finish(const int32_t *__restrict__ cells,
-                                                      const int32_t *__restrict__ faces, int32_t *__restrict__ info) {
+                                                      const int32_t *__restrict__ faces,
+                                                      const int32_t *__restrict__ step_flag,
+                                                      int32_t *__restrict__ info) {
     __shared__ int32_t red[2][kBlock / 64];
     int32_t a = 0, b = 0;
     for (int c = threadIdx.x; c < kLists; c += kBlock) {
@@ -253,6 +374,7 @@ __global__ void __launch_bounds__(kBlock) k_tb_finish(const int32_t *__restrict_
         }
         info[TB_CELLS] = a;
         info[TB_FACES] = b;
+        info[TB_NONFIN] = *step_flag;
     }
 }
 

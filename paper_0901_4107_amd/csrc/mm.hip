@@ -32,11 +32,27 @@ namespace {
 
 inline int64_t align256(int64_t x) { return (x + 255) / 256 * 256; }
 
+// Sub-list capacities of an individual-timestep context. The active-face
+// list takes what either path appends to one sub-list: the face scan of
+// dense points (list_cap of its grid) or, on sparse points, the sides of
+// the cells that reach one active sub-list, estimated as 1.25 times their
+// mean count plus 1024 (mm_tb_begin checks the exact sums and keeps to the
+// dense path where they do not fit). The touched list also takes those
+// cells themselves.
+inline int64_t tb_cells_per_residue(int64_t n) { return (grid_for(n) + kLists - 1) / kLists * kBlock; }
+inline int64_t tb_face_cap(int64_t n, int64_t nf) {
+    const int64_t sparse = (int64_t)(1.25 * (2.0 * (double)nf / (double)n) * (double)tb_cells_per_residue(n)) + 1024;
+    const int64_t dense = list_cap(grid_for(nf));
+    return sparse > dense ? sparse : dense;
+}
+inline int64_t tb_touch_cap(int64_t n, int64_t nf) { return tb_face_cap(n, nf) + tb_cells_per_residue(n); }
+inline int64_t split_ints(int64_t cap) { return (int64_t)kLists * kListPad + kLists * cap; }
+
 struct Layout {
     int64_t flags, diag, mlp, dtdev, bhard, dtpart, bsum, off, cursor, ent, nbr;
     int64_t srec, frec, rec, flux;          // double path (frec always)
     int64_t srec32, mrec, wf64, rec32, hard; // mixed path
-    int64_t tb_bin, tb_trec, tb_sig, tb_touch, tb_cells, tb_faces, tb_info;   // individual timesteps
+    int64_t tb_bin, tb_trec, tb_sig, tb_touch, tb_cells, tb_faces, tb_touched, tb_info;   // individual timesteps
     int64_t total;
 };
 
@@ -73,16 +89,18 @@ Layout make_layout(int D, int mode, bool ent, bool tb, int64_t n, int64_t nf) {
         L.mrec = take(nf * Lay<3>::MREC * sizeof(float));
         L.wf64 = take(nf * WS * sizeof(double));
         L.rec32 = take(n * REC * sizeof(float));
-        L.hard = take(list_ints(grid_for(nf)) * sizeof(int32_t));
+        // with individual timesteps the hard faces of one face sub-list
+        L.hard = take((tb ? split_ints(tb_face_cap(n, nf)) : list_ints(grid_for(nf))) * sizeof(int32_t));
     }
-    L.tb_bin = L.tb_trec = L.tb_sig = L.tb_touch = L.tb_cells = L.tb_faces = L.tb_info = -1;
+    L.tb_bin = L.tb_trec = L.tb_sig = L.tb_touch = L.tb_cells = L.tb_faces = L.tb_touched = L.tb_info = -1;
     if (tb) {
         L.tb_bin = take(n);
         L.tb_trec = take(n * sizeof(int64_t));
         L.tb_sig = take(n * (D + 2) * sizeof(double));
         L.tb_touch = take(n * sizeof(int32_t));
         L.tb_cells = take(list_ints(grid_for(n)) * sizeof(int32_t));
-        L.tb_faces = take(list_ints(grid_for(nf)) * sizeof(int32_t));
+        L.tb_faces = take(split_ints(tb_face_cap(n, nf)) * sizeof(int32_t));
+        L.tb_touched = take(split_ints(tb_touch_cap(n, nf)) * sizeof(int32_t));
         L.tb_info = take(TB_INFO_INTS * sizeof(int32_t));
     }
     L.total = o;
@@ -111,7 +129,9 @@ struct mm_ctx {
         double dt_max = 0.0;
         int32_t levels = 0;
         int64_t ti = 0;
-        int32_t cur = 0;   // stamp of the current point
+        int32_t cur = 0;          // stamp of the current point
+        bool sparse_ok = false;   // the sparse path's appends fit the sub-lists
+        int32_t counts[kTbMaxLevels + 1] = {};   // cells per bin after the last point
     } tb;
     Layout lay;
     hipStream_t st() const { return (hipStream_t)p.stream; }
@@ -682,6 +702,22 @@ mm_status mm_tb_begin(mm_ctx *c, double dt_max, int32_t levels) {
     if (!(dt_max > 0.0) || !isfinite(dt_max) || levels < 0 || levels > kTbMaxLevels) return MM_E_ARG;
     if (!c->have_mesh) return MM_E_STATE;
     const Layout &L = c->lay;
+    // exact per-residue sums for the sparse path's sub-lists (the info block
+    // is reused as scratch before k_tb_init fills it)
+    int32_t *scratch = c->at<int32_t>(L.tb_touched);
+    k_fill_i32<<<plain_grid(2 * kLists), kBlock, 0, c->st()>>>(scratch, 2 * kLists, 0);
+    k_tb_bound<<<plain_grid(c->n), kBlock, 0, c->st()>>>(c->n, grid_for(c->n), c->at<int32_t>(L.off), scratch,
+                                                        scratch + kLists);
+    MM_LAUNCH_CHECK();
+    int32_t sums[2 * kLists];
+    MM_CHECK(hipMemcpyAsync(sums, scratch, sizeof(sums), hipMemcpyDeviceToHost, c->st()));
+    MM_CHECK(hipStreamSynchronize(c->st()));
+    int64_t ms = 0, mt = 0;
+    for (int k = 0; k < kLists; k++) {
+        ms = sums[k] > ms ? sums[k] : ms;
+        mt = (int64_t)sums[k] + sums[kLists + k] > mt ? (int64_t)sums[k] + sums[kLists + k] : mt;
+    }
+    c->tb.sparse_ok = ms <= tb_face_cap(c->n, c->nf) && mt <= tb_touch_cap(c->n, c->nf);
     k_tb_init<<<plain_grid(c->n > TB_INFO_INTS ? c->n : TB_INFO_INTS), kBlock, 0, c->st()>>>(
         c->n, levels, c->at<int8_t>(L.tb_bin), c->at<int64_t>(L.tb_trec), c->at<int32_t>(L.tb_touch),
         c->at<int32_t>(L.tb_info));
@@ -691,10 +727,15 @@ mm_status mm_tb_begin(mm_ctx *c, double dt_max, int32_t levels) {
     c->tb.levels = levels;
     c->tb.ti = 0;
     c->tb.cur = 0;
+    for (int b = 0; b <= kTbMaxLevels; b++) c->tb.counts[b] = b == levels ? (int32_t)c->n : 0;
     return MM_OK;
 }
 
-template <int D, typename T> static void tb_point(mm_ctx *c, double *Q, T *rec) {
+// One synchronisation point. Sparse points (at most 1/8 of the cells due,
+// known from the bin counts of the previous point) find their faces and
+// touched cells from the active cells' side lists; dense points scan every
+// face and update every stamped cell. Both give the same fluxes and sums.
+template <int D, typename T> static bool tb_point(mm_ctx *c, double *Q, T *rec) {
     const Layout &L = c->lay;
     hipStream_t s = c->st();
     mm_ctx::Timeline &tb = c->tb;
@@ -703,18 +744,21 @@ template <int D, typename T> static void tb_point(mm_ctx *c, double *Q, T *rec) 
     double *sig = c->at<double>(L.tb_sig);
     int32_t *touch = c->at<int32_t>(L.tb_touch);
     int32_t *cells = c->at<int32_t>(L.tb_cells), *faces = c->at<int32_t>(L.tb_faces);
+    int32_t *touched = c->at<int32_t>(L.tb_touched);
     int32_t *info = c->at<int32_t>(L.tb_info);
     int32_t *flags = c->at<int32_t>(L.flags);
-    const int64_t ccap = list_cap(grid_for(c->n)), fcap = list_cap(grid_for(c->nf));
+    const int64_t ccap = list_cap(grid_for(c->n)), fcap = tb_face_cap(c->n, c->nf);
+    const int64_t tcap = tb_touch_cap(c->n, c->nf);
     const bool mixed = c->p.mode == MM_MIXED;
+    int64_t due = 0;
+    for (int b = 0; b <= tb.levels; b++)
+        if ((tb.ti & ((int64_t(1) << b) - 1)) == 0) due += tb.counts[b];
+    const bool sparse = tb.sparse_ok && 8 * due <= c->n;
     const T *srec = mixed ? (const T *)c->at<float>(L.srec32) : (const T *)c->at<double>(L.srec);
     T *grad = grad_block<D>(c, rec);
+    int32_t *hard = mixed ? c->at<int32_t>(L.hard) : nullptr;
     const unsigned lg = kHardGrid;   // list-walking grids: a multiple of kLists
-    // per point: both list headers, the error slot and the step's non-finite flag
-    k_fill_i32<<<kLists * kListPad / kBlock, kBlock, 0, s>>>(cells, kLists * kListPad, 0);
-    k_fill_i32<<<kLists * kListPad / kBlock, kBlock, 0, s>>>(faces, kLists * kListPad, 0);
-    k_fill_i32<<<1, kBlock, 0, s>>>(info + TB_ERR, 1, 0);
-    k_fill_i32<<<1, kBlock, 0, s>>>(flags + 2, 1, 0);
+    k_tb_reset<<<1, kBlock, 0, s>>>(cells, faces, touched, hard, info, flags + 2);
     k_tb_open<D, T><<<grid_for(c->n), kBlock, 0, s>>>(c->n, tb.ti, bin, trec, c->p.gamma, c->mesh.volume, Q,
                                                       c->mesh.mesh_vel, c->mesh.centroid_off, rec, sig, cells, ccap);
     k_tb_bins<D><<<lg, kBlock, 0, s>>>(cells, ccap, tb.ti, tb.dt_max, tb.levels, c->p.cfl, c->at<int32_t>(L.off),
@@ -722,8 +766,13 @@ template <int D, typename T> static void tb_point(mm_ctx *c, double *Q, T *rec) 
                                        info);
     k_grad_limit_list<D, T><<<lg, kBlock, 0, s>>>(cells, ccap, c->at<int32_t>(L.off), c->at<int32_t>(L.nbr), srec,
                                                   c->mesh.volume, rec, grad);
-    k_tb_faces<<<grid_for(c->nf), kBlock, 0, s>>>(c->nf, c->mesh.face_L, c->mesh.face_R, bin, tb.ti, info, touch,
-                                                  tb.cur, faces, fcap);
+    if (sparse)
+        k_tb_claim<D><<<lg, kBlock, 0, s>>>(cells, ccap, tb.ti, c->at<int32_t>(L.off), c->at<int32_t>(L.ent),
+                                            c->at<int32_t>(L.nbr), bin, info, touch, tb.cur, faces, fcap, touched,
+                                            tcap);
+    else
+        k_tb_faces<<<grid_for(c->nf), kBlock, 0, s>>>(c->nf, c->mesh.face_L, c->mesh.face_R, bin, tb.ti, info,
+                                                      touch, tb.cur, faces, fcap);
     const TbView view{bin, trec, tb.ti, tb.dt_max, tb.levels};
     DiagDev *diag = c->at<DiagDev>(L.diag);
     const MlpPacked *mlp = active_mlp(c);
@@ -736,8 +785,6 @@ template <int D, typename T> static void tb_point(mm_ctx *c, double *Q, T *rec) 
                                    c->p.newton_max_iter, mlp, flux, diag);
     } else {
         const GasConst<float> kf(c->p.gamma);
-        int32_t *hard = c->at<int32_t>(L.hard);
-        k_fill_i32<<<kLists * kListPad / kBlock, kBlock, 0, s>>>(hard, kLists * kListPad, 0);
         auto kern = mlp ? k_face_flux_mixed_list<D, true> : k_face_flux_mixed_list<D, false>;
         kern<<<lg, kBlock, 0, s>>>(faces, fcap, c->mesh.face_L, c->mesh.face_R, c->at<float>(L.mrec),
                                    c->at<double>(L.wf64), (const float *)rec, (const float *)grad, view, kf,
@@ -748,10 +795,15 @@ template <int D, typename T> static void tb_point(mm_ctx *c, double *Q, T *rec) 
             (const float *)grad, nullptr, 0.0, kf.g, kg, c->p.newton_tol64, hard, fcap, flux, diag, nullptr, c->n,
             view);
     }
-    k_tb_update<D><<<group_grid(D, c->n), kBlock, 0, s>>>(c->n, c->at<int32_t>(L.off), c->at<int32_t>(L.ent),
-                                                           c->at<int32_t>(L.nbr), bin, tb.ti, touch, tb.cur, flux, Q,
-                                                           flags + 1);
-    k_tb_finish<<<1, kBlock, 0, s>>>(cells, faces, info);
+    if (sparse)
+        k_tb_update_list<D><<<lg, kBlock, 0, s>>>(touched, tcap, c->n, c->at<int32_t>(L.off), c->at<int32_t>(L.ent),
+                                                  c->at<int32_t>(L.nbr), bin, tb.ti, flux, Q, flags + 1);
+    else
+        k_tb_update<D><<<group_grid(D, c->n), kBlock, 0, s>>>(c->n, c->at<int32_t>(L.off), c->at<int32_t>(L.ent),
+                                                               c->at<int32_t>(L.nbr), bin, tb.ti, touch, tb.cur,
+                                                               flux, Q, flags + 1);
+    k_tb_finish<<<1, kBlock, 0, s>>>(cells, faces, flags + 2, info);
+    return sparse;
 }
 
 mm_status mm_tb_step(mm_ctx *c, double *Q, mm_tb_info *out) {
@@ -761,19 +813,21 @@ mm_status mm_tb_step(mm_ctx *c, double *Q, mm_tb_info *out) {
     hipStream_t s = c->st();
     const bool f64 = c->p.mode == MM_FP64;
     void *rec = f64 ? (void *)c->at<double>(L.rec) : (void *)c->at<float>(L.rec32);
-    if (c->D == 3) f64 ? tb_point<3, double>(c, Q, (double *)rec) : tb_point<3, float>(c, Q, (float *)rec);
-    else f64 ? tb_point<2, double>(c, Q, (double *)rec) : tb_point<2, float>(c, Q, (float *)rec);
+    const bool sparse = c->D == 3
+        ? (f64 ? tb_point<3, double>(c, Q, (double *)rec) : tb_point<3, float>(c, Q, (float *)rec))
+        : (f64 ? tb_point<2, double>(c, Q, (double *)rec) : tb_point<2, float>(c, Q, (float *)rec));
     MM_LAUNCH_CHECK();
-    int32_t info[TB_INFO_INTS], nonfin = 0;
+    int32_t info[TB_INFO_INTS];
     MM_CHECK(hipMemcpyAsync(info, c->at<int32_t>(L.tb_info), sizeof(info), hipMemcpyDeviceToHost, s));
-    MM_CHECK(hipMemcpyAsync(&nonfin, c->at<int32_t>(L.flags) + 2, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     MM_CHECK(hipStreamSynchronize(s));
+    const int32_t nonfin = info[TB_NONFIN];
     mm_ctx::Timeline &tb = c->tb;
     if (info[TB_ERR]) {
         tb.on = false;   // bins and records of the active cells have moved on; Q has not
         return MM_E_RANGE;
     }
     int lo = -1, hi = -1;
+    for (int b = 0; b <= tb.levels; b++) tb.counts[b] = info[TB_COUNTS + b];
     for (int b = 0; b <= tb.levels; b++)
         if (info[TB_COUNTS + b] > 0) {
             if (lo < 0) lo = b;
@@ -790,6 +844,8 @@ mm_status mm_tb_step(mm_ctx *c, double *Q, mm_tb_info *out) {
         out->active_faces = info[TB_FACES];
         out->min_bin = lo;
         out->max_bin = hi;
+        out->sparse = sparse ? 1 : 0;
+        out->reserved = 0;
         out->next_time = ldexp(tb.dt_max, -tb.levels) * (double)next;
     }
     tb.ti = next;

@@ -50,7 +50,7 @@ class mm_diag(ctypes.Structure):
 class mm_tb_info(ctypes.Structure):
     _fields_ = [("tick", ctypes.c_int64), ("next_tick", ctypes.c_int64), ("active_cells", ctypes.c_int64),
                 ("active_faces", ctypes.c_int64), ("min_bin", ctypes.c_int32), ("max_bin", ctypes.c_int32),
-                ("next_time", ctypes.c_double)]
+                ("sparse", ctypes.c_int32), ("reserved", ctypes.c_int32), ("next_time", ctypes.c_double)]
 
 
 class MMError(RuntimeError):
@@ -281,10 +281,10 @@ class Context:
     def mm_tb_step(self, Q: torch.Tensor) -> dict:
         """One synchronisation point on Q in place; returns the point's
         summary (tick, next_tick, active_cells, active_faces, min_bin,
-        max_bin, next_time)."""
+        max_bin, sparse, next_time)."""
         info = mm_tb_info()
         _check("mm_tb_step", lib().mm_tb_step(self._ctx, _ptr(Q), ctypes.byref(info)))
-        return {name: getattr(info, name) for name, _ in mm_tb_info._fields_}
+        return {name: getattr(info, name) for name, _ in mm_tb_info._fields_ if name != "reserved"}
 
     def mm_tb_state(self, bins: torch.Tensor | None = None, trec: torch.Tensor | None = None):
         """Copies of the bins (int8 [N]) and step start ticks (int64 [N])."""

@@ -4,7 +4,8 @@ configuration bench.py times, through the C ABI:
 - the boosted 3D Kelvin-Helmholtz step on 128^3 Poisson points
   (16.3M faces): the double path element by element against the oracle's
   whole step, the mixed + learned form within the stated rest-frame L1;
-  the same with the entropy scheme for cold flows;
+  the same with the entropy scheme for cold flows, and the first points of
+  an individual-timestep timeline;
 - the 2^24-problem Riemann batch: a seeded sample of 2^17 problems solved
   one by one by the oracle against the double and the mixed + learned
   batches, every output of the batch finite, the learned guess's iteration
@@ -129,6 +130,57 @@ def test_kh3d_128_entropy(kh3d_128):
     assert np.all(l1 <= L1_BOUND), l1
     assert l1s <= L1_BOUND
     assert np.all(np.isfinite(Qm))
+
+
+def test_kh3d_128_individual_steps(kh3d_128):
+    """The headline workload on individual power-of-two timesteps, in the
+    configuration the benchmark times (dt_max four Courant steps, the fewest
+    levels whose smallest step fits every criterion): the first three
+    synchronisation points (the first opens every cell) against the oracle's
+    timeline, the double path element by element with the same ticks,
+    counts, bins and step starts, mixed + learned within the stated
+    rest-frame L1 with the same bins."""
+    wl = kh3d_128
+    m, g = wl.mesh, wl.gamma
+    W = O.prim(3, g, m.volume, wl.Q)
+    dmin = O.tb_criterion(m, g, wl.cfl, W).min()
+    dt_max = 4.0 * O.cfl_dt(m, g, wl.cfl, W)
+    levels = 6
+    while np.ldexp(dt_max, -levels) > dmin:
+        levels += 1
+    tl = O.Timeline(m, g, wl.cfl, dt_max, levels)
+    ctxs = {}
+    for name, mode, guess in (("double", mm.MM_FP64, mm.MM_GUESS_STANDARD),
+                              ("mixed+learned", mm.MM_MIXED, mm.MM_GUESS_LEARNED)):
+        ctx = mm.Context(3, g, wl.cfl, mode=mode, guess=guess, steps=mm.MM_STEPS_INDIVIDUAL)
+        if guess == mm.MM_GUESS_LEARNED:
+            ctx.mm_mlp_load(learned.load(g))
+        ctx.mm_mesh_upload(mm.DeviceMesh.from_host(m))
+        ctx.mm_tb_begin(dt_max, levels)
+        ctxs[name] = (ctx, torch.from_numpy(np.ascontiguousarray(wl.Q)).cuda())
+    Qo = np.ascontiguousarray(wl.Q).copy()
+    bins = torch.empty(m.n_cells, dtype=torch.int8, device="cuda")
+    trec = torch.empty(m.n_cells, dtype=torch.int64, device="cuda")
+    for k in range(3):
+        note(f"individual steps, {levels} levels: oracle point {k}")
+        r = tl.step(Qo)
+        assert r["status"] == 0
+        for name, (ctx, Qd) in ctxs.items():
+            info = ctx.mm_tb_step(Qd)
+            assert info["tick"] == r["ti"] and info["next_tick"] == r["next"], (name, k, info)
+            assert info["active_cells"] == r["active"].sum() and info["active_faces"] == r["n_faces"], (name, k)
+            ctx.mm_tb_state(bins, trec)
+            assert np.array_equal(bins.cpu().numpy(), tl.bin), (name, k)
+            assert np.array_equal(trec.cpu().numpy(), tl.trec), (name, k)
+            Qg = Qd.cpu().numpy()
+            if name == "double":
+                err = normwise_rel(Qg, Qo)
+                note(f"point {k} (tick {r['ti']}, {r['n_faces']} faces): double normwise {err}")
+                assert np.all(err <= TOL64), err
+            else:
+                l1 = l1_state(boost(Qg, -wl.boost), boost(Qo, -wl.boost))
+                note(f"point {k}: mixed + learned rest-frame L1 {l1}")
+                assert np.all(l1 <= L1_BOUND), l1
 
 
 def batch(S, mode, guess, gamma):

@@ -1,9 +1,10 @@
 """Individual power-of-two timesteps (Section 7.2) through the C ABI against
 the oracle's timeline: one occupied bin equals the global step bit for bit;
-point by point over full cycles, the double path matches the oracle's ticks,
-active counts, bins and step starts exactly and its state to 1e-12; the
-mixed + learned form stays within the stated L1; and the error and state
-rules of the entry points."""
+point by point over full cycles (dense points scanning every face and
+sparse ones working from the active cells, both taken), the double path
+matches the oracle's ticks, active counts, bins and step starts exactly and
+its state to 1e-12; the mixed + learned form stays within the stated L1;
+and the error and state rules of the entry points."""
 import sys
 
 import numpy as np
@@ -121,10 +122,18 @@ def test_double_points_match_the_oracle(make, levels, spread):
         err = normwise_rel(Qd.cpu().numpy(), Qo)
         worst[0] = max(worst[0], float(err.max()))
         assert np.all(err <= TOL), (k, err)
-    points, tl, _, _, _ = run_both(wl, wl.Q, levels, spread, 2, check)
-    note(f"{wl.name}: {points} points over two cycles, bins {np.bincount(tl.bin, minlength=levels + 1)}, "
-         f"worst norm-wise error {worst[0]:.2e}")
+    sparse = [0]
+
+    def check_and_count(k, r, info, Qo, Qd, tl, ctx):
+        check(k, r, info, Qo, Qd, tl, ctx)
+        if info["sparse"]:   # taken only where at most 1/8 of the cells are due
+            assert 8 * r["active"].sum() <= n
+        sparse[0] += info["sparse"]
+    points, tl, _, _, _ = run_both(wl, wl.Q, levels, spread, 2, check_and_count)
+    note(f"{wl.name}: {points} points over two cycles ({sparse[0]} sparse), bins "
+         f"{np.bincount(tl.bin, minlength=levels + 1)}, worst norm-wise error {worst[0]:.2e}")
     assert len(np.unique(tl.bin)) >= 2
+    assert 0 < sparse[0] < points     # both paths taken
 
 
 def test_mixed_learned_cycle():
