@@ -299,22 +299,6 @@ k_grad_limit(int64_t n, const int32_t *__restrict__ off, const int32_t *__restri
     grad_cell<D, T>(i, threadIdx.x % GS, off, nbr, srec, V, prim, grad_out);
 }
 
-// The same for the cells of a split list (the active cells of an
-// individual-timestep point): each lane group walks its block's sub-list.
-template <int D, typename T>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 3)))
-k_grad_limit_list(const int32_t *__restrict__ list, int64_t cap, const int32_t *__restrict__ off,
-                  const int32_t *__restrict__ nbr, const T *__restrict__ srec, const double *__restrict__ V,
-                  const T *__restrict__ prim, T *__restrict__ grad_out) {
-    constexpr int GS = Group<D>::GS, G = kBlock / GS;
-    const int c = blockIdx.x % kLists;
-    const int32_t *items = list + (int64_t)kLists * kListPad + c * cap;
-    const int64_t count = list[c * kListPad];
-    const int64_t stride = (int64_t)(gridDim.x / kLists) * G;
-    for (int64_t q = (int64_t)(blockIdx.x / kLists) * G + threadIdx.x / GS; q < count; q += stride)
-        grad_cell<D, T>(items[q], threadIdx.x % GS, off, nbr, srec, V, prim, grad_out);
-}
-
 // Step (vii): Q_i <- Q_i - sum of the fluxes of faces where i is left
 // + sum where i is right (Section 3, discrete update), the face sums taken
 // by the cell's lane group. A non-finite result raises flags[0] (kept until

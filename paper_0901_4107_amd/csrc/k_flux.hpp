@@ -352,6 +352,7 @@ struct TbView {
     int64_t ti;
     double dt_max;
     int32_t levels;
+    const int32_t *halt;   // nonzero: a criterion failed, no face is fluxed
     // Face (l, r) is integrated over fdt = 2^min(bin_l, bin_r) ticks; each
     // side is predicted from its record to the middle of that step,
     // (ti - trec) ticks + fdt/2.
@@ -725,7 +726,7 @@ __global__ void __launch_bounds__(kBlock) k_face_flux64_list(const int32_t *__re
     constexpr int NV = D + 2;
     const int c = blockIdx.x % kLists;
     const int32_t *items = list + (int64_t)kLists * kListPad + c * cap;
-    const int64_t count = list[c * kListPad];
+    const int64_t count = *tb.halt ? 0 : list[c * kListPad];
     const int64_t stride = (int64_t)(gridDim.x / kLists) * kBlock;
     LaneDiag ld;
     for (int64_t base = (int64_t)(blockIdx.x / kLists) * kBlock; base < count; base += stride) {
@@ -756,7 +757,7 @@ k_face_flux_mixed_list(const int32_t *__restrict__ list, int64_t cap, const int3
     constexpr int NV = D + 2;
     const int c = blockIdx.x % kLists;
     const int32_t *items = list + (int64_t)kLists * kListPad + c * cap;
-    const int64_t count = list[c * kListPad];
+    const int64_t count = *tb.halt ? 0 : list[c * kListPad];
     const int64_t stride = (int64_t)(gridDim.x / kLists) * kBlock;
     LaneDiag ld;
     for (int64_t base = (int64_t)(blockIdx.x / kLists) * kBlock; base < count; base += stride) {

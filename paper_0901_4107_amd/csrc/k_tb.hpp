@@ -1,27 +1,26 @@
 // k_tb.hpp -- individual power-of-two timesteps (Section 7.2): the kernels
-// of one synchronisation point besides the gradient and flux passes, which
-// run the shared bodies over lists (k_grad_limit_list, k_face_flux*_list).
+// of one synchronisation point besides the flux passes, which run the
+// shared face bodies over lists (k_face_flux*_list).
 //
 // Time is counted in ticks of dt_max / 2^levels. A cell in bin b takes
 // steps of 2^b ticks that start at multiples of 2^b. At tick ti:
 //   k_tb_open    per cell     the cells whose step ends now become active:
 //                             primitive and signal records, trec = ti, and
 //                             a split list of them
-//   k_tb_bins    active list  neighbour signal-speed criterion and the bin
-//                             rules; occupancy counts per bin
-//   (gradients of the active cells)
+//   k_tb_active  lane group   neighbour signal-speed criterion and the bin
+//                per active   rules (occupancy counts per bin), the
+//                cell         gradient, and on sparse points the active faces
+//                             from the cell's side list (every face of an
+//                             active cell is active) and the touched cells
 //   k_tb_faces   per face     (dense points) a face is active when the
 //                             smaller step of its cells starts now: split
 //                             list, and both cells stamped as touched
-//   k_tb_claim   lane group   (sparse points) the same faces from the
-//                per active   active cells' side lists (every face of an
-//                cell         active cell is active), and a list of the
-//                             touched cells
 //   (fluxes of the active faces, each over its own step)
 //   k_tb_update  lane group   touched cells add the signed, time-integrated
 //                per cell     fluxes of their active faces (all cells with
 //                             a stamp check, or the touched list)
-//   k_tb_finish  one block    list sizes and the non-finite flag for the host
+//   k_tb_finish  one block    list sizes and the non-finite flag for the
+//                             host; clears the lists for the next point
 #pragma once
 
 #include "common.hpp"
@@ -36,8 +35,8 @@ enum : int { TB_ERR = 0, TB_CELLS = 1, TB_FACES = 2, TB_NONFIN = 3, TB_COUNTS = 
 
 __device__ __forceinline__ bool tb_starts(int64_t ti, int b) { return (ti & ((int64_t(1) << b) - 1)) == 0; }
 
-// Start of a point: the counters of up to four split lists (null ones
-// skipped), the error slot and the point's non-finite flag.
+// Start of a timeline: the counters of up to four split lists (null ones
+// skipped), the error slot and the non-finite flag.
 __global__ void __launch_bounds__(kBlock) k_tb_reset(int32_t *l0, int32_t *l1, int32_t *l2, int32_t *l3,
                                                      int32_t *info, int32_t *step_flag) {
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -117,24 +116,38 @@ __global__ void __launch_bounds__(kBlock) k_tb_open(int64_t n, int64_t ti, const
     list_append(list, cap, act, (int32_t)i);
 }
 
-// The criterion and bin of each active cell (eq. EqnTiStepIndividual over
-// the Voronoi neighbours):
-//   dt_i = C min(tau_i, R_i / (c_i + |v_i - w_i|)),
-//   tau_i = min over faces of |d| / v_sig, v_sig = c_L + c_R - (v_R - v_L).n
-// (a face with v_sig <= 0 sets no bound), by a lane group per cell walking
-// the cell's sides. The bin is the largest b <= levels with
-// dt_max 2^(b - levels) <= dt_i; the cell takes it if it is not above its
-// old bin, else moves up one bin where that bin starts a step at ti, else
-// keeps its bin. A criterion below one tick raises info[TB_ERR] and leaves
-// the bin. Occupancy changes are gathered per block in LDS and added to the
-// counts once per block and bin.
-template <int D>
-__global__ void __launch_bounds__(kBlock) k_tb_bins(const int32_t *__restrict__ list, int64_t cap, int64_t ti,
-                                                    double dt_max, int32_t levels, double cfl,
-                                                    const int32_t *__restrict__ off, const int32_t *__restrict__ ent,
-                                                    const int32_t *__restrict__ nbr, const double *__restrict__ frec,
-                                                    const double *__restrict__ sig, int8_t *__restrict__ bin,
-                                                    int32_t *__restrict__ info) {
+// The work of each active cell, by a lane group walking the cell's sides:
+//  1. its criterion and bin (eq. EqnTiStepIndividual over the Voronoi
+//     neighbours):
+//       dt_i = C min(tau_i, R_i / (c_i + |v_i - w_i|)),
+//       tau_i = min over faces of |d| / v_sig,
+//       v_sig = c_L + c_R - (v_R - v_L).n
+//     (a face with v_sig <= 0 sets no bound). The bin is the largest
+//     b <= levels with dt_max 2^(b - levels) <= dt_i; the cell takes it if it
+//     is not above its old bin, else moves up one bin where that bin starts
+//     a step at ti, else keeps its bin. A criterion below one tick raises
+//     info[TB_ERR] (the flux and update passes then do nothing) and leaves
+//     the bin. Occupancy changes are gathered per block in LDS and added to
+//     the counts once per block and bin;
+//  2. its gradient and limiter (grad_cell, from the primitive records of
+//     all cells: fresh for the active ones, of their last active step for
+//     the rest);
+//  3. with CLAIM (sparse points), its share of the active faces: every face
+//     of an active cell is active, since its smaller step divides the active
+//     cell's; a face is listed by its active cell if the other cell is
+//     inactive, else by its left cell. The cell itself and its inactive
+//     neighbours (once each, by the touch stamp exchanged to cur) go to the
+//     touched list. Whether a neighbour is active does not depend on the bin
+//     updates of step 1 racing with the read: an active cell's old and new
+//     bins both start a step at ti.
+template <int D, typename T, bool CLAIM>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 3)))
+k_tb_active(const int32_t *__restrict__ list, int64_t cap, int64_t ti, double dt_max, int32_t levels, double cfl,
+            const int32_t *__restrict__ off, const int32_t *__restrict__ ent, const int32_t *__restrict__ nbr,
+            const double *__restrict__ frec, const double *__restrict__ sig, int8_t *__restrict__ bin,
+            int32_t *__restrict__ info, const T *__restrict__ srec, const double *__restrict__ V,
+            const T *__restrict__ prim, T *__restrict__ grad_out, int32_t *__restrict__ touch, int32_t cur,
+            int32_t *__restrict__ faces, int64_t fcap, int32_t *__restrict__ touched, int64_t tcap) {
     using Y = Lay<D>;
     constexpr int SG = D + 2;
     constexpr int GS = Group<D>::GS, G = kBlock / GS;
@@ -149,10 +162,12 @@ __global__ void __launch_bounds__(kBlock) k_tb_bins(const int32_t *__restrict__ 
     const double tick = ldexp(dt_max, -levels);
     for (int64_t q = (int64_t)(blockIdx.x / kLists) * G + threadIdx.x / GS; q < count; q += stride) {
         const int64_t i = items[q];
+        const int32_t e0 = off[i], e1 = off[i + 1];
+        // 1
         double si[SG];
         load_rec<SG>(sig + i * SG, si);
         double tau = INFINITY;
-        for (int32_t e = off[i] + lane; e < off[i + 1]; e += GS) {
+        for (int32_t e = e0 + lane; e < e1; e += GS) {
             const int32_t en = ent[e];
             const int64_t f = en >> 1, j = nbr[e];
             const bool i_right = en & 1;
@@ -168,22 +183,43 @@ __global__ void __launch_bounds__(kBlock) k_tb_bins(const int32_t *__restrict__ 
             if (vsig > 0.0) tau = fmin(tau, fr[0] / vsig);
         }
         tau = grp_min<GS>(tau);
-        if (lane != 0) continue;
-        const double dti = cfl * fmin(tau, si[D + 1]);
-        if (!(dti >= tick)) {
-            atomicOr(info + TB_ERR, 1);
-            continue;
+        if (lane == 0) {
+            const double dti = cfl * fmin(tau, si[D + 1]);
+            if (!(dti >= tick)) {
+                atomicOr(info + TB_ERR, 1);
+            } else {
+                int b = levels;
+                while (b > 0 && ldexp(dt_max, b - levels) > dti) b--;
+                const int old = bin[i];
+                int nb = old;
+                if (b <= old) nb = b;
+                else if (tb_starts(ti, old + 1)) nb = old + 1;
+                if (nb != old) {
+                    bin[i] = (int8_t)nb;
+                    atomicAdd(&delta[old], -1);
+                    atomicAdd(&delta[nb], 1);
+                }
+            }
         }
-        int b = levels;
-        while (b > 0 && ldexp(dt_max, b - levels) > dti) b--;
-        const int old = bin[i];
-        int nb = old;
-        if (b <= old) nb = b;
-        else if (tb_starts(ti, old + 1)) nb = old + 1;
-        if (nb != old) {
-            bin[i] = (int8_t)nb;
-            atomicAdd(&delta[old], -1);
-            atomicAdd(&delta[nb], 1);
+        // 2
+        grad_cell<D, T>(i, lane, off, nbr, srec, V, prim, grad_out);
+        // 3
+        if constexpr (CLAIM) {
+            list_append(touched, tcap, lane == 0, (int32_t)i);
+            for (int32_t e = e0 + lane; __any(e < e1); e += GS) {
+                bool claim = false, fresh = false;
+                int32_t f = 0, j = 0;
+                if (e < e1) {
+                    const int32_t en = ent[e];
+                    f = en >> 1;
+                    j = nbr[e];
+                    const bool j_active = tb_starts(ti, bin[j]);
+                    claim = !j_active || !(en & 1);
+                    if (!j_active && touch[j] != cur) fresh = atomicExch(touch + j, cur) != cur;
+                }
+                list_append(faces, fcap, claim, f);
+                list_append(touched, tcap, fresh, j);
+            }
         }
     }
     __syncthreads();
@@ -211,50 +247,6 @@ __global__ void __launch_bounds__(kBlock) k_tb_faces(int64_t nf, const int32_t *
         }
     }
     list_append(list, cap, act, (int32_t)f);
-}
-
-// Sparse points: the active faces from the active cells' side lists (every
-// face of an active cell is active, since its smaller step divides the
-// active cell's). A face is listed by its active cell if the other cell is
-// inactive, else by its left cell. The active cells and the inactive
-// neighbours (once each, by the stamp exchanged to cur) go to the touched
-// list. A lane group per cell; the append rounds are wave-uniform.
-template <int D>
-__global__ void __launch_bounds__(kBlock) k_tb_claim(const int32_t *__restrict__ list, int64_t cap, int64_t ti,
-                                                     const int32_t *__restrict__ off, const int32_t *__restrict__ ent,
-                                                     const int32_t *__restrict__ nbr, const int8_t *__restrict__ bin,
-                                                     const int32_t *__restrict__ info, int32_t *__restrict__ touch,
-                                                     int32_t cur, int32_t *__restrict__ faces, int64_t fcap,
-                                                     int32_t *__restrict__ touched, int64_t tcap) {
-    constexpr int GS = Group<D>::GS, G = kBlock / GS;
-    const int lane = threadIdx.x % GS;
-    const int c = blockIdx.x % kLists;
-    const int32_t *items = list + (int64_t)kLists * kListPad + c * cap;
-    const int64_t count = info[TB_ERR] ? 0 : list[c * kListPad];
-    const int64_t stride = (int64_t)(gridDim.x / kLists) * G;
-    for (int64_t base = (int64_t)(blockIdx.x / kLists) * G; base < count; base += stride) {
-        const int64_t q = base + threadIdx.x / GS;
-        const bool live = q < count;
-        const int64_t i = live ? items[q] : 0;
-        int32_t e = live ? off[i] + lane : 0;
-        const int32_t e1 = live ? off[i + 1] : 0;
-        list_append(touched, tcap, live && lane == 0, (int32_t)i);
-        while (__any(e < e1)) {
-            bool claim = false, fresh = false;
-            int32_t f = 0, j = 0;
-            if (e < e1) {
-                const int32_t en = ent[e];
-                f = en >> 1;
-                j = nbr[e];
-                const bool j_active = tb_starts(ti, bin[j]);
-                claim = !j_active || !(en & 1);
-                if (!j_active && touch[j] != cur) fresh = atomicExch(touch + j, cur) != cur;
-            }
-            list_append(faces, fcap, claim, f);
-            list_append(touched, tcap, fresh, j);
-            e += GS;
-        }
-    }
 }
 
 // The update of a touched cell i by its lane group: Q_i gains the signed
@@ -336,22 +328,24 @@ __global__ void __launch_bounds__(kBlock) k_tb_update_list(const int32_t *__rest
                                                            const int32_t *__restrict__ nbr,
                                                            const int8_t *__restrict__ bin, int64_t ti,
                                                            const double *__restrict__ flux, double *__restrict__ Q,
-                                                           int32_t *__restrict__ flags) {
+                                                           int32_t *__restrict__ flags,
+                                                           const int32_t *__restrict__ info) {
     constexpr int GS = Group<D>::GS, G = kBlock / GS;
     const int c = blockIdx.x % kLists;
     const int32_t *items = list + (int64_t)kLists * kListPad + c * cap;
-    const int64_t count = list[c * kListPad];
+    const int64_t count = info[TB_ERR] ? 0 : list[c * kListPad];
     const int64_t stride = (int64_t)(gridDim.x / kLists) * G;
     for (int64_t q = (int64_t)(blockIdx.x / kLists) * G + threadIdx.x / GS; q < count; q += stride)
         tb_update_cell<D>(items[q], threadIdx.x % GS, n, off, ent, nbr, bin, ti, flux, Q, flags);
 }
 
-// Sizes of the point's two split lists into info[TB_CELLS], info[TB_FACES],
-// and the point's non-finite flag into info[TB_NONFIN].
-__global__ void __launch_bounds__(kBlock) k_tb_finish(const int32_t *__restrict__ cells,
-                                                      const int32_t *__restrict__ faces,
-                                                      const int32_t *__restrict__ step_flag,
-                                                      int32_t *__restrict__ info) {
+// End of a point: the sizes of its active-cell and active-face lists into
+// info[TB_CELLS], info[TB_FACES] and its non-finite flag into
+// info[TB_NONFIN]; then the counters of its lists (hard may be null) and the
+// flag are cleared for the next point.
+__global__ void __launch_bounds__(kBlock) k_tb_finish(int32_t *__restrict__ cells, int32_t *__restrict__ faces,
+                                                      int32_t *__restrict__ touched, int32_t *__restrict__ hard,
+                                                      int32_t *__restrict__ step_flag, int32_t *__restrict__ info) {
     __shared__ int32_t red[2][kBlock / 64];
     int32_t a = 0, b = 0;
     for (int c = threadIdx.x; c < kLists; c += kBlock) {
@@ -376,6 +370,14 @@ __global__ void __launch_bounds__(kBlock) k_tb_finish(const int32_t *__restrict_
         info[TB_FACES] = b;
         info[TB_NONFIN] = *step_flag;
     }
+    __syncthreads();
+    for (int c = threadIdx.x; c < kLists; c += kBlock) {
+        cells[c * kListPad] = 0;
+        faces[c * kListPad] = 0;
+        touched[c * kListPad] = 0;
+        if (hard) hard[c * kListPad] = 0;
+    }
+    if (threadIdx.x == 0) *step_flag = 0;
 }
 
 }  // namespace mm

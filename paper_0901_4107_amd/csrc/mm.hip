@@ -702,8 +702,8 @@ mm_status mm_tb_begin(mm_ctx *c, double dt_max, int32_t levels) {
     if (!(dt_max > 0.0) || !isfinite(dt_max) || levels < 0 || levels > kTbMaxLevels) return MM_E_ARG;
     if (!c->have_mesh) return MM_E_STATE;
     const Layout &L = c->lay;
-    // exact per-residue sums for the sparse path's sub-lists (the info block
-    // is reused as scratch before k_tb_init fills it)
+    // exact per-residue sums for the sparse path's sub-lists (the touched
+    // list's region serves as scratch before the timeline starts)
     int32_t *scratch = c->at<int32_t>(L.tb_touched);
     k_fill_i32<<<plain_grid(2 * kLists), kBlock, 0, c->st()>>>(scratch, 2 * kLists, 0);
     k_tb_bound<<<plain_grid(c->n), kBlock, 0, c->st()>>>(c->n, grid_for(c->n), c->at<int32_t>(L.off), scratch,
@@ -721,6 +721,12 @@ mm_status mm_tb_begin(mm_ctx *c, double dt_max, int32_t levels) {
     k_tb_init<<<plain_grid(c->n > TB_INFO_INTS ? c->n : TB_INFO_INTS), kBlock, 0, c->st()>>>(
         c->n, levels, c->at<int8_t>(L.tb_bin), c->at<int64_t>(L.tb_trec), c->at<int32_t>(L.tb_touch),
         c->at<int32_t>(L.tb_info));
+    // each point's finish clears its lists for the next one; the first
+    // starts from this
+    k_tb_reset<<<1, kBlock, 0, c->st()>>>(c->at<int32_t>(L.tb_cells), c->at<int32_t>(L.tb_faces),
+                                          c->at<int32_t>(L.tb_touched),
+                                          c->p.mode == MM_MIXED ? c->at<int32_t>(L.hard) : nullptr,
+                                          c->at<int32_t>(L.tb_info), c->at<int32_t>(L.flags) + 2);
     MM_LAUNCH_CHECK();
     c->tb.on = true;
     c->tb.dt_max = dt_max;
@@ -758,22 +764,16 @@ template <int D, typename T> static bool tb_point(mm_ctx *c, double *Q, T *rec) 
     T *grad = grad_block<D>(c, rec);
     int32_t *hard = mixed ? c->at<int32_t>(L.hard) : nullptr;
     const unsigned lg = kHardGrid;   // list-walking grids: a multiple of kLists
-    k_tb_reset<<<1, kBlock, 0, s>>>(cells, faces, touched, hard, info, flags + 2);
     k_tb_open<D, T><<<grid_for(c->n), kBlock, 0, s>>>(c->n, tb.ti, bin, trec, c->p.gamma, c->mesh.volume, Q,
                                                       c->mesh.mesh_vel, c->mesh.centroid_off, rec, sig, cells, ccap);
-    k_tb_bins<D><<<lg, kBlock, 0, s>>>(cells, ccap, tb.ti, tb.dt_max, tb.levels, c->p.cfl, c->at<int32_t>(L.off),
-                                       c->at<int32_t>(L.ent), c->at<int32_t>(L.nbr), c->at<double>(L.frec), sig, bin,
-                                       info);
-    k_grad_limit_list<D, T><<<lg, kBlock, 0, s>>>(cells, ccap, c->at<int32_t>(L.off), c->at<int32_t>(L.nbr), srec,
-                                                  c->mesh.volume, rec, grad);
-    if (sparse)
-        k_tb_claim<D><<<lg, kBlock, 0, s>>>(cells, ccap, tb.ti, c->at<int32_t>(L.off), c->at<int32_t>(L.ent),
-                                            c->at<int32_t>(L.nbr), bin, info, touch, tb.cur, faces, fcap, touched,
-                                            tcap);
-    else
+    auto active = sparse ? k_tb_active<D, T, true> : k_tb_active<D, T, false>;
+    active<<<lg, kBlock, 0, s>>>(cells, ccap, tb.ti, tb.dt_max, tb.levels, c->p.cfl, c->at<int32_t>(L.off),
+                                 c->at<int32_t>(L.ent), c->at<int32_t>(L.nbr), c->at<double>(L.frec), sig, bin, info,
+                                 srec, c->mesh.volume, rec, grad, touch, tb.cur, faces, fcap, touched, tcap);
+    if (!sparse)
         k_tb_faces<<<grid_for(c->nf), kBlock, 0, s>>>(c->nf, c->mesh.face_L, c->mesh.face_R, bin, tb.ti, info,
                                                       touch, tb.cur, faces, fcap);
-    const TbView view{bin, trec, tb.ti, tb.dt_max, tb.levels};
+    const TbView view{bin, trec, tb.ti, tb.dt_max, tb.levels, info + TB_ERR};
     DiagDev *diag = c->at<DiagDev>(L.diag);
     const MlpPacked *mlp = active_mlp(c);
     const GasConst<double> kg(c->p.gamma);
@@ -797,12 +797,12 @@ template <int D, typename T> static bool tb_point(mm_ctx *c, double *Q, T *rec) 
     }
     if (sparse)
         k_tb_update_list<D><<<lg, kBlock, 0, s>>>(touched, tcap, c->n, c->at<int32_t>(L.off), c->at<int32_t>(L.ent),
-                                                  c->at<int32_t>(L.nbr), bin, tb.ti, flux, Q, flags + 1);
+                                                  c->at<int32_t>(L.nbr), bin, tb.ti, flux, Q, flags + 1, info);
     else
         k_tb_update<D><<<group_grid(D, c->n), kBlock, 0, s>>>(c->n, c->at<int32_t>(L.off), c->at<int32_t>(L.ent),
                                                                c->at<int32_t>(L.nbr), bin, tb.ti, touch, tb.cur,
                                                                flux, Q, flags + 1);
-    k_tb_finish<<<1, kBlock, 0, s>>>(cells, faces, flags + 2, info);
+    k_tb_finish<<<1, kBlock, 0, s>>>(cells, faces, touched, hard, flags + 2, info);
     return sparse;
 }
 
