@@ -201,13 +201,15 @@ def time_individual(mm, learned, torch, wl, dmesh, form, dt_courant, step_ms, de
     dt_max, levels = 4.0 * dt_courant, 6
 
     def cycle(Q):
+        """One cycle in batches of up to 64 points (one synchronisation per
+        batch); the smallest and largest bins seen at the batch ends."""
         ctx.mm_tb_begin(dt_max, levels)
         pts, faces, cells, b0, hi = 0, 0, 0, levels, 0
         while True:
-            info = ctx.mm_tb_step(Q)
-            pts += 1
-            faces += info["active_faces"]
-            cells += info["active_cells"]
+            info = ctx.mm_tb_advance(Q, 1 << levels, 64)
+            pts += info["points"]
+            faces += info["total_faces"]
+            cells += info["total_cells"]
             b0, hi = min(b0, info["min_bin"]), max(hi, info["max_bin"])
             if info["next_tick"] >= 1 << levels:
                 return pts, faces, cells, b0, hi

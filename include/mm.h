@@ -357,16 +357,20 @@ mm_status mm_reset_diag(mm_ctx *ctx);
  * Static gravity is not combined with it (MM_E_STATE).
  * ------------------------------------------------------------------------ */
 typedef struct {
-    int64_t tick;          /* the point just performed (ticks) */
+    int64_t tick;          /* the last point performed (ticks) */
     int64_t next_tick;     /* the next point */
     int64_t active_cells;  /* cells whose step started at tick */
     int64_t active_faces;  /* faces integrated at tick */
-    int32_t min_bin;       /* occupied bins after the point */
+    int32_t min_bin;       /* occupied bins after that point */
     int32_t max_bin;
-    int32_t sparse;        /* 1: the point found its faces from the active cells'
+    int32_t sparse;        /* 1: that point found its faces from the active cells'
                               side lists (at most 1/8 of the cells due); 0: it
                               scanned every face. Same results either way. */
+    int32_t points;        /* points performed by the call */
+    int32_t sparse_points; /* of which sparse */
     int32_t reserved;
+    int64_t total_cells;   /* active cells summed over the call's points */
+    int64_t total_faces;   /* active faces summed over the call's points */
     double next_time;      /* next_tick dt_max / 2^levels */
 } mm_tb_info;
 
@@ -376,12 +380,20 @@ typedef struct {
  * or on a context not created with MM_STEPS_INDIVIDUAL. */
 mm_status mm_tb_begin(mm_ctx *ctx, double dt_max, int32_t levels);
 
-/* One synchronisation point on Q ([D+2][N] device, updated in place);
- * info (host, may be NULL) receives the point's summary. Synchronises the
- * stream. MM_E_RANGE when an active cell's criterion is below one tick:
- * then Q is untouched, but the timeline has ended (bins and records of the
- * point's active cells have changed; begin a new one). MM_E_NONFINITE when
- * the point left a non-finite conserved value (the timeline advances). */
+/* Up to max_points (>= 1) synchronisation points on Q ([D+2][N] device,
+ * updated in place), stopping before the first point whose tick is at or
+ * beyond until_tick: the points are enqueued without the host in between
+ * (the timeline's tick and path live on the device; a point past the stop
+ * tick does nothing), and the call synchronises once at the end. info
+ * (host, may be NULL) receives the last point's summary and the call's
+ * totals. MM_E_RANGE when an active cell's criterion is below one tick:
+ * that point and every later one leave Q untouched, and the timeline has
+ * ended (bins and records of that point's active cells have changed; begin
+ * a new one). MM_E_NONFINITE when a point left a non-finite conserved value
+ * (the timeline advances). */
+mm_status mm_tb_advance(mm_ctx *ctx, double *Q, int64_t until_tick, int32_t max_points, mm_tb_info *info);
+
+/* One synchronisation point: mm_tb_advance with no stop tick and one point. */
 mm_status mm_tb_step(mm_ctx *ctx, double *Q, mm_tb_info *info);
 
 /* Device copies of the timeline's per-cell bins [N] and the ticks at which

@@ -116,4 +116,33 @@ __device__ __forceinline__ ListWalk list_walk(const int32_t *list, int64_t cap) 
     return w;
 }
 
+// Individual timesteps: the slots of a timeline's info block in device
+// memory.
+enum : int {
+    TB_ERR = 0,         // a criterion fell below one tick: the timeline halts
+    TB_CELLS = 1,       // active cells of the last point performed
+    TB_FACES = 2,       // active faces of the last point performed
+    TB_NONFIN = 3,      // a non-finite state since the batch began
+    TB_SPARSE = 4,      // path of the next point (1: from the active cells' sides)
+    TB_LIVE = 5,        // the current point runs (not halted, tick below the stop tick)
+    TB_LO = 6,          // smallest and largest occupied bins
+    TB_HI = 7,
+    TB_COUNTS = 8,      // cells per bin, TB_COUNTS + b for b <= kTbMaxLevels
+    TB_TI = 40,         // int64: the current tick
+    TB_LAST = 42,       // int64: tick of the last point performed
+    TB_SUMC = 44,       // int64: active cells over the batch
+    TB_SUMF = 46,       // int64: active faces over the batch
+    TB_UNTIL = 48,      // int64: the batch's stop tick
+    TB_NPTS = 50,       // points performed in the batch
+    TB_CUR = 51,        // touch stamp of the current point (points since begin)
+    TB_NSPARSE = 52,    // sparse points in the batch
+    TB_LASTSPARSE = 53, // path of the last point performed
+    TB_INFO_INTS = 64
+};
+
+__device__ __forceinline__ int64_t &tb64(int32_t *info, int slot) { return *reinterpret_cast<int64_t *>(info + slot); }
+__device__ __forceinline__ int64_t tb64(const int32_t *info, int slot) {
+    return *reinterpret_cast<const int64_t *>(info + slot);
+}
+
 }  // namespace mm

@@ -345,14 +345,15 @@ __device__ __forceinline__ void store_face(double *p, const double (&F)[NV], con
 
 // One point of the individual-timestep integration (Section 7.2) as the
 // face kernels see it: per-cell bins and record times (in ticks), the
-// point's tick ti, and dt_max = 2^levels ticks.
+// point's tick ti (read from the info block at the start of a kernel), and
+// dt_max = 2^levels ticks.
 struct TbView {
     const int8_t *bin;
     const int64_t *trec;
     int64_t ti;
     double dt_max;
     int32_t levels;
-    const int32_t *halt;   // nonzero: a criterion failed, no face is fluxed
+    const int32_t *info;   // the timeline's info block (tick, halt and run flags)
     // Face (l, r) is integrated over fdt = 2^min(bin_l, bin_r) ticks; each
     // side is predicted from its record to the middle of that step,
     // (ti - trec) ticks + fdt/2.
@@ -684,6 +685,7 @@ __global__ void __launch_bounds__(kBlock) k_face_flux_hard(const int32_t *__rest
     constexpr int NV = D + 2;
     constexpr int FS = NV + (ENT ? 2 : 0);
     const ListWalk lw = list_walk(hard_list, cap);
+    if (tb.bin) tb.ti = tb64(tb.info, TB_TI);
     LaneDiag ld;
     for (int64_t q = lw.start; q < lw.count; q += lw.stride) {
         const int64_t f = lw.items[q];
@@ -726,7 +728,8 @@ __global__ void __launch_bounds__(kBlock) k_face_flux64_list(const int32_t *__re
     constexpr int NV = D + 2;
     const int c = blockIdx.x % kLists;
     const int32_t *items = list + (int64_t)kLists * kListPad + c * cap;
-    const int64_t count = *tb.halt ? 0 : list[c * kListPad];
+    tb.ti = tb64(tb.info, TB_TI);
+    const int64_t count = (!tb.info[TB_LIVE] || tb.info[TB_ERR]) ? 0 : list[c * kListPad];
     const int64_t stride = (int64_t)(gridDim.x / kLists) * kBlock;
     LaneDiag ld;
     for (int64_t base = (int64_t)(blockIdx.x / kLists) * kBlock; base < count; base += stride) {
@@ -757,7 +760,8 @@ k_face_flux_mixed_list(const int32_t *__restrict__ list, int64_t cap, const int3
     constexpr int NV = D + 2;
     const int c = blockIdx.x % kLists;
     const int32_t *items = list + (int64_t)kLists * kListPad + c * cap;
-    const int64_t count = *tb.halt ? 0 : list[c * kListPad];
+    tb.ti = tb64(tb.info, TB_TI);
+    const int64_t count = (!tb.info[TB_LIVE] || tb.info[TB_ERR]) ? 0 : list[c * kListPad];
     const int64_t stride = (int64_t)(gridDim.x / kLists) * kBlock;
     LaneDiag ld;
     for (int64_t base = (int64_t)(blockIdx.x / kLists) * kBlock; base < count; base += stride) {

@@ -39,10 +39,14 @@ inline int64_t align256(int64_t x) { return (x + 255) / 256 * 256; }
 // mean count plus 1024 (mm_tb_begin checks the exact sums and keeps to the
 // dense path where they do not fit). The touched list also takes those
 // cells themselves.
+constexpr unsigned kTbGrid = 8 * kLists;   // the fixed grids of a point's list walks and scans
 inline int64_t tb_cells_per_residue(int64_t n) { return (grid_for(n) + kLists - 1) / kLists * kBlock; }
 inline int64_t tb_face_cap(int64_t n, int64_t nf) {
     const int64_t sparse = (int64_t)(1.25 * (2.0 * (double)nf / (double)n) * (double)tb_cells_per_residue(n)) + 1024;
-    const int64_t dense = list_cap(grid_for(nf));
+    // the face scan: kTbGrid / kLists blocks per sub-list, each appending at
+    // most kBlock faces per round
+    const int64_t rounds = (nf + (int64_t)kTbGrid * kBlock - 1) / ((int64_t)kTbGrid * kBlock);
+    const int64_t dense = (int64_t)kTbGrid / kLists * kBlock * rounds;
     return sparse > dense ? sparse : dense;
 }
 inline int64_t tb_touch_cap(int64_t n, int64_t nf) { return tb_face_cap(n, nf) + tb_cells_per_residue(n); }
@@ -124,14 +128,12 @@ struct mm_ctx {
     const double *last_dt_dev = nullptr;  // timestep of the last face-flux pass (device) ...
     double last_dt = 0.0;                 // ... or its value
     bool have_dt = false;
-    struct Timeline {
+    struct Timeline {   // host copies; the state itself is in the info block
         bool on = false;
         double dt_max = 0.0;
         int32_t levels = 0;
-        int64_t ti = 0;
-        int32_t cur = 0;          // stamp of the current point
+        int64_t ti = 0;           // as of the last synchronisation
         bool sparse_ok = false;   // the sparse path's appends fit the sub-lists
-        int32_t counts[kTbMaxLevels + 1] = {};   // cells per bin after the last point
     } tb;
     Layout lay;
     hipStream_t st() const { return (hipStream_t)p.stream; }
@@ -732,19 +734,19 @@ mm_status mm_tb_begin(mm_ctx *c, double dt_max, int32_t levels) {
     c->tb.dt_max = dt_max;
     c->tb.levels = levels;
     c->tb.ti = 0;
-    c->tb.cur = 0;
-    for (int b = 0; b <= kTbMaxLevels; b++) c->tb.counts[b] = b == levels ? (int32_t)c->n : 0;
     return MM_OK;
 }
 
-// One synchronisation point. Sparse points (at most 1/8 of the cells due,
-// known from the bin counts of the previous point) find their faces and
-// touched cells from the active cells' side lists; dense points scan every
-// face and update every stamped cell. Both give the same fluxes and sums.
-template <int D, typename T> static bool tb_point(mm_ctx *c, double *Q, T *rec) {
+// One synchronisation point, enqueued with the same arguments at every
+// point: the tick, the path and whether the point runs at all come from the
+// info block. Sparse points (at most 1/8 of the cells due) find their faces
+// and touched cells from the active cells' side lists; dense points scan
+// every face and update every stamped cell. Both give the same fluxes and
+// sums.
+template <int D, typename T> static void tb_point(mm_ctx *c, double *Q, T *rec) {
     const Layout &L = c->lay;
     hipStream_t s = c->st();
-    mm_ctx::Timeline &tb = c->tb;
+    const mm_ctx::Timeline &tb = c->tb;
     int8_t *bin = c->at<int8_t>(L.tb_bin);
     int64_t *trec = c->at<int64_t>(L.tb_trec);
     double *sig = c->at<double>(L.tb_sig);
@@ -756,101 +758,90 @@ template <int D, typename T> static bool tb_point(mm_ctx *c, double *Q, T *rec) 
     const int64_t ccap = list_cap(grid_for(c->n)), fcap = tb_face_cap(c->n, c->nf);
     const int64_t tcap = tb_touch_cap(c->n, c->nf);
     const bool mixed = c->p.mode == MM_MIXED;
-    int64_t due = 0;
-    for (int b = 0; b <= tb.levels; b++)
-        if ((tb.ti & ((int64_t(1) << b) - 1)) == 0) due += tb.counts[b];
-    const bool sparse = tb.sparse_ok && 8 * due <= c->n;
     const T *srec = mixed ? (const T *)c->at<float>(L.srec32) : (const T *)c->at<double>(L.srec);
     T *grad = grad_block<D>(c, rec);
     int32_t *hard = mixed ? c->at<int32_t>(L.hard) : nullptr;
-    const unsigned lg = kHardGrid;   // list-walking grids: a multiple of kLists
-    k_tb_open<D, T><<<grid_for(c->n), kBlock, 0, s>>>(c->n, tb.ti, bin, trec, c->p.gamma, c->mesh.volume, Q,
+    const int32_t *off = c->at<int32_t>(L.off), *ent = c->at<int32_t>(L.ent), *nbr = c->at<int32_t>(L.nbr);
+    k_tb_open<D, T><<<grid_for(c->n), kBlock, 0, s>>>(c->n, info, bin, trec, c->p.gamma, c->mesh.volume, Q,
                                                       c->mesh.mesh_vel, c->mesh.centroid_off, rec, sig, cells, ccap);
-    auto active = sparse ? k_tb_active<D, T, true> : k_tb_active<D, T, false>;
-    active<<<lg, kBlock, 0, s>>>(cells, ccap, tb.ti, tb.dt_max, tb.levels, c->p.cfl, c->at<int32_t>(L.off),
-                                 c->at<int32_t>(L.ent), c->at<int32_t>(L.nbr), c->at<double>(L.frec), sig, bin, info,
-                                 srec, c->mesh.volume, rec, grad, touch, tb.cur, faces, fcap, touched, tcap);
-    if (!sparse)
-        k_tb_faces<<<grid_for(c->nf), kBlock, 0, s>>>(c->nf, c->mesh.face_L, c->mesh.face_R, bin, tb.ti, info,
-                                                      touch, tb.cur, faces, fcap);
-    const TbView view{bin, trec, tb.ti, tb.dt_max, tb.levels, info + TB_ERR};
+    k_tb_active<D, T><<<kTbGrid, kBlock, 0, s>>>(cells, ccap, tb.dt_max, tb.levels, c->p.cfl, off, ent, nbr,
+                                                 c->at<double>(L.frec), sig, bin, info, srec, c->mesh.volume, rec,
+                                                 grad, touch, faces, fcap, touched, tcap);
+    k_tb_faces<<<kTbGrid, kBlock, 0, s>>>(c->nf, c->mesh.face_L, c->mesh.face_R, bin, info, touch, faces, fcap);
+    const TbView view{bin, trec, 0, tb.dt_max, tb.levels, info};
     DiagDev *diag = c->at<DiagDev>(L.diag);
     const MlpPacked *mlp = active_mlp(c);
     const GasConst<double> kg(c->p.gamma);
     double *flux = c->at<double>(L.flux);
     if (!mixed) {
         auto kern = mlp ? k_face_flux64_list<D, true> : k_face_flux64_list<D, false>;
-        kern<<<lg, kBlock, 0, s>>>(faces, fcap, c->mesh.face_L, c->mesh.face_R, c->at<double>(L.frec),
-                                   (const double *)rec, (const double *)grad, view, kg, c->p.newton_tol64,
-                                   c->p.newton_max_iter, mlp, flux, diag);
+        kern<<<kTbGrid, kBlock, 0, s>>>(faces, fcap, c->mesh.face_L, c->mesh.face_R, c->at<double>(L.frec),
+                                        (const double *)rec, (const double *)grad, view, kg, c->p.newton_tol64,
+                                        c->p.newton_max_iter, mlp, flux, diag);
     } else {
         const GasConst<float> kf(c->p.gamma);
         auto kern = mlp ? k_face_flux_mixed_list<D, true> : k_face_flux_mixed_list<D, false>;
-        kern<<<lg, kBlock, 0, s>>>(faces, fcap, c->mesh.face_L, c->mesh.face_R, c->at<float>(L.mrec),
-                                   c->at<double>(L.wf64), (const float *)rec, (const float *)grad, view, kf,
-                                   kg.g_over_gm1, (float)c->p.newton_tol32, c->p.newton_max_iter, mlp, flux, hard,
-                                   diag);
-        k_face_flux_hard<D, false, false><<<kHardGrid, kBlock, 0, s>>>(
+        kern<<<kTbGrid, kBlock, 0, s>>>(faces, fcap, c->mesh.face_L, c->mesh.face_R, c->at<float>(L.mrec),
+                                        c->at<double>(L.wf64), (const float *)rec, (const float *)grad, view, kf,
+                                        kg.g_over_gm1, (float)c->p.newton_tol32, c->p.newton_max_iter, mlp, flux,
+                                        hard, diag);
+        k_face_flux_hard<D, false, false><<<kTbGrid, kBlock, 0, s>>>(
             c->mesh.face_L, c->mesh.face_R, c->at<float>(L.mrec), c->at<double>(L.wf64), (const float *)rec,
             (const float *)grad, nullptr, 0.0, kf.g, kg, c->p.newton_tol64, hard, fcap, flux, diag, nullptr, c->n,
             view);
     }
-    if (sparse)
-        k_tb_update_list<D><<<lg, kBlock, 0, s>>>(touched, tcap, c->n, c->at<int32_t>(L.off), c->at<int32_t>(L.ent),
-                                                  c->at<int32_t>(L.nbr), bin, tb.ti, flux, Q, flags + 1, info);
-    else
-        k_tb_update<D><<<group_grid(D, c->n), kBlock, 0, s>>>(c->n, c->at<int32_t>(L.off), c->at<int32_t>(L.ent),
-                                                               c->at<int32_t>(L.nbr), bin, tb.ti, touch, tb.cur,
-                                                               flux, Q, flags + 1);
-    k_tb_finish<<<1, kBlock, 0, s>>>(cells, faces, touched, hard, flags + 2, info);
-    return sparse;
+    k_tb_update_list<D><<<kTbGrid, kBlock, 0, s>>>(touched, tcap, c->n, off, ent, nbr, bin, flux, Q, flags + 1, info);
+    k_tb_update<D><<<kTbGrid, kBlock, 0, s>>>(c->n, off, ent, nbr, bin, info, touch, flux, Q, flags + 1);
+    k_tb_finish<<<1, kBlock, 0, s>>>(c->n, tb.levels, tb.sparse_ok ? 1 : 0, cells, faces, touched, hard, flags + 2,
+                                     info);
 }
 
-mm_status mm_tb_step(mm_ctx *c, double *Q, mm_tb_info *out) {
-    if (!c || !Q) return MM_E_ARG;
+mm_status mm_tb_advance(mm_ctx *c, double *Q, int64_t until_tick, int32_t max_points, mm_tb_info *out) {
+    if (!c || !Q || max_points < 1) return MM_E_ARG;
     if (!c->have_mesh || !c->tb.on || c->accel) return MM_E_STATE;
     const Layout &L = c->lay;
     hipStream_t s = c->st();
     const bool f64 = c->p.mode == MM_FP64;
     void *rec = f64 ? (void *)c->at<double>(L.rec) : (void *)c->at<float>(L.rec32);
-    const bool sparse = c->D == 3
-        ? (f64 ? tb_point<3, double>(c, Q, (double *)rec) : tb_point<3, float>(c, Q, (float *)rec))
-        : (f64 ? tb_point<2, double>(c, Q, (double *)rec) : tb_point<2, float>(c, Q, (float *)rec));
+    int32_t *info = c->at<int32_t>(L.tb_info);
+    k_tb_batch<<<1, 1, 0, s>>>(info, until_tick);
+    for (int32_t k = 0; k < max_points; k++) {
+        if (c->D == 3) f64 ? tb_point<3, double>(c, Q, (double *)rec) : tb_point<3, float>(c, Q, (float *)rec);
+        else f64 ? tb_point<2, double>(c, Q, (double *)rec) : tb_point<2, float>(c, Q, (float *)rec);
+    }
     MM_LAUNCH_CHECK();
-    int32_t info[TB_INFO_INTS];
-    MM_CHECK(hipMemcpyAsync(info, c->at<int32_t>(L.tb_info), sizeof(info), hipMemcpyDeviceToHost, s));
+    int32_t h[TB_INFO_INTS];
+    MM_CHECK(hipMemcpyAsync(h, info, sizeof(h), hipMemcpyDeviceToHost, s));
     MM_CHECK(hipStreamSynchronize(s));
-    const int32_t nonfin = info[TB_NONFIN];
     mm_ctx::Timeline &tb = c->tb;
-    if (info[TB_ERR]) {
-        tb.on = false;   // bins and records of the active cells have moved on; Q has not
+    auto i64 = [&](int slot) { int64_t v; std::memcpy(&v, h + slot, sizeof(v)); return v; };
+    tb.ti = i64(TB_TI);
+    const int64_t sumf = i64(TB_SUMF);
+    c->faces_done += (uint64_t)sumf;
+    c->waves_done += (uint64_t)((sumf + 63) / 64);
+    if (out) {
+        out->tick = i64(TB_LAST);
+        out->next_tick = tb.ti;
+        out->active_cells = h[TB_CELLS];
+        out->active_faces = h[TB_FACES];
+        out->min_bin = h[TB_LO];
+        out->max_bin = h[TB_HI];
+        out->sparse = h[TB_LASTSPARSE];
+        out->points = h[TB_NPTS];
+        out->sparse_points = h[TB_NSPARSE];
+        out->total_cells = i64(TB_SUMC);
+        out->total_faces = sumf;
+        out->next_time = ldexp(tb.dt_max, -tb.levels) * (double)tb.ti;
+    }
+    if (h[TB_ERR]) {
+        tb.on = false;   // bins and records of the failed point's active cells have moved on; Q has not
         return MM_E_RANGE;
     }
-    int lo = -1, hi = -1;
-    for (int b = 0; b <= tb.levels; b++) tb.counts[b] = info[TB_COUNTS + b];
-    for (int b = 0; b <= tb.levels; b++)
-        if (info[TB_COUNTS + b] > 0) {
-            if (lo < 0) lo = b;
-            hi = b;
-        }
-    if (lo < 0) return MM_E_DEVICE;   // the counts always hold every cell
-    const int64_t next = ((tb.ti >> lo) + 1) << lo;
-    c->faces_done += (uint64_t)info[TB_FACES];
-    c->waves_done += (uint64_t)((info[TB_FACES] + 63) / 64);
-    if (out) {
-        out->tick = tb.ti;
-        out->next_tick = next;
-        out->active_cells = info[TB_CELLS];
-        out->active_faces = info[TB_FACES];
-        out->min_bin = lo;
-        out->max_bin = hi;
-        out->sparse = sparse ? 1 : 0;
-        out->reserved = 0;
-        out->next_time = ldexp(tb.dt_max, -tb.levels) * (double)next;
-    }
-    tb.ti = next;
-    tb.cur += 1;
-    return nonfin ? MM_E_NONFINITE : MM_OK;
+    return h[TB_NONFIN] ? MM_E_NONFINITE : MM_OK;
+}
+
+mm_status mm_tb_step(mm_ctx *c, double *Q, mm_tb_info *out) {
+    return mm_tb_advance(c, Q, INT64_MAX, 1, out);
 }
 
 mm_status mm_tb_state(mm_ctx *c, int8_t *bins, int64_t *trec) {

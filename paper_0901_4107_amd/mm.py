@@ -50,7 +50,9 @@ class mm_diag(ctypes.Structure):
 class mm_tb_info(ctypes.Structure):
     _fields_ = [("tick", ctypes.c_int64), ("next_tick", ctypes.c_int64), ("active_cells", ctypes.c_int64),
                 ("active_faces", ctypes.c_int64), ("min_bin", ctypes.c_int32), ("max_bin", ctypes.c_int32),
-                ("sparse", ctypes.c_int32), ("reserved", ctypes.c_int32), ("next_time", ctypes.c_double)]
+                ("sparse", ctypes.c_int32), ("points", ctypes.c_int32), ("sparse_points", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("total_cells", ctypes.c_int64), ("total_faces", ctypes.c_int64),
+                ("next_time", ctypes.c_double)]
 
 
 class MMError(RuntimeError):
@@ -91,6 +93,7 @@ SIGNATURES = {
     "mm_set_gravity": (ctypes.c_int32, [_vp, _vp]),
     "mm_tb_begin": (ctypes.c_int32, [_vp, ctypes.c_double, ctypes.c_int32]),
     "mm_tb_step": (ctypes.c_int32, [_vp, _vp, ctypes.POINTER(mm_tb_info)]),
+    "mm_tb_advance": (ctypes.c_int32, [_vp, _vp, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(mm_tb_info)]),
     "mm_tb_state": (ctypes.c_int32, [_vp, _vp, _vp]),
 }
 
@@ -281,9 +284,18 @@ class Context:
     def mm_tb_step(self, Q: torch.Tensor) -> dict:
         """One synchronisation point on Q in place; returns the point's
         summary (tick, next_tick, active_cells, active_faces, min_bin,
-        max_bin, sparse, next_time)."""
+        max_bin, sparse, points, sparse_points, total_cells, total_faces,
+        next_time)."""
         info = mm_tb_info()
         _check("mm_tb_step", lib().mm_tb_step(self._ctx, _ptr(Q), ctypes.byref(info)))
+        return {name: getattr(info, name) for name, _ in mm_tb_info._fields_ if name != "reserved"}
+
+    def mm_tb_advance(self, Q: torch.Tensor, until_tick: int, max_points: int) -> dict:
+        """Up to max_points points, stopping at until_tick, synchronising
+        once; returns the last point's summary and the call's totals."""
+        info = mm_tb_info()
+        _check("mm_tb_advance", lib().mm_tb_advance(self._ctx, _ptr(Q), int(until_tick), int(max_points),
+                                                    ctypes.byref(info)))
         return {name: getattr(info, name) for name, _ in mm_tb_info._fields_ if name != "reserved"}
 
     def mm_tb_state(self, bins: torch.Tensor | None = None, trec: torch.Tensor | None = None):

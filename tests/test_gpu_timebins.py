@@ -230,3 +230,46 @@ def test_entry_point_rules():
     assert e.value.status == mm.MM_E_STATE
     ctx.mm_set_gravity(None)
     ctx.mm_tb_step(Q)
+
+
+def test_batches_equal_single_points():
+    """mm_tb_advance runs a cycle in batches without the host between the
+    points: the state equals the point-by-point run bit for bit, the
+    batches' point counts and face totals add up to the single points', a
+    batch stops exactly at its stop tick (a mid-cycle one included), and a
+    batch whose stop tick is reached performs nothing."""
+    wl = Random(3000, 3, 819)
+    n = wl.mesh.n_cells
+    levels = 5
+    dt_max = np.ldexp(0.99 * 0.25 * min_criterion(wl), levels)
+    one, batch = context(wl), context(wl)
+    Q1 = torch.from_numpy(np.ascontiguousarray(wl.Q)).cuda()
+    Qb = Q1.clone()
+    one.mm_tb_begin(dt_max, levels)
+    batch.mm_tb_begin(dt_max, levels)
+    ticks, faces = [], 0
+    while True:
+        info = one.mm_tb_step(Q1)
+        ticks.append(info["tick"])
+        faces += info["active_faces"]
+        if info["next_tick"] >= 2 ** levels:
+            break
+    half = 2 ** (levels - 1)
+    got = batch.mm_tb_advance(Qb, half, 1000)
+    assert got["next_tick"] == half and got["points"] == sum(t < half for t in ticks)
+    idle = batch.mm_tb_advance(Qb, half, 7)
+    assert idle["points"] == 0 and idle["next_tick"] == half
+    pts, fsum = got["points"], got["total_faces"]
+    while True:
+        got = batch.mm_tb_advance(Qb, 2 ** levels, 5)
+        pts += got["points"]
+        fsum += got["total_faces"]
+        if got["next_tick"] >= 2 ** levels:
+            break
+    note(f"{wl.name}: {len(ticks)} points, {faces} faces; batched {pts} points, {fsum} faces, "
+         f"last batch {got['points']} points ({got['sparse_points']} sparse)")
+    assert pts == len(ticks) and fsum == faces
+    assert torch.equal(Q1, Qb)
+    b1, t1 = state(one, n)
+    bb, tb = state(batch, n)
+    assert np.array_equal(b1, bb) and np.array_equal(t1, tb)
