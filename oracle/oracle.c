@@ -765,17 +765,86 @@ void oracle_apply_update_entropy(const om_mesh *M, const om_params *prm, const d
 /*   p_i += (dt/2) (m_i^(n) + m_i^(n+1)) g_i,                              */
 /*   E_i += (dt/2) (p_i^(n) + p_i^(n+1)) . g_i  (m v at both ends),        */
 /* then, with s_flux (may be NULL), the entropy treatment above.          */
+/* The keep decision of the entropy treatment: with mode 1 the Mach number */
+/* switch above; with mode 2 the energy switch of Section 3.5 (eqs.       */
+/* eqnScrit1, eqnScrit2): a cell is cold and keeps its advected entropy   */
+/* when its expected new thermal energy E_th = E - M v^2/2 (after the      */
+/* conservative update and the gravitational sources) satisfies            */
+/*   alpha_s > 0 and E_th < alpha_s E_kin^max,  or                         */
+/*   beta_s > 0, a field given, and E_th < beta_s M |g_i| R_i,             */
+/* with E_kin^max the largest M_j |v_j - w_i|^2 / 2 over the cell and its   */
+/* face neighbours, measured in the frame of the cell's generator (w_i)    */
+/* from the states at the start of the step (the neighbours' new states    */
+/* are not known while the cell is updated), and R_i the radius of the     */
+/* cell's volume. Readings: the start-of-step states; alpha_s or beta_s    */
+/* <= 0 switches its condition off; M in eqnScrit2 is the new mass.       */
+typedef struct {
+    int mode;               /* 1 Mach number, 2 energy */
+    double mach_thresh, alpha_s, beta_s;
+} om_switch;
+
+static void update_core(const om_mesh *M, const om_params *prm, double dt, const double *accel,
+                        const double *face_flux, const double *s_flux, const double *mach, const om_switch *sw,
+                        double *Q, int32_t *kept);
+
 void oracle_update_full(const om_mesh *M, const om_params *prm, double dt, const double *accel,
                         const double *face_flux, const double *s_flux, const double *mach, double mach_thresh,
+                        double *Q, int32_t *kept)
+{
+    const om_switch sw = {1, mach_thresh, 0.0, 0.0};
+    update_core(M, prm, dt, accel, face_flux, s_flux, mach, &sw, Q, kept);
+}
+
+void oracle_update_energy_switch(const om_mesh *M, const om_params *prm, double dt, const double *accel,
+                                 const double *face_flux, const double *s_flux, double alpha_s, double beta_s,
+                                 double *Q, int32_t *kept)
+{
+    const om_switch sw = {2, 0.0, alpha_s, beta_s};
+    update_core(M, prm, dt, accel, face_flux, s_flux, NULL, &sw, Q, kept);
+}
+
+static void update_core(const om_mesh *M, const om_params *prm, double dt, const double *accel,
+                        const double *face_flux, const double *s_flux, const double *mach, const om_switch *sw,
                         double *Q, int32_t *kept)
 {
     const int D = M->dim, nv = D + 2;
     const int64_t n = M->n_cells, nf = M->n_faces;
     const double g = prm->gamma;
-    double *old = NULL;
+    double *old = NULL, *ekmax = NULL;
     if (accel) {
         old = (double *)malloc(sizeof(double) * (D + 1) * n);
         memcpy(old, Q, sizeof(double) * (D + 1) * n);        /* m, p at the start */
+    }
+    if (s_flux && sw->mode == 2) {
+        /* E_kin^max from the start-of-step states, in each cell's frame */
+        ekmax = (double *)malloc(sizeof(double) * n);
+        double *vel = (double *)calloc((size_t)D * n, sizeof(double));
+        for (int64_t i = 0; i < n; i++)
+            if (Q[i] > 0.0)
+                for (int k = 0; k < D; k++) vel[k * n + i] = Q[(1 + k) * n + i] / Q[i];
+        for (int64_t i = 0; i < n; i++) {
+            double e = 0.0;
+            for (int k = 0; k < D; k++) {
+                const double dv = vel[k * n + i] - M->mesh_vel[k * n + i];
+                e += dv * dv;
+            }
+            ekmax[i] = Q[i] > 0.0 ? 0.5 * Q[i] * e : 0.0;
+        }
+        for (int64_t f = 0; f < nf; f++) {
+            const int64_t cell[2] = {M->face_L[f], M->face_R[f]};
+            for (int s2 = 0; s2 < 2; s2++) {
+                const int64_t i = cell[s2], j = cell[1 - s2];
+                if (!(Q[j] > 0.0)) continue;
+                double e = 0.0;
+                for (int k = 0; k < D; k++) {
+                    const double dv = vel[k * n + j] - M->mesh_vel[k * n + i];
+                    e += dv * dv;
+                }
+                e *= 0.5 * Q[j];
+                if (e > ekmax[i]) ekmax[i] = e;
+            }
+        }
+        free(vel);
     }
     oracle_apply_update(M, face_flux, Q);
     if (accel) {
@@ -798,14 +867,29 @@ void oracle_update_full(const om_mesh *M, const om_params *prm, double dt, const
         int64_t l = M->face_L[f], r = M->face_R[f];
         Q[nv * n + l] -= s_flux[f];
         Q[nv * n + r] += s_flux[f];
-        if (mach[f] > mmax[l]) mmax[l] = mach[f];
-        if (mach[f] > mmax[r]) mmax[r] = mach[f];
+        if (mach) {
+            if (mach[f] > mmax[l]) mmax[l] = mach[f];
+            if (mach[f] > mmax[r]) mmax[r] = mach[f];
+        }
     }
     for (int64_t i = 0; i < n; i++) {
         const double m = Q[i], V = M->volume[i], S = Q[nv * n + i];
         double p2 = 0.0;
         for (int k = 0; k < D; k++) p2 += Q[(1 + k) * n + i] * Q[(1 + k) * n + i];
-        const int keep = mmax[i] < mach_thresh && m > 0.0 && S > 0.0;
+        int cold;
+        if (sw->mode == 1) {
+            cold = mmax[i] < sw->mach_thresh;
+        } else {
+            const double eth = m > 0.0 ? Q[(nv - 1) * n + i] - 0.5 * p2 / m : 0.0;
+            cold = sw->alpha_s > 0.0 && eth < sw->alpha_s * ekmax[i];
+            if (!cold && sw->beta_s > 0.0 && accel) {
+                double g2 = 0.0;
+                for (int k = 0; k < D; k++) g2 += accel[k * n + i] * accel[k * n + i];
+                const double R = (D == 3) ? cbrt(3.0 * V / (4.0 * PI_D)) : sqrt(V / PI_D);
+                cold = eth < sw->beta_s * m * sqrt(g2) * R;
+            }
+        }
+        const int keep = cold && m > 0.0 && S > 0.0;
         if (kept) kept[i] = keep;
         if (!(m > 0.0)) { Q[nv * n + i] = 0.0; continue; }
         const double rho = m / V, ke = 0.5 * p2 / m;
@@ -818,6 +902,7 @@ void oracle_update_full(const om_mesh *M, const om_params *prm, double dt, const
         }
     }
     free(mmax);
+    free(ekmax);
 }
 
 /* The step with the entropy row: primitives, gradients, timestep and     */
@@ -1119,4 +1204,26 @@ done:
     free(Wn);
     free(dti);
     return status;
+}
+
+/* The step with the energy switch of the entropy treatment (Section 3.5, */
+/* eqs. eqnScrit1-eqnScrit2) and an optional static field: as             */
+/* oracle_hydro_step_full with update_core's mode 2.                     */
+double oracle_hydro_step_energy(const om_mesh *M, const om_params *prm, double dt, const double *accel,
+                                double alpha_s, double beta_s, double *Q, int32_t *kept)
+{
+    const int D = M->dim, nv = D + 2;
+    const int64_t n = M->n_cells, nf = M->n_faces;
+    double *W = (double *)malloc(sizeof(double) * nv * n);
+    double *gr = (double *)malloc(sizeof(double) * nv * D * n);
+    double *gl = (double *)malloc(sizeof(double) * nv * D * n);
+    double *fl = (double *)malloc(sizeof(double) * nv * nf);
+    double *sf = (double *)malloc(sizeof(double) * nf);
+    oracle_prim(D, n, prm->gamma, M->volume, Q, W);
+    oracle_gradients(M, W, gr, gl, NULL);
+    if (!(dt > 0.0)) dt = oracle_cfl_dt(M, prm, W);
+    oracle_face_fluxes_full(M, prm, dt, accel, W, gl, fl, NULL, NULL, sf, NULL);
+    oracle_update_energy_switch(M, prm, dt, accel, fl, sf, alpha_s, beta_s, Q, kept);
+    free(W); free(gr); free(gl); free(fl); free(sf);
+    return dt;
 }

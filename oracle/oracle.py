@@ -75,6 +75,9 @@ def _lib():
                                                _dp, ctypes.c_int32, ctypes.c_double, _dp, _ip]
         lib.oracle_shock_mach.restype = ctypes.c_double
         lib.oracle_shock_mach.argtypes = [ctypes.c_double, _dp, _dp]
+        lib.oracle_hydro_step_energy.restype = ctypes.c_double
+        lib.oracle_hydro_step_energy.argtypes = [ctypes.POINTER(_OMesh), ctypes.POINTER(_OParams), ctypes.c_double,
+                                                 _dp, ctypes.c_double, ctypes.c_double, _dp, _ip]
         lib.oracle_tb_criterion.argtypes = [ctypes.POINTER(_OMesh), ctypes.POINTER(_OParams), _dp, _dp]
         lib.oracle_tb_step.restype = ctypes.c_int
         lib.oracle_tb_step.argtypes = [ctypes.POINTER(_OMesh), ctypes.POINTER(_OParams), ctypes.c_double,
@@ -237,6 +240,21 @@ def hydro_step_full(mesh, gamma, cfl, Q, dt=0.0, accel=None, mach_thresh=None):
                                          _d(acc) if acc is not None else None, int(ent),
                                          float(mach_thresh) if ent else 0.0, _d(Q), _i(kept))
     return Q, used, (kept if ent else None)
+
+
+def hydro_step_energy(mesh, gamma, cfl, Q, alpha_s, beta_s=0.0, dt=0.0, accel=None):
+    """One step with the entropy row (Q [D+3][N]) and the energy switch of
+    Section 3.5 (eqs. eqnScrit1-eqnScrit2), optionally with a static field.
+    Returns (Q_new, dt_used, kept)."""
+    h = _Held(mesh)
+    Q = _f64(Q).copy()
+    kept = np.empty(h.n, dtype=np.int32)
+    p = _OParams(float(gamma), float(cfl))
+    acc = _f64(accel) if accel is not None else None
+    used = _lib().oracle_hydro_step_energy(ctypes.byref(h.s), ctypes.byref(p), float(dt),
+                                           _d(acc) if acc is not None else None, float(alpha_s), float(beta_s),
+                                           _d(Q), _i(kept))
+    return Q, used, kept
 
 
 def mesh_velocity(mesh, gamma, W, eta=0.25, chi=1.0, dt_lloyd=0.0):
