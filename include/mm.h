@@ -77,6 +77,16 @@ typedef int32_t mm_status;
  * S = M P / rho^gamma of its conservatively updated state. */
 #define MM_ENTROPY_OFF  0
 #define MM_ENTROPY_MACH 1
+/* The energy switch of the same section (eqs. eqnScrit1, eqnScrit2) in
+ * place of the Mach number: a cell is cold, and keeps its entropy, when its
+ * new thermal energy E - |p|^2/(2M) is below alpha_s times the largest
+ * kinetic energy M_j |v_j - w_i|^2 / 2 of the cell and its face neighbours
+ * (states at the start of the step, in the frame of the cell's generator),
+ * or, with a static field (mm_set_gravity), below beta_s M |g_i| R_i, R_i
+ * the radius of the cell's volume. A parameter <= 0 switches its condition
+ * off. The update reads the primitive records of the last gradient pass
+ * (mm_gradients, or the step's own). */
+#define MM_ENTROPY_ENERGY 2
 
 /* Timestep scheme (Section 7.2). MM_STEPS_INDIVIDUAL adds the arrays of a
  * power-of-two timeline to the workspace (mm_tb_begin, mm_tb_step); the
@@ -104,6 +114,9 @@ typedef struct {
     double mach_thresh;       /* MM_ENTROPY_MACH: cells whose largest face shock Mach
                                  number is below this keep their entropy (the paper
                                  suggests about 1.1); <= 0 never keeps; not NaN */
+    double alpha_s;           /* MM_ENTROPY_ENERGY: eqnScrit1's factor (the paper uses
+                                 about 0.01); >= 0 and finite */
+    double beta_s;            /* MM_ENTROPY_ENERGY: eqnScrit2's factor; >= 0 and finite */
 } mm_params;
 
 /* Doubles per face record of the face-flux array: the D+2 fluxes
@@ -154,7 +167,8 @@ typedef struct mm_ctx mm_ctx;
 
 /* Create a context for the given parameters. Allocates host memory only.
  * MM_E_ARG for a bad dimension, mode, guess, entropy or steps value,
- * gamma <= 1, or individual timesteps with the entropy row. */
+ * gamma <= 1, a NaN mach_thresh or a negative or non-finite alpha_s or
+ * beta_s with their mode, or individual timesteps with the entropy row. */
 mm_status mm_create(const mm_params *params, mm_ctx **out);
 
 /* Destroy a context (NULL is accepted). Does not free the workspace. */

@@ -310,16 +310,52 @@ k_grad_limit(int64_t n, const int32_t *__restrict__ off, const int32_t *__restri
 // entropy, keeps it: P = (S/M) rho^gamma and E = P V/(gamma-1) + |p|^2/(2M).
 // Every other cell takes S = M P / rho^gamma of its updated state (0 for
 // M <= 0). The cells that keep are counted in entropy_kept.
+// With the energy switch (ESW, Section 3.5, eqs. eqnScrit1-eqnScrit2) the
+// cell is cold instead when its new thermal energy E - |p|^2/(2M) is below
+// alpha_s times the largest M_j |v_j - w_i|^2 / 2 over the cell and its
+// face neighbours (start-of-step primitive records, in the frame of the
+// cell's generator), or (with GRAV) below beta_s M |g| R.
 // GRAV (Section 5.2, a static field g = accel [D][n]): before the entropy
 // treatment, p += (dt/2)(M^n + M^(n+1)) g and E += (dt/2)(p^n + p^(n+1)).g,
 // dt from dt_ptr when it is set, else dt_val.
-template <int D, bool ENT, bool GRAV>
+struct EnergySwitch {
+    double alpha_s, beta_s;   // a condition <= 0 is off
+    const void *prim;         // the step's primitive records (float ones hold v - w of their cell)
+    int32_t prim_f32;
+    int32_t reserved;
+    const int32_t *nbr;       // side neighbours, CSR order
+    const double *mvel;       // generator velocities [D][n]
+};
+
+// M_j |v_j - w|^2 / 2 from cell j's primitive record, M_j = rho_j V_j (0 for
+// a vacuum record).
+template <int D>
+__device__ __forceinline__ double ekin_in_frame(const EnergySwitch &es, int64_t j, const double *__restrict__ V,
+                                                int64_t n, const double (&w)[D]) {
+    using Y = Lay<D>;
+    double rho, v[D];
+    if (es.prim_f32) {
+        const float *p = (const float *)es.prim + j * Y::PREC;
+        rho = p[Y::W];
+        for (int k = 0; k < D; k++) v[k] = (double)p[Y::W + 1 + k] + es.mvel[k * n + j];
+    } else {
+        const double *p = (const double *)es.prim + j * Y::PREC;
+        rho = p[Y::W];
+        for (int k = 0; k < D; k++) v[k] = p[Y::W + 1 + k];
+    }
+    double e = 0.0;
+    for (int k = 0; k < D; k++) e += (v[k] - w[k]) * (v[k] - w[k]);
+    return rho > 0.0 ? 0.5 * (rho * V[j]) * e : 0.0;
+}
+
+template <int D, bool ENT, bool GRAV, bool ESW = false>
 __global__ void __launch_bounds__(kBlock) k_update(int64_t n, const int32_t *__restrict__ off,
                                                    const int32_t *__restrict__ ent, const double *__restrict__ flux,
                                                    double *__restrict__ Q, int32_t *__restrict__ flags,
                                                    const double *__restrict__ V, double gamma, double mach_thresh,
                                                    DiagDev *diag, const double *__restrict__ accel,
-                                                   const double *__restrict__ dt_ptr, double dt_val) {
+                                                   const double *__restrict__ dt_ptr, double dt_val,
+                                                   EnergySwitch es) {
     constexpr int NV = D + 2;
     constexpr int FS = NV + (ENT ? 2 : 0);   // record stride
     constexpr int NS = NV + (ENT ? 1 : 0);   // summed rows
@@ -355,6 +391,16 @@ __global__ void __launch_bounds__(kBlock) k_update(int64_t n, const int32_t *__r
     }
     for (int c = 0; c < NS; c++) acc[c] = grp_sum<GS>(acc[c]);
     if constexpr (ENT) mx = grp_max<GS>(mx);
+    double ekmax = 0.0;
+    if constexpr (ENT && ESW) {
+        {
+            double wi[D];
+            for (int k = 0; k < D; k++) wi[k] = es.mvel[k * n + i];
+            for (int32_t q = b + lane; q < e; q += GS) ekmax = fmax(ekmax, ekin_in_frame<D>(es, es.nbr[q], V, n, wi));
+            if (lane == 0) ekmax = fmax(ekmax, ekin_in_frame<D>(es, i, V, n, wi));
+            ekmax = grp_max<GS>(ekmax);
+        }
+    }
     bool keep = false;
     if (lane == 0) {
         double q[NS];
@@ -371,12 +417,26 @@ __global__ void __launch_bounds__(kBlock) k_update(int64_t n, const int32_t *__r
         }
         if constexpr (ENT) {
             const double m = q[0], S = q[NV];
-            keep = mx < mach_thresh && m > 0.0 && S > 0.0;
+            double p2 = 0.0;
+            for (int k = 0; k < D; k++) p2 += q[1 + k] * q[1 + k];
+            bool cold = mx < mach_thresh;
+            if constexpr (ESW) {
+                const double eth = m > 0.0 ? q[NV - 1] - 0.5 * p2 / m : 0.0;
+                cold = es.alpha_s > 0.0 && eth < es.alpha_s * ekmax;
+                if constexpr (GRAV) {
+                    if (!cold && es.beta_s > 0.0) {
+                        double g2 = 0.0;
+                        for (int k = 0; k < D; k++) g2 += accel[k * n + i] * accel[k * n + i];
+                        const double vol = V[i];
+                        const double R = (D == 3) ? cbrt(vol * (3.0 / (4.0 * M_PI))) : sqrt(vol * (1.0 / M_PI));
+                        cold = eth < es.beta_s * m * sqrt(g2) * R;
+                    }
+                }
+            }
+            keep = cold && m > 0.0 && S > 0.0;
             if (!(m > 0.0)) {
                 q[NV] = 0.0;
             } else {
-                double p2 = 0.0;
-                for (int k = 0; k < D; k++) p2 += q[1 + k] * q[1 + k];
                 const double vol = V[i], rho = m / vol, ke = 0.5 * p2 / m;
                 if (keep) {
                     const double P = (S / m) * mm_pow(rho, gamma);

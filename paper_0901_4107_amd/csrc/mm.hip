@@ -128,6 +128,7 @@ struct mm_ctx {
     const double *last_dt_dev = nullptr;  // timestep of the last face-flux pass (device) ...
     double last_dt = 0.0;                 // ... or its value
     bool have_dt = false;
+    const void *last_rec = nullptr;       // records of the last gradient pass
     struct Timeline {   // host copies; the state itself is in the info block
         bool on = false;
         double dt_max = 0.0;
@@ -184,7 +185,13 @@ mm_status mm_create(const mm_params *params, mm_ctx **out) {
     if (params->mode != MM_FP64 && params->mode != MM_MIXED) return MM_E_ARG;
     if (params->guess != MM_GUESS_STANDARD && params->guess != MM_GUESS_LEARNED) return MM_E_ARG;
     if (!(params->gamma > 1.0) || !(params->cfl > 0.0)) return MM_E_ARG;
-    if (params->entropy != MM_ENTROPY_OFF && params->entropy != MM_ENTROPY_MACH) return MM_E_ARG;
+    if (params->entropy != MM_ENTROPY_OFF && params->entropy != MM_ENTROPY_MACH &&
+        params->entropy != MM_ENTROPY_ENERGY)
+        return MM_E_ARG;
+    if (params->entropy == MM_ENTROPY_ENERGY &&
+        (!(params->alpha_s >= 0.0) || !(params->beta_s >= 0.0) || !isfinite(params->alpha_s) ||
+         !isfinite(params->beta_s)))
+        return MM_E_ARG;
     if (params->entropy != MM_ENTROPY_OFF && params->mach_thresh != params->mach_thresh) return MM_E_ARG;
     if (params->steps != MM_STEPS_GLOBAL && params->steps != MM_STEPS_INDIVIDUAL) return MM_E_ARG;
     if (params->steps == MM_STEPS_INDIVIDUAL && params->entropy != MM_ENTROPY_OFF) return MM_E_ARG;
@@ -290,6 +297,7 @@ mm_status mm_mesh_upload(mm_ctx *c, const mm_mesh *m) {
     if (L.total > c->ws_bytes) return MM_E_WORKSPACE;
     c->have_mesh = false;
     c->tb.on = false;
+    c->last_rec = nullptr;
     c->accel = nullptr;   // a field belongs to the mesh it was set for
     c->have_dt = false;
     c->lay = L;
@@ -376,6 +384,7 @@ template <int D, typename T> static mm_status gradients_t(mm_ctx *c, const doubl
 
 static mm_status gradients_into(mm_ctx *c, const double *Q, void *rec, double *dt_part) {
     const bool f64 = c->p.mode == MM_FP64;
+    c->last_rec = rec;   // the energy switch of the entropy scheme reads these records at the update
     if (c->D == 3)
         return f64 ? gradients_t<3, double>(c, Q, (double *)rec, dt_part) : gradients_t<3, float>(c, Q, (float *)rec, dt_part);
     return f64 ? gradients_t<2, double>(c, Q, (double *)rec, dt_part) : gradients_t<2, float>(c, Q, (float *)rec, dt_part);
@@ -444,21 +453,26 @@ mm_status mm_face_fluxes(mm_ctx *c, double dt, const void *recon, double *face_f
     return fluxes_into(c, nullptr, dt, recon, face_flux);
 }
 
-template <int D, bool ENT, bool GRAV> static void launch_update(mm_ctx *c, const double *flux, double *Q) {
+template <int D, bool ENT, bool GRAV, bool ESW = false>
+static void launch_update(mm_ctx *c, const double *flux, double *Q) {
     const Layout &L = c->lay;
-    k_update<D, ENT, GRAV><<<group_grid(D, c->n), kBlock, 0, c->st()>>>(
+    EnergySwitch es{c->p.alpha_s, c->p.beta_s, c->last_rec, c->p.mode == MM_MIXED ? 1 : 0, 0,
+                    c->at<int32_t>(L.nbr), c->mesh.mesh_vel};
+    k_update<D, ENT, GRAV, ESW><<<group_grid(D, c->n), kBlock, 0, c->st()>>>(
         c->n, c->at<int32_t>(L.off), c->at<int32_t>(L.ent), flux, Q, c->at<int32_t>(L.flags) + 1, c->mesh.volume,
-        c->p.gamma, c->p.mach_thresh, c->at<DiagDev>(L.diag), c->accel, c->last_dt_dev, c->last_dt);
+        c->p.gamma, c->p.mach_thresh, c->at<DiagDev>(L.diag), c->accel, c->last_dt_dev, c->last_dt, es);
 }
 
 template <int D> static void launch_update_d(mm_ctx *c, const double *flux, double *Q) {
-    const bool e = c->p.entropy != 0, g = c->accel != nullptr;
-    if (e) g ? launch_update<D, true, true>(c, flux, Q) : launch_update<D, true, false>(c, flux, Q);
+    const bool e = c->p.entropy != 0, g = c->accel != nullptr, w = c->p.entropy == MM_ENTROPY_ENERGY;
+    if (w) g ? launch_update<D, true, true, true>(c, flux, Q) : launch_update<D, true, false, true>(c, flux, Q);
+    else if (e) g ? launch_update<D, true, true>(c, flux, Q) : launch_update<D, true, false>(c, flux, Q);
     else g ? launch_update<D, false, true>(c, flux, Q) : launch_update<D, false, false>(c, flux, Q);
 }
 
 static mm_status update_into(mm_ctx *c, const double *flux, double *Q) {
     if (c->accel && !c->have_dt) return MM_E_STATE;   // the source terms need the flux pass's timestep
+    if (c->p.entropy == MM_ENTROPY_ENERGY && !c->last_rec) return MM_E_STATE;   // no records for the switch
     if (c->D == 3) launch_update_d<3>(c, flux, Q);
     else launch_update_d<2>(c, flux, Q);
     MM_LAUNCH_CHECK();

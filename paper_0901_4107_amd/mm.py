@@ -21,7 +21,7 @@ MM_OK, MM_E_ARG, MM_E_MESH, MM_E_DEVICE, MM_E_STATE, MM_E_WORKSPACE, MM_E_NONFIN
 MM_E_RANGE = -7
 MM_FP64, MM_MIXED = 0, 1
 MM_GUESS_STANDARD, MM_GUESS_LEARNED = 0, 1
-MM_ENTROPY_OFF, MM_ENTROPY_MACH = 0, 1
+MM_ENTROPY_OFF, MM_ENTROPY_MACH, MM_ENTROPY_ENERGY = 0, 1, 2
 MM_STEPS_GLOBAL, MM_STEPS_INDIVIDUAL = 0, 1
 
 _vp = ctypes.c_void_p
@@ -31,7 +31,8 @@ class mm_params(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("mode", ctypes.c_int32), ("guess", ctypes.c_int32),
                 ("newton_max_iter", ctypes.c_int32), ("gamma", ctypes.c_double), ("cfl", ctypes.c_double),
                 ("newton_tol64", ctypes.c_double), ("newton_tol32", ctypes.c_double), ("stream", _vp),
-                ("entropy", ctypes.c_int32), ("steps", ctypes.c_int32), ("mach_thresh", ctypes.c_double)]
+                ("entropy", ctypes.c_int32), ("steps", ctypes.c_int32), ("mach_thresh", ctypes.c_double),
+                ("alpha_s", ctypes.c_double), ("beta_s", ctypes.c_double)]
 
 
 class mm_mesh(ctypes.Structure):
@@ -171,11 +172,13 @@ class Context:
     def __init__(self, dim: int, gamma: float, cfl: float = 0.4, mode: int = MM_FP64,
                  guess: int = MM_GUESS_STANDARD, newton_max_iter: int = 0, newton_tol64: float = 0.0,
                  newton_tol32: float = 0.0, device="cuda", stream: torch.cuda.Stream | None = None,
-                 entropy: int = MM_ENTROPY_OFF, mach_thresh: float = 1.1, steps: int = MM_STEPS_GLOBAL):
+                 entropy: int = MM_ENTROPY_OFF, mach_thresh: float = 1.1, steps: int = MM_STEPS_GLOBAL,
+                 alpha_s: float = 0.01, beta_s: float = 0.0):
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.params = mm_params(dim, mode, guess, newton_max_iter, gamma, cfl, newton_tol64, newton_tol32,
-                                ctypes.c_void_p(self.stream.cuda_stream), entropy, steps, mach_thresh)
+                                ctypes.c_void_p(self.stream.cuda_stream), entropy, steps, mach_thresh, alpha_s,
+                                beta_s)
         self.dim = dim
         self.mode = mode
         self.entropy = entropy

@@ -32,11 +32,11 @@ def test_library_exports_every_declared_symbol():
 def _params(**kw):
     p = dict(dim=3, mode=mm.MM_FP64, guess=mm.MM_GUESS_STANDARD, newton_max_iter=0, gamma=5 / 3, cfl=0.4,
              newton_tol64=0.0, newton_tol32=0.0, stream=None, entropy=mm.MM_ENTROPY_OFF, mach_thresh=1.1,
-             steps=mm.MM_STEPS_GLOBAL)
+             steps=mm.MM_STEPS_GLOBAL, alpha_s=0.01, beta_s=0.0)
     p.update(kw)
     return mm.mm_params(p["dim"], p["mode"], p["guess"], p["newton_max_iter"], p["gamma"], p["cfl"],
                         p["newton_tol64"], p["newton_tol32"], p["stream"], p["entropy"], p["steps"],
-                        p["mach_thresh"])
+                        p["mach_thresh"], p["alpha_s"], p["beta_s"])
 
 
 def _create(**kw):
@@ -46,9 +46,13 @@ def _create(**kw):
 
 
 @pytest.mark.parametrize("kw", [dict(dim=1), dict(dim=4), dict(mode=7), dict(guess=3), dict(gamma=1.0),
-                                dict(gamma=float("nan")), dict(cfl=0.0), dict(entropy=2),
+                                dict(gamma=float("nan")), dict(cfl=0.0), dict(entropy=-1),
                                 dict(entropy=mm.MM_ENTROPY_MACH, mach_thresh=float("nan")), dict(steps=2),
-                                dict(steps=-1), dict(steps=mm.MM_STEPS_INDIVIDUAL, entropy=mm.MM_ENTROPY_MACH)])
+                                dict(steps=-1), dict(steps=mm.MM_STEPS_INDIVIDUAL, entropy=mm.MM_ENTROPY_MACH),
+                                dict(entropy=3), dict(entropy=mm.MM_ENTROPY_ENERGY, alpha_s=-0.1),
+                                dict(entropy=mm.MM_ENTROPY_ENERGY, alpha_s=float("nan")),
+                                dict(entropy=mm.MM_ENTROPY_ENERGY, beta_s=float("inf")),
+                                dict(steps=mm.MM_STEPS_INDIVIDUAL, entropy=mm.MM_ENTROPY_ENERGY)])
 def test_create_rejects_bad_params(kw):
     st, ctx = _create(**kw)
     assert st == mm.MM_E_ARG and not ctx.value
