@@ -77,10 +77,12 @@ def l1_rest(a, b, boost):
     return num / np.where(den > 0, den, 1.0)
 
 
-def make_context(mm, learned, m, wl, form, dev, mach_thresh=None, steps=0):
+def make_context(mm, learned, m, wl, form, dev, mach_thresh=None, steps=0, alpha_s=None):
     mode = mm.MM_FP64 if form.startswith("fp64") else mm.MM_MIXED
     guess = mm.MM_GUESS_LEARNED if form.endswith("learned") else mm.MM_GUESS_STANDARD
     ent = {} if mach_thresh is None else {"entropy": mm.MM_ENTROPY_MACH, "mach_thresh": mach_thresh}
+    if alpha_s is not None:
+        ent = {"entropy": mm.MM_ENTROPY_ENERGY, "alpha_s": alpha_s}
     ctx = mm.Context(m.dim, wl.gamma, wl.cfl, mode=mode, guess=guess, device=dev, steps=steps, **ent)
     if guess == mm.MM_GUESS_LEARNED:
         params = learned.load(wl.gamma, dev)
@@ -90,14 +92,16 @@ def make_context(mm, learned, m, wl, form, dev, mach_thresh=None, steps=0):
     return ctx
 
 
-def time_form(mm, learned, torch, wl, dmesh, form, steps, warmup, dev, mach_thresh=None):
+def time_form(mm, learned, torch, wl, dmesh, form, steps, warmup, dev, mach_thresh=None, alpha_s=None):
     """Time `form` on the workload; with mach_thresh, the entropy scheme
-    for cold flows (entropy row in Q, Mach switch at that threshold)."""
+    for cold flows (entropy row in Q, Mach switch at that threshold); with
+    alpha_s, the same scheme with its energy switch."""
     from paper_0901_4107_amd.inputs.configs import with_entropy
     m = wl.mesh
-    ctx = make_context(mm, learned, m, wl, form, dev, mach_thresh)
+    ctx = make_context(mm, learned, m, wl, form, dev, mach_thresh, alpha_s=alpha_s)
     ctx.mm_mesh_upload(dmesh)
-    Q0 = torch.from_numpy(with_entropy(wl) if mach_thresh is not None else np.ascontiguousarray(wl.Q)).to(dev)
+    ent = mach_thresh is not None or alpha_s is not None
+    Q0 = torch.from_numpy(with_entropy(wl) if ent else np.ascontiguousarray(wl.Q)).to(dev)
     Q = Q0.clone()
     rec = ctx.recon_buffer(m.n_cells)
     F = ctx.flux_buffer(m.n_faces)
@@ -326,6 +330,13 @@ def bench_step(args):
                           "face_fluxes_per_s": m.n_faces / (ent["ms"] * 1e-3), "flux_kernel_ms": ent["flux_ms"],
                           "kept_fraction": ent["diag"]["entropy_kept"] / m.n_cells,
                           "step_time_vs_plain": ent["ms"] / head["ms"]}
+        esw = time_form(mm, learned, torch, wl, dmesh, args.mode, args.steps, args.warmup, dev,
+                        alpha_s=args.alpha_s)
+        log(f"{args.mode} with the energy switch: {esw['ms']:.3f} ms/step")
+        out["entropy_energy_switch"] = {"form": args.mode, "alpha_s": args.alpha_s, "ms_per_step": esw["ms"],
+                                        "face_fluxes_per_s": m.n_faces / (esw["ms"] * 1e-3),
+                                        "kept_fraction": esw["diag"]["entropy_kept"] / m.n_cells,
+                                        "step_time_vs_plain": esw["ms"] / head["ms"]}
     if not args.no_entropy:
         out["mesh_motion"] = time_mesh_motion(mm, torch, wl, dmesh, args.steps, dev)
         log(f"mesh motion: {out['mesh_motion']}")
@@ -418,6 +429,8 @@ def main():
     ap.add_argument("--no-entropy", action="store_true", help="skip the run with the entropy scheme for cold flows")
     ap.add_argument("--mach-thresh", type=float, default=1.1, help="Mach switch of the entropy scheme")
     ap.add_argument("--no-individual", action="store_true", help="skip the individual-timestep cycle")
+    ap.add_argument("--alpha-s", type=float, default=0.01,
+                    help="energy switch of the entropy scheme: thermal below alpha_s times the kinetic energy")
     ap.add_argument("--threads", type=int, default=0, help="host threads for the mesh builder")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MB")
     args = ap.parse_args()
