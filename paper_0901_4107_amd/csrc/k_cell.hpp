@@ -324,27 +324,34 @@ struct EnergySwitch {
     int32_t prim_f32;
     int32_t reserved;
     const int32_t *nbr;       // side neighbours, CSR order
-    const double *mvel;       // generator velocities [D][n]
+    const double *mvel;       // generator velocities [D][n] (double records)
+    const float *srec32;      // side records, w_j - w_i at 1 + D (float records)
 };
 
-// M_j |v_j - w|^2 / 2 from cell j's primitive record, M_j = rho_j V_j (0 for
-// a vacuum record).
+// M_j |v_j - w_i|^2 / 2 of the neighbour j across side q of cell i (j = i,
+// q < 0: the cell itself) from j's primitive record, M_j = rho_j V_j (0 for a
+// vacuum record). Double records hold v_j (w_i given); float records hold
+// v_j - w_j, and the side record adds w_j - w_i.
 template <int D>
-__device__ __forceinline__ double ekin_in_frame(const EnergySwitch &es, int64_t j, const double *__restrict__ V,
-                                                int64_t n, const double (&w)[D]) {
+__device__ __forceinline__ double ekin_in_frame(const EnergySwitch &es, int64_t j, int64_t q,
+                                                const double *__restrict__ V, const double (&wi)[D]) {
     using Y = Lay<D>;
-    double rho, v[D];
+    double rho, dv[D];
     if (es.prim_f32) {
-        const float *p = (const float *)es.prim + j * Y::PREC;
-        rho = p[Y::W];
-        for (int k = 0; k < D; k++) v[k] = (double)p[Y::W + 1 + k] + es.mvel[k * n + j];
+        float p[1 + D];
+        load_rec<1 + D>((const float *)es.prim + j * Y::PREC + Y::W, p);
+        rho = p[0];
+        for (int k = 0; k < D; k++) dv[k] = (double)p[1 + k];
+        if (q >= 0)
+            for (int k = 0; k < D; k++) dv[k] += (double)es.srec32[q * Y::SREC32 + 1 + D + k];
     } else {
-        const double *p = (const double *)es.prim + j * Y::PREC;
-        rho = p[Y::W];
-        for (int k = 0; k < D; k++) v[k] = p[Y::W + 1 + k];
+        double p[1 + D];
+        load_rec<1 + D>((const double *)es.prim + j * Y::PREC + Y::W, p);
+        rho = p[0];
+        for (int k = 0; k < D; k++) dv[k] = p[1 + k] - wi[k];
     }
     double e = 0.0;
-    for (int k = 0; k < D; k++) e += (v[k] - w[k]) * (v[k] - w[k]);
+    for (int k = 0; k < D; k++) e += dv[k] * dv[k];
     return rho > 0.0 ? 0.5 * (rho * V[j]) * e : 0.0;
 }
 
@@ -395,9 +402,9 @@ __global__ void __launch_bounds__(kBlock) k_update(int64_t n, const int32_t *__r
     if constexpr (ENT && ESW) {
         {
             double wi[D];
-            for (int k = 0; k < D; k++) wi[k] = es.mvel[k * n + i];
-            for (int32_t q = b + lane; q < e; q += GS) ekmax = fmax(ekmax, ekin_in_frame<D>(es, es.nbr[q], V, n, wi));
-            if (lane == 0) ekmax = fmax(ekmax, ekin_in_frame<D>(es, i, V, n, wi));
+            for (int k = 0; k < D; k++) wi[k] = es.prim_f32 ? 0.0 : es.mvel[k * n + i];
+            for (int32_t q = b + lane; q < e; q += GS) ekmax = fmax(ekmax, ekin_in_frame<D>(es, es.nbr[q], q, V, wi));
+            if (lane == 0) ekmax = fmax(ekmax, ekin_in_frame<D>(es, i, -1, V, wi));
             ekmax = grp_max<GS>(ekmax);
         }
     }

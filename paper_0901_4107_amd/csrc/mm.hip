@@ -456,8 +456,9 @@ mm_status mm_face_fluxes(mm_ctx *c, double dt, const void *recon, double *face_f
 template <int D, bool ENT, bool GRAV, bool ESW = false>
 static void launch_update(mm_ctx *c, const double *flux, double *Q) {
     const Layout &L = c->lay;
-    EnergySwitch es{c->p.alpha_s, c->p.beta_s, c->last_rec, c->p.mode == MM_MIXED ? 1 : 0, 0,
-                    c->at<int32_t>(L.nbr), c->mesh.mesh_vel};
+    const bool mixed = c->p.mode == MM_MIXED;
+    EnergySwitch es{c->p.alpha_s, c->p.beta_s, c->last_rec, mixed ? 1 : 0, 0, c->at<int32_t>(L.nbr),
+                    c->mesh.mesh_vel, mixed ? c->at<float>(L.srec32) : nullptr};
     k_update<D, ENT, GRAV, ESW><<<group_grid(D, c->n), kBlock, 0, c->st()>>>(
         c->n, c->at<int32_t>(L.off), c->at<int32_t>(L.ent), flux, Q, c->at<int32_t>(L.flags) + 1, c->mesh.volume,
         c->p.gamma, c->p.mach_thresh, c->at<DiagDev>(L.diag), c->accel, c->last_dt_dev, c->last_dt, es);
