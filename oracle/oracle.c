@@ -1227,3 +1227,23 @@ double oracle_hydro_step_energy(const om_mesh *M, const om_params *prm, double d
     free(W); free(gr); free(gl); free(fl); free(sf);
     return dt;
 }
+
+/* ------------------------------------------------------------------ */
+/* Reflective walls by mirrored generators: each ghost cell g takes the */
+/* conserved state of its source cell with the momentum component     */
+/* normal to the wall (row 1 + axis) negated, all nrow rows of Q      */
+/* [nrow][N] (the entropy row included when present). The ghosts'      */
+/* generators are the sources' mirror images, so the wall face between */
+/* a cell and its image carries a symmetric Riemann problem: no mass   */
+/* or energy flux, and the momentum flux of the star pressure; the     */
+/* reflective condition for the moving-mesh scheme.                   */
+/* ------------------------------------------------------------------ */
+void oracle_reflect(int32_t nrow, int64_t n, double *Q, int64_t n_ghost, const int32_t *ghost,
+                    const int32_t *src, int32_t axis)
+{
+    for (int64_t k = 0; k < n_ghost; k++) {
+        const int64_t g = ghost[k], s = src[k];
+        for (int c = 0; c < nrow; c++) Q[c * n + g] = Q[c * n + s];
+        Q[(1 + axis) * n + g] = -Q[(1 + axis) * n + s];
+    }
+}

@@ -78,6 +78,7 @@ def _lib():
         lib.oracle_hydro_step_energy.restype = ctypes.c_double
         lib.oracle_hydro_step_energy.argtypes = [ctypes.POINTER(_OMesh), ctypes.POINTER(_OParams), ctypes.c_double,
                                                  _dp, ctypes.c_double, ctypes.c_double, _dp, _ip]
+        lib.oracle_reflect.argtypes = [ctypes.c_int32, ctypes.c_int64, _dp, ctypes.c_int64, _ip, _ip, ctypes.c_int32]
         lib.oracle_tb_criterion.argtypes = [ctypes.POINTER(_OMesh), ctypes.POINTER(_OParams), _dp, _dp]
         lib.oracle_tb_step.restype = ctypes.c_int
         lib.oracle_tb_step.argtypes = [ctypes.POINTER(_OMesh), ctypes.POINTER(_OParams), ctypes.c_double,
@@ -368,3 +369,13 @@ class Timeline:
             self.ti = nxt.value
         return dict(status=st, ti=ti, next=nxt.value if st == 0 else ti, active=active.astype(bool),
                     face_dt=face_dt, pred=pred, n_faces=na.value)
+
+
+def reflect(Q, ghost, src, axis):
+    """Ghost cells' states from their sources with the normal momentum
+    (row 1 + axis) negated; returns a copy of Q [rows][N]."""
+    Q = _f64(Q).copy()
+    g = np.ascontiguousarray(ghost, dtype=np.int32)
+    s = np.ascontiguousarray(src, dtype=np.int32)
+    _lib().oracle_reflect(Q.shape[0], Q.shape[1], _d(Q), g.shape[0], _i(g), _i(s), int(axis))
+    return Q

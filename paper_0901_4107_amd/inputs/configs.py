@@ -255,3 +255,83 @@ def riemann_problems(n: int = 1 << 24, seed: int = 1003, side: int = 64, nthread
     body = [p[:, rng.integers(0, p.shape[1], k)] for p, k in zip(pools, per)]
     out = np.concatenate(body + [riemann_tails(n_tail, gamma, rng)], axis=1)
     return np.ascontiguousarray(out[:, rng.permutation(n)])
+
+
+# ---------------------------------------------------------------------------
+# Reflective walls by mirrored generators.
+#
+# The domain is lo < y < hi (axis 1) inside the unit box, periodic in the
+# other axes. Every generator within `layer` of a wall is mirrored across it
+# into the band [0, lo) or (hi, 1]; the periodic tessellation of the whole
+# set then clips each interior cell exactly at the wall planes (a point of
+# the domain is nearer to an interior generator than to any mirror image),
+# and an interior cell's only face with a mirror cell is the wall face
+# shared with its own image. Before each step the mirror ("ghost") cells
+# take their source cells' states with the normal momentum negated; the
+# wall faces then carry symmetric Riemann problems: no mass or energy
+# flux, the pressure's momentum flux. With layer >= 3 cell spacings the
+# first rows of ghosts see mirrored neighbourhoods, so their gradients are
+# the mirrored ones too.
+# ---------------------------------------------------------------------------
+@dataclass
+class Walls:
+    mesh: Mesh
+    ghost: np.ndarray      # [G] int32 ghost cell indices
+    src: np.ndarray        # [G] int32 their source cells
+    axis: int              # the walls' normal axis
+    interior: np.ndarray   # [N] bool
+
+
+def mirrored_mesh(points: np.ndarray, lo: float, hi: float, layer: float, nthreads: int = 0) -> Walls:
+    """Tessellation of `points` (interior generators, lo < y < hi) with their
+    mirror images across y = lo and y = hi (those within `layer` of a wall),
+    cells in Morton order; lo - layer >= 0 and hi + layer <= 1."""
+    assert lo - layer >= 0.0 and hi + layer <= 1.0
+    p = np.asarray(points, dtype=np.float64)
+    y = p[:, 1]
+    assert np.all((y > lo) & (y < hi))
+    low = np.nonzero(y - lo < layer)[0]
+    high = np.nonzero(hi - y < layer)[0]
+    ml, mh = p[low].copy(), p[high].copy()
+    ml[:, 1] = 2.0 * lo - ml[:, 1]
+    mh[:, 1] = 2.0 * hi - mh[:, 1]
+    allp = np.concatenate([p, ml, mh])
+    n = p.shape[0]
+    src = np.concatenate([low, high])
+    ghost = n + np.arange(src.shape[0])
+    order = morton_order(allp)
+    inv = np.empty_like(order)
+    inv[order] = np.arange(order.shape[0])
+    mesh = build_mesh(allp[order], nthreads)
+    interior = np.zeros(allp.shape[0], bool)
+    interior[inv[:n]] = True
+    return Walls(mesh, inv[ghost].astype(np.int32), inv[src].astype(np.int32), 1, interior)
+
+
+def reflect_states(Q: np.ndarray, walls: Walls) -> np.ndarray:
+    """The ghost cells' conserved states from their sources, the normal
+    momentum negated (rows 1 + axis); Q [rows][N], a copy."""
+    Q = np.array(Q, dtype=np.float64, copy=True)
+    Q[:, walls.ghost] = Q[:, walls.src]
+    Q[1 + walls.axis, walls.ghost] *= -1.0
+    return Q
+
+
+def walled_lattice(nx: int, lo: float = 0.125, hi: float = 0.875, jitter: float = 0.0, seed: int = 0) -> tuple:
+    """2D Cartesian lattice of spacing 1/nx in the domain lo < y < hi
+    (an integral number of rows), mirrored across the walls into the bands
+    outside them (layer lo = 1 - hi). Returns (walls, x, y), the
+    generators' coordinates."""
+    h = 1.0 / nx
+    rows = int(round((hi - lo) / h))
+    assert abs(rows * h - (hi - lo)) < 1e-12
+    xs = (np.arange(nx) + 0.5) * h
+    ys = lo + (np.arange(rows) + 0.5) * h
+    X, Y = np.meshgrid(xs, ys, indexing="ij")
+    pts = np.stack([X.ravel(), Y.ravel()], axis=1)
+    if jitter:
+        rng = np.random.default_rng(seed)
+        pts = pts + rng.uniform(-jitter * h, jitter * h, pts.shape)
+    walls = mirrored_mesh(pts, lo, hi, min(lo, 1.0 - hi))
+    pos = walls.mesh.positions
+    return walls, pos[:, 0], pos[:, 1]

@@ -1,0 +1,155 @@
+"""Pins of reflective walls by mirrored generators (the boundary of the
+paper's Rayleigh-Taylor setup, Section 8): generators near a wall are
+mirrored across it, and before each step the mirror cells take their
+sources' states with the normal momentum negated (oracle_reflect).
+
+Pinned against: the tessellation (each interior cell meets the mirror cells
+only in one face on the wall plane, with its own image); a gas driven into
+a wall against the textbook reflected shock (star pressure of the exact
+solver, whose own pins are independent, and the shock jump); exact
+conservation of mass, energy and the momentum parallel to the walls; an
+isothermal atmosphere in a uniform field held between the walls, its
+residual velocities falling with resolution (at first order: the mirrored
+profile has a kink at the wall that the limiter flattens)."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_0901_4107_amd.inputs.configs import (conserved_from_primitive, mirrored_mesh, poisson_points,
+                                                walled_lattice)
+
+LO, HI = 0.125, 0.875
+
+
+def wall_faces(w):
+    m = w.mesh
+    ghost = np.zeros(m.n_cells, bool)
+    ghost[w.ghost] = True
+    L, R = m.face_L, m.face_R
+    return np.nonzero((w.interior[L] & ghost[R]) | (w.interior[R] & ghost[L]))[0], ghost
+
+
+@pytest.mark.parametrize("kind", ["lattice", "jittered", "poisson"])
+def test_wall_faces(kind):
+    """Every interior cell touching a wall meets the mirror cells in exactly
+    one face, with its own image, lying on the wall plane with the wall's
+    normal; the walls' total area is the box width twice and the interior
+    volume is the domain's."""
+    if kind == "poisson":
+        rng = np.random.default_rng(921)
+        pts = poisson_points(1500, 2, rng)
+        pts = pts[(pts[:, 1] > LO) & (pts[:, 1] < HI)]
+        w = mirrored_mesh(pts, LO, HI, LO)
+    else:
+        w, _, _ = walled_lattice(32, jitter=0.2 if kind == "jittered" else 0.0, seed=922)
+    m = w.mesh
+    faces, ghost = wall_faces(w)
+    src_of = -np.ones(m.n_cells, np.int64)
+    src_of[w.ghost] = w.src
+    L, R = m.face_L[faces], m.face_R[faces]
+    inner = np.where(ghost[R], L, R)
+    outer = np.where(ghost[R], R, L)
+    assert np.all(src_of[outer] == inner)
+    assert len(np.unique(inner)) == len(inner)
+    d = m.face_sep[:, faces]
+    assert np.allclose(d[0], 0.0, atol=1e-12)             # normal along y
+    fy = m.positions[L, 1] + m.face_ctr[1, faces]           # centroid height
+    assert np.all(np.minimum(np.abs(fy - LO), np.abs(fy - HI)) < 1e-12)
+    assert abs(m.face_area[faces].sum() - 2.0) < 1e-10
+    assert abs(m.volume[w.interior].sum() - (HI - LO)) < 1e-12
+
+
+def run(w, Q, t_end, g, accel=None):
+    m = w.mesh
+    t = 0.0
+    while t < t_end:
+        Q = O.reflect(Q, w.ghost, w.src, 1)
+        W = O.prim(2, g, m.volume, Q)
+        dt = min(O.cfl_dt(m, g, 0.4, W), t_end - t)
+        if accel is None:
+            Q, used = O.hydro_step(m, g, 0.4, Q, dt=dt)
+        else:
+            Q, used, _ = O.hydro_step_full(m, g, 0.4, Q, dt=dt, accel=accel)
+        t += used
+    return Q
+
+
+def test_reflected_shock():
+    """Gas at rest density and pressure 1 moving at u = 1 into the lower
+    wall: a shock reflects with the star state of the colliding streams
+    (rho, +u, P | rho, -u, P) behind it, velocity zero, pressure p* from the
+    exact solver, density from the shock jump
+    rho*/rho = (p*/P + mu) / (mu p*/P + 1), mu = (g-1)/(g+1), moving away at
+    s = u rho / (rho* - rho). At t = 0.2 on a 64-column lattice the rows
+    between the wall and the front hold p* to 2.5%, rho* to 3.5% and |v| <
+    0.04 u (the first row, with the usual start-up dip, and the rows at the
+    front excepted), and the front is within one row of its exact height."""
+    g = 5.0 / 3.0
+    w, x, y = walled_lattice(64)
+    m = w.mesh
+    n = m.n_cells
+    Q = conserved_from_primitive(m.volume, np.ones(n), np.stack([np.zeros(n), np.full(n, -1.0)]), np.ones(n), g)
+    r = O.riemann(g, 1.0, 1.0, 1.0, 1.0, -1.0, 1.0)
+    ps = float(r["pstar"][0])
+    mu = (g - 1.0) / (g + 1.0)
+    rs = (ps + mu) / (mu * ps + 1.0)
+    s = 1.0 / (rs - 1.0)
+    W = O.prim(2, g, m.volume, run(w, Q, 0.2, g))
+    it = w.interior
+    h = 1.0 / 64
+    front = LO + s * 0.2
+    behind = it & (y > LO + 1.5 * h) & (y < front - 2 * h)
+    assert behind.sum() > 6 * 64
+    assert np.all(np.abs(W[3, behind] / ps - 1.0) < 0.025)
+    assert np.all(np.abs(W[0, behind] / rs - 1.0) < 0.035)
+    assert np.all(np.abs(W[2, behind]) < 0.04)
+    rows = np.unique(np.round(y[it], 9))
+    P_row = np.array([W[3, it][np.abs(y[it] - yy) < 1e-6].mean() for yy in rows])
+    k = np.nonzero(P_row < 0.5 * (ps + 1.0))[0][0]          # first row beyond the front
+    y_front = rows[k - 1] + (rows[k] - rows[k - 1]) * (P_row[k - 1] - 0.5 * (ps + 1.0)) / (P_row[k - 1] - P_row[k])
+    assert abs(y_front - front) < h
+
+
+def test_conservation_with_walls():
+    """A sheared, compressed flow bouncing between the walls: the interior
+    totals of mass, energy and x-momentum (parallel to the walls) stay at
+    their initial values to round-off; the y-momentum does not (the walls
+    push)."""
+    g = 1.4
+    rng = np.random.default_rng(923)
+    w, x, y = walled_lattice(32, jitter=0.2, seed=924)
+    m = w.mesh
+    n = m.n_cells
+    rho = 1.0 + 0.3 * np.sin(2 * np.pi * x) * np.cos(3 * np.pi * y)
+    vel = np.stack([0.5 * np.sin(2 * np.pi * y), -0.7 * np.cos(2 * np.pi * x)])
+    P = 1.0 + 0.2 * rng.uniform(size=n)
+    Q = O.reflect(conserved_from_primitive(m.volume, rho, vel, P, g), w.ghost, w.src, 1)
+    it = w.interior
+    tot0 = Q[:, it].sum(axis=1)
+    Q = run(w, Q, 0.3, g)
+    tot = Q[:, it].sum(axis=1)
+    scale = np.abs(Q[:, it]).sum(axis=1)
+    for c in (0, 1, 3):
+        assert abs(tot[c] - tot0[c]) < 1e-13 * scale[c], c
+    assert abs(tot[2] - tot0[2]) > 1e-3 * scale[2]
+
+
+def test_atmosphere_between_walls():
+    """rho = exp(-g0 (y - lo) / c^2), P = rho c^2 in the field g = -g0 y
+    (mirrored in the ghost cells) is in equilibrium; to t = 0.3 the interior
+    residual velocities stay below 0.012 c on 16 columns and fall by at
+    least 1.8 per halving of the spacing."""
+    g = 5.0 / 3.0
+    res = []
+    for nx in (16, 32):
+        w, x, y = walled_lattice(nx)
+        m = w.mesh
+        n = m.n_cells
+        rho = np.exp(-0.5 * (y - LO))
+        acc = np.zeros((2, n))
+        acc[1] = -0.5
+        acc[1, w.ghost] = 0.5
+        Q = O.reflect(conserved_from_primitive(m.volume, rho, np.zeros((2, n)), rho, g), w.ghost, w.src, 1)
+        W = O.prim(2, g, m.volume, run(w, Q, 0.3, g, accel=acc))
+        res.append(np.abs(W[1:3][:, w.interior]).max())
+    assert res[0] < 0.012 and res[0] / res[1] > 1.8, res
