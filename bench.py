@@ -18,7 +18,9 @@ HIP events on the library's stream) and the CPU oracle's rate on the host
 cold flows (Section 3.5: entropy row, Mach switch at --mach-thresh) and
 reported under "entropy"; the mesh-motion entry points (Section 4.1
 generator velocities, volume rate, velocity replacement) are timed on the
-same mesh under "mesh_motion". ``--workload riemann`` instead times the batched
+same mesh under "mesh_motion". ``--workload rt3d`` times the step with
+reflective walls and a static field (Section 8.8's setup, mirror cells
+included in the cell and face counts). ``--workload riemann`` instead times the batched
 exact solver on 2^24 independent Riemann problems (standard vs learned
 guess).
 """
@@ -100,6 +102,11 @@ def time_form(mm, learned, torch, wl, dmesh, form, steps, warmup, dev, mach_thre
     m = wl.mesh
     ctx = make_context(mm, learned, m, wl, form, dev, mach_thresh, alpha_s=alpha_s)
     ctx.mm_mesh_upload(dmesh)
+    if wl.walls is not None:
+        ctx.mm_set_walls(torch.from_numpy(wl.walls.ghost).to(dev), torch.from_numpy(wl.walls.src).to(dev),
+                         wl.walls.axis)
+    if wl.accel is not None:
+        ctx.mm_set_gravity(torch.from_numpy(np.ascontiguousarray(wl.accel)).to(dev))
     ent = mach_thresh is not None or alpha_s is not None
     Q0 = torch.from_numpy(with_entropy(wl) if ent else np.ascontiguousarray(wl.Q)).to(dev)
     Q = Q0.clone()
@@ -115,7 +122,10 @@ def time_form(mm, learned, torch, wl, dmesh, form, steps, warmup, dev, mach_thre
     for _ in range(warmup):
         ctx.mm_hydro_step(Q, sync=False)
     torch.cuda.synchronize()
-    tot0 = Q.sum(dim=1)
+    # totals over the domain: the mirror cells of walls are excluded
+    keep = (slice(None) if wl.walls is None else
+            torch.from_numpy(np.nonzero(wl.walls.interior)[0]).to(dev))
+    tot0 = Q[:, keep].sum(dim=1)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t_wall = time.perf_counter()
     e0.record(stream)
@@ -127,10 +137,10 @@ def time_form(mm, learned, torch, wl, dmesh, form, steps, warmup, dev, mach_thre
     ms = e0.elapsed_time(e1) / steps
     # conservation over the timed steps: change of the totals of m, p, E,
     # relative to the total mass, momentum magnitude and energy
-    tot1 = Q.sum(dim=1)
+    tot1 = Q[:, keep].sum(dim=1)
     D = m.dim
     scale = torch.abs(tot0).clone()
-    scale[1:1 + D] = torch.sqrt(torch.sum(Q[1:1 + D] ** 2, dim=0)).sum()
+    scale[1:1 + D] = torch.sqrt(torch.sum(Q[1:1 + D][:, keep] ** 2, dim=0)).sum()
     cons = (torch.abs(tot1 - tot0) / scale).cpu().numpy()
     # the dominant kernel alone, on the initial state's records
     ctx.mm_gradients(Q0, rec)
@@ -267,6 +277,8 @@ def bench_step(args):
         wl = configs.kh3d(n_points=(args.size or 128) ** 3, nthreads=args.threads)
     elif args.workload == "random3d":
         wl = configs.random3d(n_side=args.size or 64, nthreads=args.threads)
+    elif args.workload == "rt3d":
+        wl = configs.rt3d(n_side=args.size or 128, nthreads=args.threads)
     else:
         wl = configs.sedov3d(n_side=args.size or 256, nthreads=args.threads)
     m = wl.mesh
@@ -302,8 +314,9 @@ def bench_step(args):
     nbytes, per_face, per_cell = flux_kernel_bytes(m.dim, m.n_cells, m.n_faces, mixed)
     achieved = nbytes / (head["flux_ms"] * 1e-3) / 1e9
     lrn = 'true' if args.mode.endswith('learned') else 'false'
-    kname = (f"k_face_flux_mixed<{m.dim}, {lrn}, false, false>" if mixed
-             else f"k_face_flux64<{m.dim}, {lrn}, false, false>")
+    grv = 'true' if wl.accel is not None else 'false'
+    kname = (f"k_face_flux_mixed<{m.dim}, {lrn}, false, {grv}>" if mixed
+             else f"k_face_flux64<{m.dim}, {lrn}, false, {grv}>")
     from paper_0901_4107_amd.prof_summary import read_traffic
     traffic = read_traffic(os.path.join(ROOT, "profiles"), kname, wl.name)
     out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -340,7 +353,10 @@ def bench_step(args):
     if not args.no_entropy:
         out["mesh_motion"] = time_mesh_motion(mm, torch, wl, dmesh, args.steps, dev)
         log(f"mesh motion: {out['mesh_motion']}")
-    if not args.no_individual:
+    if wl.walls is not None:
+        out["config"]["walls"] = {"axis": wl.walls.axis, "mirror_cells": int(len(wl.walls.ghost)),
+                                  "domain_cells": int(wl.walls.interior.sum()), "field": "uniform -0.1 along y"}
+    if not args.no_individual and wl.walls is None and wl.accel is None:   # neither combines with a timeline
         ind = time_individual(mm, learned, torch, wl, dmesh, args.mode, head["dt"], head["ms"], dev)
         out["individual_timesteps"] = ind
         log(f"individual timesteps: {ind['points_per_cycle']} points, {ind['cycle_ms']:.2f} ms per cycle of "
@@ -421,7 +437,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="kh3d", choices=["kh3d", "random3d", "sedov3d", "riemann"])
+    ap.add_argument("--workload", default="kh3d", choices=["kh3d", "random3d", "sedov3d", "rt3d", "riemann"])
     ap.add_argument("--size", type=int, default=0, help="points per axis (lattice) or cube root of the point count")
     ap.add_argument("--mode", default="mixed+learned", choices=["fp64", "fp64+learned", "mixed", "mixed+learned"])
     ap.add_argument("--no-compare", action="store_true", help="skip the double-precision comparison run")

@@ -274,6 +274,35 @@ mm_status mm_mesh_set_velocity(mm_ctx *ctx, const double *mesh_vel);
  * fixed over the step. MM_E_STATE without a mesh. */
 mm_status mm_set_gravity(mm_ctx *ctx, const double *accel);
 
+/* Reflective walls by mirrored generators (the boundary of the paper's
+ * Rayleigh-Taylor test, Section 8; the mirroring of Section 3.6,
+ * boundary conditions). The uploaded mesh is the caller's
+ * tessellation of the generators together with their mirror images across
+ * each wall plane normal to coordinate axis `axis` (0 <= axis < D), so that
+ * the cells of the images close the domain at the walls. ghost [n_ghost]
+ * and src [n_ghost] (int32 device arrays, kept by reference until the next
+ * mm_mesh_upload, which clears them, or the next mm_set_walls) name each
+ * mirror cell and the cell it images. n_ghost = 0 removes the walls.
+ * Before each step, mm_hydro_step sets every mirror cell's state to its
+ * source's with the momentum along `axis` negated (every other row of Q,
+ * the entropy row included, copied), so that each wall face carries a
+ * symmetric Riemann problem; the caller's split path calls mm_reflect
+ * before mm_gradients. The mirror cells are then cells like the others:
+ * they are updated by the step and overwritten by the next reflection, and
+ * sums over the domain exclude them. A field set with mm_set_gravity must
+ * hold the mirrored field (its component along `axis` negated) at the
+ * mirror cells. Checks the lists on the device and synchronises: MM_E_ARG
+ * if n_ghost is negative or not below N, a pointer is NULL, `axis` is out
+ * of range, an index is outside [0, N), a mirror cell is its own source,
+ * listed twice or the source of another (the walls are then removed);
+ * MM_E_STATE without a mesh. Ends a timeline (mm_tb_begin). */
+mm_status mm_set_walls(mm_ctx *ctx, int64_t n_ghost, const int32_t *ghost, const int32_t *src, int32_t axis);
+
+/* The reflection of mm_set_walls on Q ([nrow][N] device, nrow = D+2, or
+ * D+3 with the entropy row), enqueued on the context's stream; nothing
+ * without walls. MM_E_STATE without a mesh. */
+mm_status mm_reflect(mm_ctx *ctx, double *Q);
+
 /* ------------------------------------------------------------------------
  * Learned starting guess for the Newton iteration on the star pressure
  * (a 3 -> 64 -> 64 -> 1 ReLU network; not part of the paper's method, which
@@ -368,7 +397,7 @@ mm_status mm_reset_diag(mm_ctx *ctx);
  * shared); mm_tb_step then returns MM_E_STATE until the next mm_tb_begin.
  * The tessellation stays fixed along the timeline; with moving generators
  * the caller rebuilds and re-uploads the mesh and begins a new timeline.
- * Static gravity is not combined with it (MM_E_STATE).
+ * Static gravity and walls are not combined with it (MM_E_STATE).
  * ------------------------------------------------------------------------ */
 typedef struct {
     int64_t tick;          /* the last point performed (ticks) */

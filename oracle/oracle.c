@@ -1229,7 +1229,8 @@ double oracle_hydro_step_energy(const om_mesh *M, const om_params *prm, double d
 }
 
 /* ------------------------------------------------------------------ */
-/* Reflective walls by mirrored generators: each ghost cell g takes the */
+/* Reflective walls by mirrored generators (Section 3.6, boundary     */
+/* conditions): each ghost cell g takes the                           */
 /* conserved state of its source cell with the momentum component     */
 /* normal to the wall (row 1 + axis) negated, all nrow rows of Q      */
 /* [nrow][N] (the entropy row included when present). The ghosts'      */

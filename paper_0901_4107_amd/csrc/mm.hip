@@ -24,6 +24,7 @@
 #include "k_learn.hpp"
 #include "k_mesh.hpp"
 #include "k_tb.hpp"
+#include "k_walls.hpp"
 #include "layout.hpp"
 
 using namespace mm;
@@ -129,6 +130,11 @@ struct mm_ctx {
     double last_dt = 0.0;                 // ... or its value
     bool have_dt = false;
     const void *last_rec = nullptr;       // records of the last gradient pass
+    struct Walls {      // mirror cells of reflective walls (caller's device lists)
+        int64_t n = 0;
+        const int32_t *ghost = nullptr, *src = nullptr;
+        int32_t axis = 0;
+    } walls;
     struct Timeline {   // host copies; the state itself is in the info block
         bool on = false;
         double dt_max = 0.0;
@@ -298,7 +304,8 @@ mm_status mm_mesh_upload(mm_ctx *c, const mm_mesh *m) {
     c->have_mesh = false;
     c->tb.on = false;
     c->last_rec = nullptr;
-    c->accel = nullptr;   // a field belongs to the mesh it was set for
+    c->accel = nullptr;   // a field and walls belong to the mesh they were set for
+    c->walls = mm_ctx::Walls();
     c->have_dt = false;
     c->lay = L;
     c->n = n;
@@ -487,6 +494,50 @@ mm_status mm_set_gravity(mm_ctx *c, const double *accel) {
     return MM_OK;
 }
 
+static int row_count(const mm_ctx *c) { return c->D + 2 + (c->p.entropy ? 1 : 0); }
+
+static void launch_reflect(mm_ctx *c, double *Q) {
+    k_reflect<<<plain_grid(c->walls.n), kBlock, 0, c->st()>>>(c->n, c->walls.n, row_count(c), c->walls.axis,
+                                                              c->walls.ghost, c->walls.src, Q);
+}
+
+mm_status mm_set_walls(mm_ctx *c, int64_t n_ghost, const int32_t *ghost, const int32_t *src, int32_t axis) {
+    if (!c) return MM_E_ARG;
+    if (!c->have_mesh) return MM_E_STATE;
+    if (n_ghost < 0 || n_ghost >= c->n) return MM_E_ARG;
+    c->walls = mm_ctx::Walls();
+    c->tb.on = false;   // a timeline does not reflect
+    if (n_ghost == 0) return MM_OK;
+    if (!ghost || !src || axis < 0 || axis >= c->D) return MM_E_ARG;
+    const Layout &L = c->lay;
+    hipStream_t s = c->st();
+    int32_t *flag = c->at<int32_t>(L.flags) + 8;
+    int32_t *mark = c->at<int32_t>(L.cursor);   // free after the upload
+    k_fill_i32<<<1, kBlock, 0, s>>>(flag, 1, 0);
+    k_fill_i32<<<plain_grid(c->n), kBlock, 0, s>>>(mark, c->n, 0);
+    k_walls_mark<<<plain_grid(n_ghost), kBlock, 0, s>>>(c->n, n_ghost, ghost, src, mark, flag);
+    k_walls_check<<<plain_grid(n_ghost), kBlock, 0, s>>>(c->n, n_ghost, ghost, src, mark, flag);
+    MM_LAUNCH_CHECK();
+    int32_t bad = 0;
+    MM_CHECK(hipMemcpyAsync(&bad, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    MM_CHECK(hipStreamSynchronize(s));
+    if (bad) return MM_E_ARG;
+    c->walls.n = n_ghost;
+    c->walls.ghost = ghost;
+    c->walls.src = src;
+    c->walls.axis = axis;
+    return MM_OK;
+}
+
+mm_status mm_reflect(mm_ctx *c, double *Q) {
+    if (!c || !Q) return MM_E_ARG;
+    if (!c->have_mesh) return MM_E_STATE;
+    if (!c->walls.n) return MM_OK;
+    launch_reflect(c, Q);
+    MM_LAUNCH_CHECK();
+    return MM_OK;
+}
+
 mm_status mm_mesh_velocity(mm_ctx *c, const double *Q, double eta, double chi, double dt_lloyd, double *w_out) {
     if (!c || !Q || !w_out) return MM_E_ARG;
     if (!(eta > 0.0) || !(chi >= 0.0) || !isfinite(eta) || !isfinite(chi) || !(dt_lloyd >= 0.0) || !isfinite(dt_lloyd))
@@ -539,6 +590,10 @@ mm_status mm_hydro_step(mm_ctx *c, double *Q, double dt, double *dt_used) {
     c->tb.on = false;   // the step rewrites the cell records a timeline keeps
     const Layout &L = c->lay;
     hipStream_t s = c->st();
+    if (c->walls.n) {
+        launch_reflect(c, Q);
+        MM_LAUNCH_CHECK();
+    }
     void *rec = c->p.mode == MM_FP64 ? (void *)c->at<double>(L.rec) : (void *)c->at<float>(L.rec32);
     double *dt_part = c->at<double>(L.dtpart);
     double *dt_dev = c->at<double>(L.dtdev);
@@ -813,7 +868,7 @@ template <int D, typename T> static void tb_point(mm_ctx *c, double *Q, T *rec) 
 
 mm_status mm_tb_advance(mm_ctx *c, double *Q, int64_t until_tick, int32_t max_points, mm_tb_info *out) {
     if (!c || !Q || max_points < 1) return MM_E_ARG;
-    if (!c->have_mesh || !c->tb.on || c->accel) return MM_E_STATE;
+    if (!c->have_mesh || !c->tb.on || c->accel || c->walls.n) return MM_E_STATE;
     const Layout &L = c->lay;
     hipStream_t s = c->st();
     const bool f64 = c->p.mode == MM_FP64;

@@ -15,6 +15,8 @@ Workloads
   kh3d       3D Kelvin-Helmholtz shear layer on Poisson points with a uniform
              bulk boost and a comoving mesh (Galilean-invariance workload).
   sedov3d    3D Sedov-Taylor blast on a jittered lattice (Section 8.4).
+  rt3d       3D single-mode Rayleigh-Taylor setup (Section 8.8) between two
+             reflective walls in a static field, on a jittered lattice.
 """
 from __future__ import annotations
 
@@ -35,6 +37,8 @@ class Workload:
     boost: np.ndarray      # [D] uniform bulk velocity added to the flow (zeros if none)
     seed: int
     prim: tuple = None     # (rho [N], vel [D][N], P [N]) the initial primitive fields
+    walls: "Walls" = None  # reflective walls (mirror cells), if any
+    accel: np.ndarray = None   # [D][N] static field, if any
 
     @property
     def dim(self) -> int:
@@ -308,15 +312,6 @@ def mirrored_mesh(points: np.ndarray, lo: float, hi: float, layer: float, nthrea
     return Walls(mesh, inv[ghost].astype(np.int32), inv[src].astype(np.int32), 1, interior)
 
 
-def reflect_states(Q: np.ndarray, walls: Walls) -> np.ndarray:
-    """The ghost cells' conserved states from their sources, the normal
-    momentum negated (rows 1 + axis); Q [rows][N], a copy."""
-    Q = np.array(Q, dtype=np.float64, copy=True)
-    Q[:, walls.ghost] = Q[:, walls.src]
-    Q[1 + walls.axis, walls.ghost] *= -1.0
-    return Q
-
-
 def walled_lattice(nx: int, lo: float = 0.125, hi: float = 0.875, jitter: float = 0.0, seed: int = 0) -> tuple:
     """2D Cartesian lattice of spacing 1/nx in the domain lo < y < hi
     (an integral number of rows), mirrored across the walls into the bands
@@ -335,3 +330,38 @@ def walled_lattice(nx: int, lo: float = 0.125, hi: float = 0.875, jitter: float 
     walls = mirrored_mesh(pts, lo, hi, min(lo, 1.0 - hi))
     pos = walls.mesh.positions
     return walls, pos[:, 0], pos[:, 1]
+
+
+def rt3d(n_side: int = 128, layer: int = 4, jitter: float = 0.1, seed: int = 1005, nthreads: int = 0) -> Workload:
+    """Rayleigh-Taylor setup of Section 8.8 in the unit box: reflective walls
+    at y = lo = layer h and y = hi = 1 - lo (h = 1/n_side; the generators in
+    lo < y < hi a jittered lattice, their mirror images filling the `layer`
+    rows beyond each wall), periodic in x and z. rho = 2 above the mid-plane
+    y = 1/2, 1 below; gamma = 1.4; P = P0 + g (y - 1/2) rho with P0 = 2.5 and
+    g = -0.1 (hydrostatic); v_y = w0 [1 - cos(2 pi x)][1 - cos(2 pi (y - lo)
+    / (hi - lo))] with w0 = 0.0025, one mode vanishing at the walls (the
+    paper's box is 0.5 x 1.5; this one is 1 x (hi - lo), uniform in z). The
+    field at the mirror cells is mirrored (+0.1). Mesh at rest."""
+    rng = np.random.default_rng(seed)
+    gamma = 1.4
+    h = 1.0 / n_side
+    lo, hi = layer * h, 1.0 - layer * h
+    rows = n_side - 2 * layer
+    axes = [(np.arange(n_side) + 0.5) * h, lo + (np.arange(rows) + 0.5) * h, (np.arange(n_side) + 0.5) * h]
+    pts = np.stack(np.meshgrid(*axes, indexing="ij"), axis=-1).reshape(-1, 3)
+    pts = pts + rng.uniform(-jitter, jitter, size=pts.shape) * h
+    pts[:, 0] = np.mod(pts[:, 0], 1.0)
+    pts[:, 2] = np.mod(pts[:, 2], 1.0)
+    walls = mirrored_mesh(pts, lo, hi, lo, nthreads)
+    mesh = walls.mesh
+    n = mesh.n_cells
+    x, y = mesh.positions[:, 0], mesh.positions[:, 1]
+    rho = np.where(y > 0.5, 2.0, 1.0)
+    P = 2.5 - 0.1 * (y - 0.5) * rho
+    vy = 0.0025 * (1.0 - np.cos(2 * np.pi * x)) * (1.0 - np.cos(2 * np.pi * (y - lo) / (hi - lo)))
+    vel = np.stack([np.zeros(n), vy, np.zeros(n)])
+    Q = conserved_from_primitive(mesh.volume, rho, vel, P, gamma)
+    accel = np.zeros((3, n))
+    accel[1] = -0.1
+    accel[1, walls.ghost] = 0.1
+    return Workload(f"rt3d_{n_side}^3", mesh, Q, gamma, 0.4, np.zeros(3), seed, (rho, vel, P), walls, accel)

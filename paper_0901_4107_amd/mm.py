@@ -92,6 +92,8 @@ SIGNATURES = {
     "mm_volume_rate": (ctypes.c_int32, [_vp, _vp]),
     "mm_mesh_set_velocity": (ctypes.c_int32, [_vp, _vp]),
     "mm_set_gravity": (ctypes.c_int32, [_vp, _vp]),
+    "mm_set_walls": (ctypes.c_int32, [_vp, ctypes.c_int64, _vp, _vp, ctypes.c_int32]),
+    "mm_reflect": (ctypes.c_int32, [_vp, _vp]),
     "mm_tb_begin": (ctypes.c_int32, [_vp, ctypes.c_double, ctypes.c_int32]),
     "mm_tb_step": (ctypes.c_int32, [_vp, _vp, ctypes.POINTER(mm_tb_info)]),
     "mm_tb_advance": (ctypes.c_int32, [_vp, _vp, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(mm_tb_info)]),
@@ -273,6 +275,16 @@ class Context:
     def mm_set_gravity(self, accel: torch.Tensor | None):
         _check("mm_set_gravity", lib().mm_set_gravity(self._ctx, _ptr(accel)))
         self._accel = accel  # kept alive while the library refers to it
+
+    def mm_set_walls(self, ghost: torch.Tensor | None, src: torch.Tensor | None, axis: int = 1):
+        """Mirror cells ghost [k] of src [k] (int32 device); None removes the walls."""
+        n = 0 if ghost is None else int(ghost.numel())
+        self._walls = None
+        _check("mm_set_walls", lib().mm_set_walls(self._ctx, n, _ptr(ghost), _ptr(src), int(axis)))
+        self._walls = (ghost, src)  # kept alive while the library refers to them
+
+    def mm_reflect(self, Q: torch.Tensor):
+        _check("mm_reflect", lib().mm_reflect(self._ctx, _ptr(Q)))
 
     def mm_volume_rate(self, rate: torch.Tensor):
         _check("mm_volume_rate", lib().mm_volume_rate(self._ctx, _ptr(rate)))

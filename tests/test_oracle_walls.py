@@ -1,5 +1,6 @@
 """Pins of reflective walls by mirrored generators (the boundary of the
-paper's Rayleigh-Taylor setup, Section 8): generators near a wall are
+Rayleigh-Taylor test of Section 8, by the mirroring of Section 3.6,
+boundary conditions): generators near a wall are
 mirrored across it, and before each step the mirror cells take their
 sources' states with the normal momentum negated (oracle_reflect).
 
@@ -153,3 +154,26 @@ def test_atmosphere_between_walls():
         W = O.prim(2, g, m.volume, run(w, Q, 0.3, g, accel=acc))
         res.append(np.abs(W[1:3][:, w.interior]).max())
     assert res[0] < 0.012 and res[0] / res[1] > 1.8, res
+
+
+def test_rt3d_setup():
+    """The Rayleigh-Taylor workload: the domain between the walls holds its
+    volume, the mirror cells hold the mirrored field, the pressure is
+    hydrostatic (dP/dy = g rho on either side of the mid-plane, continuous
+    across it), and the perturbation vanishes at the walls."""
+    from paper_0901_4107_amd.inputs.configs import rt3d
+    wl = rt3d(n_side=16)
+    w, m = wl.walls, wl.mesh
+    h = 1.0 / 16
+    lo, hi = 4 * h, 1.0 - 4 * h
+    assert abs(m.volume[w.interior].sum() - (hi - lo)) < 1e-12
+    assert np.all(wl.accel[1, w.interior] == -0.1) and np.all(wl.accel[1, w.ghost] == 0.1)
+    rho, vel, P = wl.prim
+    y = m.positions[:, 1]
+    for side, r in ((y > 0.5, 2.0), (y < 0.5, 1.0)):
+        assert np.all(rho[side] == r)
+        slope, at_mid = np.polyfit(y[side] - 0.5, P[side], 1)
+        assert abs(slope + 0.1 * r) < 1e-10 and abs(at_mid - 2.5) < 1e-12
+    assert np.abs(vel[1][np.abs(y - lo) < 1e-3 * h]).max(initial=0.0) < 1e-12
+    faces, ghost = wall_faces(w)
+    assert abs(m.face_area[faces].sum() - 2.0) < 1e-10
