@@ -286,19 +286,21 @@ class Walls:
     interior: np.ndarray   # [N] bool
 
 
-def mirrored_mesh(points: np.ndarray, lo: float, hi: float, layer: float, nthreads: int = 0) -> Walls:
-    """Tessellation of `points` (interior generators, lo < y < hi) with their
-    mirror images across y = lo and y = hi (those within `layer` of a wall),
-    cells in Morton order; lo - layer >= 0 and hi + layer <= 1."""
+def mirrored_mesh(points: np.ndarray, lo: float, hi: float, layer: float, nthreads: int = 0,
+                  axis: int = 1) -> Walls:
+    """Tessellation of `points` (interior generators, lo < x_axis < hi, y by
+    default) with their mirror images across the walls x_axis = lo and
+    x_axis = hi (those within `layer` of a wall), cells in Morton order;
+    lo - layer >= 0 and hi + layer <= 1."""
     assert lo - layer >= 0.0 and hi + layer <= 1.0
     p = np.asarray(points, dtype=np.float64)
-    y = p[:, 1]
+    y = p[:, axis]
     assert np.all((y > lo) & (y < hi))
     low = np.nonzero(y - lo < layer)[0]
     high = np.nonzero(hi - y < layer)[0]
     ml, mh = p[low].copy(), p[high].copy()
-    ml[:, 1] = 2.0 * lo - ml[:, 1]
-    mh[:, 1] = 2.0 * hi - mh[:, 1]
+    ml[:, axis] = 2.0 * lo - ml[:, axis]
+    mh[:, axis] = 2.0 * hi - mh[:, axis]
     allp = np.concatenate([p, ml, mh])
     n = p.shape[0]
     src = np.concatenate([low, high])
@@ -309,7 +311,7 @@ def mirrored_mesh(points: np.ndarray, lo: float, hi: float, layer: float, nthrea
     mesh = build_mesh(allp[order], nthreads)
     interior = np.zeros(allp.shape[0], bool)
     interior[inv[:n]] = True
-    return Walls(mesh, inv[ghost].astype(np.int32), inv[src].astype(np.int32), 1, interior)
+    return Walls(mesh, inv[ghost].astype(np.int32), inv[src].astype(np.int32), axis, interior)
 
 
 def walled_lattice(nx: int, lo: float = 0.125, hi: float = 0.875, jitter: float = 0.0, seed: int = 0) -> tuple:
