@@ -366,7 +366,11 @@ def bench_step(args):
         from oracle import oracle as O
         log("cpu baseline: oracle hydro step on the full workload (1 thread)")
         t = time.time()
-        O.hydro_step(m, wl.gamma, wl.cfl, wl.Q)
+        if wl.walls is None and wl.accel is None:
+            O.hydro_step(m, wl.gamma, wl.cfl, wl.Q)
+        else:   # the same work as the device step: reflection, step with the field
+            Q = wl.Q if wl.walls is None else O.reflect(wl.Q, wl.walls.ghost, wl.walls.src, wl.walls.axis)
+            O.hydro_step_full(m, wl.gamma, wl.cfl, Q, accel=wl.accel)
         el = time.time() - t
         out["cpu_baseline"] = {"value": m.n_faces / el, "unit": "face-fluxes/s", "cores": 1, "kind": "oracle",
                                "sample": f"one full oracle hydro step on the whole {wl.name} workload "
