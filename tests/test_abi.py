@@ -100,6 +100,11 @@ def test_workspace_and_state_errors_without_device():
         assert L.mm_mesh_set_velocity(ctx, P) == mm.MM_E_STATE
         assert L.mm_set_gravity(ctx, P) == mm.MM_E_STATE
         assert L.mm_volume_rate(ctx, None) == mm.MM_E_ARG
+        # walls: no context, then the missing mesh (lists are checked on the device after that)
+        assert L.mm_set_walls(None, 4, P, P, 1) == mm.MM_E_ARG
+        assert L.mm_set_walls(ctx, 4, P, P, 1) == mm.MM_E_STATE
+        assert L.mm_reflect(ctx, None) == mm.MM_E_ARG
+        assert L.mm_reflect(ctx, P) == mm.MM_E_STATE
     finally:
         L.mm_destroy(ctx)
     assert L.mm_destroy(None) == mm.MM_OK

@@ -212,6 +212,9 @@ def test_wall_list_checks():
         ctx.mm_tb_step(dev(Q))
     assert e.value.status == mm.MM_E_STATE
     ctx.mm_set_walls(None, None)
+    Qd = dev(Q)
+    ctx.mm_reflect(Qd)          # nothing without walls
+    assert np.array_equal(Qd.cpu().numpy(), Q)
     ctx.mm_tb_begin(0.01, 4)
     ctx.mm_tb_step(dev(Q))
     # a new upload of the mesh removes the walls set for the old one
