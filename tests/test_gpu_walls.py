@@ -1,7 +1,7 @@
 """Reflective walls by mirrored generators (mm_set_walls, mm_reflect) through
 the C ABI, against the oracle's reflection and step: several steps in
 double to 1e-12 (a shock reflecting off a wall; a 3D slab of random states
-with the entropy row; an atmosphere held by a field; the Rayleigh-Taylor
+with the entropy row and either switch; an atmosphere held by a field; the Rayleigh-Taylor
 setup), the mixed + learned
 form within the stated L1, the split path equal to the step, and the checks
 of the wall lists."""
@@ -87,6 +87,9 @@ def oracle_steps(w, g, Q, steps, kind, accel=None):
         dt = O.cfl_dt(m, g, 0.4, O.prim(D, g, m.volume, Q[:D + 2]))
         if kind == "entropy":
             Q, _, _ = O.hydro_step_entropy(m, g, 0.4, Q, 0.3, dt=dt)
+        elif kind == "energy":
+            Q, _, kept = O.hydro_step_energy(m, g, 0.4, Q, 0.3, dt=dt)
+            assert 0 < kept.sum() < m.n_cells
         elif accel is not None:
             Q, _, _ = O.hydro_step_full(m, g, 0.4, Q, dt=dt, accel=accel)
         else:
@@ -95,7 +98,7 @@ def oracle_steps(w, g, Q, steps, kind, accel=None):
     return Q, dts
 
 
-@pytest.mark.parametrize("case", ["piston", "slab3d_entropy", "atmosphere_gravity", "rt3d"])
+@pytest.mark.parametrize("case", ["piston", "slab3d_entropy", "slab3d_energy", "atmosphere_gravity", "rt3d"])
 def test_double_steps_match_oracle(case):
     accel = None
     if case == "piston":
@@ -104,6 +107,9 @@ def test_double_steps_match_oracle(case):
     elif case == "slab3d_entropy":
         w, g, Q = slab3d(932)
         kw, kind = dict(entropy=mm.MM_ENTROPY_MACH, mach_thresh=0.3), "entropy"
+    elif case == "slab3d_energy":
+        w, g, Q = slab3d(935)
+        kw, kind = dict(entropy=mm.MM_ENTROPY_ENERGY, alpha_s=0.3), "energy"
     elif case == "atmosphere_gravity":
         w, g, Q, accel = atmosphere()
         kw, kind = {}, "plain"
