@@ -84,3 +84,13 @@ def test_boost_raises_the_fixed_mesh_error():
     base, _ = evolve(40, 0.0, 0.3, moving=False)
     l1, _ = evolve(40, 1.0, 0.3, moving=False)
     assert l1 > 1.1 * base, (l1, base)      # 0.0107 against 0.0089
+
+
+def test_moving_mesh_error_falls_at_the_papers_rate():
+    """The paper finds the moving-mesh L1 error of the vortex falling as
+    N^-1.4 (N cells per dimension). To t = 0.3 it is 0.0106 on 40^2 and
+    0.0041 on 80^2: a factor 2.61, N^-1.38 (from 20^2, where the vortex's
+    inner ring spans four cells, the factor is only 1.96)."""
+    l1_40, _ = evolve(40, 0.0, 0.3)
+    l1_80, _ = evolve(80, 0.0, 0.3)
+    assert 2.3 < l1_40 / l1_80 < 3.0, (l1_40, l1_80)
