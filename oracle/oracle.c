@@ -20,12 +20,22 @@
  *   face_sep   d = r_R - r_L (periodic image of R as seen from L)
  *   centroid_off  delta_i = s_i - r_i
  * The face normal points from L to R.
+ *
+ * Threads: the loops of the step run on the host's cores (OpenMP). Each
+ * parallel loop treats independent faces or cells; where the plain method
+ * scatters face terms into cells (gradients, the update), each cell instead
+ * gathers its faces' terms in ascending face order, which is the order in
+ * which a single loop over the faces adds them, so the results are the same
+ * bit for bit for any number of threads.
  */
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 #include <float.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define PI_D 3.14159265358979323846
 
@@ -45,6 +55,63 @@ typedef struct {
     double gamma;
     double cfl;
 } om_params;
+
+/* Number of host threads for the loops below (1 without OpenMP). */
+void oracle_set_threads(int32_t n)
+{
+#ifdef _OPENMP
+    omp_set_num_threads(n > 0 ? n : 1);
+#else
+    (void)n;
+#endif
+}
+
+int32_t oracle_threads(void)
+{
+#ifdef _OPENMP
+    return (int32_t)omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* The faces of every cell in ascending face order: cell i has the faces
+ * face[off[i] .. off[i+1]-1], right[q] = 1 where i is the face's right cell.
+ * A counting sort over the face list, in one plain loop. */
+typedef struct {
+    int64_t *off;
+    int32_t *face;
+    int8_t *right;
+} om_sides;
+
+static void sides_build(const om_mesh *M, om_sides *S)
+{
+    const int64_t n = M->n_cells, nf = M->n_faces;
+    S->off = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    S->face = (int32_t *)malloc(sizeof(int32_t) * 2 * (size_t)nf);
+    S->right = (int8_t *)malloc(2 * (size_t)nf);
+    for (int64_t f = 0; f < nf; f++) {
+        S->off[M->face_L[f] + 1]++;
+        S->off[M->face_R[f] + 1]++;
+    }
+    for (int64_t i = 0; i < n; i++) S->off[i + 1] += S->off[i];
+    int64_t *next = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    memcpy(next, S->off, sizeof(int64_t) * (size_t)n);
+    for (int64_t f = 0; f < nf; f++) {
+        int64_t q = next[M->face_L[f]]++;
+        S->face[q] = (int32_t)f;
+        S->right[q] = 0;
+        q = next[M->face_R[f]]++;
+        S->face[q] = (int32_t)f;
+        S->right[q] = 1;
+    }
+    free(next);
+}
+
+static void sides_free(om_sides *S)
+{
+    free(S->off); free(S->face); free(S->right);
+}
 
 /* ------------------------------------------------------------------ */
 /* Exact Riemann solver for the 1D Euler equations of an ideal gas.      */
@@ -300,6 +367,7 @@ void oracle_prim(int32_t dim, int64_t n, double g, const double *V,
                  const double *Q, double *W)
 {
     const int nv = dim + 2;
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; i++) {
         double m = Q[0 * n + i];
         double E = Q[(nv - 1) * n + i];
@@ -332,53 +400,48 @@ void oracle_prim(int32_t dim, int64_t n, double g, const double *V,
 /* Delta phi_ij = grad phi_i . (f_ij - s_i). A |Delta phi| at round-off   */
 /* level (<= 1e-13 max(|phi_i|, phi_max - phi_min)) is read as zero.      */
 /* ------------------------------------------------------------------ */
-void oracle_gradients(const om_mesh *M, const double *W, double *grad_raw,
-                      double *grad_lim, double *alpha)
+static void gradients_with(const om_mesh *M, const om_sides *S, const double *W, double *grad_raw,
+                           double *grad_lim, double *alpha)
 {
     const int D = M->dim, nv = D + 2;
     const int64_t n = M->n_cells, nf = M->n_faces;
     const double *A = M->face_area, *gc = M->face_ctr, *ds = M->face_sep;
-    double *phimin = (double *)malloc(sizeof(double) * nv * n);
-    double *phimax = (double *)malloc(sizeof(double) * nv * n);
-    double *acc = (double *)calloc((size_t)nv * D * n, sizeof(double));
 
-    for (int c = 0; c < nv; c++)
-        for (int64_t i = 0; i < n; i++) {
-            phimin[c * n + i] = W[c * n + i];
-            phimax[c * n + i] = W[c * n + i];
-        }
-
-    for (int64_t f = 0; f < nf; f++) {
-        int64_t l = M->face_L[f], r = M->face_R[f];
-        double d[3] = {0, 0, 0}, cc[3] = {0, 0, 0}, ell = 0.0;
-        for (int k = 0; k < D; k++) { d[k] = ds[k * nf + f]; ell += d[k] * d[k]; }
-        ell = sqrt(ell);
-        for (int k = 0; k < D; k++) cc[k] = gc[k * nf + f] - 0.5 * d[k];
-        for (int c = 0; c < nv; c++) {
-            double pl = W[c * n + l], pr = W[c * n + r];
-            for (int k = 0; k < D; k++) {
-                double G = A[f] / ell * ((pr - pl) * cc[k] + 0.5 * (pl + pr) * d[k]);
-                acc[(c * D + k) * n + l] += G;
-                acc[(c * D + k) * n + r] -= G;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; i++) {
+        double acc[5][3] = {{0}}, phimin[5], phimax[5];
+        for (int c = 0; c < nv; c++) { phimin[c] = W[c * n + i]; phimax[c] = W[c * n + i]; }
+        /* the face terms of cell i, from the left cell's view: + on the
+           left cell, - on the right one */
+        for (int64_t q = S->off[i]; q < S->off[i + 1]; q++) {
+            const int64_t f = S->face[q];
+            const int right = S->right[q];
+            const int64_t l = M->face_L[f], r = M->face_R[f];
+            double d[3] = {0, 0, 0}, cc[3] = {0, 0, 0}, ell = 0.0;
+            for (int k = 0; k < D; k++) { d[k] = ds[k * nf + f]; ell += d[k] * d[k]; }
+            ell = sqrt(ell);
+            for (int k = 0; k < D; k++) cc[k] = gc[k * nf + f] - 0.5 * d[k];
+            for (int c = 0; c < nv; c++) {
+                double pl = W[c * n + l], pr = W[c * n + r];
+                for (int k = 0; k < D; k++) {
+                    double G = A[f] / ell * ((pr - pl) * cc[k] + 0.5 * (pl + pr) * d[k]);
+                    if (right) acc[c][k] -= G;
+                    else acc[c][k] += G;
+                }
+                double other = right ? pl : pr;
+                if (other < phimin[c]) phimin[c] = other;
+                if (other > phimax[c]) phimax[c] = other;
             }
-            if (pr < phimin[c * n + l]) phimin[c * n + l] = pr;
-            if (pr > phimax[c * n + l]) phimax[c * n + l] = pr;
-            if (pl < phimin[c * n + r]) phimin[c * n + r] = pl;
-            if (pl > phimax[c * n + r]) phimax[c * n + r] = pl;
         }
-    }
-    for (int c = 0; c < nv; c++)
-        for (int k = 0; k < D; k++)
-            for (int64_t i = 0; i < n; i++)
-                grad_raw[(c * D + k) * n + i] = acc[(c * D + k) * n + i] / M->volume[i];
+        for (int c = 0; c < nv; c++)
+            for (int k = 0; k < D; k++)
+                grad_raw[(c * D + k) * n + i] = acc[c][k] / M->volume[i];
 
-    /* limiter */
-    double *al = (double *)malloc(sizeof(double) * nv * n);
-    for (int64_t q = 0; q < (int64_t)nv * n; q++) al[q] = 1.0;
-    for (int64_t f = 0; f < nf; f++) {
-        int64_t side_cell[2] = {M->face_L[f], M->face_R[f]};
-        for (int s = 0; s < 2; s++) {
-            int64_t i = side_cell[s];
+        /* limiter: every face of cell i */
+        double al[5] = {1.0, 1.0, 1.0, 1.0, 1.0};
+        for (int64_t q = S->off[i]; q < S->off[i + 1]; q++) {
+            const int64_t f = S->face[q];
+            const int s = S->right[q];
             double dx[3] = {0, 0, 0};
             for (int k = 0; k < D; k++) {
                 /* f - s_i: for L, g - delta_L; for R, g - d - delta_R */
@@ -389,22 +452,30 @@ void oracle_gradients(const om_mesh *M, const double *W, double *grad_raw,
                 double phi = W[c * n + i];
                 double dphi = 0.0;
                 for (int k = 0; k < D; k++) dphi += grad_raw[(c * D + k) * n + i] * dx[k];
-                double range = phimax[c * n + i] - phimin[c * n + i];
+                double range = phimax[c] - phimin[c];
                 double tol = 1e-13 * fmax(fabs(phi), range);
                 double psi;
-                if (dphi > tol) psi = (phimax[c * n + i] - phi) / dphi;
-                else if (dphi < -tol) psi = (phimin[c * n + i] - phi) / dphi;
+                if (dphi > tol) psi = (phimax[c] - phi) / dphi;
+                else if (dphi < -tol) psi = (phimin[c] - phi) / dphi;
                 else psi = 1.0;
-                if (psi < al[c * n + i]) al[c * n + i] = psi;
+                if (psi < al[c]) al[c] = psi;
             }
         }
+        for (int c = 0; c < nv; c++) {
+            for (int k = 0; k < D; k++)
+                grad_lim[(c * D + k) * n + i] = al[c] * grad_raw[(c * D + k) * n + i];
+            if (alpha) alpha[c * n + i] = al[c];
+        }
     }
-    for (int c = 0; c < nv; c++)
-        for (int k = 0; k < D; k++)
-            for (int64_t i = 0; i < n; i++)
-                grad_lim[(c * D + k) * n + i] = al[c * n + i] * grad_raw[(c * D + k) * n + i];
-    if (alpha) memcpy(alpha, al, sizeof(double) * nv * n);
-    free(al); free(acc); free(phimin); free(phimax);
+}
+
+void oracle_gradients(const om_mesh *M, const double *W, double *grad_raw,
+                      double *grad_lim, double *alpha)
+{
+    om_sides S;
+    sides_build(M, &S);
+    gradients_with(M, &S, W, grad_raw, grad_lim, alpha);
+    sides_free(&S);
 }
 
 /* ------------------------------------------------------------------ */
@@ -417,6 +488,7 @@ void oracle_face_velocity(const om_mesh *M, double *wf)
 {
     const int D = M->dim;
     const int64_t n = M->n_cells, nf = M->n_faces;
+#pragma omp parallel for schedule(static)
     for (int64_t f = 0; f < nf; f++) {
         int64_t l = M->face_L[f], r = M->face_R[f];
         double d[3] = {0, 0, 0}, cc[3] = {0, 0, 0}, ell2 = 0.0, proj = 0.0;
@@ -659,6 +731,7 @@ void oracle_face_fluxes_full(const om_mesh *M, const om_params *prm, double dt, 
     const double pdt[2] = {dt, dt};
     double *wf = (double *)malloc(sizeof(double) * M->dim * nf);
     oracle_face_velocity(M, wf);
+#pragma omp parallel for schedule(dynamic, 4096)
     for (int64_t f = 0; f < nf; f++) {
         double F[5];
         int fb = face_flux_one(M, prm, wf, f, pdt, dt, accel, W, grad, F, kase ? kase + f : NULL,
@@ -674,17 +747,27 @@ void oracle_face_fluxes_full(const om_mesh *M, const om_params *prm, double dt, 
 /* with F_ji = -F_ij (Section 3, discrete update): the left cell loses   */
 /* the face flux and the right cell gains it, in face-list order.        */
 /* ------------------------------------------------------------------ */
-void oracle_apply_update(const om_mesh *M, const double *face_flux, double *Q)
+static void apply_update_with(const om_mesh *M, const om_sides *S, const double *face_flux, double *Q)
 {
     const int nv = M->dim + 2;
     const int64_t n = M->n_cells, nf = M->n_faces;
-    for (int64_t f = 0; f < nf; f++) {
-        int64_t l = M->face_L[f], r = M->face_R[f];
-        for (int c = 0; c < nv; c++) {
-            Q[c * n + l] -= face_flux[c * nf + f];
-            Q[c * n + r] += face_flux[c * nf + f];
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; i++)
+        for (int64_t q = S->off[i]; q < S->off[i + 1]; q++) {
+            const int64_t f = S->face[q];
+            for (int c = 0; c < nv; c++) {
+                if (S->right[q]) Q[c * n + i] += face_flux[c * nf + f];
+                else Q[c * n + i] -= face_flux[c * nf + f];
+            }
         }
-    }
+}
+
+void oracle_apply_update(const om_mesh *M, const double *face_flux, double *Q)
+{
+    om_sides S;
+    sides_build(M, &S);
+    apply_update_with(M, &S, face_flux, Q);
+    sides_free(&S);
 }
 
 /* ------------------------------------------------------------------ */
@@ -698,6 +781,11 @@ double oracle_cfl_dt(const om_mesh *M, const om_params *prm, const double *W)
     const int D = M->dim, nv = D + 2;
     const int64_t n = M->n_cells;
     double best = INFINITY;
+    /* per-thread minima, then their minimum (a minimum is exact in any order) */
+#pragma omp parallel
+    {
+    double mine = INFINITY;
+#pragma omp for schedule(static)
     for (int64_t i = 0; i < n; i++) {
         double rho = W[0 * n + i], P = W[(nv - 1) * n + i];
         if (!(rho > 0.0 && P > 0.0)) continue;
@@ -709,7 +797,10 @@ double oracle_cfl_dt(const om_mesh *M, const om_params *prm, const double *W)
             rel += dv * dv;
         }
         double dti = prm->cfl * R / (c + sqrt(rel));
-        if (dti < best) best = dti;
+        if (dti < mine) mine = dti;
+    }
+#pragma omp critical
+    if (mine < best) best = mine;
     }
     return best;
 }
@@ -727,11 +818,14 @@ double oracle_hydro_step(const om_mesh *M, const om_params *prm, double dt, doub
     double *gr = (double *)malloc(sizeof(double) * nv * D * n);
     double *gl = (double *)malloc(sizeof(double) * nv * D * n);
     double *fl = (double *)malloc(sizeof(double) * nv * nf);
+    om_sides S;
+    sides_build(M, &S);
     oracle_prim(D, n, prm->gamma, M->volume, Q, W);
-    oracle_gradients(M, W, gr, gl, NULL);
+    gradients_with(M, &S, W, gr, gl, NULL);
     if (!(dt > 0.0)) dt = oracle_cfl_dt(M, prm, W);
     oracle_face_fluxes(M, prm, dt, W, gl, fl, NULL, NULL);
-    oracle_apply_update(M, fl, Q);
+    apply_update_with(M, &S, fl, Q);
+    sides_free(&S);
     free(W); free(gr); free(gl); free(fl);
     return dt;
 }

@@ -19,10 +19,13 @@ _ip = ctypes.POINTER(ctypes.c_int32)
 
 
 def build() -> str:
-    """Compile the oracle with gcc (plain -O2, no fast-math, no FMA)."""
+    """Compile the oracle with gcc (plain -O2, no fast-math, no FMA; OpenMP
+    over independent faces and cells, bitwise the same for any thread
+    count)."""
     src = os.path.join(_HERE, "oracle.c")
-    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall",
-                           "-ffp-contract=off", "-o", _SO, src, "-lm"])
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall", "-fopenmp",
+                           "-ffp-contract=off", "-o", _SO + ".tmp", src, "-lm"])
+    os.replace(_SO + ".tmp", _SO)
     return _SO
 
 
@@ -43,6 +46,8 @@ def _lib():
         if not os.path.exists(_SO):
             build()
         lib = ctypes.CDLL(_SO)
+        lib.oracle_set_threads.argtypes = [ctypes.c_int32]
+        lib.oracle_threads.restype = ctypes.c_int32
         lib.oracle_riemann_batch.argtypes = [ctypes.c_int64, ctypes.c_double] + [_dp] * 12 + [_ip, _ip]
         lib.oracle_pressure_function.restype = ctypes.c_double
         lib.oracle_pressure_function.argtypes = [ctypes.c_double, _dp, _dp, ctypes.c_double]
@@ -87,6 +92,15 @@ def _lib():
                                        ctypes.POINTER(ctypes.c_int64)]
         _LIB = lib
     return _LIB
+
+
+def set_threads(n: int) -> None:
+    """Host threads of the oracle's loops (results do not depend on it)."""
+    _lib().oracle_set_threads(int(n))
+
+
+def threads() -> int:
+    return int(_lib().oracle_threads())
 
 
 def _d(a):
