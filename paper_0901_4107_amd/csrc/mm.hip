@@ -259,14 +259,14 @@ static const MlpPacked *active_mlp(const mm_ctx *c) {
     return (c->p.guess == MM_GUESS_LEARNED && c->mlp_ready) ? c->at<MlpPacked>(c->lay.mlp) : nullptr;
 }
 
-static mm_status scan_inclusive(mm_ctx *c, int32_t *data, int64_t n, int32_t *scratch) {
+static mm_status scan_inclusive(mm_ctx *c, int32_t *data, int64_t n, int32_t *tile_sums) {
     const unsigned tiles = (unsigned)((n + 1023) / 1024);
-    k_scan_tiles<<<tiles, kBlock, 0, c->st()>>>(data, n, scratch);
+    k_scan_tiles<<<tiles, kBlock, 0, c->st()>>>(data, n, tile_sums);
     MM_LAUNCH_CHECK();
     if (tiles > 1) {
-        mm_status s = scan_inclusive(c, scratch, tiles, scratch + tiles + 1);
+        mm_status s = scan_inclusive(c, tile_sums, tiles, tile_sums + tiles + 1);
         if (s != MM_OK) return s;
-        k_scan_add<<<tiles, kBlock, 0, c->st()>>>(data, n, scratch);
+        k_scan_add<<<tiles, kBlock, 0, c->st()>>>(data, n, tile_sums);
         MM_LAUNCH_CHECK();
     }
     return MM_OK;
@@ -657,13 +657,13 @@ int64_t mm_mlp_grad_scratch_bytes(int64_t n) {
     return ((n + kMlpTile - 1) / kMlpTile) * (int64_t)(kMlpParams + 1) * (int64_t)sizeof(float);
 }
 
-mm_status mm_mlp_grad(const float *params, int64_t n, int64_t n_total, const float *X, const float *T, void *scratch,
+mm_status mm_mlp_grad(const float *params, int64_t n, int64_t n_total, const float *X, const float *T, void *partials,
                       float *grad, void *stream) {
-    if (!params || !X || !T || !scratch || !grad || n < 1 || n_total < 1) return MM_E_ARG;
+    if (!params || !X || !T || !partials || !grad || n < 1 || n_total < 1) return MM_E_ARG;
     const int64_t nb = (n + kMlpTile - 1) / kMlpTile;
     hipStream_t s = (hipStream_t)stream;
-    k_mlp_grad_partial<<<(unsigned)nb, kBlock, 0, s>>>(n, 1.0f / (float)n_total, params, X, T, (float *)scratch);
-    k_mlp_reduce<<<plain_grid(kMlpParams + 1), kBlock, 0, s>>>(nb, (const float *)scratch, grad);
+    k_mlp_grad_partial<<<(unsigned)nb, kBlock, 0, s>>>(n, 1.0f / (float)n_total, params, X, T, (float *)partials);
+    k_mlp_reduce<<<plain_grid(kMlpParams + 1), kBlock, 0, s>>>(nb, (const float *)partials, grad);
     MM_LAUNCH_CHECK();
     return MM_OK;
 }
@@ -775,14 +775,14 @@ mm_status mm_tb_begin(mm_ctx *c, double dt_max, int32_t levels) {
     if (!c->have_mesh) return MM_E_STATE;
     const Layout &L = c->lay;
     // exact per-residue sums for the sparse path's sub-lists (the touched
-    // list's region serves as scratch before the timeline starts)
-    int32_t *scratch = c->at<int32_t>(L.tb_touched);
-    k_fill_i32<<<plain_grid(2 * kLists), kBlock, 0, c->st()>>>(scratch, 2 * kLists, 0);
-    k_tb_bound<<<plain_grid(c->n), kBlock, 0, c->st()>>>(c->n, grid_for(c->n), c->at<int32_t>(L.off), scratch,
-                                                        scratch + kLists);
+    // list's region holds them before the timeline starts)
+    int32_t *sums_dev = c->at<int32_t>(L.tb_touched);
+    k_fill_i32<<<plain_grid(2 * kLists), kBlock, 0, c->st()>>>(sums_dev, 2 * kLists, 0);
+    k_tb_bound<<<plain_grid(c->n), kBlock, 0, c->st()>>>(c->n, grid_for(c->n), c->at<int32_t>(L.off), sums_dev,
+                                                        sums_dev + kLists);
     MM_LAUNCH_CHECK();
     int32_t sums[2 * kLists];
-    MM_CHECK(hipMemcpyAsync(sums, scratch, sizeof(sums), hipMemcpyDeviceToHost, c->st()));
+    MM_CHECK(hipMemcpyAsync(sums, sums_dev, sizeof(sums), hipMemcpyDeviceToHost, c->st()));
     MM_CHECK(hipStreamSynchronize(c->st()));
     int64_t ms = 0, mt = 0;
     for (int k = 0; k < kLists; k++) {

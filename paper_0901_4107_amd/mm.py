@@ -133,6 +133,20 @@ def _check(call, status):
         raise MMError(call, status)
 
 
+def _need(t: torch.Tensor | None, name: str, dtype: torch.dtype, numel: int, optional: bool = False):
+    """Refuse a tensor the library would read or write out of bounds: it must
+    have the element type the entry point takes and at least `numel`
+    elements (device residence and contiguity are checked by _ptr)."""
+    if t is None:
+        if optional:
+            return
+        raise ValueError(f"{name}: a tensor is required")
+    if t.dtype != dtype:
+        raise ValueError(f"{name}: dtype {t.dtype}, the library takes {dtype}")
+    if t.numel() < numel:
+        raise ValueError(f"{name}: {t.numel()} elements, the library needs at least {numel}")
+
+
 @dataclass
 class DeviceMesh:
     """Device copies of a tessellation in the layouts of ``mm_mesh``."""
@@ -163,6 +177,12 @@ class DeviceMesh:
                    i32(mesh.face_R), f64(mesh.face_area), f64(mesh.face_ctr), f64(mesh.face_sep))
 
     def as_struct(self) -> mm_mesh:
+        n, nf, D = self.n_cells, self.n_faces, self.dim
+        for name, dt, size in (("volume", torch.float64, n), ("centroid_off", torch.float64, D * n),
+                               ("mesh_vel", torch.float64, D * n), ("face_L", torch.int32, nf),
+                               ("face_R", torch.int32, nf), ("face_area", torch.float64, nf),
+                               ("face_ctr", torch.float64, D * nf), ("face_sep", torch.float64, D * nf)):
+            _need(getattr(self, name), f"mm_mesh.{name}", dt, size)
         return mm_mesh(self.n_cells, self.n_faces, _ptr(self.volume), _ptr(self.centroid_off), _ptr(self.mesh_vel),
                        _ptr(self.face_L), _ptr(self.face_R), _ptr(self.face_area), _ptr(self.face_ctr),
                        _ptr(self.face_sep))
@@ -195,6 +215,33 @@ class Context:
             _LIB.mm_destroy(self._ctx)
             self._ctx = None
 
+    # --- sizes the library derives from the uploaded mesh --------------------
+    def _cells(self, call: str) -> int:
+        if self._mesh is None:
+            raise MMError(call, MM_E_STATE)
+        return self._mesh.n_cells
+
+    def _faces(self, call: str) -> int:
+        if self._mesh is None:
+            raise MMError(call, MM_E_STATE)
+        return self._mesh.n_faces
+
+    def _rows(self) -> int:
+        """Rows of Q: D + 2 conserved totals, plus the entropy row."""
+        return self.dim + 2 + (1 if self.entropy else 0)
+
+    def _recon_dtype(self):
+        return torch.float64 if self.mode == MM_FP64 else torch.float32
+
+    def _need_Q(self, Q, call):
+        _need(Q, f"{call}: Q", torch.float64, self._rows() * self._cells(call))
+
+    def _need_recon(self, recon, call):
+        _need(recon, f"{call}: recon", self._recon_dtype(), self._cells(call) * recon_stride(self.dim))
+
+    def _need_flux(self, flux, call):
+        _need(flux, f"{call}: face_flux", torch.float64, self._faces(call) * flux_stride(self.dim, self.entropy))
+
     # --- C ABI, one method per entry point ----------------------------------
     def mm_workspace_bytes(self, n_cells: int, n_faces: int) -> int:
         return int(lib().mm_workspace_bytes(self._ctx, n_cells, n_faces))
@@ -215,16 +262,23 @@ class Context:
         _check("mm_mesh_upload", lib().mm_mesh_upload(self._ctx, ctypes.byref(mesh.as_struct())))
 
     def mm_gradients(self, Q: torch.Tensor, recon: torch.Tensor):
+        self._need_Q(Q, "mm_gradients")
+        self._need_recon(recon, "mm_gradients")
         _check("mm_gradients", lib().mm_gradients(self._ctx, _ptr(Q), _ptr(recon)))
 
     def mm_face_fluxes(self, dt: float, recon: torch.Tensor, face_flux: torch.Tensor):
+        self._need_recon(recon, "mm_face_fluxes")
+        self._need_flux(face_flux, "mm_face_fluxes")
         _check("mm_face_fluxes", lib().mm_face_fluxes(self._ctx, float(dt), _ptr(recon), _ptr(face_flux)))
 
     def mm_apply_update(self, face_flux: torch.Tensor, Q: torch.Tensor):
+        self._need_flux(face_flux, "mm_apply_update")
+        self._need_Q(Q, "mm_apply_update")
         _check("mm_apply_update", lib().mm_apply_update(self._ctx, _ptr(face_flux), _ptr(Q)))
 
     def mm_hydro_step(self, Q: torch.Tensor, dt: float = 0.0, sync: bool = True):
         """One step on Q in place; returns the timestep used (None if sync=False)."""
+        self._need_Q(Q, "mm_hydro_step")
         if sync:
             used = ctypes.c_double(0.0)
             _check("mm_hydro_step", lib().mm_hydro_step(self._ctx, _ptr(Q), float(dt), ctypes.byref(used)))
@@ -247,49 +301,73 @@ class Context:
             self.mm_set_workspace(torch.empty(need + 256, dtype=torch.uint8, device=self.device))
 
     def mm_mlp_load(self, params: torch.Tensor):
+        _need(params, "mm_mlp_load: params", torch.float32, MM_MLP_PARAMS)
         self.ensure_workspace()
         _check("mm_mlp_load", lib().mm_mlp_load(self._ctx, _ptr(params)))
         self._mlp = params
 
     def mm_mlp_infer(self, X: torch.Tensor, Y: torch.Tensor):
+        n = X.shape[0]
+        _need(X, "mm_mlp_infer: X", torch.float32, 3 * n)
+        _need(Y, "mm_mlp_infer: Y", torch.float32, n)
         _check("mm_mlp_infer", lib().mm_mlp_infer(self._ctx, X.shape[0], _ptr(X), _ptr(Y)))
 
     def mm_riemann_batch(self, states: torch.Tensor, out: torch.Tensor, iters: torch.Tensor | None = None):
-        """states [6][n] double -> out [n][4] (rho_F, u_F, P_F, p*), iters [n]."""
+        """states [6][n] double -> out [n][5] double (rho_F, u_F, P_F, p*,
+        p_std), iters [n] int32 (optional)."""
+        if states.dim() != 2 or states.shape[0] != 6:
+            raise ValueError("mm_riemann_batch: states must be [6][n]")
+        n = states.shape[1]
+        _need(states, "mm_riemann_batch: states", torch.float64, 6 * n)
+        _need(out, "mm_riemann_batch: out", torch.float64, 5 * n)
+        _need(iters, "mm_riemann_batch: iters", torch.int32, n, optional=True)
         self.ensure_workspace()
         _check("mm_riemann_batch", lib().mm_riemann_batch(self._ctx, states.shape[1], _ptr(states), _ptr(out),
                                                           _ptr(iters)))
 
     def mm_face_states(self, dt: float, recon: torch.Tensor, out: torch.Tensor):
+        self._need_recon(recon, "mm_face_states")
+        _need(out, "mm_face_states: out", torch.float32, 6 * self._faces("mm_face_states"))
         _check("mm_face_states", lib().mm_face_states(self._ctx, float(dt), _ptr(recon), _ptr(out)))
 
     def mm_mesh_velocity(self, Q: torch.Tensor, w_out: torch.Tensor, eta: float = 0.25, chi: float = 1.0,
                          dt_lloyd: float = 0.0):
+        n = self._cells("mm_mesh_velocity")
+        _need(Q, "mm_mesh_velocity: Q", torch.float64, (self.dim + 2) * n)
+        _need(w_out, "mm_mesh_velocity: w_out", torch.float64, self.dim * n)
         _check("mm_mesh_velocity", lib().mm_mesh_velocity(self._ctx, _ptr(Q), float(eta), float(chi),
                                                           float(dt_lloyd), _ptr(w_out)))
 
     def mm_mesh_set_velocity(self, w: torch.Tensor):
+        _need(w, "mm_mesh_set_velocity: w", torch.float64, self.dim * self._cells("mm_mesh_set_velocity"))
         _check("mm_mesh_set_velocity", lib().mm_mesh_set_velocity(self._ctx, _ptr(w)))
         self._mesh_vel = w  # kept alive while the library refers to it
 
     def mm_set_gravity(self, accel: torch.Tensor | None):
+        _need(accel, "mm_set_gravity: accel", torch.float64, self.dim * self._cells("mm_set_gravity"), optional=True)
         _check("mm_set_gravity", lib().mm_set_gravity(self._ctx, _ptr(accel)))
         self._accel = accel  # kept alive while the library refers to it
 
     def mm_set_walls(self, ghost: torch.Tensor | None, src: torch.Tensor | None, axis: int = 1):
         """Mirror cells ghost [k] of src [k] (int32 device); None removes the walls."""
         n = 0 if ghost is None else int(ghost.numel())
+        if n:
+            _need(ghost, "mm_set_walls: ghost", torch.int32, n)
+            _need(src, "mm_set_walls: src", torch.int32, n)
         self._walls = None
         _check("mm_set_walls", lib().mm_set_walls(self._ctx, n, _ptr(ghost), _ptr(src), int(axis)))
         self._walls = (ghost, src)  # kept alive while the library refers to them
 
     def mm_reflect(self, Q: torch.Tensor):
+        self._need_Q(Q, "mm_reflect")
         _check("mm_reflect", lib().mm_reflect(self._ctx, _ptr(Q)))
 
     def mm_volume_rate(self, rate: torch.Tensor):
+        _need(rate, "mm_volume_rate: rate", torch.float64, self._cells("mm_volume_rate"))
         _check("mm_volume_rate", lib().mm_volume_rate(self._ctx, _ptr(rate)))
 
     def mm_entropy_init(self, Q: torch.Tensor):
+        self._need_Q(Q, "mm_entropy_init")
         _check("mm_entropy_init", lib().mm_entropy_init(self._ctx, _ptr(Q)))
 
 
@@ -301,6 +379,7 @@ class Context:
         summary (tick, next_tick, active_cells, active_faces, min_bin,
         max_bin, sparse, points, sparse_points, total_cells, total_faces,
         next_time)."""
+        self._need_Q(Q, "mm_tb_step")
         info = mm_tb_info()
         _check("mm_tb_step", lib().mm_tb_step(self._ctx, _ptr(Q), ctypes.byref(info)))
         return {name: getattr(info, name) for name, _ in mm_tb_info._fields_ if name != "reserved"}
@@ -308,6 +387,7 @@ class Context:
     def mm_tb_advance(self, Q: torch.Tensor, until_tick: int, max_points: int) -> dict:
         """Up to max_points points, stopping at until_tick, synchronising
         once; returns the last point's summary and the call's totals."""
+        self._need_Q(Q, "mm_tb_advance")
         info = mm_tb_info()
         _check("mm_tb_advance", lib().mm_tb_advance(self._ctx, _ptr(Q), int(until_tick), int(max_points),
                                                     ctypes.byref(info)))
@@ -315,10 +395,9 @@ class Context:
 
     def mm_tb_state(self, bins: torch.Tensor | None = None, trec: torch.Tensor | None = None):
         """Copies of the bins (int8 [N]) and step start ticks (int64 [N])."""
-        if bins is not None and bins.dtype != torch.int8:
-            raise ValueError("bins must be int8")
-        if trec is not None and trec.dtype != torch.int64:
-            raise ValueError("trec must be int64")
+        n = self._cells("mm_tb_state")
+        _need(bins, "mm_tb_state: bins", torch.int8, n, optional=True)
+        _need(trec, "mm_tb_state: trec", torch.int64, n, optional=True)
         _check("mm_tb_state", lib().mm_tb_state(self._ctx, _ptr(bins), _ptr(trec)))
 
     def recon_buffer(self, n_cells: int):
@@ -341,6 +420,10 @@ def _stream_ptr(stream):
 
 
 def mm_mlp_forward(params: torch.Tensor, X: torch.Tensor, Y: torch.Tensor, stream=None):
+    n = X.shape[0]
+    _need(params, "mm_mlp_forward: params", torch.float32, MM_MLP_PARAMS)
+    _need(X, "mm_mlp_forward: X", torch.float32, 3 * n)
+    _need(Y, "mm_mlp_forward: Y", torch.float32, n)
     _check("mm_mlp_forward", lib().mm_mlp_forward(_ptr(params), X.shape[0], _ptr(X), _ptr(Y), _stream_ptr(stream)))
 
 
@@ -350,11 +433,19 @@ def mm_mlp_grad_scratch_bytes(n: int) -> int:
 
 def mm_mlp_grad(params, X, T, scratch, grad, n_total=None, stream=None):
     n = X.shape[0]
+    _need(params, "mm_mlp_grad: params", torch.float32, MM_MLP_PARAMS)
+    _need(X, "mm_mlp_grad: X", torch.float32, 3 * n)
+    _need(T, "mm_mlp_grad: T", torch.float32, n)
+    if scratch is None or scratch.numel() * scratch.element_size() < mm_mlp_grad_scratch_bytes(n):
+        raise ValueError("mm_mlp_grad: scratch smaller than mm_mlp_grad_scratch_bytes(n)")
+    _need(grad, "mm_mlp_grad: grad", torch.float32, MM_MLP_PARAMS)
     _check("mm_mlp_grad", lib().mm_mlp_grad(_ptr(params), n, n if n_total is None else n_total, _ptr(X), _ptr(T),
                                             _ptr(scratch), _ptr(grad), _stream_ptr(stream)))
 
 
 def mm_mlp_adam(params, grad, m1, m2, lr, beta1, beta2, eps, step, stream=None):
+    for name, t in (("params", params), ("grad", grad), ("m1", m1), ("m2", m2)):
+        _need(t, f"mm_mlp_adam: {name}", torch.float32, MM_MLP_PARAMS)
     _check("mm_mlp_adam", lib().mm_mlp_adam(_ptr(params), _ptr(grad), _ptr(m1), _ptr(m2), lr, beta1, beta2, eps,
                                             step, _stream_ptr(stream)))
 

@@ -158,3 +158,22 @@ def test_mixed_workspace_is_smaller_per_cell():
         assert L.mm_workspace_bytes(c64, 10 ** 6, 8 * 10 ** 6) > 0
     finally:
         L.mm_destroy(c64); L.mm_destroy(c32)
+
+
+def test_binding_refuses_tensors_the_library_would_overrun():
+    """The binding checks element type and size before a call reaches the
+    library (the C ABI takes bare pointers): a batch output of 4 instead of
+    5 doubles per problem, a float state array or missing rows raise."""
+    import torch
+    need = mm._need
+    need(torch.empty(10, dtype=torch.float64), "x", torch.float64, 10)
+    need(None, "x", torch.float64, 10, optional=True)
+    with pytest.raises(ValueError, match="dtype"):
+        need(torch.empty(10, dtype=torch.float32), "x", torch.float64, 10)
+    with pytest.raises(ValueError, match="at least 50"):
+        need(torch.empty((10, 4), dtype=torch.float64), "out", torch.float64, 5 * 10)
+    with pytest.raises(ValueError, match="required"):
+        need(None, "x", torch.float64, 1)
+    # sizes of the entry points' arrays follow the header's strides
+    assert mm.recon_stride(3) == 24 and mm.recon_stride(2) == 16
+    assert mm.flux_stride(3) == 5 and mm.flux_stride(3, mm.MM_ENTROPY_ENERGY) == 7
