@@ -47,19 +47,39 @@ def log(msg):
 
 
 def flux_kernel_bytes(dim, n_cells, n_faces, mixed):
-    """Algorithmic HBM bytes of one face-flux launch. Per face: the two cell
-    indices, the face geometry (A, |d|, n, c) and velocity, and the flux
-    written; per cell (each gathered once under ideal reuse) its
-    reconstruction record (primitives, gradients, s - r). Double: all double;
-    mixed: float geometry and w_L - w_R, double w_f, float records."""
+    """Algorithmic HBM bytes of one face-flux launch, itemised from what the
+    step needs per face and per cell, each item read or written once (ideal
+    reuse of the cell data):
+      per face: the two cell indices L, R (int32); the area A, the face
+                centroid g = f - r_L and the separation d = r_R - r_L in the
+                path's precision (float in the mixed form); the face velocity
+                w_f and the D + 2 fluxes written, in double;
+      per cell: the primitives W (D + 2), their limited gradients
+                ((D + 2) D) and the centroid offset s - r (D), in the path's
+                precision.
+    The library's own face record carries derived values on top (|d|, the
+    normal, w_L - w_R): those count as overhead against this figure, not as
+    algorithmic bytes."""
     nv = dim + 2
-    if not mixed:
-        per_face = 2 * 4 + (2 + 3 * dim) * 8 + nv * 8
-        per_cell = (nv + nv * dim + dim) * 8
-    else:
-        per_face = 2 * 4 + (2 + 3 * dim) * 4 + dim * 8 + nv * 8
-        per_cell = (nv + nv * dim + dim) * 4
+    fp = 4 if mixed else 8
+    per_face = 2 * 4 + (1 + 2 * dim) * fp + dim * 8 + nv * 8
+    per_cell = (nv + nv * dim + dim) * fp
     return n_faces * per_face + n_cells * per_cell, per_face, per_cell
+
+
+def host_cpu():
+    """The host the CPU baseline ran on: logical CPUs and model name."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.lower().startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "cpu_model": model,
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
 
 
 def l1_rest(a, b, boost):
@@ -321,9 +341,17 @@ def bench_step(args):
     traffic = read_traffic(os.path.join(ROOT, "profiles"), kname, wl.name)
     out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                       "traffic_vs_algorithmic": None if traffic is None else traffic / nbytes,
                        "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE, WRITE_SIZE, copy-scaled)",
                        "kernel": kname, "algorithmic_bytes": nbytes,
                        "bytes_per_face": per_face, "bytes_per_cell": per_cell}
+    if args.mode == "mixed+learned" and not args.no_compare:
+        std = time_form(mm, learned, torch, wl, dmesh, "mixed", args.steps, args.warmup, dev)
+        log(f"mixed (standard guess): {std['ms']:.3f} ms/step, flux kernel {std['flux_ms']:.3f} ms")
+        out["mixed_standard_guess"] = {"ms_per_step": std["ms"], "face_fluxes_per_s": m.n_faces / (std["ms"] * 1e-3),
+                                       "flux_kernel_ms": std["flux_ms"], "newton": newton_summary(std["diag"]),
+                                       "learned_step_speedup": std["ms"] / head["ms"],
+                                       "learned_flux_kernel_speedup": std["flux_ms"] / head["flux_ms"]}
     if args.mode != "fp64" and not args.no_compare:
         base = time_form(mm, learned, torch, wl, dmesh, "fp64", args.steps, args.warmup, dev)
         log(f"fp64: {base['ms']:.3f} ms/step, flux kernel {base['flux_ms']:.3f} ms")
@@ -363,19 +391,41 @@ def bench_step(args):
             f"{2 ** ind['levels']} ticks; {ind['flux_ratio_vs_global_at_smallest_bin']:.1f}x fewer fluxes than a "
             f"global step at the smallest bin")
     if not args.no_cpu_baseline:
-        from oracle import oracle as O
-        log("cpu baseline: oracle hydro step on the full workload (1 thread)")
+        out["cpu_baseline"] = cpu_baseline(wl)
+    return out
+
+
+def cpu_baseline(wl):
+    """The oracle's whole step on the whole workload: once on one thread, and
+    three times on every thread OpenMP is given (the median), the results
+    being the same bit for bit. `value` is the all-thread rate."""
+    from oracle import oracle as O
+    m = wl.mesh
+
+    def one_step():
         t = time.time()
         if wl.walls is None and wl.accel is None:
             O.hydro_step(m, wl.gamma, wl.cfl, wl.Q)
         else:   # the same work as the device step: reflection, step with the field
             Q = wl.Q if wl.walls is None else O.reflect(wl.Q, wl.walls.ghost, wl.walls.src, wl.walls.axis)
             O.hydro_step_full(m, wl.gamma, wl.cfl, Q, accel=wl.accel)
-        el = time.time() - t
-        out["cpu_baseline"] = {"value": m.n_faces / el, "unit": "face-fluxes/s", "cores": 1, "kind": "oracle",
-                               "sample": f"one full oracle hydro step on the whole {wl.name} workload "
-                                         f"({m.n_faces} faces), single thread, {el:.1f} s"}
-    return out
+        return time.time() - t
+
+    all_threads = O.threads()
+    try:
+        O.set_threads(1)
+        log("cpu baseline: oracle hydro step on the full workload, 1 thread")
+        t1 = one_step()
+        O.set_threads(all_threads)
+        log(f"cpu baseline: the same on {all_threads} threads (median of 3)")
+        tn = float(np.median([one_step() for _ in range(3)]))
+    finally:
+        O.set_threads(all_threads)
+    return {"value": m.n_faces / tn, "unit": "face-fluxes/s", "cores": all_threads, "kind": "oracle",
+            "sample": f"one full oracle hydro step on the whole {wl.name} workload ({m.n_faces} faces): "
+                      f"{tn:.2f} s on {all_threads} threads (median of 3), {t1:.2f} s on 1 thread",
+            "single_thread": {"value": m.n_faces / t1, "unit": "face-fluxes/s", "cores": 1, "seconds": t1},
+            "all_threads_seconds": tn, "host": host_cpu()}
 
 
 def bench_riemann(args):

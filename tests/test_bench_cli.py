@@ -22,10 +22,14 @@ def test_more_than_one_gpu_is_refused():
 def test_flux_byte_model():
     sys.path.insert(0, ROOT)
     import bench
+    # per face: L, R; A, g, d in the path's precision; w_f and the 5 fluxes
+    # in double. Per cell: W, its gradient and s - r in the path's precision.
     nbytes, pf, pc = bench.flux_kernel_bytes(3, 10, 100, mixed=False)
-    assert (pf, pc) == (8 + 11 * 8 + 5 * 8, 23 * 8)       # indices, A |d| n c w_f, flux; W, grad, s - r
+    assert (pf, pc) == (8 + 7 * 8 + 3 * 8 + 5 * 8, 23 * 8)
     nbytes_m, pfm, pcm = bench.flux_kernel_bytes(3, 10, 100, mixed=True)
-    assert (pfm, pcm) == (8 + 11 * 4 + 3 * 8 + 5 * 8, 23 * 4)
+    assert (pfm, pcm) == (8 + 7 * 4 + 3 * 8 + 5 * 8, 23 * 4)
+    # the headline mesh: 100 B per face and 92 B per cell in the mixed form
+    assert bench.flux_kernel_bytes(3, 2097152, 16291535, mixed=True)[0] == 16291535 * 100 + 2097152 * 92
     assert nbytes == 100 * pf + 10 * pc and nbytes_m == 100 * pfm + 10 * pcm
 
 

@@ -14,11 +14,14 @@ from oracle import oracle as O
 from paper_0901_4107_amd import mm
 from paper_0901_4107_amd.inputs import build_mesh
 from paper_0901_4107_amd.inputs.configs import kh2d, random3d, sedov3d, conserved_from_primitive, poisson_points
-from tests.util import boost, normwise_rel
+from tests.util import assert_cell_rel, boost, normwise_rel, update_condition
 
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-12  # norm-wise relative, per conserved / primitive component
+# per cell, mass and energy: |got - want| / |want| <= CELL_TOL K_i, K_i the
+# condition of the cell's update (its terms' size against its result)
+CELL_TOL = 1e-12
 
 
 def note(msg):
@@ -94,9 +97,16 @@ def check_one_step(wl, tol=TOL):
     used = r.ctx.mm_hydro_step(r.Q)
     Qs, dto = O.hydro_step(m, wl.gamma, wl.cfl, wl.Q)
     assert abs(used - dto) <= 1e-14 * dto
-    err = assert_close(r.Q.cpu().numpy(), Qs, tol, "hydro step")
+    Qg = r.Q.cpu().numpy()
+    err = assert_close(Qg, Qs, tol, "hydro step")
+    # mass and energy cell by cell (the normwise bound above lets a light
+    # cell hide in the scale of a heavy one)
+    me = (0, m.dim + 1)
+    K = update_condition(m, wl.Q, Fo, Qs, me)
+    cell = assert_cell_rel(Qg, Qs, K, me, CELL_TOL, "hydro step, m and E per cell")
     diag = r.ctx.mm_get_diag()
-    note(f"  max normwise error {err.max():.2e}; vacuum faces {int(np.sum(kase != 0))}, "
+    note(f"  max normwise error {err.max():.2e}; per-cell relative m {cell[0]:.2e} E {cell[1]:.2e} "
+         f"(largest K {K.max():.3g}); vacuum faces {int(np.sum(kase != 0))}, "
          f"fallbacks {int(fb.sum())}; diag {diag}")
     assert diag["vacuum"] == int(np.sum(kase != 0))
     assert diag["positivity_fallback"] == int(fb.sum())

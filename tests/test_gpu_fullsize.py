@@ -10,10 +10,11 @@ configuration bench.py times, through the C ABI:
   one by one by the oracle against the double and the mixed + learned
   batches, every output of the batch finite, the learned guess's iteration
   gain on the whole batch;
-- the 256^3 Sedov step (133M faces): properties that hold at any size
-  (conservation; mass and energy of the cells away from the blast unchanged
-  bit for bit, their momentum change at round-off), the mixed + learned form
-  against the double one.
+- the 256^3 Sedov step (133M faces): both forms against the oracle's whole
+  step at full size (double to 1e-12 normwise and per cell in m and E,
+  mixed + learned within the stated L1), plus properties that hold at any
+  size (conservation; mass and energy of the cells away from the blast
+  unchanged bit for bit, their momentum change at round-off).
 """
 import sys
 
@@ -24,12 +25,25 @@ import torch
 from oracle import oracle as O
 from paper_0901_4107_amd import learned, mm
 from paper_0901_4107_amd.inputs import configs
-from tests.util import boost, l1_state, normwise_rel
+from tests.util import assert_cell_rel, boost, l1_state, normwise_rel, update_condition
 
 pytestmark = pytest.mark.gpu
 
 TOL64 = 1e-12
 L1_BOUND = 1e-6
+CELL_TOL = 1e-12   # per cell, m and E: |got - want| / |want| <= CELL_TOL K_i
+
+
+def oracle_step(wl):
+    """The oracle's whole step split into its parts, so that the face fluxes
+    are at hand for the per-cell condition of the update; the same
+    arithmetic as O.hydro_step."""
+    m = wl.mesh
+    W = O.prim(m.dim, wl.gamma, m.volume, wl.Q)
+    _, G, _ = O.gradients(m, W)
+    dt = O.cfl_dt(m, wl.gamma, wl.cfl, W)
+    F, _, _ = O.face_fluxes(m, wl.gamma, dt, W, G)
+    return O.apply_update(m, F, wl.Q), dt, F
 
 
 def note(msg):
@@ -62,12 +76,14 @@ def test_kh3d_128_headline(kh3d_128):
     wl = kh3d_128
     m = wl.mesh
     note(f"kh3d: N={m.n_cells} F={m.n_faces}; oracle step")
-    Qo, dto = O.hydro_step(m, wl.gamma, wl.cfl, wl.Q)
+    Qo, dto, Fo = oracle_step(wl)
     note("double step")
     Q64, used, diag = step(wl, mm.MM_FP64, mm.MM_GUESS_STANDARD)
     assert abs(used - dto) <= 1e-14 * dto
     err = normwise_rel(Q64, Qo)
-    note(f"double vs oracle: normwise {err}; diag {diag}")
+    K = update_condition(m, wl.Q, Fo, Qo, (0, 4))
+    cell = assert_cell_rel(Q64, Qo, K, (0, 4), CELL_TOL, "kh3d double, m and E per cell")
+    note(f"double vs oracle: normwise {err}; per-cell relative m {cell[0]:.2e} E {cell[1]:.2e}; diag {diag}")
     assert np.all(err <= TOL64), err
     assert diag["unconverged"] == 0
     note("mixed + learned step")
@@ -236,11 +252,20 @@ def test_riemann_batch_2p24():
     assert np.percentile(res["mixed+learned"], 99) <= np.percentile(res["mixed"], 99)
 
 
-def test_sedov_256_properties():
+def test_sedov_256_oracle_and_properties():
+    """The 256^3 point explosion (133M faces) in both forms the benchmark
+    times, against the oracle's whole step at full size: double within
+    1e-12 normwise and per cell (m, E), mixed + learned within the stated
+    L1. Besides: conservation, and the cells more than two faces from the
+    blast unchanged in mass and energy bit for bit, their momentum change at
+    round-off of P dt A."""
     note("building sedov 256^3")
     wl = configs.sedov3d(nthreads=16)
     m = wl.mesh
-    note(f"sedov: N={m.n_cells} F={m.n_faces}")
+    note(f"sedov: N={m.n_cells} F={m.n_faces}; oracle step on {O.threads()} threads")
+    Qo, dto, Fo = oracle_step(wl)
+    K = update_condition(m, wl.Q, Fo, Qo, (0, 4))
+    del Fo
     # cells more than two faces away from an energised cell see only the
     # uniform state at rest during one step
     hot = wl.Q[4] > 2 * np.median(wl.Q[4])
@@ -250,11 +275,9 @@ def test_sedov_256_properties():
         near[m.face_L[touch]] = True
         near[m.face_R[touch]] = True
     far = ~near
-    area = np.zeros(m.n_cells)
-    np.add.at(area, m.face_L, m.face_area)
-    np.add.at(area, m.face_R, m.face_area)
+    area = (np.bincount(m.face_L, weights=m.face_area, minlength=m.n_cells)
+            + np.bincount(m.face_R, weights=m.face_area, minlength=m.n_cells))
     P0 = 1e-5
-    results = {}
     for name, mode, guess, ptol in (("double", mm.MM_FP64, mm.MM_GUESS_STANDARD, 1e-12),
                                     ("mixed+learned", mm.MM_MIXED, mm.MM_GUESS_LEARNED, 1e-6)):
         note(f"{name} step")
@@ -263,14 +286,21 @@ def test_sedov_256_properties():
         scale[1:4] = np.abs(wl.Q[4]).sum()   # momentum against the energy scale (v = 0 initially)
         cons = np.abs(Q1.sum(axis=1) - wl.Q.sum(axis=1)) / scale
         dp = np.sqrt(np.sum((Q1[1:4, far] - wl.Q[1:4, far]) ** 2, axis=0)) / (P0 * dt * area[far])
-        note(f"{name}: dt {dt:.3e}; conservation {cons}; far cells {far.sum()}, "
+        note(f"{name}: dt {dt:.3e} (oracle {dto:.3e}); conservation {cons}; far cells {far.sum()}, "
              f"max |dp| / (P dt A) {dp.max():.2e}; diag {diag}")
+        assert abs(dt - dto) <= 1e-12 * dto
         assert np.all(cons <= 1e-13), cons
         assert np.array_equal(Q1[0, far], wl.Q[0, far]), name
         assert np.array_equal(Q1[4, far], wl.Q[4, far]), name
         assert dp.max() <= ptol, name
         assert diag["unconverged"] == 0
-        results[name] = Q1
-    l1 = l1_state(results["mixed+learned"], results["double"])
-    note(f"mixed + learned vs double: L1 {l1}")
-    assert np.all(l1 <= L1_BOUND), l1
+        if name == "double":
+            err = normwise_rel(Q1, Qo)
+            cell = assert_cell_rel(Q1, Qo, K, (0, 4), CELL_TOL, "sedov double, m and E per cell")
+            note(f"double vs oracle: normwise {err}; per-cell relative m {cell[0]:.2e} E {cell[1]:.2e}")
+            assert np.all(err <= TOL64), err
+        else:
+            l1 = l1_state(Q1, Qo)
+            note(f"mixed + learned vs oracle: L1 {l1}")
+            assert np.all(l1 <= L1_BOUND), l1
+        del Q1

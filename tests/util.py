@@ -64,3 +64,38 @@ def blast_radius(mesh, rho, centre=0.5):
     curv = y0 - 2.0 * y1 + y2
     off = 0.5 * (y0 - y2) / curv if curv < 0 else 0.0
     return (i + 0.5 + off) * h, float(y1)
+
+
+def update_condition(mesh, Q0, F, Q1, rows):
+    """Condition of each cell's update for the given rows of Q:
+    K_i = (|Q0_i| + sum over the cell's faces |F_f|) / |Q1_i| (at least 1),
+    the size of the terms the update sums against the result. Rounding of
+    relative size eps in those terms moves Q1_i by up to about eps K_i |Q1_i|.
+    F [D+2][F] are the face fluxes (dt A Fhat) of the step."""
+    K = np.empty((len(rows), mesh.n_cells))
+    for a, row in enumerate(rows):
+        aF = np.abs(F[row])
+        s = (np.abs(Q0[row]) + np.bincount(mesh.face_L, weights=aF, minlength=mesh.n_cells)
+             + np.bincount(mesh.face_R, weights=aF, minlength=mesh.n_cells))
+        K[a] = np.maximum(s / np.maximum(np.abs(Q1[row]), 1e-300), 1.0)
+    return K
+
+
+def cell_rel(got, want, rows, floor=1e-12):
+    """Per-cell relative error of the given rows: |got - want| / |want| per
+    cell, against floor * max |want| where a cell's value is near zero."""
+    out = []
+    for row in rows:
+        w = np.abs(want[row])
+        out.append(np.abs(got[row] - want[row]) / np.maximum(w, floor * w.max()))
+    return np.array(out)
+
+
+def assert_cell_rel(got, want, K, rows, tol, what):
+    """Per cell and row: |got - want| / |want| <= tol * K_i (K from
+    update_condition). Returns the largest plain per-cell relative error of
+    each row."""
+    rel = cell_rel(got, want, rows)
+    worst = np.max(rel / K, axis=1)
+    assert np.all(worst <= tol), f"{what}: per-cell relative error / K {worst}, rows {rows}"
+    return np.max(rel, axis=1)
