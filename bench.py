@@ -438,7 +438,7 @@ def bench_riemann(args):
     gamma = 5.0 / 3.0
     n = args.size or (1 << 24)
     t0 = time.time()
-    S = torch.from_numpy(configs.riemann_problems(n, nthreads=args.threads)).cuda()
+    S = torch.from_numpy(configs.riemann_problems(n)).cuda()
     log(f"riemann workload: {n} problems built in {time.time() - t0:.1f}s")
     params = learned.load(gamma)
     res = {}

@@ -17,9 +17,14 @@ Workloads
   sedov3d    3D Sedov-Taylor blast on a jittered lattice (Section 8.4).
   rt3d       3D single-mode Rayleigh-Taylor setup (Section 8.8) between two
              reflective walls in a static field, on a jittered lattice.
+  riemann_problems
+             independent 1D Riemann problems drawn from histograms of the
+             problems that runs of random3d, kh3d and sedov3d pose (a data
+             file produced offline), plus hard tails.
 """
 from __future__ import annotations
 
+import os
 from dataclasses import dataclass
 
 import numpy as np
@@ -170,35 +175,6 @@ def sedov3d(n_side: int = 256, jitter: float = 0.1, seed: int = 1004, n_hot: int
     return Workload(f"sedov3d_{n_side}^3", mesh, Q, gamma, 0.4, np.zeros(3), seed, (rho, vel, P))
 
 
-def blast_shell_states(mesh, gamma: float = 5.0 / 3.0, r_shock: float = 0.15, rho0: float = 1.0,
-                       p0: float = 1e-5, energy: float = 1.0):
-    """Primitive states (rho, vel [3][N], P) of an approximate point
-    explosion grown to shock radius r_shock around the box centre: a stand-in
-    for the states a Sedov run passes through, with their structure (a
-    strong shock, a hot rarefied interior, the cold ambient gas), not the
-    exact self-similar solution. Shock speed from the similarity scaling
-    R = xi0 (E t^2 / rho0)^(1/5) with xi0 = 1.15 (gamma = 5/3), so
-    v_s = (2/5) R / t; post-shock state from the strong-shock jump
-    conditions (rho (g+1)/(g-1), velocity 2 v_s/(g+1), pressure
-    2 rho0 v_s^2/(g+1)); inside, for x = r/R: rho ~ x^(3/(g-1)), v ~ x,
-    P ~ 0.3 + 0.7 x^5 (power-law shapes of the interior)."""
-    xi0 = 1.15
-    t = (r_shock / xi0) ** 2.5 * np.sqrt(rho0 / energy)
-    vs = 0.4 * r_shock / t
-    rho2 = rho0 * (gamma + 1.0) / (gamma - 1.0)
-    v2 = 2.0 * vs / (gamma + 1.0)
-    p2 = 2.0 * rho0 * vs * vs / (gamma + 1.0)
-    d = mesh.positions - 0.5
-    r = np.sqrt(np.sum(d * d, axis=1))
-    x = r / r_shock
-    inside = x < 1.0
-    rho = np.where(inside, np.maximum(rho2 * x ** (3.0 / (gamma - 1.0)), 1e-6 * rho2), rho0)
-    P = np.where(inside, p2 * (0.3 + 0.7 * x ** 5), p0)
-    vr = np.where(inside, v2 * x, 0.0)
-    vel = (d / np.maximum(r, 1e-300)[:, None] * vr[:, None]).T
-    return rho, np.ascontiguousarray(vel), P
-
-
 def riemann_tails(n: int, gamma: float, rng) -> np.ndarray:
     """Hard-tail Riemann problems [6][n] (rho_L, u_L, P_L, rho_R, u_R, P_R):
     half near vacuum (velocity jump 80-99.5% of the vacuum threshold
@@ -222,41 +198,61 @@ def riemann_tails(n: int, gamma: float, rng) -> np.ndarray:
     return np.stack([rho[0], u[0], P[0], rho[1], u[1], P[1]])
 
 
-def face_pair_problems(wl: Workload) -> np.ndarray:
-    """The Riemann problems [6][F] posed by the cell-centre states on the two
-    sides of every face of a workload: density, velocity along the L->R
-    normal, pressure."""
-    rho, vel, P = wl.prim
-    m = wl.mesh
-    n = m.face_sep / np.sqrt(np.sum(m.face_sep ** 2, axis=0))
-    uL = np.sum(vel[:, m.face_L] * n, axis=0)
-    uR = np.sum(vel[:, m.face_R] * n, axis=0)
-    return np.stack([rho[m.face_L], uL, P[m.face_L], rho[m.face_R], uR, P[m.face_R]])
+HARVEST = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "data", "riemann_harvest.npz")
+HARVEST_SOURCES = ("random3d", "kh3d", "sedov3d")
 
 
-def riemann_problems(n: int = 1 << 24, seed: int = 1003, side: int = 64, nthreads: int = 0) -> np.ndarray:
-    """16M-style batch of independent 1D Riemann problems [6][n]: face-pair
-    problems of the random-state and boosted Kelvin-Helmholtz workloads and
-    of a grown blast (blast_shell_states on the Sedov mesh; side^3 cells
-    each), resampled with replacement to 95% of n, plus 5% hard tails
-    (riemann_tails). The blast pairs are taken where the two sides differ
-    (the blast region)."""
+def load_harvest(path: str = HARVEST) -> dict:
+    """Histograms of the face-frame Riemann problems that runs of the
+    random-state, boosted Kelvin-Helmholtz and point-explosion workloads pose
+    (a data file of plain arrays; see its producer's description in the
+    file's arrays: per source '<name>_joint' over (ln rho_R/rho_L,
+    ln P_R/P_L, (u_R - u_L)/(c_L + c_R)), '<name>_scale' over
+    (ln rho_L, ln P_L), '<name>_frame' over u_L / c_L, and 'edges_*')."""
+    with np.load(path, allow_pickle=False) as z:
+        return {k: z[k] for k in z.files}
+
+
+def sample_harvest(h: dict, source: str, n: int, gamma: float, rng) -> np.ndarray:
+    """n problems [6][n] (rho_L, u_L, P_L, rho_R, u_R, P_R) drawn from one
+    source's histograms: a joint bin by its count, a scale bin and a frame
+    bin likewise, each value uniform inside its bin; then
+    rho_R = rho_L e^x0, P_R = P_L e^x1, u_L = m c_L, u_R = u_L + x2 (c_L + c_R)
+    with c = sqrt(gamma P / rho)."""
+    def bins(counts, k):
+        p = counts.ravel().astype(np.float64)
+        return np.unravel_index(rng.choice(p.size, size=k, p=p / p.sum()), counts.shape)
+
+    def inside(edges, i):
+        return edges[i] + (edges[i + 1] - edges[i]) * rng.random(i.shape)
+
+    i0, i1, i2 = bins(h[f"{source}_joint"], n)
+    x0, x1, x2 = inside(h["edges_x0"], i0), inside(h["edges_x1"], i1), inside(h["edges_x2"], i2)
+    a, b = bins(h[f"{source}_scale"], n)
+    lr, lp = inside(h["edges_lr"], a), inside(h["edges_lp"], b)
+    (im,) = bins(h[f"{source}_frame"], n)
+    mach = inside(h["edges_m"], im)
+    rhoL, PL = np.exp(lr), np.exp(lp)
+    rhoR, PR = rhoL * np.exp(x0), PL * np.exp(x1)
+    cL, cR = np.sqrt(gamma * PL / rhoL), np.sqrt(gamma * PR / rhoR)
+    uL = mach * cL
+    uR = uL + x2 * (cL + cR)
+    return np.stack([rhoL, uL, PL, rhoR, uR, PR])
+
+
+def riemann_problems(n: int = 1 << 24, seed: int = 1003, path: str = HARVEST) -> np.ndarray:
+    """Batch of independent 1D Riemann problems [6][n]: 95% drawn in equal
+    thirds from the histograms of the problems that runs of the
+    random-state, boosted Kelvin-Helmholtz and point-explosion workloads pose
+    (load_harvest; problems that generate vacuum are not among them), 5% hard
+    tails (riemann_tails), in a seeded random order."""
     rng = np.random.default_rng(seed)
-    gamma = 5.0 / 3.0
-    pools = []
-    for wl in (random3d(n_side=side, seed=seed + 1, nthreads=nthreads),
-               kh3d(n_points=side ** 3, seed=seed + 2, nthreads=nthreads),
-               sedov3d(n_side=side, seed=seed + 3, nthreads=nthreads)):
-        if wl.name.startswith("sedov"):
-            wl.prim = blast_shell_states(wl.mesh, wl.gamma)
-        s = face_pair_problems(wl)
-        if wl.name.startswith("sedov"):
-            s = s[:, (s[0] != s[3]) | (s[1] != s[4]) | (s[2] != s[5])]
-        pools.append(s)
+    h = load_harvest(path)
+    gamma = float(h["gamma"])
     n_tail = n // 20
     n_body = n - n_tail
     per = [n_body // 3, n_body // 3, n_body - 2 * (n_body // 3)]
-    body = [p[:, rng.integers(0, p.shape[1], k)] for p, k in zip(pools, per)]
+    body = [sample_harvest(h, src, k, gamma, rng) for src, k in zip(HARVEST_SOURCES, per)]
     out = np.concatenate(body + [riemann_tails(n_tail, gamma, rng)], axis=1)
     return np.ascontiguousarray(out[:, rng.permutation(n)])
 

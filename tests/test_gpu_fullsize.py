@@ -212,7 +212,7 @@ def batch(S, mode, guess, gamma):
 def test_riemann_batch_2p24():
     gamma = 5.0 / 3.0
     note("building the 2^24 Riemann problems")
-    S_host = configs.riemann_problems(nthreads=16)
+    S_host = configs.riemann_problems()
     S = torch.from_numpy(S_host).cuda()
     n = S.shape[1]
     rng = np.random.default_rng(77)

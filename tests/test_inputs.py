@@ -6,14 +6,43 @@ from paper_0901_4107_amd.inputs import configs
 
 
 def test_riemann_problems_seeded_and_valid():
-    a = configs.riemann_problems(n=4096, side=12, nthreads=4)
-    b = configs.riemann_problems(n=4096, side=12, nthreads=4)
+    a = configs.riemann_problems(n=4096)
+    b = configs.riemann_problems(n=4096)
     assert a.shape == (6, 4096)
     assert np.array_equal(a, b)
     assert np.all(np.isfinite(a))
     assert np.all(a[[0, 3]] > 0) and np.all(a[[2, 5]] > 0)
-    c = configs.riemann_problems(n=4096, side=12, seed=5, nthreads=4)
+    c = configs.riemann_problems(n=4096, seed=5)
     assert not np.array_equal(a, c)
+
+
+def test_harvest_sampling_follows_the_histograms():
+    """Problems drawn from one source's histograms land in its bins with the
+    bins' frequencies (a chi-square-like check on the joint histogram's
+    largest bins), and the drawn features reproduce the histogram's
+    quantities: x0 = ln(rho_R/rho_L), x1 = ln(P_R/P_L),
+    x2 = (u_R - u_L)/(c_L + c_R) and u_L / c_L inside the edges; no problem
+    generates vacuum (x2 < 2/(gamma - 1))."""
+    h = configs.load_harvest()
+    g = float(h["gamma"])
+    rng = np.random.default_rng(11)
+    for src in configs.HARVEST_SOURCES:
+        n = 200000
+        S = configs.sample_harvest(h, src, n, g, rng)
+        rl, ul, pl, rr, ur, pr = S
+        cl, cr = np.sqrt(g * pl / rl), np.sqrt(g * pr / rr)
+        f = np.stack([np.log(rr / rl), np.log(pr / pl), (ur - ul) / (cl + cr)], axis=1)
+        assert np.all(f[:, 2] < 2.0 / (g - 1.0))
+        e = [h["edges_x0"], h["edges_x1"], h["edges_x2"]]
+        got, _ = np.histogramdd(f, bins=e)
+        want = h[f"{src}_joint"].astype(np.float64)
+        want *= n / want.sum()
+        big = want > 2000
+        assert np.all(np.abs(got[big] - want[big]) <= 5 * np.sqrt(want[big])), src
+        assert got[want == 0].sum() <= 1e-4 * n, src   # only round-off of exp and log at bin edges
+        m = ul / cl
+        assert np.all((m >= h["edges_m"][0]) & (m <= h["edges_m"][-1]))
+        assert int(h[f"{src}_problems"]) > 10 ** 5
 
 
 def test_riemann_tails_reach_the_stated_extremes():
@@ -28,32 +57,3 @@ def test_riemann_tails_reach_the_stated_extremes():
     assert ratio.min() >= 1e2 * (1 - 1e-12) and ratio.max() <= 1e6 * (1 + 1e-12)
     assert ratio.max() > 1e5                                # the range is covered
     assert np.all(ur[h:] <= ul[h:])                         # colliding flows
-
-
-def test_blast_shell_jump_conditions():
-    """Just inside the shock the stand-in's state is the strong-shock
-    post-shock state: mass and momentum fluxes through the moving shock
-    balance (Rankine-Hugoniot), and the density jump is (g+1)/(g-1)."""
-    g = 5.0 / 3.0
-    wl = configs.sedov3d(n_side=24, nthreads=4)
-    rho, vel, P = configs.blast_shell_states(wl.mesh, g, r_shock=0.2)
-    d = wl.mesh.positions - 0.5
-    r = np.sqrt(np.sum(d * d, axis=1))
-    inside = r < 0.2
-    assert np.all(P[~inside] == 1e-5) and np.all(rho[~inside] == 1.0)
-    assert np.all(vel[:, ~inside] == 0.0)
-    # radial velocity, outward, growing with r inside
-    vr = np.sum(vel * (d / r[:, None]).T, axis=0)
-    assert np.all(vr[inside] >= 0)
-    # extrapolate the interior profile to x = 1: the post-shock state
-    xi0, E, rho0 = 1.15, 1.0, 1.0
-    t = (0.2 / xi0) ** 2.5 * np.sqrt(rho0 / E)
-    vs = 0.4 * 0.2 / t
-    edge = inside & (r > 0.19)
-    x = r[edge] / 0.2
-    rho2 = np.max(rho[edge] / x ** (3 / (g - 1)))
-    v2 = np.max(vr[edge] / x)
-    p2 = np.max(P[edge] / (0.3 + 0.7 * x ** 5))
-    assert abs(rho2 / rho0 - (g + 1) / (g - 1)) < 1e-12
-    assert abs(rho0 * vs - rho2 * (vs - v2)) <= 1e-12 * rho0 * vs            # mass
-    assert abs((p2 - 1e-5) - rho0 * vs * v2) <= 1e-4 * p2                     # momentum (strong shock)
