@@ -84,8 +84,8 @@ typedef int32_t mm_status;
  * (states at the start of the step, in the frame of the cell's generator),
  * or, with a static field (mm_set_gravity), below beta_s M |g_i| R_i, R_i
  * the radius of the cell's volume. A parameter <= 0 switches its condition
- * off. The update reads the primitive records of the last gradient pass
- * (mm_gradients, or the step's own). */
+ * off. The face pass records each face's two neighbour energies
+ * (MM_FLUX_STRIDE); the cell's own comes from Q at the start of the update. */
 #define MM_ENTROPY_ENERGY 2
 
 /* Timestep scheme (Section 7.2). MM_STEPS_INDIVIDUAL adds the arrays of a
@@ -124,8 +124,11 @@ typedef struct {
  * the face's Mach number: the larger over its sides of
  * sqrt((g+1)/(2g) p* / p_K + (g-1)/(2g)), the Mach number of the shock into
  * side K where p* > p_K and below 1 on a rarefied side; 0 without a star
- * state. */
-#define MM_FLUX_STRIDE(dim, entropy) ((dim) + 2 + ((entropy) ? 2 : 0))
+ * state. With MM_ENTROPY_ENERGY two more: the kinetic energies
+ * M_R |v_R - w_L|^2 / 2 and M_L |v_L - w_R|^2 / 2 of each side in the other
+ * side's generator frame (start-of-step states, M_K = rho_K V_K), what the
+ * update's energy switch needs of the face. */
+#define MM_FLUX_STRIDE(dim, entropy) ((dim) + 2 + ((entropy) ? 2 : 0) + ((entropy) == MM_ENTROPY_ENERGY ? 2 : 0))
 
 /* The given tessellation (Section 3, step list item (i)) and the generator
  * velocities w_i (item (iv)). All device pointers, all kept by reference
@@ -137,7 +140,7 @@ typedef struct {
     const double *volume;        /* [N]    V_i > 0 */
     const double *centroid_off;  /* [D][N] s_i - r_i (centre of mass minus generator) */
     const double *mesh_vel;      /* [D][N] generator velocities w_i */
-    const int32_t *face_L;       /* [F]    0 <= L < N */
+    const int32_t *face_L;       /* [F]    0 <= L < N, non-decreasing in f (faces sorted by left cell) */
     const int32_t *face_R;       /* [F]    0 <= R < N, R != L */
     const double *face_area;     /* [F]    A_f >= 0 */
     const double *face_ctr;      /* [D][F] f - r_L, face centroid relative to L's generator */
@@ -189,9 +192,12 @@ mm_status mm_set_workspace(mm_ctx *ctx, void *dev_ptr, int64_t bytes);
  * face centroid induced by the generators' relative motion).
  * Synchronises the stream (to read the validation result).
  * MM_E_MESH if an index is out of range, L == R, a volume is not positive,
- * an area is negative, a separation is zero, any value is not finite, or a
+ * an area is negative, a separation is zero, any value is not finite, a
  * cell's faces do not close (|sum A n| > 1e-9 sum A; every Voronoi cell is
- * closed, and the gradient estimate relies on it);
+ * closed, and the gradient estimate relies on it), or the faces are not
+ * sorted by left cell (face_L must not decrease: each cell's left faces are
+ * then one contiguous range, which the face pass sums itself for the
+ * update);
  * MM_E_WORKSPACE if the workspace is too small; MM_E_STATE without one. */
 mm_status mm_mesh_upload(mm_ctx *ctx, const mm_mesh *mesh);
 

@@ -1,5 +1,6 @@
 // k_cell.hpp -- per-cell kernels: primitives and the Courant timestep,
-// gradients with slope limiting, and the conservative update.
+// gradients with slope limiting, the entropy row's start, mesh motion (the
+// conservative update is in k_update.hpp).
 //
 // The gradient and update kernels give each cell a group of GS lanes
 // (4; a wavefront serves 16 cells) that walk the cell's
@@ -106,15 +107,31 @@ __device__ __forceinline__ double cell_prim(int64_t i, int64_t n, double gamma, 
     return sqrt(gamma * P / rho);
 }
 
+// The gather record of a cell (mixed mode) from its float primitive record:
+// rho, v_i - w_i, P, then w_i - W0 rounded to float from double, W0 the
+// reference velocity w0 [D] (device).
+template <int D>
+__device__ __forceinline__ void gather_rec(int64_t i, int64_t n, const float (&r)[Lay<D>::PREC],
+                                           const double *__restrict__ mvel, const double *__restrict__ w0,
+                                           float (&g)[Lay<D>::GATH]) {
+    using Y = Lay<D>;
+    for (int k = 0; k < Y::GATH; k++) g[k] = 0.0f;
+    for (int c = 0; c < Y::NV; c++) g[c] = r[Y::W + c];
+    for (int k = 0; k < D; k++) g[Y::GW + k] = (float)(mvel[k * n + i] - w0[k]);
+}
+
 // Step (ii) and the timestep bound of step (v) (Section 7.1): the primitive
 // record of every cell (cell_prim) and the per-block minimum of
 //   dt_i = C R_i / (c_i + |v_i - w_i|), R_i the radius of the cell's volume;
 // vacuum cells impose no limit. As the first kernel of a step it clears the
 // step's non-finite flag (step_flag, may be null).
+// In the mixed mode (T = float) also the gather records (gather, with the
+// reference velocity w0).
 template <int D, typename T>
 __global__ void __launch_bounds__(kBlock) k_prim_cfl(int64_t n, double gamma, double cfl, const double *__restrict__ V,
                                                      const double *__restrict__ Q, const double *__restrict__ mvel,
                                                      const double *__restrict__ coff, T *__restrict__ prim,
+                                                     float *__restrict__ gather, const double *__restrict__ w0,
                                                      double *__restrict__ dt_part, int32_t *step_flag) {
     using Y = Lay<D>;
     const int64_t i = xcd_global_id();
@@ -127,6 +144,11 @@ __global__ void __launch_bounds__(kBlock) k_prim_cfl(int64_t n, double gamma, do
         const double c = cell_prim<D, T>(i, n, gamma, V, Q, mvel, coff, r, v, rel2, R, ok);
         if (ok) dti = cfl * R / (c + sqrt(rel2));
         store_rec<Y::PREC>(prim + i * Y::PREC, r);
+        if constexpr (sizeof(T) == 4) {
+            float g[Y::GATH];
+            gather_rec<D>(i, n, r, mvel, w0, g);
+            store_rec<Y::GATH>(gather + i * Y::GATH, g);
+        }
     }
     dti = block_min(dti);
     if (threadIdx.x == 0) dt_part[xcd_tile()] = dti;
@@ -142,6 +164,61 @@ __global__ void __launch_bounds__(1024) k_min_final(int64_t nparts, const double
     if (threadIdx.x == 0) {
         for (int k = 1; k < 16; k++) v = fmin(v, red[k]);
         out[0] = v;
+    }
+}
+
+// The reference velocity W0 of the mixed mode's gather records: per
+// component the midrange (min + max)/2 of the generator velocities, which
+// makes the largest |w_i - W0| (and so the float rounding of w_i - W0) as
+// small as it can be. Per-block minima and maxima part [grid][2D], then one
+// block for w0 [D]; both order-independent.
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_w0_part(int64_t n, const double *__restrict__ mvel,
+                                                    double *__restrict__ part) {
+    __shared__ double red[2 * D][kBlock / 64];
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    for (int k = 0; k < D; k++) {
+        double lo = i < n ? mvel[k * n + i] : INFINITY;
+        double hi = i < n ? mvel[k * n + i] : -INFINITY;
+        for (int off = 32; off > 0; off >>= 1) {
+            lo = fmin(lo, __shfl_xor(lo, off, 64));
+            hi = fmax(hi, __shfl_xor(hi, off, 64));
+        }
+        if ((threadIdx.x & 63) == 0) {
+            red[2 * k][threadIdx.x / 64] = lo;
+            red[2 * k + 1][threadIdx.x / 64] = hi;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * D) {
+        const int q = threadIdx.x;
+        double v = red[q][0];
+        for (int w = 1; w < kBlock / 64; w++) v = (q & 1) ? fmax(v, red[q][w]) : fmin(v, red[q][w]);
+        part[(int64_t)blockIdx.x * 2 * D + q] = v;
+    }
+}
+
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_w0_final(int64_t nparts, const double *__restrict__ part,
+                                                     double *__restrict__ w0) {
+    __shared__ double red[2 * D][kBlock / 64];
+    for (int q = 0; q < 2 * D; q++) {
+        double v = (q & 1) ? -INFINITY : INFINITY;
+        for (int64_t b = threadIdx.x; b < nparts; b += kBlock)
+            v = (q & 1) ? fmax(v, part[b * 2 * D + q]) : fmin(v, part[b * 2 * D + q]);
+        for (int off = 32; off > 0; off >>= 1)
+            v = (q & 1) ? fmax(v, __shfl_xor(v, off, 64)) : fmin(v, __shfl_xor(v, off, 64));
+        if ((threadIdx.x & 63) == 0) red[q][threadIdx.x / 64] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < D) {
+        const int k = threadIdx.x;
+        double lo = red[2 * k][0], hi = red[2 * k + 1][0];
+        for (int w = 1; w < kBlock / 64; w++) {
+            lo = fmin(lo, red[2 * k][w]);
+            hi = fmax(hi, red[2 * k + 1][w]);
+        }
+        w0[k] = 0.5 * lo + 0.5 * hi;
     }
 }
 
@@ -165,8 +242,11 @@ __global__ void __launch_bounds__(1024) k_min_final(int64_t nparts, const double
 // sides with |Dl| <= tol never hold that maximum unless no side exceeds tol,
 // so the lanes keep plain maxima and minima of Dl and the tolerance is
 // applied once per cell.
-// Mixed mode (T = float): velocities in the record are relative to the
-// cell's generator, so the side record's w_j - w_i restores v_j - v_i.
+// Mixed mode (T = float): velocities in the records are relative to each
+// cell's own generator, so the velocity difference across a side is
+//   v_j - v_i = [(v_j - w_j) - (v_i - w_i)] + [(w_j - W0) - (w_i - W0)],
+// both brackets from the two cells' gather records (no lab-frame velocity is
+// formed in float).
 // Each lane keeps its first KR sides (A/|r|, f - r_i) in registers for the
 // limiter pass and issues their loads together; sides beyond GS*KR (rare)
 // are walked by a loop that re-reads them.
@@ -175,13 +255,15 @@ template <int D, typename T> struct SideAcc {
     T acc[NV][D], dmx[NV], dmn[NV];
 };
 
+// One side: s the side record, pj the neighbour's values and wi the cell's
+// (W; in the mixed mode followed by w - W0 at GW).
 template <int D, typename T, bool MIXED>
 __device__ __forceinline__ void grad_side(const T *s, const T *pj, const T *wi, SideAcc<D, T> &a) {
     constexpr int NV = D + 2;
     const T w = s[0];
     for (int c = 0; c < NV; c++) {
         T dphi = pj[c] - wi[c];
-        if (MIXED && c >= 1 && c <= D) dphi += s[1 + D + (c - 1)];
+        if (MIXED && c >= 1 && c <= D) dphi += pj[Lay<D>::GW + c - 1] - wi[Lay<D>::GW + c - 1];
         const T ad = w * dphi;
         for (int k = 0; k < D; k++) a.acc[c][k] += ad * s[1 + k];
         a.dmx[c] = fmax(a.dmx[c], dphi);
@@ -203,35 +285,41 @@ __device__ __forceinline__ void limit_side(const T *g, const T *dl, const T (&gr
 }
 
 // The gradient and limiter of cell i by its lane group (lane = index in
-// the group); every lane of the group calls it with the same i.
+// the group); every lane of the group calls it with the same i. gath: the
+// gather records (mixed mode; unused in double, where the neighbours'
+// primitive records serve).
 template <int D, typename T>
 __device__ __forceinline__ void grad_cell(int64_t i, int lane, const int32_t *__restrict__ off,
                                           const int32_t *__restrict__ nbr, const T *__restrict__ srec,
                                           const double *__restrict__ V, const T *__restrict__ prim,
-                                          T *__restrict__ grad_out) {
+                                          const float *__restrict__ gath, T *__restrict__ grad_out) {
     using Y = Lay<D>;
     constexpr int NV = D + 2;
     constexpr int GS = Group<D>::GS;
     constexpr bool mixed = sizeof(T) == 4;
     constexpr int KR = mixed ? 5 : 3;   // sides per lane held in registers
     constexpr int SR = mixed ? Y::SREC32 : Y::SREC64;
+    constexpr int NJ = mixed ? Y::GATH : NV;   // values read of a neighbour
     const T eps_t = mixed ? (T)1e-6 : (T)1e-13;
+    const T *nrec = mixed ? (const T *)gath : prim + Y::W;
+    constexpr int NS = mixed ? Y::GATH : Y::PREC;   // their stride
     const int32_t b = off[i], e = off[i + 1];
     // the lane's first KR sides: side records and neighbour indices, then
-    // the neighbours' primitive records, all in flight together (an absent
-    // side reads record 0 of the arrays and is skipped)
-    T sr[KR][SR], pj[KR][NV];   // of a neighbour's record only W is needed
+    // the neighbours' records, all in flight together (an absent side reads
+    // record 0 of the arrays and is skipped)
+    T sr[KR][SR], pj[KR][NJ];
     bool has[KR];
     for (int r = 0; r < KR; r++) {
         const int32_t q = b + lane + r * GS;
         has[r] = q < e;
         const int32_t qq = has[r] ? q : 0;
         load_rec<SR>(srec + (int64_t)qq * SR, sr[r]);
-        load_rec<NV>(prim + (int64_t)nbr[qq] * Y::PREC + Y::W, pj[r]);
+        load_rec<NJ>(nrec + (int64_t)nbr[qq] * NS, pj[r]);
     }
-    T pi[Y::PREC];
+    T pi[Y::PREC], wi[NJ];
     load_rec<Y::PREC>(prim + i * Y::PREC, pi);
-    const T *wi = pi + Y::W, *dl = pi + Y::DL;
+    load_rec<NJ>(nrec + i * NS, wi);
+    const T *dl = pi + Y::DL;
     SideAcc<D, T> a;
     for (int c = 0; c < NV; c++) {
         a.dmx[c] = (T)0;
@@ -241,9 +329,9 @@ __device__ __forceinline__ void grad_cell(int64_t i, int lane, const int32_t *__
     for (int r = 0; r < KR; r++)
         if (has[r]) grad_side<D, T, mixed>(sr[r], pj[r], wi, a);
     for (int32_t q = b + lane + KR * GS; q < e; q += GS) {
-        T s2[SR], p2[NV];
+        T s2[SR], p2[NJ];
         load_rec<SR>(srec + (int64_t)q * SR, s2);
-        load_rec<NV>(prim + (int64_t)nbr[q] * Y::PREC + Y::W, p2);
+        load_rec<NJ>(nrec + (int64_t)nbr[q] * NS, p2);
         grad_side<D, T, mixed>(s2, p2, wi, a);
     }
     const T inv_v = (T)(1.0 / V[i]);
@@ -292,185 +380,12 @@ __device__ __forceinline__ void grad_cell(int64_t i, int lane, const int32_t *__
 template <int D, typename T>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 4)))
 k_grad_limit(int64_t n, const int32_t *__restrict__ off, const int32_t *__restrict__ nbr, const T *__restrict__ srec,
-             const double *__restrict__ V, const T *__restrict__ prim, T *__restrict__ grad_out) {
+             const double *__restrict__ V, const T *__restrict__ prim, const float *__restrict__ gath,
+             T *__restrict__ grad_out) {
     constexpr int GS = Group<D>::GS;
     const int64_t i = xcd_tile() * (kBlock / GS) + threadIdx.x / GS;
     if (i >= n) return;  // whole groups leave together
-    grad_cell<D, T>(i, threadIdx.x % GS, off, nbr, srec, V, prim, grad_out);
-}
-
-// Step (vii): Q_i <- Q_i - sum of the fluxes of faces where i is left
-// + sum where i is right (Section 3, discrete update), the face sums taken
-// by the cell's lane group. A non-finite result raises flags[0] (kept until
-// the diagnostics are reset) and flags[1] (this step's).
-// ENT (Section 3.5): Q has the total entropy S as row D+2 and each flux
-// record carries the face's entropy flux and shock Mach number. S is
-// updated by its flux sum like the other rows; then a cell whose faces'
-// largest Mach number is below mach_thresh, with positive new mass and
-// entropy, keeps it: P = (S/M) rho^gamma and E = P V/(gamma-1) + |p|^2/(2M).
-// Every other cell takes S = M P / rho^gamma of its updated state (0 for
-// M <= 0). The cells that keep are counted in entropy_kept.
-// With the energy switch (ESW, Section 3.5, eqs. eqnScrit1-eqnScrit2) the
-// cell is cold instead when its new thermal energy E - |p|^2/(2M) is below
-// alpha_s times the largest M_j |v_j - w_i|^2 / 2 over the cell and its
-// face neighbours (start-of-step primitive records, in the frame of the
-// cell's generator), or (with GRAV) below beta_s M |g| R.
-// GRAV (Section 5.2, a static field g = accel [D][n]): before the entropy
-// treatment, p += (dt/2)(M^n + M^(n+1)) g and E += (dt/2)(p^n + p^(n+1)).g,
-// dt from dt_ptr when it is set, else dt_val.
-struct EnergySwitch {
-    double alpha_s, beta_s;   // a condition <= 0 is off
-    const void *prim;         // the step's primitive records (float ones hold v - w of their cell)
-    int32_t prim_f32;
-    int32_t reserved;
-    const int32_t *nbr;       // side neighbours, CSR order
-    const double *mvel;       // generator velocities [D][n] (double records)
-    const float *srec32;      // side records, w_j - w_i at 1 + D (float records)
-};
-
-// M_j |v_j - w_i|^2 / 2 of the neighbour j across side q of cell i (j = i,
-// q < 0: the cell itself) from j's primitive record, M_j = rho_j V_j (0 for a
-// vacuum record). Double records hold v_j (w_i given); float records hold
-// v_j - w_j, and the side record adds w_j - w_i.
-template <int D>
-__device__ __forceinline__ double ekin_in_frame(const EnergySwitch &es, int64_t j, int64_t q,
-                                                const double *__restrict__ V, const double (&wi)[D]) {
-    using Y = Lay<D>;
-    double rho, dv[D];
-    if (es.prim_f32) {
-        float p[1 + D];
-        load_rec<1 + D>((const float *)es.prim + j * Y::PREC + Y::W, p);
-        rho = p[0];
-        for (int k = 0; k < D; k++) dv[k] = (double)p[1 + k];
-        if (q >= 0)
-            for (int k = 0; k < D; k++) dv[k] += (double)es.srec32[q * Y::SREC32 + 1 + D + k];
-    } else {
-        double p[1 + D];
-        load_rec<1 + D>((const double *)es.prim + j * Y::PREC + Y::W, p);
-        rho = p[0];
-        for (int k = 0; k < D; k++) dv[k] = p[1 + k] - wi[k];
-    }
-    double e = 0.0;
-    for (int k = 0; k < D; k++) e += dv[k] * dv[k];
-    return rho > 0.0 ? 0.5 * (rho * V[j]) * e : 0.0;
-}
-
-template <int D, bool ENT, bool GRAV, bool ESW = false>
-__global__ void __launch_bounds__(kBlock) k_update(int64_t n, const int32_t *__restrict__ off,
-                                                   const int32_t *__restrict__ ent, const double *__restrict__ flux,
-                                                   double *__restrict__ Q, int32_t *__restrict__ flags,
-                                                   const double *__restrict__ V, double gamma, double mach_thresh,
-                                                   DiagDev *diag, const double *__restrict__ accel,
-                                                   const double *__restrict__ dt_ptr, double dt_val,
-                                                   EnergySwitch es) {
-    constexpr int NV = D + 2;
-    constexpr int FS = NV + (ENT ? 2 : 0);   // record stride
-    constexpr int NS = NV + (ENT ? 1 : 0);   // summed rows
-    constexpr int GS = Group<D>::GS;
-    constexpr int KR = ENT ? 4 : 5;
-    const int lane = threadIdx.x % GS;
-    const int64_t i = xcd_tile() * (kBlock / GS) + threadIdx.x / GS;
-    if (i >= n) return;
-    double acc[NS], mx = 0.0;
-    for (int c = 0; c < NS; c++) acc[c] = 0.0;
-    const int32_t b = off[i], e = off[i + 1];
-    // the lane's first KR sides with their flux records in flight together
-    // (an absent side reads record 0 and adds nothing), then the rare rest
-    double F[KR][FS], sg[KR];
-    for (int r = 0; r < KR; r++) {
-        const int32_t q = b + lane + r * GS;
-        const int32_t en = q < e ? ent[q] : 0;
-        sg[r] = q < e ? ((en & 1) ? 1.0 : -1.0) : 0.0;
-        load_rec<FS>(flux + (int64_t)(en >> 1) * FS, F[r]);
-    }
-    for (int r = 0; r < KR; r++)
-        if (sg[r] != 0.0) {
-            for (int c = 0; c < NS; c++) acc[c] += sg[r] * F[r][c];
-            if constexpr (ENT) mx = fmax(mx, F[r][NV + 1]);
-        }
-    for (int32_t q = b + lane + KR * GS; q < e; q += GS) {
-        const int32_t en = ent[q];
-        double Fq[FS];
-        load_rec<FS>(flux + (int64_t)(en >> 1) * FS, Fq);
-        const double s1 = (en & 1) ? 1.0 : -1.0;
-        for (int c = 0; c < NS; c++) acc[c] += s1 * Fq[c];
-        if constexpr (ENT) mx = fmax(mx, Fq[NV + 1]);
-    }
-    for (int c = 0; c < NS; c++) acc[c] = grp_sum<GS>(acc[c]);
-    if constexpr (ENT) mx = grp_max<GS>(mx);
-    double ekmax = 0.0;
-    if constexpr (ENT && ESW) {
-        {
-            double wi[D];
-            for (int k = 0; k < D; k++) wi[k] = es.prim_f32 ? 0.0 : es.mvel[k * n + i];
-            for (int32_t q = b + lane; q < e; q += GS) ekmax = fmax(ekmax, ekin_in_frame<D>(es, es.nbr[q], q, V, wi));
-            if (lane == 0) ekmax = fmax(ekmax, ekin_in_frame<D>(es, i, -1, V, wi));
-            ekmax = grp_max<GS>(ekmax);
-        }
-    }
-    bool keep = false;
-    if (lane == 0) {
-        double q[NS];
-        for (int c = 0; c < NS; c++) q[c] = Q[c * n + i] + acc[c];
-        if constexpr (GRAV) {
-            const double hdt = 0.5 * (dt_ptr ? *dt_ptr : dt_val), m0 = Q[i];
-            double work = 0.0;
-            for (int k = 0; k < D; k++) {
-                const double gk = accel[k * n + i], p0 = Q[(1 + k) * n + i];
-                q[1 + k] += hdt * (m0 + q[0]) * gk;
-                work += (p0 + q[1 + k]) * gk;
-            }
-            q[NV - 1] += hdt * work;
-        }
-        if constexpr (ENT) {
-            const double m = q[0], S = q[NV];
-            double p2 = 0.0;
-            for (int k = 0; k < D; k++) p2 += q[1 + k] * q[1 + k];
-            bool cold = mx < mach_thresh;
-            if constexpr (ESW) {
-                const double eth = m > 0.0 ? q[NV - 1] - 0.5 * p2 / m : 0.0;
-                cold = es.alpha_s > 0.0 && eth < es.alpha_s * ekmax;
-                if constexpr (GRAV) {
-                    if (!cold && es.beta_s > 0.0) {
-                        double g2 = 0.0;
-                        for (int k = 0; k < D; k++) g2 += accel[k * n + i] * accel[k * n + i];
-                        const double vol = V[i];
-                        const double R = (D == 3) ? cbrt(vol * (3.0 / (4.0 * M_PI))) : sqrt(vol * (1.0 / M_PI));
-                        cold = eth < es.beta_s * m * sqrt(g2) * R;
-                    }
-                }
-            }
-            keep = cold && m > 0.0 && S > 0.0;
-            if (!(m > 0.0)) {
-                q[NV] = 0.0;
-            } else {
-                const double vol = V[i], rho = m / vol, ke = 0.5 * p2 / m;
-                if (keep) {
-                    const double P = (S / m) * mm_pow(rho, gamma);
-                    q[NV - 1] = P * vol / (gamma - 1.0) + ke;
-                } else {
-                    const double P = (gamma - 1.0) * (q[NV - 1] - ke) / vol;
-                    q[NV] = m * P / mm_pow(rho, gamma);
-                }
-            }
-        }
-        bool fin = true;
-        for (int c = 0; c < NS; c++) {
-            Q[c * n + i] = q[c];
-            fin = fin && isfinite(q[c]);
-        }
-        if (!fin) {
-            atomicOr(flags, 1);       // since the last diagnostics reset
-            atomicOr(flags + 1, 1);   // this step
-        }
-    }
-    if constexpr (ENT) {
-        // every lane of the wavefront whose group is live takes part; lane 0
-        // of the wavefront holds the lowest cell index, so it is live too
-        const unsigned long long kb = __ballot(keep);
-        if (diag && (threadIdx.x & 63) == 0 && kb)
-            atomicAdd(&diag[blockIdx.x & (kDiagSlots - 1)].entropy_kept, (unsigned long long)__popcll(kb));
-    }
+    grad_cell<D, T>(i, threadIdx.x % GS, off, nbr, srec, V, prim, gath, grad_out);
 }
 
 // The total entropy of every cell from its conserved state (Section 3.5):

@@ -16,6 +16,7 @@
 #pragma once
 
 #include "common.hpp"
+#include "k_update.hpp"
 #include "layout.hpp"
 #include "mlp.hpp"
 #include "riemann.hpp"
@@ -333,14 +334,37 @@ __device__ __forceinline__ void entropy_terms(const FaceState<T> &fs, T rhoL, T 
     }
 }
 
-// One face's record: the NV fluxes, then (FS = NV + 2) the entropy flux and
-// the Mach number.
-template <int NV, int FS>
-__device__ __forceinline__ void store_face(double *p, const double (&F)[NV], const double (&X)[2]) {
-    double r[FS];
-    for (int c = 0; c < NV; c++) r[c] = F[c];
-    for (int c = NV; c < FS; c++) r[c] = X[c - NV];
-    store_rec<FS>(p, r);
+// The energy switch's per-face values (Section 3.5, eq. eqnScrit1): the
+// kinetic energy of each neighbour in the other's generator frame, from the
+// start-of-step states, M_K = rho_K V_K (0 for a vacuum side):
+//   ek_RL = M_R |v_R - w_L|^2 / 2,  ek_LR = M_L |v_L - w_R|^2 / 2,
+// given dv_RL = v_R - w_L and dv_LR = v_L - w_R.
+template <int D>
+__device__ __forceinline__ void esw_terms(double rhoL, double rhoR, double VL, double VR, const double (&dv_RL)[D],
+                                          const double (&dv_LR)[D], double &ek_RL, double &ek_LR) {
+    double eR = 0.0, eL = 0.0;
+    for (int k = 0; k < D; k++) {
+        eR += dv_RL[k] * dv_RL[k];
+        eL += dv_LR[k] * dv_LR[k];
+    }
+    ek_RL = rhoR > 0.0 ? 0.5 * (rhoR * VR) * eR : 0.0;
+    ek_LR = rhoL > 0.0 ? 0.5 * (rhoL * VL) * eL : 0.0;
+}
+
+// A face's values besides its D + 2 fluxes (EM the entropy mode): the
+// entropy flux and the Mach number (EM >= 1), ek_RL and ek_LR (EM == 2).
+struct FaceX {
+    double v[4];
+};
+
+// One face's record, face-major (the Rec<D, EM>::FM values).
+template <int D, int EM>
+__device__ __forceinline__ void store_face(double *p, const double (&F)[D + 2], const FaceX &X) {
+    using RC = Rec<D, EM>;
+    double r[RC::FM];
+    for (int c = 0; c < D + 2; c++) r[c] = F[c];
+    for (int c = D + 2; c < RC::FM; c++) r[c] = X.v[c - D - 2];
+    store_rec<RC::FM>(p, r);
 }
 
 // One point of the individual-timestep integration (Section 7.2) as the
@@ -388,33 +412,44 @@ __device__ __forceinline__ void lab_flux(double rho, double u, double P, const d
     out[NV - 1] = scale * (eps + Piw + 0.5 * mf * w2);
 }
 
+// What the face bodies read besides the records: the static field
+// (GRAV, Section 5.2; accel [D][n], g = -grad Phi), and for the energy
+// switch the cell volumes and (double path) the generator velocities.
+struct FaceAux {
+    const double *accel;
+    const double *V;
+    const double *mvel;
+    int64_t n;
+};
+
 // Double-precision flux of face f (dt A Fhat into F), the body of the face
 // kernel. The left and right states are predicted over hdtL and hdtR (dt/2
 // each in a global step; with individual timesteps each side's record age
 // plus half the face's step). Every thread of the block calls it (the
 // learned staging holds barriers); active = false does no face. LEARNED
 // compiles the fused network in; the standard-guess instantiation carries
-// none of its registers. ENT adds the entropy flux and the shock Mach
-// number (X). GRAV adds the half-step kick hdt g_K of a static field
-// (Section 5.2; accel [D][n], g = -grad Phi) to each side's predicted
-// velocity; a face that falls back to its unextrapolated states takes none.
-template <int D, bool LEARNED, bool ENT, bool GRAV>
+// none of its registers. EM >= 1 adds the entropy flux and the shock Mach
+// number, EM == 2 the energy switch's values (X). GRAV adds the half-step
+// kick hdt g_K of the static field to each side's predicted velocity; a
+// face that falls back to its unextrapolated states takes none.
+template <int D, bool LEARNED, int EM, bool GRAV>
 __device__ __forceinline__ void face_flux64(bool active, int64_t f, const int32_t *__restrict__ fL,
                                             const int32_t *__restrict__ fR, const double *__restrict__ frec,
                                             const double *__restrict__ prim, const double *__restrict__ grad,
                                             double dt, double hdtL, double hdtR, const GasConst<double> &kg,
-                                            double tol, int maxit,
-                                            const MlpPacked *mlp, const double *__restrict__ accel, int64_t n,
-                                            LaneDiag &ld, double (&F)[D + 2], double (&X)[2]) {
+                                            double tol, int maxit, const MlpPacked *mlp, const FaceAux &aux,
+                                            LaneDiag &ld, double (&F)[D + 2], FaceX &X) {
     using Y = Lay<D>;
     constexpr int NV = D + 2;
     double A = 0.0, nrm[D], w[D], xl[NV], xr[NV], uL = 0.0, uR = 0.0;
+    double rhoL0 = 0.0, rhoR0 = 0.0, dv_RL[D], dv_LR[D];
     for (int c = 0; c < NV; c++) { xl[c] = 1.0; xr[c] = 1.0; }
     if (active) {
         double fr[Y::FREC];
         load_rec<Y::FREC>(frec + f * Y::FREC, fr);
-        const CellRec<D, double> rl = load_cell<D>(prim, grad, fL[f]);
-        const CellRec<D, double> rr = load_cell<D>(prim, grad, fR[f]);
+        const int64_t l = fL[f], r = fR[f];
+        const CellRec<D, double> rl = load_cell<D>(prim, grad, l);
+        const CellRec<D, double> rr = load_cell<D>(prim, grad, r);
         A = fr[Y::FA];
         const double hl = 0.5 * fr[Y::FELL];
         double gL[D], gR[D];
@@ -425,16 +460,23 @@ __device__ __forceinline__ void face_flux64(bool active, int64_t f, const int32_
             gL[k] = c + hl * nrm[k];   // f - r_L
             gR[k] = c - hl * nrm[k];   // f - r_R
         }
+        if constexpr (EM == 2) {   // lab-frame velocities against the other generator
+            rhoL0 = rl.p[Y::W];
+            rhoR0 = rr.p[Y::W];
+            for (int k = 0; k < D; k++) {
+                dv_RL[k] = rr.p[Y::W + 1 + k] - aux.mvel[k * aux.n + l];
+                dv_LR[k] = rl.p[Y::W + 1 + k] - aux.mvel[k * aux.n + r];
+            }
+        }
         double cl[NV], cr[NV], vf[D];
         for (int k = 0; k < D; k++) vf[k] = rl.p[Y::W + 1 + k] - w[k];
         half_step<D, double>(rl, vf, gL, kg.g, hdtL, xl, cl);
         for (int k = 0; k < D; k++) vf[k] = rr.p[Y::W + 1 + k] - w[k];
         half_step<D, double>(rr, vf, gR, kg.g, hdtR, xr, cr);
         if constexpr (GRAV) {
-            const int64_t l = fL[f], r = fR[f];
             for (int k = 0; k < D; k++) {
-                xl[1 + k] += hdtL * accel[k * n + l];
-                xr[1 + k] += hdtR * accel[k * n + r];
+                xl[1 + k] += hdtL * aux.accel[k * aux.n + l];
+                xr[1 + k] += hdtR * aux.accel[k * aux.n + r];
             }
         }
         if (!(xl[0] > 0.0 && xl[NV - 1] > 0.0 && xr[0] > 0.0 && xr[NV - 1] > 0.0)) {
@@ -458,36 +500,37 @@ __device__ __forceinline__ void face_flux64(bool active, int64_t f, const int32_
         double tv[D];
         for (int k = 0; k < D; k++) tv[k] = xs[1 + k] - un * nrm[k];
         lab_flux<D>(fs.rho, fs.u, fs.P, tv, nrm, w, kg.g_over_gm1, dt * A, F);
-        if constexpr (ENT) {
+        if constexpr (EM != 0) {
             double AU, mach;
             entropy_terms<double>(fs, xl[0], xl[NV - 1], xr[0], xr[NV - 1], kg, AU, mach);
-            X[0] = F[0] * AU;
-            X[1] = mach;
+            X.v[0] = F[0] * AU;
+            X.v[1] = mach;
         }
+        if constexpr (EM == 2)
+            esw_terms<D>(rhoL0, rhoR0, aux.V[fL[f]], aux.V[fR[f]], dv_RL, dv_LR, X.v[2], X.v[3]);
     }
 }
 
-// Double-precision face flux kernel: one lane per face, fluxes stored
-// face-major (ENT: each record followed by the entropy flux and the Mach
-// number).
-template <int D, bool LEARNED, bool ENT, bool GRAV>
+// Double-precision face flux kernel: one lane per face, records
+// face-major (Rec<D, EM>::FM values per face).
+template <int D, bool LEARNED, int EM, bool GRAV>
 __global__ void __launch_bounds__(kBlock) k_face_flux64(int64_t nf, const int32_t *__restrict__ fL,
                                                         const int32_t *__restrict__ fR, const double *__restrict__ frec,
                                                         const double *__restrict__ prim, const double *__restrict__ grad,
                                                         const double *__restrict__ dt_ptr, double dt_val,
                                                         GasConst<double> kg, double tol, int maxit,
                                                         const MlpPacked *mlp, double *__restrict__ flux, DiagDev *diag,
-                                                        const double *__restrict__ accel, int64_t n) {
+                                                        FaceAux aux) {
     constexpr int NV = D + 2;
-    constexpr int FS = NV + (ENT ? 2 : 0);
     const int64_t f = xcd_global_id();
     const bool active = f < nf;
     LaneDiag ld;
     const double dt = dt_ptr ? *dt_ptr : dt_val;
-    double F[NV], X[2];
-    face_flux64<D, LEARNED, ENT, GRAV>(active, f, fL, fR, frec, prim, grad, dt, 0.5 * dt, 0.5 * dt, kg, tol, maxit,
-                                       mlp, accel, n, ld, F, X);
-    if (active) store_face<NV, FS>(flux + f * FS, F, X);
+    double F[NV];
+    FaceX X;
+    face_flux64<D, LEARNED, EM, GRAV>(active, f, fL, fR, frec, prim, grad, dt, 0.5 * dt, 0.5 * dt, kg, tol, maxit,
+                                      mlp, aux, ld, F, X);
+    if (active) store_face<D, EM>(flux + f * Rec<D, EM>::FM, F, X);
     if (diag) flush_diag(ld, diag);
 }
 
@@ -495,26 +538,29 @@ __global__ void __launch_bounds__(kBlock) k_face_flux64(int64_t nf, const int32_
 // frame transform and half step on velocities relative to the face (the
 // cell record holds v_i - w_i and w_K - w_f follows from the face record's
 // w_L - w_R, so v - w_f = (v_K - w_K) + (w_K - w_f) never forms a lab-frame
-// velocity).
+// velocity). With EM == 2 also the energy switch's values (ek_RL, ek_LR):
+// v_R - w_L = (v_R - w_R) - (w_L - w_R) and v_L - w_R = (v_L - w_L) + (w_L - w_R).
 template <int D> struct MixedFace {
     float xl[D + 2], xr[D + 2], uL, uR, nrm[D], A;
     bool posfb;
+    double ek_RL, ek_LR;
 };
 
-template <int D, bool GRAV>
+template <int D, int EM, bool GRAV>
 __device__ __forceinline__ MixedFace<D> mixed_face_states(int64_t f, const int32_t *__restrict__ fL,
                                                           const int32_t *__restrict__ fR,
                                                           const float *__restrict__ mrec,
                                                           const float *__restrict__ prim,
                                                           const float *__restrict__ grad, float hdtL, float hdtR,
-                                                          float gam, const double *__restrict__ accel, int64_t n) {
+                                                          float gam, const FaceAux &aux) {
     using Y = Lay<D>;
     constexpr int NV = D + 2;
     MixedFace<D> o;
     float fr[Y::MREC];
     load_rec<Y::MREC>(mrec + f * Y::MREC, fr);
-    const CellRec<D, float> rl = load_cell<D>(prim, grad, fL[f]);
-    const CellRec<D, float> rr = load_cell<D>(prim, grad, fR[f]);
+    const int64_t l = fL[f], r = fR[f];
+    const CellRec<D, float> rl = load_cell<D>(prim, grad, l);
+    const CellRec<D, float> rr = load_cell<D>(prim, grad, r);
     o.A = fr[Y::FA];
     const float hl = 0.5f * fr[Y::FELL];
     float gL[D], gR[D], cl[NV], cr[NV], vf[D], dw[D], proj = 0.0f;
@@ -526,6 +572,15 @@ __device__ __forceinline__ MixedFace<D> mixed_face_states(int64_t f, const int32
         dw[k] = fr[Y::MDW + k];
         proj += dw[k] * c;
     }
+    o.ek_RL = o.ek_LR = 0.0;
+    if constexpr (EM == 2) {
+        double dv_RL[D], dv_LR[D];
+        for (int k = 0; k < D; k++) {
+            dv_RL[k] = (double)rr.p[Y::W + 1 + k] - (double)dw[k];
+            dv_LR[k] = (double)rl.p[Y::W + 1 + k] + (double)dw[k];
+        }
+        esw_terms<D>((double)rl.p[Y::W], (double)rr.p[Y::W], aux.V[l], aux.V[r], dv_RL, dv_LR, o.ek_RL, o.ek_LR);
+    }
     // w_L - w_f = dw/2 - (dw.c/|d|) n and w_R - w_f = -dw/2 - (dw.c/|d|) n
     proj *= 0.5f / hl;
     for (int k = 0; k < D; k++) vf[k] = rl.p[Y::W + 1 + k] + (0.5f * dw[k] - proj * o.nrm[k]);
@@ -533,10 +588,9 @@ __device__ __forceinline__ MixedFace<D> mixed_face_states(int64_t f, const int32
     for (int k = 0; k < D; k++) vf[k] = rr.p[Y::W + 1 + k] + (-0.5f * dw[k] - proj * o.nrm[k]);
     half_step<D, float>(rr, vf, gR, gam, hdtR, o.xr, cr);
     if constexpr (GRAV) {   // the half-step kick of a static field (Section 5.2)
-        const int64_t l = fL[f], r = fR[f];
         for (int k = 0; k < D; k++) {
-            o.xl[1 + k] += hdtL * (float)accel[k * n + l];
-            o.xr[1 + k] += hdtR * (float)accel[k * n + r];
+            o.xl[1 + k] += hdtL * (float)aux.accel[k * aux.n + l];
+            o.xr[1 + k] += hdtR * (float)aux.accel[k * aux.n + r];
         }
     }
     o.posfb = !(o.xl[0] > 0.0f && o.xl[NV - 1] > 0.0f && o.xr[0] > 0.0f && o.xr[NV - 1] > 0.0f);
@@ -565,28 +619,31 @@ __device__ __forceinline__ void mixed_lab_flux(const MixedFace<D> &m, double rho
     lab_flux<D>(rho, u, P, tv, nd, w, g_over_gm1, dt * (double)m.A, out);
 }
 
+// LDS the learned staging of the mixed kernel parks the face states in while
+// the network runs (floats).
+template <int D> constexpr int stash_floats() { return (2 * (D + 2) + D + 1) * kBlock; }
+
 // Mixed-precision flux of face f (dt A Fhat into F): float face states and
 // float Newton; the lab-frame flux and everything after it in double. Faces
 // the float solve judges hard (strong rarefaction or near vacuum, tiny
 // guess, no convergence) come back with hard = true and no flux. The body
 // of the face kernel. Every thread of the block calls it (the learned staging holds
 // barriers); active = false does no face. While the network runs, the face
-// states wait in LDS, so the network's registers come on top of few live
-// values.
-template <int D, bool LEARNED, bool ENT, bool GRAV>
+// states wait in LDS (stash: (2(D+2) + D + 1) kBlock floats), so the
+// network's registers come on top of few live values.
+template <int D, bool LEARNED, int EM, bool GRAV>
 __device__ __forceinline__ void face_flux_mixed(bool active, int64_t f, const int32_t *__restrict__ fL,
                                                 const int32_t *__restrict__ fR, const float *__restrict__ mrec,
                                                 const double *__restrict__ wf64, const float *__restrict__ prim,
                                                 const float *__restrict__ grad, double dt, double hdtL, double hdtR,
                                                 const GasConst<float> &kf, double g_over_gm1, float tol32, int maxit,
-                                                const MlpPacked *mlp,
-                                                const double *__restrict__ accel, int64_t n,
-                                                LaneDiag &ld, bool &hard, double (&F)[D + 2], double (&X)[2]) {
+                                                const MlpPacked *mlp, const FaceAux &aux, float *stash,
+                                                LaneDiag &ld, bool &hard, double (&F)[D + 2], FaceX &X) {
     constexpr int NV = D + 2;
     hard = false;
     MixedFace<D> m;
     if (active) {
-        m = mixed_face_states<D, GRAV>(f, fL, fR, mrec, prim, grad, (float)hdtL, (float)hdtR, kf.g, accel, n);
+        m = mixed_face_states<D, EM, GRAV>(f, fL, fR, mrec, prim, grad, (float)hdtL, (float)hdtR, kf.g, aux);
         ld.posfb += m.posfb ? 1 : 0;
     } else {
         for (int c = 0; c < NV; c++) { m.xl[c] = 1.0f; m.xr[c] = 1.0f; }
@@ -596,7 +653,6 @@ __device__ __forceinline__ void face_flux_mixed(bool active, int64_t f, const in
     float pl = no_guess<float>();
     if constexpr (LEARNED) {
         __shared__ LearnLds sh;
-        __shared__ float stash[2 * NV + D + 1][kBlock];
         const bool want =
             active && wants_learned<float>(m.xl[0], m.uL, m.xl[NV - 1], m.xr[0], m.uR, m.xr[NV - 1], kf.g);
         int slot = 0;
@@ -604,14 +660,14 @@ __device__ __forceinline__ void face_flux_mixed(bool active, int64_t f, const in
         if (total > 0) {   // the same for the whole block
             if (want) learn_put<float>(sh, slot, m.xl[0], m.uL, m.xl[NV - 1], m.xr[0], m.uR, m.xr[NV - 1], kf.g);
             const int t = threadIdx.x;
-            for (int c = 0; c < NV; c++) { stash[c][t] = m.xl[c]; stash[NV + c][t] = m.xr[c]; }
-            for (int k = 0; k < D; k++) stash[2 * NV + k][t] = m.nrm[k];
-            stash[2 * NV + D][t] = m.A;
+            for (int c = 0; c < NV; c++) { stash[c * kBlock + t] = m.xl[c]; stash[(NV + c) * kBlock + t] = m.xr[c]; }
+            for (int k = 0; k < D; k++) stash[(2 * NV + k) * kBlock + t] = m.nrm[k];
+            stash[(2 * NV + D) * kBlock + t] = m.A;
             learn_run(sh, mlp, total);
             pl = learn_get<float>(sh, want, slot);
-            for (int c = 0; c < NV; c++) { m.xl[c] = stash[c][t]; m.xr[c] = stash[NV + c][t]; }
-            for (int k = 0; k < D; k++) m.nrm[k] = stash[2 * NV + k][t];
-            m.A = stash[2 * NV + D][t];
+            for (int c = 0; c < NV; c++) { m.xl[c] = stash[c * kBlock + t]; m.xr[c] = stash[(NV + c) * kBlock + t]; }
+            for (int k = 0; k < D; k++) m.nrm[k] = stash[(2 * NV + k) * kBlock + t];
+            m.A = stash[(2 * NV + D) * kBlock + t];
             m.uL = 0.0f;
             m.uR = 0.0f;
             for (int k = 0; k < D; k++) { m.uL += m.xl[1 + k] * m.nrm[k]; m.uR += m.xr[1 + k] * m.nrm[k]; }
@@ -624,20 +680,24 @@ __device__ __forceinline__ void face_flux_mixed(bool active, int64_t f, const in
                                                 maxit, pl, true, ld, hard);
         if (!hard) {
             mixed_lab_flux<D>(m, fs.rho, fs.u, fs.P, fs.side, wf64, f, g_over_gm1, dt, F);
-            if constexpr (ENT) {
+            if constexpr (EM != 0) {
                 float AU, mach;
                 entropy_terms<float>(fs, m.xl[0], m.xl[NV - 1], m.xr[0], m.xr[NV - 1], kf, AU, mach);
-                X[0] = F[0] * (double)AU;
-                X[1] = (double)mach;
+                X.v[0] = F[0] * (double)AU;
+                X.v[1] = (double)mach;
             }
+        }
+        if constexpr (EM == 2) {
+            X.v[2] = m.ek_RL;
+            X.v[3] = m.ek_LR;
         }
     }
 }
 
-// Mixed-precision face flux kernel: one lane per face; hard faces are
-// appended to a split list (wave-aggregated) and left to k_face_flux_hard.
-// Held to 7 wavefronts per SIMD (72 registers, no spills).
-template <int D, bool LEARNED, bool ENT, bool GRAV>
+// Mixed-precision face flux kernel: one lane per face, records face-major;
+// hard faces are appended to a split list (wave-aggregated) and left to
+// k_face_flux_hard. Held to 7 wavefronts per SIMD.
+template <int D, bool LEARNED, int EM, bool GRAV>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) k_face_flux_mixed(int64_t nf, const int32_t *__restrict__ fL,
                                                             const int32_t *__restrict__ fR,
                                                             const float *__restrict__ mrec,
@@ -648,29 +708,59 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))
                                                             GasConst<float> kf, double g_over_gm1, float tol32,
                                                             int maxit, const MlpPacked *mlp,
                                                             double *__restrict__ flux, int32_t *__restrict__ hard_list,
-                                                            int64_t cap, DiagDev *diag,
-                                                            const double *__restrict__ accel, int64_t n) {
+                                                            int64_t cap, DiagDev *diag, FaceAux aux) {
     constexpr int NV = D + 2;
-    constexpr int FS = NV + (ENT ? 2 : 0);
+    __shared__ float stash[LEARNED ? stash_floats<D>() : 1];
     const int64_t f = xcd_global_id();
     const bool active = f < nf;
     LaneDiag ld;
     bool hard;
     const double dt = dt_ptr ? *dt_ptr : dt_val;
-    double F[NV], X[2];
-    face_flux_mixed<D, LEARNED, ENT, GRAV>(active, f, fL, fR, mrec, wf64, prim, grad, dt, 0.5 * dt, 0.5 * dt, kf,
-                                           g_over_gm1, tol32, maxit, mlp, accel, n, ld, hard, F, X);
-    if (active && !hard) store_face<NV, FS>(flux + f * FS, F, X);
+    double F[NV];
+    FaceX X;
+    face_flux_mixed<D, LEARNED, EM, GRAV>(active, f, fL, fR, mrec, wf64, prim, grad, dt, 0.5 * dt, 0.5 * dt, kf,
+                                          g_over_gm1, tol32, maxit, mlp, aux, stash, ld, hard, F, X);
+    if (active && !hard) store_face<D, EM>(flux + f * Rec<D, EM>::FM, F, X);
     list_append(hard_list, cap, hard, (int32_t)f);
     if (diag) flush_diag(ld, diag);
 }
 
+// The double solve of a hard face: the float face states recomputed by the
+// same code (hence identical), the Riemann problem in double, the lab-frame
+// flux; over the prediction intervals hl, hr and the step dt.
+template <int D, int EM, bool GRAV>
+__device__ __forceinline__ void hard_face(int64_t f, const int32_t *__restrict__ fL, const int32_t *__restrict__ fR,
+                                          const float *__restrict__ mrec, const double *__restrict__ wf64,
+                                          const float *__restrict__ prim, const float *__restrict__ grad, double dt,
+                                          double hl, double hr, float gam, const GasConst<double> &kg, double tol64,
+                                          const FaceAux &aux, LaneDiag &ld, double (&F)[D + 2], FaceX &X) {
+    constexpr int NV = D + 2;
+    const MixedFace<D> m =
+        mixed_face_states<D, EM, GRAV>(f, fL, fR, mrec, prim, grad, (float)hl, (float)hr, gam, aux);
+    bool h2;
+    FaceState<double> fd = solve_face<double>(m.xl[0], m.uL, m.xl[NV - 1], m.xr[0], m.uR, m.xr[NV - 1], kg, tol64,
+                                              50, no_guess<double>(), false, ld, h2);
+    ld.fp64fb += 1;
+    mixed_lab_flux<D>(m, fd.rho, fd.u, fd.P, fd.side, wf64, f, kg.g_over_gm1, dt, F);
+    if constexpr (EM != 0) {
+        double AU, mach;
+        entropy_terms<double>(fd, (double)m.xl[0], (double)m.xl[NV - 1], (double)m.xr[0], (double)m.xr[NV - 1], kg,
+                              AU, mach);
+        X.v[0] = F[0] * AU;
+        X.v[1] = mach;
+    }
+    if constexpr (EM == 2) {
+        X.v[2] = m.ek_RL;
+        X.v[3] = m.ek_LR;
+    }
+}
+
 // Double re-solve of the hard faces listed by k_face_flux_mixed (a split
-// list of sub-list capacity cap). A fixed grid walks the list, so the
-// launch needs no host-side count; the float face states are recomputed by
-// the same code, hence identical. With tb.bin set (individual timesteps)
-// each face takes its step and prediction intervals from the timeline.
-template <int D, bool ENT, bool GRAV>
+// list of sub-list capacity cap), face-major records. A fixed grid
+// walks the list, so the launch needs no host-side count. With tb.bin set
+// (individual timesteps) each face takes its step and prediction intervals
+// from the timeline.
+template <int D, int EM, bool GRAV>
 __global__ void __launch_bounds__(kBlock) k_face_flux_hard(const int32_t *__restrict__ fL,
                                                            const int32_t *__restrict__ fR,
                                                            const float *__restrict__ mrec,
@@ -680,10 +770,9 @@ __global__ void __launch_bounds__(kBlock) k_face_flux_hard(const int32_t *__rest
                                                            const double *__restrict__ dt_ptr, double dt_val,
                                                            float gam, GasConst<double> kg, double tol64,
                                                            const int32_t *__restrict__ hard_list, int64_t cap,
-                                                           double *__restrict__ flux, DiagDev *diag,
-                                                           const double *__restrict__ accel, int64_t n, TbView tb) {
+                                                           double *__restrict__ flux, DiagDev *diag, FaceAux aux,
+                                                           TbView tb) {
     constexpr int NV = D + 2;
-    constexpr int FS = NV + (ENT ? 2 : 0);
     const ListWalk lw = list_walk(hard_list, cap);
     if (tb.bin) tb.ti = tb64(tb.info, TB_TI);
     LaneDiag ld;
@@ -691,22 +780,10 @@ __global__ void __launch_bounds__(kBlock) k_face_flux_hard(const int32_t *__rest
         const int64_t f = lw.items[q];
         double dt = dt_ptr ? *dt_ptr : dt_val, hl = 0.5 * dt, hr = 0.5 * dt;
         if (tb.bin) tb.face(fL[f], fR[f], dt, hl, hr);
-        const MixedFace<D> m =
-            mixed_face_states<D, GRAV>(f, fL, fR, mrec, prim, grad, (float)hl, (float)hr, gam, accel, n);
-        bool h2;
-        FaceState<double> fd = solve_face<double>(m.xl[0], m.uL, m.xl[NV - 1], m.xr[0], m.uR, m.xr[NV - 1], kg,
-                                                  tol64, 50, no_guess<double>(), false, ld, h2);
-        ld.fp64fb += 1;
-        double F[NV], X[2];
-        mixed_lab_flux<D>(m, fd.rho, fd.u, fd.P, fd.side, wf64, f, kg.g_over_gm1, dt, F);
-        if constexpr (ENT) {
-            double AU, mach;
-            entropy_terms<double>(fd, (double)m.xl[0], (double)m.xl[NV - 1], (double)m.xr[0], (double)m.xr[NV - 1],
-                                  kg, AU, mach);
-            X[0] = F[0] * AU;
-            X[1] = mach;
-        }
-        store_face<NV, FS>(flux + f * FS, F, X);
+        double F[NV];
+        FaceX X;
+        hard_face<D, EM, GRAV>(f, fL, fR, mrec, wf64, prim, grad, dt, hl, hr, gam, kg, tol64, aux, ld, F, X);
+        store_face<D, EM>(flux + f * Rec<D, EM>::FM, F, X);
     }
     if (diag) flush_diag(ld, diag);
 }
@@ -738,10 +815,11 @@ __global__ void __launch_bounds__(kBlock) k_face_flux64_list(const int32_t *__re
         const int64_t f = active ? items[q] : 0;
         double fdt = 0.0, hl = 0.0, hr = 0.0;
         if (active) tb.face(fL[f], fR[f], fdt, hl, hr);
-        double F[NV], X[2];
-        face_flux64<D, LEARNED, false, false>(active, f, fL, fR, frec, prim, grad, fdt, hl, hr, kg, tol, maxit, mlp,
-                                              nullptr, 0, ld, F, X);
-        if (active) store_face<NV, NV>(flux + f * NV, F, X);
+        double F[NV];
+        FaceX X;
+        face_flux64<D, LEARNED, 0, false>(active, f, fL, fR, frec, prim, grad, fdt, hl, hr, kg, tol, maxit, mlp,
+                                          FaceAux{nullptr, nullptr, nullptr, 0}, ld, F, X);
+        if (active) store_face<D, 0>(flux + f * NV, F, X);
     }
     if (diag) flush_diag(ld, diag);
 }
@@ -758,6 +836,7 @@ k_face_flux_mixed_list(const int32_t *__restrict__ list, int64_t cap, const int3
                        float tol32, int maxit, const MlpPacked *mlp, double *__restrict__ flux,
                        int32_t *__restrict__ hard_list, DiagDev *diag) {
     constexpr int NV = D + 2;
+    __shared__ float stash[LEARNED ? stash_floats<D>() : 1];
     const int c = blockIdx.x % kLists;
     const int32_t *items = list + (int64_t)kLists * kListPad + c * cap;
     tb.ti = tb64(tb.info, TB_TI);
@@ -771,10 +850,12 @@ k_face_flux_mixed_list(const int32_t *__restrict__ list, int64_t cap, const int3
         double fdt = 0.0, hl = 0.0, hr = 0.0;
         if (active) tb.face(fL[f], fR[f], fdt, hl, hr);
         bool hard;
-        double F[NV], X[2];
-        face_flux_mixed<D, LEARNED, false, false>(active, f, fL, fR, mrec, wf64, prim, grad, fdt, hl, hr, kf,
-                                                  g_over_gm1, tol32, maxit, mlp, nullptr, 0, ld, hard, F, X);
-        if (active && !hard) store_face<NV, NV>(flux + f * NV, F, X);
+        double F[NV];
+        FaceX X;
+        face_flux_mixed<D, LEARNED, 0, false>(active, f, fL, fR, mrec, wf64, prim, grad, fdt, hl, hr, kf,
+                                              g_over_gm1, tol32, maxit, mlp, FaceAux{nullptr, nullptr, nullptr, 0},
+                                              stash, ld, hard, F, X);
+        if (active && !hard) store_face<D, 0>(flux + f * NV, F, X);
         list_append(hard_list, cap, active && hard, (int32_t)f);
     }
     if (diag) flush_diag(ld, diag);

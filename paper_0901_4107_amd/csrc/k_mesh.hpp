@@ -10,7 +10,7 @@ namespace mm {
 
 enum MeshFlag : int {
     MF_INDEX = 1, MF_SELF = 2, MF_VOLUME = 4, MF_AREA = 8, MF_SEP = 16, MF_CTR = 32,
-    MF_CENTROID = 64, MF_MESHVEL = 128, MF_OPEN = 256
+    MF_CENTROID = 64, MF_MESHVEL = 128, MF_OPEN = 256, MF_ORDER = 512
 };
 
 __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
@@ -147,6 +147,45 @@ __global__ void k_sort_segments(int64_t n, const int32_t *off, int32_t *ent, int
     }
 }
 
+// The update's view of each cell's faces (k_update.hpp), from its side list
+// (ascending face order): the number of faces where it is the left and the
+// right cell, into lcnt[i] and rcnt[i] (for the offset scans).
+__global__ void k_lr_count(int64_t n, const int32_t *__restrict__ off, const int32_t *__restrict__ ent,
+                           int32_t *__restrict__ lcnt, int32_t *__restrict__ rcnt) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    int32_t nl = 0, nr = 0;
+    for (int32_t q = off[i]; q < off[i + 1]; q++) {
+        if (ent[q] & 1) nr++;
+        else nl++;
+    }
+    lcnt[i] = nl;
+    rcnt[i] = nr;
+}
+
+// After the scans: each cell's right faces in ascending face order
+// (rface[roff[i] ...]), and the check that the faces are sorted by left
+// cell (the k-th left face of cell i must be face loff[i] + k, else
+// MF_ORDER).
+__global__ void k_lr_fill(int64_t n, const int32_t *__restrict__ off, const int32_t *__restrict__ ent,
+                          const int32_t *__restrict__ loff, const int32_t *__restrict__ roff,
+                          int32_t *__restrict__ rface, int32_t *flags) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    int32_t kl = loff[i], kr = roff[i];
+    bool bad = false;
+    for (int32_t q = off[i]; q < off[i + 1]; q++) {
+        const int32_t en = ent[q], f = en >> 1;
+        if (en & 1) {
+            rface[kr++] = f;
+        } else {
+            bad = bad || f != kl;
+            kl++;
+        }
+    }
+    if (bad) atomicOr(flags, MF_ORDER);
+}
+
 // Face records (Section 3.3 geometry and face velocity):
 //   n = d/|d|, c = f - (r_L + r_R)/2 = g - d/2,
 //   w_f = (w_L + w_R)/2 + [(w_L - w_R) . c / |d|] n.
@@ -197,16 +236,16 @@ __global__ void __launch_bounds__(kBlock) k_face_records(int64_t n, int64_t nf, 
     }
 }
 
-// Side records in CSR order, one lane per cell: A/|d| and f - r_i in double
-// for the double path, with w_j - w_i in float for the mixed path, and the
+// Side records in CSR order, one lane per cell: A/|d| and f - r_i, in
+// double for the double path and in float for the mixed path, and the
 // closure test of each cell,
 // |sum_faces A n_out| <= 1e-9 sum_faces A. A closed surface is a property of
 // every Voronoi cell; the gradient kernels rely on it.
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_side_records(int64_t n, int64_t nf, const int32_t *off,
-                                                         const int32_t *ent, const int32_t *nbr, const double *area,
-                                                         const double *ctr, const double *sep, const double *mvel,
-                                                         double *srec, int mixed, float *srec32, int32_t *flags) {
+                                                         const int32_t *ent, const double *area, const double *ctr,
+                                                         const double *sep, double *srec, int mixed, float *srec32,
+                                                         int32_t *flags) {
     using Y = Lay<D>;
     int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
@@ -221,7 +260,6 @@ __global__ void __launch_bounds__(kBlock) k_side_records(int64_t n, int64_t nf, 
         const double ell = sqrt(s2), A = area[f];
         double o[Y::SREC64];
         o[0] = A / ell;
-        const int32_t j = nbr[q];
         for (int k = 0; k < D; k++) {
             const double c = ctr[k * nf + f] - 0.5 * d[k];
             o[1 + k] = c + 0.5 * sg * d[k];
@@ -232,13 +270,9 @@ __global__ void __launch_bounds__(kBlock) k_side_records(int64_t n, int64_t nf, 
             for (int k = 0; k < Y::SREC64; k++) srec[(int64_t)q * Y::SREC64 + k] = o[k];
         asum += A;
         if (mixed) {
-            float *m = srec32 + (int64_t)q * Y::SREC32;
-            m[0] = (float)(A / ell);
-            for (int k = 0; k < D; k++) {
-                m[1 + k] = (float)o[1 + k];
-                m[1 + D + k] = (float)(mvel[k * n + j] - mvel[k * n + i]);
-            }
-            for (int k = 1 + 2 * D; k < Y::SREC32; k++) m[k] = 0.0f;
+            float m[Y::SREC32];
+            for (int k = 0; k < Y::SREC32; k++) m[k] = (float)o[k];
+            store_rec<Y::SREC32>(srec32 + (int64_t)q * Y::SREC32, m);
         }
     }
     double cl2 = 0.0;

@@ -31,6 +31,7 @@
 
 #include "common.hpp"
 #include "k_cell.hpp"
+#include "k_update.hpp"
 #include "layout.hpp"
 
 namespace mm {
@@ -124,6 +125,7 @@ __global__ void __launch_bounds__(kBlock) k_tb_open(int64_t n, int32_t *__restri
                                                     double gamma, const double *__restrict__ V,
                                                     const double *__restrict__ Q, const double *__restrict__ mvel,
                                                     const double *__restrict__ coff, T *__restrict__ prim,
+                                                    float *__restrict__ gather, const double *__restrict__ w0,
                                                     double *__restrict__ sig, int32_t *__restrict__ list,
                                                     int64_t cap) {
     using Y = Lay<D>;
@@ -142,6 +144,11 @@ __global__ void __launch_bounds__(kBlock) k_tb_open(int64_t n, int32_t *__restri
             bool ok;
             const double c = cell_prim<D, T>(i, n, gamma, V, Q, mvel, coff, r, v, rel2, R, ok);
             store_rec<Y::PREC>(prim + i * Y::PREC, r);
+            if constexpr (sizeof(T) == 4) {   // the mixed mode's gather record
+                float g[Y::GATH];
+                gather_rec<D>(i, n, r, mvel, w0, g);
+                store_rec<Y::GATH>(gather + i * Y::GATH, g);
+            }
             double s[SG];
             s[0] = c;
             for (int k = 0; k < D; k++) s[1 + k] = v[k];
@@ -183,7 +190,8 @@ k_tb_active(const int32_t *__restrict__ list, int64_t cap, double dt_max, int32_
             const int32_t *__restrict__ off, const int32_t *__restrict__ ent, const int32_t *__restrict__ nbr,
             const double *__restrict__ frec, const double *__restrict__ sig, int8_t *__restrict__ bin,
             int32_t *__restrict__ info, const T *__restrict__ srec, const double *__restrict__ V,
-            const T *__restrict__ prim, T *__restrict__ grad_out, int32_t *__restrict__ touch,
+            const T *__restrict__ prim, const float *__restrict__ gath, T *__restrict__ grad_out,
+            int32_t *__restrict__ touch,
             int32_t *__restrict__ faces, int64_t fcap, int32_t *__restrict__ touched, int64_t tcap) {
     using Y = Lay<D>;
     constexpr int SG = D + 2;
@@ -242,7 +250,7 @@ k_tb_active(const int32_t *__restrict__ list, int64_t cap, double dt_max, int32_
             }
         }
         // 2
-        grad_cell<D, T>(i, lane, off, nbr, srec, V, prim, grad_out);
+        grad_cell<D, T>(i, lane, off, nbr, srec, V, prim, gath, grad_out);
         // 3
         if (claim_faces) {   // the same for the whole grid
             list_append(touched, tcap, lane == 0, (int32_t)i);
@@ -294,69 +302,41 @@ __global__ void __launch_bounds__(kBlock) k_tb_faces(int64_t nf, const int32_t *
     }
 }
 
-// The update of a touched cell i by its lane group: Q_i gains the signed
-// time-integrated fluxes of its active faces (the same lane-group sums, in
-// the same order, as the global update, inactive faces adding nothing). A
-// non-finite result raises flags[0] and flags[1] like the global update.
+// Where a cell's faces are, for the update (k_update.hpp): its left range,
+// its right-cell slots and their faces, and every face's two cells.
+struct TbSides {
+    const int32_t *lOff, *rOff, *rFace, *fL, *fR;
+};
+
+// The update of a touched cell i by its lane group: Q_i changes by the
+// time-integrated fluxes of its active faces (a face is active when the
+// smaller step of its two cells starts at ti), in the global update's
+// order (k_update.hpp), inactive faces adding nothing; so that a point at
+// which every cell is active is the global step bit for bit. A non-finite
+// result raises flags[0] and flags[1] like the global update.
 template <int D>
-__device__ __forceinline__ void tb_update_cell(int64_t i, int lane, int64_t n, const int32_t *__restrict__ off,
-                                               const int32_t *__restrict__ ent, const int32_t *__restrict__ nbr,
+__device__ __forceinline__ void tb_update_cell(int64_t i, int lane, int64_t n, const TbSides &sd,
                                                const int8_t *__restrict__ bin, int64_t ti,
                                                const double *__restrict__ flux, double *__restrict__ Q,
                                                int32_t *__restrict__ flags) {
     constexpr int NV = D + 2;
-    constexpr int GS = Group<D>::GS;
-    constexpr int KR = 5;
-    const int bi = bin[i];
-    double acc[NV];
-    for (int c = 0; c < NV; c++) acc[c] = 0.0;
-    const int32_t b = off[i], e = off[i + 1];
-    double F[KR][NV], sg[KR];
-    for (int r = 0; r < KR; r++) {
-        const int32_t q = b + lane + r * GS;
-        bool live = q < e;
-        int32_t en = 0;
-        if (live) {
-            en = ent[q];
-            const int bj = bin[nbr[q]];
-            live = tb_starts(ti, bi < bj ? bi : bj);
-        }
-        sg[r] = live ? ((en & 1) ? 1.0 : -1.0) : 0.0;
-        load_rec<NV>(flux + (int64_t)(live ? (en >> 1) : 0) * NV, F[r]);
-    }
-    for (int r = 0; r < KR; r++)
-        if (sg[r] != 0.0)
-            for (int c = 0; c < NV; c++) acc[c] += sg[r] * F[r][c];
-    for (int32_t q = b + lane + KR * GS; q < e; q += GS) {
-        const int32_t en = ent[q];
-        const int bj = bin[nbr[q]];
-        if (!tb_starts(ti, bi < bj ? bi : bj)) continue;
-        double Fq[NV];
-        load_rec<NV>(flux + (int64_t)(en >> 1) * NV, Fq);
-        const double s1 = (en & 1) ? 1.0 : -1.0;
-        for (int c = 0; c < NV; c++) acc[c] += s1 * Fq[c];
-    }
-    for (int c = 0; c < NV; c++) acc[c] = grp_sum<GS>(acc[c]);
+    auto live = [&](int32_t f) {
+        const int bl = bin[sd.fL[f]], br = bin[sd.fR[f]];
+        return tb_starts(ti, bl < br ? bl : br);
+    };
+    double acc[NV], mx, ek;
+    cell_sums<D, 0>(i, lane, sd.lOff, sd.rOff, sd.rFace, flux, live, acc, mx, ek);
     if (lane == 0) {
-        bool fin = true;
-        for (int c = 0; c < NV; c++) {
-            const double qn = Q[c * n + i] + acc[c];
-            Q[c * n + i] = qn;
-            fin = fin && isfinite(qn);
-        }
-        if (!fin) {
-            atomicOr(flags, 1);
-            atomicOr(flags + 1, 1);
-        }
+        UpdateArgs u{};
+        u.flags = flags;
+        finish_cell<D, 0, false>(i, n, acc, 0.0, 0.0, Q, u);
     }
 }
 
 // Dense points: every cell, those not stamped at this point leaving at
 // once; a fixed grid of lane groups strides over the cells.
 template <int D>
-__global__ void __launch_bounds__(kBlock) k_tb_update(int64_t n, const int32_t *__restrict__ off,
-                                                      const int32_t *__restrict__ ent,
-                                                      const int32_t *__restrict__ nbr, const int8_t *__restrict__ bin,
+__global__ void __launch_bounds__(kBlock) k_tb_update(int64_t n, TbSides sd, const int8_t *__restrict__ bin,
                                                       const int32_t *__restrict__ info,
                                                       const int32_t *__restrict__ touch,
                                                       const double *__restrict__ flux, double *__restrict__ Q,
@@ -366,16 +346,13 @@ __global__ void __launch_bounds__(kBlock) k_tb_update(int64_t n, const int32_t *
     const int64_t ti = tb64(info, TB_TI);
     const int32_t cur = info[TB_CUR];
     for (int64_t i = (int64_t)blockIdx.x * G + threadIdx.x / GS; i < n; i += (int64_t)gridDim.x * G)
-        if (touch[i] == cur) tb_update_cell<D>(i, threadIdx.x % GS, n, off, ent, nbr, bin, ti, flux, Q, flags);
+        if (touch[i] == cur) tb_update_cell<D>(i, threadIdx.x % GS, n, sd, bin, ti, flux, Q, flags);
 }
 
 // Sparse points: the cells of the touched list.
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_tb_update_list(const int32_t *__restrict__ list, int64_t cap, int64_t n,
-                                                           const int32_t *__restrict__ off,
-                                                           const int32_t *__restrict__ ent,
-                                                           const int32_t *__restrict__ nbr,
-                                                           const int8_t *__restrict__ bin,
+                                                           TbSides sd, const int8_t *__restrict__ bin,
                                                            const double *__restrict__ flux, double *__restrict__ Q,
                                                            int32_t *__restrict__ flags,
                                                            const int32_t *__restrict__ info) {
@@ -387,7 +364,7 @@ __global__ void __launch_bounds__(kBlock) k_tb_update_list(const int32_t *__rest
     const int64_t count = list[c * kListPad];
     const int64_t stride = (int64_t)(gridDim.x / kLists) * G;
     for (int64_t q = (int64_t)(blockIdx.x / kLists) * G + threadIdx.x / GS; q < count; q += stride)
-        tb_update_cell<D>(items[q], threadIdx.x % GS, n, off, ent, nbr, bin, ti, flux, Q, flags);
+        tb_update_cell<D>(items[q], threadIdx.x % GS, n, sd, bin, ti, flux, Q, flags);
 }
 
 // End of a point: on a point that ran and did not halt, the sizes of its

@@ -1,0 +1,233 @@
+// k_update.hpp -- step (vii), the conservative update (Section 3, eq.
+// eqnupdate): each cell loses the fluxes of the faces where it is the left
+// cell and gains those where it is the right cell.
+//
+// Faces are sorted by their left cell, so the faces of which cell i is the
+// left cell form the contiguous range [lOff_i, lOff_{i+1}) of the face
+// records: a wavefront's cells read one contiguous stretch of records for
+// their left sides. The right sides are the faces rFace[rOff_i ...], in
+// ascending face order, gathered. Lane l of the cell's group of GS lanes
+// sums, from 0, minus the left faces lOff_i + l, + GS, ... and then plus
+// the right faces of slots rOff_i + l, + GS, ...; the group's butterfly sum
+// is added to Q_i. Every path (the step, the split entry points, the
+// individual timesteps) uses this order, so they give the same bits.
+//
+// Records (face-major, written by the face kernels). EM is the entropy
+// mode (0 off, 1 Mach switch, 2 energy switch). A face's values: the D + 2
+// fluxes, then (EM >= 1) the entropy flux and the face's shock Mach number,
+// then (EM == 2) the kinetic energies of the two neighbours in each other's
+// generator frames (Section 3.5, eq. eqnScrit1):
+//   ek_RL = M_R |v_R - w_L|^2 / 2 (for the left cell's switch),
+//   ek_LR = M_L |v_L - w_R|^2 / 2 (for the right cell's).
+#pragma once
+
+#include "common.hpp"
+#include "k_cell.hpp"
+#include "layout.hpp"
+
+namespace mm {
+
+template <int D, int EM> struct Rec {
+    static constexpr int NV = D + 2;
+    static constexpr int NS = NV + (EM ? 1 : 0);                       // summed values
+    static constexpr int MACH = NV + 1, EK_RL = NV + 2, EK_LR = NV + 3;  // maxima
+    static constexpr int FM = NV + (EM ? 2 : 0) + (EM == 2 ? 2 : 0);   // record stride
+};
+
+// What the end of a cell's update needs besides the sums.
+struct UpdateArgs {
+    int32_t *flags;            // [0] since the diagnostics' reset, [1] this step
+    const double *V;
+    double gamma, mach_thresh;
+    DiagDev *diag;
+    const double *accel;       // static field [D][n] or null
+    const double *dt_ptr;      // timestep of the flux pass (device) or null
+    double dt_val;             // ... or its value
+    double alpha_s, beta_s;    // energy switch
+    const double *mvel;        // generator velocities [D][n]
+};
+
+// The end of cell i's update, by lane 0 of its group: Q_i <- Q_i + acc,
+// then the static field's sources (Section 5.2, a static field g = accel
+// [D][n]: p += (dt/2)(M^n + M^(n+1)) g and E += (dt/2)(p^n + p^(n+1)).g, dt
+// of the flux pass) and the entropy treatment (Section 3.5: a cell keeps
+// its advected entropy, P = (S/M) rho^gamma and E = P V/(gamma-1) +
+// |p|^2/(2M), when it is cold -- its largest face Mach number below
+// mach_thresh (EM == 1), or its new thermal energy E - |p|^2/(2M) below
+// alpha_s times the largest neighbour kinetic energy in its generator's
+// frame, or with a field below beta_s M |g| R (EM == 2) -- and its new mass
+// and entropy are positive; every other cell takes S = M P / rho^gamma of
+// its updated state, 0 for M <= 0).
+// mx: the largest face Mach number, ek: the largest neighbour kinetic energy
+// in the cell's generator frame (the cell's own is added here, from Q at the
+// start of the step). Returns whether the cell kept its entropy.
+template <int D, int EM, bool GRAV>
+__device__ __forceinline__ bool finish_cell(int64_t i, int64_t n, const double *acc, double mx, double ek,
+                                            double *__restrict__ Q, const UpdateArgs &u) {
+    constexpr int NV = D + 2;
+    constexpr int NS = Rec<D, EM>::NS;
+    double q[NS];
+    for (int c = 0; c < NS; c++) q[c] = Q[c * n + i] + acc[c];
+    if constexpr (EM == 2) {
+        const double m0 = Q[i];
+        if (m0 > 0.0) {
+            double e = 0.0;
+            for (int k = 0; k < D; k++) {
+                const double dv = Q[(1 + k) * n + i] / m0 - u.mvel[k * n + i];
+                e += dv * dv;
+            }
+            ek = fmax(ek, 0.5 * m0 * e);
+        }
+    }
+    if constexpr (GRAV) {
+        const double hdt = 0.5 * (u.dt_ptr ? *u.dt_ptr : u.dt_val), m0 = Q[i];
+        double work = 0.0;
+        for (int k = 0; k < D; k++) {
+            const double gk = u.accel[k * n + i], p0 = Q[(1 + k) * n + i];
+            q[1 + k] += hdt * (m0 + q[0]) * gk;
+            work += (p0 + q[1 + k]) * gk;
+        }
+        q[NV - 1] += hdt * work;
+    }
+    bool keep = false;
+    if constexpr (EM != 0) {
+        const double m = q[0], S = q[NV];
+        double p2 = 0.0;
+        for (int k = 0; k < D; k++) p2 += q[1 + k] * q[1 + k];
+        bool cold = mx < u.mach_thresh;
+        if constexpr (EM == 2) {
+            const double eth = m > 0.0 ? q[NV - 1] - 0.5 * p2 / m : 0.0;
+            cold = u.alpha_s > 0.0 && eth < u.alpha_s * ek;
+            if constexpr (GRAV) {
+                if (!cold && u.beta_s > 0.0) {
+                    double g2 = 0.0;
+                    for (int k = 0; k < D; k++) g2 += u.accel[k * n + i] * u.accel[k * n + i];
+                    const double vol = u.V[i];
+                    const double R = (D == 3) ? cbrt(vol * (3.0 / (4.0 * M_PI))) : sqrt(vol * (1.0 / M_PI));
+                    cold = eth < u.beta_s * m * sqrt(g2) * R;
+                }
+            }
+        }
+        keep = cold && m > 0.0 && S > 0.0;
+        if (!(m > 0.0)) {
+            q[NV] = 0.0;
+        } else {
+            const double vol = u.V[i], rho = m / vol, ke = 0.5 * p2 / m;
+            if (keep) {
+                const double P = (S / m) * mm_pow(rho, u.gamma);
+                q[NV - 1] = P * vol / (u.gamma - 1.0) + ke;
+            } else {
+                const double P = (u.gamma - 1.0) * (q[NV - 1] - ke) / vol;
+                q[NV] = m * P / mm_pow(rho, u.gamma);
+            }
+        }
+    }
+    bool fin = true;
+    for (int c = 0; c < NS; c++) {
+        Q[c * n + i] = q[c];
+        fin = fin && isfinite(q[c]);
+    }
+    if (!fin) {
+        atomicOr(u.flags, 1);       // since the last diagnostics reset
+        atomicOr(u.flags + 1, 1);   // this step
+    }
+    return keep;
+}
+
+// The cells that kept their entropy, one atomic per wavefront. Every lane of
+// the wavefront whose group is live takes part; lane 0 of the wavefront
+// holds the lowest cell index, so it is live too.
+__device__ __forceinline__ void count_kept(bool keep, DiagDev *diag) {
+    const unsigned long long kb = __ballot(keep);
+    if (diag && (threadIdx.x & 63) == 0 && kb)
+        atomicAdd(&diag[blockIdx.x & (kDiagSlots - 1)].entropy_kept, (unsigned long long)__popcll(kb));
+}
+
+// The sums of cell i by lane `lane` of its group: acc = the lane's share
+// (minus its left faces, plus its right faces, in that order), butterfly
+// summed over the group; mx, ek the group's largest Mach number and
+// neighbour energy. live(f): whether face f takes part (individual
+// timesteps); the rest contribute nothing. Each lane keeps up to KL left and
+// KR right records in flight together, the rare rest in loops.
+template <int D, int EM, typename Live>
+__device__ __forceinline__ void cell_sums(int64_t i, int lane, const int32_t *__restrict__ lOff,
+                                          const int32_t *__restrict__ rOff, const int32_t *__restrict__ rFace,
+                                          const double *__restrict__ flux, Live live,
+                                          double (&acc)[Rec<D, EM>::NS], double &mx, double &ek) {
+    using RC = Rec<D, EM>;
+    constexpr int NS = RC::NS, FM = RC::FM;
+    constexpr int FL = EM == 2 ? RC::EK_RL + 1 : FM;   // values read of a left face
+    constexpr int GS = Group<D>::GS;
+    constexpr int KL = 2, KR = 2;
+    for (int c = 0; c < NS; c++) acc[c] = 0.0;
+    mx = 0.0;
+    ek = 0.0;
+    const int32_t l0 = lOff[i], l1 = lOff[i + 1], r0 = rOff[i], r1 = rOff[i + 1];
+    double FLr[KL][FL], FRr[KR][FM];
+    bool hl[KL], hr[KR];
+    int32_t fr[KR];
+    for (int r = 0; r < KR; r++) {
+        const int32_t q = r0 + lane + r * GS;
+        fr[r] = q < r1 ? rFace[q] : 0;
+    }
+    for (int r = 0; r < KL; r++) {
+        const int32_t f = l0 + lane + r * GS;
+        hl[r] = f < l1 && live(f);
+        load_rec<FL>(flux + (int64_t)(hl[r] ? f : 0) * FM, FLr[r]);
+    }
+    for (int r = 0; r < KR; r++) {
+        hr[r] = r0 + lane + r * GS < r1 && live(fr[r]);
+        load_rec<FM>(flux + (int64_t)(hr[r] ? fr[r] : 0) * FM, FRr[r]);
+    }
+    auto take_left = [&](const double *F) {
+        for (int c = 0; c < NS; c++) acc[c] -= F[c];
+        if constexpr (EM != 0) mx = fmax(mx, F[RC::MACH]);
+        if constexpr (EM == 2) ek = fmax(ek, F[RC::EK_RL]);
+    };
+    auto take_right = [&](const double *F) {
+        for (int c = 0; c < NS; c++) acc[c] += F[c];
+        if constexpr (EM != 0) mx = fmax(mx, F[RC::MACH]);
+        if constexpr (EM == 2) ek = fmax(ek, F[RC::EK_LR]);
+    };
+    for (int r = 0; r < KL; r++)
+        if (hl[r]) take_left(FLr[r]);
+    for (int32_t f = l0 + lane + KL * GS; f < l1; f += GS) {
+        if (!live(f)) continue;
+        double F[FL];
+        load_rec<FL>(flux + (int64_t)f * FM, F);
+        take_left(F);
+    }
+    for (int r = 0; r < KR; r++)
+        if (hr[r]) take_right(FRr[r]);
+    for (int32_t q = r0 + lane + KR * GS; q < r1; q += GS) {
+        const int32_t f = rFace[q];
+        if (!live(f)) continue;
+        double F[FM];
+        load_rec<FM>(flux + (int64_t)f * FM, F);
+        take_right(F);
+    }
+    for (int c = 0; c < NS; c++) acc[c] = grp_sum<GS>(acc[c]);
+    if constexpr (EM != 0) mx = grp_max<GS>(mx);
+    if constexpr (EM == 2) ek = grp_max<GS>(ek);
+}
+
+// The update (the step, mm_apply_update): one lane group per cell.
+template <int D, int EM, bool GRAV>
+__global__ void __launch_bounds__(kBlock) k_update(int64_t n, const int32_t *__restrict__ lOff,
+                                                   const int32_t *__restrict__ rOff,
+                                                   const int32_t *__restrict__ rFace,
+                                                   const double *__restrict__ flux, double *__restrict__ Q,
+                                                   UpdateArgs u) {
+    using RC = Rec<D, EM>;
+    constexpr int GS = Group<D>::GS;
+    const int lane = threadIdx.x % GS;
+    const int64_t i = xcd_tile() * (kBlock / GS) + threadIdx.x / GS;
+    if (i >= n) return;
+    double acc[RC::NS], mx, ek;
+    cell_sums<D, EM>(i, lane, lOff, rOff, rFace, flux, [](int32_t) { return true; }, acc, mx, ek);
+    bool keep = false;
+    if (lane == 0) keep = finish_cell<D, EM, GRAV>(i, n, acc, mx, ek, Q, u);
+    if constexpr (EM != 0) count_kept(keep, u.diag);
+}
+
+}  // namespace mm

@@ -8,6 +8,10 @@
 //                              padding to 16 (3D) / 8 (2D)
 // In double precision the velocities are lab-frame; in the mixed mode the
 // records are float and hold v_i - w_i.
+// Gather record (mixed mode), one per cell [N][GATH], what a neighbour's
+// gradient pass reads of a cell: rho, v_i - w_i (D), P, w_i - W0 (D), padding
+// to 8; W0 the midrange of the generator velocities (a uniform bulk motion
+// leaves every w_i - W0 at zero, so it costs no float bits).
 //
 // Face record (double path), one per face:
 //   A, |d|, n (D) = d/|d|, c (D) = f - (r_L + r_R)/2, w_f (D).
@@ -19,7 +23,7 @@
 // Face fluxes: face-major, D + 2 doubles per face.
 // Side record, one per (cell, face) pair in CSR order:
 //   double path: A/|d|, f - r_i (D)             stride 4
-//   mixed path:  A/|d|, f - r_i (D), w_j - w_i (D)  stride 8 (float)
+//   mixed path:  A/|d|, f - r_i (D)             stride 4 (float)
 #pragma once
 
 namespace mm {
@@ -42,7 +46,9 @@ template <int D> struct Lay {
     static constexpr int FSTRIDE = NV;
     // side records
     static constexpr int SREC64 = 4;
-    static constexpr int SREC32 = 8;
+    static constexpr int SREC32 = 4;
+    // gather records (mixed mode)
+    static constexpr int GATH = 8, GW = NV;   // w_i - W0 at element GW
 };
 
 }  // namespace mm

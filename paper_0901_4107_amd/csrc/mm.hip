@@ -24,6 +24,7 @@
 #include "k_learn.hpp"
 #include "k_mesh.hpp"
 #include "k_tb.hpp"
+#include "k_update.hpp"
 #include "k_walls.hpp"
 #include "layout.hpp"
 
@@ -53,16 +54,21 @@ inline int64_t tb_face_cap(int64_t n, int64_t nf) {
 inline int64_t tb_touch_cap(int64_t n, int64_t nf) { return tb_face_cap(n, nf) + tb_cells_per_residue(n); }
 inline int64_t split_ints(int64_t cap) { return (int64_t)kLists * kListPad + kLists * cap; }
 
+inline unsigned plain_grid_n(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
 struct Layout {
     int64_t flags, diag, mlp, dtdev, bhard, dtpart, bsum, off, cursor, ent, nbr;
-    int64_t srec, frec, rec, flux;          // double path (frec always)
-    int64_t srec32, mrec, wf64, rec32, hard; // mixed path
+    int64_t loff, roff, rface;              // the update's left ranges and right faces
+    int64_t srec, frec, rec, flux;          // double path (frec always; flux: timelines only)
+    int64_t srec32, mrec, wf64, rec32, hard, gath, w0, w0part; // mixed path
     int64_t tb_bin, tb_trec, tb_sig, tb_touch, tb_cells, tb_faces, tb_touched, tb_info;   // individual timesteps
     int64_t total;
 };
 
-Layout make_layout(int D, int mode, bool ent, bool tb, int64_t n, int64_t nf) {
+// em: the entropy mode (0 off, MM_ENTROPY_MACH, MM_ENTROPY_ENERGY).
+Layout make_layout(int D, int mode, int em, bool tb, int64_t n, int64_t nf) {
     const int NV = D + 2;
+    const int FM = NV + (em ? 2 : 0) + (em == MM_ENTROPY_ENERGY ? 2 : 0);   // Rec<D, em>::FM
     const int REC = (D == 3) ? Lay<3>::REC : Lay<2>::REC;
     const int FREC = (D == 3) ? Lay<3>::FREC : Lay<2>::FREC;
     const int WS = (D == 3) ? Lay<3>::WSTRIDE : Lay<2>::WSTRIDE;
@@ -84,13 +90,19 @@ Layout make_layout(int D, int mode, bool ent, bool tb, int64_t n, int64_t nf) {
     L.ent = take(2 * nf * sizeof(int32_t));
     L.nbr = take(2 * nf * sizeof(int32_t));
     L.frec = take(nf * FREC * sizeof(double));
-    L.flux = take(nf * (NV + (ent ? 2 : 0)) * sizeof(double));
-    L.srec = L.srec32 = L.mrec = L.wf64 = L.rec32 = L.rec = L.hard = -1;
+    L.loff = take((n + 1) * sizeof(int32_t));
+    L.roff = take((n + 1) * sizeof(int32_t));
+    L.rface = take(nf * sizeof(int32_t));
+    L.flux = take(nf * FM * sizeof(double));
+    L.srec = L.srec32 = L.mrec = L.wf64 = L.rec32 = L.rec = L.hard = L.gath = L.w0 = L.w0part = -1;
     if (mode == MM_FP64) {
         L.srec = take(2 * nf * Lay<3>::SREC64 * sizeof(double));
         L.rec = take(n * REC * sizeof(double));
     } else {
         L.srec32 = take(2 * nf * Lay<3>::SREC32 * sizeof(float));
+        L.gath = take(n * Lay<3>::GATH * sizeof(float));
+        L.w0 = take(4 * sizeof(double));
+        L.w0part = take((int64_t)plain_grid_n(n) * 2 * 3 * sizeof(double));
         L.mrec = take(nf * Lay<3>::MREC * sizeof(float));
         L.wf64 = take(nf * WS * sizeof(double));
         L.rec32 = take(n * REC * sizeof(float));
@@ -129,7 +141,6 @@ struct mm_ctx {
     const double *last_dt_dev = nullptr;  // timestep of the last face-flux pass (device) ...
     double last_dt = 0.0;                 // ... or its value
     bool have_dt = false;
-    const void *last_rec = nullptr;       // records of the last gradient pass
     struct Walls {      // mirror cells of reflective walls (caller's device lists)
         int64_t n = 0;
         const int32_t *ghost = nullptr, *src = nullptr;
@@ -220,7 +231,7 @@ mm_status mm_destroy(mm_ctx *ctx) {
 int64_t mm_workspace_bytes(const mm_ctx *ctx, int64_t n_cells, int64_t n_faces) {
     if (!ctx || n_cells < 2 || n_faces < 1 || n_faces >= (int64_t(1) << 30) || n_cells >= (int64_t(1) << 31) - 1)
         return -1;
-    return make_layout(ctx->D, ctx->p.mode, ctx->p.entropy != 0, ctx->p.steps != 0, n_cells, n_faces).total;
+    return make_layout(ctx->D, ctx->p.mode, ctx->p.entropy, ctx->p.steps != 0, n_cells, n_faces).total;
 }
 
 mm_status mm_set_workspace(mm_ctx *ctx, void *dev_ptr, int64_t bytes) {
@@ -232,7 +243,7 @@ mm_status mm_set_workspace(mm_ctx *ctx, void *dev_ptr, int64_t bytes) {
     ctx->diag_ready = false;
     // fixed-size regions (flags, diagnostics, network) sit at offsets that
     // no mesh changes
-    ctx->lay = make_layout(ctx->D, ctx->p.mode, ctx->p.entropy != 0, ctx->p.steps != 0, 2, 1);
+    ctx->lay = make_layout(ctx->D, ctx->p.mode, ctx->p.entropy, ctx->p.steps != 0, 2, 1);
     return MM_OK;
 }
 
@@ -250,7 +261,7 @@ static mm_status clear_diag(mm_ctx *c) {
 
 // Workspace present and its fixed regions initialised.
 static mm_status need_ws(mm_ctx *c) {
-    if (!c->ws || c->ws_bytes < make_layout(c->D, c->p.mode, c->p.entropy != 0, c->p.steps != 0, 2, 1).total) return MM_E_STATE;
+    if (!c->ws || c->ws_bytes < make_layout(c->D, c->p.mode, c->p.entropy, c->p.steps != 0, 2, 1).total) return MM_E_STATE;
     if (!c->diag_ready) return clear_diag(c);
     return MM_OK;
 }
@@ -279,16 +290,28 @@ template <int D> static void launch_validate(mm_ctx *c, const mm_mesh *m, int32_
                                                                         m->mesh_vel, flags);
 }
 
-template <int D> static void launch_records(mm_ctx *c, const mm_mesh *m, int32_t *flags) {
+// Face records and, in the mixed mode, the reference velocity W0 of the
+// gather records: everything that depends on the generator velocities.
+template <int D> static void launch_face_records(mm_ctx *c, const mm_mesh *m) {
     const Layout &L = c->lay;
     const int mixed = c->p.mode == MM_MIXED;
     k_face_records<D><<<plain_grid(m->n_faces), kBlock, 0, c->st()>>>(
         m->n_cells, m->n_faces, m->face_L, m->face_R, m->face_area, m->face_ctr, m->face_sep, m->mesh_vel,
         c->at<double>(L.frec), mixed, mixed ? c->at<float>(L.mrec) : nullptr, mixed ? c->at<double>(L.wf64) : nullptr);
+    if (mixed) {
+        const unsigned g = plain_grid(m->n_cells);
+        k_w0_part<D><<<g, kBlock, 0, c->st()>>>(m->n_cells, m->mesh_vel, c->at<double>(L.w0part));
+        k_w0_final<D><<<1, kBlock, 0, c->st()>>>(g, c->at<double>(L.w0part), c->at<double>(L.w0));
+    }
+}
+
+// Side records (geometry only) and the closure test.
+template <int D> static void launch_side_records(mm_ctx *c, const mm_mesh *m, int32_t *flags) {
+    const Layout &L = c->lay;
+    const int mixed = c->p.mode == MM_MIXED;
     k_side_records<D><<<plain_grid(m->n_cells), kBlock, 0, c->st()>>>(
-        m->n_cells, m->n_faces, c->at<int32_t>(L.off), c->at<int32_t>(L.ent), c->at<int32_t>(L.nbr), m->face_area,
-        m->face_ctr, m->face_sep, m->mesh_vel, mixed ? nullptr : c->at<double>(L.srec), mixed,
-        mixed ? c->at<float>(L.srec32) : nullptr, flags);
+        m->n_cells, m->n_faces, c->at<int32_t>(L.off), c->at<int32_t>(L.ent), m->face_area, m->face_ctr,
+        m->face_sep, mixed ? nullptr : c->at<double>(L.srec), mixed, mixed ? c->at<float>(L.srec32) : nullptr, flags);
 }
 
 mm_status mm_mesh_upload(mm_ctx *c, const mm_mesh *m) {
@@ -299,11 +322,10 @@ mm_status mm_mesh_upload(mm_ctx *c, const mm_mesh *m) {
     if (!m->volume || !m->centroid_off || !m->mesh_vel || !m->face_L || !m->face_R || !m->face_area ||
         !m->face_ctr || !m->face_sep)
         return MM_E_ARG;
-    Layout L = make_layout(c->D, c->p.mode, c->p.entropy != 0, c->p.steps != 0, n, nf);
+    Layout L = make_layout(c->D, c->p.mode, c->p.entropy, c->p.steps != 0, n, nf);
     if (L.total > c->ws_bytes) return MM_E_WORKSPACE;
     c->have_mesh = false;
     c->tb.on = false;
-    c->last_rec = nullptr;
     c->accel = nullptr;   // a field and walls belong to the mesh they were set for
     c->walls = mm_ctx::Walls();
     c->have_dt = false;
@@ -334,8 +356,25 @@ mm_status mm_mesh_upload(mm_ctx *c, const mm_mesh *m) {
     k_fill_sides<<<plain_grid(nf), kBlock, 0, s>>>(nf, m->face_L, m->face_R, cur, ent, nbr);
     k_sort_segments<<<plain_grid(n), kBlock, 0, s>>>(n, off, ent, nbr);
     MM_LAUNCH_CHECK();
-    if (c->D == 3) launch_records<3>(c, m, flags);
-    else launch_records<2>(c, m, flags);
+    // the update's left ranges and right-cell slots
+    int32_t *loff = c->at<int32_t>(L.loff), *roff = c->at<int32_t>(L.roff);
+    k_fill_i32<<<1, kBlock, 0, s>>>(loff, 1, 0);
+    k_fill_i32<<<1, kBlock, 0, s>>>(roff, 1, 0);
+    k_lr_count<<<plain_grid(n), kBlock, 0, s>>>(n, off, ent, loff + 1, roff + 1);
+    MM_LAUNCH_CHECK();
+    st = scan_inclusive(c, loff + 1, n, c->at<int32_t>(L.bsum));
+    if (st != MM_OK) return st;
+    st = scan_inclusive(c, roff + 1, n, c->at<int32_t>(L.bsum));
+    if (st != MM_OK) return st;
+    k_lr_fill<<<plain_grid(n), kBlock, 0, s>>>(n, off, ent, loff, roff, c->at<int32_t>(L.rface), flags);
+    MM_LAUNCH_CHECK();
+    if (c->D == 3) {
+        launch_face_records<3>(c, m);
+        launch_side_records<3>(c, m, flags);
+    } else {
+        launch_face_records<2>(c, m);
+        launch_side_records<2>(c, m, flags);
+    }
     MM_LAUNCH_CHECK();
     MM_CHECK(hipMemcpyAsync(&hflags, flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     MM_CHECK(hipStreamSynchronize(s));
@@ -357,11 +396,11 @@ mm_status mm_mesh_set_velocity(mm_ctx *c, const double *mesh_vel) {
     if (c->D == 3) {
         k_validate_cells<3><<<plain_grid(m->n_cells), kBlock, 0, s>>>(m->n_cells, m->volume, m->centroid_off,
                                                                       m->mesh_vel, flags);
-        launch_records<3>(c, m, flags);
+        launch_face_records<3>(c, m);
     } else {
         k_validate_cells<2><<<plain_grid(m->n_cells), kBlock, 0, s>>>(m->n_cells, m->volume, m->centroid_off,
                                                                       m->mesh_vel, flags);
-        launch_records<2>(c, m, flags);
+        launch_face_records<2>(c, m);
     }
     MM_LAUNCH_CHECK();
     int32_t hflags = 0;
@@ -379,19 +418,21 @@ template <int D, typename T> static T *grad_block(const mm_ctx *c, T *rec) { ret
 template <int D, typename T> static mm_status gradients_t(mm_ctx *c, const double *Q, T *rec, double *dt_part) {
     const Layout &L = c->lay;
     hipStream_t s = c->st();
-    const T *srec = sizeof(T) == 8 ? (const T *)c->at<double>(L.srec) : (const T *)c->at<float>(L.srec32);
+    const bool f64 = sizeof(T) == 8;
+    const T *srec = f64 ? (const T *)c->at<double>(L.srec) : (const T *)c->at<float>(L.srec32);
+    float *gath = f64 ? nullptr : c->at<float>(L.gath);
+    const double *w0 = f64 ? nullptr : c->at<double>(L.w0);
     k_prim_cfl<D, T><<<grid_for(c->n), kBlock, 0, s>>>(c->n, c->p.gamma, c->p.cfl, c->mesh.volume, Q,
-                                                      c->mesh.mesh_vel, c->mesh.centroid_off, rec, dt_part,
-                                                      c->at<int32_t>(L.flags) + 2);
+                                                      c->mesh.mesh_vel, c->mesh.centroid_off, rec, gath, w0,
+                                                      dt_part, c->at<int32_t>(L.flags) + 2);
     k_grad_limit<D, T><<<group_grid(D, c->n), kBlock, 0, s>>>(c->n, c->at<int32_t>(L.off), c->at<int32_t>(L.nbr),
-                                                              srec, c->mesh.volume, rec, grad_block<D>(c, rec));
+                                                              srec, c->mesh.volume, rec, gath, grad_block<D>(c, rec));
     MM_LAUNCH_CHECK();
     return MM_OK;
 }
 
 static mm_status gradients_into(mm_ctx *c, const double *Q, void *rec, double *dt_part) {
     const bool f64 = c->p.mode == MM_FP64;
-    c->last_rec = rec;   // the energy switch of the entropy scheme reads these records at the update
     if (c->D == 3)
         return f64 ? gradients_t<3, double>(c, Q, (double *)rec, dt_part) : gradients_t<3, float>(c, Q, (float *)rec, dt_part);
     return f64 ? gradients_t<2, double>(c, Q, (double *)rec, dt_part) : gradients_t<2, float>(c, Q, (float *)rec, dt_part);
@@ -404,7 +445,10 @@ mm_status mm_gradients(mm_ctx *c, const double *Q, void *recon) {
     return gradients_into(c, Q, recon, c->at<double>(c->lay.dtpart));
 }
 
-template <int D, bool ENT, bool GRAV>
+static FaceAux face_aux(const mm_ctx *c) { return FaceAux{c->accel, c->mesh.volume, c->mesh.mesh_vel, c->n}; }
+
+// The face fluxes in entropy mode EM, face-major records into flux.
+template <int D, int EM, bool GRAV>
 static mm_status fluxes_t(mm_ctx *c, const double *dt_dev, double dt, const void *rec, double *flux) {
     const Layout &L = c->lay;
     hipStream_t s = c->st();
@@ -412,30 +456,42 @@ static mm_status fluxes_t(mm_ctx *c, const double *dt_dev, double dt, const void
     const MlpPacked *mlp = active_mlp(c);
     const GasConst<double> kg(c->p.gamma);
     const GasConst<float> kf(c->p.gamma);
+    const FaceAux aux = face_aux(c);
     if (c->p.mode == MM_FP64) {
-        auto kern = mlp ? k_face_flux64<D, true, ENT, GRAV> : k_face_flux64<D, false, ENT, GRAV>;
+        auto kern = mlp ? k_face_flux64<D, true, EM, GRAV> : k_face_flux64<D, false, EM, GRAV>;
         const double *prim = (const double *)rec;
         kern<<<grid_for(c->nf), kBlock, 0, s>>>(c->nf, c->mesh.face_L, c->mesh.face_R, c->at<double>(L.frec), prim,
                                                 grad_block<D>(c, prim), dt_dev, dt, kg, c->p.newton_tol64,
-                                                c->p.newton_max_iter, mlp, flux, diag, c->accel, c->n);
+                                                c->p.newton_max_iter, mlp, flux, diag, aux);
     } else {
         int32_t *hard = c->at<int32_t>(L.hard);
         const int64_t cap = list_cap(grid_for(c->nf));
         k_fill_i32<<<kLists * kListPad / kBlock, kBlock, 0, s>>>(hard, kLists * kListPad, 0);
-        auto kern = mlp ? k_face_flux_mixed<D, true, ENT, GRAV> : k_face_flux_mixed<D, false, ENT, GRAV>;
+        auto kern = mlp ? k_face_flux_mixed<D, true, EM, GRAV> : k_face_flux_mixed<D, false, EM, GRAV>;
         const float *prim = (const float *)rec;
         kern<<<grid_for(c->nf), kBlock, 0, s>>>(c->nf, c->mesh.face_L, c->mesh.face_R, c->at<float>(L.mrec),
                                                 c->at<double>(L.wf64), prim, grad_block<D>(c, prim), dt_dev, dt, kf,
                                                 kg.g_over_gm1, (float)c->p.newton_tol32, c->p.newton_max_iter, mlp,
-                                                flux, hard, cap, diag, c->accel, c->n);
-        k_face_flux_hard<D, ENT, GRAV><<<kHardGrid, kBlock, 0, s>>>(c->mesh.face_L, c->mesh.face_R, c->at<float>(L.mrec),
-                                                        c->at<double>(L.wf64), prim, grad_block<D>(c, prim), dt_dev,
-                                                        dt, kf.g,
-                                                        kg, c->p.newton_tol64, hard, cap, flux, diag, c->accel,
-                                                        c->n, TbView{});
+                                                flux, hard, cap, diag, aux);
+        k_face_flux_hard<D, EM, GRAV><<<kHardGrid, kBlock, 0, s>>>(
+            c->mesh.face_L, c->mesh.face_R, c->at<float>(L.mrec), c->at<double>(L.wf64), prim, grad_block<D>(c, prim),
+            dt_dev, dt, kf.g, kg, c->p.newton_tol64, hard, cap, flux, diag, aux, TbView{});
     }
     MM_LAUNCH_CHECK();
     return MM_OK;
+}
+
+template <int D>
+static mm_status fluxes_d(mm_ctx *c, const double *dt_dev, double dt, const void *rec, double *flux) {
+    const bool g = c->accel != nullptr;
+    switch (c->p.entropy) {
+        case MM_ENTROPY_MACH:
+            return g ? fluxes_t<D, 1, true>(c, dt_dev, dt, rec, flux) : fluxes_t<D, 1, false>(c, dt_dev, dt, rec, flux);
+        case MM_ENTROPY_ENERGY:
+            return g ? fluxes_t<D, 2, true>(c, dt_dev, dt, rec, flux) : fluxes_t<D, 2, false>(c, dt_dev, dt, rec, flux);
+        default:
+            return g ? fluxes_t<D, 0, true>(c, dt_dev, dt, rec, flux) : fluxes_t<D, 0, false>(c, dt_dev, dt, rec, flux);
+    }
 }
 
 static mm_status fluxes_into(mm_ctx *c, const double *dt_dev, double dt, const void *rec, double *flux) {
@@ -444,13 +500,7 @@ static mm_status fluxes_into(mm_ctx *c, const double *dt_dev, double dt, const v
     c->last_dt_dev = dt_dev;
     c->last_dt = dt;
     c->have_dt = true;
-    const bool e = c->p.entropy != 0, g = c->accel != nullptr;
-    if (c->D == 3) {
-        if (e) return g ? fluxes_t<3, true, true>(c, dt_dev, dt, rec, flux) : fluxes_t<3, true, false>(c, dt_dev, dt, rec, flux);
-        return g ? fluxes_t<3, false, true>(c, dt_dev, dt, rec, flux) : fluxes_t<3, false, false>(c, dt_dev, dt, rec, flux);
-    }
-    if (e) return g ? fluxes_t<2, true, true>(c, dt_dev, dt, rec, flux) : fluxes_t<2, true, false>(c, dt_dev, dt, rec, flux);
-    return g ? fluxes_t<2, false, true>(c, dt_dev, dt, rec, flux) : fluxes_t<2, false, false>(c, dt_dev, dt, rec, flux);
+    return c->D == 3 ? fluxes_d<3>(c, dt_dev, dt, rec, flux) : fluxes_d<2>(c, dt_dev, dt, rec, flux);
 }
 
 mm_status mm_face_fluxes(mm_ctx *c, double dt, const void *recon, double *face_flux) {
@@ -460,27 +510,31 @@ mm_status mm_face_fluxes(mm_ctx *c, double dt, const void *recon, double *face_f
     return fluxes_into(c, nullptr, dt, recon, face_flux);
 }
 
-template <int D, bool ENT, bool GRAV, bool ESW = false>
-static void launch_update(mm_ctx *c, const double *flux, double *Q) {
+static UpdateArgs update_args(const mm_ctx *c) {
     const Layout &L = c->lay;
-    const bool mixed = c->p.mode == MM_MIXED;
-    EnergySwitch es{c->p.alpha_s, c->p.beta_s, c->last_rec, mixed ? 1 : 0, 0, c->at<int32_t>(L.nbr),
-                    c->mesh.mesh_vel, mixed ? c->at<float>(L.srec32) : nullptr};
-    k_update<D, ENT, GRAV, ESW><<<group_grid(D, c->n), kBlock, 0, c->st()>>>(
-        c->n, c->at<int32_t>(L.off), c->at<int32_t>(L.ent), flux, Q, c->at<int32_t>(L.flags) + 1, c->mesh.volume,
-        c->p.gamma, c->p.mach_thresh, c->at<DiagDev>(L.diag), c->accel, c->last_dt_dev, c->last_dt, es);
+    return UpdateArgs{c->at<int32_t>(L.flags) + 1, c->mesh.volume, c->p.gamma, c->p.mach_thresh,
+                      c->at<DiagDev>(L.diag), c->accel, c->last_dt_dev, c->last_dt, c->p.alpha_s, c->p.beta_s,
+                      c->mesh.mesh_vel};
+}
+
+// The update from face-major records.
+template <int D, int EM, bool GRAV> static void launch_update(mm_ctx *c, const double *flux, double *Q) {
+    const Layout &L = c->lay;
+    k_update<D, EM, GRAV><<<group_grid(D, c->n), kBlock, 0, c->st()>>>(
+        c->n, c->at<int32_t>(L.loff), c->at<int32_t>(L.roff), c->at<int32_t>(L.rface), flux, Q, update_args(c));
 }
 
 template <int D> static void launch_update_d(mm_ctx *c, const double *flux, double *Q) {
-    const bool e = c->p.entropy != 0, g = c->accel != nullptr, w = c->p.entropy == MM_ENTROPY_ENERGY;
-    if (w) g ? launch_update<D, true, true, true>(c, flux, Q) : launch_update<D, true, false, true>(c, flux, Q);
-    else if (e) g ? launch_update<D, true, true>(c, flux, Q) : launch_update<D, true, false>(c, flux, Q);
-    else g ? launch_update<D, false, true>(c, flux, Q) : launch_update<D, false, false>(c, flux, Q);
+    const bool g = c->accel != nullptr;
+    switch (c->p.entropy) {
+        case MM_ENTROPY_MACH: g ? launch_update<D, 1, true>(c, flux, Q) : launch_update<D, 1, false>(c, flux, Q); break;
+        case MM_ENTROPY_ENERGY: g ? launch_update<D, 2, true>(c, flux, Q) : launch_update<D, 2, false>(c, flux, Q); break;
+        default: g ? launch_update<D, 0, true>(c, flux, Q) : launch_update<D, 0, false>(c, flux, Q);
+    }
 }
 
 static mm_status update_into(mm_ctx *c, const double *flux, double *Q) {
     if (c->accel && !c->have_dt) return MM_E_STATE;   // the source terms need the flux pass's timestep
-    if (c->p.entropy == MM_ENTROPY_ENERGY && !c->last_rec) return MM_E_STATE;   // no records for the switch
     if (c->D == 3) launch_update_d<3>(c, flux, Q);
     else launch_update_d<2>(c, flux, Q);
     MM_LAUNCH_CHECK();
@@ -832,11 +886,14 @@ template <int D, typename T> static void tb_point(mm_ctx *c, double *Q, T *rec) 
     T *grad = grad_block<D>(c, rec);
     int32_t *hard = mixed ? c->at<int32_t>(L.hard) : nullptr;
     const int32_t *off = c->at<int32_t>(L.off), *ent = c->at<int32_t>(L.ent), *nbr = c->at<int32_t>(L.nbr);
+    float *gath = mixed ? c->at<float>(L.gath) : nullptr;
+    const double *w0 = mixed ? c->at<double>(L.w0) : nullptr;
     k_tb_open<D, T><<<grid_for(c->n), kBlock, 0, s>>>(c->n, info, bin, trec, c->p.gamma, c->mesh.volume, Q,
-                                                      c->mesh.mesh_vel, c->mesh.centroid_off, rec, sig, cells, ccap);
+                                                      c->mesh.mesh_vel, c->mesh.centroid_off, rec, gath, w0, sig,
+                                                      cells, ccap);
     k_tb_active<D, T><<<kTbGrid, kBlock, 0, s>>>(cells, ccap, tb.dt_max, tb.levels, c->p.cfl, off, ent, nbr,
                                                  c->at<double>(L.frec), sig, bin, info, srec, c->mesh.volume, rec,
-                                                 grad, touch, faces, fcap, touched, tcap);
+                                                 gath, grad, touch, faces, fcap, touched, tcap);
     k_tb_faces<<<kTbGrid, kBlock, 0, s>>>(c->nf, c->mesh.face_L, c->mesh.face_R, bin, info, touch, faces, fcap);
     const TbView view{bin, trec, 0, tb.dt_max, tb.levels, info};
     DiagDev *diag = c->at<DiagDev>(L.diag);
@@ -855,13 +912,15 @@ template <int D, typename T> static void tb_point(mm_ctx *c, double *Q, T *rec) 
                                         c->at<double>(L.wf64), (const float *)rec, (const float *)grad, view, kf,
                                         kg.g_over_gm1, (float)c->p.newton_tol32, c->p.newton_max_iter, mlp, flux,
                                         hard, diag);
-        k_face_flux_hard<D, false, false><<<kTbGrid, kBlock, 0, s>>>(
+        k_face_flux_hard<D, 0, false><<<kTbGrid, kBlock, 0, s>>>(
             c->mesh.face_L, c->mesh.face_R, c->at<float>(L.mrec), c->at<double>(L.wf64), (const float *)rec,
-            (const float *)grad, nullptr, 0.0, kf.g, kg, c->p.newton_tol64, hard, fcap, flux, diag, nullptr, c->n,
-            view);
+            (const float *)grad, nullptr, 0.0, kf.g, kg, c->p.newton_tol64, hard, fcap, flux, diag,
+            FaceAux{nullptr, nullptr, nullptr, c->n}, view);
     }
-    k_tb_update_list<D><<<kTbGrid, kBlock, 0, s>>>(touched, tcap, c->n, off, ent, nbr, bin, flux, Q, flags + 1, info);
-    k_tb_update<D><<<kTbGrid, kBlock, 0, s>>>(c->n, off, ent, nbr, bin, info, touch, flux, Q, flags + 1);
+    const TbSides sd{c->at<int32_t>(L.loff), c->at<int32_t>(L.roff), c->at<int32_t>(L.rface), c->mesh.face_L,
+                     c->mesh.face_R};
+    k_tb_update_list<D><<<kTbGrid, kBlock, 0, s>>>(touched, tcap, c->n, sd, bin, flux, Q, flags + 1, info);
+    k_tb_update<D><<<kTbGrid, kBlock, 0, s>>>(c->n, sd, bin, info, touch, flux, Q, flags + 1);
     k_tb_finish<<<1, kBlock, 0, s>>>(c->n, tb.levels, tb.sparse_ok ? 1 : 0, cells, faces, touched, hard, flags + 2,
                                      info);
 }
