@@ -362,6 +362,31 @@ mm_status mm_mlp_adam(float *params, const float *grad, float *m1, float *m2, fl
  * workspace, not a mesh. */
 mm_status mm_riemann_batch(mm_ctx *ctx, int64_t n, const double *states, double *out, int32_t *iters);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * batch as mm_riemann_batch without a context or workspace. params gives
+ * mode, guess, gamma, Newton tolerances, iteration limit and stream (the
+ * stream must belong to the current device; dim, cfl and the entropy and
+ * timestep fields are ignored). The call's scratch -- the hard-problem
+ * list of the float form and the packed network of the learned guess -- is
+ * a fixed array of MM_NOALLOC_SCRATCH_BYTES in device memory, one per GPU,
+ * held from the library's first call on that GPU until the process ends;
+ * problems go through it in chunks of MM_NOALLOC_CHUNK, so any
+ * n <= MM_NOALLOC_MAX_BATCH fits. The call allocates nothing (no hipMalloc,
+ * hipFree or allocating library routine); mlp_params (device float
+ * [MM_MLP_PARAMS], required with MM_GUESS_LEARNED, else ignored) is packed
+ * into the scratch on every call. Results equal mm_riemann_batch's for the
+ * same params bit for bit; no diagnostics are counted. Calls that overlap
+ * on one GPU (other streams, other threads) share the one scratch and
+ * race: the caller orders them. MM_E_ARG for n < 1, n > MM_NOALLOC_MAX_BATCH,
+ * null pointers or invalid params; MM_E_DEVICE if the scratch cannot be
+ * found on the current device. */
+#define MM_NOALLOC_CHUNK ((int64_t)1 << 20)
+#define MM_NOALLOC_MAX_BATCH ((int64_t)1 << 32)
+#define MM_NOALLOC_SCRATCH_BYTES ((int64_t)4243456) /* 4.05 MiB */
+mm_status mm_riemann_batch_noalloc(const mm_params *params, int64_t n, const double *states, double *out,
+                                   int32_t *iters, const float *mlp_params);
+
 /* The face-frame Riemann inputs of every face of the uploaded mesh for a
  * step dt > 0 from double reconstruction records (MM_FP64 contexts only):
  * out [6][F] float = (rho_L, u_L, P_L, rho_R, u_R, P_R) after extrapolation,

@@ -15,6 +15,7 @@
 
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "../../include/mm.h"
@@ -757,6 +758,82 @@ mm_status mm_riemann_batch(mm_ctx *c, int64_t n, const double *states, double *o
                                                          iters, hard, cap, diag);
             k_riemann_hard<<<kHardGrid, kBlock, 0, c->st()>>>(n, i0, states, kg, c->p.newton_tol64, hard, cap, out,
                                                               iters, diag);
+        }
+    }
+    MM_LAUNCH_CHECK();
+    return MM_OK;
+}
+
+// ------------------------------------------------------------------------
+// The batch without a context (mm_riemann_batch_noalloc): its scratch is a
+// fixed array in device memory, one copy per GPU. Host code never passes the
+// array's name to a kernel or a copy (in host code it names a host-side
+// stand-in); it uses the device address that hipGetSymbolAddress returns for
+// the current device, looked up once per device and kept.
+namespace {
+
+constexpr int64_t kNoAllocHardInts = (int64_t)kLists * kListPad + (int64_t)kLists * ((MM_NOALLOC_CHUNK / kBlock + kLists - 1) / kLists * kBlock);
+constexpr int64_t kNoAllocMlpOff = (kNoAllocHardInts * 4 + 255) / 256 * 256;   // bytes
+static_assert(kNoAllocMlpOff + (int64_t)sizeof(MlpPacked) <= MM_NOALLOC_SCRATCH_BYTES, "scratch too small");
+static_assert(MM_NOALLOC_SCRATCH_BYTES % 4 == 0, "scratch of whole words");
+
+__device__ __align__(256) int32_t scratch[MM_NOALLOC_SCRATCH_BYTES / 4];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// The scratch's device address on the current device (nullptr on failure).
+void *scratch_on_current_device() {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+mm_status mm_riemann_batch_noalloc(const mm_params *params, int64_t n, const double *states, double *out,
+                                   int32_t *iters, const float *mlp_params) {
+    if (!params || !states || !out || n < 1 || n > MM_NOALLOC_MAX_BATCH) return MM_E_ARG;
+    if (params->mode != MM_FP64 && params->mode != MM_MIXED) return MM_E_ARG;
+    if (params->guess != MM_GUESS_STANDARD && params->guess != MM_GUESS_LEARNED) return MM_E_ARG;
+    if (params->guess == MM_GUESS_LEARNED && !mlp_params) return MM_E_ARG;
+    if (!(params->gamma > 1.0) || !isfinite(params->gamma)) return MM_E_ARG;
+    // the context's defaults for unset solver parameters (mm_create)
+    const int maxit = params->newton_max_iter > 0 ? params->newton_max_iter : 50;
+    const double tol64 = params->newton_tol64 > 0.0 ? params->newton_tol64 : 1e-10;
+    const double tol32 = params->newton_tol32 > 0.0 ? params->newton_tol32 : 1e-5;
+    char *sp = (char *)scratch_on_current_device();
+    if (!sp) return MM_E_DEVICE;
+    hipStream_t s = (hipStream_t)params->stream;
+    int32_t *hard = (int32_t *)sp;
+    MlpPacked *mlp = nullptr;
+    if (params->guess == MM_GUESS_LEARNED) {
+        mlp = (MlpPacked *)(sp + kNoAllocMlpOff);
+        k_mlp_pack<<<1, kBlock, 0, s>>>(mlp_params, mlp);
+    }
+    const GasConst<double> kg(params->gamma);
+    for (int64_t i0 = 0; i0 < n; i0 += MM_NOALLOC_CHUNK) {
+        const int64_t nc = n - i0 < MM_NOALLOC_CHUNK ? n - i0 : MM_NOALLOC_CHUNK;
+        if (params->mode == MM_FP64) {
+            auto kern = mlp ? k_riemann_batch<double, true> : k_riemann_batch<double, false>;
+            kern<<<plain_grid(nc), kBlock, 0, s>>>(n, i0, nc, states, kg, tol64, maxit, mlp, out, iters, nullptr, 0,
+                                                   nullptr);
+        } else {
+            const int64_t cap = list_cap(plain_grid(nc));
+            // the list counters start at zero for every chunk (a fill kernel,
+            // so that the call can be captured)
+            k_fill_i32<<<kLists * kListPad / kBlock, kBlock, 0, s>>>(hard, kLists * kListPad, 0);
+            auto kern = mlp ? k_riemann_batch<float, true> : k_riemann_batch<float, false>;
+            kern<<<plain_grid(nc), kBlock, 0, s>>>(n, i0, nc, states, GasConst<float>(params->gamma), (float)tol32,
+                                                   maxit, mlp, out, iters, hard, cap, nullptr);
+            k_riemann_hard<<<kHardGrid, kBlock, 0, s>>>(n, i0, states, kg, tol64, hard, cap, out, iters, nullptr);
         }
     }
     MM_LAUNCH_CHECK();

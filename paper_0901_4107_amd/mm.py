@@ -86,6 +86,7 @@ SIGNATURES = {
     "mm_mlp_adam": (ctypes.c_int32, [_vp, _vp, _vp, _vp, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                      ctypes.c_float, ctypes.c_int32, _vp]),
     "mm_riemann_batch": (ctypes.c_int32, [_vp, ctypes.c_int64, _vp, _vp, _vp]),
+    "mm_riemann_batch_noalloc": (ctypes.c_int32, [ctypes.POINTER(mm_params), ctypes.c_int64, _vp, _vp, _vp, _vp]),
     "mm_face_states": (ctypes.c_int32, [_vp, ctypes.c_double, _vp, _vp]),
     "mm_entropy_init": (ctypes.c_int32, [_vp, _vp]),
     "mm_mesh_velocity": (ctypes.c_int32, [_vp, _vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, _vp]),
@@ -448,6 +449,32 @@ def mm_mlp_adam(params, grad, m1, m2, lr, beta1, beta2, eps, step, stream=None):
         _need(t, f"mm_mlp_adam: {name}", torch.float32, MM_MLP_PARAMS)
     _check("mm_mlp_adam", lib().mm_mlp_adam(_ptr(params), _ptr(grad), _ptr(m1), _ptr(m2), lr, beta1, beta2, eps,
                                             step, _stream_ptr(stream)))
+
+MM_NOALLOC_CHUNK = 1 << 20
+MM_NOALLOC_MAX_BATCH = 1 << 32
+
+
+def mm_riemann_batch_noalloc(states: torch.Tensor, out: torch.Tensor, iters: torch.Tensor | None = None,
+                             gamma: float = 5.0 / 3.0, mode: int = MM_FP64, guess: int = MM_GUESS_STANDARD,
+                             mlp_params: torch.Tensor | None = None, newton_max_iter: int = 0,
+                             newton_tol64: float = 0.0, newton_tol32: float = 0.0, stream=None):
+    """The batch of mm_riemann_batch without a context or workspace: the
+    library's fixed per-GPU scratch serves instead, and nothing is
+    allocated. states [6][n] double -> out [n][5] double, iters [n] int32
+    (optional); mlp_params (float [MM_MLP_PARAMS]) with the learned guess."""
+    if states.dim() != 2 or states.shape[0] != 6:
+        raise ValueError("mm_riemann_batch_noalloc: states must be [6][n]")
+    n = states.shape[1]
+    _need(states, "mm_riemann_batch_noalloc: states", torch.float64, 6 * n)
+    _need(out, "mm_riemann_batch_noalloc: out", torch.float64, 5 * n)
+    _need(iters, "mm_riemann_batch_noalloc: iters", torch.int32, n, optional=True)
+    _need(mlp_params, "mm_riemann_batch_noalloc: mlp_params", torch.float32, MM_MLP_PARAMS,
+          optional=guess != MM_GUESS_LEARNED)
+    p = mm_params(3, mode, guess, newton_max_iter, gamma, 0.4, newton_tol64, newton_tol32, _stream_ptr(stream),
+                  MM_ENTROPY_OFF, MM_STEPS_GLOBAL, 1.1, 0.0, 0.0)
+    _check("mm_riemann_batch_noalloc", lib().mm_riemann_batch_noalloc(ctypes.byref(p), n, _ptr(states), _ptr(out),
+                                                                      _ptr(iters), _ptr(mlp_params)))
+
 
 def flux_stride(dim: int, entropy: int = MM_ENTROPY_OFF) -> int:
     """MM_FLUX_STRIDE: doubles per face record of the face-flux array."""
