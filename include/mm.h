@@ -84,8 +84,10 @@ typedef int32_t mm_status;
  * (states at the start of the step, in the frame of the cell's generator),
  * or, with a static field (mm_set_gravity), below beta_s M |g_i| R_i, R_i
  * the radius of the cell's volume. A parameter <= 0 switches its condition
- * off. The face pass records each face's two neighbour energies
- * (MM_FLUX_STRIDE); the cell's own comes from Q at the start of the update. */
+ * off. The gradient pass (mm_gradients, or the step's own) records each
+ * cell's largest neighbour energy in the workspace, from the states it
+ * takes the gradients of; mm_apply_update returns MM_E_STATE before any
+ * gradient pass. The cell's own energy comes from Q at the update. */
 #define MM_ENTROPY_ENERGY 2
 
 /* Timestep scheme (Section 7.2). MM_STEPS_INDIVIDUAL adds the arrays of a
@@ -124,11 +126,8 @@ typedef struct {
  * the face's Mach number: the larger over its sides of
  * sqrt((g+1)/(2g) p* / p_K + (g-1)/(2g)), the Mach number of the shock into
  * side K where p* > p_K and below 1 on a rarefied side; 0 without a star
- * state. With MM_ENTROPY_ENERGY two more: the kinetic energies
- * M_R |v_R - w_L|^2 / 2 and M_L |v_L - w_R|^2 / 2 of each side in the other
- * side's generator frame (start-of-step states, M_K = rho_K V_K), what the
- * update's energy switch needs of the face. */
-#define MM_FLUX_STRIDE(dim, entropy) ((dim) + 2 + ((entropy) ? 2 : 0) + ((entropy) == MM_ENTROPY_ENERGY ? 2 : 0))
+ * state. */
+#define MM_FLUX_STRIDE(dim, entropy) ((dim) + 2 + ((entropy) ? 2 : 0))
 
 /* The given tessellation (Section 3, step list item (i)) and the generator
  * velocities w_i (item (iv)). All device pointers, all kept by reference

@@ -284,15 +284,61 @@ __device__ __forceinline__ void limit_side(const T *g, const T *dl, const T (&gr
     }
 }
 
+// The energy switch's neighbour term (Section 3.5, eq. eqnScrit1): the
+// kinetic energy of neighbour j in the frame of cell i's generator,
+// M_j |v_j - w_i|^2 / 2 with M_j = rho_j V_j (0 for a vacuum neighbour), from
+// j's values pj as the gradient pass reads them: double primitive records
+// hold v_j (wi = w_i); float gather records hold v_j - w_j and w_j - W0
+// (wi: cell i's w_i - W0), so v_j - w_i = (v_j - w_j) + [(w_j - W0) - (w_i - W0)].
+template <int D, typename T>
+__device__ __forceinline__ double ekin_in_frame(const T *pj, const T *wi, double Vj, const double (&wlab)[D]) {
+    double e = 0.0;
+    for (int k = 0; k < D; k++) {
+        const double dv = sizeof(T) == 4
+                              ? (double)pj[1 + k] + ((double)pj[Lay<D>::GW + k] - (double)wi[Lay<D>::GW + k])
+                              : (double)pj[1 + k] - wlab[k];
+        e += dv * dv;
+    }
+    return pj[0] > (T)0 ? 0.5 * ((double)pj[0] * Vj) * e : 0.0;
+}
+
 // The gradient and limiter of cell i by its lane group (lane = index in
 // the group); every lane of the group calls it with the same i. gath: the
 // gather records (mixed mode; unused in double, where the neighbours'
-// primitive records serve).
+// primitive records serve). With ESW, also the energy switch's largest
+// neighbour kinetic energy in the frame of the cell's generator, into
+// ekmax[i] (the states are the step's start states, those the gradient is
+// taken from; mvel the generator velocities). win: the block's window of
+// gather records, starting at cell c0 (null: every record from HBM).
+// The gradient kernel's window (mixed mode): the gather records of the kGWin
+// cells centred on its block's 64 cells, staged in LDS once per block. Cells
+// are in Morton order, so most neighbours of a block's cells fall inside it
+// (about 60% on a Poisson mesh); the rest are gathered from HBM.
+constexpr int kGWin = 128;
+// The record of neighbour j: from the window when it holds j, else from the
+// records nrec of stride NSs.
 template <int D, typename T>
+__device__ __forceinline__ void load_nb(const T *__restrict__ nrec, int64_t j, int NSs, const float *win, int64_t c0,
+                                        T (&o)[sizeof(T) == 4 ? Lay<D>::GATH : D + 2]) {
+    constexpr int NJ = sizeof(T) == 4 ? Lay<D>::GATH : D + 2;
+    if constexpr (sizeof(T) == 4) {
+        const int64_t k = j - c0;
+        if (win && k >= 0 && k < kGWin) {
+            load_rec<NJ>((const T *)win + k * NJ, o);
+            return;
+        }
+    }
+    load_rec<NJ>(nrec + j * NSs, o);
+}
+
+template <int D, typename T, bool ESW = false>
 __device__ __forceinline__ void grad_cell(int64_t i, int lane, const int32_t *__restrict__ off,
                                           const int32_t *__restrict__ nbr, const T *__restrict__ srec,
                                           const double *__restrict__ V, const T *__restrict__ prim,
-                                          const float *__restrict__ gath, T *__restrict__ grad_out) {
+                                          const float *__restrict__ gath, T *__restrict__ grad_out,
+                                          const double *__restrict__ mvel = nullptr, int64_t n = 0,
+                                          double *__restrict__ ekmax = nullptr, const float *win = nullptr,
+                                          int64_t c0 = 0) {
     using Y = Lay<D>;
     constexpr int NV = D + 2;
     constexpr int GS = Group<D>::GS;
@@ -314,11 +360,11 @@ __device__ __forceinline__ void grad_cell(int64_t i, int lane, const int32_t *__
         has[r] = q < e;
         const int32_t qq = has[r] ? q : 0;
         load_rec<SR>(srec + (int64_t)qq * SR, sr[r]);
-        load_rec<NJ>(nrec + (int64_t)nbr[qq] * NS, pj[r]);
+        load_nb<D, T>(nrec, nbr[qq], NS, win, c0, pj[r]);
     }
     T pi[Y::PREC], wi[NJ];
     load_rec<Y::PREC>(prim + i * Y::PREC, pi);
-    load_rec<NJ>(nrec + i * NS, wi);
+    load_nb<D, T>(nrec, i, NS, win, c0, wi);
     const T *dl = pi + Y::DL;
     SideAcc<D, T> a;
     for (int c = 0; c < NV; c++) {
@@ -326,13 +372,25 @@ __device__ __forceinline__ void grad_cell(int64_t i, int lane, const int32_t *__
         a.dmn[c] = (T)0;
         for (int k = 0; k < D; k++) a.acc[c][k] = (T)0;
     }
+    double wlab[D], ek = 0.0;
+    if constexpr (ESW)
+        for (int k = 0; k < D; k++) wlab[k] = mixed ? 0.0 : mvel[k * n + i];
     for (int r = 0; r < KR; r++)
-        if (has[r]) grad_side<D, T, mixed>(sr[r], pj[r], wi, a);
+        if (has[r]) {
+            grad_side<D, T, mixed>(sr[r], pj[r], wi, a);
+            if constexpr (ESW) ek = fmax(ek, ekin_in_frame<D, T>(pj[r], wi, V[nbr[b + lane + r * GS]], wlab));
+        }
     for (int32_t q = b + lane + KR * GS; q < e; q += GS) {
         T s2[SR], p2[NJ];
         load_rec<SR>(srec + (int64_t)q * SR, s2);
-        load_rec<NJ>(nrec + (int64_t)nbr[q] * NS, p2);
+        const int32_t j = nbr[q];
+        load_nb<D, T>(nrec, j, NS, win, c0, p2);
         grad_side<D, T, mixed>(s2, p2, wi, a);
+        if constexpr (ESW) ek = fmax(ek, ekin_in_frame<D, T>(p2, wi, V[j], wlab));
+    }
+    if constexpr (ESW) {
+        ek = grp_max<GS>(ek);
+        if (lane == 0) ekmax[i] = ek;
     }
     const T inv_v = (T)(1.0 / V[i]);
     T grad[NV][D], dmx[NV], dmn[NV];
@@ -376,16 +434,34 @@ __device__ __forceinline__ void grad_cell(int64_t i, int lane, const int32_t *__
 
 // The gather-bound gradient kernels gain from one more wavefront per SIMD
 // than the register count the compiler picks on its own (5 float / 4 double,
-// about 7-9% faster; the 3D double kernel spills a few bytes per lane).
-template <int D, typename T>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 4)))
+// about 7-9% faster; the 3D double kernel spills a few bytes per lane); with
+// the energy switch's neighbour energies one fewer (4 float, 3 double),
+// where they do not spill.
+template <int D, typename T, bool ESW>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? (ESW ? 4 : 5) : (ESW ? 3 : 4))))
 k_grad_limit(int64_t n, const int32_t *__restrict__ off, const int32_t *__restrict__ nbr, const T *__restrict__ srec,
              const double *__restrict__ V, const T *__restrict__ prim, const float *__restrict__ gath,
-             T *__restrict__ grad_out) {
+             T *__restrict__ grad_out, const double *__restrict__ mvel, double *__restrict__ ekmax) {
     constexpr int GS = Group<D>::GS;
     const int64_t i = xcd_tile() * (kBlock / GS) + threadIdx.x / GS;
+    // mixed mode: stage the window (every lane takes part in the copy and the
+    // barrier before any group leaves)
+    const float *win = nullptr;
+    int64_t c0 = 0;
+    if constexpr (sizeof(T) == 4) {
+        __shared__ float wbuf[kGWin * Lay<D>::GATH];
+        c0 = xcd_tile() * (kBlock / GS) - (kGWin - kBlock / GS) / 2;
+        for (int e = threadIdx.x; e < kGWin * Lay<D>::GATH / 4; e += kBlock) {
+            const int64_t j = c0 + e / (Lay<D>::GATH / 4);
+            f32x4u v = {0.0f, 0.0f, 0.0f, 0.0f};
+            if (j >= 0 && j < n) v = *reinterpret_cast<const f32x4u *>(gath + j * Lay<D>::GATH + (e % (Lay<D>::GATH / 4)) * 4);
+            *reinterpret_cast<f32x4u *>(wbuf + e * 4) = v;
+        }
+        __syncthreads();
+        win = wbuf;
+    }
     if (i >= n) return;  // whole groups leave together
-    grad_cell<D, T>(i, threadIdx.x % GS, off, nbr, srec, V, prim, gath, grad_out);
+    grad_cell<D, T, ESW>(i, threadIdx.x % GS, off, nbr, srec, V, prim, gath, grad_out, mvel, n, ekmax, win, c0);
 }
 
 // The total entropy of every cell from its conserved state (Section 3.5):

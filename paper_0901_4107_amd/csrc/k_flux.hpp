@@ -117,6 +117,54 @@ __device__ __forceinline__ CellRec<D, T> load_cell(const T *__restrict__ prim, c
     return c;
 }
 
+// A window of cell records staged in LDS by the block: cells
+// [c0, c0 + kWin), PREC + GREC floats each, c0 the left cell of the block's
+// first face. Faces are sorted by left cell and cells run along a
+// space-filling curve, so the window holds every left cell of the block's
+// faces and about two thirds of their right cells (on Poisson meshes);
+// those records come from LDS, the rest from memory.
+constexpr int kWin = 128;
+struct Window {
+    const float *buf;
+    int64_t c0;
+};
+
+template <int D>
+__device__ __forceinline__ CellRec<D, float> load_cell_w(const float *__restrict__ prim, const float *__restrict__ grad,
+                                                         int64_t i, const Window &w) {
+    constexpr int RF = Lay<D>::PREC + Lay<D>::GREC;
+    const int64_t k = i - w.c0;
+    if (w.buf && k >= 0 && k < kWin) {
+        CellRec<D, float> c;
+        const float *r = w.buf + k * RF;
+        load_rec<Lay<D>::PREC>(r, c.p);
+        load_rec<Lay<D>::GREC>(r + Lay<D>::PREC, c.g);
+        return c;
+    }
+    return load_cell<D>(prim, grad, i);
+}
+
+// Every thread of the block calls it (it holds a barrier); f0 the block's
+// first face, n the number of cells.
+template <int D>
+__device__ __forceinline__ Window stage_window(float *buf, int64_t f0, int64_t nf, const int32_t *__restrict__ fL,
+                                               const float *__restrict__ prim, const float *__restrict__ grad,
+                                               int64_t n) {
+    constexpr int RF = Lay<D>::PREC + Lay<D>::GREC, P4 = Lay<D>::PREC / 4;
+    const int64_t c0 = f0 < nf ? fL[f0] : 0;
+    for (int e = threadIdx.x; e < kWin * RF / 4; e += kBlock) {
+        const int cell = e / (RF / 4), part = e % (RF / 4);
+        const int64_t j = c0 + cell;
+        f32x4u v = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (j < n)
+            v = part < P4 ? *reinterpret_cast<const f32x4u *>(prim + j * Lay<D>::PREC + part * 4)
+                          : *reinterpret_cast<const f32x4u *>(grad + j * Lay<D>::GREC + (part - P4) * 4);
+        *reinterpret_cast<f32x4u *>(buf + cell * RF + part * 4) = v;
+    }
+    __syncthreads();
+    return Window{buf, c0};
+}
+
 template <int D, typename T>
 __device__ __forceinline__ void half_step(const CellRec<D, T> &r, const T *vface, const T *gfr, T gamma, T hdt,
                                           T out[D + 2], T cen[D + 2]) {
@@ -314,6 +362,38 @@ __device__ __forceinline__ T learned_guess(const MlpPacked *P, bool want, T rhoL
     return corr;
 }
 
+// The learned guess for the problems of one wavefront, with no barrier and
+// no LDS (every lane of the wavefront calls it, full exec mask): the lanes
+// that want the network are packed to the front by lane reads, the network
+// runs over ceil(count / 32) passes of 32 columns, and each result is read
+// back by its lane. The other wavefronts of the block run on meanwhile.
+// NaN for lanes with want = false.
+template <typename T>
+__device__ __forceinline__ T learned_guess_wave(const MlpPacked *P, bool want, T rhoL, T uL, T PL, T rhoR, T uR,
+                                                T PR, float gamma) {
+    const unsigned long long m = __ballot(want);
+    if (P == nullptr || m == 0ull) return no_guess<T>();   // the same for the whole wavefront
+    const int lane = threadIdx.x & 63;
+    const int count = __popcll(m);
+    float x0 = 0.0f, x1 = 0.0f, x2 = 0.0f;
+    if (want) mlp_features((float)rhoL, (float)uL, (float)PL, (float)rhoR, (float)uR, (float)PR, gamma, x0, x1, x2);
+    // lane j < count takes the j-th wanting lane: the smallest s with
+    // popcount(m & (2^(s+1) - 1)) = j + 1, by bisection on s
+    int s = 0;
+    for (int step = 32; step > 0; step >>= 1) {
+        const int t = s + step - 1;
+        if (__popcll(m & (t >= 63 ? ~0ull : ((2ull << t) - 1ull))) <= lane) s += step;
+    }
+    const bool has = lane < count;
+    const float y0 = __shfl(x0, s, 64), y1 = __shfl(x1, s, 64), y2 = __shfl(x2, s, 64);
+    const float y = mlp_wave_infer(P, has ? y0 : 0.0f, has ? y1 : 0.0f, has ? y2 : 0.0f, count > 32 ? 2 : 1);
+    const float back = __shfl(y, __popcll(m & ((1ull << lane) - 1ull)), 64);
+    if (!want) return no_guess<T>();
+    // the network predicts ln(p* / p_standard) / kMlpScaleY
+    const float corr = kMlpScaleY * back;
+    return (corr > -20.0f && corr < 20.0f) ? (T)corr : no_guess<T>();
+}
+
 // Section 3.5 (poorly resolved cold flows), per face: the entropy flux is
 // the mass flux times A_U = P_U / rho_U^gamma of the upwind side of the
 // Riemann problem, the side the face state is sampled from (AU = 0 for a
@@ -334,27 +414,10 @@ __device__ __forceinline__ void entropy_terms(const FaceState<T> &fs, T rhoL, T 
     }
 }
 
-// The energy switch's per-face values (Section 3.5, eq. eqnScrit1): the
-// kinetic energy of each neighbour in the other's generator frame, from the
-// start-of-step states, M_K = rho_K V_K (0 for a vacuum side):
-//   ek_RL = M_R |v_R - w_L|^2 / 2,  ek_LR = M_L |v_L - w_R|^2 / 2,
-// given dv_RL = v_R - w_L and dv_LR = v_L - w_R.
-template <int D>
-__device__ __forceinline__ void esw_terms(double rhoL, double rhoR, double VL, double VR, const double (&dv_RL)[D],
-                                          const double (&dv_LR)[D], double &ek_RL, double &ek_LR) {
-    double eR = 0.0, eL = 0.0;
-    for (int k = 0; k < D; k++) {
-        eR += dv_RL[k] * dv_RL[k];
-        eL += dv_LR[k] * dv_LR[k];
-    }
-    ek_RL = rhoR > 0.0 ? 0.5 * (rhoR * VR) * eR : 0.0;
-    ek_LR = rhoL > 0.0 ? 0.5 * (rhoL * VL) * eL : 0.0;
-}
-
 // A face's values besides its D + 2 fluxes (EM the entropy mode): the
-// entropy flux and the Mach number (EM >= 1), ek_RL and ek_LR (EM == 2).
+// entropy flux and the Mach number (EM >= 1).
 struct FaceX {
-    double v[4];
+    double v[2];
 };
 
 // One face's record, face-major (the Rec<D, EM>::FM values).
@@ -413,12 +476,9 @@ __device__ __forceinline__ void lab_flux(double rho, double u, double P, const d
 }
 
 // What the face bodies read besides the records: the static field
-// (GRAV, Section 5.2; accel [D][n], g = -grad Phi), and for the energy
-// switch the cell volumes and (double path) the generator velocities.
+// (GRAV, Section 5.2; accel [D][n], g = -grad Phi).
 struct FaceAux {
     const double *accel;
-    const double *V;
-    const double *mvel;
     int64_t n;
 };
 
@@ -429,7 +489,7 @@ struct FaceAux {
 // learned staging holds barriers); active = false does no face. LEARNED
 // compiles the fused network in; the standard-guess instantiation carries
 // none of its registers. EM >= 1 adds the entropy flux and the shock Mach
-// number, EM == 2 the energy switch's values (X). GRAV adds the half-step
+// number (X). GRAV adds the half-step
 // kick hdt g_K of the static field to each side's predicted velocity; a
 // face that falls back to its unextrapolated states takes none.
 template <int D, bool LEARNED, int EM, bool GRAV>
@@ -442,7 +502,6 @@ __device__ __forceinline__ void face_flux64(bool active, int64_t f, const int32_
     using Y = Lay<D>;
     constexpr int NV = D + 2;
     double A = 0.0, nrm[D], w[D], xl[NV], xr[NV], uL = 0.0, uR = 0.0;
-    double rhoL0 = 0.0, rhoR0 = 0.0, dv_RL[D], dv_LR[D];
     for (int c = 0; c < NV; c++) { xl[c] = 1.0; xr[c] = 1.0; }
     if (active) {
         double fr[Y::FREC];
@@ -459,14 +518,6 @@ __device__ __forceinline__ void face_flux64(bool active, int64_t f, const int32_
             const double c = fr[Y::FC + k];
             gL[k] = c + hl * nrm[k];   // f - r_L
             gR[k] = c - hl * nrm[k];   // f - r_R
-        }
-        if constexpr (EM == 2) {   // lab-frame velocities against the other generator
-            rhoL0 = rl.p[Y::W];
-            rhoR0 = rr.p[Y::W];
-            for (int k = 0; k < D; k++) {
-                dv_RL[k] = rr.p[Y::W + 1 + k] - aux.mvel[k * aux.n + l];
-                dv_LR[k] = rl.p[Y::W + 1 + k] - aux.mvel[k * aux.n + r];
-            }
         }
         double cl[NV], cr[NV], vf[D];
         for (int k = 0; k < D; k++) vf[k] = rl.p[Y::W + 1 + k] - w[k];
@@ -506,8 +557,6 @@ __device__ __forceinline__ void face_flux64(bool active, int64_t f, const int32_
             X.v[0] = F[0] * AU;
             X.v[1] = mach;
         }
-        if constexpr (EM == 2)
-            esw_terms<D>(rhoL0, rhoR0, aux.V[fL[f]], aux.V[fR[f]], dv_RL, dv_LR, X.v[2], X.v[3]);
     }
 }
 
@@ -538,12 +587,10 @@ __global__ void __launch_bounds__(kBlock) k_face_flux64(int64_t nf, const int32_
 // frame transform and half step on velocities relative to the face (the
 // cell record holds v_i - w_i and w_K - w_f follows from the face record's
 // w_L - w_R, so v - w_f = (v_K - w_K) + (w_K - w_f) never forms a lab-frame
-// velocity). With EM == 2 also the energy switch's values (ek_RL, ek_LR):
-// v_R - w_L = (v_R - w_R) - (w_L - w_R) and v_L - w_R = (v_L - w_L) + (w_L - w_R).
+// velocity).
 template <int D> struct MixedFace {
     float xl[D + 2], xr[D + 2], uL, uR, nrm[D], A;
     bool posfb;
-    double ek_RL, ek_LR;
 };
 
 template <int D, int EM, bool GRAV>
@@ -552,15 +599,16 @@ __device__ __forceinline__ MixedFace<D> mixed_face_states(int64_t f, const int32
                                                           const float *__restrict__ mrec,
                                                           const float *__restrict__ prim,
                                                           const float *__restrict__ grad, float hdtL, float hdtR,
-                                                          float gam, const FaceAux &aux) {
+                                                          float gam, const FaceAux &aux,
+                                                          const Window &win = Window{nullptr, 0}) {
     using Y = Lay<D>;
     constexpr int NV = D + 2;
     MixedFace<D> o;
     float fr[Y::MREC];
     load_rec<Y::MREC>(mrec + f * Y::MREC, fr);
     const int64_t l = fL[f], r = fR[f];
-    const CellRec<D, float> rl = load_cell<D>(prim, grad, l);
-    const CellRec<D, float> rr = load_cell<D>(prim, grad, r);
+    const CellRec<D, float> rl = load_cell_w<D>(prim, grad, l, win);
+    const CellRec<D, float> rr = load_cell_w<D>(prim, grad, r, win);
     o.A = fr[Y::FA];
     const float hl = 0.5f * fr[Y::FELL];
     float gL[D], gR[D], cl[NV], cr[NV], vf[D], dw[D], proj = 0.0f;
@@ -571,15 +619,6 @@ __device__ __forceinline__ MixedFace<D> mixed_face_states(int64_t f, const int32
         gR[k] = c - hl * o.nrm[k];
         dw[k] = fr[Y::MDW + k];
         proj += dw[k] * c;
-    }
-    o.ek_RL = o.ek_LR = 0.0;
-    if constexpr (EM == 2) {
-        double dv_RL[D], dv_LR[D];
-        for (int k = 0; k < D; k++) {
-            dv_RL[k] = (double)rr.p[Y::W + 1 + k] - (double)dw[k];
-            dv_LR[k] = (double)rl.p[Y::W + 1 + k] + (double)dw[k];
-        }
-        esw_terms<D>((double)rl.p[Y::W], (double)rr.p[Y::W], aux.V[l], aux.V[r], dv_RL, dv_LR, o.ek_RL, o.ek_LR);
     }
     // w_L - w_f = dw/2 - (dw.c/|d|) n and w_R - w_f = -dw/2 - (dw.c/|d|) n
     proj *= 0.5f / hl;
@@ -638,12 +677,13 @@ __device__ __forceinline__ void face_flux_mixed(bool active, int64_t f, const in
                                                 const float *__restrict__ grad, double dt, double hdtL, double hdtR,
                                                 const GasConst<float> &kf, double g_over_gm1, float tol32, int maxit,
                                                 const MlpPacked *mlp, const FaceAux &aux, float *stash,
-                                                LaneDiag &ld, bool &hard, double (&F)[D + 2], FaceX &X) {
+                                                LaneDiag &ld, bool &hard, double (&F)[D + 2], FaceX &X,
+                                                const Window &win = Window{nullptr, 0}) {
     constexpr int NV = D + 2;
     hard = false;
     MixedFace<D> m;
     if (active) {
-        m = mixed_face_states<D, EM, GRAV>(f, fL, fR, mrec, prim, grad, (float)hdtL, (float)hdtR, kf.g, aux);
+        m = mixed_face_states<D, EM, GRAV>(f, fL, fR, mrec, prim, grad, (float)hdtL, (float)hdtR, kf.g, aux, win);
         ld.posfb += m.posfb ? 1 : 0;
     } else {
         for (int c = 0; c < NV; c++) { m.xl[c] = 1.0f; m.xr[c] = 1.0f; }
@@ -687,10 +727,6 @@ __device__ __forceinline__ void face_flux_mixed(bool active, int64_t f, const in
                 X.v[1] = (double)mach;
             }
         }
-        if constexpr (EM == 2) {
-            X.v[2] = m.ek_RL;
-            X.v[3] = m.ek_LR;
-        }
     }
 }
 
@@ -710,16 +746,21 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))
                                                             double *__restrict__ flux, int32_t *__restrict__ hard_list,
                                                             int64_t cap, DiagDev *diag, FaceAux aux) {
     constexpr int NV = D + 2;
-    __shared__ float stash[LEARNED ? stash_floats<D>() : 1];
+    constexpr int SW = kWin * (Lay<D>::PREC + Lay<D>::GREC);
+    constexpr int SS = LEARNED ? stash_floats<D>() : 1;
+    // the staged window of cell records; once the face states are formed, the
+    // learned staging (its first barrier comes after every read of the window)
+    __shared__ float stash[SW > SS ? SW : SS];
     const int64_t f = xcd_global_id();
     const bool active = f < nf;
+    const Window win = stage_window<D>(stash, xcd_tile() * kBlock, nf, fL, prim, grad, aux.n);
     LaneDiag ld;
     bool hard;
     const double dt = dt_ptr ? *dt_ptr : dt_val;
     double F[NV];
     FaceX X;
     face_flux_mixed<D, LEARNED, EM, GRAV>(active, f, fL, fR, mrec, wf64, prim, grad, dt, 0.5 * dt, 0.5 * dt, kf,
-                                          g_over_gm1, tol32, maxit, mlp, aux, stash, ld, hard, F, X);
+                                          g_over_gm1, tol32, maxit, mlp, aux, stash, ld, hard, F, X, win);
     if (active && !hard) store_face<D, EM>(flux + f * Rec<D, EM>::FM, F, X);
     list_append(hard_list, cap, hard, (int32_t)f);
     if (diag) flush_diag(ld, diag);
@@ -748,10 +789,6 @@ __device__ __forceinline__ void hard_face(int64_t f, const int32_t *__restrict__
                               AU, mach);
         X.v[0] = F[0] * AU;
         X.v[1] = mach;
-    }
-    if constexpr (EM == 2) {
-        X.v[2] = m.ek_RL;
-        X.v[3] = m.ek_LR;
     }
 }
 
@@ -818,7 +855,7 @@ __global__ void __launch_bounds__(kBlock) k_face_flux64_list(const int32_t *__re
         double F[NV];
         FaceX X;
         face_flux64<D, LEARNED, 0, false>(active, f, fL, fR, frec, prim, grad, fdt, hl, hr, kg, tol, maxit, mlp,
-                                          FaceAux{nullptr, nullptr, nullptr, 0}, ld, F, X);
+                                          FaceAux{nullptr, 0}, ld, F, X);
         if (active) store_face<D, 0>(flux + f * NV, F, X);
     }
     if (diag) flush_diag(ld, diag);
@@ -853,7 +890,7 @@ k_face_flux_mixed_list(const int32_t *__restrict__ list, int64_t cap, const int3
         double F[NV];
         FaceX X;
         face_flux_mixed<D, LEARNED, 0, false>(active, f, fL, fR, mrec, wf64, prim, grad, fdt, hl, hr, kf,
-                                              g_over_gm1, tol32, maxit, mlp, FaceAux{nullptr, nullptr, nullptr, 0},
+                                              g_over_gm1, tol32, maxit, mlp, FaceAux{nullptr, 0},
                                               stash, ld, hard, F, X);
         if (active && !hard) store_face<D, 0>(flux + f * NV, F, X);
         list_append(hard_list, cap, active && hard, (int32_t)f);

@@ -215,7 +215,7 @@ __global__ void __launch_bounds__(kBlock) k_riemann_batch(int64_t n, int64_t i0,
     T pl = no_guess<T>();
     if constexpr (LEARNED) {
         const bool want = ok && wants_learned<T>(s[0], s[1], s[2], s[3], s[4], s[5], kt.g);
-        pl = learned_guess<T>(mlp, want, s[0], s[1], s[2], s[3], s[4], s[5], (float)kt.g);
+        pl = learned_guess_wave<T>(mlp, want, s[0], s[1], s[2], s[3], s[4], s[5], (float)kt.g);
     }
     LaneDiag ld;
     bool hard = false;

@@ -1,9 +1,11 @@
-// k_mesh.hpp -- device side of mm_mesh_upload: validation, the per-cell
-// list of face sides (CSR, ascending face order inside each cell), the face
-// geometry and the face velocities.
+// k_mesh.hpp -- device side of mm_mesh_upload: validation, each cell's left
+// face range and sorted right faces, the per-cell side lists of the
+// gradient pass (left faces then right faces), the face geometry and the
+// face velocities.
 #pragma once
 
 #include "common.hpp"
+#include "k_cell.hpp"
 #include "layout.hpp"
 
 namespace mm {
@@ -33,6 +35,7 @@ __global__ void __launch_bounds__(kBlock) k_validate_faces(int64_t n, int64_t nf
         int32_t l = L[f], r = R[f];
         if (l < 0 || l >= n || r < 0 || r >= n) bad |= MF_INDEX;
         if (l == r) bad |= MF_SELF;
+        if (f > 0 && l < L[f - 1]) bad |= MF_ORDER;   // faces sorted by left cell
         double a = area[f];
         if (!(a >= 0.0) || !isfinite(a)) bad |= MF_AREA;
         double s2 = 0.0;
@@ -63,15 +66,6 @@ __global__ void __launch_bounds__(kBlock) k_validate_cells(int64_t n, const doub
         }
     }
     if (bad) atomicOr(flags, bad);
-}
-
-// cnt[c] = number of faces that cell c touches (cnt points at off + 1).
-__global__ void k_count_sides(int64_t nf, const int32_t *L, const int32_t *R, int32_t *cnt) {
-    int64_t f = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (f < nf) {
-        atomicAdd(&cnt[L[f]], 1);
-        atomicAdd(&cnt[R[f]], 1);
-    }
 }
 
 // In-place inclusive scan of 1024-element tiles; tile totals go to bsum.
@@ -111,79 +105,74 @@ __global__ void k_scan_add(int32_t *data, int64_t n, const int32_t *bsum_incl) {
     }
 }
 
-// Place every face side into its cell's segment. The order inside a
-// segment is fixed afterwards by k_sort_segments.
-__global__ void k_fill_sides(int64_t nf, const int32_t *L, const int32_t *R, int32_t *cursor,
-                             int32_t *ent, int32_t *nb) {
-    int64_t f = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (f < nf) {
-        int32_t l = L[f], r = R[f];
-        int32_t p = atomicAdd(&cursor[l], 1);
-        ent[p] = (int32_t)(2 * f);
-        nb[p] = r;
-        int32_t q = atomicAdd(&cursor[r], 1);
-        ent[q] = (int32_t)(2 * f + 1);
-        nb[q] = l;
+// Faces sorted by left cell: the first face of every cell's left range by
+// binary search over face_L (loff [n + 1]; cells without left faces get the
+// next range's start, loff[n] = nf).
+__global__ void __launch_bounds__(kBlock) k_left_offsets(int64_t n, int64_t nf, const int32_t *__restrict__ L,
+                                                         int32_t *__restrict__ loff) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i > n) return;
+    int64_t lo = 0, hi = nf;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (L[mid] < i) lo = mid + 1;
+        else hi = mid;
     }
+    loff[i] = (int32_t)lo;
 }
 
-// Sort each cell's face sides by face index (insertion sort: segments hold
-// ~6 entries in 2D and ~15 in 3D), making every per-cell sum deterministic
-// and equal in order to a loop over the face list.
-__global__ void k_sort_segments(int64_t n, const int32_t *off, int32_t *ent, int32_t *nb) {
-    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    int32_t b = off[i], e = off[i + 1];
-    for (int32_t a = b + 1; a < e; a++) {
-        int32_t ke = ent[a], kn = nb[a];
-        int32_t j = a - 1;
-        while (j >= b && ent[j] > ke) {
-            ent[j + 1] = ent[j];
-            nb[j + 1] = nb[j];
-            j--;
-        }
-        ent[j + 1] = ke;
-        nb[j + 1] = kn;
-    }
+// rcnt[c] = number of faces whose right cell is c (rcnt points at roff + 1).
+__global__ void k_count_right(int64_t nf, const int32_t *__restrict__ R, int32_t *__restrict__ rcnt) {
+    const int64_t f = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (f < nf) atomicAdd(&rcnt[R[f]], 1);
 }
 
-// The update's view of each cell's faces (k_update.hpp), from its side list
-// (ascending face order): the number of faces where it is the left and the
-// right cell, into lcnt[i] and rcnt[i] (for the offset scans).
-__global__ void k_lr_count(int64_t n, const int32_t *__restrict__ off, const int32_t *__restrict__ ent,
-                           int32_t *__restrict__ lcnt, int32_t *__restrict__ rcnt) {
+// Every face into its right cell's slots (any order; k_sort_right fixes it).
+__global__ void k_place_right(int64_t nf, const int32_t *__restrict__ R, int32_t *__restrict__ cursor,
+                              int32_t *__restrict__ rface) {
+    const int64_t f = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (f < nf) rface[atomicAdd(&cursor[R[f]], 1)] = (int32_t)f;
+}
+
+// Each cell's right faces in ascending face order, one thread per cell: up
+// to 16 in registers through a bitonic sorting network, longer lists
+// (rare) by insertion in memory.
+__global__ void __launch_bounds__(kBlock) k_sort_right(int64_t n, const int32_t *__restrict__ roff,
+                                                       int32_t *__restrict__ rface) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
-    int32_t nl = 0, nr = 0;
-    for (int32_t q = off[i]; q < off[i + 1]; q++) {
-        if (ent[q] & 1) nr++;
-        else nl++;
-    }
-    lcnt[i] = nl;
-    rcnt[i] = nr;
-}
-
-// After the scans: each cell's right faces in ascending face order
-// (rface[roff[i] ...]), and the check that the faces are sorted by left
-// cell (the k-th left face of cell i must be face loff[i] + k, else
-// MF_ORDER).
-__global__ void k_lr_fill(int64_t n, const int32_t *__restrict__ off, const int32_t *__restrict__ ent,
-                          const int32_t *__restrict__ loff, const int32_t *__restrict__ roff,
-                          int32_t *__restrict__ rface, int32_t *flags) {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    int32_t kl = loff[i], kr = roff[i];
-    bool bad = false;
-    for (int32_t q = off[i]; q < off[i + 1]; q++) {
-        const int32_t en = ent[q], f = en >> 1;
-        if (en & 1) {
-            rface[kr++] = f;
-        } else {
-            bad = bad || f != kl;
-            kl++;
+    const int32_t b = roff[i], m = roff[i + 1] - b;
+    if (m <= 16) {
+        int32_t k[16];
+#pragma unroll
+        for (int j = 0; j < 16; j++) k[j] = j < m ? rface[b + j] : INT32_MAX;
+#pragma unroll
+        for (int size = 2; size <= 16; size <<= 1)
+#pragma unroll
+            for (int stride = size >> 1; stride > 0; stride >>= 1)
+#pragma unroll
+                for (int j = 0; j < 16; j++) {
+                    const int p = j ^ stride;
+                    if (p > j) {
+                        const bool up = (j & size) == 0;
+                        const int32_t x = k[j], y = k[p];
+                        if ((x > y) == up) { k[j] = y; k[p] = x; }
+                    }
+                }
+#pragma unroll
+        for (int j = 0; j < 16; j++)
+            if (j < m) rface[b + j] = k[j];
+    } else {
+        for (int32_t a = b + 1; a < b + m; a++) {
+            const int32_t key = rface[a];
+            int32_t j = a - 1;
+            while (j >= b && rface[j] > key) {
+                rface[j + 1] = rface[j];
+                j--;
+            }
+            rface[j + 1] = key;
         }
     }
-    if (bad) atomicOr(flags, MF_ORDER);
 }
 
 // Face records (Section 3.3 geometry and face velocity):
@@ -236,48 +225,68 @@ __global__ void __launch_bounds__(kBlock) k_face_records(int64_t n, int64_t nf, 
     }
 }
 
-// Side records in CSR order, one lane per cell: A/|d| and f - r_i, in
-// double for the double path and in float for the mixed path, and the
-// closure test of each cell,
-// |sum_faces A n_out| <= 1e-9 sum_faces A. A closed surface is a property of
-// every Voronoi cell; the gradient kernels rely on it.
+// The per-cell side lists of the gradient pass, one lane group per cell:
+// its left faces (face order) then its right faces (face order), so that
+// off[i] = loff[i] + roff[i]; per side ent = face << 1 | is_right, the
+// neighbour, and the side record A/|d|, f - r_i (double or float); and the
+// closure test |sum_faces A n_out| <= 1e-9 sum_faces A of every cell (a
+// closed surface is a property of every Voronoi cell; the gradient relies
+// on it).
 template <int D>
-__global__ void __launch_bounds__(kBlock) k_side_records(int64_t n, int64_t nf, const int32_t *off,
-                                                         const int32_t *ent, const double *area, const double *ctr,
-                                                         const double *sep, double *srec, int mixed, float *srec32,
-                                                         int32_t *flags) {
+__global__ void __launch_bounds__(kBlock) k_sides(int64_t n, int64_t nf, const int32_t *__restrict__ L,
+                                                  const int32_t *__restrict__ R, const double *__restrict__ area,
+                                                  const double *__restrict__ ctr, const double *__restrict__ sep,
+                                                  const int32_t *__restrict__ loff, const int32_t *__restrict__ roff,
+                                                  const int32_t *__restrict__ rface, int32_t *__restrict__ off,
+                                                  int32_t *__restrict__ ent, int32_t *__restrict__ nbr,
+                                                  double *__restrict__ srec, float *__restrict__ srec32,
+                                                  int32_t *flags) {
     using Y = Lay<D>;
-    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    constexpr int GS = Group<D>::GS;
+    const int lane = threadIdx.x % GS;
+    const int64_t i = (int64_t)blockIdx.x * (kBlock / GS) + threadIdx.x / GS;
     if (i >= n) return;
+    const int32_t l0 = loff[i], nl = loff[i + 1] - l0, r0 = roff[i], nr = roff[i + 1] - r0;
+    const int32_t o = l0 + r0;
+    if (lane == 0) {
+        off[i] = o;
+        if (i == n - 1) off[n] = loff[n] + roff[n];
+    }
     double clo[D], asum = 0.0;
     for (int k = 0; k < D; k++) clo[k] = 0.0;
-    for (int32_t q = off[i]; q < off[i + 1]; q++) {
-        const int32_t en = ent[q];
-        const int64_t f = en >> 1;
-        const double sg = (en & 1) ? -1.0 : 1.0;  // outward separation e = sg * d
+    for (int32_t k = lane; k < nl + nr; k += GS) {
+        const bool right = k >= nl;
+        const int32_t f = right ? rface[r0 + k - nl] : l0 + k;
+        const double sg = right ? -1.0 : 1.0;   // outward separation e = sg * d
         double d[D], s2 = 0.0;
-        for (int k = 0; k < D; k++) { d[k] = sep[k * nf + f]; s2 += d[k] * d[k]; }
+        for (int c = 0; c < D; c++) { d[c] = sep[c * nf + f]; s2 += d[c] * d[c]; }
         const double ell = sqrt(s2), A = area[f];
-        double o[Y::SREC64];
-        o[0] = A / ell;
-        for (int k = 0; k < D; k++) {
-            const double c = ctr[k * nf + f] - 0.5 * d[k];
-            o[1 + k] = c + 0.5 * sg * d[k];
-            clo[k] += A * sg * d[k] / ell;
+        double rec[Y::SREC64];
+        rec[0] = A / ell;
+        for (int c = 0; c < D; c++) {
+            const double cc = ctr[c * nf + f] - 0.5 * d[c];
+            rec[1 + c] = cc + 0.5 * sg * d[c];
+            clo[c] += A * sg * d[c] / ell;
         }
-        for (int k = 1 + D; k < Y::SREC64; k++) o[k] = 0.0;
-        if (!mixed)
-            for (int k = 0; k < Y::SREC64; k++) srec[(int64_t)q * Y::SREC64 + k] = o[k];
+        for (int c = 1 + D; c < Y::SREC64; c++) rec[c] = 0.0;
         asum += A;
-        if (mixed) {
+        const int64_t q = o + k;
+        ent[q] = (int32_t)(2 * f + (right ? 1 : 0));
+        nbr[q] = right ? L[f] : R[f];
+        if (srec) store_rec<Y::SREC64>(srec + q * Y::SREC64, rec);
+        else {
             float m[Y::SREC32];
-            for (int k = 0; k < Y::SREC32; k++) m[k] = (float)o[k];
-            store_rec<Y::SREC32>(srec32 + (int64_t)q * Y::SREC32, m);
+            for (int c = 0; c < Y::SREC32; c++) m[c] = (float)rec[c];
+            store_rec<Y::SREC32>(srec32 + q * Y::SREC32, m);
         }
     }
     double cl2 = 0.0;
-    for (int k = 0; k < D; k++) cl2 += clo[k] * clo[k];
-    if (!(sqrt(cl2) <= 1e-9 * asum)) atomicOr(flags, MF_OPEN);
+    for (int c = 0; c < D; c++) {
+        clo[c] = grp_sum<GS>(clo[c]);
+        cl2 += clo[c] * clo[c];
+    }
+    asum = grp_sum<GS>(asum);
+    if (lane == 0 && !(sqrt(cl2) <= 1e-9 * asum)) atomicOr(flags, MF_OPEN);
 }
 
 }  // namespace mm

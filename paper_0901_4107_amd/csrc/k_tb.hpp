@@ -324,12 +324,12 @@ __device__ __forceinline__ void tb_update_cell(int64_t i, int lane, int64_t n, c
         const int bl = bin[sd.fL[f]], br = bin[sd.fR[f]];
         return tb_starts(ti, bl < br ? bl : br);
     };
-    double acc[NV], mx, ek;
-    cell_sums<D, 0>(i, lane, sd.lOff, sd.rOff, sd.rFace, flux, live, acc, mx, ek);
+    double acc[NV], mx;
+    cell_sums<D, 0>(i, lane, sd.lOff, sd.rOff, sd.rFace, flux, live, acc, mx);
     if (lane == 0) {
         UpdateArgs u{};
         u.flags = flags;
-        finish_cell<D, 0, false>(i, n, acc, 0.0, 0.0, Q, u);
+        finish_cell<D, 0, false>(i, n, acc, 0.0, Q, u);
     }
 }
 

@@ -14,11 +14,9 @@
 //
 // Records (face-major, written by the face kernels). EM is the entropy
 // mode (0 off, 1 Mach switch, 2 energy switch). A face's values: the D + 2
-// fluxes, then (EM >= 1) the entropy flux and the face's shock Mach number,
-// then (EM == 2) the kinetic energies of the two neighbours in each other's
-// generator frames (Section 3.5, eq. eqnScrit1):
-//   ek_RL = M_R |v_R - w_L|^2 / 2 (for the left cell's switch),
-//   ek_LR = M_L |v_L - w_R|^2 / 2 (for the right cell's).
+// fluxes, then (EM >= 1) the entropy flux and the face's shock Mach number.
+// The energy switch's neighbour energies come from the gradient pass
+// (ekmax, one per cell).
 #pragma once
 
 #include "common.hpp"
@@ -29,9 +27,9 @@ namespace mm {
 
 template <int D, int EM> struct Rec {
     static constexpr int NV = D + 2;
-    static constexpr int NS = NV + (EM ? 1 : 0);                       // summed values
-    static constexpr int MACH = NV + 1, EK_RL = NV + 2, EK_LR = NV + 3;  // maxima
-    static constexpr int FM = NV + (EM ? 2 : 0) + (EM == 2 ? 2 : 0);   // record stride
+    static constexpr int NS = NV + (EM ? 1 : 0);   // summed values
+    static constexpr int MACH = NV + 1;            // a maximum
+    static constexpr int FM = NV + (EM ? 2 : 0);   // record stride
 };
 
 // What the end of a cell's update needs besides the sums.
@@ -45,6 +43,7 @@ struct UpdateArgs {
     double dt_val;             // ... or its value
     double alpha_s, beta_s;    // energy switch
     const double *mvel;        // generator velocities [D][n]
+    const double *ekmax;       // energy switch: the gradient pass's largest neighbour energy per cell
 };
 
 // The end of cell i's update, by lane 0 of its group: Q_i <- Q_i + acc,
@@ -58,17 +57,20 @@ struct UpdateArgs {
 // frame, or with a field below beta_s M |g| R (EM == 2) -- and its new mass
 // and entropy are positive; every other cell takes S = M P / rho^gamma of
 // its updated state, 0 for M <= 0).
-// mx: the largest face Mach number, ek: the largest neighbour kinetic energy
-// in the cell's generator frame (the cell's own is added here, from Q at the
-// start of the step). Returns whether the cell kept its entropy.
+// mx: the largest face Mach number; the largest neighbour kinetic energy in
+// the cell's generator frame is the gradient pass's ekmax, the cell's own
+// added here from Q at the start of the step. Returns whether the cell kept
+// its entropy.
 template <int D, int EM, bool GRAV>
-__device__ __forceinline__ bool finish_cell(int64_t i, int64_t n, const double *acc, double mx, double ek,
+__device__ __forceinline__ bool finish_cell(int64_t i, int64_t n, const double *acc, double mx,
                                             double *__restrict__ Q, const UpdateArgs &u) {
     constexpr int NV = D + 2;
     constexpr int NS = Rec<D, EM>::NS;
     double q[NS];
     for (int c = 0; c < NS; c++) q[c] = Q[c * n + i] + acc[c];
+    double ek = 0.0;
     if constexpr (EM == 2) {
+        ek = u.ekmax[i];
         const double m0 = Q[i];
         if (m0 > 0.0) {
             double e = 0.0;
@@ -145,25 +147,23 @@ __device__ __forceinline__ void count_kept(bool keep, DiagDev *diag) {
 
 // The sums of cell i by lane `lane` of its group: acc = the lane's share
 // (minus its left faces, plus its right faces, in that order), butterfly
-// summed over the group; mx, ek the group's largest Mach number and
-// neighbour energy. live(f): whether face f takes part (individual
-// timesteps); the rest contribute nothing. Each lane keeps up to KL left and
-// KR right records in flight together, the rare rest in loops.
+// summed over the group; mx the group's largest face Mach number. live(f):
+// whether face f takes part (individual timesteps); the rest contribute
+// nothing. Each lane keeps up to KL left and KR right records in flight
+// together, the rare rest in loops.
 template <int D, int EM, typename Live>
 __device__ __forceinline__ void cell_sums(int64_t i, int lane, const int32_t *__restrict__ lOff,
                                           const int32_t *__restrict__ rOff, const int32_t *__restrict__ rFace,
                                           const double *__restrict__ flux, Live live,
-                                          double (&acc)[Rec<D, EM>::NS], double &mx, double &ek) {
+                                          double (&acc)[Rec<D, EM>::NS], double &mx) {
     using RC = Rec<D, EM>;
     constexpr int NS = RC::NS, FM = RC::FM;
-    constexpr int FL = EM == 2 ? RC::EK_RL + 1 : FM;   // values read of a left face
     constexpr int GS = Group<D>::GS;
     constexpr int KL = 2, KR = 2;
     for (int c = 0; c < NS; c++) acc[c] = 0.0;
     mx = 0.0;
-    ek = 0.0;
     const int32_t l0 = lOff[i], l1 = lOff[i + 1], r0 = rOff[i], r1 = rOff[i + 1];
-    double FLr[KL][FL], FRr[KR][FM];
+    double FLr[KL][FM], FRr[KR][FM];
     bool hl[KL], hr[KR];
     int32_t fr[KR];
     for (int r = 0; r < KR; r++) {
@@ -173,42 +173,35 @@ __device__ __forceinline__ void cell_sums(int64_t i, int lane, const int32_t *__
     for (int r = 0; r < KL; r++) {
         const int32_t f = l0 + lane + r * GS;
         hl[r] = f < l1 && live(f);
-        load_rec<FL>(flux + (int64_t)(hl[r] ? f : 0) * FM, FLr[r]);
+        load_rec<FM>(flux + (int64_t)(hl[r] ? f : 0) * FM, FLr[r]);
     }
     for (int r = 0; r < KR; r++) {
         hr[r] = r0 + lane + r * GS < r1 && live(fr[r]);
         load_rec<FM>(flux + (int64_t)(hr[r] ? fr[r] : 0) * FM, FRr[r]);
     }
-    auto take_left = [&](const double *F) {
-        for (int c = 0; c < NS; c++) acc[c] -= F[c];
+    auto take = [&](const double *F, double sign) {
+        for (int c = 0; c < NS; c++) acc[c] += sign * F[c];
         if constexpr (EM != 0) mx = fmax(mx, F[RC::MACH]);
-        if constexpr (EM == 2) ek = fmax(ek, F[RC::EK_RL]);
-    };
-    auto take_right = [&](const double *F) {
-        for (int c = 0; c < NS; c++) acc[c] += F[c];
-        if constexpr (EM != 0) mx = fmax(mx, F[RC::MACH]);
-        if constexpr (EM == 2) ek = fmax(ek, F[RC::EK_LR]);
     };
     for (int r = 0; r < KL; r++)
-        if (hl[r]) take_left(FLr[r]);
+        if (hl[r]) take(FLr[r], -1.0);
     for (int32_t f = l0 + lane + KL * GS; f < l1; f += GS) {
         if (!live(f)) continue;
-        double F[FL];
-        load_rec<FL>(flux + (int64_t)f * FM, F);
-        take_left(F);
+        double F[FM];
+        load_rec<FM>(flux + (int64_t)f * FM, F);
+        take(F, -1.0);
     }
     for (int r = 0; r < KR; r++)
-        if (hr[r]) take_right(FRr[r]);
+        if (hr[r]) take(FRr[r], 1.0);
     for (int32_t q = r0 + lane + KR * GS; q < r1; q += GS) {
         const int32_t f = rFace[q];
         if (!live(f)) continue;
         double F[FM];
         load_rec<FM>(flux + (int64_t)f * FM, F);
-        take_right(F);
+        take(F, 1.0);
     }
     for (int c = 0; c < NS; c++) acc[c] = grp_sum<GS>(acc[c]);
     if constexpr (EM != 0) mx = grp_max<GS>(mx);
-    if constexpr (EM == 2) ek = grp_max<GS>(ek);
 }
 
 // The update (the step, mm_apply_update): one lane group per cell.
@@ -223,10 +216,10 @@ __global__ void __launch_bounds__(kBlock) k_update(int64_t n, const int32_t *__r
     const int lane = threadIdx.x % GS;
     const int64_t i = xcd_tile() * (kBlock / GS) + threadIdx.x / GS;
     if (i >= n) return;
-    double acc[RC::NS], mx, ek;
-    cell_sums<D, EM>(i, lane, lOff, rOff, rFace, flux, [](int32_t) { return true; }, acc, mx, ek);
+    double acc[RC::NS], mx;
+    cell_sums<D, EM>(i, lane, lOff, rOff, rFace, flux, [](int32_t) { return true; }, acc, mx);
     bool keep = false;
-    if (lane == 0) keep = finish_cell<D, EM, GRAV>(i, n, acc, mx, ek, Q, u);
+    if (lane == 0) keep = finish_cell<D, EM, GRAV>(i, n, acc, mx, Q, u);
     if constexpr (EM != 0) count_kept(keep, u.diag);
 }
 

@@ -85,15 +85,17 @@ __device__ __forceinline__ void mlp_features(float rhoL, float uL, float PL, flo
 // pass's columns, then layers 2 and 3 one output tile at a time. Each weight
 // is read twice per wavefront (L1 hits); the scheduling barriers keep each
 // tile's weight loads next to their use, so the network adds few registers
-// to the flux code's.
-__device__ __forceinline__ float mlp_wave_infer(const MlpPacked *__restrict__ P, float x0, float x1, float x2) {
+// to the flux code's. npass (1 or 2, the same for the whole wavefront):
+// with 1 only the first 32 lanes' columns are evaluated.
+__device__ __forceinline__ float mlp_wave_infer(const MlpPacked *__restrict__ P, float x0, float x1, float x2,
+                                                int npass = 2) {
     const int lane = threadIdx.x & 63;
     const int src = lane & 15;
     const bool low = lane < 16;
     const int rbase = 4 * (lane >> 4);
     float yy = 0.0f;
 #pragma unroll 1
-    for (int pass = 0; pass < 2; pass++) {
+    for (int pass = 0; pass < npass; pass++) {
         // the weights are re-read in each pass rather than held in
         // registers across both: the empty asm makes the offset opaque, so
         // the loads stay inside the pass

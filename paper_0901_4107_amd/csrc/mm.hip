@@ -60,6 +60,7 @@ inline unsigned plain_grid_n(int64_t n) { return (unsigned)((n + kBlock - 1) / k
 struct Layout {
     int64_t flags, diag, mlp, dtdev, bhard, dtpart, bsum, off, cursor, ent, nbr;
     int64_t loff, roff, rface;              // the update's left ranges and right faces
+    int64_t ekmax;                          // energy switch: neighbour energies per cell
     int64_t srec, frec, rec, flux;          // double path (frec always; flux: timelines only)
     int64_t srec32, mrec, wf64, rec32, hard, gath, w0, w0part; // mixed path
     int64_t tb_bin, tb_trec, tb_sig, tb_touch, tb_cells, tb_faces, tb_touched, tb_info;   // individual timesteps
@@ -69,7 +70,7 @@ struct Layout {
 // em: the entropy mode (0 off, MM_ENTROPY_MACH, MM_ENTROPY_ENERGY).
 Layout make_layout(int D, int mode, int em, bool tb, int64_t n, int64_t nf) {
     const int NV = D + 2;
-    const int FM = NV + (em ? 2 : 0) + (em == MM_ENTROPY_ENERGY ? 2 : 0);   // Rec<D, em>::FM
+    const int FM = NV + (em ? 2 : 0);   // Rec<D, em>::FM
     const int REC = (D == 3) ? Lay<3>::REC : Lay<2>::REC;
     const int FREC = (D == 3) ? Lay<3>::FREC : Lay<2>::FREC;
     const int WS = (D == 3) ? Lay<3>::WSTRIDE : Lay<2>::WSTRIDE;
@@ -95,6 +96,7 @@ Layout make_layout(int D, int mode, int em, bool tb, int64_t n, int64_t nf) {
     L.roff = take((n + 1) * sizeof(int32_t));
     L.rface = take(nf * sizeof(int32_t));
     L.flux = take(nf * FM * sizeof(double));
+    L.ekmax = em == MM_ENTROPY_ENERGY ? take(n * sizeof(double)) : -1;
     L.srec = L.srec32 = L.mrec = L.wf64 = L.rec32 = L.rec = L.hard = L.gath = L.w0 = L.w0part = -1;
     if (mode == MM_FP64) {
         L.srec = take(2 * nf * Lay<3>::SREC64 * sizeof(double));
@@ -139,6 +141,7 @@ struct mm_ctx {
     uint64_t faces_done = 0, waves_done = 0;
     mm_mesh mesh;
     const double *accel = nullptr;        // static gravitational field [D][N], or none
+    bool have_ek = false;                 // the energy switch's neighbour energies are in the workspace
     const double *last_dt_dev = nullptr;  // timestep of the last face-flux pass (device) ...
     double last_dt = 0.0;                 // ... or its value
     bool have_dt = false;
@@ -306,15 +309,6 @@ template <int D> static void launch_face_records(mm_ctx *c, const mm_mesh *m) {
     }
 }
 
-// Side records (geometry only) and the closure test.
-template <int D> static void launch_side_records(mm_ctx *c, const mm_mesh *m, int32_t *flags) {
-    const Layout &L = c->lay;
-    const int mixed = c->p.mode == MM_MIXED;
-    k_side_records<D><<<plain_grid(m->n_cells), kBlock, 0, c->st()>>>(
-        m->n_cells, m->n_faces, c->at<int32_t>(L.off), c->at<int32_t>(L.ent), m->face_area, m->face_ctr,
-        m->face_sep, mixed ? nullptr : c->at<double>(L.srec), mixed, mixed ? c->at<float>(L.srec32) : nullptr, flags);
-}
-
 mm_status mm_mesh_upload(mm_ctx *c, const mm_mesh *m) {
     if (!c || !m) return MM_E_ARG;
     if (!c->ws) return MM_E_STATE;
@@ -328,6 +322,7 @@ mm_status mm_mesh_upload(mm_ctx *c, const mm_mesh *m) {
     c->have_mesh = false;
     c->tb.on = false;
     c->accel = nullptr;   // a field and walls belong to the mesh they were set for
+    c->have_ek = false;
     c->walls = mm_ctx::Walls();
     c->have_dt = false;
     c->lay = L;
@@ -346,35 +341,35 @@ mm_status mm_mesh_upload(mm_ctx *c, const mm_mesh *m) {
     MM_CHECK(hipStreamSynchronize(s));
     if (hflags) return MM_E_MESH;
 
+    // each cell's left range (faces are sorted by left cell) and its right
+    // faces in ascending face order
     int32_t *off = c->at<int32_t>(L.off), *cur = c->at<int32_t>(L.cursor);
-    int32_t *ent = c->at<int32_t>(L.ent), *nbr = c->at<int32_t>(L.nbr);
-    k_fill_i32<<<plain_grid(n + 1), kBlock, 0, s>>>(off, n + 1, 0);
-    k_count_sides<<<plain_grid(nf), kBlock, 0, s>>>(nf, m->face_L, m->face_R, off + 1);
+    int32_t *loff = c->at<int32_t>(L.loff), *roff = c->at<int32_t>(L.roff), *rface = c->at<int32_t>(L.rface);
+    k_left_offsets<<<plain_grid(n + 1), kBlock, 0, s>>>(n, nf, m->face_L, loff);
+    k_fill_i32<<<plain_grid(n + 1), kBlock, 0, s>>>(roff, n + 1, 0);
+    k_count_right<<<plain_grid(nf), kBlock, 0, s>>>(nf, m->face_R, roff + 1);
     MM_LAUNCH_CHECK();
-    mm_status st = scan_inclusive(c, off + 1, n, c->at<int32_t>(L.bsum));
+    mm_status st = scan_inclusive(c, roff + 1, n, c->at<int32_t>(L.bsum));
     if (st != MM_OK) return st;
-    k_copy_i32<<<plain_grid(n), kBlock, 0, s>>>(cur, off, n);
-    k_fill_sides<<<plain_grid(nf), kBlock, 0, s>>>(nf, m->face_L, m->face_R, cur, ent, nbr);
-    k_sort_segments<<<plain_grid(n), kBlock, 0, s>>>(n, off, ent, nbr);
+    k_copy_i32<<<plain_grid(n), kBlock, 0, s>>>(cur, roff, n);
+    k_place_right<<<plain_grid(nf), kBlock, 0, s>>>(nf, m->face_R, cur, rface);
+    k_sort_right<<<plain_grid(n), kBlock, 0, s>>>(n, roff, rface);
     MM_LAUNCH_CHECK();
-    // the update's left ranges and right-cell slots
-    int32_t *loff = c->at<int32_t>(L.loff), *roff = c->at<int32_t>(L.roff);
-    k_fill_i32<<<1, kBlock, 0, s>>>(loff, 1, 0);
-    k_fill_i32<<<1, kBlock, 0, s>>>(roff, 1, 0);
-    k_lr_count<<<plain_grid(n), kBlock, 0, s>>>(n, off, ent, loff + 1, roff + 1);
-    MM_LAUNCH_CHECK();
-    st = scan_inclusive(c, loff + 1, n, c->at<int32_t>(L.bsum));
-    if (st != MM_OK) return st;
-    st = scan_inclusive(c, roff + 1, n, c->at<int32_t>(L.bsum));
-    if (st != MM_OK) return st;
-    k_lr_fill<<<plain_grid(n), kBlock, 0, s>>>(n, off, ent, loff, roff, c->at<int32_t>(L.rface), flags);
-    MM_LAUNCH_CHECK();
+    // the gradient pass's side lists and records, the closure test; the face
+    // records and face velocities
+    const bool mixed = c->p.mode == MM_MIXED;
+    double *srec = mixed ? nullptr : c->at<double>(L.srec);
+    float *srec32 = mixed ? c->at<float>(L.srec32) : nullptr;
     if (c->D == 3) {
+        k_sides<3><<<group_grid(3, n), kBlock, 0, s>>>(n, nf, m->face_L, m->face_R, m->face_area, m->face_ctr,
+                                                       m->face_sep, loff, roff, rface, off, c->at<int32_t>(L.ent),
+                                                       c->at<int32_t>(L.nbr), srec, srec32, flags);
         launch_face_records<3>(c, m);
-        launch_side_records<3>(c, m, flags);
     } else {
+        k_sides<2><<<group_grid(2, n), kBlock, 0, s>>>(n, nf, m->face_L, m->face_R, m->face_area, m->face_ctr,
+                                                       m->face_sep, loff, roff, rface, off, c->at<int32_t>(L.ent),
+                                                       c->at<int32_t>(L.nbr), srec, srec32, flags);
         launch_face_records<2>(c, m);
-        launch_side_records<2>(c, m, flags);
     }
     MM_LAUNCH_CHECK();
     MM_CHECK(hipMemcpyAsync(&hflags, flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -426,8 +421,16 @@ template <int D, typename T> static mm_status gradients_t(mm_ctx *c, const doubl
     k_prim_cfl<D, T><<<grid_for(c->n), kBlock, 0, s>>>(c->n, c->p.gamma, c->p.cfl, c->mesh.volume, Q,
                                                       c->mesh.mesh_vel, c->mesh.centroid_off, rec, gath, w0,
                                                       dt_part, c->at<int32_t>(L.flags) + 2);
-    k_grad_limit<D, T><<<group_grid(D, c->n), kBlock, 0, s>>>(c->n, c->at<int32_t>(L.off), c->at<int32_t>(L.nbr),
-                                                              srec, c->mesh.volume, rec, gath, grad_block<D>(c, rec));
+    if (c->p.entropy == MM_ENTROPY_ENERGY) {   // with the energy switch's neighbour energies
+        k_grad_limit<D, T, true><<<group_grid(D, c->n), kBlock, 0, s>>>(
+            c->n, c->at<int32_t>(L.off), c->at<int32_t>(L.nbr), srec, c->mesh.volume, rec, gath, grad_block<D>(c, rec),
+            c->mesh.mesh_vel, c->at<double>(L.ekmax));
+        c->have_ek = true;
+    } else {
+        k_grad_limit<D, T, false><<<group_grid(D, c->n), kBlock, 0, s>>>(
+            c->n, c->at<int32_t>(L.off), c->at<int32_t>(L.nbr), srec, c->mesh.volume, rec, gath, grad_block<D>(c, rec),
+            nullptr, nullptr);
+    }
     MM_LAUNCH_CHECK();
     return MM_OK;
 }
@@ -446,7 +449,7 @@ mm_status mm_gradients(mm_ctx *c, const double *Q, void *recon) {
     return gradients_into(c, Q, recon, c->at<double>(c->lay.dtpart));
 }
 
-static FaceAux face_aux(const mm_ctx *c) { return FaceAux{c->accel, c->mesh.volume, c->mesh.mesh_vel, c->n}; }
+static FaceAux face_aux(const mm_ctx *c) { return FaceAux{c->accel, c->n}; }
 
 // The face fluxes in entropy mode EM, face-major records into flux.
 template <int D, int EM, bool GRAV>
@@ -488,8 +491,8 @@ static mm_status fluxes_d(mm_ctx *c, const double *dt_dev, double dt, const void
     switch (c->p.entropy) {
         case MM_ENTROPY_MACH:
             return g ? fluxes_t<D, 1, true>(c, dt_dev, dt, rec, flux) : fluxes_t<D, 1, false>(c, dt_dev, dt, rec, flux);
-        case MM_ENTROPY_ENERGY:
-            return g ? fluxes_t<D, 2, true>(c, dt_dev, dt, rec, flux) : fluxes_t<D, 2, false>(c, dt_dev, dt, rec, flux);
+        case MM_ENTROPY_ENERGY:   // the same face records as the Mach switch
+            return g ? fluxes_t<D, 1, true>(c, dt_dev, dt, rec, flux) : fluxes_t<D, 1, false>(c, dt_dev, dt, rec, flux);
         default:
             return g ? fluxes_t<D, 0, true>(c, dt_dev, dt, rec, flux) : fluxes_t<D, 0, false>(c, dt_dev, dt, rec, flux);
     }
@@ -515,7 +518,7 @@ static UpdateArgs update_args(const mm_ctx *c) {
     const Layout &L = c->lay;
     return UpdateArgs{c->at<int32_t>(L.flags) + 1, c->mesh.volume, c->p.gamma, c->p.mach_thresh,
                       c->at<DiagDev>(L.diag), c->accel, c->last_dt_dev, c->last_dt, c->p.alpha_s, c->p.beta_s,
-                      c->mesh.mesh_vel};
+                      c->mesh.mesh_vel, L.ekmax >= 0 ? c->at<double>(L.ekmax) : nullptr};
 }
 
 // The update from face-major records.
@@ -536,6 +539,7 @@ template <int D> static void launch_update_d(mm_ctx *c, const double *flux, doub
 
 static mm_status update_into(mm_ctx *c, const double *flux, double *Q) {
     if (c->accel && !c->have_dt) return MM_E_STATE;   // the source terms need the flux pass's timestep
+    if (c->p.entropy == MM_ENTROPY_ENERGY && !c->have_ek) return MM_E_STATE;   // no gradient pass yet
     if (c->D == 3) launch_update_d<3>(c, flux, Q);
     else launch_update_d<2>(c, flux, Q);
     MM_LAUNCH_CHECK();
@@ -992,7 +996,7 @@ template <int D, typename T> static void tb_point(mm_ctx *c, double *Q, T *rec) 
         k_face_flux_hard<D, 0, false><<<kTbGrid, kBlock, 0, s>>>(
             c->mesh.face_L, c->mesh.face_R, c->at<float>(L.mrec), c->at<double>(L.wf64), (const float *)rec,
             (const float *)grad, nullptr, 0.0, kf.g, kg, c->p.newton_tol64, hard, fcap, flux, diag,
-            FaceAux{nullptr, nullptr, nullptr, c->n}, view);
+            FaceAux{nullptr, c->n}, view);
     }
     const TbSides sd{c->at<int32_t>(L.loff), c->at<int32_t>(L.roff), c->at<int32_t>(L.rface), c->mesh.face_L,
                      c->mesh.face_R};

@@ -478,7 +478,7 @@ def mm_riemann_batch_noalloc(states: torch.Tensor, out: torch.Tensor, iters: tor
 
 def flux_stride(dim: int, entropy: int = MM_ENTROPY_OFF) -> int:
     """MM_FLUX_STRIDE: doubles per face record of the face-flux array."""
-    return dim + 2 + (2 if entropy else 0) + (2 if entropy == MM_ENTROPY_ENERGY else 0)
+    return dim + 2 + (2 if entropy else 0)
 
 
 def recon_stride(dim: int) -> int:

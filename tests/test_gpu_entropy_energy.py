@@ -139,16 +139,18 @@ def test_gravity_condition_in_free_fall():
 
 def test_split_entry_points_equal_the_step():
     """mm_gradients, mm_face_fluxes and mm_apply_update equal mm_hydro_step
-    bit for bit in the energy mode: the face records carry each face's two
-    neighbour energies (MM_FLUX_STRIDE has two more doubles), the step's
-    fused face pass and update sum them in the same order."""
+    bit for bit in the energy mode (the update reads the neighbour energies
+    of the last gradient pass); an update before any gradient pass is
+    refused."""
     wl = random3d(n_side=12, seed=916)
     m = wl.mesh
     Q = with_entropy(wl)
     ctx = context(m, wl.gamma, wl.cfl, 0.05)
     F = ctx.flux_buffer(m.n_faces)
-    assert F.shape[1] == m.dim + 6
     Q2 = torch.from_numpy(Q.copy()).cuda()
+    with pytest.raises(mm.MMError) as e:
+        ctx.mm_apply_update(F, Q2)
+    assert e.value.status == mm.MM_E_STATE
     Q1 = torch.from_numpy(Q.copy()).cuda()
     dt = ctx.mm_hydro_step(Q1)
     rec = ctx.recon_buffer(m.n_cells)
