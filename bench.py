@@ -335,8 +335,8 @@ def bench_step(args):
     achieved = nbytes / (head["flux_ms"] * 1e-3) / 1e9
     lrn = 'true' if args.mode.endswith('learned') else 'false'
     grv = 'true' if wl.accel is not None else 'false'
-    kname = (f"k_face_flux_mixed<{m.dim}, {lrn}, false, {grv}>" if mixed
-             else f"k_face_flux64<{m.dim}, {lrn}, false, {grv}>")
+    kname = (f"k_face_flux_mixed<{m.dim}, {lrn}, 0, {grv}>" if mixed
+             else f"k_face_flux64<{m.dim}, {lrn}, 0, {grv}>")
     from paper_0901_4107_amd.prof_summary import read_traffic
     traffic = read_traffic(os.path.join(ROOT, "profiles"), kname, wl.name)
     out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

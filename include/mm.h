@@ -17,7 +17,7 @@
  * - Face fluxes are double, face-major: face_flux[f*FS + c] =
  *   dt * A_f * Fhat_c(f), c over (mass, momentum (D), energy), FS =
  *   MM_FLUX_STRIDE(D, entropy) (with the entropy row, then the entropy
- *   flux and the face's shock Mach number).
+ *   flux, and with MM_ENTROPY_MACH the face's shock Mach number).
  * - The reconstruction buffer (mm_gradients' output) holds
  *   MM_RECON_STRIDE(D) elements per cell (24 in 3D, 16 in 2D) as two
  *   blocks:
@@ -122,12 +122,15 @@ typedef struct {
 } mm_params;
 
 /* Doubles per face record of the face-flux array: the D+2 fluxes
- * dt A Fhat, then with the entropy row the entropy flux dt A m_F A_U and
- * the face's Mach number: the larger over its sides of
+ * dt A Fhat, then with the entropy row the entropy flux dt A m_F A_U, and
+ * with MM_ENTROPY_MACH (whose switch reads it; MM_ENTROPY_ENERGY's does
+ * not, and its records end after the entropy flux) the face's Mach number:
+ * the larger over its sides of
  * sqrt((g+1)/(2g) p* / p_K + (g-1)/(2g)), the Mach number of the shock into
  * side K where p* > p_K and below 1 on a rarefied side; 0 without a star
  * state. */
-#define MM_FLUX_STRIDE(dim, entropy) ((dim) + 2 + ((entropy) ? 2 : 0))
+#define MM_FLUX_STRIDE(dim, entropy) \
+    ((dim) + 2 + ((entropy) == MM_ENTROPY_MACH ? 2 : ((entropy) == MM_ENTROPY_ENERGY ? 1 : 0)))
 
 /* The given tessellation (Section 3, step list item (i)) and the generator
  * velocities w_i (item (iv)). All device pointers, all kept by reference

@@ -290,16 +290,17 @@ __device__ __forceinline__ void limit_side(const T *g, const T *dl, const T (&gr
 // j's values pj as the gradient pass reads them: double primitive records
 // hold v_j (wi = w_i); float gather records hold v_j - w_j and w_j - W0
 // (wi: cell i's w_i - W0), so v_j - w_i = (v_j - w_j) + [(w_j - W0) - (w_i - W0)].
+// In the records' precision: the float form's velocities carry float
+// rounding already, and the switch compares this with the cell's thermal
+// energy at a threshold alpha far above it.
 template <int D, typename T>
-__device__ __forceinline__ double ekin_in_frame(const T *pj, const T *wi, double Vj, const double (&wlab)[D]) {
-    double e = 0.0;
+__device__ __forceinline__ T ekin_in_frame(const T *pj, const T *wi, double Vj, const double (&wlab)[D]) {
+    T e = (T)0;
     for (int k = 0; k < D; k++) {
-        const double dv = sizeof(T) == 4
-                              ? (double)pj[1 + k] + ((double)pj[Lay<D>::GW + k] - (double)wi[Lay<D>::GW + k])
-                              : (double)pj[1 + k] - wlab[k];
+        const T dv = sizeof(T) == 4 ? pj[1 + k] + (pj[Lay<D>::GW + k] - wi[Lay<D>::GW + k]) : pj[1 + k] - (T)wlab[k];
         e += dv * dv;
     }
-    return pj[0] > (T)0 ? 0.5 * ((double)pj[0] * Vj) * e : 0.0;
+    return pj[0] > (T)0 ? (T)0.5 * (pj[0] * (T)Vj) * e : (T)0;
 }
 
 // The gradient and limiter of cell i by its lane group (lane = index in
@@ -324,11 +325,20 @@ __device__ __forceinline__ void load_nb(const T *__restrict__ nrec, int64_t j, i
     if constexpr (sizeof(T) == 4) {
         const int64_t k = j - c0;
         if (win && k >= 0 && k < kGWin) {
-            load_rec<NJ>((const T *)win + k * NJ, o);
+            load_rec_lds<NJ>((lds_cfloat *)win + k * NJ, o);
             return;
         }
     }
     load_rec<NJ>(nrec + j * NSs, o);
+}
+
+// The volume of neighbour j (energy switch): from the window's volumes vwin
+// when it holds j, else from V.
+__device__ __forceinline__ double nb_vol(const double *__restrict__ V, int64_t j, const double *vwin, int64_t c0) {
+    typedef __attribute__((address_space(3))) const double lds_cdouble;
+    const int64_t k = j - c0;
+    if (vwin && k >= 0 && k < kGWin) return ((lds_cdouble *)vwin)[k];
+    return V[j];
 }
 
 template <int D, typename T, bool ESW = false>
@@ -338,12 +348,12 @@ __device__ __forceinline__ void grad_cell(int64_t i, int lane, const int32_t *__
                                           const float *__restrict__ gath, T *__restrict__ grad_out,
                                           const double *__restrict__ mvel = nullptr, int64_t n = 0,
                                           double *__restrict__ ekmax = nullptr, const float *win = nullptr,
-                                          int64_t c0 = 0) {
+                                          int64_t c0 = 0, const double *vwin = nullptr) {
     using Y = Lay<D>;
     constexpr int NV = D + 2;
     constexpr int GS = Group<D>::GS;
     constexpr bool mixed = sizeof(T) == 4;
-    constexpr int KR = mixed ? 5 : 3;   // sides per lane held in registers
+    constexpr int KR = mixed ? (ESW ? 3 : 4) : 3;   // sides per lane held in registers
     constexpr int SR = mixed ? Y::SREC32 : Y::SREC64;
     constexpr int NJ = mixed ? Y::GATH : NV;   // values read of a neighbour
     const T eps_t = mixed ? (T)1e-6 : (T)1e-13;
@@ -354,13 +364,16 @@ __device__ __forceinline__ void grad_cell(int64_t i, int lane, const int32_t *__
     // the neighbours' records, all in flight together (an absent side reads
     // record 0 of the arrays and is skipped)
     T sr[KR][SR], pj[KR][NJ];
+    double vj[KR];
     bool has[KR];
     for (int r = 0; r < KR; r++) {
         const int32_t q = b + lane + r * GS;
         has[r] = q < e;
         const int32_t qq = has[r] ? q : 0;
         load_rec<SR>(srec + (int64_t)qq * SR, sr[r]);
-        load_nb<D, T>(nrec, nbr[qq], NS, win, c0, pj[r]);
+        const int32_t jn = nbr[qq];
+        load_nb<D, T>(nrec, jn, NS, win, c0, pj[r]);
+        if constexpr (ESW) vj[r] = nb_vol(V, jn, vwin, c0);
     }
     T pi[Y::PREC], wi[NJ];
     load_rec<Y::PREC>(prim + i * Y::PREC, pi);
@@ -372,13 +385,14 @@ __device__ __forceinline__ void grad_cell(int64_t i, int lane, const int32_t *__
         a.dmn[c] = (T)0;
         for (int k = 0; k < D; k++) a.acc[c][k] = (T)0;
     }
-    double wlab[D], ek = 0.0;
+    double wlab[D];
+    T ek = (T)0;
     if constexpr (ESW)
         for (int k = 0; k < D; k++) wlab[k] = mixed ? 0.0 : mvel[k * n + i];
     for (int r = 0; r < KR; r++)
         if (has[r]) {
             grad_side<D, T, mixed>(sr[r], pj[r], wi, a);
-            if constexpr (ESW) ek = fmax(ek, ekin_in_frame<D, T>(pj[r], wi, V[nbr[b + lane + r * GS]], wlab));
+            if constexpr (ESW) ek = fmax(ek, ekin_in_frame<D, T>(pj[r], wi, vj[r], wlab));
         }
     for (int32_t q = b + lane + KR * GS; q < e; q += GS) {
         T s2[SR], p2[NJ];
@@ -386,11 +400,11 @@ __device__ __forceinline__ void grad_cell(int64_t i, int lane, const int32_t *__
         const int32_t j = nbr[q];
         load_nb<D, T>(nrec, j, NS, win, c0, p2);
         grad_side<D, T, mixed>(s2, p2, wi, a);
-        if constexpr (ESW) ek = fmax(ek, ekin_in_frame<D, T>(p2, wi, V[j], wlab));
+        if constexpr (ESW) ek = fmax(ek, ekin_in_frame<D, T>(p2, wi, nb_vol(V, j, vwin, c0), wlab));
     }
     if constexpr (ESW) {
         ek = grp_max<GS>(ek);
-        if (lane == 0) ekmax[i] = ek;
+        if (lane == 0) ekmax[i] = (double)ek;
     }
     const T inv_v = (T)(1.0 / V[i]);
     T grad[NV][D], dmx[NV], dmn[NV];
@@ -434,11 +448,13 @@ __device__ __forceinline__ void grad_cell(int64_t i, int lane, const int32_t *__
 
 // The gather-bound gradient kernels gain from one more wavefront per SIMD
 // than the register count the compiler picks on its own (5 float / 4 double,
-// about 7-9% faster; the 3D double kernel spills a few bytes per lane); with
-// the energy switch's neighbour energies one fewer (4 float, 3 double),
-// where they do not spill.
+// about 7-9% faster; the 3D double kernel spills a few bytes per lane). The
+// float kernels hold 4 sides per lane in registers, 3 with the energy
+// switch's neighbour energies, which keeps both at 5 without spills (a spill
+// of 32 bytes per lane cost the float kernel about 20%); the double kernel
+// with the switch runs at 3.
 template <int D, typename T, bool ESW>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? (ESW ? 4 : 5) : (ESW ? 3 : 4))))
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : (ESW ? 3 : 4))))
 k_grad_limit(int64_t n, const int32_t *__restrict__ off, const int32_t *__restrict__ nbr, const T *__restrict__ srec,
              const double *__restrict__ V, const T *__restrict__ prim, const float *__restrict__ gath,
              T *__restrict__ grad_out, const double *__restrict__ mvel, double *__restrict__ ekmax) {
@@ -447,6 +463,7 @@ k_grad_limit(int64_t n, const int32_t *__restrict__ off, const int32_t *__restri
     // mixed mode: stage the window (every lane takes part in the copy and the
     // barrier before any group leaves)
     const float *win = nullptr;
+    const double *vwin = nullptr;
     int64_t c0 = 0;
     if constexpr (sizeof(T) == 4) {
         __shared__ float wbuf[kGWin * Lay<D>::GATH];
@@ -457,11 +474,20 @@ k_grad_limit(int64_t n, const int32_t *__restrict__ off, const int32_t *__restri
             if (j >= 0 && j < n) v = *reinterpret_cast<const f32x4u *>(gath + j * Lay<D>::GATH + (e % (Lay<D>::GATH / 4)) * 4);
             *reinterpret_cast<f32x4u *>(wbuf + e * 4) = v;
         }
+        if constexpr (ESW) {   // and the window's volumes
+            __shared__ double vbuf[kGWin];
+            for (int e = threadIdx.x; e < kGWin; e += kBlock) {
+                const int64_t j = c0 + e;
+                vbuf[e] = (j >= 0 && j < n) ? V[j] : 0.0;
+            }
+            vwin = vbuf;
+        }
         __syncthreads();
         win = wbuf;
     }
     if (i >= n) return;  // whole groups leave together
-    grad_cell<D, T, ESW>(i, threadIdx.x % GS, off, nbr, srec, V, prim, gath, grad_out, mvel, n, ekmax, win, c0);
+    grad_cell<D, T, ESW>(i, threadIdx.x % GS, off, nbr, srec, V, prim, gath, grad_out, mvel, n, ekmax, win, c0,
+                         vwin);
 }
 
 // The total entropy of every cell from its conserved state (Section 3.5):

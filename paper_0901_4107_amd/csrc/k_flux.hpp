@@ -136,9 +136,9 @@ __device__ __forceinline__ CellRec<D, float> load_cell_w(const float *__restrict
     const int64_t k = i - w.c0;
     if (w.buf && k >= 0 && k < kWin) {
         CellRec<D, float> c;
-        const float *r = w.buf + k * RF;
-        load_rec<Lay<D>::PREC>(r, c.p);
-        load_rec<Lay<D>::GREC>(r + Lay<D>::PREC, c.g);
+        lds_cfloat *r = (lds_cfloat *)w.buf + k * RF;
+        load_rec_lds<Lay<D>::PREC>(r, c.p);
+        load_rec_lds<Lay<D>::GREC>(r + Lay<D>::PREC, c.g);
         return c;
     }
     return load_cell<D>(prim, grad, i);
@@ -264,14 +264,20 @@ template <typename T> __device__ __forceinline__ T no_guess() { return (T)__buil
 template <typename T>
 __device__ __forceinline__ bool wants_learned(T rhoL, T uL, T PL, T rhoR, T uR, T PR, T gamma) {
     if (!(rhoL > (T)0 && PL > (T)0 && rhoR > (T)0 && PR > (T)0)) return false;
-    const T cL = mm_sqrt(gamma * PL / rhoL), cR = mm_sqrt(gamma * PR / rhoR);
-    const T du = uR - uL;
-    if (!(cL + cR - (T)0.5 * (gamma - (T)1) * du > (T)0)) return false;
     const T pmin = PL < PR ? PL : PR, pmax = PL < PR ? PR : PL;
     const T rmin = rhoL < rhoR ? rhoL : rhoR, rmax = rhoL < rhoR ? rhoR : rhoL;
+    const bool ratio = rmax >= (T)kMlpGateRatio * rmin || pmax >= (T)kMlpGateRatio * pmin;
+    const T cL2 = gamma * PL / rhoL, cR2 = gamma * PR / rhoR;
+    const T du = uR - uL;
+    // a mild problem leaves before any root: without a strong ratio the jump
+    // must reach kMlpGateDu (c_L + c_R) >= kMlpGateDu sqrt(c_L^2 + c_R^2); the
+    // margin 0.99 keeps this test from rejecting a face the exact one below
+    // would accept
+    if (!ratio && du * du < (T)(0.99 * kMlpGateDu * kMlpGateDu) * (cL2 + cR2)) return false;
+    const T cL = mm_sqrt(cL2), cR = mm_sqrt(cR2);
+    if (!(cL + cR - (T)0.5 * (gamma - (T)1) * du > (T)0)) return false;
     const T adu = du < (T)0 ? -du : du;
-    if (!(rmax >= (T)kMlpGateRatio * rmin || pmax >= (T)kMlpGateRatio * pmin || adu >= (T)kMlpGateDu * (cL + cR)))
-        return false;
+    if (!(ratio || adu >= (T)kMlpGateDu * (cL + cR))) return false;
     const T ppv = (T)0.5 * (PL + PR) - (T)0.125 * du * (rhoL + rhoR) * (cL + cR);
     if (pmax <= (T)2 * pmin && ppv >= pmin && ppv <= pmax) return false;
     if (ppv < pmin) {
@@ -415,7 +421,8 @@ __device__ __forceinline__ void entropy_terms(const FaceState<T> &fs, T rhoL, T 
 }
 
 // A face's values besides its D + 2 fluxes (EM the entropy mode): the
-// entropy flux and the Mach number (EM >= 1).
+// entropy flux (EM >= 1) and the Mach number (EM == 1; the energy switch
+// does not read it, and its record ends before it).
 struct FaceX {
     double v[2];
 };
@@ -669,7 +676,8 @@ template <int D> constexpr int stash_floats() { return (2 * (D + 2) + D + 1) * k
 // of the face kernel. Every thread of the block calls it (the learned staging holds
 // barriers); active = false does no face. While the network runs, the face
 // states wait in LDS (stash: (2(D+2) + D + 1) kBlock floats), so the
-// network's registers come on top of few live values.
+// network's registers come on top of few live values. once: the kernel calls
+// this once per thread (no barrier for a next call).
 template <int D, bool LEARNED, int EM, bool GRAV>
 __device__ __forceinline__ void face_flux_mixed(bool active, int64_t f, const int32_t *__restrict__ fL,
                                                 const int32_t *__restrict__ fR, const float *__restrict__ mrec,
@@ -678,7 +686,7 @@ __device__ __forceinline__ void face_flux_mixed(bool active, int64_t f, const in
                                                 const GasConst<float> &kf, double g_over_gm1, float tol32, int maxit,
                                                 const MlpPacked *mlp, const FaceAux &aux, float *stash,
                                                 LaneDiag &ld, bool &hard, double (&F)[D + 2], FaceX &X,
-                                                const Window &win = Window{nullptr, 0}) {
+                                                const Window &win = Window{nullptr, 0}, bool once = false) {
     constexpr int NV = D + 2;
     hard = false;
     MixedFace<D> m;
@@ -713,7 +721,8 @@ __device__ __forceinline__ void face_flux_mixed(bool active, int64_t f, const in
             for (int k = 0; k < D; k++) { m.uL += m.xl[1 + k] * m.nrm[k]; m.uR += m.xr[1 + k] * m.nrm[k]; }
         }
         // every thread has read the staging before a next call rewrites it
-        if (mlp) __syncthreads();
+        // (once: the kernel makes no next call)
+        if (mlp && !once) __syncthreads();
     }
     if (active) {
         FaceState<float> fs = solve_face<float>(m.xl[0], m.uL, m.xl[NV - 1], m.xr[0], m.uR, m.xr[NV - 1], kf, tol32,
@@ -760,7 +769,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))
     double F[NV];
     FaceX X;
     face_flux_mixed<D, LEARNED, EM, GRAV>(active, f, fL, fR, mrec, wf64, prim, grad, dt, 0.5 * dt, 0.5 * dt, kf,
-                                          g_over_gm1, tol32, maxit, mlp, aux, stash, ld, hard, F, X, win);
+                                          g_over_gm1, tol32, maxit, mlp, aux, stash, ld, hard, F, X, win, true);
     if (active && !hard) store_face<D, EM>(flux + f * Rec<D, EM>::FM, F, X);
     list_append(hard_list, cap, hard, (int32_t)f);
     if (diag) flush_diag(ld, diag);

@@ -14,9 +14,9 @@
 //
 // Records (face-major, written by the face kernels). EM is the entropy
 // mode (0 off, 1 Mach switch, 2 energy switch). A face's values: the D + 2
-// fluxes, then (EM >= 1) the entropy flux and the face's shock Mach number.
-// The energy switch's neighbour energies come from the gradient pass
-// (ekmax, one per cell).
+// fluxes, then (EM >= 1) the entropy flux, then (EM == 1) the face's shock
+// Mach number. The energy switch's neighbour energies come from the
+// gradient pass (ekmax, one per cell).
 #pragma once
 
 #include "common.hpp"
@@ -27,9 +27,9 @@ namespace mm {
 
 template <int D, int EM> struct Rec {
     static constexpr int NV = D + 2;
-    static constexpr int NS = NV + (EM ? 1 : 0);   // summed values
-    static constexpr int MACH = NV + 1;            // a maximum
-    static constexpr int FM = NV + (EM ? 2 : 0);   // record stride
+    static constexpr int NS = NV + (EM ? 1 : 0);                      // summed values
+    static constexpr int MACH = NV + 1;                               // a maximum (EM == 1)
+    static constexpr int FM = NV + (EM == 1 ? 2 : (EM == 2 ? 1 : 0)); // record stride
 };
 
 // What the end of a cell's update needs besides the sums.
@@ -181,7 +181,7 @@ __device__ __forceinline__ void cell_sums(int64_t i, int lane, const int32_t *__
     }
     auto take = [&](const double *F, double sign) {
         for (int c = 0; c < NS; c++) acc[c] += sign * F[c];
-        if constexpr (EM != 0) mx = fmax(mx, F[RC::MACH]);
+        if constexpr (EM == 1) mx = fmax(mx, F[RC::MACH]);
     };
     for (int r = 0; r < KL; r++)
         if (hl[r]) take(FLr[r], -1.0);
@@ -201,16 +201,17 @@ __device__ __forceinline__ void cell_sums(int64_t i, int lane, const int32_t *__
         take(F, 1.0);
     }
     for (int c = 0; c < NS; c++) acc[c] = grp_sum<GS>(acc[c]);
-    if constexpr (EM != 0) mx = grp_max<GS>(mx);
+    if constexpr (EM == 1) mx = grp_max<GS>(mx);
 }
 
-// The update (the step, mm_apply_update): one lane group per cell.
+// The update (the step, mm_apply_update): one lane group per cell. It waits
+// on its gathers, so it runs at the most wavefronts per SIMD its registers
+// allow without spills (with the energy switch the compiler alone would
+// take 5 where 7 fit).
 template <int D, int EM, bool GRAV>
-__global__ void __launch_bounds__(kBlock) k_update(int64_t n, const int32_t *__restrict__ lOff,
-                                                   const int32_t *__restrict__ rOff,
-                                                   const int32_t *__restrict__ rFace,
-                                                   const double *__restrict__ flux, double *__restrict__ Q,
-                                                   UpdateArgs u) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(EM == 1 ? 6 : (EM == 2 ? 7 : 8))))
+k_update(int64_t n, const int32_t *__restrict__ lOff, const int32_t *__restrict__ rOff,
+         const int32_t *__restrict__ rFace, const double *__restrict__ flux, double *__restrict__ Q, UpdateArgs u) {
     using RC = Rec<D, EM>;
     constexpr int GS = Group<D>::GS;
     const int lane = threadIdx.x % GS;

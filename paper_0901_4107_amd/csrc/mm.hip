@@ -70,7 +70,7 @@ struct Layout {
 // em: the entropy mode (0 off, MM_ENTROPY_MACH, MM_ENTROPY_ENERGY).
 Layout make_layout(int D, int mode, int em, bool tb, int64_t n, int64_t nf) {
     const int NV = D + 2;
-    const int FM = NV + (em ? 2 : 0);   // Rec<D, em>::FM
+    const int FM = NV + (em == MM_ENTROPY_MACH ? 2 : (em ? 1 : 0));   // Rec<D, em>::FM
     const int REC = (D == 3) ? Lay<3>::REC : Lay<2>::REC;
     const int FREC = (D == 3) ? Lay<3>::FREC : Lay<2>::FREC;
     const int WS = (D == 3) ? Lay<3>::WSTRIDE : Lay<2>::WSTRIDE;
@@ -491,8 +491,8 @@ static mm_status fluxes_d(mm_ctx *c, const double *dt_dev, double dt, const void
     switch (c->p.entropy) {
         case MM_ENTROPY_MACH:
             return g ? fluxes_t<D, 1, true>(c, dt_dev, dt, rec, flux) : fluxes_t<D, 1, false>(c, dt_dev, dt, rec, flux);
-        case MM_ENTROPY_ENERGY:   // the same face records as the Mach switch
-            return g ? fluxes_t<D, 1, true>(c, dt_dev, dt, rec, flux) : fluxes_t<D, 1, false>(c, dt_dev, dt, rec, flux);
+        case MM_ENTROPY_ENERGY:   // the entropy flux without the Mach number
+            return g ? fluxes_t<D, 2, true>(c, dt_dev, dt, rec, flux) : fluxes_t<D, 2, false>(c, dt_dev, dt, rec, flux);
         default:
             return g ? fluxes_t<D, 0, true>(c, dt_dev, dt, rec, flux) : fluxes_t<D, 0, false>(c, dt_dev, dt, rec, flux);
     }

@@ -410,7 +410,8 @@ class Context:
 
     def flux_buffer(self, n_faces: int):
         """Face fluxes [F][MM_FLUX_STRIDE] (double): D+2 fluxes, then with the
-        entropy row the entropy flux and the face's shock Mach number."""
+        entropy row the entropy flux, and with the Mach switch the face's shock
+        Mach number."""
         return torch.empty((n_faces, flux_stride(self.dim, self.entropy)), dtype=torch.float64, device=self.device)
 
 
@@ -478,7 +479,7 @@ def mm_riemann_batch_noalloc(states: torch.Tensor, out: torch.Tensor, iters: tor
 
 def flux_stride(dim: int, entropy: int = MM_ENTROPY_OFF) -> int:
     """MM_FLUX_STRIDE: doubles per face record of the face-flux array."""
-    return dim + 2 + (2 if entropy else 0)
+    return dim + 2 + {MM_ENTROPY_MACH: 2, MM_ENTROPY_ENERGY: 1}.get(entropy, 0)
 
 
 def recon_stride(dim: int) -> int:

@@ -4,6 +4,10 @@ kept with the library.
     python -m paper_0901_4107_amd.prof_summary trace DIR
         per-kernel calls, average and total duration from a --kernel-trace run
 
+    python -m paper_0901_4107_amd.prof_summary counters DIR [--kernel NAME]
+        per-kernel averages of every counter of a --pmc run (dispatches of
+        the kernels whose name contains NAME, default every mm:: kernel)
+
     python -m paper_0901_4107_amd.prof_summary traffic --kernel NAME --workload W \\
         --fetch DIR --write DIR --copy-fetch DIR --copy-write DIR
         HBM bytes per launch of the kernels whose name contains NAME, from a
@@ -55,6 +59,20 @@ def counter_kib(path: str, counter: str, kernel: str) -> list[float]:
     return [v for name, v in rows if kernel in _short(name)]
 
 
+def counters(path: str, kernel: str = "mm::") -> str:
+    c = _db(path)
+    agg = defaultdict(lambda: defaultdict(list))
+    for name, counter, v in c.execute("select kernel_name, counter_name, value from counters_collection"):
+        if kernel in name:
+            agg[_short(name)][counter].append(v)
+    lines = []
+    for k in sorted(agg):
+        vals = " ".join(f"{cn}={sum(v) / len(v):.0f}" for cn, v in sorted(agg[k].items()))
+        n = max(len(v) for v in agg[k].values())
+        lines.append(f"{k} dispatches={n} {vals}")
+    return "\n".join(lines)
+
+
 def traffic(a) -> str:
     copy_bytes = a.copy_mib * (1 << 20)
     fk = counter_kib(a.copy_fetch, "FETCH_SIZE", a.copy_kernel)
@@ -98,6 +116,9 @@ def main():
     sub = ap.add_subparsers(dest="cmd", required=True)
     t = sub.add_parser("trace")
     t.add_argument("dir")
+    q = sub.add_parser("counters")
+    q.add_argument("dir")
+    q.add_argument("--kernel", default="mm::")
     r = sub.add_parser("traffic")
     r.add_argument("--kernel", required=True)
     r.add_argument("--workload", required=True)
@@ -108,7 +129,12 @@ def main():
     r.add_argument("--copy-mib", type=int, default=1024)
     r.add_argument("--copy-kernel", default="copyBuffer")
     a = ap.parse_args()
-    print(trace(a.dir) if a.cmd == "trace" else traffic(a))
+    if a.cmd == "trace":
+        print(trace(a.dir))
+    elif a.cmd == "counters":
+        print(counters(a.dir, a.kernel))
+    else:
+        print(traffic(a))
 
 
 if __name__ == "__main__":
