@@ -563,7 +563,8 @@ __global__ void __launch_bounds__(kBlock) k_mesh_velocity(int64_t n, const doubl
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_volume_rate(int64_t n, const int32_t *__restrict__ off,
                                                         const int32_t *__restrict__ ent,
-                                                        const double *__restrict__ frec, double *__restrict__ rate) {
+                                                        const double *__restrict__ frec,
+                                                        const double *__restrict__ wf64, double *__restrict__ rate) {
     using Y = Lay<D>;
     constexpr int GS = Group<D>::GS;
     const int lane = threadIdx.x % GS;
@@ -572,10 +573,11 @@ __global__ void __launch_bounds__(kBlock) k_volume_rate(int64_t n, const int32_t
     double acc = 0.0;
     for (int32_t q = off[i] + lane; q < off[i + 1]; q += GS) {
         const int32_t en = ent[q];
-        double fr[Y::FREC];
+        double fr[Y::FREC], w[D];
         load_rec<Y::FREC>(frec + (int64_t)(en >> 1) * Y::FREC, fr);
+        load_rec<Y::WSTRIDE>(wf64 + (int64_t)(en >> 1) * Y::WSTRIDE, w);
         double wn = 0.0;
-        for (int k = 0; k < D; k++) wn += fr[Y::FW + k] * fr[Y::FN + k];
+        for (int k = 0; k < D; k++) wn += w[k] * fr[Y::FN + k];
         acc += ((en & 1) ? -1.0 : 1.0) * fr[Y::FA] * wn;
     }
     acc = grp_sum<GS>(acc);

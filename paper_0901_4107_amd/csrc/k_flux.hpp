@@ -502,7 +502,7 @@ struct FaceAux {
 template <int D, bool LEARNED, int EM, bool GRAV>
 __device__ __forceinline__ void face_flux64(bool active, int64_t f, const int32_t *__restrict__ fL,
                                             const int32_t *__restrict__ fR, const double *__restrict__ frec,
-                                            const double *__restrict__ prim, const double *__restrict__ grad,
+                                            const double *__restrict__ wf64, const double *__restrict__ prim, const double *__restrict__ grad,
                                             double dt, double hdtL, double hdtR, const GasConst<double> &kg,
                                             double tol, int maxit, const MlpPacked *mlp, const FaceAux &aux,
                                             LaneDiag &ld, double (&F)[D + 2], FaceX &X) {
@@ -513,6 +513,7 @@ __device__ __forceinline__ void face_flux64(bool active, int64_t f, const int32_
     if (active) {
         double fr[Y::FREC];
         load_rec<Y::FREC>(frec + f * Y::FREC, fr);
+        load_rec<Y::WSTRIDE>(wf64 + f * Y::WSTRIDE, w);
         const int64_t l = fL[f], r = fR[f];
         const CellRec<D, double> rl = load_cell<D>(prim, grad, l);
         const CellRec<D, double> rr = load_cell<D>(prim, grad, r);
@@ -521,7 +522,6 @@ __device__ __forceinline__ void face_flux64(bool active, int64_t f, const int32_
         double gL[D], gR[D];
         for (int k = 0; k < D; k++) {
             nrm[k] = fr[Y::FN + k];
-            w[k] = fr[Y::FW + k];
             const double c = fr[Y::FC + k];
             gL[k] = c + hl * nrm[k];   // f - r_L
             gR[k] = c - hl * nrm[k];   // f - r_R
@@ -571,7 +571,7 @@ __device__ __forceinline__ void face_flux64(bool active, int64_t f, const int32_
 // face-major (Rec<D, EM>::FM values per face).
 template <int D, bool LEARNED, int EM, bool GRAV>
 __global__ void __launch_bounds__(kBlock) k_face_flux64(int64_t nf, const int32_t *__restrict__ fL,
-                                                        const int32_t *__restrict__ fR, const double *__restrict__ frec,
+                                                        const int32_t *__restrict__ fR, const double *__restrict__ frec, const double *__restrict__ wf64,
                                                         const double *__restrict__ prim, const double *__restrict__ grad,
                                                         const double *__restrict__ dt_ptr, double dt_val,
                                                         GasConst<double> kg, double tol, int maxit,
@@ -584,7 +584,7 @@ __global__ void __launch_bounds__(kBlock) k_face_flux64(int64_t nf, const int32_
     const double dt = dt_ptr ? *dt_ptr : dt_val;
     double F[NV];
     FaceX X;
-    face_flux64<D, LEARNED, EM, GRAV>(active, f, fL, fR, frec, prim, grad, dt, 0.5 * dt, 0.5 * dt, kg, tol, maxit,
+    face_flux64<D, LEARNED, EM, GRAV>(active, f, fL, fR, frec, wf64, prim, grad, dt, 0.5 * dt, 0.5 * dt, kg, tol, maxit,
                                       mlp, aux, ld, F, X);
     if (active) store_face<D, EM>(flux + f * Rec<D, EM>::FM, F, X);
     if (diag) flush_diag(ld, diag);
@@ -842,7 +842,7 @@ template <int D, bool LEARNED>
 __global__ void __launch_bounds__(kBlock) k_face_flux64_list(const int32_t *__restrict__ list, int64_t cap,
                                                              const int32_t *__restrict__ fL,
                                                              const int32_t *__restrict__ fR,
-                                                             const double *__restrict__ frec,
+                                                             const double *__restrict__ frec, const double *__restrict__ wf64,
                                                              const double *__restrict__ prim,
                                                              const double *__restrict__ grad, TbView tb,
                                                              GasConst<double> kg, double tol, int maxit,
@@ -863,7 +863,7 @@ __global__ void __launch_bounds__(kBlock) k_face_flux64_list(const int32_t *__re
         if (active) tb.face(fL[f], fR[f], fdt, hl, hr);
         double F[NV];
         FaceX X;
-        face_flux64<D, LEARNED, 0, false>(active, f, fL, fR, frec, prim, grad, fdt, hl, hr, kg, tol, maxit, mlp,
+        face_flux64<D, LEARNED, 0, false>(active, f, fL, fR, frec, wf64, prim, grad, fdt, hl, hr, kg, tol, maxit, mlp,
                                           FaceAux{nullptr, 0}, ld, F, X);
         if (active) store_face<D, 0>(flux + f * NV, F, X);
     }

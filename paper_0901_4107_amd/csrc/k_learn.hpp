@@ -269,6 +269,7 @@ template <int D>
 __global__ void __launch_bounds__(kBlock) k_face_states64(int64_t nf, const int32_t *__restrict__ fL,
                                                           const int32_t *__restrict__ fR,
                                                           const double *__restrict__ frec,
+                                                          const double *__restrict__ wf64,
                                                           const double *__restrict__ prim,
                                                           const double *__restrict__ grad, double dt, double gamma,
                                                           float *__restrict__ out) {
@@ -276,13 +277,13 @@ __global__ void __launch_bounds__(kBlock) k_face_states64(int64_t nf, const int3
     constexpr int NV = D + 2;
     const int64_t f = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (f >= nf) return;
-    double fr[Y::FREC];
+    double fr[Y::FREC], w[D];
     load_rec<Y::FREC>(frec + f * Y::FREC, fr);
+    load_rec<Y::WSTRIDE>(wf64 + f * Y::WSTRIDE, w);
     const double hl = 0.5 * fr[Y::FELL];
-    double nrm[D], w[D], gL[D], gR[D];
+    double nrm[D], gL[D], gR[D];
     for (int k = 0; k < D; k++) {
         nrm[k] = fr[Y::FN + k];
-        w[k] = fr[Y::FW + k];
         gL[k] = fr[Y::FC + k] + hl * nrm[k];
         gR[k] = fr[Y::FC + k] - hl * nrm[k];
     }

@@ -1,7 +1,7 @@
 // k_mesh.hpp -- device side of mm_mesh_upload: validation, each cell's left
-// face range and sorted right faces, the per-cell side lists of the
-// gradient pass (left faces then right faces), the face geometry and the
-// face velocities.
+// face range and sorted right faces, the face geometry and face velocities
+// with the per-cell side lists of the gradient pass (left faces then right
+// faces) written face by face, and the cells' closure test.
 #pragma once
 
 #include "common.hpp"
@@ -136,9 +136,9 @@ __global__ void k_place_right(int64_t nf, const int32_t *__restrict__ R, int32_t
 
 // Each cell's right faces in ascending face order, one thread per cell: up
 // to 16 in registers through a bitonic sorting network, longer lists
-// (rare) by insertion in memory.
+// (rare) by insertion in memory. pos[f] = the slot of face f in rface.
 __global__ void __launch_bounds__(kBlock) k_sort_right(int64_t n, const int32_t *__restrict__ roff,
-                                                       int32_t *__restrict__ rface) {
+                                                       int32_t *__restrict__ rface, int32_t *__restrict__ pos) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     const int32_t b = roff[i], m = roff[i + 1] - b;
@@ -161,7 +161,10 @@ __global__ void __launch_bounds__(kBlock) k_sort_right(int64_t n, const int32_t 
                 }
 #pragma unroll
         for (int j = 0; j < 16; j++)
-            if (j < m) rface[b + j] = k[j];
+            if (j < m) {
+                rface[b + j] = k[j];
+                pos[k[j]] = b + j;
+            }
     } else {
         for (int32_t a = b + 1; a < b + m; a++) {
             const int32_t key = rface[a];
@@ -172,20 +175,34 @@ __global__ void __launch_bounds__(kBlock) k_sort_right(int64_t n, const int32_t 
             }
             rface[j + 1] = key;
         }
+        for (int32_t a = b; a < b + m; a++) pos[rface[a]] = a;
     }
 }
+
+// Where the gradient pass's side lists put a face (each cell's left faces
+// in face order, then its right faces in face order): its left side at
+// f + roff[L], its right side at loff[R + 1] + pos[f] (pos from
+// k_sort_right); per side ent = face << 1 | is_right, the neighbour, and
+// the side record A/|d|, f - r_i = c +- (|d|/2) n (double or float).
+struct SideOut {
+    const int32_t *loff, *roff, *pos;
+    int32_t *ent, *nbr;
+    double *srec;    // double path, or
+    float *srec32;   // mixed path
+};
 
 // Face records (Section 3.3 geometry and face velocity):
 //   n = d/|d|, c = f - (r_L + r_R)/2 = g - d/2,
 //   w_f = (w_L + w_R)/2 + [(w_L - w_R) . c / |d|] n.
-// The double record always; the mixed record (float geometry, the
-// generators' velocities relative to the face) and the double face velocity
-// when mixed != 0.
+// The double geometry record and the face velocity always; the mixed
+// record (float geometry, the generators' velocities relative to the face)
+// when mixed != 0; with so.ent (the upload, not a change of velocities)
+// also the face's two side records.
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_face_records(int64_t n, int64_t nf, const int32_t *L, const int32_t *R,
                                                          const double *area, const double *ctr, const double *sep,
                                                          const double *mvel, double *frec, int mixed, float *mrec,
-                                                         double *wf64) {
+                                                         double *wf64, SideOut so) {
     using Y = Lay<D>;
     int64_t f = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (f >= nf) return;
@@ -201,55 +218,70 @@ __global__ void __launch_bounds__(kBlock) k_face_records(int64_t n, int64_t nf, 
     for (int k = 0; k < D; k++) proj += (wl[k] - wr[k]) * c[k];
     const double ell = sqrt(s2);
     const double inv = 1.0 / ell;
-    double *o = frec + f * Y::FREC;
-    o[Y::FA] = area[f];
+    const double A = area[f];
+    double o[Y::FREC];
+    o[Y::FA] = A;
     o[Y::FELL] = ell;
     double w[D];
     for (int k = 0; k < D; k++) {
         o[Y::FN + k] = d[k] * inv;
         o[Y::FC + k] = c[k];
         w[k] = 0.5 * (wl[k] + wr[k]) + proj * d[k] / s2;
-        o[Y::FW + k] = w[k];
     }
+    store_rec<Y::FREC>(frec + f * Y::FREC, o);
+    store_rec<Y::WSTRIDE>(wf64 + f * Y::WSTRIDE, w);
     if (mixed) {
-        float *m = mrec + f * Y::MREC;
-        m[Y::FA] = (float)area[f];
+        float m[Y::MREC];
+        m[Y::FA] = (float)A;
         m[Y::FELL] = (float)ell;
         for (int k = 0; k < D; k++) {
-            m[Y::FN + k] = (float)(d[k] * inv);
+            m[Y::FN + k] = (float)o[Y::FN + k];
             m[Y::FC + k] = (float)c[k];
             m[Y::MDW + k] = (float)(wl[k] - wr[k]);
-            wf64[f * Y::WSTRIDE + k] = w[k];
         }
-
+        store_rec<Y::MREC>(mrec + f * Y::MREC, m);
+    }
+    if (so.ent) {
+        const int64_t q[2] = {f + so.roff[l], (int64_t)so.loff[r + 1] + so.pos[f]};
+        const double hl = 0.5 * ell;
+        for (int side = 0; side < 2; side++) {
+            const double sg = side ? -1.0 : 1.0;
+            double rec[Y::SREC64];
+            rec[0] = A / ell;
+            for (int k = 0; k < D; k++) rec[1 + k] = c[k] + sg * hl * o[Y::FN + k];
+            for (int k = 1 + D; k < Y::SREC64; k++) rec[k] = 0.0;
+            so.ent[q[side]] = (int32_t)(2 * f + side);
+            so.nbr[q[side]] = side ? l : r;
+            if (so.srec) store_rec<Y::SREC64>(so.srec + q[side] * Y::SREC64, rec);
+            else {
+                float m[Y::SREC32];
+                for (int k = 0; k < Y::SREC32; k++) m[k] = (float)rec[k];
+                store_rec<Y::SREC32>(so.srec32 + q[side] * Y::SREC32, m);
+            }
+        }
     }
 }
 
-// The per-cell side lists of the gradient pass, one lane group per cell:
-// its left faces (face order) then its right faces (face order), so that
-// off[i] = loff[i] + roff[i]; per side ent = face << 1 | is_right, the
-// neighbour, and the side record A/|d|, f - r_i (double or float); and the
+// The gradient pass's list offsets off[i] = loff[i] + roff[i] and the
 // closure test |sum_faces A n_out| <= 1e-9 sum_faces A of every cell (a
 // closed surface is a property of every Voronoi cell; the gradient relies
-// on it).
+// on it), one lane group per cell over its left range and right faces,
+// A and n from the face records.
 template <int D>
-__global__ void __launch_bounds__(kBlock) k_sides(int64_t n, int64_t nf, const int32_t *__restrict__ L,
-                                                  const int32_t *__restrict__ R, const double *__restrict__ area,
-                                                  const double *__restrict__ ctr, const double *__restrict__ sep,
-                                                  const int32_t *__restrict__ loff, const int32_t *__restrict__ roff,
-                                                  const int32_t *__restrict__ rface, int32_t *__restrict__ off,
-                                                  int32_t *__restrict__ ent, int32_t *__restrict__ nbr,
-                                                  double *__restrict__ srec, float *__restrict__ srec32,
-                                                  int32_t *flags) {
+__global__ void __launch_bounds__(kBlock) k_closure(int64_t n, const double *__restrict__ frec,
+                                                    const int32_t *__restrict__ loff, const int32_t *__restrict__ roff,
+                                                    const int32_t *__restrict__ rface, int32_t *__restrict__ off,
+                                                    int32_t *flags) {
     using Y = Lay<D>;
     constexpr int GS = Group<D>::GS;
+    constexpr int NH = 2 + D;   // A, |d|, n
+    static_assert(Y::FA == 0 && Y::FELL == 1 && Y::FN == 2, "face record head");
     const int lane = threadIdx.x % GS;
     const int64_t i = (int64_t)blockIdx.x * (kBlock / GS) + threadIdx.x / GS;
     if (i >= n) return;
     const int32_t l0 = loff[i], nl = loff[i + 1] - l0, r0 = roff[i], nr = roff[i + 1] - r0;
-    const int32_t o = l0 + r0;
     if (lane == 0) {
-        off[i] = o;
+        off[i] = l0 + r0;
         if (i == n - 1) off[n] = loff[n] + roff[n];
     }
     double clo[D], asum = 0.0;
@@ -257,28 +289,11 @@ __global__ void __launch_bounds__(kBlock) k_sides(int64_t n, int64_t nf, const i
     for (int32_t k = lane; k < nl + nr; k += GS) {
         const bool right = k >= nl;
         const int32_t f = right ? rface[r0 + k - nl] : l0 + k;
-        const double sg = right ? -1.0 : 1.0;   // outward separation e = sg * d
-        double d[D], s2 = 0.0;
-        for (int c = 0; c < D; c++) { d[c] = sep[c * nf + f]; s2 += d[c] * d[c]; }
-        const double ell = sqrt(s2), A = area[f];
-        double rec[Y::SREC64];
-        rec[0] = A / ell;
-        for (int c = 0; c < D; c++) {
-            const double cc = ctr[c * nf + f] - 0.5 * d[c];
-            rec[1 + c] = cc + 0.5 * sg * d[c];
-            clo[c] += A * sg * d[c] / ell;
-        }
-        for (int c = 1 + D; c < Y::SREC64; c++) rec[c] = 0.0;
-        asum += A;
-        const int64_t q = o + k;
-        ent[q] = (int32_t)(2 * f + (right ? 1 : 0));
-        nbr[q] = right ? L[f] : R[f];
-        if (srec) store_rec<Y::SREC64>(srec + q * Y::SREC64, rec);
-        else {
-            float m[Y::SREC32];
-            for (int c = 0; c < Y::SREC32; c++) m[c] = (float)rec[c];
-            store_rec<Y::SREC32>(srec32 + q * Y::SREC32, m);
-        }
+        double fr[NH];
+        load_rec<NH>(frec + (int64_t)f * Y::FREC, fr);
+        const double sa = right ? -fr[Y::FA] : fr[Y::FA];   // outward normal: n on the left, -n on the right
+        for (int c = 0; c < D; c++) clo[c] += sa * fr[Y::FN + c];
+        asum += fr[Y::FA];
     }
     double cl2 = 0.0;
     for (int c = 0; c < D; c++) {

@@ -13,13 +13,13 @@
 // to 8; W0 the midrange of the generator velocities (a uniform bulk motion
 // leaves every w_i - W0 at zero, so it costs no float bits).
 //
-// Face record (double path), one per face:
-//   A, |d|, n (D) = d/|d|, c (D) = f - (r_L + r_R)/2, w_f (D).
+// Face record (double geometry), one per face, 64-byte aligned in 3D:
+//   A, |d|, n (D) = d/|d|, c (D) = f - (r_L + r_R)/2;
+// the double face velocity w_f in its own array, D per face (both paths).
 // Mixed face record (float), one per face:
 //   A, |d|, n (D), c (D), dw (D) = w_L - w_R;
 //   the generators' velocities relative to the face follow from dw:
 //   w_L - w_f = dw/2 - (dw.c/|d|) n,  w_R - w_f = -dw/2 - (dw.c/|d|) n;
-//   plus the double face velocity w_f in its own array, D per face.
 // Face fluxes: face-major, D + 2 doubles per face.
 // Side record, one per (cell, face) pair in CSR order:
 //   double path: A/|d|, f - r_i (D)             stride 4
@@ -36,8 +36,8 @@ template <int D> struct Lay {
     static constexpr int GREC = (D == 3) ? 16 : 8;
     static constexpr int REC = PREC + GREC;
     // double face record
-    static constexpr int FA = 0, FELL = 1, FN = 2, FC = 2 + D, FW = 2 + 2 * D;
-    static constexpr int FREC = 2 + 3 * D;
+    static constexpr int FA = 0, FELL = 1, FN = 2, FC = 2 + D;
+    static constexpr int FREC = 2 + 2 * D;
     // mixed face record
     static constexpr int MDW = 2 + 2 * D;
     static constexpr int MREC = 2 + 3 * D;

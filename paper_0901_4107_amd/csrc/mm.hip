@@ -61,8 +61,8 @@ struct Layout {
     int64_t flags, diag, mlp, dtdev, bhard, dtpart, bsum, off, cursor, ent, nbr;
     int64_t loff, roff, rface;              // the update's left ranges and right faces
     int64_t ekmax;                          // energy switch: neighbour energies per cell
-    int64_t srec, frec, rec, flux;          // double path (frec always; flux: timelines only)
-    int64_t srec32, mrec, wf64, rec32, hard, gath, w0, w0part; // mixed path
+    int64_t srec, frec, wf64, rec, flux;    // double path (frec, wf64 always; flux: timelines only)
+    int64_t srec32, mrec, rec32, hard, gath, w0, w0part;       // mixed path
     int64_t tb_bin, tb_trec, tb_sig, tb_touch, tb_cells, tb_faces, tb_touched, tb_info;   // individual timesteps
     int64_t total;
 };
@@ -88,16 +88,17 @@ Layout make_layout(int D, int mode, int em, bool tb, int64_t n, int64_t nf) {
     while (m > 1) { m = (m + 1023) / 1024; bs += m + 1; }
     L.bsum = take((bs + 4) * sizeof(int32_t));
     L.off = take((n + 1) * sizeof(int32_t));
-    L.cursor = take(n * sizeof(int32_t));
+    L.cursor = take((n > nf ? n : nf) * sizeof(int32_t));   // cursors, then each face's right slot
     L.ent = take(2 * nf * sizeof(int32_t));
     L.nbr = take(2 * nf * sizeof(int32_t));
     L.frec = take(nf * FREC * sizeof(double));
+    L.wf64 = take(nf * WS * sizeof(double));
     L.loff = take((n + 1) * sizeof(int32_t));
     L.roff = take((n + 1) * sizeof(int32_t));
     L.rface = take(nf * sizeof(int32_t));
     L.flux = take(nf * FM * sizeof(double));
     L.ekmax = em == MM_ENTROPY_ENERGY ? take(n * sizeof(double)) : -1;
-    L.srec = L.srec32 = L.mrec = L.wf64 = L.rec32 = L.rec = L.hard = L.gath = L.w0 = L.w0part = -1;
+    L.srec = L.srec32 = L.mrec = L.rec32 = L.rec = L.hard = L.gath = L.w0 = L.w0part = -1;
     if (mode == MM_FP64) {
         L.srec = take(2 * nf * Lay<3>::SREC64 * sizeof(double));
         L.rec = take(n * REC * sizeof(double));
@@ -107,7 +108,6 @@ Layout make_layout(int D, int mode, int em, bool tb, int64_t n, int64_t nf) {
         L.w0 = take(4 * sizeof(double));
         L.w0part = take((int64_t)plain_grid_n(n) * 2 * 3 * sizeof(double));
         L.mrec = take(nf * Lay<3>::MREC * sizeof(float));
-        L.wf64 = take(nf * WS * sizeof(double));
         L.rec32 = take(n * REC * sizeof(float));
         // with individual timesteps the hard faces of one face sub-list
         L.hard = take((tb ? split_ints(tb_face_cap(n, nf)) : list_ints(grid_for(nf))) * sizeof(int32_t));
@@ -295,13 +295,14 @@ template <int D> static void launch_validate(mm_ctx *c, const mm_mesh *m, int32_
 }
 
 // Face records and, in the mixed mode, the reference velocity W0 of the
-// gather records: everything that depends on the generator velocities.
-template <int D> static void launch_face_records(mm_ctx *c, const mm_mesh *m) {
+// gather records: everything that depends on the generator velocities;
+// with so.ent (the upload) also the side records.
+template <int D> static void launch_face_records(mm_ctx *c, const mm_mesh *m, const SideOut &so = SideOut{}) {
     const Layout &L = c->lay;
     const int mixed = c->p.mode == MM_MIXED;
     k_face_records<D><<<plain_grid(m->n_faces), kBlock, 0, c->st()>>>(
         m->n_cells, m->n_faces, m->face_L, m->face_R, m->face_area, m->face_ctr, m->face_sep, m->mesh_vel,
-        c->at<double>(L.frec), mixed, mixed ? c->at<float>(L.mrec) : nullptr, mixed ? c->at<double>(L.wf64) : nullptr);
+        c->at<double>(L.frec), mixed, mixed ? c->at<float>(L.mrec) : nullptr, c->at<double>(L.wf64), so);
     if (mixed) {
         const unsigned g = plain_grid(m->n_cells);
         k_w0_part<D><<<g, kBlock, 0, c->st()>>>(m->n_cells, m->mesh_vel, c->at<double>(L.w0part));
@@ -353,23 +354,21 @@ mm_status mm_mesh_upload(mm_ctx *c, const mm_mesh *m) {
     if (st != MM_OK) return st;
     k_copy_i32<<<plain_grid(n), kBlock, 0, s>>>(cur, roff, n);
     k_place_right<<<plain_grid(nf), kBlock, 0, s>>>(nf, m->face_R, cur, rface);
-    k_sort_right<<<plain_grid(n), kBlock, 0, s>>>(n, roff, rface);
+    int32_t *pos = cur;   // the cursors are spent: each face's slot in rface
+    k_sort_right<<<plain_grid(n), kBlock, 0, s>>>(n, roff, rface, pos);
     MM_LAUNCH_CHECK();
-    // the gradient pass's side lists and records, the closure test; the face
-    // records and face velocities
+    // the face records and face velocities; from them the gradient pass's
+    // side lists and records, and the closure test
     const bool mixed = c->p.mode == MM_MIXED;
     double *srec = mixed ? nullptr : c->at<double>(L.srec);
     float *srec32 = mixed ? c->at<float>(L.srec32) : nullptr;
+    const SideOut so{loff, roff, pos, c->at<int32_t>(L.ent), c->at<int32_t>(L.nbr), srec, srec32};
     if (c->D == 3) {
-        k_sides<3><<<group_grid(3, n), kBlock, 0, s>>>(n, nf, m->face_L, m->face_R, m->face_area, m->face_ctr,
-                                                       m->face_sep, loff, roff, rface, off, c->at<int32_t>(L.ent),
-                                                       c->at<int32_t>(L.nbr), srec, srec32, flags);
-        launch_face_records<3>(c, m);
+        launch_face_records<3>(c, m, so);
+        k_closure<3><<<group_grid(3, n), kBlock, 0, s>>>(n, c->at<double>(L.frec), loff, roff, rface, off, flags);
     } else {
-        k_sides<2><<<group_grid(2, n), kBlock, 0, s>>>(n, nf, m->face_L, m->face_R, m->face_area, m->face_ctr,
-                                                       m->face_sep, loff, roff, rface, off, c->at<int32_t>(L.ent),
-                                                       c->at<int32_t>(L.nbr), srec, srec32, flags);
-        launch_face_records<2>(c, m);
+        launch_face_records<2>(c, m, so);
+        k_closure<2><<<group_grid(2, n), kBlock, 0, s>>>(n, c->at<double>(L.frec), loff, roff, rface, off, flags);
     }
     MM_LAUNCH_CHECK();
     MM_CHECK(hipMemcpyAsync(&hflags, flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -464,7 +463,8 @@ static mm_status fluxes_t(mm_ctx *c, const double *dt_dev, double dt, const void
     if (c->p.mode == MM_FP64) {
         auto kern = mlp ? k_face_flux64<D, true, EM, GRAV> : k_face_flux64<D, false, EM, GRAV>;
         const double *prim = (const double *)rec;
-        kern<<<grid_for(c->nf), kBlock, 0, s>>>(c->nf, c->mesh.face_L, c->mesh.face_R, c->at<double>(L.frec), prim,
+        kern<<<grid_for(c->nf), kBlock, 0, s>>>(c->nf, c->mesh.face_L, c->mesh.face_R, c->at<double>(L.frec),
+                                                c->at<double>(L.wf64), prim,
                                                 grad_block<D>(c, prim), dt_dev, dt, kg, c->p.newton_tol64,
                                                 c->p.newton_max_iter, mlp, flux, diag, aux);
     } else {
@@ -618,10 +618,12 @@ mm_status mm_volume_rate(mm_ctx *c, double *rate) {
     const Layout &L = c->lay;
     if (c->D == 3)
         k_volume_rate<3><<<group_grid(3, c->n), kBlock, 0, c->st()>>>(c->n, c->at<int32_t>(L.off),
-                                                                      c->at<int32_t>(L.ent), c->at<double>(L.frec), rate);
+                                                                      c->at<int32_t>(L.ent), c->at<double>(L.frec),
+                                                                      c->at<double>(L.wf64), rate);
     else
         k_volume_rate<2><<<group_grid(2, c->n), kBlock, 0, c->st()>>>(c->n, c->at<int32_t>(L.off),
-                                                                      c->at<int32_t>(L.ent), c->at<double>(L.frec), rate);
+                                                                      c->at<int32_t>(L.ent), c->at<double>(L.frec),
+                                                                      c->at<double>(L.wf64), rate);
     MM_LAUNCH_CHECK();
     return MM_OK;
 }
@@ -850,11 +852,13 @@ mm_status mm_face_states(mm_ctx *c, double dt, const void *recon, float *out) {
     if (!c->have_mesh) return MM_E_STATE;
     if (c->D == 3)
         k_face_states64<3><<<plain_grid(c->nf), kBlock, 0, c->st()>>>(
-            c->nf, c->mesh.face_L, c->mesh.face_R, c->at<double>(c->lay.frec), (const double *)recon,
+            c->nf, c->mesh.face_L, c->mesh.face_R, c->at<double>(c->lay.frec), c->at<double>(c->lay.wf64),
+            (const double *)recon,
             grad_block<3>(c, (const double *)recon), dt, c->p.gamma, out);
     else
         k_face_states64<2><<<plain_grid(c->nf), kBlock, 0, c->st()>>>(
-            c->nf, c->mesh.face_L, c->mesh.face_R, c->at<double>(c->lay.frec), (const double *)recon,
+            c->nf, c->mesh.face_L, c->mesh.face_R, c->at<double>(c->lay.frec), c->at<double>(c->lay.wf64),
+            (const double *)recon,
             grad_block<2>(c, (const double *)recon), dt, c->p.gamma, out);
     MM_LAUNCH_CHECK();
     return MM_OK;
@@ -984,8 +988,8 @@ template <int D, typename T> static void tb_point(mm_ctx *c, double *Q, T *rec) 
     if (!mixed) {
         auto kern = mlp ? k_face_flux64_list<D, true> : k_face_flux64_list<D, false>;
         kern<<<kTbGrid, kBlock, 0, s>>>(faces, fcap, c->mesh.face_L, c->mesh.face_R, c->at<double>(L.frec),
-                                        (const double *)rec, (const double *)grad, view, kg, c->p.newton_tol64,
-                                        c->p.newton_max_iter, mlp, flux, diag);
+                                        c->at<double>(L.wf64), (const double *)rec, (const double *)grad, view, kg,
+                                        c->p.newton_tol64, c->p.newton_max_iter, mlp, flux, diag);
     } else {
         const GasConst<float> kf(c->p.gamma);
         auto kern = mlp ? k_face_flux_mixed_list<D, true> : k_face_flux_mixed_list<D, false>;
