@@ -107,17 +107,22 @@ __device__ __forceinline__ double cell_prim(int64_t i, int64_t n, double gamma, 
     return sqrt(gamma * P / rho);
 }
 
-// The gather record of a cell (mixed mode) from its float primitive record:
-// rho, v_i - w_i, P, then w_i - W0 rounded to float from double, W0 the
+// The gather record of a cell (mixed mode) from its float primitive record
+// and its double lab velocity v (0 for vacuum): rho, v_i - W0, P, then
+// w_i - W0, each velocity difference rounded to float from double, W0 the
 // reference velocity w0 [D] (device).
 template <int D>
-__device__ __forceinline__ void gather_rec(int64_t i, int64_t n, const float (&r)[Lay<D>::PREC],
+__device__ __forceinline__ void gather_rec(int64_t i, int64_t n, const float (&r)[Lay<D>::PREC], const double (&v)[D],
                                            const double *__restrict__ mvel, const double *__restrict__ w0,
                                            float (&g)[Lay<D>::GATH]) {
     using Y = Lay<D>;
     for (int k = 0; k < Y::GATH; k++) g[k] = 0.0f;
-    for (int c = 0; c < Y::NV; c++) g[c] = r[Y::W + c];
-    for (int k = 0; k < D; k++) g[Y::GW + k] = (float)(mvel[k * n + i] - w0[k]);
+    g[Y::W] = r[Y::W];
+    g[Y::W + Y::NV - 1] = r[Y::W + Y::NV - 1];
+    for (int k = 0; k < D; k++) {
+        g[Y::W + 1 + k] = (float)(v[k] - w0[k]);
+        g[Y::GW + k] = (float)(mvel[k * n + i] - w0[k]);
+    }
 }
 
 // Step (ii) and the timestep bound of step (v) (Section 7.1): the primitive
@@ -146,7 +151,7 @@ __global__ void __launch_bounds__(kBlock) k_prim_cfl(int64_t n, double gamma, do
         store_rec<Y::PREC>(prim + i * Y::PREC, r);
         if constexpr (sizeof(T) == 4) {
             float g[Y::GATH];
-            gather_rec<D>(i, n, r, mvel, w0, g);
+            gather_rec<D>(i, n, r, v, mvel, w0, g);
             store_rec<Y::GATH>(gather + i * Y::GATH, g);
         }
     }
@@ -242,11 +247,11 @@ __global__ void __launch_bounds__(kBlock) k_w0_final(int64_t nparts, const doubl
 // sides with |Dl| <= tol never hold that maximum unless no side exceeds tol,
 // so the lanes keep plain maxima and minima of Dl and the tolerance is
 // applied once per cell.
-// Mixed mode (T = float): velocities in the records are relative to each
-// cell's own generator, so the velocity difference across a side is
-//   v_j - v_i = [(v_j - w_j) - (v_i - w_i)] + [(w_j - W0) - (w_i - W0)],
-// both brackets from the two cells' gather records (no lab-frame velocity is
-// formed in float).
+// Mixed mode (T = float): the gather records hold velocities relative to
+// the reference velocity W0 (the midrange of the generator velocities), so
+// the velocity difference across a side is
+//   v_j - v_i = (v_j - W0) - (v_i - W0)
+// and no lab-frame velocity is formed in float.
 // Each lane keeps its first KR sides (A/|r|, f - r_i) in registers for the
 // limiter pass and issues their loads together; sides beyond GS*KR (rare)
 // are walked by a loop that re-reads them.
@@ -256,14 +261,13 @@ template <int D, typename T> struct SideAcc {
 };
 
 // One side: s the side record, pj the neighbour's values and wi the cell's
-// (W; in the mixed mode followed by w - W0 at GW).
-template <int D, typename T, bool MIXED>
+// (W, velocities relative to W0 in the mixed mode).
+template <int D, typename T>
 __device__ __forceinline__ void grad_side(const T *s, const T *pj, const T *wi, SideAcc<D, T> &a) {
     constexpr int NV = D + 2;
     const T w = s[0];
     for (int c = 0; c < NV; c++) {
-        T dphi = pj[c] - wi[c];
-        if (MIXED && c >= 1 && c <= D) dphi += pj[Lay<D>::GW + c - 1] - wi[Lay<D>::GW + c - 1];
+        const T dphi = pj[c] - wi[c];
         const T ad = w * dphi;
         for (int k = 0; k < D; k++) a.acc[c][k] += ad * s[1 + k];
         a.dmx[c] = fmax(a.dmx[c], dphi);
@@ -288,8 +292,8 @@ __device__ __forceinline__ void limit_side(const T *g, const T *dl, const T (&gr
 // kinetic energy of neighbour j in the frame of cell i's generator,
 // M_j |v_j - w_i|^2 / 2 with M_j = rho_j V_j (0 for a vacuum neighbour), from
 // j's values pj as the gradient pass reads them: double primitive records
-// hold v_j (wi = w_i); float gather records hold v_j - w_j and w_j - W0
-// (wi: cell i's w_i - W0), so v_j - w_i = (v_j - w_j) + [(w_j - W0) - (w_i - W0)].
+// hold v_j (wlab = w_i); float gather records hold v_j - W0, and cell i's
+// record w_i - W0 (in wi), so v_j - w_i = (v_j - W0) - (w_i - W0).
 // In the records' precision: the float form's velocities carry float
 // rounding already, and the switch compares this with the cell's thermal
 // energy at a threshold alpha far above it.
@@ -297,7 +301,7 @@ template <int D, typename T>
 __device__ __forceinline__ T ekin_in_frame(const T *pj, const T *wi, double Vj, const double (&wlab)[D]) {
     T e = (T)0;
     for (int k = 0; k < D; k++) {
-        const T dv = sizeof(T) == 4 ? pj[1 + k] + (pj[Lay<D>::GW + k] - wi[Lay<D>::GW + k]) : pj[1 + k] - (T)wlab[k];
+        const T dv = sizeof(T) == 4 ? pj[1 + k] - wi[Lay<D>::GW + k] : pj[1 + k] - (T)wlab[k];
         e += dv * dv;
     }
     return pj[0] > (T)0 ? (T)0.5 * (pj[0] * (T)Vj) * e : (T)0;
@@ -353,7 +357,7 @@ __device__ __forceinline__ void grad_cell(int64_t i, int lane, const int32_t *__
     constexpr int NV = D + 2;
     constexpr int GS = Group<D>::GS;
     constexpr bool mixed = sizeof(T) == 4;
-    constexpr int KR = mixed ? (ESW ? 3 : 4) : 3;   // sides per lane held in registers
+    constexpr int KR = mixed ? (ESW ? 3 : 5) : 3;   // sides per lane held in registers
     constexpr int SR = mixed ? Y::SREC32 : Y::SREC64;
     constexpr int NJ = mixed ? Y::GATH : NV;   // values read of a neighbour
     const T eps_t = mixed ? (T)1e-6 : (T)1e-13;
@@ -391,7 +395,7 @@ __device__ __forceinline__ void grad_cell(int64_t i, int lane, const int32_t *__
         for (int k = 0; k < D; k++) wlab[k] = mixed ? 0.0 : mvel[k * n + i];
     for (int r = 0; r < KR; r++)
         if (has[r]) {
-            grad_side<D, T, mixed>(sr[r], pj[r], wi, a);
+            grad_side<D, T>(sr[r], pj[r], wi, a);
             if constexpr (ESW) ek = fmax(ek, ekin_in_frame<D, T>(pj[r], wi, vj[r], wlab));
         }
     for (int32_t q = b + lane + KR * GS; q < e; q += GS) {
@@ -399,7 +403,7 @@ __device__ __forceinline__ void grad_cell(int64_t i, int lane, const int32_t *__
         load_rec<SR>(srec + (int64_t)q * SR, s2);
         const int32_t j = nbr[q];
         load_nb<D, T>(nrec, j, NS, win, c0, p2);
-        grad_side<D, T, mixed>(s2, p2, wi, a);
+        grad_side<D, T>(s2, p2, wi, a);
         if constexpr (ESW) ek = fmax(ek, ekin_in_frame<D, T>(p2, wi, nb_vol(V, j, vwin, c0), wlab));
     }
     if constexpr (ESW) {
@@ -449,10 +453,10 @@ __device__ __forceinline__ void grad_cell(int64_t i, int lane, const int32_t *__
 // The gather-bound gradient kernels gain from one more wavefront per SIMD
 // than the register count the compiler picks on its own (5 float / 4 double,
 // about 7-9% faster; the 3D double kernel spills a few bytes per lane). The
-// float kernels hold 4 sides per lane in registers, 3 with the energy
-// switch's neighbour energies, which keeps both at 5 without spills (a spill
-// of 32 bytes per lane cost the float kernel about 20%); the double kernel
-// with the switch runs at 3.
+// float kernels hold 5 sides per lane in registers, 3 with the energy
+// switch's neighbour energies, which keeps both at 5 or more without spills
+// (a spill of 32 bytes per lane once cost the float kernel about 20%); the
+// double kernel with the switch runs at 3.
 template <int D, typename T, bool ESW>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : (ESW ? 3 : 4))))
 k_grad_limit(int64_t n, const int32_t *__restrict__ off, const int32_t *__restrict__ nbr, const T *__restrict__ srec,

@@ -146,7 +146,7 @@ __global__ void __launch_bounds__(kBlock) k_tb_open(int64_t n, int32_t *__restri
             store_rec<Y::PREC>(prim + i * Y::PREC, r);
             if constexpr (sizeof(T) == 4) {   // the mixed mode's gather record
                 float g[Y::GATH];
-                gather_rec<D>(i, n, r, mvel, w0, g);
+                gather_rec<D>(i, n, r, v, mvel, w0, g);
                 store_rec<Y::GATH>(gather + i * Y::GATH, g);
             }
             double s[SG];

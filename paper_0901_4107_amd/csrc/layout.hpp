@@ -9,9 +9,9 @@
 // In double precision the velocities are lab-frame; in the mixed mode the
 // records are float and hold v_i - w_i.
 // Gather record (mixed mode), one per cell [N][GATH], what a neighbour's
-// gradient pass reads of a cell: rho, v_i - w_i (D), P, w_i - W0 (D), padding
-// to 8; W0 the midrange of the generator velocities (a uniform bulk motion
-// leaves every w_i - W0 at zero, so it costs no float bits).
+// gradient pass reads of a cell: rho, v_i - W0 (D), P, w_i - W0 (D), padding
+// to 8; W0 the midrange of the generator velocities (a bulk motion the mesh
+// follows leaves these differences small, so it costs no float bits).
 //
 // Face record (double geometry), one per face, 64-byte aligned in 3D:
 //   A, |d|, n (D) = d/|d|, c (D) = f - (r_L + r_R)/2;
