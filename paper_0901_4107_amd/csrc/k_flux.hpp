@@ -665,19 +665,22 @@ __device__ __forceinline__ void mixed_lab_flux(const MixedFace<D> &m, double rho
     lab_flux<D>(rho, u, P, tv, nd, w, g_over_gm1, dt * (double)m.A, out);
 }
 
-// LDS the learned staging of the mixed kernel parks the face states in while
-// the network runs (floats).
-template <int D> constexpr int stash_floats() { return (2 * (D + 2) + D + 1) * kBlock; }
+// LDS the learned guess of the mixed kernel parks the two face states in
+// while the network runs (floats; each lane its own slots).
+template <int D> constexpr int stash_floats() { return 2 * (D + 2) * kBlock; }
 
 // Mixed-precision flux of face f (dt A Fhat into F): float face states and
 // float Newton; the lab-frame flux and everything after it in double. Faces
 // the float solve judges hard (strong rarefaction or near vacuum, tiny
 // guess, no convergence) come back with hard = true and no flux. The body
-// of the face kernel. Every thread of the block calls it (the learned staging holds
-// barriers); active = false does no face. While the network runs, the face
-// states wait in LDS (stash: (2(D+2) + D + 1) kBlock floats), so the
-// network's registers come on top of few live values. once: the kernel calls
-// this once per thread (no barrier for a next call).
+// of the face kernel; active = false does no face, but every lane of a
+// wavefront calls it (the learned guess works across the wavefront). Only a
+// wavefront with a face the gate passes runs the network, over its gated
+// faces compacted by lane reads (learned_guess_wave); meanwhile the two
+// face states wait in the lane's own LDS slots (stash: 2(D+2) kBlock floats,
+// apart from the window) and the normal and area are read again from the
+// face record, so the network's registers come on top of few live values.
+// No barrier: the other wavefronts of the block run on.
 template <int D, bool LEARNED, int EM, bool GRAV>
 __device__ __forceinline__ void face_flux_mixed(bool active, int64_t f, const int32_t *__restrict__ fL,
                                                 const int32_t *__restrict__ fR, const float *__restrict__ mrec,
@@ -686,7 +689,7 @@ __device__ __forceinline__ void face_flux_mixed(bool active, int64_t f, const in
                                                 const GasConst<float> &kf, double g_over_gm1, float tol32, int maxit,
                                                 const MlpPacked *mlp, const FaceAux &aux, float *stash,
                                                 LaneDiag &ld, bool &hard, double (&F)[D + 2], FaceX &X,
-                                                const Window &win = Window{nullptr, 0}, bool once = false) {
+                                                const Window &win = Window{nullptr, 0}) {
     constexpr int NV = D + 2;
     hard = false;
     MixedFace<D> m;
@@ -700,29 +703,24 @@ __device__ __forceinline__ void face_flux_mixed(bool active, int64_t f, const in
     }
     float pl = no_guess<float>();
     if constexpr (LEARNED) {
-        __shared__ LearnLds sh;
         const bool want =
             active && wants_learned<float>(m.xl[0], m.uL, m.xl[NV - 1], m.xr[0], m.uR, m.xr[NV - 1], kf.g);
-        int slot = 0;
-        const int total = mlp ? learn_count(sh, want, slot) : 0;
-        if (total > 0) {   // the same for the whole block
-            if (want) learn_put<float>(sh, slot, m.xl[0], m.uL, m.xl[NV - 1], m.xr[0], m.uR, m.xr[NV - 1], kf.g);
+        if (mlp && __ballot(want) != 0ull) {   // the same for the whole wavefront
             const int t = threadIdx.x;
             for (int c = 0; c < NV; c++) { stash[c * kBlock + t] = m.xl[c]; stash[(NV + c) * kBlock + t] = m.xr[c]; }
-            for (int k = 0; k < D; k++) stash[(2 * NV + k) * kBlock + t] = m.nrm[k];
-            stash[(2 * NV + D) * kBlock + t] = m.A;
-            learn_run(sh, mlp, total);
-            pl = learn_get<float>(sh, want, slot);
+            pl = learned_guess_wave<float>(mlp, want, m.xl[0], m.uL, m.xl[NV - 1], m.xr[0], m.uR, m.xr[NV - 1], kf.g);
             for (int c = 0; c < NV; c++) { m.xl[c] = stash[c * kBlock + t]; m.xr[c] = stash[(NV + c) * kBlock + t]; }
-            for (int k = 0; k < D; k++) m.nrm[k] = stash[(2 * NV + k) * kBlock + t];
-            m.A = stash[(2 * NV + D) * kBlock + t];
+            float fr[2 + D];   // A, |d|, n
+            load_rec<2 + D>(mrec + (active ? f : 0) * Lay<D>::MREC, fr);
+            m.A = fr[Lay<D>::FA];
             m.uL = 0.0f;
             m.uR = 0.0f;
-            for (int k = 0; k < D; k++) { m.uL += m.xl[1 + k] * m.nrm[k]; m.uR += m.xr[1 + k] * m.nrm[k]; }
+            for (int k = 0; k < D; k++) {
+                m.nrm[k] = fr[Lay<D>::FN + k];
+                m.uL += m.xl[1 + k] * m.nrm[k];
+                m.uR += m.xr[1 + k] * m.nrm[k];
+            }
         }
-        // every thread has read the staging before a next call rewrites it
-        // (once: the kernel makes no next call)
-        if (mlp && !once) __syncthreads();
     }
     if (active) {
         FaceState<float> fs = solve_face<float>(m.xl[0], m.uL, m.xl[NV - 1], m.xr[0], m.uR, m.xr[NV - 1], kf, tol32,
@@ -756,20 +754,20 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))
                                                             int64_t cap, DiagDev *diag, FaceAux aux) {
     constexpr int NV = D + 2;
     constexpr int SW = kWin * (Lay<D>::PREC + Lay<D>::GREC);
-    constexpr int SS = LEARNED ? stash_floats<D>() : 1;
-    // the staged window of cell records; once the face states are formed, the
-    // learned staging (its first barrier comes after every read of the window)
-    __shared__ float stash[SW > SS ? SW : SS];
+    // the staged window of cell records, and apart from it the learned
+    // guess's parking slots
+    __shared__ float wbuf[SW];
+    __shared__ float stash[LEARNED ? stash_floats<D>() : 1];
     const int64_t f = xcd_global_id();
     const bool active = f < nf;
-    const Window win = stage_window<D>(stash, xcd_tile() * kBlock, nf, fL, prim, grad, aux.n);
+    const Window win = stage_window<D>(wbuf, xcd_tile() * kBlock, nf, fL, prim, grad, aux.n);
     LaneDiag ld;
     bool hard;
     const double dt = dt_ptr ? *dt_ptr : dt_val;
     double F[NV];
     FaceX X;
     face_flux_mixed<D, LEARNED, EM, GRAV>(active, f, fL, fR, mrec, wf64, prim, grad, dt, 0.5 * dt, 0.5 * dt, kf,
-                                          g_over_gm1, tol32, maxit, mlp, aux, stash, ld, hard, F, X, win, true);
+                                          g_over_gm1, tol32, maxit, mlp, aux, stash, ld, hard, F, X, win);
     if (active && !hard) store_face<D, EM>(flux + f * Rec<D, EM>::FM, F, X);
     list_append(hard_list, cap, hard, (int32_t)f);
     if (diag) flush_diag(ld, diag);
