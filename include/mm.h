@@ -27,7 +27,10 @@
  *                                limited gradient, element c*D + k =
  *                                dW_c/dx_k, padding
  *   In MM_FP64 its elements are double and v is the lab-frame velocity; in
- *   MM_MIXED they are float and v holds v_i - w_i.
+ *   MM_MIXED they are float and v holds v_i - W0, W0 the midrange (min +
+ *   max)/2 of the generator velocities per component at the last
+ *   mm_mesh_upload or mm_mesh_set_velocity (the buffer belongs to that
+ *   mesh state).
  * - The normal of face f points from its left cell face_L[f] to its right
  *   cell face_R[f]; Fhat(f) is the flux leaving the left cell.
  * - Calls enqueue work on params.stream (a hipStream_t; NULL = the null

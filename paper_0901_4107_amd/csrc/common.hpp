@@ -60,11 +60,11 @@ template <int N, typename T> __device__ __forceinline__ void load_rec(const T *_
 typedef __attribute__((address_space(3))) const float lds_cfloat;
 template <int N> __device__ __forceinline__ void load_rec_lds(lds_cfloat *p, float (&o)[N]) {
     typedef __attribute__((address_space(3))) const f32x4u lds_cf32x4;
-    static_assert(N % 4 == 0, "whole 16-byte parts");
     for (int i = 0; i < N / 4; i++) {
         const f32x4u v = *reinterpret_cast<lds_cf32x4 *>(p + i * 4);
         for (int j = 0; j < 4; j++) o[i * 4 + j] = v[j];
     }
+    for (int k = N / 4 * 4; k < N; k++) o[k] = p[k];
 }
 template <int N, typename T> __device__ __forceinline__ void store_rec(T *__restrict__ p, const T (&o)[N]) {
     using V = typename Vec16<T>::type;

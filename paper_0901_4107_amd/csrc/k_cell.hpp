@@ -68,20 +68,25 @@ __device__ __forceinline__ double block_min(double v) {
 // Step (ii) for one cell (Section 3, state vector and equation of state):
 //   rho = m/V, v = p/m, P = (g-1)(E - m v^2/2)/V.
 // Fills the primitive record (W and s_i - r_i, whole); in the mixed mode
-// (T = float) the velocity stored is v_i - w_i. Returns the cell's sound
-// speed (0 unless rho > 0 and P > 0) and sets v (lab frame), |v - w|^2, the
-// radius R of the cell's volume and ok = (rho > 0 and P > 0). Cells with
-// m <= 0 are vacuum: W = 0, v = 0.
+// (T = float) the velocity stored is v_i - W0, rounded once from double, W0
+// the reference velocity w0 [D] (device). Returns the cell's sound speed (0
+// unless rho > 0 and P > 0) and sets v (lab frame), |v - w|^2, the radius R
+// of the cell's volume and ok = (rho > 0 and P > 0). Cells with m <= 0 are
+// vacuum: rho = P = 0, v = 0.
 template <int D, typename T>
 __device__ __forceinline__ double cell_prim(int64_t i, int64_t n, double gamma, const double *__restrict__ V,
                                             const double *__restrict__ Q, const double *__restrict__ mvel,
-                                            const double *__restrict__ coff, T (&r)[Lay<D>::PREC], double (&v)[D],
-                                            double &rel2, double &R, bool &ok) {
+                                            const double *__restrict__ coff, const double *__restrict__ w0,
+                                            T (&r)[Lay<D>::PREC], double (&v)[D], double &rel2, double &R, bool &ok) {
     using Y = Lay<D>;
     constexpr int NV = D + 2;
     constexpr bool rel = sizeof(T) == 4;
     for (int k = 0; k < Y::PREC; k++) r[k] = (T)0;
-    for (int k = 0; k < D; k++) { r[Y::DL + k] = (T)coff[k * n + i]; v[k] = 0.0; }
+    for (int k = 0; k < D; k++) {
+        r[Y::DL + k] = (T)coff[k * n + i];
+        v[k] = 0.0;
+        if (rel) r[Y::W + 1 + k] = (T)(0.0 - w0[k]);
+    }
     rel2 = 0.0;
     R = 0.0;
     ok = false;
@@ -95,7 +100,7 @@ __device__ __forceinline__ double cell_prim(int64_t i, int64_t n, double gamma, 
         ke += v[k] * v[k];
         const double dv = v[k] - mvel[k * n + i];
         rel2 += dv * dv;
-        r[Y::W + 1 + k] = rel ? (T)dv : (T)v[k];
+        r[Y::W + 1 + k] = rel ? (T)(v[k] - w0[k]) : (T)v[k];
     }
     const double rho = m / vol;
     const double P = (gamma - 1.0) * (Q[(NV - 1) * n + i] - 0.5 * m * ke) / vol;
@@ -107,37 +112,18 @@ __device__ __forceinline__ double cell_prim(int64_t i, int64_t n, double gamma, 
     return sqrt(gamma * P / rho);
 }
 
-// The gather record of a cell (mixed mode) from its float primitive record
-// and its double lab velocity v (0 for vacuum): rho, v_i - W0, P, then
-// w_i - W0, each velocity difference rounded to float from double, W0 the
-// reference velocity w0 [D] (device).
-template <int D>
-__device__ __forceinline__ void gather_rec(int64_t i, int64_t n, const float (&r)[Lay<D>::PREC], const double (&v)[D],
-                                           const double *__restrict__ mvel, const double *__restrict__ w0,
-                                           float (&g)[Lay<D>::GATH]) {
-    using Y = Lay<D>;
-    for (int k = 0; k < Y::GATH; k++) g[k] = 0.0f;
-    g[Y::W] = r[Y::W];
-    g[Y::W + Y::NV - 1] = r[Y::W + Y::NV - 1];
-    for (int k = 0; k < D; k++) {
-        g[Y::W + 1 + k] = (float)(v[k] - w0[k]);
-        g[Y::GW + k] = (float)(mvel[k * n + i] - w0[k]);
-    }
-}
-
 // Step (ii) and the timestep bound of step (v) (Section 7.1): the primitive
 // record of every cell (cell_prim) and the per-block minimum of
 //   dt_i = C R_i / (c_i + |v_i - w_i|), R_i the radius of the cell's volume;
 // vacuum cells impose no limit. As the first kernel of a step it clears the
-// step's non-finite flag (step_flag, may be null).
-// In the mixed mode (T = float) also the gather records (gather, with the
-// reference velocity w0).
+// step's non-finite flag (step_flag, may be null). w0: the mixed mode's
+// reference velocity (null in double).
 template <int D, typename T>
 __global__ void __launch_bounds__(kBlock) k_prim_cfl(int64_t n, double gamma, double cfl, const double *__restrict__ V,
                                                      const double *__restrict__ Q, const double *__restrict__ mvel,
                                                      const double *__restrict__ coff, T *__restrict__ prim,
-                                                     float *__restrict__ gather, const double *__restrict__ w0,
-                                                     double *__restrict__ dt_part, int32_t *step_flag) {
+                                                     const double *__restrict__ w0, double *__restrict__ dt_part,
+                                                     int32_t *step_flag) {
     using Y = Lay<D>;
     const int64_t i = xcd_global_id();
     if (step_flag && blockIdx.x == 0 && threadIdx.x == 0) *step_flag = 0;
@@ -146,14 +132,9 @@ __global__ void __launch_bounds__(kBlock) k_prim_cfl(int64_t n, double gamma, do
         T r[Y::PREC];
         double v[D], rel2, R;
         bool ok;
-        const double c = cell_prim<D, T>(i, n, gamma, V, Q, mvel, coff, r, v, rel2, R, ok);
+        const double c = cell_prim<D, T>(i, n, gamma, V, Q, mvel, coff, w0, r, v, rel2, R, ok);
         if (ok) dti = cfl * R / (c + sqrt(rel2));
         store_rec<Y::PREC>(prim + i * Y::PREC, r);
-        if constexpr (sizeof(T) == 4) {
-            float g[Y::GATH];
-            gather_rec<D>(i, n, r, v, mvel, w0, g);
-            store_rec<Y::GATH>(gather + i * Y::GATH, g);
-        }
     }
     dti = block_min(dti);
     if (threadIdx.x == 0) dt_part[xcd_tile()] = dti;
@@ -172,10 +153,10 @@ __global__ void __launch_bounds__(1024) k_min_final(int64_t nparts, const double
     }
 }
 
-// The reference velocity W0 of the mixed mode's gather records: per
-// component the midrange (min + max)/2 of the generator velocities, which
-// makes the largest |w_i - W0| (and so the float rounding of w_i - W0) as
-// small as it can be. Per-block minima and maxima part [grid][2D], then one
+// The reference velocity W0 of the mixed mode's records: per component the
+// midrange (min + max)/2 of the generator velocities, which makes the
+// largest |w_i - W0| (and so the float rounding of velocities relative to
+// W0 on a mesh that follows the flow) as small as it can be. Per-block minima and maxima part [grid][2D], then one
 // block for w0 [D]; both order-independent.
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_w0_part(int64_t n, const double *__restrict__ mvel,
@@ -247,7 +228,7 @@ __global__ void __launch_bounds__(kBlock) k_w0_final(int64_t nparts, const doubl
 // sides with |Dl| <= tol never hold that maximum unless no side exceeds tol,
 // so the lanes keep plain maxima and minima of Dl and the tolerance is
 // applied once per cell.
-// Mixed mode (T = float): the gather records hold velocities relative to
+// Mixed mode (T = float): the primitive records hold velocities relative to
 // the reference velocity W0 (the midrange of the generator velocities), so
 // the velocity difference across a side is
 //   v_j - v_i = (v_j - W0) - (v_i - W0)
@@ -291,49 +272,40 @@ __device__ __forceinline__ void limit_side(const T *g, const T *dl, const T (&gr
 // The energy switch's neighbour term (Section 3.5, eq. eqnScrit1): the
 // kinetic energy of neighbour j in the frame of cell i's generator,
 // M_j |v_j - w_i|^2 / 2 with M_j = rho_j V_j (0 for a vacuum neighbour), from
-// j's values pj as the gradient pass reads them: double primitive records
-// hold v_j (wlab = w_i); float gather records hold v_j - W0, and cell i's
-// record w_i - W0 (in wi), so v_j - w_i = (v_j - W0) - (w_i - W0).
-// In the records' precision: the float form's velocities carry float
-// rounding already, and the switch compares this with the cell's thermal
-// energy at a threshold alpha far above it.
+// j's values pj as the gradient pass reads them: the primitive records hold
+// v_j (double) or v_j - W0 (float), and wg is w_i in the same frame, so
+// v_j - w_i = pj's velocity - wg. In the records' precision: the float
+// form's velocities carry float rounding already, and the switch compares
+// this with the cell's thermal energy at a threshold alpha far above it.
 template <int D, typename T>
-__device__ __forceinline__ T ekin_in_frame(const T *pj, const T *wi, double Vj, const double (&wlab)[D]) {
+__device__ __forceinline__ T ekin_in_frame(const T *pj, double Vj, const double (&wg)[D]) {
     T e = (T)0;
     for (int k = 0; k < D; k++) {
-        const T dv = sizeof(T) == 4 ? pj[1 + k] - wi[Lay<D>::GW + k] : pj[1 + k] - (T)wlab[k];
+        const T dv = pj[1 + k] - (T)wg[k];
         e += dv * dv;
     }
     return pj[0] > (T)0 ? (T)0.5 * (pj[0] * (T)Vj) * e : (T)0;
 }
 
-// The gradient and limiter of cell i by its lane group (lane = index in
-// the group); every lane of the group calls it with the same i. gath: the
-// gather records (mixed mode; unused in double, where the neighbours'
-// primitive records serve). With ESW, also the energy switch's largest
-// neighbour kinetic energy in the frame of the cell's generator, into
-// ekmax[i] (the states are the step's start states, those the gradient is
-// taken from; mvel the generator velocities). win: the block's window of
-// gather records, starting at cell c0 (null: every record from HBM).
-// The gradient kernel's window (mixed mode): the gather records of the kGWin
-// cells centred on its block's 64 cells, staged in LDS once per block. Cells
-// are in Morton order, so most neighbours of a block's cells fall inside it
-// (about 60% on a Poisson mesh); the rest are gathered from HBM.
+// The gradient kernel's window (mixed mode): the primitive records of the
+// kGWin cells centred on its block's 64 cells, staged in LDS once per block.
+// Cells are in Morton order, so most neighbours of a block's cells fall
+// inside it (about 60% on a Poisson mesh); the rest are gathered from HBM.
 constexpr int kGWin = 128;
-// The record of neighbour j: from the window when it holds j, else from the
-// records nrec of stride NSs.
+// W of neighbour j (its primitive record's first D + 2 values): from the
+// window when it holds j, else from the records prim.
 template <int D, typename T>
-__device__ __forceinline__ void load_nb(const T *__restrict__ nrec, int64_t j, int NSs, const float *win, int64_t c0,
-                                        T (&o)[sizeof(T) == 4 ? Lay<D>::GATH : D + 2]) {
-    constexpr int NJ = sizeof(T) == 4 ? Lay<D>::GATH : D + 2;
+__device__ __forceinline__ void load_nb(const T *__restrict__ prim, int64_t j, const float *win, int64_t c0,
+                                        T (&o)[D + 2]) {
+    constexpr int NJ = D + 2, PREC = Lay<D>::PREC;
     if constexpr (sizeof(T) == 4) {
         const int64_t k = j - c0;
         if (win && k >= 0 && k < kGWin) {
-            load_rec_lds<NJ>((lds_cfloat *)win + k * NJ, o);
+            load_rec_lds<NJ>((lds_cfloat *)win + k * PREC, o);
             return;
         }
     }
-    load_rec<NJ>(nrec + j * NSs, o);
+    load_rec<NJ>(prim + j * PREC + Lay<D>::W, o);
 }
 
 // The volume of neighbour j (energy switch): from the window's volumes vwin
@@ -345,12 +317,21 @@ __device__ __forceinline__ double nb_vol(const double *__restrict__ V, int64_t j
     return V[j];
 }
 
+// The gradient and limiter of cell i by its lane group (lane = index in
+// the group); every lane of the group calls it with the same i. The
+// neighbours' W come from their primitive records. With ESW, also the
+// energy switch's largest neighbour kinetic energy in the frame of the
+// cell's generator, into ekmax[i] (the states are the step's start states,
+// those the gradient is taken from; mvel the generator velocities, w0 the
+// mixed mode's reference velocity). win: the block's window of primitive
+// records, starting at cell c0 (null: every record from HBM); vwin the
+// window's volumes.
 template <int D, typename T, bool ESW = false>
 __device__ __forceinline__ void grad_cell(int64_t i, int lane, const int32_t *__restrict__ off,
                                           const int32_t *__restrict__ nbr, const T *__restrict__ srec,
                                           const double *__restrict__ V, const T *__restrict__ prim,
-                                          const float *__restrict__ gath, T *__restrict__ grad_out,
-                                          const double *__restrict__ mvel = nullptr, int64_t n = 0,
+                                          T *__restrict__ grad_out, const double *__restrict__ mvel = nullptr,
+                                          const double *__restrict__ w0 = nullptr, int64_t n = 0,
                                           double *__restrict__ ekmax = nullptr, const float *win = nullptr,
                                           int64_t c0 = 0, const double *vwin = nullptr) {
     using Y = Lay<D>;
@@ -359,10 +340,8 @@ __device__ __forceinline__ void grad_cell(int64_t i, int lane, const int32_t *__
     constexpr bool mixed = sizeof(T) == 4;
     constexpr int KR = mixed ? (ESW ? 3 : 5) : 3;   // sides per lane held in registers
     constexpr int SR = mixed ? Y::SREC32 : Y::SREC64;
-    constexpr int NJ = mixed ? Y::GATH : NV;   // values read of a neighbour
+    constexpr int NJ = NV;   // values read of a neighbour: its W
     const T eps_t = mixed ? (T)1e-6 : (T)1e-13;
-    const T *nrec = mixed ? (const T *)gath : prim + Y::W;
-    constexpr int NS = mixed ? Y::GATH : Y::PREC;   // their stride
     const int32_t b = off[i], e = off[i + 1];
     // the lane's first KR sides: side records and neighbour indices, then
     // the neighbours' records, all in flight together (an absent side reads
@@ -376,12 +355,12 @@ __device__ __forceinline__ void grad_cell(int64_t i, int lane, const int32_t *__
         const int32_t qq = has[r] ? q : 0;
         load_rec<SR>(srec + (int64_t)qq * SR, sr[r]);
         const int32_t jn = nbr[qq];
-        load_nb<D, T>(nrec, jn, NS, win, c0, pj[r]);
+        load_nb<D, T>(prim, jn, win, c0, pj[r]);
         if constexpr (ESW) vj[r] = nb_vol(V, jn, vwin, c0);
     }
-    T pi[Y::PREC], wi[NJ];
+    T pi[Y::PREC];
     load_rec<Y::PREC>(prim + i * Y::PREC, pi);
-    load_nb<D, T>(nrec, i, NS, win, c0, wi);
+    const T *wi = pi + Y::W;
     const T *dl = pi + Y::DL;
     SideAcc<D, T> a;
     for (int c = 0; c < NV; c++) {
@@ -391,20 +370,20 @@ __device__ __forceinline__ void grad_cell(int64_t i, int lane, const int32_t *__
     }
     double wlab[D];
     T ek = (T)0;
-    if constexpr (ESW)
-        for (int k = 0; k < D; k++) wlab[k] = mixed ? 0.0 : mvel[k * n + i];
+    if constexpr (ESW)   // the cell's generator velocity, in the records' frame
+        for (int k = 0; k < D; k++) wlab[k] = mixed ? mvel[k * n + i] - w0[k] : mvel[k * n + i];
     for (int r = 0; r < KR; r++)
         if (has[r]) {
             grad_side<D, T>(sr[r], pj[r], wi, a);
-            if constexpr (ESW) ek = fmax(ek, ekin_in_frame<D, T>(pj[r], wi, vj[r], wlab));
+            if constexpr (ESW) ek = fmax(ek, ekin_in_frame<D, T>(pj[r], vj[r], wlab));
         }
     for (int32_t q = b + lane + KR * GS; q < e; q += GS) {
         T s2[SR], p2[NJ];
         load_rec<SR>(srec + (int64_t)q * SR, s2);
         const int32_t j = nbr[q];
-        load_nb<D, T>(nrec, j, NS, win, c0, p2);
+        load_nb<D, T>(prim, j, win, c0, p2);
         grad_side<D, T>(s2, p2, wi, a);
-        if constexpr (ESW) ek = fmax(ek, ekin_in_frame<D, T>(p2, wi, nb_vol(V, j, vwin, c0), wlab));
+        if constexpr (ESW) ek = fmax(ek, ekin_in_frame<D, T>(p2, nb_vol(V, j, vwin, c0), wlab));
     }
     if constexpr (ESW) {
         ek = grp_max<GS>(ek);
@@ -460,8 +439,8 @@ __device__ __forceinline__ void grad_cell(int64_t i, int lane, const int32_t *__
 template <int D, typename T, bool ESW>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : (ESW ? 3 : 4))))
 k_grad_limit(int64_t n, const int32_t *__restrict__ off, const int32_t *__restrict__ nbr, const T *__restrict__ srec,
-             const double *__restrict__ V, const T *__restrict__ prim, const float *__restrict__ gath,
-             T *__restrict__ grad_out, const double *__restrict__ mvel, double *__restrict__ ekmax) {
+             const double *__restrict__ V, const T *__restrict__ prim, T *__restrict__ grad_out,
+             const double *__restrict__ mvel, const double *__restrict__ w0, double *__restrict__ ekmax) {
     constexpr int GS = Group<D>::GS;
     const int64_t i = xcd_tile() * (kBlock / GS) + threadIdx.x / GS;
     // mixed mode: stage the window (every lane takes part in the copy and the
@@ -470,12 +449,13 @@ k_grad_limit(int64_t n, const int32_t *__restrict__ off, const int32_t *__restri
     const double *vwin = nullptr;
     int64_t c0 = 0;
     if constexpr (sizeof(T) == 4) {
-        __shared__ float wbuf[kGWin * Lay<D>::GATH];
+        constexpr int PREC = Lay<D>::PREC;
+        __shared__ float wbuf[kGWin * PREC];
         c0 = xcd_tile() * (kBlock / GS) - (kGWin - kBlock / GS) / 2;
-        for (int e = threadIdx.x; e < kGWin * Lay<D>::GATH / 4; e += kBlock) {
-            const int64_t j = c0 + e / (Lay<D>::GATH / 4);
+        for (int e = threadIdx.x; e < kGWin * PREC / 4; e += kBlock) {
+            const int64_t j = c0 + e / (PREC / 4);
             f32x4u v = {0.0f, 0.0f, 0.0f, 0.0f};
-            if (j >= 0 && j < n) v = *reinterpret_cast<const f32x4u *>(gath + j * Lay<D>::GATH + (e % (Lay<D>::GATH / 4)) * 4);
+            if (j >= 0 && j < n) v = *reinterpret_cast<const f32x4u *>((const float *)prim + j * PREC + (e % (PREC / 4)) * 4);
             *reinterpret_cast<f32x4u *>(wbuf + e * 4) = v;
         }
         if constexpr (ESW) {   // and the window's volumes
@@ -490,8 +470,7 @@ k_grad_limit(int64_t n, const int32_t *__restrict__ off, const int32_t *__restri
         win = wbuf;
     }
     if (i >= n) return;  // whole groups leave together
-    grad_cell<D, T, ESW>(i, threadIdx.x % GS, off, nbr, srec, V, prim, gath, grad_out, mvel, n, ekmax, win, c0,
-                         vwin);
+    grad_cell<D, T, ESW>(i, threadIdx.x % GS, off, nbr, srec, V, prim, grad_out, mvel, w0, n, ekmax, win, c0, vwin);
 }
 
 // The total entropy of every cell from its conserved state (Section 3.5):

@@ -592,9 +592,8 @@ __global__ void __launch_bounds__(kBlock) k_face_flux64(int64_t nf, const int32_
 
 // Float face-frame states of one face for the mixed path: reconstruction,
 // frame transform and half step on velocities relative to the face (the
-// cell record holds v_i - w_i and w_K - w_f follows from the face record's
-// w_L - w_R, so v - w_f = (v_K - w_K) + (w_K - w_f) never forms a lab-frame
-// velocity).
+// cell record holds v_K - W0 and the face record w_f - W0, both rounded
+// from double, so v_K - w_f never forms a lab-frame velocity in float).
 template <int D> struct MixedFace {
     float xl[D + 2], xr[D + 2], uL, uR, nrm[D], A;
     bool posfb;
@@ -618,20 +617,17 @@ __device__ __forceinline__ MixedFace<D> mixed_face_states(int64_t f, const int32
     const CellRec<D, float> rr = load_cell_w<D>(prim, grad, r, win);
     o.A = fr[Y::FA];
     const float hl = 0.5f * fr[Y::FELL];
-    float gL[D], gR[D], cl[NV], cr[NV], vf[D], dw[D], proj = 0.0f;
+    float gL[D], gR[D], cl[NV], cr[NV], vf[D];
     for (int k = 0; k < D; k++) {
         o.nrm[k] = fr[Y::FN + k];
         const float c = fr[Y::FC + k];
         gL[k] = c + hl * o.nrm[k];
         gR[k] = c - hl * o.nrm[k];
-        dw[k] = fr[Y::MDW + k];
-        proj += dw[k] * c;
     }
-    // w_L - w_f = dw/2 - (dw.c/|d|) n and w_R - w_f = -dw/2 - (dw.c/|d|) n
-    proj *= 0.5f / hl;
-    for (int k = 0; k < D; k++) vf[k] = rl.p[Y::W + 1 + k] + (0.5f * dw[k] - proj * o.nrm[k]);
+    // v_K - w_f = (v_K - W0) - (w_f - W0)
+    for (int k = 0; k < D; k++) vf[k] = rl.p[Y::W + 1 + k] - fr[Y::MWF + k];
     half_step<D, float>(rl, vf, gL, gam, hdtL, o.xl, cl);
-    for (int k = 0; k < D; k++) vf[k] = rr.p[Y::W + 1 + k] + (-0.5f * dw[k] - proj * o.nrm[k]);
+    for (int k = 0; k < D; k++) vf[k] = rr.p[Y::W + 1 + k] - fr[Y::MWF + k];
     half_step<D, float>(rr, vf, gR, gam, hdtR, o.xr, cr);
     if constexpr (GRAV) {   // the half-step kick of a static field (Section 5.2)
         for (int k = 0; k < D; k++) {

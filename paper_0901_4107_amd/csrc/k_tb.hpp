@@ -125,8 +125,7 @@ __global__ void __launch_bounds__(kBlock) k_tb_open(int64_t n, int32_t *__restri
                                                     double gamma, const double *__restrict__ V,
                                                     const double *__restrict__ Q, const double *__restrict__ mvel,
                                                     const double *__restrict__ coff, T *__restrict__ prim,
-                                                    float *__restrict__ gather, const double *__restrict__ w0,
-                                                    double *__restrict__ sig, int32_t *__restrict__ list,
+                                                    const double *__restrict__ w0, double *__restrict__ sig, int32_t *__restrict__ list,
                                                     int64_t cap) {
     using Y = Lay<D>;
     constexpr int SG = D + 2;
@@ -142,13 +141,8 @@ __global__ void __launch_bounds__(kBlock) k_tb_open(int64_t n, int32_t *__restri
             T r[Y::PREC];
             double v[D], rel2, R;
             bool ok;
-            const double c = cell_prim<D, T>(i, n, gamma, V, Q, mvel, coff, r, v, rel2, R, ok);
+            const double c = cell_prim<D, T>(i, n, gamma, V, Q, mvel, coff, w0, r, v, rel2, R, ok);
             store_rec<Y::PREC>(prim + i * Y::PREC, r);
-            if constexpr (sizeof(T) == 4) {   // the mixed mode's gather record
-                float g[Y::GATH];
-                gather_rec<D>(i, n, r, v, mvel, w0, g);
-                store_rec<Y::GATH>(gather + i * Y::GATH, g);
-            }
             double s[SG];
             s[0] = c;
             for (int k = 0; k < D; k++) s[1 + k] = v[k];
@@ -190,7 +184,7 @@ k_tb_active(const int32_t *__restrict__ list, int64_t cap, double dt_max, int32_
             const int32_t *__restrict__ off, const int32_t *__restrict__ ent, const int32_t *__restrict__ nbr,
             const double *__restrict__ frec, const double *__restrict__ sig, int8_t *__restrict__ bin,
             int32_t *__restrict__ info, const T *__restrict__ srec, const double *__restrict__ V,
-            const T *__restrict__ prim, const float *__restrict__ gath, T *__restrict__ grad_out,
+            const T *__restrict__ prim, T *__restrict__ grad_out,
             int32_t *__restrict__ touch,
             int32_t *__restrict__ faces, int64_t fcap, int32_t *__restrict__ touched, int64_t tcap) {
     using Y = Lay<D>;
@@ -250,7 +244,7 @@ k_tb_active(const int32_t *__restrict__ list, int64_t cap, double dt_max, int32_
             }
         }
         // 2
-        grad_cell<D, T>(i, lane, off, nbr, srec, V, prim, gath, grad_out);
+        grad_cell<D, T>(i, lane, off, nbr, srec, V, prim, grad_out);
         // 3
         if (claim_faces) {   // the same for the whole grid
             list_append(touched, tcap, lane == 0, (int32_t)i);

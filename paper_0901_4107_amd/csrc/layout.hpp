@@ -7,19 +7,16 @@
 //   gradient block  [N][GREC]: limited gradient, element c*D + k = dW_c/dx_k,
 //                              padding to 16 (3D) / 8 (2D)
 // In double precision the velocities are lab-frame; in the mixed mode the
-// records are float and hold v_i - w_i.
-// Gather record (mixed mode), one per cell [N][GATH], what a neighbour's
-// gradient pass reads of a cell: rho, v_i - W0 (D), P, w_i - W0 (D), padding
-// to 8; W0 the midrange of the generator velocities (a bulk motion the mesh
-// follows leaves these differences small, so it costs no float bits).
+// records are float and hold v_i - W0, W0 the midrange of the generator
+// velocities (a bulk motion the mesh follows leaves these differences small,
+// so it costs no float bits).
 //
 // Face record (double geometry), one per face, 64-byte aligned in 3D:
 //   A, |d|, n (D) = d/|d|, c (D) = f - (r_L + r_R)/2;
 // the double face velocity w_f in its own array, D per face (both paths).
 // Mixed face record (float), one per face:
-//   A, |d|, n (D), c (D), dw (D) = w_L - w_R;
-//   the generators' velocities relative to the face follow from dw:
-//   w_L - w_f = dw/2 - (dw.c/|d|) n,  w_R - w_f = -dw/2 - (dw.c/|d|) n;
+//   A, |d|, n (D), c (D), w_f - W0 (D), rounded once from double; with the
+//   cells' v_K - W0 the face-frame velocities are (v_K - W0) - (w_f - W0);
 // Face fluxes: face-major, D + 2 doubles per face.
 // Side record, one per (cell, face) pair in CSR order:
 //   double path: A/|d|, f - r_i (D)             stride 4
@@ -39,7 +36,7 @@ template <int D> struct Lay {
     static constexpr int FA = 0, FELL = 1, FN = 2, FC = 2 + D;
     static constexpr int FREC = 2 + 2 * D;
     // mixed face record
-    static constexpr int MDW = 2 + 2 * D;
+    static constexpr int MWF = 2 + 2 * D;
     static constexpr int MREC = 2 + 3 * D;
     static constexpr int WSTRIDE = D;
     // face fluxes
@@ -47,8 +44,6 @@ template <int D> struct Lay {
     // side records
     static constexpr int SREC64 = 4;
     static constexpr int SREC32 = 4;
-    // gather records (mixed mode)
-    static constexpr int GATH = 8, GW = NV;   // w_i - W0 at element GW
 };
 
 }  // namespace mm

@@ -62,7 +62,7 @@ struct Layout {
     int64_t loff, roff, rface;              // the update's left ranges and right faces
     int64_t ekmax;                          // energy switch: neighbour energies per cell
     int64_t srec, frec, wf64, rec, flux;    // double path (frec, wf64 always; flux: timelines only)
-    int64_t srec32, mrec, rec32, hard, gath, w0, w0part;       // mixed path
+    int64_t srec32, mrec, rec32, hard, w0, w0part;             // mixed path
     int64_t tb_bin, tb_trec, tb_sig, tb_touch, tb_cells, tb_faces, tb_touched, tb_info;   // individual timesteps
     int64_t total;
 };
@@ -98,13 +98,12 @@ Layout make_layout(int D, int mode, int em, bool tb, int64_t n, int64_t nf) {
     L.rface = take(nf * sizeof(int32_t));
     L.flux = take(nf * FM * sizeof(double));
     L.ekmax = em == MM_ENTROPY_ENERGY ? take(n * sizeof(double)) : -1;
-    L.srec = L.srec32 = L.mrec = L.rec32 = L.rec = L.hard = L.gath = L.w0 = L.w0part = -1;
+    L.srec = L.srec32 = L.mrec = L.rec32 = L.rec = L.hard = L.w0 = L.w0part = -1;
     if (mode == MM_FP64) {
         L.srec = take(2 * nf * Lay<3>::SREC64 * sizeof(double));
         L.rec = take(n * REC * sizeof(double));
     } else {
         L.srec32 = take(2 * nf * Lay<3>::SREC32 * sizeof(float));
-        L.gath = take(n * Lay<3>::GATH * sizeof(float));
         L.w0 = take(4 * sizeof(double));
         L.w0part = take((int64_t)plain_grid_n(n) * 2 * 3 * sizeof(double));
         L.mrec = take(nf * Lay<3>::MREC * sizeof(float));
@@ -294,20 +293,21 @@ template <int D> static void launch_validate(mm_ctx *c, const mm_mesh *m, int32_
                                                                         m->mesh_vel, flags);
 }
 
-// Face records and, in the mixed mode, the reference velocity W0 of the
-// gather records: everything that depends on the generator velocities;
-// with so.ent (the upload) also the side records.
+// The mixed mode's reference velocity W0 (the midrange of the generator
+// velocities) and the face records: everything that depends on the
+// generator velocities; with so.ent (the upload) also the side records.
 template <int D> static void launch_face_records(mm_ctx *c, const mm_mesh *m, const SideOut &so = SideOut{}) {
     const Layout &L = c->lay;
     const int mixed = c->p.mode == MM_MIXED;
-    k_face_records<D><<<plain_grid(m->n_faces), kBlock, 0, c->st()>>>(
-        m->n_cells, m->n_faces, m->face_L, m->face_R, m->face_area, m->face_ctr, m->face_sep, m->mesh_vel,
-        c->at<double>(L.frec), mixed, mixed ? c->at<float>(L.mrec) : nullptr, c->at<double>(L.wf64), so);
     if (mixed) {
         const unsigned g = plain_grid(m->n_cells);
         k_w0_part<D><<<g, kBlock, 0, c->st()>>>(m->n_cells, m->mesh_vel, c->at<double>(L.w0part));
         k_w0_final<D><<<1, kBlock, 0, c->st()>>>(g, c->at<double>(L.w0part), c->at<double>(L.w0));
     }
+    k_face_records<D><<<plain_grid(m->n_faces), kBlock, 0, c->st()>>>(
+        m->n_cells, m->n_faces, m->face_L, m->face_R, m->face_area, m->face_ctr, m->face_sep, m->mesh_vel,
+        c->at<double>(L.frec), mixed, mixed ? c->at<float>(L.mrec) : nullptr, mixed ? c->at<double>(L.w0) : nullptr,
+        c->at<double>(L.wf64), so);
 }
 
 mm_status mm_mesh_upload(mm_ctx *c, const mm_mesh *m) {
@@ -415,20 +415,19 @@ template <int D, typename T> static mm_status gradients_t(mm_ctx *c, const doubl
     hipStream_t s = c->st();
     const bool f64 = sizeof(T) == 8;
     const T *srec = f64 ? (const T *)c->at<double>(L.srec) : (const T *)c->at<float>(L.srec32);
-    float *gath = f64 ? nullptr : c->at<float>(L.gath);
     const double *w0 = f64 ? nullptr : c->at<double>(L.w0);
     k_prim_cfl<D, T><<<grid_for(c->n), kBlock, 0, s>>>(c->n, c->p.gamma, c->p.cfl, c->mesh.volume, Q,
-                                                      c->mesh.mesh_vel, c->mesh.centroid_off, rec, gath, w0,
-                                                      dt_part, c->at<int32_t>(L.flags) + 2);
+                                                      c->mesh.mesh_vel, c->mesh.centroid_off, rec, w0, dt_part,
+                                                      c->at<int32_t>(L.flags) + 2);
     if (c->p.entropy == MM_ENTROPY_ENERGY) {   // with the energy switch's neighbour energies
         k_grad_limit<D, T, true><<<group_grid(D, c->n), kBlock, 0, s>>>(
-            c->n, c->at<int32_t>(L.off), c->at<int32_t>(L.nbr), srec, c->mesh.volume, rec, gath, grad_block<D>(c, rec),
-            c->mesh.mesh_vel, c->at<double>(L.ekmax));
+            c->n, c->at<int32_t>(L.off), c->at<int32_t>(L.nbr), srec, c->mesh.volume, rec, grad_block<D>(c, rec),
+            c->mesh.mesh_vel, w0, c->at<double>(L.ekmax));
         c->have_ek = true;
     } else {
         k_grad_limit<D, T, false><<<group_grid(D, c->n), kBlock, 0, s>>>(
-            c->n, c->at<int32_t>(L.off), c->at<int32_t>(L.nbr), srec, c->mesh.volume, rec, gath, grad_block<D>(c, rec),
-            nullptr, nullptr);
+            c->n, c->at<int32_t>(L.off), c->at<int32_t>(L.nbr), srec, c->mesh.volume, rec, grad_block<D>(c, rec),
+            nullptr, nullptr, nullptr);
     }
     MM_LAUNCH_CHECK();
     return MM_OK;
@@ -971,14 +970,13 @@ template <int D, typename T> static void tb_point(mm_ctx *c, double *Q, T *rec) 
     T *grad = grad_block<D>(c, rec);
     int32_t *hard = mixed ? c->at<int32_t>(L.hard) : nullptr;
     const int32_t *off = c->at<int32_t>(L.off), *ent = c->at<int32_t>(L.ent), *nbr = c->at<int32_t>(L.nbr);
-    float *gath = mixed ? c->at<float>(L.gath) : nullptr;
     const double *w0 = mixed ? c->at<double>(L.w0) : nullptr;
     k_tb_open<D, T><<<grid_for(c->n), kBlock, 0, s>>>(c->n, info, bin, trec, c->p.gamma, c->mesh.volume, Q,
-                                                      c->mesh.mesh_vel, c->mesh.centroid_off, rec, gath, w0, sig,
-                                                      cells, ccap);
+                                                      c->mesh.mesh_vel, c->mesh.centroid_off, rec, w0, sig, cells,
+                                                      ccap);
     k_tb_active<D, T><<<kTbGrid, kBlock, 0, s>>>(cells, ccap, tb.dt_max, tb.levels, c->p.cfl, off, ent, nbr,
                                                  c->at<double>(L.frec), sig, bin, info, srec, c->mesh.volume, rec,
-                                                 gath, grad, touch, faces, fcap, touched, tcap);
+                                                 grad, touch, faces, fcap, touched, tcap);
     k_tb_faces<<<kTbGrid, kBlock, 0, s>>>(c->nf, c->mesh.face_L, c->mesh.face_R, bin, info, touch, faces, fcap);
     const TbView view{bin, trec, 0, tb.dt_max, tb.levels, info};
     DiagDev *diag = c->at<DiagDev>(L.diag);
