@@ -497,7 +497,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=25,
+                    help="untimed steps first (with 3 the first form timed in a process ran 2-4%% slow: the clocks ramp)")
     ap.add_argument("--workload", default="kh3d", choices=["kh3d", "random3d", "sedov3d", "rt3d", "riemann"])
     ap.add_argument("--size", type=int, default=0, help="points per axis (lattice) or cube root of the point count")
     ap.add_argument("--mode", default="mixed+learned", choices=["fp64", "fp64+learned", "mixed", "mixed+learned"])
