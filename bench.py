@@ -39,6 +39,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Riemann face fluxes/sec, 3D 128³ Voronoi; mixed+learned vs FP64 at set error"
 HBM_PEAK_GBS = 8000.0
+WARM_S = 0.25          # seconds of untimed steps before each form is timed, at least
 SET_ERROR = 1e-6   # rest-frame L1 per conserved component, mixed forms vs double
 
 
@@ -139,8 +140,15 @@ def time_form(mm, learned, torch, wl, dmesh, form, steps, warmup, dev, mach_thre
     # W untimed steps, then exactly K timed consecutive steps (Courant
     # timestep recomputed on the device each step), bracketed by device
     # synchronisation
-    for _ in range(warmup):
+    # W untimed steps, and at least WARM_S seconds of them: the clocks take
+    # longer than a few steps to ramp
+    t_warm = time.perf_counter()
+    k = 0
+    while k < warmup or time.perf_counter() - t_warm < WARM_S:
         ctx.mm_hydro_step(Q, sync=False)
+        k += 1
+        if k % 10 == 0:
+            torch.cuda.synchronize()
     torch.cuda.synchronize()
     # totals over the domain: the mirror cells of walls are excluded
     keep = (slice(None) if wl.walls is None else
@@ -164,7 +172,7 @@ def time_form(mm, learned, torch, wl, dmesh, form, steps, warmup, dev, mach_thre
     cons = (torch.abs(tot1 - tot0) / scale).cpu().numpy()
     # the dominant kernel alone, on the initial state's records
     ctx.mm_gradients(Q0, rec)
-    for _ in range(warmup):
+    for _ in range(max(warmup, 10)):
         ctx.mm_face_fluxes(dt, rec, F)
     torch.cuda.synchronize()
     fev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * steps)]
@@ -498,7 +506,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=25,
-                    help="untimed steps first (with 3 the first form timed in a process ran 2-4%% slow: the clocks ramp)")
+                    help="untimed steps first, and at least 0.25 s of them (with 3 steps the first form timed in a "
+                         "process ran 2-4%% slow: the clocks ramp)")
     ap.add_argument("--workload", default="kh3d", choices=["kh3d", "random3d", "sedov3d", "rt3d", "riemann"])
     ap.add_argument("--size", type=int, default=0, help="points per axis (lattice) or cube root of the point count")
     ap.add_argument("--mode", default="mixed+learned", choices=["fp64", "fp64+learned", "mixed", "mixed+learned"])
