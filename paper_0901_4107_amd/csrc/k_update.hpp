@@ -150,9 +150,8 @@ __device__ __forceinline__ void count_kept(bool keep, DiagDev *diag) {
 // summed over the group; mx the group's largest face Mach number. live(f):
 // whether face f takes part (individual timesteps); the rest contribute
 // nothing. Each lane keeps up to KL left and KR right records in flight
-// together (3 and 3 for the plain records, 2 and 2 for the longer entropy
-// records), the rest in loops; the order of the sums does not depend on
-// KL and KR.
+// together (3 and 3; 2 and 2 for the Mach switch's 56-byte records), the
+// rest in loops; the order of the sums does not depend on KL and KR.
 template <int D, int EM, typename Live>
 __device__ __forceinline__ void cell_sums(int64_t i, int lane, const int32_t *__restrict__ lOff,
                                           const int32_t *__restrict__ rOff, const int32_t *__restrict__ rFace,
@@ -161,7 +160,7 @@ __device__ __forceinline__ void cell_sums(int64_t i, int lane, const int32_t *__
     using RC = Rec<D, EM>;
     constexpr int NS = RC::NS, FM = RC::FM;
     constexpr int GS = Group<D>::GS;
-    constexpr int KL = EM ? 2 : 3, KR = EM ? 2 : 3;
+    constexpr int KL = EM == 1 ? 2 : 3, KR = EM == 1 ? 2 : 3;
     for (int c = 0; c < NS; c++) acc[c] = 0.0;
     mx = 0.0;
     const int32_t l0 = lOff[i], l1 = lOff[i + 1], r0 = rOff[i], r1 = rOff[i + 1];
@@ -208,10 +207,10 @@ __device__ __forceinline__ void cell_sums(int64_t i, int lane, const int32_t *__
 
 // The update (the step, mm_apply_update): one lane group per cell. It waits
 // on its gathers: the plain kernel keeps 6 records per lane in flight at 6
-// wavefronts per SIMD (1.5% faster per step than 4 at 8); with the energy
-// switch the compiler alone would take 5 wavefronts where 7 fit.
+// wavefronts per SIMD (1.5% faster per step than 4 at 8), the energy
+// switch's 6 at 5 (1% faster per step than 4 at 7).
 template <int D, int EM, bool GRAV>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(EM == 1 ? 6 : (EM == 2 ? 7 : 6))))
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(EM == 1 ? 6 : (EM == 2 ? 5 : 6))))
 k_update(int64_t n, const int32_t *__restrict__ lOff, const int32_t *__restrict__ rOff,
          const int32_t *__restrict__ rFace, const double *__restrict__ flux, double *__restrict__ Q, UpdateArgs u) {
     using RC = Rec<D, EM>;
