@@ -85,14 +85,20 @@ def test_random_states_mixed_with_fp64_fallback():
     assert np.all(err <= 1e-5), err
 
 
-def test_mixed_galilean_invariance():
+@pytest.mark.parametrize("mach", [10.0, 1000.0])
+def test_mixed_galilean_invariance(mach):
     """The same KH run with and without the bulk boost (mesh comoving) gives
-    rest-frame results that agree to float precision: the boost is absorbed
-    into the face velocities and never enters the float arithmetic."""
+    rest-frame results that agree to float precision, at 10 and at 1000
+    sound speeds: the float records hold velocities relative to the
+    midrange of the generator velocities, so the boost is absorbed into the
+    double face velocities and never enters the float arithmetic."""
     a = kh3d(n_points=20 ** 3, seed=77, boost_mach=0.0)
-    b = kh3d(n_points=20 ** 3, seed=77, boost_mach=10.0)
+    b = kh3d(n_points=20 ** 3, seed=77, boost_mach=mach)
     Qa, _, _ = mixed_step(a, dt=1e-3)
     Qb, _, _ = mixed_step(b, dt=1e-3)
     err = l1_state(boost(Qb, -b.boost), Qa)
     print(f"mixed Galilean rest-frame L1 {err}", flush=True)
-    assert np.all(err <= 1e-7), err
+    # the float arithmetic sees the same numbers in both runs; what is left
+    # is the double rounding of the lab-frame fluxes and states at the
+    # boost's magnitude (measured 3e-15 at 10 and 3e-13 at 1000 sound speeds)
+    assert np.all(err <= 1e-10), err
