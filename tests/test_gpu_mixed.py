@@ -100,5 +100,7 @@ def test_mixed_galilean_invariance(mach):
     print(f"mixed Galilean rest-frame L1 {err}", flush=True)
     # the float arithmetic sees the same numbers in both runs; what is left
     # is the double rounding of the lab-frame fluxes and states at the
-    # boost's magnitude (measured 3e-15 at 10 and 3e-13 at 1000 sound speeds)
-    assert np.all(err <= 1e-10), err
+    # boost's magnitude, growing as its square in the energy (measured: mass
+    # 0; momentum 3e-15 and 3e-13, energy 1.3e-14 and 1.3e-10 at 10 and
+    # 1000 sound speeds)
+    assert np.all(err <= 1e-14 * (1.0 + mach ** 2)), err
