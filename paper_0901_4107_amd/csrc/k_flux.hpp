@@ -483,10 +483,12 @@ __device__ __forceinline__ void lab_flux(double rho, double u, double P, const d
 }
 
 // What the face bodies read besides the records: the static field
-// (GRAV, Section 5.2; accel [D][n], g = -grad Phi).
+// (GRAV, Section 5.2; accel [D][n], g = -grad Phi) and the mixed form's
+// reference velocity W0 (w0 [D]).
 struct FaceAux {
     const double *accel;
     int64_t n;
+    const double *w0 = nullptr;
 };
 
 // Double-precision flux of face f (dt A Fhat into F), the body of the face
@@ -603,6 +605,7 @@ template <int D, int EM, bool GRAV>
 __device__ __forceinline__ MixedFace<D> mixed_face_states(int64_t f, const int32_t *__restrict__ fL,
                                                           const int32_t *__restrict__ fR,
                                                           const float *__restrict__ mrec,
+                                                          const double *__restrict__ wf64,
                                                           const float *__restrict__ prim,
                                                           const float *__restrict__ grad, float hdtL, float hdtR,
                                                           float gam, const FaceAux &aux,
@@ -612,6 +615,10 @@ __device__ __forceinline__ MixedFace<D> mixed_face_states(int64_t f, const int32
     MixedFace<D> o;
     float fr[Y::MREC];
     load_rec<Y::MREC>(mrec + f * Y::MREC, fr);
+    double wf[D];
+    load_rec<Y::WSTRIDE>(wf64 + f * Y::WSTRIDE, wf);
+    float wfo[D];   // w_f - W0, rounded once
+    for (int k = 0; k < D; k++) wfo[k] = (float)(wf[k] - aux.w0[k]);
     const int64_t l = fL[f], r = fR[f];
     const CellRec<D, float> rl = load_cell_w<D>(prim, grad, l, win);
     const CellRec<D, float> rr = load_cell_w<D>(prim, grad, r, win);
@@ -625,9 +632,9 @@ __device__ __forceinline__ MixedFace<D> mixed_face_states(int64_t f, const int32
         gR[k] = c - hl * o.nrm[k];
     }
     // v_K - w_f = (v_K - W0) - (w_f - W0)
-    for (int k = 0; k < D; k++) vf[k] = rl.p[Y::W + 1 + k] - fr[Y::MWF + k];
+    for (int k = 0; k < D; k++) vf[k] = rl.p[Y::W + 1 + k] - wfo[k];
     half_step<D, float>(rl, vf, gL, gam, hdtL, o.xl, cl);
-    for (int k = 0; k < D; k++) vf[k] = rr.p[Y::W + 1 + k] - fr[Y::MWF + k];
+    for (int k = 0; k < D; k++) vf[k] = rr.p[Y::W + 1 + k] - wfo[k];
     half_step<D, float>(rr, vf, gR, gam, hdtR, o.xr, cr);
     if constexpr (GRAV) {   // the half-step kick of a static field (Section 5.2)
         for (int k = 0; k < D; k++) {
@@ -690,7 +697,8 @@ __device__ __forceinline__ void face_flux_mixed(bool active, int64_t f, const in
     hard = false;
     MixedFace<D> m;
     if (active) {
-        m = mixed_face_states<D, EM, GRAV>(f, fL, fR, mrec, prim, grad, (float)hdtL, (float)hdtR, kf.g, aux, win);
+        m = mixed_face_states<D, EM, GRAV>(f, fL, fR, mrec, wf64, prim, grad, (float)hdtL, (float)hdtR, kf.g, aux,
+                                           win);
         ld.posfb += m.posfb ? 1 : 0;
     } else {
         for (int c = 0; c < NV; c++) { m.xl[c] = 1.0f; m.xr[c] = 1.0f; }
@@ -780,7 +788,7 @@ __device__ __forceinline__ void hard_face(int64_t f, const int32_t *__restrict__
                                           const FaceAux &aux, LaneDiag &ld, double (&F)[D + 2], FaceX &X) {
     constexpr int NV = D + 2;
     const MixedFace<D> m =
-        mixed_face_states<D, EM, GRAV>(f, fL, fR, mrec, prim, grad, (float)hl, (float)hr, gam, aux);
+        mixed_face_states<D, EM, GRAV>(f, fL, fR, mrec, wf64, prim, grad, (float)hl, (float)hr, gam, aux);
     bool h2;
     FaceState<double> fd = solve_face<double>(m.xl[0], m.uL, m.xl[NV - 1], m.xr[0], m.uR, m.xr[NV - 1], kg, tol64,
                                               50, no_guess<double>(), false, ld, h2);
@@ -874,7 +882,7 @@ k_face_flux_mixed_list(const int32_t *__restrict__ list, int64_t cap, const int3
                        const double *__restrict__ wf64, const float *__restrict__ prim,
                        const float *__restrict__ grad, TbView tb, GasConst<float> kf, double g_over_gm1,
                        float tol32, int maxit, const MlpPacked *mlp, double *__restrict__ flux,
-                       int32_t *__restrict__ hard_list, DiagDev *diag) {
+                       int32_t *__restrict__ hard_list, DiagDev *diag, const double *__restrict__ w0) {
     constexpr int NV = D + 2;
     __shared__ float stash[LEARNED ? stash_floats<D>() : 1];
     const int c = blockIdx.x % kLists;
@@ -893,7 +901,7 @@ k_face_flux_mixed_list(const int32_t *__restrict__ list, int64_t cap, const int3
         double F[NV];
         FaceX X;
         face_flux_mixed<D, LEARNED, 0, false>(active, f, fL, fR, mrec, wf64, prim, grad, fdt, hl, hr, kf,
-                                              g_over_gm1, tol32, maxit, mlp, FaceAux{nullptr, 0},
+                                              g_over_gm1, tol32, maxit, mlp, FaceAux{nullptr, 0, w0},
                                               stash, ld, hard, F, X);
         if (active && !hard) store_face<D, 0>(flux + f * NV, F, X);
         list_append(hard_list, cap, active && hard, (int32_t)f);

@@ -194,15 +194,14 @@ struct SideOut {
 // Face records (Section 3.3 geometry and face velocity):
 //   n = d/|d|, c = f - (r_L + r_R)/2 = g - d/2,
 //   w_f = (w_L + w_R)/2 + [(w_L - w_R) . c / |d|] n.
-// The double geometry record and the face velocity always; the mixed
-// record (float geometry and w_f - W0, W0 the reference velocity w0 [D])
-// when mixed != 0; with so.ent (the upload, not a change of velocities)
-// also the face's two side records.
+// The double geometry record and the face velocity always; the float
+// geometry record when mixed != 0; with so.ent (the upload, not a change of
+// velocities) also the face's two side records.
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_face_records(int64_t n, int64_t nf, const int32_t *L, const int32_t *R,
                                                          const double *area, const double *ctr, const double *sep,
                                                          const double *mvel, double *frec, int mixed, float *mrec,
-                                                         const double *w0, double *wf64, SideOut so) {
+                                                         double *wf64, SideOut so) {
     using Y = Lay<D>;
     int64_t f = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (f >= nf) return;
@@ -237,7 +236,6 @@ __global__ void __launch_bounds__(kBlock) k_face_records(int64_t n, int64_t nf, 
         for (int k = 0; k < D; k++) {
             m[Y::FN + k] = (float)o[Y::FN + k];
             m[Y::FC + k] = (float)c[k];
-            m[Y::MWF + k] = (float)(w[k] - w0[k]);
         }
         store_rec<Y::MREC>(mrec + f * Y::MREC, m);
     }

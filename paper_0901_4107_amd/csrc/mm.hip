@@ -306,8 +306,7 @@ template <int D> static void launch_face_records(mm_ctx *c, const mm_mesh *m, co
     }
     k_face_records<D><<<plain_grid(m->n_faces), kBlock, 0, c->st()>>>(
         m->n_cells, m->n_faces, m->face_L, m->face_R, m->face_area, m->face_ctr, m->face_sep, m->mesh_vel,
-        c->at<double>(L.frec), mixed, mixed ? c->at<float>(L.mrec) : nullptr, mixed ? c->at<double>(L.w0) : nullptr,
-        c->at<double>(L.wf64), so);
+        c->at<double>(L.frec), mixed, mixed ? c->at<float>(L.mrec) : nullptr, c->at<double>(L.wf64), so);
 }
 
 mm_status mm_mesh_upload(mm_ctx *c, const mm_mesh *m) {
@@ -447,7 +446,9 @@ mm_status mm_gradients(mm_ctx *c, const double *Q, void *recon) {
     return gradients_into(c, Q, recon, c->at<double>(c->lay.dtpart));
 }
 
-static FaceAux face_aux(const mm_ctx *c) { return FaceAux{c->accel, c->n}; }
+static FaceAux face_aux(const mm_ctx *c) {
+    return FaceAux{c->accel, c->n, c->p.mode == MM_MIXED ? c->at<double>(c->lay.w0) : nullptr};
+}
 
 // The face fluxes in entropy mode EM, face-major records into flux.
 template <int D, int EM, bool GRAV>
@@ -994,11 +995,11 @@ template <int D, typename T> static void tb_point(mm_ctx *c, double *Q, T *rec) 
         kern<<<kTbGrid, kBlock, 0, s>>>(faces, fcap, c->mesh.face_L, c->mesh.face_R, c->at<float>(L.mrec),
                                         c->at<double>(L.wf64), (const float *)rec, (const float *)grad, view, kf,
                                         kg.g_over_gm1, (float)c->p.newton_tol32, c->p.newton_max_iter, mlp, flux,
-                                        hard, diag);
+                                        hard, diag, c->at<double>(L.w0));
         k_face_flux_hard<D, 0, false><<<kTbGrid, kBlock, 0, s>>>(
             c->mesh.face_L, c->mesh.face_R, c->at<float>(L.mrec), c->at<double>(L.wf64), (const float *)rec,
             (const float *)grad, nullptr, 0.0, kf.g, kg, c->p.newton_tol64, hard, fcap, flux, diag,
-            FaceAux{nullptr, c->n}, view);
+            FaceAux{nullptr, c->n, c->at<double>(L.w0)}, view);
     }
     const TbSides sd{c->at<int32_t>(L.loff), c->at<int32_t>(L.roff), c->at<int32_t>(L.rface), c->mesh.face_L,
                      c->mesh.face_R};
