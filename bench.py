@@ -58,8 +58,8 @@ def flux_kernel_bytes(dim, n_cells, n_faces, mixed):
       per cell: the primitives W (D + 2), their limited gradients
                 ((D + 2) D) and the centroid offset s - r (D), in the path's
                 precision.
-    The library's own face record carries derived values on top (|d|, the
-    normal, w_L - w_R): those count as overhead against this figure, not as
+    The library's own face record stores |d| and the normal in place of d
+    (one value more): that counts as overhead against this figure, not as
     algorithmic bytes."""
     nv = dim + 2
     fp = 4 if mixed else 8
