@@ -232,8 +232,14 @@ def test_invalid_meshes_are_rejected():
     ctx = mm.Context(3, 1.4)
     good = mm.DeviceMesh.from_host(mesh)
     ctx.mm_mesh_upload(good)
+    last = mesh.n_faces - 1
+    assert mesh.face_L[last] > 0
     for field, idx, val in [("face_L", 3, -1), ("face_R", 5, mesh.n_cells), ("face_R", 7, int(mesh.face_L[7])),
-                            ("volume", 2, 0.0), ("face_area", 1, -1.0), ("face_sep", 4, float("nan"))]:
+                            ("volume", 2, 0.0), ("face_area", 1, -1.0), ("face_sep", 4, float("nan")),
+                            # faces no longer sorted by their left cell
+                            ("face_L", last, 0),
+                            # two cells no longer closed (the closure check after the side lists)
+                            ("face_area", 6, 2.0 * float(mesh.face_area[6]))]:
         bad = mm.DeviceMesh.from_host(mesh)
         t = getattr(bad, field)
         t.view(-1)[idx] = val
