@@ -271,6 +271,54 @@ def test_cfl_closed_form():
         assert abs(O.cfl_dt(mesh, g, 0.4, W) - want) <= 1e-15 * want
 
 
+def test_cfl_against_lattice_closed_forms():
+    """Section 7.1's Courant step pinned by what fixes it independently of
+    its formula: on a regular periodic lattice of n^2 (2D) or n^3 (3D) cells
+    every volume is 1/n^D exactly, so at rest with one sound speed c the
+    step is C R / c with R = (1/n^2 / pi)^(1/2) or (3/(4 pi n^3))^(1/3);
+    one hotter cell (4x the pressure, twice the sound speed) sets the
+    minimum alone; a boost of every velocity and generator velocity leaves
+    it unchanged (only v - w enters); doubling every speed (P x 4, v and w
+    x 2) halves it; a vacuum cell imposes no limit."""
+    from paper_0901_4107_amd.inputs.configs import jittered_lattice
+    rng = np.random.default_rng(0)
+    g, C = 5.0 / 3.0, 0.4
+    for dim, n in ((2, 8), (3, 6)):
+        mesh = build_mesh(jittered_lattice(n, dim, 0.0, rng))
+        N = mesh.n_cells
+        assert N == n ** dim and np.allclose(mesh.volume, 1.0 / N, rtol=1e-12, atol=0)
+        R = np.sqrt(1.0 / N / np.pi) if dim == 2 else (3.0 / (4.0 * np.pi * N)) ** (1.0 / 3.0)
+        rho, P = np.ones(N), np.ones(N)
+        c = np.sqrt(g)
+        W = np.concatenate([rho[None], np.zeros((dim, N)), P[None]])
+        mesh.with_velocity(np.zeros((dim, N)))
+        assert abs(O.cfl_dt(mesh, g, C, W) - C * R / c) <= 1e-14 * C * R / c
+        # one hot cell: twice the sound speed, half the step
+        Wh = W.copy(); Wh[dim + 1, 5] = 4.0
+        assert abs(O.cfl_dt(mesh, g, C, Wh) - C * R / (2 * c)) <= 1e-14 * C * R / c
+        # moving gas on a comoving mesh: |v - w| = 0 whatever the boost
+        v = rng.normal(size=(dim, N))
+        u = np.array([30.0, -7.0, 2.0][:dim])[:, None]
+        Wv = W.copy(); Wv[1:1 + dim] = v
+        mesh.with_velocity(np.ascontiguousarray(v))
+        dt_v = O.cfl_dt(mesh, g, C, Wv)
+        assert abs(dt_v - C * R / c) <= 1e-14 * C * R / c
+        # gas moving against a mesh at rest limits by c + |v|, boosts cancel
+        mesh.with_velocity(np.zeros((dim, N)))
+        dt_a = O.cfl_dt(mesh, g, C, Wv)
+        assert abs(dt_a - C * R * np.min(1.0 / (c + np.linalg.norm(v, axis=0)))) <= 1e-13 * dt_a
+        Wb = Wv.copy(); Wb[1:1 + dim] += u
+        mesh.with_velocity(np.ascontiguousarray(np.broadcast_to(u, (dim, N))))
+        assert abs(O.cfl_dt(mesh, g, C, Wb) - dt_a) <= 1e-13 * dt_a
+        # every speed doubled: half the step
+        W2 = Wv.copy(); W2[dim + 1] *= 4.0; W2[1:1 + dim] *= 2.0
+        mesh.with_velocity(np.zeros((dim, N)))
+        assert abs(O.cfl_dt(mesh, g, C, W2) - 0.5 * dt_a) <= 1e-13 * dt_a
+        # a vacuum cell with a huge velocity imposes nothing
+        W0 = W.copy(); W0[0, 3] = 0.0; W0[dim + 1, 3] = 0.0; W0[1, 3] = 1e9
+        assert abs(O.cfl_dt(mesh, g, C, W0) - C * R / c) <= 1e-14 * C * R / c
+
+
 def test_prim_roundtrip():
     rng = np.random.default_rng(8)
     n, g = 1000, 5.0 / 3.0
