@@ -289,10 +289,11 @@ __device__ __forceinline__ bool wants_learned(T rhoL, T uL, T PL, T rhoR, T uR, 
     return true;
 }
 
-// Block-wide staging of the learned guess: the problems of a block that
-// want the network are compacted, so only ceil(count / 64) wavefronts
-// evaluate it, each for 64 problems. Every thread of the block takes part
-// in each phase (they hold barriers):
+// Block-wide staging of the learned guess (the double flux kernels; the
+// float ones and the batch use the per-wavefront form below): the problems
+// of a block that want the network are compacted, so only ceil(count / 64)
+// wavefronts evaluate it, each for 64 problems. Every thread of the block
+// takes part in each phase (they hold barriers):
 //   learn_count  how many threads of the block want the network (the same
 //                for the whole block), and this thread's slot among them;
 //   learn_put    a wanting thread stores its features in its slot;
