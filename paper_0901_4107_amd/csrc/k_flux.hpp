@@ -606,7 +606,6 @@ template <int D, int EM, bool GRAV>
 __device__ __forceinline__ MixedFace<D> mixed_face_states(int64_t f, const int32_t *__restrict__ fL,
                                                           const int32_t *__restrict__ fR,
                                                           const float *__restrict__ mrec,
-                                                          const double *__restrict__ wf64,
                                                           const float *__restrict__ prim,
                                                           const float *__restrict__ grad, float hdtL, float hdtR,
                                                           float gam, const FaceAux &aux,
@@ -616,10 +615,6 @@ __device__ __forceinline__ MixedFace<D> mixed_face_states(int64_t f, const int32
     MixedFace<D> o;
     float fr[Y::MREC];
     load_rec<Y::MREC>(mrec + f * Y::MREC, fr);
-    double wf[D];
-    load_rec<Y::WSTRIDE>(wf64 + f * Y::WSTRIDE, wf);
-    float wfo[D];   // w_f - W0, rounded once
-    for (int k = 0; k < D; k++) wfo[k] = (float)(wf[k] - aux.w0[k]);
     const int64_t l = fL[f], r = fR[f];
     const CellRec<D, float> rl = load_cell_w<D>(prim, grad, l, win);
     const CellRec<D, float> rr = load_cell_w<D>(prim, grad, r, win);
@@ -633,9 +628,9 @@ __device__ __forceinline__ MixedFace<D> mixed_face_states(int64_t f, const int32
         gR[k] = c - hl * o.nrm[k];
     }
     // v_K - w_f = (v_K - W0) - (w_f - W0)
-    for (int k = 0; k < D; k++) vf[k] = rl.p[Y::W + 1 + k] - wfo[k];
+    for (int k = 0; k < D; k++) vf[k] = rl.p[Y::W + 1 + k] - fr[Y::MW + k];
     half_step<D, float>(rl, vf, gL, gam, hdtL, o.xl, cl);
-    for (int k = 0; k < D; k++) vf[k] = rr.p[Y::W + 1 + k] - wfo[k];
+    for (int k = 0; k < D; k++) vf[k] = rr.p[Y::W + 1 + k] - fr[Y::MW + k];
     half_step<D, float>(rr, vf, gR, gam, hdtR, o.xr, cr);
     if constexpr (GRAV) {   // the half-step kick of a static field (Section 5.2)
         for (int k = 0; k < D; k++) {
@@ -652,19 +647,24 @@ __device__ __forceinline__ MixedFace<D> mixed_face_states(int64_t f, const int32
     return o;
 }
 
+// The lab-frame flux of a mixed face: the face velocity is W0 + (w_f - W0)
+// as the face record holds it, the one the face frame was formed with, so
+// the transform there and back is exact.
 template <int D>
 __device__ __forceinline__ void mixed_lab_flux(const MixedFace<D> &m, double rho, double u, double P, int side,
-                                               const double *__restrict__ wf64, int64_t f, double g_over_gm1,
-                                               double dt, double (&out)[D + 2]) {
+                                               const float *__restrict__ mrec, int64_t f,
+                                               const double *__restrict__ w0, double g_over_gm1, double dt,
+                                               double (&out)[D + 2]) {
     using Y = Lay<D>;
     const float *xs = side ? m.xr : m.xl;
     const float un = side ? m.uR : m.uL;
-    double tv[D], nd[D], wr[Y::WSTRIDE];
-    load_rec<Y::WSTRIDE>(wf64 + f * Y::WSTRIDE, wr);
-    const double *w = wr;
+    float wo[D];
+    load_rec<D>(mrec + f * Y::MREC + Y::MW, wo);
+    double tv[D], nd[D], w[D];
     for (int k = 0; k < D; k++) {
         tv[k] = (double)(xs[1 + k] - un * m.nrm[k]);
         nd[k] = (double)m.nrm[k];
+        w[k] = w0[k] + (double)wo[k];
     }
     lab_flux<D>(rho, u, P, tv, nd, w, g_over_gm1, dt * (double)m.A, out);
 }
@@ -688,7 +688,7 @@ template <int D> constexpr int stash_floats() { return 2 * (D + 2) * kBlock; }
 template <int D, bool LEARNED, int EM, bool GRAV>
 __device__ __forceinline__ void face_flux_mixed(bool active, int64_t f, const int32_t *__restrict__ fL,
                                                 const int32_t *__restrict__ fR, const float *__restrict__ mrec,
-                                                const double *__restrict__ wf64, const float *__restrict__ prim,
+                                                const float *__restrict__ prim,
                                                 const float *__restrict__ grad, double dt, double hdtL, double hdtR,
                                                 const GasConst<float> &kf, double g_over_gm1, float tol32, int maxit,
                                                 const MlpPacked *mlp, const FaceAux &aux, float *stash,
@@ -698,8 +698,7 @@ __device__ __forceinline__ void face_flux_mixed(bool active, int64_t f, const in
     hard = false;
     MixedFace<D> m;
     if (active) {
-        m = mixed_face_states<D, EM, GRAV>(f, fL, fR, mrec, wf64, prim, grad, (float)hdtL, (float)hdtR, kf.g, aux,
-                                           win);
+        m = mixed_face_states<D, EM, GRAV>(f, fL, fR, mrec, prim, grad, (float)hdtL, (float)hdtR, kf.g, aux, win);
         ld.posfb += m.posfb ? 1 : 0;
     } else {
         for (int c = 0; c < NV; c++) { m.xl[c] = 1.0f; m.xr[c] = 1.0f; }
@@ -731,7 +730,7 @@ __device__ __forceinline__ void face_flux_mixed(bool active, int64_t f, const in
         FaceState<float> fs = solve_face<float>(m.xl[0], m.uL, m.xl[NV - 1], m.xr[0], m.uR, m.xr[NV - 1], kf, tol32,
                                                 maxit, pl, true, ld, hard);
         if (!hard) {
-            mixed_lab_flux<D>(m, fs.rho, fs.u, fs.P, fs.side, wf64, f, g_over_gm1, dt, F);
+            mixed_lab_flux<D>(m, fs.rho, fs.u, fs.P, fs.side, mrec, f, aux.w0, g_over_gm1, dt, F);
             if constexpr (EM != 0) {
                 float AU, mach;
                 entropy_terms<float>(fs, m.xl[0], m.xl[NV - 1], m.xr[0], m.xr[NV - 1], kf, AU, mach);
@@ -749,7 +748,6 @@ template <int D, bool LEARNED, int EM, bool GRAV>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) k_face_flux_mixed(int64_t nf, const int32_t *__restrict__ fL,
                                                             const int32_t *__restrict__ fR,
                                                             const float *__restrict__ mrec,
-                                                            const double *__restrict__ wf64,
                                                             const float *__restrict__ prim,
                                                             const float *__restrict__ grad,
                                                             const double *__restrict__ dt_ptr, double dt_val,
@@ -771,7 +769,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))
     const double dt = dt_ptr ? *dt_ptr : dt_val;
     double F[NV];
     FaceX X;
-    face_flux_mixed<D, LEARNED, EM, GRAV>(active, f, fL, fR, mrec, wf64, prim, grad, dt, 0.5 * dt, 0.5 * dt, kf,
+    face_flux_mixed<D, LEARNED, EM, GRAV>(active, f, fL, fR, mrec, prim, grad, dt, 0.5 * dt, 0.5 * dt, kf,
                                           g_over_gm1, tol32, maxit, mlp, aux, stash, ld, hard, F, X, win);
     if (active && !hard) store_face<D, EM>(flux + f * Rec<D, EM>::FM, F, X);
     list_append(hard_list, cap, hard, (int32_t)f);
@@ -783,18 +781,18 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))
 // flux; over the prediction intervals hl, hr and the step dt.
 template <int D, int EM, bool GRAV>
 __device__ __forceinline__ void hard_face(int64_t f, const int32_t *__restrict__ fL, const int32_t *__restrict__ fR,
-                                          const float *__restrict__ mrec, const double *__restrict__ wf64,
+                                          const float *__restrict__ mrec,
                                           const float *__restrict__ prim, const float *__restrict__ grad, double dt,
                                           double hl, double hr, float gam, const GasConst<double> &kg, double tol64,
                                           const FaceAux &aux, LaneDiag &ld, double (&F)[D + 2], FaceX &X) {
     constexpr int NV = D + 2;
     const MixedFace<D> m =
-        mixed_face_states<D, EM, GRAV>(f, fL, fR, mrec, wf64, prim, grad, (float)hl, (float)hr, gam, aux);
+        mixed_face_states<D, EM, GRAV>(f, fL, fR, mrec, prim, grad, (float)hl, (float)hr, gam, aux);
     bool h2;
     FaceState<double> fd = solve_face<double>(m.xl[0], m.uL, m.xl[NV - 1], m.xr[0], m.uR, m.xr[NV - 1], kg, tol64,
                                               50, no_guess<double>(), false, ld, h2);
     ld.fp64fb += 1;
-    mixed_lab_flux<D>(m, fd.rho, fd.u, fd.P, fd.side, wf64, f, kg.g_over_gm1, dt, F);
+    mixed_lab_flux<D>(m, fd.rho, fd.u, fd.P, fd.side, mrec, f, aux.w0, kg.g_over_gm1, dt, F);
     if constexpr (EM != 0) {
         double AU, mach;
         entropy_terms<double>(fd, (double)m.xl[0], (double)m.xl[NV - 1], (double)m.xr[0], (double)m.xr[NV - 1], kg,
@@ -813,7 +811,6 @@ template <int D, int EM, bool GRAV>
 __global__ void __launch_bounds__(kBlock) k_face_flux_hard(const int32_t *__restrict__ fL,
                                                            const int32_t *__restrict__ fR,
                                                            const float *__restrict__ mrec,
-                                                           const double *__restrict__ wf64,
                                                            const float *__restrict__ prim,
                                                            const float *__restrict__ grad,
                                                            const double *__restrict__ dt_ptr, double dt_val,
@@ -831,7 +828,7 @@ __global__ void __launch_bounds__(kBlock) k_face_flux_hard(const int32_t *__rest
         if (tb.bin) tb.face(fL[f], fR[f], dt, hl, hr);
         double F[NV];
         FaceX X;
-        hard_face<D, EM, GRAV>(f, fL, fR, mrec, wf64, prim, grad, dt, hl, hr, gam, kg, tol64, aux, ld, F, X);
+        hard_face<D, EM, GRAV>(f, fL, fR, mrec, prim, grad, dt, hl, hr, gam, kg, tol64, aux, ld, F, X);
         store_face<D, EM>(flux + f * Rec<D, EM>::FM, F, X);
     }
     if (diag) flush_diag(ld, diag);
@@ -880,7 +877,7 @@ template <int D, bool LEARNED>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5)))
 k_face_flux_mixed_list(const int32_t *__restrict__ list, int64_t cap, const int32_t *__restrict__ fL,
                        const int32_t *__restrict__ fR, const float *__restrict__ mrec,
-                       const double *__restrict__ wf64, const float *__restrict__ prim,
+                       const float *__restrict__ prim,
                        const float *__restrict__ grad, TbView tb, GasConst<float> kf, double g_over_gm1,
                        float tol32, int maxit, const MlpPacked *mlp, double *__restrict__ flux,
                        int32_t *__restrict__ hard_list, DiagDev *diag, const double *__restrict__ w0) {
@@ -901,7 +898,7 @@ k_face_flux_mixed_list(const int32_t *__restrict__ list, int64_t cap, const int3
         bool hard;
         double F[NV];
         FaceX X;
-        face_flux_mixed<D, LEARNED, 0, false>(active, f, fL, fR, mrec, wf64, prim, grad, fdt, hl, hr, kf,
+        face_flux_mixed<D, LEARNED, 0, false>(active, f, fL, fR, mrec, prim, grad, fdt, hl, hr, kf,
                                               g_over_gm1, tol32, maxit, mlp, FaceAux{nullptr, 0, w0},
                                               stash, ld, hard, F, X);
         if (active && !hard) store_face<D, 0>(flux + f * NV, F, X);

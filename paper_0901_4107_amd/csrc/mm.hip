@@ -306,7 +306,8 @@ template <int D> static void launch_face_records(mm_ctx *c, const mm_mesh *m, co
     }
     k_face_records<D><<<plain_grid(m->n_faces), kBlock, 0, c->st()>>>(
         m->n_cells, m->n_faces, m->face_L, m->face_R, m->face_area, m->face_ctr, m->face_sep, m->mesh_vel,
-        c->at<double>(L.frec), mixed, mixed ? c->at<float>(L.mrec) : nullptr, c->at<double>(L.wf64), so);
+        c->at<double>(L.frec), mixed ? c->at<double>(L.w0) : nullptr, mixed ? c->at<float>(L.mrec) : nullptr,
+        c->at<double>(L.wf64), so);
 }
 
 mm_status mm_mesh_upload(mm_ctx *c, const mm_mesh *m) {
@@ -473,12 +474,12 @@ static mm_status fluxes_t(mm_ctx *c, const double *dt_dev, double dt, const void
         k_fill_i32<<<kLists * kListPad / kBlock, kBlock, 0, s>>>(hard, kLists * kListPad, 0);
         auto kern = mlp ? k_face_flux_mixed<D, true, EM, GRAV> : k_face_flux_mixed<D, false, EM, GRAV>;
         const float *prim = (const float *)rec;
-        kern<<<grid_for(c->nf), kBlock, 0, s>>>(c->nf, c->mesh.face_L, c->mesh.face_R, c->at<float>(L.mrec),
-                                                c->at<double>(L.wf64), prim, grad_block<D>(c, prim), dt_dev, dt, kf,
+        kern<<<grid_for(c->nf), kBlock, 0, s>>>(c->nf, c->mesh.face_L, c->mesh.face_R, c->at<float>(L.mrec), prim,
+                                                grad_block<D>(c, prim), dt_dev, dt, kf,
                                                 kg.g_over_gm1, (float)c->p.newton_tol32, c->p.newton_max_iter, mlp,
                                                 flux, hard, cap, diag, aux);
         k_face_flux_hard<D, EM, GRAV><<<kHardGrid, kBlock, 0, s>>>(
-            c->mesh.face_L, c->mesh.face_R, c->at<float>(L.mrec), c->at<double>(L.wf64), prim, grad_block<D>(c, prim),
+            c->mesh.face_L, c->mesh.face_R, c->at<float>(L.mrec), prim, grad_block<D>(c, prim),
             dt_dev, dt, kf.g, kg, c->p.newton_tol64, hard, cap, flux, diag, aux, TbView{});
     }
     MM_LAUNCH_CHECK();
@@ -993,11 +994,11 @@ template <int D, typename T> static void tb_point(mm_ctx *c, double *Q, T *rec) 
         const GasConst<float> kf(c->p.gamma);
         auto kern = mlp ? k_face_flux_mixed_list<D, true> : k_face_flux_mixed_list<D, false>;
         kern<<<kTbGrid, kBlock, 0, s>>>(faces, fcap, c->mesh.face_L, c->mesh.face_R, c->at<float>(L.mrec),
-                                        c->at<double>(L.wf64), (const float *)rec, (const float *)grad, view, kf,
+                                        (const float *)rec, (const float *)grad, view, kf,
                                         kg.g_over_gm1, (float)c->p.newton_tol32, c->p.newton_max_iter, mlp, flux,
                                         hard, diag, c->at<double>(L.w0));
         k_face_flux_hard<D, 0, false><<<kTbGrid, kBlock, 0, s>>>(
-            c->mesh.face_L, c->mesh.face_R, c->at<float>(L.mrec), c->at<double>(L.wf64), (const float *)rec,
+            c->mesh.face_L, c->mesh.face_R, c->at<float>(L.mrec), (const float *)rec,
             (const float *)grad, nullptr, 0.0, kf.g, kg, c->p.newton_tol64, hard, fcap, flux, diag,
             FaceAux{nullptr, c->n, c->at<double>(L.w0)}, view);
     }
