@@ -67,16 +67,17 @@ __device__ __forceinline__ double block_min(double v) {
 
 // Step (ii) for one cell (Section 3, state vector and equation of state):
 //   rho = m/V, v = p/m, P = (g-1)(E - m v^2/2)/V.
-// Fills the primitive record (W and s_i - r_i, whole); in the mixed mode
+// Fills the primitive record (W and s_i - r_i, whole; coff [D][n] the
+// centroid offsets in double or, rounded once, in the records' float); in the mixed mode
 // (T = float) the velocity stored is v_i - W0, rounded once from double, W0
 // the reference velocity w0 [D] (device). Returns the cell's sound speed (0
 // unless rho > 0 and P > 0) and sets v (lab frame), |v - w|^2, the radius R
 // of the cell's volume and ok = (rho > 0 and P > 0). Cells with m <= 0 are
 // vacuum: rho = P = 0, v = 0.
-template <int D, typename T>
+template <int D, typename T, typename C>
 __device__ __forceinline__ double cell_prim(int64_t i, int64_t n, double gamma, const double *__restrict__ V,
                                             const double *__restrict__ Q, const double *__restrict__ mvel,
-                                            const double *__restrict__ coff, const double *__restrict__ w0,
+                                            const C *__restrict__ coff, const double *__restrict__ w0,
                                             T (&r)[Lay<D>::PREC], double (&v)[D], double &rel2, double &R, bool &ok) {
     using Y = Lay<D>;
     constexpr int NV = D + 2;
@@ -117,11 +118,12 @@ __device__ __forceinline__ double cell_prim(int64_t i, int64_t n, double gamma, 
 //   dt_i = C R_i / (c_i + |v_i - w_i|), R_i the radius of the cell's volume;
 // vacuum cells impose no limit. As the first kernel of a step it clears the
 // step's non-finite flag (step_flag, may be null). w0: the mixed mode's
-// reference velocity (null in double).
+// reference velocity (null in double). coff: the centroid offsets in the
+// records' precision (the mixed mode's float copy, made at upload).
 template <int D, typename T>
 __global__ void __launch_bounds__(kBlock) k_prim_cfl(int64_t n, double gamma, double cfl, const double *__restrict__ V,
                                                      const double *__restrict__ Q, const double *__restrict__ mvel,
-                                                     const double *__restrict__ coff, T *__restrict__ prim,
+                                                     const T *__restrict__ coff, T *__restrict__ prim,
                                                      const double *__restrict__ w0, double *__restrict__ dt_part,
                                                      int32_t *step_flag) {
     using Y = Lay<D>;
@@ -138,6 +140,15 @@ __global__ void __launch_bounds__(kBlock) k_prim_cfl(int64_t n, double gamma, do
     }
     dti = block_min(dti);
     if (threadIdx.x == 0) dt_part[xcd_tile()] = dti;
+}
+
+// The mixed mode's float copy of the centroid offsets s_i - r_i [D][n],
+// rounded once per mesh as the primitive records hold them.
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_coff32(int64_t n, const double *__restrict__ coff, float *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    for (int k = 0; k < D; k++) out[k * n + i] = (float)coff[k * n + i];
 }
 
 __global__ void __launch_bounds__(1024) k_min_final(int64_t nparts, const double *part, double *out) {

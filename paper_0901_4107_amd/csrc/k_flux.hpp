@@ -484,12 +484,14 @@ __device__ __forceinline__ void lab_flux(double rho, double u, double P, const d
 }
 
 // What the face bodies read besides the records: the static field
-// (GRAV, Section 5.2; accel [D][n], g = -grad Phi) and the mixed form's
-// reference velocity W0 (w0 [D]).
+// (GRAV, Section 5.2; accel [D][n], g = -grad Phi), the mixed form's
+// reference velocity W0, by value (a kernel argument the lab-frame flux
+// takes from scalar registers), and its faces' w_f - W0 ([F][D] floats).
 struct FaceAux {
     const double *accel;
     int64_t n;
-    const double *w0 = nullptr;
+    double w0[3] = {0.0, 0.0, 0.0};
+    const float *wrel = nullptr;
 };
 
 // Double-precision flux of face f (dt A Fhat into F), the body of the face
@@ -613,8 +615,9 @@ __device__ __forceinline__ MixedFace<D> mixed_face_states(int64_t f, const int32
     using Y = Lay<D>;
     constexpr int NV = D + 2;
     MixedFace<D> o;
-    float fr[Y::MREC];
+    float fr[Y::MREC], wo[D];
     load_rec<Y::MREC>(mrec + f * Y::MREC, fr);
+    load_rec<D>(aux.wrel + f * D, wo);
     const int64_t l = fL[f], r = fR[f];
     const CellRec<D, float> rl = load_cell_w<D>(prim, grad, l, win);
     const CellRec<D, float> rr = load_cell_w<D>(prim, grad, r, win);
@@ -628,9 +631,9 @@ __device__ __forceinline__ MixedFace<D> mixed_face_states(int64_t f, const int32
         gR[k] = c - hl * o.nrm[k];
     }
     // v_K - w_f = (v_K - W0) - (w_f - W0)
-    for (int k = 0; k < D; k++) vf[k] = rl.p[Y::W + 1 + k] - fr[Y::MW + k];
+    for (int k = 0; k < D; k++) vf[k] = rl.p[Y::W + 1 + k] - wo[k];
     half_step<D, float>(rl, vf, gL, gam, hdtL, o.xl, cl);
-    for (int k = 0; k < D; k++) vf[k] = rr.p[Y::W + 1 + k] - fr[Y::MW + k];
+    for (int k = 0; k < D; k++) vf[k] = rr.p[Y::W + 1 + k] - wo[k];
     half_step<D, float>(rr, vf, gR, gam, hdtR, o.xr, cr);
     if constexpr (GRAV) {   // the half-step kick of a static field (Section 5.2)
         for (int k = 0; k < D; k++) {
@@ -652,19 +655,17 @@ __device__ __forceinline__ MixedFace<D> mixed_face_states(int64_t f, const int32
 // the transform there and back is exact.
 template <int D>
 __device__ __forceinline__ void mixed_lab_flux(const MixedFace<D> &m, double rho, double u, double P, int side,
-                                               const float *__restrict__ mrec, int64_t f,
-                                               const double *__restrict__ w0, double g_over_gm1, double dt,
+                                               int64_t f, const FaceAux &aux, double g_over_gm1, double dt,
                                                double (&out)[D + 2]) {
-    using Y = Lay<D>;
     const float *xs = side ? m.xr : m.xl;
     const float un = side ? m.uR : m.uL;
     float wo[D];
-    load_rec<D>(mrec + f * Y::MREC + Y::MW, wo);
+    load_rec<D>(aux.wrel + f * D, wo);
     double tv[D], nd[D], w[D];
     for (int k = 0; k < D; k++) {
         tv[k] = (double)(xs[1 + k] - un * m.nrm[k]);
         nd[k] = (double)m.nrm[k];
-        w[k] = w0[k] + (double)wo[k];
+        w[k] = aux.w0[k] + (double)wo[k];
     }
     lab_flux<D>(rho, u, P, tv, nd, w, g_over_gm1, dt * (double)m.A, out);
 }
@@ -730,7 +731,7 @@ __device__ __forceinline__ void face_flux_mixed(bool active, int64_t f, const in
         FaceState<float> fs = solve_face<float>(m.xl[0], m.uL, m.xl[NV - 1], m.xr[0], m.uR, m.xr[NV - 1], kf, tol32,
                                                 maxit, pl, true, ld, hard);
         if (!hard) {
-            mixed_lab_flux<D>(m, fs.rho, fs.u, fs.P, fs.side, mrec, f, aux.w0, g_over_gm1, dt, F);
+            mixed_lab_flux<D>(m, fs.rho, fs.u, fs.P, fs.side, f, aux, g_over_gm1, dt, F);
             if constexpr (EM != 0) {
                 float AU, mach;
                 entropy_terms<float>(fs, m.xl[0], m.xl[NV - 1], m.xr[0], m.xr[NV - 1], kf, AU, mach);
@@ -792,7 +793,7 @@ __device__ __forceinline__ void hard_face(int64_t f, const int32_t *__restrict__
     FaceState<double> fd = solve_face<double>(m.xl[0], m.uL, m.xl[NV - 1], m.xr[0], m.uR, m.xr[NV - 1], kg, tol64,
                                               50, no_guess<double>(), false, ld, h2);
     ld.fp64fb += 1;
-    mixed_lab_flux<D>(m, fd.rho, fd.u, fd.P, fd.side, mrec, f, aux.w0, kg.g_over_gm1, dt, F);
+    mixed_lab_flux<D>(m, fd.rho, fd.u, fd.P, fd.side, f, aux, kg.g_over_gm1, dt, F);
     if constexpr (EM != 0) {
         double AU, mach;
         entropy_terms<double>(fd, (double)m.xl[0], (double)m.xl[NV - 1], (double)m.xr[0], (double)m.xr[NV - 1], kg,
@@ -880,7 +881,7 @@ k_face_flux_mixed_list(const int32_t *__restrict__ list, int64_t cap, const int3
                        const float *__restrict__ prim,
                        const float *__restrict__ grad, TbView tb, GasConst<float> kf, double g_over_gm1,
                        float tol32, int maxit, const MlpPacked *mlp, double *__restrict__ flux,
-                       int32_t *__restrict__ hard_list, DiagDev *diag, const double *__restrict__ w0) {
+                       int32_t *__restrict__ hard_list, DiagDev *diag, FaceAux aux) {
     constexpr int NV = D + 2;
     __shared__ float stash[LEARNED ? stash_floats<D>() : 1];
     const int c = blockIdx.x % kLists;
@@ -899,7 +900,7 @@ k_face_flux_mixed_list(const int32_t *__restrict__ list, int64_t cap, const int3
         double F[NV];
         FaceX X;
         face_flux_mixed<D, LEARNED, 0, false>(active, f, fL, fR, mrec, prim, grad, fdt, hl, hr, kf,
-                                              g_over_gm1, tol32, maxit, mlp, FaceAux{nullptr, 0, w0},
+                                              g_over_gm1, tol32, maxit, mlp, aux,
                                               stash, ld, hard, F, X);
         if (active && !hard) store_face<D, 0>(flux + f * NV, F, X);
         list_append(hard_list, cap, active && hard, (int32_t)f);

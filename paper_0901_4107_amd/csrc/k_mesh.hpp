@@ -195,13 +195,13 @@ struct SideOut {
 //   n = d/|d|, c = f - (r_L + r_R)/2 = g - d/2,
 //   w_f = (w_L + w_R)/2 + [(w_L - w_R) . c / |d|] n.
 // The double geometry record and the face velocity always; the float
-// record, with w_f - W0 (W0 at w0), when mrec is given; with so.ent (the
+// record and w_f - W0 (W0 at w0, into wrel) when mrec is given; with so.ent (the
 // upload, not a change of velocities) also the face's two side records.
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_face_records(int64_t n, int64_t nf, const int32_t *L, const int32_t *R,
                                                          const double *area, const double *ctr, const double *sep,
                                                          const double *mvel, double *frec, const double *w0,
-                                                         float *mrec, double *wf64, SideOut so) {
+                                                         float *mrec, float *wrel, double *wf64, SideOut so) {
     using Y = Lay<D>;
     int64_t f = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (f >= nf) return;
@@ -230,15 +230,16 @@ __global__ void __launch_bounds__(kBlock) k_face_records(int64_t n, int64_t nf, 
     store_rec<Y::FREC>(frec + f * Y::FREC, o);
     store_rec<Y::WSTRIDE>(wf64 + f * Y::WSTRIDE, w);
     if (mrec) {
-        float m[Y::MREC];
+        float m[Y::MREC], wr[D];
         m[Y::FA] = (float)A;
         m[Y::FELL] = (float)ell;
         for (int k = 0; k < D; k++) {
             m[Y::FN + k] = (float)o[Y::FN + k];
             m[Y::FC + k] = (float)c[k];
-            m[Y::MW + k] = (float)(w[k] - w0[k]);
+            wr[k] = (float)(w[k] - w0[k]);
         }
         store_rec<Y::MREC>(mrec + f * Y::MREC, m);
+        store_rec<D>(wrel + f * D, wr);
     }
     if (so.ent) {
         const int64_t q[2] = {f + so.roff[l], (int64_t)so.loff[r + 1] + so.pos[f]};

@@ -205,24 +205,100 @@ __device__ __forceinline__ void cell_sums(int64_t i, int lane, const int32_t *__
     if constexpr (EM == 1) mx = grp_max<GS>(mx);
 }
 
-// The update (the step, mm_apply_update): one lane group per cell. It waits
-// on its gathers: the plain kernel keeps 6 records per lane in flight at 6
-// wavefronts per SIMD (1.5% faster per step than 4 at 8), the energy
-// switch's 6 at 5 (1% faster per step than 4 at 7).
+// The update (the step, mm_apply_update): one lane group per cell. Without
+// the entropy scheme a block's cells c0 .. c1-1 are the left cells of one
+// contiguous stretch of faces, [lOff_c0, lOff_c1): the block copies up to
+// kUpdStage of its records into LDS with coalesced 16-byte loads, while
+// each lane's first three right records are already being gathered, and
+// the left sums read them there (a longer stretch reads the rest from
+// global memory). 20 KB of LDS and 63 VGPRs give 8 wavefronts per SIMD;
+// 1.3% off the step against cell_sums' 3 + 3 records in flight at 6. The sums keep cell_sums' order, so
+// the bits are those of every other path. The entropy scheme's longer
+// records would cost the stage its occupancy, so its updates take
+// cell_sums as it is: the Mach switch's 56-byte records 2 + 2 per lane in
+// flight at 6 wavefronts per SIMD, the energy switch's 3 + 3 at 5.
+constexpr int kUpdStage = 512;   // records; a block averages 64 x 7.8 on a Poisson mesh
+
 template <int D, int EM, bool GRAV>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(EM == 1 ? 6 : (EM == 2 ? 5 : 6))))
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(EM == 2 ? 5 : (EM == 1 ? 6 : 7))))
 k_update(int64_t n, const int32_t *__restrict__ lOff, const int32_t *__restrict__ rOff,
          const int32_t *__restrict__ rFace, const double *__restrict__ flux, double *__restrict__ Q, UpdateArgs u) {
     using RC = Rec<D, EM>;
+    constexpr int NS = RC::NS, FM = RC::FM;
     constexpr int GS = Group<D>::GS;
     const int lane = threadIdx.x % GS;
-    const int64_t i = xcd_tile() * (kBlock / GS) + threadIdx.x / GS;
-    if (i >= n) return;
-    double acc[RC::NS], mx;
-    cell_sums<D, EM>(i, lane, lOff, rOff, rFace, flux, [](int32_t) { return true; }, acc, mx);
-    bool keep = false;
-    if (lane == 0) keep = finish_cell<D, EM, GRAV>(i, n, acc, mx, Q, u);
-    if constexpr (EM != 0) count_kept(keep, u.diag);
+    if constexpr (EM != 0) {
+        const int64_t i = xcd_tile() * (kBlock / GS) + threadIdx.x / GS;
+        if (i >= n) return;
+        double acc[NS], mx;
+        cell_sums<D, EM>(i, lane, lOff, rOff, rFace, flux, [](int32_t) { return true; }, acc, mx);
+        bool keep = false;
+        if (lane == 0) keep = finish_cell<D, EM, GRAV>(i, n, acc, mx, Q, u);
+        count_kept(keep, u.diag);
+    } else {
+        constexpr int KR = 3;
+        constexpr int PIECES = (kUpdStage * FM + 1) / 2;   // 16-byte pieces of a full stage
+        constexpr int IT = (PIECES + kBlock - 1) / kBlock;
+        __shared__ __align__(16) double stage[2 * PIECES];
+        const int64_t c0 = xcd_tile() * (kBlock / GS);
+        if (c0 >= n) return;   // the whole block
+        const int64_t i = c0 + threadIdx.x / GS;
+        const bool live = i < n;
+        const int64_t c1 = (c0 + kBlock / GS < n) ? c0 + kBlock / GS : n;
+        const int64_t ic = live ? i : c0;
+        const int32_t s0 = lOff[c0], s1 = lOff[c1];
+        const int32_t l0 = lOff[ic], l1 = live ? lOff[ic + 1] : l0;
+        const int32_t r0 = rOff[ic], r1 = live ? rOff[ic + 1] : r0;
+        const int32_t ns = (s1 - s0 < kUpdStage) ? s1 - s0 : kUpdStage;
+        int32_t fr[KR];
+        for (int r = 0; r < KR; r++) {
+            const int32_t q = r0 + lane + r * GS;
+            fr[r] = q < r1 ? rFace[q] : 0;
+        }
+        const int tot = ns * FM;
+        const double *src = flux + (int64_t)s0 * FM;
+        f64x2u piece[IT];
+        for (int k = 0; k < IT; k++) {
+            const int e = 2 * (k * kBlock + (int)threadIdx.x);
+            if (e + 1 < tot) piece[k] = *reinterpret_cast<const f64x2u *>(src + e);
+            else if (e < tot) piece[k] = f64x2u{src[e], 0.0};
+        }
+        double FRr[KR][FM];
+        bool hr[KR];
+        for (int r = 0; r < KR; r++) {
+            hr[r] = r0 + lane + r * GS < r1;
+            load_rec<FM>(flux + (int64_t)(hr[r] ? fr[r] : 0) * FM, FRr[r]);
+        }
+        typedef double f64x2a __attribute__((ext_vector_type(2)));
+        for (int k = 0; k < IT; k++) {
+            const int e = 2 * (k * kBlock + (int)threadIdx.x);
+            if (e < tot) *reinterpret_cast<f64x2a *>(stage + e) = f64x2a{piece[k][0], piece[k][1]};
+        }
+        __syncthreads();
+        if (!live) return;
+        double acc[NS];
+        for (int c = 0; c < NS; c++) acc[c] = 0.0;
+        for (int32_t f = l0 + lane; f < l1; f += GS) {
+            double F[FM];
+            const int32_t q = f - s0;
+            if (q < ns) {
+                for (int c = 0; c < FM; c++) F[c] = stage[q * FM + c];
+            } else {
+                load_rec<FM>(flux + (int64_t)f * FM, F);
+            }
+            for (int c = 0; c < NS; c++) acc[c] += -1.0 * F[c];
+        }
+        for (int r = 0; r < KR; r++)
+            if (hr[r])
+                for (int c = 0; c < NS; c++) acc[c] += 1.0 * FRr[r][c];
+        for (int32_t q = r0 + lane + KR * GS; q < r1; q += GS) {
+            double F[FM];
+            load_rec<FM>(flux + (int64_t)rFace[q] * FM, F);
+            for (int c = 0; c < NS; c++) acc[c] += 1.0 * F[c];
+        }
+        for (int c = 0; c < NS; c++) acc[c] = grp_sum<GS>(acc[c]);
+        if (lane == 0) finish_cell<D, EM, GRAV>(i, n, acc, 0.0, Q, u);
+    }
 }
 
 }  // namespace mm

@@ -15,11 +15,14 @@
 //   A, |d|, n (D) = d/|d|, c (D) = f - (r_L + r_R)/2;
 // the double face velocity w_f in its own array, D per face (the double
 // path, the volume rate).
-// Mixed face record (float), one per face, 11 floats in 3D:
-//   A, |d|, n (D), c (D), w_f - W0 (D) (formed in double, rounded once), so
-//   with the cells' v_K - W0 the face-frame velocities are
-//   (v_K - W0) - (w_f - W0), and the lab-frame flux takes the face velocity
-//   as W0 + (w_f - W0) in double: the same velocity both ways;
+// Mixed face record (float), one per face, 32 bytes in 3D:
+//   A, |d|, n (D), c (D);
+// and beside it the face velocity relative to W0, w_f - W0 (formed in
+// double, rounded once), D floats per face in its own array (a 12-byte
+// access per lane, contiguous over a wavefront). With the cells' v_K - W0
+// the face-frame velocities are (v_K - W0) - (w_f - W0), and the lab-frame
+// flux takes the face velocity as W0 + (w_f - W0) in double: the same
+// velocity both ways;
 // Face fluxes: face-major, D + 2 doubles per face.
 // Side record, one per (cell, face) pair in CSR order:
 //   double path: A/|d|, f - r_i (D)             stride 4
@@ -39,8 +42,7 @@ template <int D> struct Lay {
     static constexpr int FA = 0, FELL = 1, FN = 2, FC = 2 + D;
     static constexpr int FREC = 2 + 2 * D;
     // mixed face record
-    static constexpr int MW = 2 + 2 * D;
-    static constexpr int MREC = 2 + 3 * D;
+    static constexpr int MREC = 2 + 2 * D;
     static constexpr int WSTRIDE = D;
     // face fluxes
     static constexpr int FSTRIDE = NV;

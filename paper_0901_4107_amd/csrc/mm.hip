@@ -62,7 +62,7 @@ struct Layout {
     int64_t loff, roff, rface;              // the update's left ranges and right faces
     int64_t ekmax;                          // energy switch: neighbour energies per cell
     int64_t srec, frec, wf64, rec, flux;    // double path (frec, wf64 always; flux: timelines only)
-    int64_t srec32, mrec, rec32, hard, w0, w0part;             // mixed path
+    int64_t srec32, mrec, wrel, rec32, hard, w0, w0part, coff32;   // mixed path
     int64_t tb_bin, tb_trec, tb_sig, tb_touch, tb_cells, tb_faces, tb_touched, tb_info;   // individual timesteps
     int64_t total;
 };
@@ -98,7 +98,7 @@ Layout make_layout(int D, int mode, int em, bool tb, int64_t n, int64_t nf) {
     L.rface = take(nf * sizeof(int32_t));
     L.flux = take(nf * FM * sizeof(double));
     L.ekmax = em == MM_ENTROPY_ENERGY ? take(n * sizeof(double)) : -1;
-    L.srec = L.srec32 = L.mrec = L.rec32 = L.rec = L.hard = L.w0 = L.w0part = -1;
+    L.srec = L.srec32 = L.mrec = L.wrel = L.rec32 = L.rec = L.hard = L.w0 = L.w0part = L.coff32 = -1;
     if (mode == MM_FP64) {
         L.srec = take(2 * nf * Lay<3>::SREC64 * sizeof(double));
         L.rec = take(n * REC * sizeof(double));
@@ -107,7 +107,9 @@ Layout make_layout(int D, int mode, int em, bool tb, int64_t n, int64_t nf) {
         L.w0 = take(4 * sizeof(double));
         L.w0part = take((int64_t)plain_grid_n(n) * 2 * 3 * sizeof(double));
         L.mrec = take(nf * Lay<3>::MREC * sizeof(float));
+        L.wrel = take(nf * D * sizeof(float));
         L.rec32 = take(n * REC * sizeof(float));
+        L.coff32 = take(D * n * sizeof(float));
         // with individual timesteps the hard faces of one face sub-list
         L.hard = take((tb ? split_ints(tb_face_cap(n, nf)) : list_ints(grid_for(nf))) * sizeof(int32_t));
     }
@@ -140,6 +142,7 @@ struct mm_ctx {
     uint64_t faces_done = 0, waves_done = 0;
     mm_mesh mesh;
     const double *accel = nullptr;        // static gravitational field [D][N], or none
+    double w0h[3] = {0.0, 0.0, 0.0};      // mixed mode: W0 of the mesh's velocities (host copy)
     bool have_ek = false;                 // the energy switch's neighbour energies are in the workspace
     const double *last_dt_dev = nullptr;  // timestep of the last face-flux pass (device) ...
     double last_dt = 0.0;                 // ... or its value
@@ -296,6 +299,14 @@ template <int D> static void launch_validate(mm_ctx *c, const mm_mesh *m, int32_
 // The mixed mode's reference velocity W0 (the midrange of the generator
 // velocities) and the face records: everything that depends on the
 // generator velocities; with so.ent (the upload) also the side records.
+// The mixed mode's W0 into the context's host copy (the face kernels take it
+// by value); complete at the caller's next synchronisation.
+static mm_status fetch_w0(mm_ctx *c) {
+    if (c->p.mode != MM_MIXED) return MM_OK;
+    MM_CHECK(hipMemcpyAsync(c->w0h, c->at<double>(c->lay.w0), c->D * sizeof(double), hipMemcpyDeviceToHost, c->st()));
+    return MM_OK;
+}
+
 template <int D> static void launch_face_records(mm_ctx *c, const mm_mesh *m, const SideOut &so = SideOut{}) {
     const Layout &L = c->lay;
     const int mixed = c->p.mode == MM_MIXED;
@@ -307,7 +318,7 @@ template <int D> static void launch_face_records(mm_ctx *c, const mm_mesh *m, co
     k_face_records<D><<<plain_grid(m->n_faces), kBlock, 0, c->st()>>>(
         m->n_cells, m->n_faces, m->face_L, m->face_R, m->face_area, m->face_ctr, m->face_sep, m->mesh_vel,
         c->at<double>(L.frec), mixed ? c->at<double>(L.w0) : nullptr, mixed ? c->at<float>(L.mrec) : nullptr,
-        c->at<double>(L.wf64), so);
+        mixed ? c->at<float>(L.wrel) : nullptr, c->at<double>(L.wf64), so);
 }
 
 mm_status mm_mesh_upload(mm_ctx *c, const mm_mesh *m) {
@@ -366,11 +377,14 @@ mm_status mm_mesh_upload(mm_ctx *c, const mm_mesh *m) {
     if (c->D == 3) {
         launch_face_records<3>(c, m, so);
         k_closure<3><<<group_grid(3, n), kBlock, 0, s>>>(n, c->at<double>(L.frec), loff, roff, rface, off, flags);
+        if (mixed) k_coff32<3><<<plain_grid(n), kBlock, 0, s>>>(n, m->centroid_off, c->at<float>(L.coff32));
     } else {
         launch_face_records<2>(c, m, so);
         k_closure<2><<<group_grid(2, n), kBlock, 0, s>>>(n, c->at<double>(L.frec), loff, roff, rface, off, flags);
+        if (mixed) k_coff32<2><<<plain_grid(n), kBlock, 0, s>>>(n, m->centroid_off, c->at<float>(L.coff32));
     }
     MM_LAUNCH_CHECK();
+    if (mm_status st = fetch_w0(c); st != MM_OK) return st;
     MM_CHECK(hipMemcpyAsync(&hflags, flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     MM_CHECK(hipStreamSynchronize(s));
     if (hflags) return MM_E_MESH;
@@ -399,6 +413,7 @@ mm_status mm_mesh_set_velocity(mm_ctx *c, const double *mesh_vel) {
     }
     MM_LAUNCH_CHECK();
     int32_t hflags = 0;
+    if (mm_status st = fetch_w0(c); st != MM_OK) return st;
     MM_CHECK(hipMemcpyAsync(&hflags, flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     MM_CHECK(hipStreamSynchronize(s));
     if (hflags) return MM_E_MESH;
@@ -416,8 +431,9 @@ template <int D, typename T> static mm_status gradients_t(mm_ctx *c, const doubl
     const bool f64 = sizeof(T) == 8;
     const T *srec = f64 ? (const T *)c->at<double>(L.srec) : (const T *)c->at<float>(L.srec32);
     const double *w0 = f64 ? nullptr : c->at<double>(L.w0);
+    const T *coff = f64 ? (const T *)c->mesh.centroid_off : (const T *)c->at<float>(L.coff32);
     k_prim_cfl<D, T><<<grid_for(c->n), kBlock, 0, s>>>(c->n, c->p.gamma, c->p.cfl, c->mesh.volume, Q,
-                                                      c->mesh.mesh_vel, c->mesh.centroid_off, rec, w0, dt_part,
+                                                      c->mesh.mesh_vel, coff, rec, w0, dt_part,
                                                       c->at<int32_t>(L.flags) + 2);
     if (c->p.entropy == MM_ENTROPY_ENERGY) {   // with the energy switch's neighbour energies
         k_grad_limit<D, T, true><<<group_grid(D, c->n), kBlock, 0, s>>>(
@@ -448,7 +464,8 @@ mm_status mm_gradients(mm_ctx *c, const double *Q, void *recon) {
 }
 
 static FaceAux face_aux(const mm_ctx *c) {
-    return FaceAux{c->accel, c->n, c->p.mode == MM_MIXED ? c->at<double>(c->lay.w0) : nullptr};
+    const bool mixed = c->p.mode == MM_MIXED;
+    return FaceAux{c->accel, c->n, {c->w0h[0], c->w0h[1], c->w0h[2]}, mixed ? c->at<float>(c->lay.wrel) : nullptr};
 }
 
 // The face fluxes in entropy mode EM, face-major records into flux.
@@ -996,11 +1013,11 @@ template <int D, typename T> static void tb_point(mm_ctx *c, double *Q, T *rec) 
         kern<<<kTbGrid, kBlock, 0, s>>>(faces, fcap, c->mesh.face_L, c->mesh.face_R, c->at<float>(L.mrec),
                                         (const float *)rec, (const float *)grad, view, kf,
                                         kg.g_over_gm1, (float)c->p.newton_tol32, c->p.newton_max_iter, mlp, flux,
-                                        hard, diag, c->at<double>(L.w0));
+                                        hard, diag, face_aux(c));
         k_face_flux_hard<D, 0, false><<<kTbGrid, kBlock, 0, s>>>(
             c->mesh.face_L, c->mesh.face_R, c->at<float>(L.mrec), (const float *)rec,
             (const float *)grad, nullptr, 0.0, kf.g, kg, c->p.newton_tol64, hard, fcap, flux, diag,
-            FaceAux{nullptr, c->n, c->at<double>(L.w0)}, view);
+            face_aux(c), view);
     }
     const TbSides sd{c->at<int32_t>(L.loff), c->at<int32_t>(L.roff), c->at<int32_t>(L.rface), c->mesh.face_L,
                      c->mesh.face_R};
