@@ -88,9 +88,10 @@ typedef int32_t mm_status;
  * or, with a static field (mm_set_gravity), below beta_s M |g_i| R_i, R_i
  * the radius of the cell's volume. A parameter <= 0 switches its condition
  * off. The gradient pass (mm_gradients, or the step's own) records each
- * cell's largest neighbour energy in the workspace, from the states it
- * takes the gradients of; mm_apply_update returns MM_E_STATE before any
- * gradient pass. The cell's own energy comes from Q at the update. */
+ * cell's largest such energy (its own and its neighbours') in the
+ * workspace, from the reconstruction records it takes the gradients of
+ * (float in MM_MIXED); mm_apply_update returns MM_E_STATE before any
+ * gradient pass. */
 #define MM_ENTROPY_ENERGY 2
 
 /* Timestep scheme (Section 7.2). MM_STEPS_INDIVIDUAL adds the arrays of a

@@ -280,8 +280,8 @@ __device__ __forceinline__ void limit_side(const T *g, const T *dl, const T (&gr
     }
 }
 
-// The energy switch's neighbour term (Section 3.5, eq. eqnScrit1): the
-// kinetic energy of neighbour j in the frame of cell i's generator,
+// The energy switch's term (Section 3.5, eq. eqnScrit1): the kinetic
+// energy of neighbour j (or of cell i itself) in the frame of cell i's generator,
 // M_j |v_j - w_i|^2 / 2 with M_j = rho_j V_j (0 for a vacuum neighbour), from
 // j's values pj as the gradient pass reads them: the primitive records hold
 // v_j (double) or v_j - W0 (float), and wg is w_i in the same frame, so
@@ -289,13 +289,13 @@ __device__ __forceinline__ void limit_side(const T *g, const T *dl, const T (&gr
 // form's velocities carry float rounding already, and the switch compares
 // this with the cell's thermal energy at a threshold alpha far above it.
 template <int D, typename T>
-__device__ __forceinline__ T ekin_in_frame(const T *pj, double Vj, const double (&wg)[D]) {
+__device__ __forceinline__ T ekin_in_frame(const T *pj, T Mj, const double (&wg)[D]) {
     T e = (T)0;
     for (int k = 0; k < D; k++) {
         const T dv = pj[1 + k] - (T)wg[k];
         e += dv * dv;
     }
-    return pj[0] > (T)0 ? (T)0.5 * (pj[0] * (T)Vj) * e : (T)0;
+    return pj[0] > (T)0 ? (T)0.5 * Mj * e : (T)0;
 }
 
 // The gradient kernel's window (mixed mode): the primitive records of the
@@ -319,20 +319,22 @@ __device__ __forceinline__ void load_nb(const T *__restrict__ prim, int64_t j, c
     load_rec<NJ>(prim + j * PREC + Lay<D>::W, o);
 }
 
-// The volume of neighbour j (energy switch): from the window's volumes vwin
-// when it holds j, else from V.
-__device__ __forceinline__ double nb_vol(const double *__restrict__ V, int64_t j, const double *vwin, int64_t c0) {
-    typedef __attribute__((address_space(3))) const double lds_cdouble;
+// The mass rho_j V_j of neighbour j in the records' precision (energy
+// switch), rho_j its record's density: from the window's masses mwin (the
+// same product, formed once per window cell) when it holds j, else formed here.
+template <typename T>
+__device__ __forceinline__ T nb_mass(const double *__restrict__ V, int64_t j, T rho, const float *mwin, int64_t c0) {
     const int64_t k = j - c0;
-    if (vwin && k >= 0 && k < kGWin) return ((lds_cdouble *)vwin)[k];
-    return V[j];
+    if constexpr (sizeof(T) == 4)
+        if (mwin && k >= 0 && k < kGWin) return ((lds_cfloat *)mwin)[k];
+    return rho * (T)V[j];
 }
 
 // The gradient and limiter of cell i by its lane group (lane = index in
 // the group); every lane of the group calls it with the same i. The
 // neighbours' W come from their primitive records. With ESW, also the
-// energy switch's largest neighbour kinetic energy in the frame of the
-// cell's generator, into ekmax[i] (the states are the step's start states,
+// energy switch's largest kinetic energy of the cell and its neighbours in
+// the frame of the cell's generator, into ekmax[i] (the states are the step's start states,
 // those the gradient is taken from; mvel the generator velocities, w0 the
 // mixed mode's reference velocity). win: the block's window of primitive
 // records, starting at cell c0 (null: every record from HBM); vwin the
@@ -343,8 +345,8 @@ __device__ __forceinline__ void grad_cell(int64_t i, int lane, const int32_t *__
                                           const double *__restrict__ V, const T *__restrict__ prim,
                                           T *__restrict__ grad_out, const double *__restrict__ mvel = nullptr,
                                           const double *__restrict__ w0 = nullptr, int64_t n = 0,
-                                          double *__restrict__ ekmax = nullptr, const float *win = nullptr,
-                                          int64_t c0 = 0, const double *vwin = nullptr) {
+                                          T *__restrict__ ekmax = nullptr, const float *win = nullptr,
+                                          int64_t c0 = 0, const float *mwin = nullptr) {
     using Y = Lay<D>;
     constexpr int NV = D + 2;
     constexpr int GS = Group<D>::GS;
@@ -358,7 +360,7 @@ __device__ __forceinline__ void grad_cell(int64_t i, int lane, const int32_t *__
     // the neighbours' records, all in flight together (an absent side reads
     // record 0 of the arrays and is skipped)
     T sr[KR][SR], pj[KR][NJ];
-    double vj[KR];
+    T vj[KR];
     bool has[KR];
     for (int r = 0; r < KR; r++) {
         const int32_t q = b + lane + r * GS;
@@ -367,7 +369,7 @@ __device__ __forceinline__ void grad_cell(int64_t i, int lane, const int32_t *__
         load_rec<SR>(srec + (int64_t)qq * SR, sr[r]);
         const int32_t jn = nbr[qq];
         load_nb<D, T>(prim, jn, win, c0, pj[r]);
-        if constexpr (ESW) vj[r] = nb_vol(V, jn, vwin, c0);
+        if constexpr (ESW) vj[r] = nb_mass<T>(V, jn, pj[r][0], mwin, c0);
     }
     T pi[Y::PREC];
     load_rec<Y::PREC>(prim + i * Y::PREC, pi);
@@ -394,11 +396,11 @@ __device__ __forceinline__ void grad_cell(int64_t i, int lane, const int32_t *__
         const int32_t j = nbr[q];
         load_nb<D, T>(prim, j, win, c0, p2);
         grad_side<D, T>(s2, p2, wi, a);
-        if constexpr (ESW) ek = fmax(ek, ekin_in_frame<D, T>(p2, nb_vol(V, j, vwin, c0), wlab));
+        if constexpr (ESW) ek = fmax(ek, ekin_in_frame<D, T>(p2, nb_mass<T>(V, j, p2[0], mwin, c0), wlab));
     }
-    if constexpr (ESW) {
+    if constexpr (ESW) {   // with the cell's own, in the same frame and precision
         ek = grp_max<GS>(ek);
-        if (lane == 0) ekmax[i] = (double)ek;
+        if (lane == 0) ekmax[i] = fmax(ek, ekin_in_frame<D, T>(wi, wi[0] * (T)V[i], wlab));
     }
     const T inv_v = (T)(1.0 / V[i]);
     T grad[NV][D], dmx[NV], dmn[NV];
@@ -444,20 +446,22 @@ __device__ __forceinline__ void grad_cell(int64_t i, int lane, const int32_t *__
 // than the register count the compiler picks on its own (5 float / 4 double,
 // about 7-9% faster; the 3D double kernel spills a few bytes per lane). The
 // float kernels hold 5 sides per lane in registers, 3 with the energy
-// switch's neighbour energies, which keeps both at 5 or more without spills
-// (a spill of 32 bytes per lane once cost the float kernel about 20%); the
-// double kernel with the switch runs at 3.
+// switch's neighbour energies, without spills at 5 and (with the switch) 7
+// wavefronts per SIMD (a spill of 32 bytes per lane once cost the float
+// kernel about 20%; the switch's kernel at 7 is 1% faster per step than at
+// 6); the double kernel with the switch runs at 3.
 template <int D, typename T, bool ESW>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : (ESW ? 3 : 4))))
+__global__ void __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? (ESW ? 7 : 5) : (ESW ? 3 : 4))))
 k_grad_limit(int64_t n, const int32_t *__restrict__ off, const int32_t *__restrict__ nbr, const T *__restrict__ srec,
              const double *__restrict__ V, const T *__restrict__ prim, T *__restrict__ grad_out,
-             const double *__restrict__ mvel, const double *__restrict__ w0, double *__restrict__ ekmax) {
+             const double *__restrict__ mvel, const double *__restrict__ w0, T *__restrict__ ekmax) {
     constexpr int GS = Group<D>::GS;
     const int64_t i = xcd_tile() * (kBlock / GS) + threadIdx.x / GS;
     // mixed mode: stage the window (every lane takes part in the copy and the
     // barrier before any group leaves)
     const float *win = nullptr;
-    const double *vwin = nullptr;
+    const float *mwin = nullptr;
     int64_t c0 = 0;
     if constexpr (sizeof(T) == 4) {
         constexpr int PREC = Lay<D>::PREC;
@@ -469,19 +473,19 @@ k_grad_limit(int64_t n, const int32_t *__restrict__ off, const int32_t *__restri
             if (j >= 0 && j < n) v = *reinterpret_cast<const f32x4u *>((const float *)prim + j * PREC + (e % (PREC / 4)) * 4);
             *reinterpret_cast<f32x4u *>(wbuf + e * 4) = v;
         }
-        if constexpr (ESW) {   // and the window's volumes
-            __shared__ double vbuf[kGWin];
+        if constexpr (ESW) {   // and the window's masses rho_j V_j
+            __shared__ float mbuf[kGWin];
             for (int e = threadIdx.x; e < kGWin; e += kBlock) {
                 const int64_t j = c0 + e;
-                vbuf[e] = (j >= 0 && j < n) ? V[j] : 0.0;
+                mbuf[e] = (j >= 0 && j < n) ? ((const float *)prim)[j * PREC + Lay<D>::W] * (float)V[j] : 0.0f;
             }
-            vwin = vbuf;
+            mwin = mbuf;
         }
         __syncthreads();
         win = wbuf;
     }
     if (i >= n) return;  // whole groups leave together
-    grad_cell<D, T, ESW>(i, threadIdx.x % GS, off, nbr, srec, V, prim, grad_out, mvel, w0, n, ekmax, win, c0, vwin);
+    grad_cell<D, T, ESW>(i, threadIdx.x % GS, off, nbr, srec, V, prim, grad_out, mvel, w0, n, ekmax, win, c0, mwin);
 }
 
 // The total entropy of every cell from its conserved state (Section 3.5):

@@ -42,8 +42,8 @@ struct UpdateArgs {
     const double *dt_ptr;      // timestep of the flux pass (device) or null
     double dt_val;             // ... or its value
     double alpha_s, beta_s;    // energy switch
-    const double *mvel;        // generator velocities [D][n]
-    const double *ekmax;       // energy switch: the gradient pass's largest neighbour energy per cell
+    const double *ekmax;       // energy switch: the gradient pass's largest kinetic energy per cell,
+    const float *ekmax32;      // ... or, in the mixed mode, the same in float
 };
 
 // The end of cell i's update, by lane 0 of its group: Q_i <- Q_i + acc,
@@ -57,10 +57,9 @@ struct UpdateArgs {
 // frame, or with a field below beta_s M |g| R (EM == 2) -- and its new mass
 // and entropy are positive; every other cell takes S = M P / rho^gamma of
 // its updated state, 0 for M <= 0).
-// mx: the largest face Mach number; the largest neighbour kinetic energy in
-// the cell's generator frame is the gradient pass's ekmax, the cell's own
-// added here from Q at the start of the step. Returns whether the cell kept
-// its entropy.
+// mx: the largest face Mach number; the largest kinetic energy of the cell
+// and its neighbours in the cell's generator frame is the gradient pass's
+// ekmax. Returns whether the cell kept its entropy.
 template <int D, int EM, bool GRAV>
 __device__ __forceinline__ bool finish_cell(int64_t i, int64_t n, const double *acc, double mx,
                                             double *__restrict__ Q, const UpdateArgs &u) {
@@ -69,18 +68,7 @@ __device__ __forceinline__ bool finish_cell(int64_t i, int64_t n, const double *
     double q[NS];
     for (int c = 0; c < NS; c++) q[c] = Q[c * n + i] + acc[c];
     double ek = 0.0;
-    if constexpr (EM == 2) {
-        ek = u.ekmax[i];
-        const double m0 = Q[i];
-        if (m0 > 0.0) {
-            double e = 0.0;
-            for (int k = 0; k < D; k++) {
-                const double dv = Q[(1 + k) * n + i] / m0 - u.mvel[k * n + i];
-                e += dv * dv;
-            }
-            ek = fmax(ek, 0.5 * m0 * e);
-        }
-    }
+    if constexpr (EM == 2) ek = u.ekmax32 ? (double)u.ekmax32[i] : u.ekmax[i];
     if constexpr (GRAV) {
         const double hdt = 0.5 * (u.dt_ptr ? *u.dt_ptr : u.dt_val), m0 = Q[i];
         double work = 0.0;

@@ -60,7 +60,7 @@ inline unsigned plain_grid_n(int64_t n) { return (unsigned)((n + kBlock - 1) / k
 struct Layout {
     int64_t flags, diag, mlp, dtdev, bhard, dtpart, bsum, off, cursor, ent, nbr;
     int64_t loff, roff, rface;              // the update's left ranges and right faces
-    int64_t ekmax;                          // energy switch: neighbour energies per cell
+    int64_t ekmax;                          // energy switch: largest kinetic energy per cell (float when mixed)
     int64_t srec, frec, wf64, rec, flux;    // double path (frec, wf64 always; flux: timelines only)
     int64_t srec32, mrec, wrel, rec32, hard, w0, w0part, coff32;   // mixed path
     int64_t tb_bin, tb_trec, tb_sig, tb_touch, tb_cells, tb_faces, tb_touched, tb_info;   // individual timesteps
@@ -438,7 +438,7 @@ template <int D, typename T> static mm_status gradients_t(mm_ctx *c, const doubl
     if (c->p.entropy == MM_ENTROPY_ENERGY) {   // with the energy switch's neighbour energies
         k_grad_limit<D, T, true><<<group_grid(D, c->n), kBlock, 0, s>>>(
             c->n, c->at<int32_t>(L.off), c->at<int32_t>(L.nbr), srec, c->mesh.volume, rec, grad_block<D>(c, rec),
-            c->mesh.mesh_vel, w0, c->at<double>(L.ekmax));
+            c->mesh.mesh_vel, w0, (T *)c->at<double>(L.ekmax));
         c->have_ek = true;
     } else {
         k_grad_limit<D, T, false><<<group_grid(D, c->n), kBlock, 0, s>>>(
@@ -536,7 +536,8 @@ static UpdateArgs update_args(const mm_ctx *c) {
     const Layout &L = c->lay;
     return UpdateArgs{c->at<int32_t>(L.flags) + 1, c->mesh.volume, c->p.gamma, c->p.mach_thresh,
                       c->at<DiagDev>(L.diag), c->accel, c->last_dt_dev, c->last_dt, c->p.alpha_s, c->p.beta_s,
-                      c->mesh.mesh_vel, L.ekmax >= 0 ? c->at<double>(L.ekmax) : nullptr};
+                      (L.ekmax >= 0 && c->p.mode == MM_FP64) ? c->at<double>(L.ekmax) : nullptr,
+                      (L.ekmax >= 0 && c->p.mode == MM_MIXED) ? c->at<float>(L.ekmax) : nullptr};
 }
 
 // The update from face-major records.
