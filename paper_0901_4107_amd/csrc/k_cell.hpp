@@ -117,7 +117,8 @@ __device__ __forceinline__ double cell_prim(int64_t i, int64_t n, double gamma, 
 // record of every cell (cell_prim) and the per-block minimum of
 //   dt_i = C R_i / (c_i + |v_i - w_i|), R_i the radius of the cell's volume;
 // vacuum cells impose no limit. As the first kernel of a step it clears the
-// step's non-finite flag (step_flag, may be null). w0: the mixed mode's
+// step's non-finite flag (step_flag, may be null) and, given clear, the
+// nclear counters of the face pass's hard-face list. w0: the mixed mode's
 // reference velocity (null in double). coff: the centroid offsets in the
 // records' precision (the mixed mode's float copy, made at upload).
 template <int D, typename T>
@@ -125,10 +126,13 @@ __global__ void __launch_bounds__(kBlock) k_prim_cfl(int64_t n, double gamma, do
                                                      const double *__restrict__ Q, const double *__restrict__ mvel,
                                                      const T *__restrict__ coff, T *__restrict__ prim,
                                                      const double *__restrict__ w0, double *__restrict__ dt_part,
-                                                     int32_t *step_flag) {
+                                                     int32_t *step_flag, int32_t *__restrict__ clear, int nclear) {
     using Y = Lay<D>;
     const int64_t i = xcd_global_id();
     if (step_flag && blockIdx.x == 0 && threadIdx.x == 0) *step_flag = 0;
+    if (clear)
+        for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < nclear; q += (int64_t)gridDim.x * kBlock)
+            clear[q] = 0;
     double dti = INFINITY;
     if (i < n) {
         T r[Y::PREC];
@@ -149,19 +153,6 @@ __global__ void __launch_bounds__(kBlock) k_coff32(int64_t n, const double *__re
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     for (int k = 0; k < D; k++) out[k * n + i] = (float)coff[k * n + i];
-}
-
-__global__ void __launch_bounds__(1024) k_min_final(int64_t nparts, const double *part, double *out) {
-    __shared__ double red[16];
-    double v = INFINITY;
-    for (int64_t k = threadIdx.x; k < nparts; k += 1024) v = fmin(v, part[k]);
-    for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x / 64] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int k = 1; k < 16; k++) v = fmin(v, red[k]);
-        out[0] = v;
-    }
 }
 
 // The reference velocity W0 of the mixed mode's records: per component the
@@ -450,13 +441,22 @@ __device__ __forceinline__ void grad_cell(int64_t i, int lane, const int32_t *__
 // wavefronts per SIMD (a spill of 32 bytes per lane once cost the float
 // kernel about 20%; the switch's kernel at 7 is 1% faster per step than at
 // 6); the double kernel with the switch runs at 3.
+// With dt_out, block 0 also reduces the Courant pass's nparts block minima
+// dt_part to the global timestep (the face pass after it reads it).
 template <int D, typename T, bool ESW>
 __global__ void __launch_bounds__(kBlock)
 __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? (ESW ? 7 : 5) : (ESW ? 3 : 4))))
 k_grad_limit(int64_t n, const int32_t *__restrict__ off, const int32_t *__restrict__ nbr, const T *__restrict__ srec,
              const double *__restrict__ V, const T *__restrict__ prim, T *__restrict__ grad_out,
-             const double *__restrict__ mvel, const double *__restrict__ w0, T *__restrict__ ekmax) {
+             const double *__restrict__ mvel, const double *__restrict__ w0, T *__restrict__ ekmax,
+             const double *__restrict__ dt_part, int64_t nparts, double *__restrict__ dt_out) {
     constexpr int GS = Group<D>::GS;
+    if (dt_out && blockIdx.x == 0) {   // the whole block, before any group leaves
+        double v = INFINITY;
+        for (int64_t k = threadIdx.x; k < nparts; k += kBlock) v = fmin(v, dt_part[k]);
+        v = block_min(v);
+        if (threadIdx.x == 0) *dt_out = v;
+    }
     const int64_t i = xcd_tile() * (kBlock / GS) + threadIdx.x / GS;
     // mixed mode: stage the window (every lane takes part in the copy and the
     // barrier before any group leaves)

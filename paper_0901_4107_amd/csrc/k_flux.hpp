@@ -873,9 +873,11 @@ __global__ void __launch_bounds__(kBlock) k_face_flux64_list(const int32_t *__re
 
 // The same on the mixed path: hard faces go to the split hard list (the
 // sub-list of the block's residue, which holds at most as many items as
-// the face sub-list the block walks) for k_face_flux_hard.
+// the face sub-list the block walks) for k_face_flux_hard. The learned
+// instantiation runs at 4 wavefronts per SIMD, where it needs no spill
+// (1% faster per timeline cycle than 5 with 16 bytes spilled).
 template <int D, bool LEARNED>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5)))
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(LEARNED ? 4 : 5)))
 k_face_flux_mixed_list(const int32_t *__restrict__ list, int64_t cap, const int32_t *__restrict__ fL,
                        const int32_t *__restrict__ fR, const float *__restrict__ mrec,
                        const float *__restrict__ prim,

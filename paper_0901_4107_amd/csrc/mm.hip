@@ -4,8 +4,9 @@
 // (vii)) on a tessellation the caller provides. Device work per step:
 //   k_prim_cfl     per cell        Q -> primitives in the cell records,
 //                                  per-block Courant minimum
-//   k_min_final    one block       global timestep (stays on the device)
-//   k_grad_limit   lane group/cell limited gradients from the side records
+//   k_grad_limit   lane group/cell limited gradients from the side records;
+//                                  its block 0 the global timestep (stays on
+//                                  the device)
 //   k_face_flux*   per face        extrapolation, Riemann solve, lab-frame flux
 //   k_update       lane group/cell segmented sum of the face fluxes
 // Individual timesteps (Section 7.2, mm_tb_*) run one synchronisation point
@@ -425,35 +426,47 @@ mm_status mm_mesh_set_velocity(mm_ctx *c, const double *mesh_vel) {
 // the gradient block [N][GREC].
 template <int D, typename T> static T *grad_block(const mm_ctx *c, T *rec) { return rec + c->n * Lay<D>::PREC; }
 
-template <int D, typename T> static mm_status gradients_t(mm_ctx *c, const double *Q, T *rec, double *dt_part) {
+// What the step's own gradient pass does besides: clear the face pass's
+// hard-list counters (clear), and reduce the Courant minima to the
+// timestep on the device (dt_out).
+struct StepPass {
+    int32_t *clear = nullptr;
+    double *dt_out = nullptr;
+};
+
+template <int D, typename T>
+static mm_status gradients_t(mm_ctx *c, const double *Q, T *rec, double *dt_part, const StepPass &sp) {
     const Layout &L = c->lay;
     hipStream_t s = c->st();
     const bool f64 = sizeof(T) == 8;
     const T *srec = f64 ? (const T *)c->at<double>(L.srec) : (const T *)c->at<float>(L.srec32);
     const double *w0 = f64 ? nullptr : c->at<double>(L.w0);
     const T *coff = f64 ? (const T *)c->mesh.centroid_off : (const T *)c->at<float>(L.coff32);
-    k_prim_cfl<D, T><<<grid_for(c->n), kBlock, 0, s>>>(c->n, c->p.gamma, c->p.cfl, c->mesh.volume, Q,
-                                                      c->mesh.mesh_vel, coff, rec, w0, dt_part,
-                                                      c->at<int32_t>(L.flags) + 2);
+    const unsigned pg = grid_for(c->n);
+    k_prim_cfl<D, T><<<pg, kBlock, 0, s>>>(c->n, c->p.gamma, c->p.cfl, c->mesh.volume, Q, c->mesh.mesh_vel, coff,
+                                          rec, w0, dt_part, c->at<int32_t>(L.flags) + 2, sp.clear,
+                                          sp.clear ? kLists * kListPad : 0);
     if (c->p.entropy == MM_ENTROPY_ENERGY) {   // with the energy switch's neighbour energies
         k_grad_limit<D, T, true><<<group_grid(D, c->n), kBlock, 0, s>>>(
             c->n, c->at<int32_t>(L.off), c->at<int32_t>(L.nbr), srec, c->mesh.volume, rec, grad_block<D>(c, rec),
-            c->mesh.mesh_vel, w0, (T *)c->at<double>(L.ekmax));
+            c->mesh.mesh_vel, w0, (T *)c->at<double>(L.ekmax), dt_part, pg, sp.dt_out);
         c->have_ek = true;
     } else {
         k_grad_limit<D, T, false><<<group_grid(D, c->n), kBlock, 0, s>>>(
             c->n, c->at<int32_t>(L.off), c->at<int32_t>(L.nbr), srec, c->mesh.volume, rec, grad_block<D>(c, rec),
-            nullptr, nullptr, nullptr);
+            nullptr, nullptr, nullptr, dt_part, pg, sp.dt_out);
     }
     MM_LAUNCH_CHECK();
     return MM_OK;
 }
 
-static mm_status gradients_into(mm_ctx *c, const double *Q, void *rec, double *dt_part) {
+static mm_status gradients_into(mm_ctx *c, const double *Q, void *rec, double *dt_part, const StepPass &sp = {}) {
     const bool f64 = c->p.mode == MM_FP64;
     if (c->D == 3)
-        return f64 ? gradients_t<3, double>(c, Q, (double *)rec, dt_part) : gradients_t<3, float>(c, Q, (float *)rec, dt_part);
-    return f64 ? gradients_t<2, double>(c, Q, (double *)rec, dt_part) : gradients_t<2, float>(c, Q, (float *)rec, dt_part);
+        return f64 ? gradients_t<3, double>(c, Q, (double *)rec, dt_part, sp)
+                   : gradients_t<3, float>(c, Q, (float *)rec, dt_part, sp);
+    return f64 ? gradients_t<2, double>(c, Q, (double *)rec, dt_part, sp)
+               : gradients_t<2, float>(c, Q, (float *)rec, dt_part, sp);
 }
 
 mm_status mm_gradients(mm_ctx *c, const double *Q, void *recon) {
@@ -470,7 +483,7 @@ static FaceAux face_aux(const mm_ctx *c) {
 
 // The face fluxes in entropy mode EM, face-major records into flux.
 template <int D, int EM, bool GRAV>
-static mm_status fluxes_t(mm_ctx *c, const double *dt_dev, double dt, const void *rec, double *flux) {
+static mm_status fluxes_t(mm_ctx *c, const double *dt_dev, double dt, const void *rec, double *flux, bool cleared) {
     const Layout &L = c->lay;
     hipStream_t s = c->st();
     DiagDev *diag = c->at<DiagDev>(L.diag);
@@ -488,7 +501,8 @@ static mm_status fluxes_t(mm_ctx *c, const double *dt_dev, double dt, const void
     } else {
         int32_t *hard = c->at<int32_t>(L.hard);
         const int64_t cap = list_cap(grid_for(c->nf));
-        k_fill_i32<<<kLists * kListPad / kBlock, kBlock, 0, s>>>(hard, kLists * kListPad, 0);
+        if (!cleared)   // (the step's gradient pass has done it)
+            k_fill_i32<<<kLists * kListPad / kBlock, kBlock, 0, s>>>(hard, kLists * kListPad, 0);
         auto kern = mlp ? k_face_flux_mixed<D, true, EM, GRAV> : k_face_flux_mixed<D, false, EM, GRAV>;
         const float *prim = (const float *)rec;
         kern<<<grid_for(c->nf), kBlock, 0, s>>>(c->nf, c->mesh.face_L, c->mesh.face_R, c->at<float>(L.mrec), prim,
@@ -504,25 +518,29 @@ static mm_status fluxes_t(mm_ctx *c, const double *dt_dev, double dt, const void
 }
 
 template <int D>
-static mm_status fluxes_d(mm_ctx *c, const double *dt_dev, double dt, const void *rec, double *flux) {
+static mm_status fluxes_d(mm_ctx *c, const double *dt_dev, double dt, const void *rec, double *flux, bool cleared) {
     const bool g = c->accel != nullptr;
     switch (c->p.entropy) {
         case MM_ENTROPY_MACH:
-            return g ? fluxes_t<D, 1, true>(c, dt_dev, dt, rec, flux) : fluxes_t<D, 1, false>(c, dt_dev, dt, rec, flux);
+            return g ? fluxes_t<D, 1, true>(c, dt_dev, dt, rec, flux, cleared)
+                     : fluxes_t<D, 1, false>(c, dt_dev, dt, rec, flux, cleared);
         case MM_ENTROPY_ENERGY:   // the entropy flux without the Mach number
-            return g ? fluxes_t<D, 2, true>(c, dt_dev, dt, rec, flux) : fluxes_t<D, 2, false>(c, dt_dev, dt, rec, flux);
+            return g ? fluxes_t<D, 2, true>(c, dt_dev, dt, rec, flux, cleared)
+                     : fluxes_t<D, 2, false>(c, dt_dev, dt, rec, flux, cleared);
         default:
-            return g ? fluxes_t<D, 0, true>(c, dt_dev, dt, rec, flux) : fluxes_t<D, 0, false>(c, dt_dev, dt, rec, flux);
+            return g ? fluxes_t<D, 0, true>(c, dt_dev, dt, rec, flux, cleared)
+                     : fluxes_t<D, 0, false>(c, dt_dev, dt, rec, flux, cleared);
     }
 }
 
-static mm_status fluxes_into(mm_ctx *c, const double *dt_dev, double dt, const void *rec, double *flux) {
+static mm_status fluxes_into(mm_ctx *c, const double *dt_dev, double dt, const void *rec, double *flux,
+                             bool cleared = false) {
     c->faces_done += (uint64_t)c->nf;
     c->waves_done += (uint64_t)((c->nf + 63) / 64);
     c->last_dt_dev = dt_dev;
     c->last_dt = dt;
     c->have_dt = true;
-    return c->D == 3 ? fluxes_d<3>(c, dt_dev, dt, rec, flux) : fluxes_d<2>(c, dt_dev, dt, rec, flux);
+    return c->D == 3 ? fluxes_d<3>(c, dt_dev, dt, rec, flux, cleared) : fluxes_d<2>(c, dt_dev, dt, rec, flux, cleared);
 }
 
 mm_status mm_face_fluxes(mm_ctx *c, double dt, const void *recon, double *face_flux) {
@@ -677,16 +695,14 @@ mm_status mm_hydro_step(mm_ctx *c, double *Q, double dt, double *dt_used) {
     void *rec = c->p.mode == MM_FP64 ? (void *)c->at<double>(L.rec) : (void *)c->at<float>(L.rec32);
     double *dt_part = c->at<double>(L.dtpart);
     double *dt_dev = c->at<double>(L.dtdev);
-    mm_status st = gradients_into(c, Q, rec, dt_part);
+    StepPass sp;
+    if (c->p.mode == MM_MIXED) sp.clear = c->at<int32_t>(L.hard);
+    if (!(dt > 0.0)) sp.dt_out = dt_dev;   // the Courant step
+    mm_status st = gradients_into(c, Q, rec, dt_part, sp);
     if (st != MM_OK) return st;
-    const double *dt_src = nullptr;
-    if (!(dt > 0.0)) {
-        k_min_final<<<1, 1024, 0, s>>>(grid_for(c->n), dt_part, dt_dev);
-        MM_LAUNCH_CHECK();
-        dt_src = dt_dev;
-    }
+    const double *dt_src = sp.dt_out;
     double *flux = c->at<double>(L.flux);
-    st = fluxes_into(c, dt_src, dt, rec, flux);
+    st = fluxes_into(c, dt_src, dt, rec, flux, sp.clear != nullptr);
     if (st != MM_OK) return st;
     st = update_into(c, flux, Q);
     if (st != MM_OK) return st;
