@@ -199,7 +199,9 @@ __device__ __forceinline__ void cell_sums(int64_t i, int lane, const int32_t *__
 // kUpdStage of its records into LDS with coalesced 16-byte loads, while
 // each lane's first three right records are already being gathered, and
 // the left sums read them there (a longer stretch reads the rest from
-// global memory). 20 KB of LDS and 63 VGPRs give 8 wavefronts per SIMD;
+// global memory); so do the right sums for the faces whose left cell is in
+// the block (about half on a Poisson mesh, whose faces all run from the
+// lower cell index to the higher). 20 KB of LDS and 63 VGPRs give 8 wavefronts per SIMD;
 // 1.3% off the step against cell_sums' 3 + 3 records in flight at 6. The sums keep cell_sums' order, so
 // the bits are those of every other path. The entropy scheme's longer
 // records would cost the stage its occupancy, so its updates take
@@ -251,11 +253,14 @@ k_update(int64_t n, const int32_t *__restrict__ lOff, const int32_t *__restrict_
             if (e + 1 < tot) piece[k] = *reinterpret_cast<const f64x2u *>(src + e);
             else if (e < tot) piece[k] = f64x2u{src[e], 0.0};
         }
+        // a right face whose left cell is in the block (about half of them)
+        // has its record in the stage too: read there after the barrier
         double FRr[KR][FM];
-        bool hr[KR];
+        bool hr[KR], inst[KR];
         for (int r = 0; r < KR; r++) {
             hr[r] = r0 + lane + r * GS < r1;
-            load_rec<FM>(flux + (int64_t)(hr[r] ? fr[r] : 0) * FM, FRr[r]);
+            inst[r] = hr[r] && (uint32_t)(fr[r] - s0) < (uint32_t)ns;
+            if (hr[r] && !inst[r]) load_rec<FM>(flux + (int64_t)fr[r] * FM, FRr[r]);
         }
         typedef double f64x2a __attribute__((ext_vector_type(2)));
         for (int k = 0; k < IT; k++) {
@@ -264,6 +269,9 @@ k_update(int64_t n, const int32_t *__restrict__ lOff, const int32_t *__restrict_
         }
         __syncthreads();
         if (!live) return;
+        for (int r = 0; r < KR; r++)
+            if (inst[r])
+                for (int c = 0; c < FM; c++) FRr[r][c] = stage[(fr[r] - s0) * FM + c];
         double acc[NS];
         for (int c = 0; c < NS; c++) acc[c] = 0.0;
         for (int32_t f = l0 + lane; f < l1; f += GS) {
@@ -280,8 +288,13 @@ k_update(int64_t n, const int32_t *__restrict__ lOff, const int32_t *__restrict_
             if (hr[r])
                 for (int c = 0; c < NS; c++) acc[c] += 1.0 * FRr[r][c];
         for (int32_t q = r0 + lane + KR * GS; q < r1; q += GS) {
+            const int32_t f = rFace[q];
             double F[FM];
-            load_rec<FM>(flux + (int64_t)rFace[q] * FM, F);
+            if ((uint32_t)(f - s0) < (uint32_t)ns) {
+                for (int c = 0; c < FM; c++) F[c] = stage[(f - s0) * FM + c];
+            } else {
+                load_rec<FM>(flux + (int64_t)f * FM, F);
+            }
             for (int c = 0; c < NS; c++) acc[c] += 1.0 * F[c];
         }
         for (int c = 0; c < NS; c++) acc[c] = grp_sum<GS>(acc[c]);
