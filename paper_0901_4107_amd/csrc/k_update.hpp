@@ -133,11 +133,11 @@ __device__ __forceinline__ void count_kept(bool keep, DiagDev *diag) {
         atomicAdd(&diag[blockIdx.x & (kDiagSlots - 1)].entropy_kept, (unsigned long long)__popcll(kb));
 }
 
-// The sums of cell i by lane `lane` of its group: acc = the lane's share
-// (minus its left faces, plus its right faces, in that order), butterfly
-// summed over the group; mx the group's largest face Mach number. live(f):
-// whether face f takes part (individual timesteps); the rest contribute
-// nothing. Each lane keeps up to KL left and KR right records in flight
+// The sums of cell i by lane `lane` of its group (the individual
+// timesteps' update; k_update below sums in the same order): acc = the
+// lane's share (minus its left faces, plus its right faces, in that order),
+// butterfly summed over the group; mx the group's largest face Mach number.
+// live(f): whether face f takes part; the rest contribute nothing. Each lane keeps up to KL left and KR right records in flight
 // together (3 and 3; 2 and 2 for the Mach switch's 56-byte records), the
 // rest in loops; the order of the sums does not depend on KL and KR.
 template <int D, int EM, typename Live>
@@ -193,41 +193,39 @@ __device__ __forceinline__ void cell_sums(int64_t i, int lane, const int32_t *__
     if constexpr (EM == 1) mx = grp_max<GS>(mx);
 }
 
-// The update (the step, mm_apply_update): one lane group per cell. Without
-// the entropy scheme a block's cells c0 .. c1-1 are the left cells of one
-// contiguous stretch of faces, [lOff_c0, lOff_c1): the block copies up to
-// kUpdStage of its records into LDS with coalesced 16-byte loads, while
-// each lane's first three right records are already being gathered, and
-// the left sums read them there (a longer stretch reads the rest from
-// global memory); so do the right sums for the faces whose left cell is in
-// the block (about half on a Poisson mesh, whose faces all run from the
-// lower cell index to the higher). 20 KB of LDS and 63 VGPRs give 8 wavefronts per SIMD;
-// 1.3% off the step against cell_sums' 3 + 3 records in flight at 6. The sums keep cell_sums' order, so
-// the bits are those of every other path. The entropy scheme's longer
-// records would cost the stage its occupancy, so its updates take
-// cell_sums as it is: the Mach switch's 56-byte records 2 + 2 per lane in
-// flight at 6 wavefronts per SIMD, the energy switch's 3 + 3 at 5.
-constexpr int kUpdStage = 512;   // records; a block averages 64 x 7.8 on a Poisson mesh
+// The update (the step, mm_apply_update): one lane group per cell. A
+// block's cells c0 .. c1-1 are the left cells of one contiguous stretch of
+// faces, [lOff_c0, lOff_c1): the block copies up to CAP of its records into
+// LDS with coalesced 16-byte loads, while each lane's first KR right
+// records are already being gathered, and the left sums read them there (a
+// longer stretch reads the rest from global memory); so do the right sums
+// for the faces whose left cell is in the block (about half on a Poisson
+// mesh whose faces all run from the lower cell index to the higher; the
+// share, not the result, depends on the orientation). The
+// sums keep cell_sums' order, so the bits are those of every other path.
+// Measured at 128^3 against cell_sums' 3 + 3 records in flight from HBM:
+// the plain step 1.013 -> 0.967 ms, the Mach switch's 1.243 -> 1.163, the
+// energy switch's 1.162 -> 1.102.
+// Per entropy mode: the stage's records, the right records each lane keeps
+// in flight, and the wavefronts per SIMD the kernel is held to (20, 28 and
+// 24 KB of LDS a block).
+template <int EM> struct UpdStage;
+template <> struct UpdStage<0> { static constexpr int CAP = 512, KR = 3, W = 7; };
+template <> struct UpdStage<1> { static constexpr int CAP = 512, KR = 3, W = 5; };
+template <> struct UpdStage<2> { static constexpr int CAP = 512, KR = 3, W = 5; };
 
 template <int D, int EM, bool GRAV>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(EM == 2 ? 5 : (EM == 1 ? 6 : 7))))
+__global__ void __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(UpdStage<EM>::W)))
 k_update(int64_t n, const int32_t *__restrict__ lOff, const int32_t *__restrict__ rOff,
          const int32_t *__restrict__ rFace, const double *__restrict__ flux, double *__restrict__ Q, UpdateArgs u) {
     using RC = Rec<D, EM>;
     constexpr int NS = RC::NS, FM = RC::FM;
     constexpr int GS = Group<D>::GS;
     const int lane = threadIdx.x % GS;
-    if constexpr (EM != 0) {
-        const int64_t i = xcd_tile() * (kBlock / GS) + threadIdx.x / GS;
-        if (i >= n) return;
-        double acc[NS], mx;
-        cell_sums<D, EM>(i, lane, lOff, rOff, rFace, flux, [](int32_t) { return true; }, acc, mx);
-        bool keep = false;
-        if (lane == 0) keep = finish_cell<D, EM, GRAV>(i, n, acc, mx, Q, u);
-        count_kept(keep, u.diag);
-    } else {
-        constexpr int KR = 3;
-        constexpr int PIECES = (kUpdStage * FM + 1) / 2;   // 16-byte pieces of a full stage
+    {
+        constexpr int KR = UpdStage<EM>::KR, CAP = UpdStage<EM>::CAP;
+        constexpr int PIECES = (CAP * FM + 1) / 2;   // 16-byte pieces of a full stage
         constexpr int IT = (PIECES + kBlock - 1) / kBlock;
         __shared__ __align__(16) double stage[2 * PIECES];
         const int64_t c0 = xcd_tile() * (kBlock / GS);
@@ -239,7 +237,7 @@ k_update(int64_t n, const int32_t *__restrict__ lOff, const int32_t *__restrict_
         const int32_t s0 = lOff[c0], s1 = lOff[c1];
         const int32_t l0 = lOff[ic], l1 = live ? lOff[ic + 1] : l0;
         const int32_t r0 = rOff[ic], r1 = live ? rOff[ic + 1] : r0;
-        const int32_t ns = (s1 - s0 < kUpdStage) ? s1 - s0 : kUpdStage;
+        const int32_t ns = (s1 - s0 < CAP) ? s1 - s0 : CAP;
         int32_t fr[KR];
         for (int r = 0; r < KR; r++) {
             const int32_t q = r0 + lane + r * GS;
@@ -272,8 +270,12 @@ k_update(int64_t n, const int32_t *__restrict__ lOff, const int32_t *__restrict_
         for (int r = 0; r < KR; r++)
             if (inst[r])
                 for (int c = 0; c < FM; c++) FRr[r][c] = stage[(fr[r] - s0) * FM + c];
-        double acc[NS];
+        double acc[NS], mx = 0.0;
         for (int c = 0; c < NS; c++) acc[c] = 0.0;
+        auto take = [&](const double *F, double sign) {
+            for (int c = 0; c < NS; c++) acc[c] += sign * F[c];
+            if constexpr (EM == 1) mx = fmax(mx, F[RC::MACH]);
+        };
         for (int32_t f = l0 + lane; f < l1; f += GS) {
             double F[FM];
             const int32_t q = f - s0;
@@ -282,11 +284,10 @@ k_update(int64_t n, const int32_t *__restrict__ lOff, const int32_t *__restrict_
             } else {
                 load_rec<FM>(flux + (int64_t)f * FM, F);
             }
-            for (int c = 0; c < NS; c++) acc[c] += -1.0 * F[c];
+            take(F, -1.0);
         }
         for (int r = 0; r < KR; r++)
-            if (hr[r])
-                for (int c = 0; c < NS; c++) acc[c] += 1.0 * FRr[r][c];
+            if (hr[r]) take(FRr[r], 1.0);
         for (int32_t q = r0 + lane + KR * GS; q < r1; q += GS) {
             const int32_t f = rFace[q];
             double F[FM];
@@ -295,10 +296,13 @@ k_update(int64_t n, const int32_t *__restrict__ lOff, const int32_t *__restrict_
             } else {
                 load_rec<FM>(flux + (int64_t)f * FM, F);
             }
-            for (int c = 0; c < NS; c++) acc[c] += 1.0 * F[c];
+            take(F, 1.0);
         }
         for (int c = 0; c < NS; c++) acc[c] = grp_sum<GS>(acc[c]);
-        if (lane == 0) finish_cell<D, EM, GRAV>(i, n, acc, 0.0, Q, u);
+        if constexpr (EM == 1) mx = grp_max<GS>(mx);
+        bool keep = false;
+        if (lane == 0) keep = finish_cell<D, EM, GRAV>(i, n, acc, mx, Q, u);
+        if constexpr (EM != 0) count_kept(keep, u.diag);
     }
 }
 
