@@ -223,87 +223,85 @@ k_update(int64_t n, const int32_t *__restrict__ lOff, const int32_t *__restrict_
     constexpr int NS = RC::NS, FM = RC::FM;
     constexpr int GS = Group<D>::GS;
     const int lane = threadIdx.x % GS;
-    {
-        constexpr int KR = UpdStage<EM>::KR, CAP = UpdStage<EM>::CAP;
-        constexpr int PIECES = (CAP * FM + 1) / 2;   // 16-byte pieces of a full stage
-        constexpr int IT = (PIECES + kBlock - 1) / kBlock;
-        __shared__ __align__(16) double stage[2 * PIECES];
-        const int64_t c0 = xcd_tile() * (kBlock / GS);
-        if (c0 >= n) return;   // the whole block
-        const int64_t i = c0 + threadIdx.x / GS;
-        const bool live = i < n;
-        const int64_t c1 = (c0 + kBlock / GS < n) ? c0 + kBlock / GS : n;
-        const int64_t ic = live ? i : c0;
-        const int32_t s0 = lOff[c0], s1 = lOff[c1];
-        const int32_t l0 = lOff[ic], l1 = live ? lOff[ic + 1] : l0;
-        const int32_t r0 = rOff[ic], r1 = live ? rOff[ic + 1] : r0;
-        const int32_t ns = (s1 - s0 < CAP) ? s1 - s0 : CAP;
-        int32_t fr[KR];
-        for (int r = 0; r < KR; r++) {
-            const int32_t q = r0 + lane + r * GS;
-            fr[r] = q < r1 ? rFace[q] : 0;
-        }
-        const int tot = ns * FM;
-        const double *src = flux + (int64_t)s0 * FM;
-        f64x2u piece[IT];
-        for (int k = 0; k < IT; k++) {
-            const int e = 2 * (k * kBlock + (int)threadIdx.x);
-            if (e + 1 < tot) piece[k] = *reinterpret_cast<const f64x2u *>(src + e);
-            else if (e < tot) piece[k] = f64x2u{src[e], 0.0};
-        }
-        // a right face whose left cell is in the block (about half of them)
-        // has its record in the stage too: read there after the barrier
-        double FRr[KR][FM];
-        bool hr[KR], inst[KR];
-        for (int r = 0; r < KR; r++) {
-            hr[r] = r0 + lane + r * GS < r1;
-            inst[r] = hr[r] && (uint32_t)(fr[r] - s0) < (uint32_t)ns;
-            if (hr[r] && !inst[r]) load_rec<FM>(flux + (int64_t)fr[r] * FM, FRr[r]);
-        }
-        typedef double f64x2a __attribute__((ext_vector_type(2)));
-        for (int k = 0; k < IT; k++) {
-            const int e = 2 * (k * kBlock + (int)threadIdx.x);
-            if (e < tot) *reinterpret_cast<f64x2a *>(stage + e) = f64x2a{piece[k][0], piece[k][1]};
-        }
-        __syncthreads();
-        if (!live) return;
-        for (int r = 0; r < KR; r++)
-            if (inst[r])
-                for (int c = 0; c < FM; c++) FRr[r][c] = stage[(fr[r] - s0) * FM + c];
-        double acc[NS], mx = 0.0;
-        for (int c = 0; c < NS; c++) acc[c] = 0.0;
-        auto take = [&](const double *F, double sign) {
-            for (int c = 0; c < NS; c++) acc[c] += sign * F[c];
-            if constexpr (EM == 1) mx = fmax(mx, F[RC::MACH]);
-        };
-        for (int32_t f = l0 + lane; f < l1; f += GS) {
-            double F[FM];
-            const int32_t q = f - s0;
-            if (q < ns) {
-                for (int c = 0; c < FM; c++) F[c] = stage[q * FM + c];
-            } else {
-                load_rec<FM>(flux + (int64_t)f * FM, F);
-            }
-            take(F, -1.0);
-        }
-        for (int r = 0; r < KR; r++)
-            if (hr[r]) take(FRr[r], 1.0);
-        for (int32_t q = r0 + lane + KR * GS; q < r1; q += GS) {
-            const int32_t f = rFace[q];
-            double F[FM];
-            if ((uint32_t)(f - s0) < (uint32_t)ns) {
-                for (int c = 0; c < FM; c++) F[c] = stage[(f - s0) * FM + c];
-            } else {
-                load_rec<FM>(flux + (int64_t)f * FM, F);
-            }
-            take(F, 1.0);
-        }
-        for (int c = 0; c < NS; c++) acc[c] = grp_sum<GS>(acc[c]);
-        if constexpr (EM == 1) mx = grp_max<GS>(mx);
-        bool keep = false;
-        if (lane == 0) keep = finish_cell<D, EM, GRAV>(i, n, acc, mx, Q, u);
-        if constexpr (EM != 0) count_kept(keep, u.diag);
+    constexpr int KR = UpdStage<EM>::KR, CAP = UpdStage<EM>::CAP;
+    constexpr int PIECES = (CAP * FM + 1) / 2;   // 16-byte pieces of a full stage
+    constexpr int IT = (PIECES + kBlock - 1) / kBlock;
+    __shared__ __align__(16) double stage[2 * PIECES];
+    const int64_t c0 = xcd_tile() * (kBlock / GS);
+    if (c0 >= n) return;   // the whole block
+    const int64_t i = c0 + threadIdx.x / GS;
+    const bool live = i < n;
+    const int64_t c1 = (c0 + kBlock / GS < n) ? c0 + kBlock / GS : n;
+    const int64_t ic = live ? i : c0;
+    const int32_t s0 = lOff[c0], s1 = lOff[c1];
+    const int32_t l0 = lOff[ic], l1 = live ? lOff[ic + 1] : l0;
+    const int32_t r0 = rOff[ic], r1 = live ? rOff[ic + 1] : r0;
+    const int32_t ns = (s1 - s0 < CAP) ? s1 - s0 : CAP;
+    int32_t fr[KR];
+    for (int r = 0; r < KR; r++) {
+        const int32_t q = r0 + lane + r * GS;
+        fr[r] = q < r1 ? rFace[q] : 0;
     }
+    const int tot = ns * FM;
+    const double *src = flux + (int64_t)s0 * FM;
+    f64x2u piece[IT];
+    for (int k = 0; k < IT; k++) {
+        const int e = 2 * (k * kBlock + (int)threadIdx.x);
+        if (e + 1 < tot) piece[k] = *reinterpret_cast<const f64x2u *>(src + e);
+        else if (e < tot) piece[k] = f64x2u{src[e], 0.0};
+    }
+    // a right face whose left cell is in the block (about half of them)
+    // has its record in the stage too: read there after the barrier
+    double FRr[KR][FM];
+    bool hr[KR], inst[KR];
+    for (int r = 0; r < KR; r++) {
+        hr[r] = r0 + lane + r * GS < r1;
+        inst[r] = hr[r] && (uint32_t)(fr[r] - s0) < (uint32_t)ns;
+        if (hr[r] && !inst[r]) load_rec<FM>(flux + (int64_t)fr[r] * FM, FRr[r]);
+    }
+    typedef double f64x2a __attribute__((ext_vector_type(2)));
+    for (int k = 0; k < IT; k++) {
+        const int e = 2 * (k * kBlock + (int)threadIdx.x);
+        if (e < tot) *reinterpret_cast<f64x2a *>(stage + e) = f64x2a{piece[k][0], piece[k][1]};
+    }
+    __syncthreads();
+    if (!live) return;
+    for (int r = 0; r < KR; r++)
+        if (inst[r])
+            for (int c = 0; c < FM; c++) FRr[r][c] = stage[(fr[r] - s0) * FM + c];
+    double acc[NS], mx = 0.0;
+    for (int c = 0; c < NS; c++) acc[c] = 0.0;
+    auto take = [&](const double *F, double sign) {
+        for (int c = 0; c < NS; c++) acc[c] += sign * F[c];
+        if constexpr (EM == 1) mx = fmax(mx, F[RC::MACH]);
+    };
+    for (int32_t f = l0 + lane; f < l1; f += GS) {
+        double F[FM];
+        const int32_t q = f - s0;
+        if (q < ns) {
+            for (int c = 0; c < FM; c++) F[c] = stage[q * FM + c];
+        } else {
+            load_rec<FM>(flux + (int64_t)f * FM, F);
+        }
+        take(F, -1.0);
+    }
+    for (int r = 0; r < KR; r++)
+        if (hr[r]) take(FRr[r], 1.0);
+    for (int32_t q = r0 + lane + KR * GS; q < r1; q += GS) {
+        const int32_t f = rFace[q];
+        double F[FM];
+        if ((uint32_t)(f - s0) < (uint32_t)ns) {
+            for (int c = 0; c < FM; c++) F[c] = stage[(f - s0) * FM + c];
+        } else {
+            load_rec<FM>(flux + (int64_t)f * FM, F);
+        }
+        take(F, 1.0);
+    }
+    for (int c = 0; c < NS; c++) acc[c] = grp_sum<GS>(acc[c]);
+    if constexpr (EM == 1) mx = grp_max<GS>(mx);
+    bool keep = false;
+    if (lane == 0) keep = finish_cell<D, EM, GRAV>(i, n, acc, mx, Q, u);
+    if constexpr (EM != 0) count_kept(keep, u.diag);
 }
 
 }  // namespace mm
